@@ -1,0 +1,239 @@
+"""PDXearch, PDX-BOND, ADSampling and IVF-flat, step by step -- oracle
+(test infrastructure).
+
+What is followed, in the paper's order:
+
+* Section 4 (PDXearch framework): the search walks blocks one after the
+  other.  START: the first block is scanned without pruning to obtain a
+  threshold (here: blocks keep being scanned fully until k candidates
+  exist; before that the threshold is +inf).  Every later block is
+  scanned dimension-chunk by dimension-chunk; after each chunk a pruning
+  predicate is evaluated on the partial distances.  WARMUP keeps computing
+  all vectors of the block; once the share of not-yet-pruned vectors falls
+  below a selection threshold (20 %, Section 6.1 "Parameters"), PRUNE
+  computes only the survivors.  After the last dimension the survivors are
+  merged into the k-best list and the threshold becomes its k-th distance.
+  WARMUP vs PRUNE changes only which values are computed, never the result.
+* Section 2.3 (exact bounds) and Section 5 (PDX-BOND): the bound is the
+  partial distance itself; a vector is pruned when it is strictly higher
+  than the threshold (the current k-th best exact distance).  Dimensions
+  are visited in decreasing order of |q_j - mean_j| (distance to means).
+* Section 2.3 (ADSampling): on randomly rotated vectors, visited in their
+  natural order, every delta_d dimensions the partial distance is tested
+  against the threshold with the error bound eps0.  The paper describes
+  the test in words only; the formula is the one of the cited ADSampling
+  method: after d of D dimensions the estimate partial*D/d is compared
+  with tau*(1 + eps0/sqrt(d))^2, and at d = D the comparison is exact.
+  Parameters (Section 6.1): delta_d = 32 (D/4 when D < 128), eps0 = 2.1.
+* Section 2.1 (IVF): distances to all centroids first, then the vectors in
+  the nprobe nearest buckets; buckets are visited nearest first (ties by
+  bucket id) and the first one is the START block.
+
+All arithmetic is float64; float32 inputs are widened exactly.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from .exact import sqdist, topk_by_dist_then_id
+
+
+# --------------------------------------------------------------------------
+# dimension orders and chunking
+# --------------------------------------------------------------------------
+
+def bond_order(q: np.ndarray, mu32: np.ndarray) -> np.ndarray:
+    """PDX-BOND visit order (Section 5, distance to means): dimensions by
+    |q_j - mean_j| descending, equal keys by j ascending.  The key is formed
+    in float32, the precision of the stored vectors and means."""
+    key = np.abs(np.asarray(q, dtype=np.float32) - np.asarray(mu32, dtype=np.float32))
+    return np.argsort(-key, kind="stable").astype(np.int64)
+
+
+def ads_delta_d(d: int) -> int:
+    """Section 6.1: delta_d = 32, or D/4 when D < 128."""
+    return 32 if d >= 128 else max(1, d // 4)
+
+
+def fixed_chunks(order: np.ndarray, chunk: int) -> List[np.ndarray]:
+    return [order[i:i + chunk] for i in range(0, order.size, chunk)]
+
+
+def doubling_chunks(order: np.ndarray, first: int = 2) -> List[np.ndarray]:
+    """Section 4 WARMUP: fetch 2, then 4, then 8, ... dimensions."""
+    out, i, step = [], 0, first
+    while i < order.size:
+        out.append(order[i:i + step])
+        i += step
+        step *= 2
+    return out
+
+
+# --------------------------------------------------------------------------
+# pruning predicates: prune(partial, tau, dims_seen, D) -> bool array
+# --------------------------------------------------------------------------
+
+def bond_prunes(partial: np.ndarray, tau: float, dims_seen: int, d: int) -> np.ndarray:
+    """Exact bound: the partial distance is a lower bound (Section 2.3)."""
+    return partial > tau
+
+
+def make_ads_prunes(eps0: float) -> Callable[[np.ndarray, float, int, int], np.ndarray]:
+    """ADSampling hypothesis test with error bound eps0 (Section 2.3)."""
+
+    def prune(partial: np.ndarray, tau: float, dims_seen: int, d: int) -> np.ndarray:
+        if dims_seen >= d or not np.isfinite(eps0):
+            return partial > tau
+        ratio = d / dims_seen
+        bound = tau * (1.0 + eps0 / np.sqrt(dims_seen)) ** 2
+        return partial * ratio > bound
+
+    return prune
+
+
+def never_prunes(partial: np.ndarray, tau: float, dims_seen: int, d: int) -> np.ndarray:
+    return np.zeros(partial.shape, dtype=bool)
+
+
+# --------------------------------------------------------------------------
+# PDXearch
+# --------------------------------------------------------------------------
+
+@dataclass
+class SearchStats:
+    values_computed: int = 0      # (vector, dimension) values evaluated
+    values_total: int = 0         # values a linear scan of the same blocks would evaluate
+    survivors_per_chunk: List[int] = field(default_factory=list)
+
+    @property
+    def pruning_power(self) -> float:
+        """Share of dimension values not used (Section 2.3, pruning power)."""
+        return 1.0 - self.values_computed / max(1, self.values_total)
+
+
+class _KBest:
+    def __init__(self, k: int):
+        self.k = k
+        self.d = np.empty(0, dtype=np.float64)
+        self.i = np.empty(0, dtype=np.int64)
+
+    def merge(self, dist: np.ndarray, ids: np.ndarray) -> None:
+        d = np.concatenate([self.d, dist])
+        i = np.concatenate([self.i, ids])
+        o = np.lexsort((i, d))[: self.k]
+        self.d, self.i = d[o], i[o]
+
+    @property
+    def tau(self) -> float:
+        return float(self.d[-1]) if self.d.size == self.k else np.inf
+
+    def result(self) -> Tuple[np.ndarray, np.ndarray]:
+        return topk_by_dist_then_id(self.d, self.i, self.k)
+
+
+def pdxearch(x: np.ndarray, q: np.ndarray, k: int, blocks: Sequence[np.ndarray],
+             chunks: Sequence[np.ndarray], prune: Callable, switch: float = 0.2,
+             stats: Optional[SearchStats] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """PDXearch over ``blocks`` (arrays of row ids) with a fixed dimension
+    chunking ``chunks`` (arrays of dimension indices covering 0..D-1 once).
+
+    Returns (ids [k], dist [k]) ordered by (dist, id); pads with (-1, inf).
+    """
+    x = np.asarray(x)
+    qq = np.asarray(q, dtype=np.float64)
+    d = x.shape[1]
+    best = _KBest(k)
+    st = stats if stats is not None else SearchStats()
+    for rows in blocks:
+        rows = np.asarray(rows, dtype=np.int64)
+        if rows.size == 0:
+            continue
+        st.values_total += rows.size * d
+        xb = np.asarray(x[rows], dtype=np.float64)
+        if best.tau == np.inf:
+            # START: linear scan, no threshold yet
+            best.merge(sqdist(xb, qq), rows)
+            st.values_computed += rows.size * d
+            continue
+        tau = best.tau
+        partial = np.zeros(rows.size, dtype=np.float64)
+        alive = np.ones(rows.size, dtype=bool)
+        warmup = True
+        seen = 0
+        for ch in chunks:
+            comp = np.ones(rows.size, dtype=bool) if warmup else alive.copy()
+            diff = xb[np.ix_(comp, ch)] - qq[ch][None, :]
+            partial[comp] += np.einsum("ij,ij->i", diff, diff)
+            st.values_computed += int(comp.sum()) * ch.size
+            seen += ch.size
+            alive &= ~prune(partial, tau, seen, d)
+            st.survivors_per_chunk.append(int(alive.sum()))
+            if warmup and alive.mean() < switch:
+                warmup = False
+            if not alive.any():
+                break
+        if alive.any():
+            surv = rows[alive]
+            # survivors carry their complete distance; report it by definition
+            best.merge(sqdist(x[surv], qq), surv)
+    return best.result()
+
+
+def bond_search(x: np.ndarray, q: np.ndarray, k: int, block: int = 10_000, chunk: int = 32,
+                mu32: Optional[np.ndarray] = None, switch: float = 0.2,
+                stats: Optional[SearchStats] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Exact PDX-BOND search (Sections 4, 5, 6.5): horizontal blocks of at
+    most ``block`` rows, distance-to-means order, fixed chunks."""
+    x = np.asarray(x)
+    n, d = x.shape
+    if mu32 is None:
+        mu32 = np.asarray(x, dtype=np.float64).mean(axis=0).astype(np.float32)
+    order = bond_order(q, mu32)
+    blocks = [np.arange(s, min(n, s + block)) for s in range(0, n, block)]
+    return pdxearch(x, q, k, blocks, fixed_chunks(order, chunk), bond_prunes, switch, stats)
+
+
+def bond_search_batch(x: np.ndarray, queries: np.ndarray, k: int, **kw):
+    queries = np.atleast_2d(queries)
+    out = [bond_search(x, q, k, **kw) for q in queries]
+    return np.stack([o[0] for o in out]), np.stack([o[1] for o in out])
+
+
+# --------------------------------------------------------------------------
+# IVF
+# --------------------------------------------------------------------------
+
+def ivf_probe_order(centroids: np.ndarray, qrot: np.ndarray, nprobe: int) -> np.ndarray:
+    """The nprobe buckets with the smallest centroid distance, nearest
+    first, equal distances by bucket id (Section 2.1, IVF)."""
+    dist = sqdist(centroids, qrot)
+    return np.lexsort((np.arange(dist.size), dist))[:nprobe].astype(np.int64)
+
+
+def ivf_flat(xrot: np.ndarray, lists: Sequence[np.ndarray], centroids: np.ndarray,
+             qrot: np.ndarray, k: int, nprobe: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Exact top-k over the union of the probed buckets (IVF_FLAT)."""
+    probe = ivf_probe_order(centroids, qrot, nprobe)
+    rows = np.concatenate([np.asarray(lists[p], dtype=np.int64) for p in probe]) if probe.size else np.empty(0, np.int64)
+    if rows.size == 0:
+        return topk_by_dist_then_id(np.empty(0), np.empty(0, np.int64), k)
+    return topk_by_dist_then_id(sqdist(np.asarray(xrot)[rows], qrot), rows, k)
+
+
+def ads_ivf_search(xrot: np.ndarray, lists: Sequence[np.ndarray], centroids: np.ndarray,
+                   qrot: np.ndarray, k: int, nprobe: int, eps0: float = 2.1,
+                   delta_d: Optional[int] = None, switch: float = 0.2,
+                   stats: Optional[SearchStats] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """PDXearch with the ADSampling test inside IVF (Sections 2.3, 4, 6.2):
+    probed buckets nearest first, rotated dimensions in natural order,
+    checkpoints every delta_d dimensions."""
+    xrot = np.asarray(xrot)
+    d = xrot.shape[1]
+    dd = ads_delta_d(d) if delta_d is None else delta_d
+    probe = ivf_probe_order(centroids, qrot, nprobe)
+    blocks = [np.asarray(lists[p], dtype=np.int64) for p in probe]
+    return pdxearch(xrot, qrot, k, blocks, fixed_chunks(np.arange(d), dd),
+                    make_ads_prunes(eps0), switch, stats)

@@ -1,0 +1,16 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the bench.
+
+This package only draws random numbers.  It holds none of the search
+method's arithmetic (no distances, no ordering, no pruning), so the CPU
+oracle and the GPU path can both consume its output without sharing any
+method code.
+"""
+from .gen import (  # noqa: F401
+    Mixture,
+    isotropic_mixture,
+    skewed_mixture,
+    anisotropic_unit_mixture,
+    integer_grid,
+    workload,
+    WORKLOADS,
+)

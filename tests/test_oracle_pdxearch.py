@@ -1,0 +1,137 @@
+"""Pins for the step-by-step PDXearch / PDX-BOND / ADSampling / IVF oracle.
+
+* Hand-worked PDX-BOND runs (values computed, result) and orders.
+* Invariant: PDX-BOND never changes the exact answer (Sections 2.3, 5:
+  the partial distance is a lower bound), on integer inputs bit for bit
+  and on real inputs, for every chunking and WARMUP/PRUNE threshold.
+* ADSampling test: hand-worked thresholds; eps0 = inf reduces it to the
+  exact bound, so the IVF search equals IVF-flat.
+* IVF-flat with every bucket probed equals exact search.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, kmeans, pdxearch as px
+from oracle.layout import column_means_f32
+from tests.conftest import golden
+
+
+def test_hand_bond_runs():
+    g = golden("hand_bond.json")
+    x = np.array(g["vectors"], dtype=np.float32)
+    q = np.array(g["query"], dtype=np.float32)
+    for c in g["cases"]:
+        st = px.SearchStats()
+        ids, dist = px.bond_search(x, q, c["k"], block=g["block"], chunk=g["chunk"], stats=st)
+        assert ids.tolist() == c["ids"]
+        assert dist.tolist() == c["dist"]
+        assert st.values_computed == c["values_computed"]
+        assert st.values_total == c["values_total"]
+
+
+def test_hand_bond_orders():
+    for c in golden("hand_bond.json")["order_cases"]:
+        o = px.bond_order(np.array(c["query"], np.float32), np.array(c["means"], np.float32))
+        assert o.tolist() == c["order"]
+
+
+def test_hand_ads_thresholds():
+    g = golden("hand_ads.json")
+    prune = px.make_ads_prunes(g["eps0"])
+    for c in g["cases"]:
+        got = bool(prune(np.array([c["partial"]]), g["tau"], c["d"], g["D"])[0])
+        assert got == c["pruned"], c
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 32, 100])
+@pytest.mark.parametrize("switch", [0.0, 0.2, 1.0])
+def test_bond_equals_exact_integer(chunk, switch):
+    x, q = synth.integer_grid(1200, 100, 4, lo=-3, hi=3, seed=11)
+    want_i, want_d = exact.knn_exact(x, q, 10)
+    for i in range(q.shape[0]):
+        ids, dist = px.bond_search(x, q[i], 10, block=256, chunk=chunk, switch=switch)
+        assert ids.tolist() == want_i[i].tolist()
+        assert np.array_equal(dist, want_d[i])
+
+
+def test_bond_equals_exact_real_and_prunes():
+    x, q, _ = synth.workload("bond_1m_d960", n=6000, nq=3)
+    want_i, want_d = exact.knn_exact(x, q, 10)
+    for i in range(q.shape[0]):
+        st = px.SearchStats()
+        ids, dist = px.bond_search(x, q[i], 10, block=1000, chunk=32, stats=st)
+        assert ids.tolist() == want_i[i].tolist()
+        np.testing.assert_allclose(dist, want_d[i], rtol=1e-12)
+        # on skewed data the bound must actually prune (Section 6.4)
+        assert st.pruning_power > 0.3
+
+
+def test_bond_small_first_block_and_k_over_n():
+    x, q = synth.integer_grid(37, 5, 2, seed=5)
+    want_i, want_d = exact.knn_exact(x, q, 50)
+    for i in range(2):
+        ids, dist = px.bond_search(x, q[i], 50, block=4, chunk=2)
+        assert ids.tolist() == want_i[i].tolist()
+        assert np.array_equal(dist, want_d[i])
+
+
+def test_doubling_chunks_cover_once():
+    ch = px.doubling_chunks(np.arange(100))
+    assert [c.size for c in ch] == [2, 4, 8, 16, 32, 38]
+    assert np.array_equal(np.concatenate(ch), np.arange(100))
+    assert px.ads_delta_d(960) == 32 and px.ads_delta_d(64) == 16
+
+
+def _small_ivf(seed=1, n=3000, d=64, nlist=24):
+    mix = synth.anisotropic_unit_mixture(d, 16, seed)
+    x = mix.data(n)
+    q = mix.queries(6)
+    init = np.random.default_rng(seed).choice(n, nlist, replace=False)
+    c, lab, _ = kmeans.lloyd(x, init, 5)
+    return x, q, c, kmeans.lists_from_labels(lab, nlist)
+
+
+def test_ivf_flat_all_buckets_is_exact():
+    x, q, c, lists = _small_ivf()
+    want_i, want_d = exact.knn_exact(x, q, 10)
+    for i in range(q.shape[0]):
+        ids, dist = px.ivf_flat(x, lists, c, q[i].astype(np.float64), 10, len(lists))
+        assert ids.tolist() == want_i[i].tolist()
+        np.testing.assert_allclose(dist, want_d[i], rtol=1e-12)
+
+
+def test_ads_eps_inf_equals_ivf_flat_and_recall_monotone():
+    x, q, c, lists = _small_ivf()
+    truth, _ = exact.knn_exact(x, q, 10)
+    prev = -1.0
+    for nprobe in (1, 3, 6, 24):
+        got_flat, got_ads, got_inf = [], [], []
+        for i in range(q.shape[0]):
+            qq = q[i].astype(np.float64)
+            fi, fd = px.ivf_flat(x, lists, c, qq, 10, nprobe)
+            ii, idd = px.ads_ivf_search(x, lists, c, qq, 10, nprobe, eps0=np.inf)
+            assert ii.tolist() == fi.tolist()
+            np.testing.assert_allclose(idd, fd, rtol=1e-12)
+            ai, _ = px.ads_ivf_search(x, lists, c, qq, 10, nprobe, eps0=2.1)
+            got_flat.append(fi)
+            got_ads.append(ai)
+        r_flat = exact.recall_at_k(truth, np.stack(got_flat))
+        r_ads = exact.recall_at_k(np.stack(got_flat), np.stack(got_ads))
+        assert r_flat >= prev
+        prev = r_flat
+        assert r_ads >= 0.9
+    assert prev == 1.0
+
+
+def test_probe_order_ties_by_bucket_id():
+    c = np.array([[1.0, 0], [0, 1.0], [-1.0, 0], [3.0, 0]])
+    order = px.ivf_probe_order(c, np.zeros(2), 3)
+    assert order.tolist() == [0, 1, 2]
+
+
+def test_means_rounding_is_single():
+    x = np.array([[1.0, 0.1], [2.0, 0.2], [4.0, 0.3]], dtype=np.float32)
+    m = column_means_f32(x)
+    assert m[0] == np.float32(7.0 / 3.0)
+    assert m[1] == np.float32((np.float64(np.float32(0.1)) + np.float64(np.float32(0.2)) + np.float64(np.float32(0.3))) / 3)
