@@ -1,0 +1,231 @@
+/*
+ * pdx.h -- C ABI of libpdx: the PDX dimension-by-dimension K-nearest-
+ * neighbour scan on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kuffo, Krippner, Boncz, "PDX: A Data Layout for Vector
+ * Similarity Search" (SIGMOD 2025).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Problem (Section 2.1): a collection of n vectors of D float32
+ *   coordinates and a query q; the k vectors minimising the squared
+ *   Euclidean distance sum_i (v_i - q_i)^2 are returned.
+ * - Every data pointer is a DEVICE pointer owned by the caller (e.g. a
+ *   torch tensor), 16-byte aligned.  Matrices are row-major float32,
+ *   contiguous.  The library never allocates device memory: the index
+ *   lives in a caller buffer sized with the *_bytes query, and each search
+ *   uses a caller workspace sized with the *_workspace query.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default
+ *   stream.  Search calls only enqueue work on it (no host sync): outputs
+ *   are valid once the caller synchronises the stream.  Build calls are
+ *   synchronous (they wait on `stream` before returning).
+ * - Results: ids are int64 row numbers into the rows given to the build
+ *   call; distances are float32 squared L2, ascending by (distance, id).
+ *   If fewer than k candidates exist, the tail holds id -1 and +inf.
+ * - Errors: every call returns a pdx_status and never throws.  Argument
+ *   errors are detected on the host before anything is enqueued.
+ *   pdx_last_error() returns a thread-local description of the last
+ *   non-OK status.  A HIP error raised by an enqueue is returned as
+ *   PDX_EHIP; faults during execution surface at the caller's sync.
+ * - Concurrency: an index is read-only after its build; concurrent
+ *   searches on it are allowed, each with its own workspace and stream.
+ * - Limits: 1 <= k <= PDX_MAX_K, 1 <= D <= PDX_MAX_DIM, n < 2^31.
+ */
+#ifndef PDX_H
+#define PDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PDX_API __attribute__((visibility("default")))
+#else
+#define PDX_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pdx_status;
+#define PDX_OK 0
+#define PDX_EINVAL (-1)        /* bad argument, or non-finite data at build */
+#define PDX_EWORKSPACE (-2)    /* index buffer or workspace too small */
+#define PDX_EHIP (-3)          /* a HIP runtime call or launch failed */
+#define PDX_EUNSUPPORTED (-4)  /* valid request outside what is implemented */
+
+#define PDX_MAX_K 64
+#define PDX_MAX_DIM 4096
+
+/* Opaque host-side handle.  It points into the caller's index buffer,
+ * which must outlive it; pdx_free releases only the handle. */
+typedef struct pdx_index pdx_index;
+
+/* ---------------------------------------------------------------------
+ * Flat (exact-search) index
+ * ------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t group;      /* vectors per vectorgroup; 0 = 64 (Section 3). Only 64. */
+    int32_t start_rows; /* rows of the START block (Section 4 PHASE 0, Section
+                           6.5: blocks of at most 10K vectors); 0 = 10000 */
+} pdx_build_params;
+
+/* Device bytes pdx_build needs for n rows of d dimensions. */
+PDX_API size_t pdx_build_bytes(int64_t n, int32_t d, const pdx_build_params *params);
+
+/* pdx_build -- store the collection in the PDX layout.
+ *
+ * Section 3 and its kernel listing: rows are cut into vectorgroups of G=64
+ * and inside a group the values of one dimension are contiguous (value of
+ * dimension j of the group's i-th vector at j*64 + i); the last group is
+ * zero-padded.  Section 5: the per-dimension collection means used by the
+ * PDX-BOND order are computed (float64 accumulation, stored as float32).
+ *
+ * x           [n][d] float32 device, read only.
+ * index_mem   device buffer of index_bytes >= pdx_build_bytes(n, d, params);
+ *             owned by the caller, must stay alive while *out is used.
+ * out         receives a new handle (release with pdx_free).
+ * Returns PDX_EINVAL for n < 1, d < 1 or d > PDX_MAX_DIM, n >= 2^31, null
+ * pointers, or any non-finite value in x; PDX_EWORKSPACE if index_bytes is
+ * too small.  Synchronous. */
+PDX_API pdx_status pdx_build(const float *x, int64_t n, int32_t d, const pdx_build_params *params,
+                     void *index_mem, size_t index_bytes, void *stream, pdx_index **out);
+
+enum {
+    PDX_MODE_LINEAR = 0, /* PDX linear scan, every dimension of every vector */
+    PDX_MODE_BOND = 1    /* PDXearch with the PDX-BOND bound and order */
+};
+
+typedef struct {
+    int32_t mode;        /* PDX_MODE_LINEAR or PDX_MODE_BOND */
+    int32_t chunk;       /* dimensions per pruning step; 0 = 32 */
+    int32_t tile_groups; /* vectorgroups per wave task; 0 = library default */
+    int32_t queries_per_block; /* queries per workgroup (1, 2, 4, 8); 0 = default */
+    /* Optional instrumentation (NULL = off); neither changes the result.   */
+    void **phase_events; /* 4 hipEvent_t recorded on `stream`: at the start,
+                            after query preparation + START, after the pruned
+                            scan, at the end */
+    unsigned long long *counters; /* device [4], added to (not cleared):
+                            [0] values (vector x dimension) evaluated by START,
+                            [1] lane slots START issued, [2] values evaluated
+                            by the pruned scan (live lanes only), [3] lane
+                            slots it issued (live and pruned lanes) */
+} pdx_search_params;
+
+/* Workspace bytes for pdx_search_exact with these arguments. */
+PDX_API size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, int32_t k,
+                                  const pdx_search_params *params);
+
+/* pdx_search_exact -- exact K-nearest neighbours of nq queries.
+ *
+ * PDX_MODE_LINEAR: the kernel listing of Section 3 (L2) over every
+ * vectorgroup.  PDX_MODE_BOND: PDXearch (Section 4) with PDX-BOND
+ * (Section 5): dimensions visited by |q_j - mean_j| descending (ties by j),
+ * START scans the first start_rows rows without pruning, every later
+ * vector is dropped as soon as its partial distance after a chunk is
+ * strictly above the running k-th distance.  Both modes return the exact
+ * answer; partial sums are accumulated chunk by chunk in a fixed order per
+ * (query, vector), so the result does not depend on scheduling.
+ *
+ * q         [nq][d] float32 device.
+ * ws        device workspace of ws_bytes >= pdx_search_exact_workspace(...).
+ * out_ids   [nq][k] int64 device;  out_dist [nq][k] float32 device.
+ * A query holding a non-finite value gets ids -1 and NaN distances (the
+ * check runs on the device; the call still returns PDX_OK).
+ * nq = 0 is a successful no-op.  Returns PDX_EINVAL (null pointers, nq < 0,
+ * k < 1, unknown mode), PDX_EUNSUPPORTED (k > PDX_MAX_K), PDX_EWORKSPACE. */
+PDX_API pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, int32_t k,
+                            const pdx_search_params *params, void *ws, size_t ws_bytes,
+                            int64_t *out_ids, float *out_dist, void *stream);
+
+/* ---------------------------------------------------------------------
+ * IVF index with ADSampling
+ * ------------------------------------------------------------------ */
+
+enum { PDX_DTYPE_F32 = 0, PDX_DTYPE_BF16 = 1, PDX_DTYPE_FP8 = 2 };
+
+typedef struct {
+    int32_t kmeans_iters;   /* Lloyd iterations; 0 = 20 */
+    int32_t dtype;          /* extra low-precision copy of the rotated vectors */
+    /* Random numbers are drawn by the caller and passed in:             */
+    const double *gaussian; /* [d][d] iid N(0,1) float64 device, rotated with
+                               the Q of its QR (Haar sign fix); NULL = no rotation */
+    const int64_t *init_rows; /* [nlist] device: rows seeding k-means */
+    /* Optional precomputed parts (all device; NULL = compute):            */
+    const float *rotation;  /* [d][d] used as is (overrides gaussian)     */
+    const float *centroids; /* [nlist][d], in rotated space: skip k-means */
+    const int32_t *assign;  /* [n] bucket of each row (needs centroids)   */
+} pdx_ivf_params;
+
+PDX_API size_t pdx_ivf_build_bytes(int64_t n, int32_t d, int32_t nlist, const pdx_ivf_params *params);
+
+/* pdx_ivf_build -- IVF buckets over randomly rotated vectors, each bucket
+ * stored as PDX vectorgroups.
+ *
+ * Section 2.3 (ADSampling): a random orthogonal rotation R (float64
+ * Householder QR on the device) is applied to every row; Section 2.1
+ * (IVF): non-optimised Lloyd k-means with nlist buckets, each row in the
+ * bucket of its nearest centroid (ties: lower id); an empty bucket keeps
+ * its previous centroid.  Section 2.1 / Figure "IVF-PDX": every bucket is
+ * a PDX block.  Synchronous.
+ *
+ * Returns PDX_EINVAL for bad sizes (nlist < 1 or nlist > n), null required
+ * pointers, or non-finite data; PDX_EWORKSPACE if index_bytes is short. */
+PDX_API pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist,
+                         const pdx_ivf_params *params, void *index_mem, size_t index_bytes,
+                         void *stream, pdx_index **out);
+
+/* Copy the IVF index's parts out (any pointer may be NULL):
+ * rotation [d][d] f32, centroids [nlist][d] f32 (rotated space),
+ * assign [n] int32 (bucket of each row), list_sizes [nlist] int32. */
+PDX_API pdx_status pdx_ivf_export(const pdx_index *index, float *rotation, float *centroids,
+                          int32_t *assign, int32_t *list_sizes, void *stream);
+
+typedef struct {
+    float eps0;        /* ADSampling error bound (Section 6.1: 2.1);
+                          +INFINITY: exact within the probed buckets */
+    int32_t delta_d;   /* dimensions between tests; 0 = 32, D/4 if D < 128 */
+    int32_t dtype;     /* scan the PDX_DTYPE_* copy stored at build */
+    int32_t rerank;    /* low precision: candidates re-ranked in f32; 0 = 4k */
+} pdx_ivf_search_params;
+
+PDX_API size_t pdx_search_ivf_workspace(const pdx_index *index, int64_t nq, int32_t k, int32_t nprobe,
+                                const pdx_ivf_search_params *params);
+
+/* pdx_search_ivf -- approximate K nearest neighbours with IVF + ADSampling.
+ *
+ * Section 2.1 (IVF): the rotated query's distances to every centroid; the
+ * nprobe nearest buckets (ties by bucket id) are searched nearest first.
+ * Section 4 (PDXearch): the first probed bucket is scanned fully (START),
+ * every other one chunk by chunk in the rotated (natural) dimension order.
+ * Section 2.3 (ADSampling): after d < D dimensions a vector is dropped when
+ * partial*D/d > tau*(1 + eps0/sqrt(d))^2, tau the running k-th distance;
+ * at d = D the comparison is exact.  Distances are reported in rotated
+ * space (equal to the original up to rounding).
+ *
+ * Returns PDX_EINVAL (null pointers, k < 1, nprobe outside [1, nlist],
+ * not an IVF index), PDX_EUNSUPPORTED (k > PDX_MAX_K, dtype not stored),
+ * PDX_EWORKSPACE. */
+PDX_API pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, int32_t k,
+                          int32_t nprobe, const pdx_ivf_search_params *params, void *ws,
+                          size_t ws_bytes, int64_t *out_ids, float *out_dist, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Handles and diagnostics
+ * ------------------------------------------------------------------ */
+
+/* Releases the host handle only (the caller frees its device buffers). */
+PDX_API void pdx_free(pdx_index *index);
+
+/* Thread-local text of the last non-OK status of this thread. */
+PDX_API const char *pdx_last_error(void);
+
+/* Library version, e.g. "pdx 0.1.0 gfx950". */
+PDX_API const char *pdx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDX_H */

@@ -1,0 +1,16 @@
+"""PDX K-nearest-neighbour scan for AMD Instinct MI355X (gfx950).
+
+The search itself lives in ``libpdx.so`` (HIP kernels behind the C ABI of
+``include/pdx.h``); this package is its Python binding.  Importing the
+binding requires the built library; there is no CPU fallback.
+"""
+from .api import (  # noqa: F401
+    PdxIndex,
+    pdx_build,
+    pdx_ivf_build,
+    pdx_ivf_export,
+    pdx_search_exact,
+    pdx_search_exact_workspace,
+    pdx_search_ivf,
+    pdx_version,
+)

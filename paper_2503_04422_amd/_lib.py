@@ -1,0 +1,109 @@
+"""ctypes view of libpdx.so (the C ABI declared in include/pdx.h).
+
+The library is loaded after torch so that both share one HIP runtime (the
+same ``libamdhip64.so.7`` soname), which lets torch tensors and streams be
+handed to the library directly.  There is no fallback: if the library is
+missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime first)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdx.so")
+
+PDX_OK = 0
+PDX_EINVAL = -1
+PDX_EWORKSPACE = -2
+PDX_EHIP = -3
+PDX_EUNSUPPORTED = -4
+PDX_MAX_K = 64
+PDX_MAX_DIM = 4096
+
+PDX_MODE_LINEAR = 0
+PDX_MODE_BOND = 1
+
+PDX_DTYPE_F32 = 0
+PDX_DTYPE_BF16 = 1
+PDX_DTYPE_FP8 = 2
+
+c_void_p = ctypes.c_void_p
+c_int32 = ctypes.c_int32
+c_int64 = ctypes.c_int64
+c_size_t = ctypes.c_size_t
+
+
+class pdx_build_params(ctypes.Structure):
+    _fields_ = [("group", c_int32), ("start_rows", c_int32)]
+
+
+class pdx_search_params(ctypes.Structure):
+    _fields_ = [("mode", c_int32), ("chunk", c_int32), ("tile_groups", c_int32),
+                ("queries_per_block", c_int32), ("phase_events", c_void_p), ("counters", c_void_p)]
+
+
+class pdx_ivf_params(ctypes.Structure):
+    _fields_ = [("kmeans_iters", c_int32), ("dtype", c_int32), ("gaussian", c_void_p),
+                ("init_rows", c_void_p), ("rotation", c_void_p), ("centroids", c_void_p),
+                ("assign", c_void_p)]
+
+
+class pdx_ivf_search_params(ctypes.Structure):
+    _fields_ = [("eps0", ctypes.c_float), ("delta_d", c_int32), ("dtype", c_int32),
+                ("rerank", c_int32)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "pdx_build_bytes": (c_size_t, [c_int64, c_int32, ctypes.POINTER(pdx_build_params)]),
+    "pdx_build": (c_int32, [c_void_p, c_int64, c_int32, ctypes.POINTER(pdx_build_params), c_void_p,
+                            c_size_t, c_void_p, ctypes.POINTER(c_void_p)]),
+    "pdx_search_exact_workspace": (c_size_t, [c_void_p, c_int64, c_int32,
+                                              ctypes.POINTER(pdx_search_params)]),
+    "pdx_search_exact": (c_int32, [c_void_p, c_void_p, c_int64, c_int32,
+                                   ctypes.POINTER(pdx_search_params), c_void_p, c_size_t,
+                                   c_void_p, c_void_p, c_void_p]),
+    "pdx_ivf_build_bytes": (c_size_t, [c_int64, c_int32, c_int32, ctypes.POINTER(pdx_ivf_params)]),
+    "pdx_ivf_build": (c_int32, [c_void_p, c_int64, c_int32, c_int32, ctypes.POINTER(pdx_ivf_params),
+                                c_void_p, c_size_t, c_void_p, ctypes.POINTER(c_void_p)]),
+    "pdx_ivf_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pdx_search_ivf_workspace": (c_size_t, [c_void_p, c_int64, c_int32, c_int32,
+                                            ctypes.POINTER(pdx_ivf_search_params)]),
+    "pdx_search_ivf": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32,
+                                 ctypes.POINTER(pdx_ivf_search_params), c_void_p, c_size_t,
+                                 c_void_p, c_void_p, c_void_p]),
+    "pdx_free": (None, [c_void_p]),
+    "pdx_last_error": (ctypes.c_char_p, []),
+    "pdx_version": (ctypes.c_char_p, []),
+}
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libpdx.so is not built ({LIB_PATH}); run `python -m paper_2503_04422_amd.build` "
+            "or __graft_entry__.build() -- there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class PdxError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib.pdx_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != PDX_OK:
+        raise PdxError(status, where)

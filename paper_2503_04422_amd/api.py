@@ -1,0 +1,181 @@
+"""Python binding of libpdx: argument marshalling only.
+
+Each function has the name of the C entry point it calls.  Tensors must be
+CUDA (HIP) tensors; torch provides the device memory (index buffers,
+workspaces, outputs) and the current stream.  Every step of the search runs
+in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _stream(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != torch.float32 or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float32 tensor")
+    return t.contiguous()
+
+
+_MODES = {"linear": _lib.PDX_MODE_LINEAR, "bond": _lib.PDX_MODE_BOND}
+_DTYPES = {"f32": _lib.PDX_DTYPE_F32, "bf16": _lib.PDX_DTYPE_BF16, "fp8": _lib.PDX_DTYPE_FP8}
+
+
+class PdxIndex:
+    """Host handle plus the device buffer it points into."""
+
+    def __init__(self, handle: ctypes.c_void_p, mem: torch.Tensor, n: int, d: int, kind: str,
+                 nlist: int = 0, dtype: str = "f32"):
+        self._h = handle
+        self.mem = mem
+        self.n = n
+        self.d = d
+        self.kind = kind
+        self.nlist = nlist
+        self.dtype = dtype
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.pdx_free(h)
+            self._h = ctypes.c_void_p(None)
+
+
+def pdx_build(x: torch.Tensor, start_rows: int = 0,
+              stream: Optional[torch.cuda.Stream] = None) -> PdxIndex:
+    """Flat PDX index of the rows of ``x`` ([n, d] float32 on the GPU)."""
+    x = _dev_f32(x, "x")
+    n, d = x.shape
+    params = _lib.pdx_build_params(0, int(start_rows))
+    nbytes = lib.pdx_build_bytes(n, d, ctypes.byref(params))
+    if nbytes == 0:
+        raise ValueError(f"unsupported shape n={n} d={d}")
+    mem = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    h = ctypes.c_void_p()
+    st = lib.pdx_build(_ptr(x), n, d, ctypes.byref(params), _ptr(mem), nbytes, _stream(stream),
+                       ctypes.byref(h))
+    check(st, "pdx_build")
+    return PdxIndex(h, mem, n, d, "flat")
+
+
+def pdx_search_exact_workspace(index: PdxIndex, nq: int, k: int, mode: str = "bond", chunk: int = 0,
+                               tile_groups: int = 0, queries_per_block: int = 0) -> int:
+    p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block)
+    return int(lib.pdx_search_exact_workspace(index.handle, nq, k, ctypes.byref(p)))
+
+
+def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond", chunk: int = 0,
+                     tile_groups: int = 0, queries_per_block: int = 0,
+                     workspace: Optional[torch.Tensor] = None,
+                     phase_events=None, counters: Optional[torch.Tensor] = None,
+                     out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                     stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Exact k nearest neighbours; returns (ids [nq, k] int64, dist [nq, k] float32).
+
+    ``phase_events``: optional ctypes array of 4 hipEvent_t handles;
+    ``counters``: optional int64 GPU tensor of 4 value counters."""
+    q = _dev_f32(q, "q")
+    nq = q.shape[0]
+    if q.shape[1] != index.d:
+        raise ValueError("query dimension does not match the index")
+    p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block,
+                               ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
+                               _ptr(counters))
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+    else:
+        ids, dist = out
+    need = lib.pdx_search_exact_workspace(index.handle, nq, k, ctypes.byref(p))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
+    st = lib.pdx_search_exact(index.handle, _ptr(q), nq, k, ctypes.byref(p), _ptr(workspace),
+                              workspace.numel(), _ptr(ids), _ptr(dist), _stream(stream))
+    check(st, "pdx_search_exact")
+    return ids, dist
+
+
+def pdx_ivf_build(x: torch.Tensor, nlist: int, gaussian: Optional[torch.Tensor],
+                  init_rows: Optional[torch.Tensor], kmeans_iters: int = 0, dtype: str = "f32",
+                  rotation: Optional[torch.Tensor] = None, centroids: Optional[torch.Tensor] = None,
+                  assign: Optional[torch.Tensor] = None,
+                  stream: Optional[torch.cuda.Stream] = None) -> PdxIndex:
+    """IVF index over randomly rotated rows; buckets stored as PDX groups."""
+    x = _dev_f32(x, "x")
+    n, d = x.shape
+    keep = [t.contiguous() if t is not None else None for t in (gaussian, init_rows, rotation, centroids, assign)]
+    g, ir, rot, cen, asg = keep
+    if g is not None and g.dtype != torch.float64:
+        raise TypeError("gaussian must be float64")
+    if ir is not None and ir.dtype != torch.int64:
+        raise TypeError("init_rows must be int64")
+    if asg is not None and asg.dtype != torch.int32:
+        raise TypeError("assign must be int32")
+    p = _lib.pdx_ivf_params(int(kmeans_iters), _DTYPES[dtype], _ptr(g), _ptr(ir), _ptr(rot), _ptr(cen),
+                            _ptr(asg))
+    nbytes = lib.pdx_ivf_build_bytes(n, d, nlist, ctypes.byref(p))
+    if nbytes == 0:
+        raise ValueError(f"unsupported IVF shape n={n} d={d} nlist={nlist}")
+    mem = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    h = ctypes.c_void_p()
+    st = lib.pdx_ivf_build(_ptr(x), n, d, nlist, ctypes.byref(p), _ptr(mem), nbytes, _stream(stream),
+                           ctypes.byref(h))
+    check(st, "pdx_ivf_build")
+    return PdxIndex(h, mem, n, d, "ivf", nlist, dtype)
+
+
+def pdx_ivf_export(index: PdxIndex, stream: Optional[torch.cuda.Stream] = None):
+    """(rotation [d,d], centroids [nlist,d], assign [n] int32, list_sizes [nlist] int32)."""
+    dev = index.mem.device
+    rot = torch.empty((index.d, index.d), dtype=torch.float32, device=dev)
+    cen = torch.empty((index.nlist, index.d), dtype=torch.float32, device=dev)
+    asg = torch.empty(index.n, dtype=torch.int32, device=dev)
+    sizes = torch.empty(index.nlist, dtype=torch.int32, device=dev)
+    st = lib.pdx_ivf_export(index.handle, _ptr(rot), _ptr(cen), _ptr(asg), _ptr(sizes), _stream(stream))
+    check(st, "pdx_ivf_export")
+    return rot, cen, asg, sizes
+
+
+def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1,
+                   delta_d: int = 0, dtype: str = "f32", rerank: int = 0,
+                   workspace: Optional[torch.Tensor] = None,
+                   stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Approximate k nearest neighbours (IVF + ADSampling)."""
+    q = _dev_f32(q, "q")
+    nq = q.shape[0]
+    p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
+                                   _DTYPES[dtype], int(rerank))
+    ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+    need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
+    st = lib.pdx_search_ivf(index.handle, _ptr(q), nq, k, nprobe, ctypes.byref(p), _ptr(workspace),
+                            workspace.numel(), _ptr(ids), _ptr(dist), _stream(stream))
+    check(st, "pdx_search_ivf")
+    return ids, dist
+
+
+def pdx_version() -> str:
+    return lib.pdx_version().decode()

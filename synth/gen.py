@@ -21,6 +21,8 @@ were requested together.
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Dict, Optional, Tuple
 
@@ -67,15 +69,27 @@ class Mixture:
              start: int = 0) -> np.ndarray:
         """Rows ``start .. start+n-1`` of a stream, as float32 [n, D]."""
         out = np.empty((n, self.dim), dtype=np.float32)
+        pieces = []  # (block, offset in block, rows, position in out)
         pos = 0
         r = start
         while pos < n:
             b, off = divmod(r, _BLOCK)
             take = min(_BLOCK - off, n - pos)
-            blk = self._block(stream, qseed, b)
-            out[pos:pos + take] = blk[off:off + take]
+            pieces.append((b, off, take, pos))
             pos += take
             r += take
+
+        def fill(piece):
+            b, off, take, at = piece
+            out[at:at + take] = self._block(stream, qseed, b)[off:off + take]
+
+        if len(pieces) > 2:
+            workers = min(16, os.cpu_count() or 1, len(pieces))
+            with ThreadPoolExecutor(workers) as ex:
+                list(ex.map(fill, pieces))
+        else:
+            for pc in pieces:
+                fill(pc)
         return out
 
     def data(self, n: int, start: int = 0) -> np.ndarray:

@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every entry point of include/pdx.h,
+and its host-side argument checks answer without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pdx.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"PDX_API\s+[\w\s\*]+?\b(pdx_\w+)\s*\(", txt)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for want in ("pdx_build", "pdx_search_exact", "pdx_ivf_build", "pdx_search_ivf"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2503_04422_amd import _lib
+    for name in _declared():
+        assert hasattr(_lib.lib, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def test_host_side_argument_errors():
+    from paper_2503_04422_amd import _lib
+    lib = _lib.lib
+    h = ctypes.c_void_p()
+    assert lib.pdx_build_bytes(0, 8, None) == 0
+    assert lib.pdx_build_bytes(10, 0, None) == 0
+    assert lib.pdx_build_bytes(10, _lib.PDX_MAX_DIM + 1, None) == 0
+    assert lib.pdx_build_bytes(100, 16, None) >= 2 * 64 * 16 * 4
+    assert lib.pdx_build(None, 10, 8, None, None, 0, None, ctypes.byref(h)) == _lib.PDX_EINVAL
+    assert b"null" in lib.pdx_last_error()
+    assert lib.pdx_build(ctypes.c_void_p(256), 0, 8, None, ctypes.c_void_p(256), 1 << 20, None,
+                         ctypes.byref(h)) == _lib.PDX_EINVAL
+    assert lib.pdx_search_exact(None, None, 1, 10, None, None, 0, None, None, None) == _lib.PDX_EINVAL
+    assert lib.pdx_search_exact_workspace(None, 1, 10, None) == 0
+    assert lib.pdx_search_ivf(None, None, 1, 10, 1, None, None, 0, None, None, None) == _lib.PDX_EINVAL
+    assert lib.pdx_version().startswith(b"pdx ")

@@ -1,0 +1,154 @@
+"""GPU parity of the exact path (flat PDX index, linear scan and PDX-BOND)
+against the FP64 oracle, through the C ABI.
+
+Sizes span several vectorgroups and wave tiles with ragged tails (n not a
+multiple of 64, D not a multiple of the chunk), plus the edge cases of the
+method: k = 1, k = 64, k > n, duplicates, a query equal to a row, nq = 0,
+non-finite queries, and schedule-independence of the result.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, layout
+from tests.parity import check_knn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pdx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_04422_amd as pdx  # fails loudly if libpdx.so is missing
+    return pdx
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _search(pdx, x, q, k, **kw):
+    import torch
+    ix = pdx.pdx_build(_dev(x), start_rows=kw.pop("start_rows", 0))
+    ids, dist = pdx.pdx_search_exact(ix, _dev(q), k, **kw)
+    torch.cuda.synchronize()
+    return ix, ids.cpu().numpy(), dist.cpu().numpy()
+
+
+def test_layout_and_means_bit_exact(pdx):
+    import torch
+    for n, d in [(1, 1), (100, 37), (129, 64), (1000, 130)]:
+        x = np.random.default_rng(n + d).standard_normal((n, d)).astype(np.float32)
+        print(f"layout n={n} d={d}", flush=True)
+        ix = pdx.pdx_build(_dev(x))
+        torch.cuda.synchronize()
+        ng = (n + 63) // 64
+        nb = ng * d * 64 * 4
+        mem = ix.mem.cpu().numpy()
+        got = mem[:nb].view(np.float32).reshape(ng, d, 64)
+        assert np.array_equal(got, layout.to_pdx(x, 64))
+        off = (nb + 255) // 256 * 256
+        means = mem[off:off + 4 * d].view(np.float32)
+        want = layout.column_means_f32(x)
+        ulp = np.abs(means.view(np.int32).astype(np.int64) - want.view(np.int32).astype(np.int64))
+        assert ulp.max() <= 1
+
+
+def test_linear_small_config(pdx):
+    x, q, _ = synth.workload("linear_10k_d128")
+    print("linear 10k x 128, 100 queries", flush=True)
+    wi, wd = exact.knn_exact_c(x, q, 10)
+    _, gi, gd = _search(pdx, x, q, 10, mode="linear")
+    check_knn(x, q, gi, gd, wi, wd)
+
+
+@pytest.mark.parametrize("mode", ["linear", "bond"])
+@pytest.mark.parametrize("n,d,k", [(3001, 100, 10), (4096, 37, 1), (1000, 64, 64), (130, 5, 20)])
+def test_integer_inputs_bit_exact(pdx, mode, n, d, k):
+    x, q = synth.integer_grid(n, d, 9, lo=-4, hi=4, seed=n + d)
+    q[3] = x[17]
+    x[n - 1] = x[17]  # duplicate of a row equal to a query
+    print(f"integer {mode} n={n} d={d} k={k}", flush=True)
+    wi, wd = exact.knn_exact_c(x, q, k)
+    _, gi, gd = _search(pdx, x, q, k, mode=mode, start_rows=256)
+    check_knn(x, q, gi, gd, wi, wd, exact=True)
+
+
+def test_bond_skewed_multi_block(pdx):
+    x, q, _ = synth.workload("bond_1m_d960", n=40_000, nq=24)
+    print("bond skewed 40k x 960", flush=True)
+    wi, wd = exact.knn_exact_c(x, q, 10)
+    for kw in (dict(), dict(tile_groups=3, queries_per_block=1), dict(chunk=8, queries_per_block=8)):
+        _, gi, gd = _search(pdx, x, q, 10, mode="bond", **kw)
+        check_knn(x, q, gi, gd, wi, wd)
+
+
+def test_bond_result_independent_of_schedule(pdx):
+    x, q, _ = synth.workload("bond_1m_d960", n=20_000, nq=16)
+    print("bond schedule independence", flush=True)
+    outs = []
+    for kw in (dict(), dict(tile_groups=1, queries_per_block=2), dict(tile_groups=64, queries_per_block=8),
+               dict(mode="linear")):
+        kw.setdefault("mode", "bond")
+        _, gi, gd = _search(pdx, x, q, 10, **kw)
+        outs.append((gi, gd))
+    for gi, gd in outs[1:3]:
+        assert np.array_equal(gi, outs[0][0]) and np.array_equal(gd, outs[0][1])
+    # linear mode sums in natural order: same ids up to ties, distances within rounding
+    wi, wd = exact.knn_exact_c(x, q, 10)
+    check_knn(x, q, outs[3][0], outs[3][1], wi, wd)
+
+
+def test_k_above_n_and_single_row(pdx):
+    x = np.random.default_rng(0).standard_normal((5, 33)).astype(np.float32)
+    q = np.random.default_rng(1).standard_normal((3, 33)).astype(np.float32)
+    wi, wd = exact.knn_exact_c(x, q, 12)
+    for mode in ("linear", "bond"):
+        _, gi, gd = _search(pdx, x, q, 12, mode=mode)
+        check_knn(x, q, gi, gd, wi, wd)
+    _, gi, gd = _search(pdx, x[:1], q, 3, mode="bond")
+    assert gi[:, 0].tolist() == [0, 0, 0] and (gi[:, 1:] == -1).all()
+
+
+def test_zero_queries_and_nonfinite_query(pdx):
+    import torch
+    x, q = synth.integer_grid(500, 16, 4, seed=3)
+    ix = pdx.pdx_build(_dev(x))
+    ids, dist = pdx.pdx_search_exact(ix, torch.empty((0, 16), device="cuda"), 5)
+    assert ids.shape == (0, 5)
+    q[2, 5] = np.nan
+    ids, dist = pdx.pdx_search_exact(ix, _dev(q), 5)
+    torch.cuda.synchronize()
+    gi, gd = ids.cpu().numpy(), dist.cpu().numpy()
+    assert (gi[2] == -1).all() and np.isnan(gd[2]).all()
+    wi, wd = exact.knn_exact_c(x, q[[0, 1, 3]], 5)
+    check_knn(x, q[[0, 1, 3]], gi[[0, 1, 3]], gd[[0, 1, 3]], wi, wd, exact=True)
+
+
+def test_build_rejects_nonfinite(pdx):
+    from paper_2503_04422_amd._lib import PdxError
+    x = np.ones((70, 8), dtype=np.float32)
+    x[65, 3] = np.inf
+    with pytest.raises(PdxError):
+        pdx.pdx_build(_dev(x))
+
+
+def test_full_size_bond_sampled(pdx):
+    """1,000,000 x 960, 1,000 queries, in the bench's launch configuration;
+    a sample of queries is checked against the oracle one by one."""
+    import torch
+    x, q, _ = synth.workload("bond_1m_d960")
+    print("full size bond 1M x 960 x 1000", flush=True)
+    ix = pdx.pdx_build(_dev(x))
+    ids, dist = pdx.pdx_search_exact(ix, _dev(q), 10, mode="bond")
+    torch.cuda.synchronize()
+    gi, gd = ids.cpu().numpy(), dist.cpu().numpy()
+    sample = np.random.default_rng(0).choice(q.shape[0], 12, replace=False)
+    wi, wd = exact.knn_exact_c(x, q[sample], 10)
+    check_knn(x, q[sample], gi[sample], gd[sample], wi, wd)
+    # every query: ascending, distinct, valid
+    assert (np.diff(gd, axis=1) >= 0).all()
+    assert (gi >= 0).all() and (gi < x.shape[0]).all()
