@@ -38,6 +38,24 @@ def _hip():
     return lib
 
 
+def profiled_traffic(profile_md: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 summary, or None when the kernel sources changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", profile_md)
+    if not os.path.exists(path):
+        return None, "no profile"
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None, "no summary"
+    info = json.loads(m.group(1))
+    blob = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in info["sources"])
+    if hashlib.sha256(blob).hexdigest()[:16] != info["source_sha256_16"]:
+        return None, "kernel changed since profiled"
+    return info["traffic_bytes_per_launch"], f"profiles/{profile_md}"
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,7 +70,20 @@ def main() -> int:
                     help="wall-time budget of the oracle's CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-linear", action="store_true", help="skip the unpruned comparison run")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (calibrates HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 3}), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described "
@@ -140,8 +171,11 @@ def main() -> int:
         kern_ms = phase_ms["scan_ms"]
         kern_name = "scan_kernel<false> (linear scan)"
     achieved = scan_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+    traffic, traffic_src = (profiled_traffic("scan_bond_1m_d960.md")
+                            if (args.mode, args.workload, k) == ("bond", "bond_1m_d960", 10) else (None, "n/a"))
     roofline = {"bound": "hbm", "kernel": kern_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": traffic_src,
                 "algorithmic_bytes_per_launch": scan_bytes, "kernel_ms": round(kern_ms, 4),
                 "lane_efficiency": round(c[2] / c[3], 4) if c[3] else None}
 
