@@ -188,6 +188,13 @@ typedef struct {
     int32_t delta_d;   /* dimensions between tests; 0 = 32, D/4 if D < 128 */
     int32_t dtype;     /* scan the PDX_DTYPE_* copy stored at build */
     int32_t rerank;    /* low precision: candidates re-ranked in f32; 0 = 4k */
+    /* Optional instrumentation (NULL = off); neither changes the result.   */
+    void **phase_events; /* 4 hipEvent_t recorded on `stream`: at the start,
+                            after rotation + bucket selection + START, after
+                            the pruned scan, at the end */
+    unsigned long long *counters; /* device [4], added to: [0] values evaluated
+                            by START, [1] its lane slots, [2] values evaluated
+                            by the pruned scan (live lanes), [3] its lane slots */
 } pdx_ivf_search_params;
 
 PDX_API size_t pdx_search_ivf_workspace(const pdx_index *index, int64_t nq, int32_t k, int32_t nprobe,

@@ -53,7 +53,7 @@ class pdx_ivf_params(ctypes.Structure):
 
 class pdx_ivf_search_params(ctypes.Structure):
     _fields_ = [("eps0", ctypes.c_float), ("delta_d", c_int32), ("dtype", c_int32),
-                ("rerank", c_int32)]
+                ("rerank", c_int32), ("phase_events", c_void_p), ("counters", c_void_p)]
 
 
 # name -> (restype, argtypes)

@@ -1,0 +1,326 @@
+// IVF search with ADSampling on PDX buckets.
+//
+//  1. queries rotated (k_pair DOT) and distances to every centroid (k_pair L2);
+//  2. select: per query the nprobe nearest buckets, nearest first, ties by
+//     bucket id (Section 2.1 IVF);
+//  3. work items (query, probe rank) grouped by bucket so that the queries
+//     reading one bucket run together (the bucket stays in L2 / MALL);
+//  4. START (Section 4, PHASE 0): every query's nearest bucket is scanned
+//     without pruning; its k-th distance becomes the query's threshold;
+//  5. the other probed buckets are scanned chunk by chunk in the rotated
+//     (natural) dimension order; after d < D dimensions a vector is dropped
+//     when partial * D/d > tau * (1 + eps0/sqrt(d))^2 (ADSampling test of
+//     Section 2.3), at d = D when partial > tau; survivors enter the wave's
+//     k-best list, whose k-th distance tightens the query's threshold;
+//  6. merge of the per-item k-best lists.
+#include "pdx_internal.h"
+#include "wave_topk.h"
+
+namespace pdx {
+namespace {
+
+// nprobe nearest buckets per query: bitonic sort of (distance, bucket)
+// keys in LDS; also flags queries holding non-finite values.
+__global__ __launch_bounds__(256) void select_probe_kernel(const float *__restrict__ cd, int32_t nlist,
+                                                           int32_t pow2, const float *__restrict__ q,
+                                                           int32_t d, int32_t nprobe,
+                                                           int32_t *__restrict__ probe,
+                                                           int32_t *__restrict__ bad,
+                                                           uint32_t *__restrict__ tau) {
+    extern __shared__ uint64_t key[];
+    const int64_t qi = blockIdx.x;
+    int nonfinite = 0;
+    for (int j = threadIdx.x; j < d; j += blockDim.x) nonfinite |= !isfinite(q[qi * d + j]);
+    nonfinite = __syncthreads_or(nonfinite);
+    for (int l = threadIdx.x; l < pow2; l += blockDim.x) {
+        uint64_t kk = kEmptyKey;
+        if (l < nlist) kk = make_key(cd[qi * nlist + l], (uint32_t)l);
+        key[l] = kk;
+    }
+    __syncthreads();
+    for (int k2 = 2; k2 <= pow2; k2 <<= 1)
+        for (int j2 = k2 >> 1; j2 > 0; j2 >>= 1) {
+            for (int i = threadIdx.x; i < pow2; i += blockDim.x) {
+                int ixj = i ^ j2;
+                if (ixj > i) {
+                    uint64_t a = key[i], b = key[ixj];
+                    bool up = (i & k2) == 0;
+                    if ((a > b) == up) {
+                        key[i] = b;
+                        key[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int r = threadIdx.x; r < nprobe; r += blockDim.x)
+        probe[qi * nprobe + r] = (int32_t)(key[r] & 0xffffffffu);
+    if (threadIdx.x == 0) {
+        bad[qi] = nonfinite;
+        tau[qi] = kInfBits;
+    }
+}
+
+// items per bucket: count, exclusive prefix, scatter (START items r = 0 and
+// pruned items r >= 1 in two separate lists)
+__global__ void item_count_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe,
+                                  int32_t *__restrict__ cnt0, int32_t *__restrict__ cnt1) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq * nprobe) return;
+    int32_t r = (int32_t)(i % nprobe);
+    atomicAdd((r == 0 ? cnt0 : cnt1) + probe[i], 1);
+}
+
+__global__ __launch_bounds__(1024) void item_prefix_kernel(int32_t *__restrict__ cnt, int32_t nlist) {
+    __shared__ int32_t s[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < nlist; base += 1024) {
+        int32_t l = base + threadIdx.x;
+        int32_t c = l < nlist ? cnt[l] : 0;
+        s[threadIdx.x] = c;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (l < nlist) cnt[l] = carry + s[threadIdx.x] - c;  // exclusive -> becomes a cursor
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += s[1023];
+        __syncthreads();
+    }
+}
+
+__global__ void item_scatter_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe,
+                                    int32_t *__restrict__ cur0, int32_t *__restrict__ cur1,
+                                    int2 *__restrict__ items0, int2 *__restrict__ items1) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq * nprobe) return;
+    int32_t r = (int32_t)(i % nprobe);
+    int32_t qi = (int32_t)(i / nprobe);
+    int32_t l = probe[i];
+    if (r == 0) items0[atomicAdd(cur0 + l, 1)] = make_int2(qi, r);
+    else items1[atomicAdd(cur1 + l, 1)] = make_int2(qi, r);
+}
+
+// Scan of one bucket for one query per wave.  Work items are consecutive
+// per bucket; workgroup ids are mapped so each XCD takes a contiguous
+// range of items (and so of buckets).
+template <bool PRUNE>
+__global__ __launch_bounds__(256) void ivf_scan_kernel(
+    const float *__restrict__ pdxd, int32_t d, const int32_t *__restrict__ slot_id,
+    const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nitems,
+    const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
+    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, uint32_t nwg) {
+    // grid = 8 * ceil(nwg / 8): every (xcd, index) pair is launched once
+    const uint32_t per_xcd = gridDim.x >> 3;
+    const uint32_t wg = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t it = (int64_t)wg * 4 + wave;
+    if (wg >= nwg || it >= nitems) return;
+    const int2 item = items[it];
+    const int64_t qi = item.x;
+    const int32_t r = item.y;
+    uint64_t *myslot = slots + ((size_t)qi * nprobe + r) * k;
+    if (bad[qi]) {
+        if (lane < k) myslot[lane] = kEmptyKey;
+        return;
+    }
+    const int32_t l = probe[qi * nprobe + r];
+    const float *qp = qrot + qi * d;
+    uint64_t e = kEmptyKey, kth = kEmptyKey;
+    unsigned long long live_vals = 0, lane_vals = 0;
+    for (int32_t g = goff[l]; g < goff[l + 1]; ++g) {
+        float tau_eff = INFINITY;
+        if (PRUNE) {
+            uint32_t tg = __hip_atomic_load(tau + qi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            float tl = kth == kEmptyKey ? INFINITY : key_dist(kth);
+            tau_eff = fminf(__uint_as_float(tg), tl);
+        }
+        const int32_t vid = slot_id[(int64_t)g * kGroup + lane];
+        bool alive = vid >= 0;
+        const float *gp = pdxd + (int64_t)g * d * kGroup + lane;
+        float partial = 0.0f;
+        for (int32_t c0 = 0; c0 < d; c0 += chunk) {
+            if (PRUNE && !__any(alive)) break;
+            const int32_t c1 = min(c0 + chunk, d);
+            if (counters) {
+                live_vals += (unsigned long long)__popcll(__ballot(alive)) * (c1 - c0);
+                lane_vals += 64ull * (c1 - c0);
+            }
+            float s = 0.0f;
+            if (alive) {
+                int32_t j = c0;
+                for (; j + 8 <= c1; j += 8) {
+                    float x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) x[u] = gp[(int64_t)(j + u) * kGroup];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        float t = qp[j + u] - x[u];
+                        s = fmaf(t, t, s);
+                    }
+                }
+                for (; j < c1; ++j) {
+                    float t = qp[j] - gp[(int64_t)j * kGroup];
+                    s = fmaf(t, t, s);
+                }
+            }
+            partial += s;
+            if (PRUNE) {
+                // ADSampling test after c1 of d dimensions
+                float thr = tau_eff;
+                if (c1 < d) {
+                    float dc = (float)c1;
+                    float f = 1.0f + eps0 / sqrtf(dc);
+                    thr = tau_eff * (dc / (float)d) * f * f;
+                }
+                alive = alive && !(partial > thr);
+            }
+        }
+        topk_offer(e, kth, make_key(partial, (uint32_t)vid), alive, k, lane);
+        if (PRUNE && kth != kEmptyKey) {
+            float kt = key_dist(kth);
+            if (kt < tau_eff && lane == 0) atomicMin(tau + qi, __float_as_uint(kt));
+        }
+    }
+    if (lane < k) myslot[lane] = e;
+    if (counters && lane == 0) {
+        atomicAdd(counters, live_vals);
+        atomicAdd(counters + 1, lane_vals);
+    }
+}
+
+// k-best over a query's probe slots [r0, r1); optional threshold / result
+__global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restrict__ slots, int32_t nprobe,
+                                                       int32_t r0, int32_t r1, int32_t k,
+                                                       const int32_t *__restrict__ bad,
+                                                       uint32_t *__restrict__ tau,
+                                                       int64_t *__restrict__ out_ids,
+                                                       float *__restrict__ out_dist) {
+    const int64_t qi = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t *base = slots + ((size_t)qi * nprobe + r0) * k;
+    const int64_t total = (int64_t)(r1 - r0) * k;
+    uint64_t e = kEmptyKey, kth = kEmptyKey;
+    for (int64_t i0 = 0; i0 < total; i0 += kWave) {
+        uint64_t kk = (i0 + lane < total) ? base[i0 + lane] : kEmptyKey;
+        topk_offer(e, kth, kk, kk != kEmptyKey, k, lane);
+    }
+    if (tau && lane == 0 && kth != kEmptyKey) tau[qi] = (uint32_t)(kth >> 32);
+    if (out_ids && lane < k) {
+        int64_t id = -1;
+        float dist = INFINITY;
+        if (bad[qi]) {
+            dist = __uint_as_float(0x7fc00000u);
+        } else if (e != kEmptyKey) {
+            id = (int64_t)(e & 0xffffffffu);
+            dist = key_dist(e);
+        }
+        out_ids[qi * k + lane] = id;
+        out_dist[qi * k + lane] = dist;
+    }
+}
+
+int32_t next_pow2(int32_t v) {
+    int32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, const pdx_ivf_search_params *p,
+                void *ws, IvfPlan *plan) {
+    IvfPlan pl{};
+    pl.nq = nq;
+    pl.k = k;
+    pl.nprobe = nprobe;
+    pl.eps0 = p ? p->eps0 : 2.1f;
+    int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
+    pl.chunk = dd;
+    size_t q = (size_t)(nq > 0 ? nq : 0);
+    Carver c(ws);
+    pl.qrot = c.take<float>(q * ix->d);
+    pl.cd = c.take<float>(q * ix->nlist);
+    pl.probe = c.take<int32_t>(q * nprobe);
+    pl.bad = c.take<int32_t>(q);
+    pl.tau = c.take<uint32_t>(q);
+    pl.cnt0 = c.take<int32_t>(ix->nlist);
+    pl.cnt1 = c.take<int32_t>(ix->nlist);
+    pl.items0 = c.take<int2>(q);
+    pl.items1 = c.take<int2>(q * (nprobe - 1 > 0 ? nprobe - 1 : 1));
+    pl.slots = c.take<uint64_t>(q * nprobe * k);
+    pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
+    pl.counters = p ? p->counters : nullptr;
+    if (plan) *plan = pl;
+    return c.bytes();
+}
+
+hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64_t *out_ids, float *out_dist,
+                   hipStream_t s) {
+    const int32_t d = ix->d;
+    const int64_t nq = pl.nq;
+    hipError_t e;
+    auto mark = [&](int i) { return pl.events ? hipEventRecord(pl.events[i], s) : hipSuccess; };
+    if ((e = mark(0)) != hipSuccess) return e;
+    // 1. rotation and centroid distances
+    if (ix->has_rot) {
+        if ((e = launch_pair(0, 0, q, nq, ix->rot, d, d, pl.qrot, d, nullptr, s)) != hipSuccess) return e;
+    } else {
+        if ((e = hipMemcpyAsync(pl.qrot, q, sizeof(float) * nq * d, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return e;
+    }
+    if ((e = launch_pair(1, 0, pl.qrot, nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) !=
+        hipSuccess)
+        return e;
+    // 2. nearest buckets
+    int32_t pow2 = next_pow2(ix->nlist);
+    select_probe_kernel<<<(unsigned)nq, 256, pow2 * sizeof(uint64_t), s>>>(pl.cd, ix->nlist, pow2, q, d, pl.nprobe,
+                                                                         pl.probe, pl.bad, pl.tau);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 3. work items grouped by bucket
+    if ((e = launch_fill_i32(pl.cnt0, ix->nlist, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(pl.cnt1, ix->nlist, 0, s)) != hipSuccess) return e;
+    int64_t tot = nq * pl.nprobe;
+    unsigned gb = (unsigned)((tot + 255) / 256);
+    item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, pl.cnt0, pl.cnt1);
+    item_prefix_kernel<<<1, 1024, 0, s>>>(pl.cnt0, ix->nlist);
+    item_prefix_kernel<<<1, 1024, 0, s>>>(pl.cnt1, ix->nlist);
+    item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, pl.cnt0, pl.cnt1, pl.items0, pl.items1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 4. START
+    int64_t n0 = nq, n1 = nq * (pl.nprobe - 1);
+    auto grid_of = [](int64_t items, uint32_t *nwg) {
+        *nwg = (uint32_t)((items + 3) / 4);
+        return 8u * ((*nwg + 7u) / 8u);
+    };
+    uint32_t nwg0, nwg1;
+    unsigned grid0 = grid_of(n0, &nwg0), grid1 = grid_of(n1, &nwg1);
+    ivf_scan_kernel<false><<<grid0, 256, 0, s>>>(
+        ix->pdx, d, ix->slot_id, ix->list_goff, pl.items0, n0, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad,
+        pl.slots, pl.k, pl.chunk, pl.eps0, pl.counters, nwg0);
+    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, 1, pl.k, pl.bad, pl.tau, nullptr, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = mark(1)) != hipSuccess) return e;
+    // 5. pruned scan of the other probed buckets
+    if (n1 > 0) {
+        ivf_scan_kernel<true><<<grid1, 256, 0, s>>>(
+            ix->pdx, d, ix->slot_id, ix->list_goff, pl.items1, n1, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad,
+            pl.slots, pl.k, pl.chunk, pl.eps0, pl.counters ? pl.counters + 2 : nullptr, nwg1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = mark(2)) != hipSuccess) return e;
+    // 6. merge
+    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, pl.k, pl.bad, nullptr, out_ids,
+                                                out_dist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return mark(3);
+}
+
+}  // namespace pdx

@@ -31,6 +31,7 @@ struct pdx_index {
     // IVF
     int32_t nlist;
     int32_t dtype_mask;  // bit i set: PDX_DTYPE i stored
+    int32_t has_rot;     // 0: rows stored unrotated (rot holds the identity)
     float *rot;          // [d][d] rotation (row j = j-th output coordinate)
     float *centroids;    // [nlist][d] rotated space
     int32_t *list_goff;  // [nlist+1] first vectorgroup of each bucket
@@ -91,6 +92,46 @@ struct ExactPlan {
     hipEvent_t *events;              // optional [4]
     unsigned long long *counters;    // optional [4]
 };
+
+struct IvfPlan {
+    int64_t nq;
+    int32_t k;
+    int32_t nprobe;
+    int32_t chunk;  // dimensions between ADSampling tests
+    float eps0;
+    float *qrot;       // [nq][d]
+    float *cd;         // [nq][nlist]
+    int32_t *probe;    // [nq][nprobe]
+    int32_t *bad;      // [nq]
+    uint32_t *tau;     // [nq]
+    int32_t *cnt0, *cnt1;  // [nlist] item cursors
+    int2 *items0, *items1;
+    uint64_t *slots;   // [nq][nprobe][k]
+    hipEvent_t *events;
+    unsigned long long *counters;
+};
+
+size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, const pdx_ivf_search_params *p,
+                void *ws, IvfPlan *plan);
+hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &plan, int64_t *out_ids,
+                   float *out_dist, hipStream_t s);
+
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
+hipError_t launch_pair(int mode, int out, const float *A, int64_t m, const float *B, int64_t nb, int32_t k,
+                       float *C, int64_t ldc, unsigned long long *best, hipStream_t s);
+hipError_t launch_qr_rotation(const double *gauss, int32_t d, double *acm, double *q, double *v, double *diag,
+                              float *rot, hipStream_t s);
+hipError_t launch_gather_rows(const float *x, int64_t n, int32_t d, const int64_t *rows, int32_t count,
+                              float *out, int32_t *flag, hipStream_t s);
+hipError_t launch_labels_from_keys(const unsigned long long *best, int64_t n, int32_t *lab, hipStream_t s);
+hipError_t launch_kmeans_update(const float *x, int64_t n, int32_t d, const int32_t *lab, int32_t nlist,
+                                double *sums, int32_t *cnt, float *cen, hipStream_t s);
+hipError_t launch_check_labels(const int32_t *lab, int64_t n, int32_t nlist, int32_t *flag, hipStream_t s);
+hipError_t launch_bucketize(const float *xrot, int64_t n, int32_t d, const int32_t *lab, int32_t nlist,
+                            int32_t *blk_cnt, int32_t *size, int32_t *goff, int32_t *stats, int32_t *slot_id,
+                            int64_t max_slots, float *pdx, int64_t max_groups, hipStream_t s);
 
 size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_params *p,
                   void *ws, ExactPlan *plan);

@@ -1,36 +1,288 @@
-// IVF entry points (declared in include/pdx.h).
+// IVF entry points (declared in include/pdx.h): argument validation,
+// carving of the caller's buffers, build sequencing.
+#include <cmath>
+#include <new>
+
 #include "pdx_internal.h"
+
+namespace pdx {
+namespace {
+
+constexpr int32_t kMaxNlist = 4096;
+constexpr int32_t kRowsPerBlock = 1024;
+
+struct IvfLayout {
+    float *rot, *centroids, *pdx, *xrot;
+    int32_t *list_size, *list_goff, *stats, *assign, *slot_id, *cnt, *blk_cnt, *flag;
+    unsigned long long *best;
+    double *sums, *acm, *qd, *v, *diag;
+    int64_t max_groups;
+    size_t bytes;
+};
+
+IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, void *base) {
+    IvfLayout l{};
+    l.max_groups = (n + kGroup - 1) / kGroup + nlist;
+    int64_t nblocks = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+    Carver c(base);
+    // index proper
+    l.rot = c.take<float>((size_t)d * d);
+    l.centroids = c.take<float>((size_t)nlist * d);
+    l.list_size = c.take<int32_t>(nlist);
+    l.list_goff = c.take<int32_t>(nlist + 1);
+    l.stats = c.take<int32_t>(64);
+    l.assign = c.take<int32_t>(n);
+    l.slot_id = c.take<int32_t>((size_t)l.max_groups * kGroup);
+    l.pdx = c.take<float>((size_t)l.max_groups * d * kGroup);
+    // build scratch
+    l.xrot = c.take<float>((size_t)n * d);
+    l.best = c.take<unsigned long long>(n);
+    l.sums = c.take<double>((size_t)nlist * d);
+    l.cnt = c.take<int32_t>(nlist);
+    l.blk_cnt = c.take<int32_t>((size_t)nblocks * nlist);
+    l.acm = c.take<double>((size_t)d * d);
+    l.qd = c.take<double>((size_t)d * d);
+    l.v = c.take<double>(d);
+    l.diag = c.take<double>(d);
+    l.flag = c.take<int32_t>(64);
+    l.bytes = c.bytes();
+    return l;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+pdx_status hip_fail(hipError_t e, const char *what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return PDX_EHIP;
+}
+
+__global__ void identity_kernel(float *rot, int32_t d) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < (int64_t)d * d) rot[i] = (i / d == i % d) ? 1.0f : 0.0f;
+}
+
+bool valid_shape(int64_t n, int32_t d, int32_t nlist) {
+    return n >= 1 && n < (int64_t(1) << 31) && d >= 1 && d <= PDX_MAX_DIM && nlist >= 1 && nlist <= kMaxNlist &&
+           nlist <= n;
+}
+
+}  // namespace
+}  // namespace pdx
 
 using namespace pdx;
 
+#define TRY(expr)                                        \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
 extern "C" {
 
-size_t pdx_ivf_build_bytes(int64_t, int32_t, int32_t, const pdx_ivf_params *) { return 0; }
-
-pdx_status pdx_ivf_build(const float *, int64_t, int32_t, int32_t, const pdx_ivf_params *, void *, size_t,
-                         void *, pdx_index **out) {
-    if (out) *out = nullptr;
-    set_error("pdx_ivf_build: not implemented yet");
-    return PDX_EUNSUPPORTED;
+size_t pdx_ivf_build_bytes(int64_t n, int32_t d, int32_t nlist, const pdx_ivf_params *params) {
+    (void)params;
+    if (!valid_shape(n, d, nlist)) return 0;
+    return ivf_layout(n, d, nlist, nullptr).bytes;
 }
 
-pdx_status pdx_ivf_export(const pdx_index *, float *, float *, int32_t *, int32_t *, void *) {
-    set_error("pdx_ivf_export: not implemented yet");
-    return PDX_EUNSUPPORTED;
+pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, const pdx_ivf_params *params,
+                         void *index_mem, size_t index_bytes, void *stream, pdx_index **out) {
+    const char *what = "pdx_ivf_build";
+    if (!out) {
+        set_error("pdx_ivf_build: out is null");
+        return PDX_EINVAL;
+    }
+    *out = nullptr;
+    if (!x || !index_mem || !params) {
+        set_error("pdx_ivf_build: null data, index or params pointer");
+        return PDX_EINVAL;
+    }
+    if (!valid_shape(n, d, nlist)) {
+        set_error("pdx_ivf_build: need 1 <= nlist <= min(n, %d), 1 <= d <= %d, n < 2^31 (n=%lld d=%d nlist=%d)",
+                  kMaxNlist, PDX_MAX_DIM, (long long)n, d, nlist);
+        return PDX_EINVAL;
+    }
+    if (!params->centroids && !params->init_rows) {
+        set_error("pdx_ivf_build: init_rows is required unless centroids are given");
+        return PDX_EINVAL;
+    }
+    if (params->assign && !params->centroids) {
+        set_error("pdx_ivf_build: assign needs centroids");
+        return PDX_EINVAL;
+    }
+    if (params->dtype != PDX_DTYPE_F32) {
+        set_error("pdx_ivf_build: only f32 storage is implemented");
+        return PDX_EUNSUPPORTED;
+    }
+    if (!aligned16(x) || !aligned16(index_mem)) {
+        set_error("pdx_ivf_build: pointers must be 16-byte aligned");
+        return PDX_EINVAL;
+    }
+    IvfLayout L = ivf_layout(n, d, nlist, index_mem);
+    if (index_bytes < L.bytes) {
+        set_error("pdx_ivf_build: index buffer has %zu bytes, needs %zu", index_bytes, L.bytes);
+        return PDX_EWORKSPACE;
+    }
+    const int32_t iters = params->kmeans_iters > 0 ? params->kmeans_iters : 20;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TRY(launch_fill_i32(L.flag, 1, 0, s));
+    TRY(launch_finite_check(x, n * d, L.flag, s));
+    {
+        int32_t hf = 0;
+        TRY(hipMemcpyAsync(&hf, L.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+        if (hf) {
+            set_error("pdx_ivf_build: data holds NaN or Inf");
+            return PDX_EINVAL;
+        }
+    }
+    // rotation
+    int32_t has_rot = 1;
+    if (params->rotation) {
+        TRY(hipMemcpyAsync(L.rot, params->rotation, sizeof(float) * d * d, hipMemcpyDeviceToDevice, s));
+    } else if (params->gaussian) {
+        TRY(launch_qr_rotation(params->gaussian, d, L.acm, L.qd, L.v, L.diag, L.rot, s));
+    } else {
+        has_rot = 0;
+        identity_kernel<<<(unsigned)(((int64_t)d * d + 255) / 256), 256, 0, s>>>(L.rot, d);
+        TRY(hipGetLastError());
+    }
+    if (has_rot)
+        TRY(launch_pair(0, 0, x, n, L.rot, d, d, L.xrot, d, nullptr, s));
+    else
+        TRY(hipMemcpyAsync(L.xrot, x, sizeof(float) * n * d, hipMemcpyDeviceToDevice, s));
+    // centroids: given, or Lloyd iterations from the seed rows
+    if (params->centroids) {
+        TRY(hipMemcpyAsync(L.centroids, params->centroids, sizeof(float) * nlist * d, hipMemcpyDeviceToDevice, s));
+    } else {
+        TRY(launch_gather_rows(L.xrot, n, d, params->init_rows, nlist, L.centroids, L.flag, s));
+        for (int32_t it = 0; it < iters; ++it) {
+            TRY(launch_fill_u64(L.best, n, ~0ull, s));
+            TRY(launch_pair(1, 1, L.xrot, n, L.centroids, nlist, d, nullptr, 0, L.best, s));
+            TRY(launch_labels_from_keys(L.best, n, L.assign, s));
+            TRY(launch_kmeans_update(L.xrot, n, d, L.assign, nlist, L.sums, L.cnt, L.centroids, s));
+        }
+    }
+    // final assignment
+    if (params->assign) {
+        TRY(hipMemcpyAsync(L.assign, params->assign, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        TRY(launch_check_labels(L.assign, n, nlist, L.flag, s));
+    } else {
+        TRY(launch_fill_u64(L.best, n, ~0ull, s));
+        TRY(launch_pair(1, 1, L.xrot, n, L.centroids, nlist, d, nullptr, 0, L.best, s));
+        TRY(launch_labels_from_keys(L.best, n, L.assign, s));
+    }
+    // the flag must be read before bucketing trusts the labels
+    int32_t hflag = 0;
+    TRY(hipMemcpyAsync(&hflag, L.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    if (hflag) {
+        set_error("pdx_ivf_build: %s", (hflag & 1)   ? "data holds NaN or Inf"
+                                       : (hflag & 2) ? "init_rows holds a row outside [0, n)"
+                                                     : "assign holds a bucket outside [0, nlist)");
+        return PDX_EINVAL;
+    }
+    TRY(launch_bucketize(L.xrot, n, d, L.assign, nlist, L.blk_cnt, L.list_size, L.list_goff, L.stats, L.slot_id,
+                         L.max_groups * kGroup, L.pdx, L.max_groups, s));
+    int32_t hstats[2] = {0, 0};
+    TRY(hipMemcpyAsync(hstats, L.stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    pdx_index *ix = new (std::nothrow) pdx_index{};
+    if (!ix) {
+        set_error("pdx_ivf_build: out of host memory");
+        return PDX_EINVAL;
+    }
+    ix->kind = kIvf;
+    ix->n = n;
+    ix->d = d;
+    ix->group = kGroup;
+    ix->ngroups = hstats[0];
+    ix->max_list = hstats[1];
+    ix->nlist = nlist;
+    ix->dtype_mask = 1 << PDX_DTYPE_F32;
+    ix->has_rot = has_rot;
+    ix->rot = L.rot;
+    ix->centroids = L.centroids;
+    ix->list_goff = L.list_goff;
+    ix->list_size = L.list_size;
+    ix->slot_id = L.slot_id;
+    ix->assign = L.assign;
+    ix->pdx = L.pdx;
+    *out = ix;
+    return PDX_OK;
 }
 
-size_t pdx_search_ivf_workspace(const pdx_index *, int64_t, int32_t, int32_t, const pdx_ivf_search_params *) {
-    return 0;
+pdx_status pdx_ivf_export(const pdx_index *index, float *rotation, float *centroids, int32_t *assign,
+                          int32_t *list_sizes, void *stream) {
+    const char *what = "pdx_ivf_export";
+    if (!index || index->kind != kIvf) {
+        set_error("pdx_ivf_export: not an IVF index");
+        return PDX_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t d = index->d;
+    if (rotation) TRY(hipMemcpyAsync(rotation, index->rot, sizeof(float) * d * d, hipMemcpyDeviceToDevice, s));
+    if (centroids)
+        TRY(hipMemcpyAsync(centroids, index->centroids, sizeof(float) * index->nlist * d, hipMemcpyDeviceToDevice,
+                           s));
+    if (assign) TRY(hipMemcpyAsync(assign, index->assign, sizeof(int32_t) * index->n, hipMemcpyDeviceToDevice, s));
+    if (list_sizes)
+        TRY(hipMemcpyAsync(list_sizes, index->list_size, sizeof(int32_t) * index->nlist, hipMemcpyDeviceToDevice, s));
+    return PDX_OK;
 }
 
-pdx_status pdx_search_ivf(const pdx_index *index, const float *, int64_t, int32_t, int32_t,
-                          const pdx_ivf_search_params *, void *, size_t, int64_t *, float *, void *) {
+size_t pdx_search_ivf_workspace(const pdx_index *index, int64_t nq, int32_t k, int32_t nprobe,
+                                const pdx_ivf_search_params *params) {
+    if (!index || index->kind != kIvf || nq < 0 || k < 1 || k > PDX_MAX_K || nprobe < 1 || nprobe > index->nlist)
+        return 0;
+    return ivf_plan(index, nq, k, nprobe, params, nullptr, nullptr);
+}
+
+pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, int32_t k, int32_t nprobe,
+                          const pdx_ivf_search_params *params, void *ws, size_t ws_bytes, int64_t *out_ids,
+                          float *out_dist, void *stream) {
+    const char *what = "pdx_search_ivf";
     if (!index || index->kind != kIvf) {
         set_error("pdx_search_ivf: not an IVF index");
         return PDX_EINVAL;
     }
-    set_error("pdx_search_ivf: not implemented yet");
-    return PDX_EUNSUPPORTED;
+    if (nq < 0 || k < 1 || nprobe < 1 || nprobe > index->nlist) {
+        set_error("pdx_search_ivf: need nq >= 0, k >= 1, 1 <= nprobe <= nlist (%d)", index->nlist);
+        return PDX_EINVAL;
+    }
+    if (k > PDX_MAX_K) {
+        set_error("pdx_search_ivf: k=%d above PDX_MAX_K=%d", k, PDX_MAX_K);
+        return PDX_EUNSUPPORTED;
+    }
+    if (params && (params->delta_d < 0 || std::isnan(params->eps0) || params->eps0 < 0.0f)) {
+        set_error("pdx_search_ivf: need delta_d >= 0 and eps0 >= 0");
+        return PDX_EINVAL;
+    }
+    if (params && !((index->dtype_mask >> params->dtype) & 1)) {
+        set_error("pdx_search_ivf: dtype %d is not stored in this index", params->dtype);
+        return PDX_EUNSUPPORTED;
+    }
+    if (nq == 0) return PDX_OK;
+    if (!q || !ws || !out_ids || !out_dist) {
+        set_error("pdx_search_ivf: null pointer");
+        return PDX_EINVAL;
+    }
+    if (!aligned16(q) || !aligned16(ws)) {
+        set_error("pdx_search_ivf: pointers must be 16-byte aligned");
+        return PDX_EINVAL;
+    }
+    if (nq * (int64_t)nprobe >= (int64_t(1) << 31)) {
+        set_error("pdx_search_ivf: nq * nprobe too large");
+        return PDX_EINVAL;
+    }
+    IvfPlan plan;
+    size_t need = ivf_plan(index, nq, k, nprobe, params, ws, &plan);
+    if (ws_bytes < need) {
+        set_error("pdx_search_ivf: workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return PDX_EWORKSPACE;
+    }
+    TRY(run_ivf(index, q, plan, out_ids, out_dist, static_cast<hipStream_t>(stream)));
+    return PDX_OK;
 }
 
 }  // extern "C"
