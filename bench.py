@@ -1,19 +1,26 @@
 #!/usr/bin/env python3
-"""Throughput of the exact PDX-BOND K-NN search on one MI355X.
+"""Throughput of the PDX K-NN search on one MI355X.
 
-One step = one pdx_search_exact call over a batch of queries that are
-already resident in HBM: query preparation (distance-to-means order),
-START over the first block, the pruned chunked scan, and the k-best merge.
-Default workload: 1,000,000 x 960 float32 vectors (skewed Gaussian
-mixture standing in for GIST/960), 1,000 queries, K = 10.
+Default workload (``bond_1m_d960``): 1,000,000 x 960 float32 vectors (a
+skewed Gaussian mixture standing in for GIST/960), 1,000 queries, K = 10.
 
-Prints ONE JSON line (see the keys below), including
-  * roofline   -- the pruned-scan kernel: algorithmic bytes (values the
-                  method evaluates x 4 B, from the library's own counters)
-                  over that kernel's time measured with HIP events recorded
-                  on the search stream, against 8 TB/s HBM;
-  * cpu_baseline -- the FP64 oracle timed on a bounded sample of the same
-                  queries with every host core.
+* value: exact PDX-BOND queries per second.  One step = one
+  pdx_search_exact call over the whole query batch, inputs resident in HBM:
+  query preparation (distance-to-means order), START over the first block,
+  the pruned chunked scan, the k-best merge.
+* extra.approx: IVF + ADSampling over the same vectors (nlist 1024):
+  queries per second and recall@10 per nprobe, and the throughput at the
+  smallest nprobe reaching recall@10 >= 0.95 (recall measured against the
+  FP64 oracle on the sample of queries the CPU baseline leg computes).
+* roofline: the dominant kernel (the pruned scan): algorithmic bytes (values
+  the method evaluates x 4 B, from the library's counters) over that
+  kernel's time (HIP events recorded on the search stream), against 8 TB/s.
+* cpu_baseline: the FP64 oracle timed on a bounded sample of the same
+  queries with every host core.
+
+Other workloads: ``ivf_1m_d1536`` (IVF + ADSampling, 10,000 queries, value
+= queries/s at recall@10 >= 0.95), ``linear_10k_d128`` (exact linear scan).
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -28,14 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-
-def _hip():
-    lib = ctypes.CDLL("libamdhip64.so.7")
-    lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
-    lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
-    lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
-    return lib
+METRIC = "QPS (K=10) exact + at recall@10>=0.95, 1Mx960 fp32; achieved HBM GB/s"
 
 
 def profiled_traffic(profile_md: str):
@@ -56,13 +56,109 @@ def profiled_traffic(profile_md: str):
     return info["traffic_bytes_per_launch"], f"profiles/{profile_md}"
 
 
+class Events:
+    """hipEvent_t handles created through the HIP runtime torch loaded."""
+
+    def __init__(self, count: int):
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.arr = (ctypes.c_void_p * count)()
+        for i in range(count):
+            ev = ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(ev)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.arr[i] = ev.value
+
+    def group(self, i: int, per: int = 4):
+        return ctypes.cast(ctypes.byref(self.arr, per * i * ctypes.sizeof(ctypes.c_void_p)),
+                           ctypes.POINTER(ctypes.c_void_p))
+
+    def ms(self, a: int, b: int) -> float:
+        f = ctypes.c_float()
+        self.hip.hipEventElapsedTime(ctypes.byref(f), ctypes.c_void_p(self.arr[a]), ctypes.c_void_p(self.arr[b]))
+        return f.value
+
+
+def timed_steps(run, steps, warmup, torch, np):
+    """warmup + `steps` timed calls; run(events) enqueues one step."""
+    ev = Events(4 * max(steps, 1))
+    for _ in range(warmup):
+        run(None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        run(ev.group(i))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ph = [[ev.ms(4 * i + a, 4 * i + a + 1) for i in range(steps)] for a in range(3)]
+    return elapsed, [float(np.mean(p)) for p in ph]
+
+
+def oracle_sample(x_np, q_np, k, budget_s, np):
+    """FP64 oracle on the first queries, in batches of one query per core,
+    until the time budget is spent.  Returns (done, seconds, threads, ids, dist)."""
+    from oracle import exact
+    threads = exact.c_threads()
+    done, tc = 0, 0.0
+    ids, dist = [], []
+    while done < q_np.shape[0] and tc < budget_s:
+        sel = slice(done, min(q_np.shape[0], done + max(1, threads)))
+        t1 = time.perf_counter()
+        wi, wd = exact.knn_exact_c(x_np, q_np[sel], k)
+        tc += time.perf_counter() - t1
+        ids.append(wi)
+        dist.append(wd)
+        done = sel.stop
+    return done, tc, threads, np.concatenate(ids), np.concatenate(dist)
+
+
+def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, truth_ids, seed=42):
+    from oracle.exact import recall_at_k
+    n, d = x_dev.shape
+    nq = q_dev.shape[0]
+    rng = np.random.default_rng(seed)
+    gauss = torch.from_numpy(rng.standard_normal((d, d))).cuda()
+    init = torch.from_numpy(rng.choice(n, nlist, replace=False).astype(np.int64)).cuda()
+    t0 = time.perf_counter()
+    ix = pdx.pdx_ivf_build(x_dev, nlist, gauss, init, kmeans_iters=20)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    print(f"# ivf index built in {build_s:.1f}s", file=sys.stderr, flush=True)
+    sizes = pdx.pdx_ivf_export(ix)[3].cpu().numpy()
+    sweep = []
+    best = None
+    for p in nprobes:
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, p)), dtype=torch.uint8, device="cuda")
+        out = {}
+
+        def run(evs, p=p, ws=ws, out=out):
+            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, p, eps0=2.1, workspace=ws, phase_events=evs)
+
+        elapsed, ph = timed_steps(run, steps, warmup, torch, np)
+        ids = out["r"][0].cpu().numpy()
+        rec = recall_at_k(truth_ids, ids[: truth_ids.shape[0]]) if truth_ids is not None else None
+        row = {"nprobe": p, "qps": round(nq * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
+               "recall@10": None if rec is None else round(rec, 4),
+               "phases_ms": {"prep_start": round(ph[0], 3), "pruned_scan": round(ph[1], 3), "merge": round(ph[2], 3)}}
+        print(f"# nprobe {p}: {row['qps']} qps recall {row['recall@10']}", file=sys.stderr, flush=True)
+        sweep.append(row)
+        if rec is not None and rec >= 0.95 and best is None:
+            best = row
+    return {"nlist": nlist, "kmeans_iters": 20, "build_s": round(build_s, 2), "eps0": 2.1, "delta_d": 32,
+            "list_sizes": {"min": int(sizes.min()), "median": int(np.median(sizes)), "max": int(sizes.max())},
+            "sweep": sweep, "recall_queries": None if truth_ids is None else int(truth_ids.shape[0]),
+            "qps_at_recall_0.95": None if best is None else best["qps"],
+            "nprobe_at_recall_0.95": None if best is None else best["nprobe"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="bond_1m_d960")
-    ap.add_argument("--mode", default="bond", choices=["bond", "linear"])
+    ap.add_argument("--workload", default="bond_1m_d960",
+                    choices=["bond_1m_d960", "ivf_1m_d1536", "linear_10k_d128"])
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--tile-groups", type=int, default=0)
     ap.add_argument("--qpb", type=int, default=0)
@@ -70,6 +166,7 @@ def main() -> int:
                     help="wall-time budget of the oracle's CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-linear", action="store_true", help="skip the unpruned comparison run")
+    ap.add_argument("--no-ivf", action="store_true", help="skip the IVF + ADSampling leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -86,8 +183,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described "
-                                   "in DESIGN.md but not implemented", "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "this build runs on one GPU only (DESIGN.md describes how the path would "
+                                   "shard)", "n_gpus": args.gpus}), flush=True)
         return 2
 
     import numpy as np
@@ -101,89 +198,77 @@ def main() -> int:
     x_np, q_np, _ = synth.workload(args.workload)
     n, d = x_np.shape
     nq = q_np.shape[0]
+    k = args.k
     print(f"# generated {n} x {d}, {nq} queries in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     x = torch.from_numpy(x_np).cuda()
     q = torch.from_numpy(q_np).cuda()
+
+    cpu = None
+    truth = truth_d = None
+    if not args.no_cpu_baseline:
+        done, tc, threads, truth, truth_d = oracle_sample(x_np, q_np, k, args.cpu_seconds, np)
+        cpu = {"value": round(done / tc, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {done} of {nq} queries against all {n} x {d} vectors, FP64 brute force "
+                         f"(C, OpenMP, {threads} threads), {tc:.1f}s"}
+        print(f"# oracle sample {done} queries in {tc:.1f}s", file=sys.stderr, flush=True)
+
+    if args.workload == "ivf_1m_d1536":
+        res = bench_ivf(pdx, torch, np, x, q, 1024, [8, 16, 32, 64], k, args.steps, args.warmup, truth)
+        best = res["qps_at_recall_0.95"]
+        out = {"metric": METRIC, "value": best, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "index": "ivf",
+                          "nlist": 1024, "nprobe_sweep": [8, 16, 32, 64], "exact": False},
+               "roofline": None, "cpu_baseline": cpu, "extra": {"approx": res}}
+        print(json.dumps(out), flush=True)
+        return 0
+
+    mode = "linear" if args.workload == "linear_10k_d128" else "bond"
     ix = pdx.pdx_build(x)
-    del x
     torch.cuda.synchronize()
     print("# index built", file=sys.stderr, flush=True)
-
-    k = args.k
-    kw = dict(mode=args.mode, tile_groups=args.tile_groups, queries_per_block=args.qpb)
+    kw = dict(mode=mode, tile_groups=args.tile_groups, queries_per_block=args.qpb)
     ws = torch.empty(max(1, pdx.pdx_search_exact_workspace(ix, nq, k, **kw)), dtype=torch.uint8, device="cuda")
     ids = torch.empty((nq, k), dtype=torch.int64, device="cuda")
     dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
 
-    hip = _hip()
-    steps = args.steps
-    evs = (ctypes.c_void_p * (4 * max(steps, 1)))()
-    for i in range(4 * max(steps, 1)):
-        ev = ctypes.c_void_p()
-        if hip.hipEventCreate(ctypes.byref(ev)) != 0:
-            raise RuntimeError("hipEventCreate failed")
-        evs[i] = ev.value
-    ev_ptr = [ctypes.cast(ctypes.byref(evs, 4 * i * ctypes.sizeof(ctypes.c_void_p)), ctypes.POINTER(ctypes.c_void_p))
-              for i in range(max(steps, 1))]
-
     def step(events=None, counters=None):
         pdx.pdx_search_exact(ix, q, k, workspace=ws, out=(ids, dist), phase_events=events, counters=counters, **kw)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    t_start = time.perf_counter()
-    for i in range(steps):
-        step(events=ev_ptr[i])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    elapsed, ph = timed_steps(step, args.steps, args.warmup, torch, np)
+    steps = args.steps
     ms_per_step = 1e3 * elapsed / steps
     qps = nq * steps / elapsed
-
-    def ev_ms(a, b):
-        f = ctypes.c_float()
-        hip.hipEventElapsedTime(ctypes.byref(f), ctypes.c_void_p(evs[a]), ctypes.c_void_p(evs[b]))
-        return f.value
-
-    phases = {"prep_start_ms": [], "scan_ms": [], "merge_ms": []}
-    for i in range(steps):
-        phases["prep_start_ms"].append(ev_ms(4 * i, 4 * i + 1))
-        phases["scan_ms"].append(ev_ms(4 * i + 1, 4 * i + 2))
-        phases["merge_ms"].append(ev_ms(4 * i + 2, 4 * i + 3))
-    phase_ms = {kk: float(np.mean(v)) for kk, v in phases.items()}
+    phase_ms = {"prep_start_ms": ph[0], "scan_ms": ph[1], "merge_ms": ph[2]}
 
     # algorithmic work from the library's counters (separate, untimed call)
     cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
     step(counters=cnt)
     torch.cuda.synchronize()
     c = cnt.cpu().numpy().astype(np.float64)
-    scan_values = c[2]
-    scan_bytes = 4.0 * scan_values
-    start_values = c[0]
-    got_ids = ids.cpu().numpy()
-    got_dist = dist.cpu().numpy()
+    got_ids, got_dist = ids.cpu().numpy(), dist.cpu().numpy()
+    if truth is not None:
+        from tests.parity import check_knn
+        s = truth.shape[0]
+        check_knn(x_np, q_np[:s], got_ids[:s], got_dist[:s], truth, truth_d)
+        cpu["sample"] += "; the GPU results of the same queries matched it"
 
-    if args.mode == "bond":
-        kern_ms = phase_ms["scan_ms"]
-        kern_name = "scan_kernel<true> (pruned chunked scan)"
-    else:
-        kern_ms = phase_ms["scan_ms"]
-        kern_name = "scan_kernel<false> (linear scan)"
+    kern_ms = phase_ms["scan_ms"]
+    scan_bytes = 4.0 * c[2]
     achieved = scan_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
     traffic, traffic_src = (profiled_traffic("scan_bond_1m_d960.md")
-                            if (args.mode, args.workload, k) == ("bond", "bond_1m_d960", 10) else (None, "n/a"))
-    roofline = {"bound": "hbm", "kernel": kern_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_source": traffic_src,
+                            if (mode, args.workload, k) == ("bond", "bond_1m_d960", 10) else (None, "n/a"))
+    roofline = {"bound": "hbm", "kernel": f"pruned chunked scan ({mode})", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "traffic_source": traffic_src,
                 "algorithmic_bytes_per_launch": scan_bytes, "kernel_ms": round(kern_ms, 4),
                 "lane_efficiency": round(c[2] / c[3], 4) if c[3] else None}
-
     extra = {"phases_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
-             "values_evaluated": {"start": start_values, "scan": scan_values,
-                                  "pruning_power": round(1.0 - (start_values + scan_values) / (nq * n * d), 5)}}
+             "values_evaluated": {"start": c[0], "scan": c[2],
+                                  "pruning_power": round(1.0 - (c[0] + c[2]) / (nq * n * d), 5)}}
 
-    if args.mode == "bond" and not args.no_linear:
+    if mode == "bond" and not args.no_linear:
         lin_ws = torch.empty(max(1, pdx.pdx_search_exact_workspace(ix, nq, k, mode="linear")), dtype=torch.uint8,
                              device="cuda")
         pdx.pdx_search_exact(ix, q[:8], k, mode="linear")
@@ -194,29 +279,12 @@ def main() -> int:
         tl = time.perf_counter() - tl
         extra["own_linear_scan"] = {"qps": round(nq / tl, 1), "ms": round(1e3 * tl, 2),
                                     "note": "same kernels, no pruning (PDX linear scan)"}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import exact
-        from tests.parity import check_knn
-        threads = exact.c_threads()
-        budget = args.cpu_seconds
-        done = 0
-        tc = 0.0
-        chunk = max(1, threads)
-        while done < nq and tc < budget:
-            sel = slice(done, min(nq, done + chunk))
-            t1 = time.perf_counter()
-            wi, wd = exact.knn_exact_c(x_np, q_np[sel], k)
-            tc += time.perf_counter() - t1
-            check_knn(x_np, q_np[sel], got_ids[sel], got_dist[sel], wi, wd)
-            done = sel.stop
-        cpu = {"value": round(done / tc, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {done} of {nq} queries against all {n} x {d} vectors, FP64 brute force "
-                         f"(C, OpenMP), {tc:.1f}s; GPU results of the same queries matched it"}
+    del ws
+    if mode == "bond" and not args.no_ivf:
+        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, [2, 4, 8, 16, 32, 64], k, 3, 1, truth)
 
     out = {
-        "metric": "QPS (K=10) exact + at recall@10>=0.95, 1Mx960 fp32; achieved HBM GB/s",
+        "metric": METRIC,
         "value": round(qps, 2),
         "unit": "queries/s",
         "n_gpus": 1,
@@ -228,7 +296,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "mode": args.mode,
+        "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "mode": mode,
                    "chunk": 32, "start_rows": 10000, "exact": True},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -12,5 +12,6 @@ from .api import (  # noqa: F401
     pdx_search_exact,
     pdx_search_exact_workspace,
     pdx_search_ivf,
+    pdx_search_ivf_workspace,
     pdx_version,
 )

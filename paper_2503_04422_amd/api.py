@@ -81,7 +81,7 @@ def pdx_build(x: torch.Tensor, start_rows: int = 0,
 
 def pdx_search_exact_workspace(index: PdxIndex, nq: int, k: int, mode: str = "bond", chunk: int = 0,
                                tile_groups: int = 0, queries_per_block: int = 0) -> int:
-    p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block)
+    p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block, None, None)
     return int(lib.pdx_search_exact_workspace(index.handle, nq, k, ctypes.byref(p)))
 
 
@@ -157,15 +157,26 @@ def pdx_ivf_export(index: PdxIndex, stream: Optional[torch.cuda.Stream] = None):
     return rot, cen, asg, sizes
 
 
+def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delta_d: int = 0,
+                             dtype: str = "f32", rerank: int = 0) -> int:
+    p = _lib.pdx_ivf_search_params(2.1, int(delta_d), _DTYPES[dtype], int(rerank), None, None)
+    return int(lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p)))
+
+
 def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1,
                    delta_d: int = 0, dtype: str = "f32", rerank: int = 0,
-                   workspace: Optional[torch.Tensor] = None,
+                   workspace: Optional[torch.Tensor] = None, phase_events=None,
+                   counters: Optional[torch.Tensor] = None,
                    stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Approximate k nearest neighbours (IVF + ADSampling)."""
     q = _dev_f32(q, "q")
     nq = q.shape[0]
+    if q.shape[1] != index.d:
+        raise ValueError("query dimension does not match the index")
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
-                                   _DTYPES[dtype], int(rerank))
+                                   _DTYPES[dtype], int(rerank),
+                                   ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
+                                   _ptr(counters))
     ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
     need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
