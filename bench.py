@@ -183,8 +183,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only (DESIGN.md describes how the path would "
-                                   "shard)", "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "only one GPU is supported: the search runs on a single MI355X and no "
+                                   "multi-GPU sharding is implemented", "n_gpus": args.gpus}), flush=True)
         return 2
 
     import numpy as np
