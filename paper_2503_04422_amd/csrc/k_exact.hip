@@ -2,23 +2,32 @@
 // the chunked PDX scan with the partial-distance bound, and the k-best
 // merge.
 //
-// Mapping (one wave = one query x one vectorgroup at a time):
-//  * lane i owns vector i of the group, so every dimension is one coalesced
-//    256-byte row load (the kernel listing of Section 3, vectors across
-//    lanes instead of SIMD slots);
-//  * dimensions are visited in chunks in the query's order; after every
-//    chunk the lanes whose partial distance is strictly above the running
-//    k-th distance drop out (Sections 2.3 and 5) and a group whose lanes
-//    have all dropped is left (wave-level break-off, Section 4 PRUNE);
-//  * survivors of the last chunk enter a register k-best list of the wave;
-//    its k-th distance is published to a per-query threshold with an
-//    atomic minimum, which every wave reads before each group (threshold
-//    propagation between blocks, Section 4).  Any wave's k-th distance is
-//    an upper bound of the final one, so pruning against the minimum over
-//    waves never drops a true neighbour, and ties survive (strict test).
-//  * each vector's partial sum is accumulated chunk by chunk in the query's
-//    dimension order with fused multiply-adds, so its final distance is the
-//    same float32 value whichever wave or launch computed it.
+// Every vector's distance to a query is accumulated in one fixed order:
+// chunk by chunk in the query's visit order, each chunk as (fused
+// multiply-adds over its first 16 dimensions) + (over the rest), then added
+// to the running partial.  Whichever kernel, wave or launch evaluates a
+// (query, vector) pair therefore produces the same float32 value, and the
+// partial after any chunk is a lower bound of the full distance (sums of
+// non-negative terms are monotone under round-to-nearest).
+//
+// Two scan kernels:
+//  * scan_kernel ("group" path): one wave = one query x one vectorgroup at
+//    a time, lane i = vector i, so each dimension is one coalesced 256-byte
+//    row (the kernel listing of Section 3 with vectors across lanes); lanes
+//    drop out when their partial distance passes the threshold and the wave
+//    leaves the group when all lanes have dropped.  Used for START, the
+//    linear mode, shapes the tile path does not take, and as the fallback of
+//    the tile path.
+//  * tile_kernel ("tile" path): a workgroup stages 32 vectors x all D
+//    dimensions in LDS once and scans them for every query of the batch, so
+//    HBM is read once per batch instead of once per query.  The first chunk
+//    is scanned densely (lanes = 32 vectors x 2 half-chunks); the few
+//    survivors go to an LDS queue and are finished by "persistent" lanes,
+//    each lane carrying one (query, vector) pair chunk by chunk and taking a
+//    new pair from the queue when its pair is pruned or complete.  Completed
+//    pairs (distance <= threshold) are appended to a per-query candidate
+//    buffer; between rounds of tiles the threshold becomes the k-th smallest
+//    candidate (threshold propagation between blocks, Section 4).
 #include "pdx_internal.h"
 #include "wave_topk.h"
 
@@ -29,10 +38,11 @@ namespace {
 // Query preparation: visit order and permuted query values.
 // PDX-BOND (Section 5): dimensions by |q_j - mean_j| descending, ties by j.
 // Sort key (ascending): (~bits(|q_j - mean_j|) << 32) | j.
+// perm[j] is the j-th visited dimension; qperm[j] the query value there.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, int32_t d,
                                                    const float *__restrict__ means, int32_t mode,
-                                                   int32_t pow2, int32_t *__restrict__ perm_off,
+                                                   int32_t pow2, int32_t *__restrict__ perm,
                                                    float *__restrict__ qperm,
                                                    uint32_t *__restrict__ tau,
                                                    int32_t *__restrict__ bad) {
@@ -48,11 +58,11 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
         nonfinite |= !isfinite(v);
     }
     nonfinite = __syncthreads_or(nonfinite);
-    int32_t *po = perm_off + qi * d;
+    int32_t *po = perm + qi * d;
     float *qp = qperm + qi * d;
     if (mode == PDX_MODE_LINEAR) {
         for (int j = threadIdx.x; j < d; j += blockDim.x) {
-            po[j] = j * kGroup;
+            po[j] = j;
             qp[j] = qs[j];
         }
     } else {
@@ -83,7 +93,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
         }
         for (int j = threadIdx.x; j < d; j += blockDim.x) {
             int32_t src = static_cast<int32_t>(keys[j] & 0xffffffffu);
-            po[j] = src * kGroup;
+            po[j] = src;
             qp[j] = qs[src];
         }
     }
@@ -93,65 +103,53 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
     }
 }
 
-// Sum of (q_j - x_j)^2 over dimensions [c0, c1) of the visit order, one
-// fused multiply-add after the other starting from zero.
-template <int UNROLL>
+// Chunk [c0, c1) of the visit order for one lane's vector: the first 16
+// dimensions and the rest are summed separately, then added.
+template <bool FULL32>
 __device__ __forceinline__ float chunk_sum(const float *__restrict__ gp, const int32_t *__restrict__ po,
                                            const float *__restrict__ qp, int32_t c0, int32_t c1) {
-    float s = 0.0f;
-    int32_t j = c0;
-    for (; j + UNROLL <= c1; j += UNROLL) {
-        float x[UNROLL];
+    float lo = 0.0f, hi = 0.0f;
+    if (FULL32) {
+        float x[32];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) x[u] = gp[po[j + u]];
+        for (int u = 0; u < 32; ++u) x[u] = gp[po[c0 + u] * kGroup];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            float t = qp[j + u] - x[u];
-            s = fmaf(t, t, s);
+        for (int u = 0; u < 16; ++u) {
+            float t = qp[c0 + u] - x[u];
+            lo = fmaf(t, t, lo);
+        }
+#pragma unroll
+        for (int u = 16; u < 32; ++u) {
+            float t = qp[c0 + u] - x[u];
+            hi = fmaf(t, t, hi);
+        }
+    } else {
+        const int32_t mid = min(c0 + 16, c1);
+        for (int32_t j = c0; j < mid; ++j) {
+            float t = qp[j] - gp[po[j] * kGroup];
+            lo = fmaf(t, t, lo);
+        }
+        for (int32_t j = mid; j < c1; ++j) {
+            float t = qp[j] - gp[po[j] * kGroup];
+            hi = fmaf(t, t, hi);
         }
     }
-    for (; j < c1; ++j) {
-        float t = qp[j] - gp[po[j]];
-        s = fmaf(t, t, s);
-    }
-    return s;
+    return lo + hi;
 }
 
-// ---------------------------------------------------------------------------
-// Chunked scan over vectorgroups [g_begin, g_end).
-// Work item = (tile of tile_groups groups, block of qpb queries); wave w of
-// a workgroup serves query qb*qpb + w.  Workgroup ids are spread so that all
-// query blocks of one tile run on the same XCD (ids are dealt round-robin to
-// the 8 XCDs), keeping the tile's rows in that XCD's L2.
-// ---------------------------------------------------------------------------
+// One wave scans groups [g0, g1) for query qi and writes its k-best list to
+// myslot.  PRUNE: drop lanes whose partial exceeds the threshold.
 template <bool PRUNE>
-__global__ __launch_bounds__(512) void scan_kernel(
-    const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t g_begin, int32_t g_end,
-    int32_t tile_groups, int32_t ntiles, int32_t nqb, int64_t nq, int32_t qpb,
-    const int32_t *__restrict__ perm_off, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
-    const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t nslots, int32_t slot0,
-    int32_t k, int32_t chunk, unsigned long long *__restrict__ counters) {
-    const uint32_t L = blockIdx.x;
-    const int32_t xcd = L & 7;
-    const uint32_t r = L >> 3;
-    const int32_t qb = r % nqb;
-    const int32_t tile = (r / nqb) * 8 + xcd;
-    if (tile >= ntiles) return;
-    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t g0,
+                                            int32_t g1, int64_t qi, const int32_t *__restrict__ perm,
+                                            const float *__restrict__ qperm, uint32_t *__restrict__ tau,
+                                            uint64_t *__restrict__ myslot, int32_t k, int32_t chunk,
+                                            unsigned long long *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
-    const int64_t qi = (int64_t)qb * qpb + wave;
-    if (qi >= nq) return;
-    uint64_t *myslot = slots + ((size_t)qi * nslots + slot0 + tile) * k;
-    if (bad[qi]) {
-        if (lane < k) myslot[lane] = kEmptyKey;
-        return;
-    }
-    const int32_t *po = perm_off + qi * d;
+    const int32_t *po = perm + qi * d;
     const float *qp = qperm + qi * d;
     uint64_t e = kEmptyKey;    // this lane's entry of the wave's k-best list
     uint64_t kth = kEmptyKey;  // k-th entry (wave-uniform)
-    const int32_t g0 = g_begin + tile * tile_groups;
-    const int32_t g1 = min(g0 + tile_groups, g_end);
     unsigned long long live_vals = 0, lane_vals = 0;  // instrumentation only
     for (int32_t g = g0; g < g1; ++g) {
         float tau_eff = INFINITY;
@@ -172,7 +170,7 @@ __global__ __launch_bounds__(512) void scan_kernel(
                 lane_vals += 64ull * (c1 - c0);
             }
             float s = 0.0f;
-            if (alive) s = (c1 - c0 == 32) ? chunk_sum<32>(gp, po, qp, c0, c1) : chunk_sum<8>(gp, po, qp, c0, c1);
+            if (alive) s = (c1 - c0 == 32) ? chunk_sum<true>(gp, po, qp, c0, c1) : chunk_sum<false>(gp, po, qp, c0, c1);
             partial += s;
             if (PRUNE) alive = alive && !(partial > tau_eff);
         }
@@ -190,15 +188,70 @@ __global__ __launch_bounds__(512) void scan_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Group path over vectorgroups [g_begin, g_end).
+// Work item = (tile of tile_groups groups, block of qpb queries); wave w of
+// a workgroup serves query qb*qpb + w.  Workgroup ids are spread so that all
+// query blocks of one tile run on the same XCD (ids are dealt round-robin to
+// the 8 XCDs), keeping the tile's rows in that XCD's L2.
+// ---------------------------------------------------------------------------
+template <bool PRUNE>
+__global__ __launch_bounds__(512) void scan_kernel(
+    const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t g_begin, int32_t g_end,
+    int32_t tile_groups, int32_t ntiles, int32_t nqb, int64_t nq, int32_t qpb,
+    const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
+    const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t nslots, int32_t slot0,
+    int32_t k, int32_t chunk, unsigned long long *__restrict__ counters) {
+    const uint32_t L = blockIdx.x;
+    const int32_t xcd = L & 7;
+    const uint32_t r = L >> 3;
+    const int32_t qb = r % nqb;
+    const int32_t tile = (r / nqb) * 8 + xcd;
+    if (tile >= ntiles) return;
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t qi = (int64_t)qb * qpb + wave;
+    if (qi >= nq) return;
+    uint64_t *myslot = slots + ((size_t)qi * nslots + slot0 + tile) * k;
+    if (bad[qi]) {
+        if (lane < k) myslot[lane] = kEmptyKey;
+        return;
+    }
+    const int32_t g0 = g_begin + tile * tile_groups;
+    const int32_t g1 = min(g0 + tile_groups, g_end);
+    scan_groups<PRUNE>(pdxd, n, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
+}
+
+// Group path for the queries whose candidate buffer overflowed in the tile
+// path: every (listed query, group tile) pair, grid-stride.
+__global__ __launch_bounds__(256) void fallback_kernel(
+    const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t g_begin, int32_t g_end, int32_t tile_groups,
+    int32_t ntiles, const int32_t *__restrict__ over_list, const int32_t *__restrict__ over_count,
+    const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
+    uint64_t *__restrict__ slots, int32_t nslots, int32_t slot0, int32_t k, int32_t chunk) {
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t total = (int64_t)(*over_count) * ntiles;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < total; it += (int64_t)gridDim.x * 4) {
+        const int64_t qi = over_list[it / ntiles];
+        const int32_t tile = (int32_t)(it % ntiles);
+        const int32_t g0 = g_begin + tile * tile_groups;
+        const int32_t g1 = min(g0 + tile_groups, g_end);
+        scan_groups<true>(pdxd, n, d, g0, g1, qi, perm, qperm, tau, slots + ((size_t)qi * nslots + slot0 + tile) * k,
+                          k, chunk, nullptr);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k-best of a query's slots [slot_begin, slot_begin + slot_count).
-// Writes the threshold (k-th distance) and/or the final result.
+// Writes the threshold (k-th distance), the result, and/or the list as
+// the first k entries of the query's candidate buffer.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void merge_kernel(const uint64_t *__restrict__ slots, int32_t nslots,
                                                    int32_t slot_begin, int32_t slot_count, int32_t k,
                                                    const int32_t *__restrict__ bad,
                                                    uint32_t *__restrict__ tau,
                                                    int64_t *__restrict__ out_ids,
-                                                   float *__restrict__ out_dist) {
+                                                   float *__restrict__ out_dist, uint64_t *__restrict__ cand,
+                                                   int32_t *__restrict__ cand_cnt, int32_t cap) {
     const int64_t qi = blockIdx.x;
     const int lane = threadIdx.x;
     const uint64_t *base = slots + ((size_t)qi * nslots + slot_begin) * k;
@@ -209,6 +262,10 @@ __global__ __launch_bounds__(64) void merge_kernel(const uint64_t *__restrict__ 
         topk_offer(e, kth, key, key != kEmptyKey, k, lane);
     }
     if (tau && lane == 0 && kth != kEmptyKey) tau[qi] = static_cast<uint32_t>(kth >> 32);
+    if (cand) {
+        if (lane < k) cand[(size_t)qi * cap + lane] = e;
+        if (lane == 0) cand_cnt[qi] = k;
+    }
     if (out_ids && lane < k) {
         int64_t id = -1;
         float dist = INFINITY;
@@ -223,10 +280,312 @@ __global__ __launch_bounds__(64) void merge_kernel(const uint64_t *__restrict__ 
     }
 }
 
+// k-best of a query's candidate buffer (plus, for a query whose buffer
+// overflowed, the first k entries and the fallback slots).  Refresh mode:
+// tighten the threshold; final mode: write the result.
+__global__ __launch_bounds__(64) void cand_merge_kernel(const uint64_t *__restrict__ cand,
+                                                        const int32_t *__restrict__ cand_cnt, int32_t cap,
+                                                        int32_t k, const int32_t *__restrict__ bad,
+                                                        uint32_t *__restrict__ tau,
+                                                        const uint64_t *__restrict__ slots, int32_t nslots,
+                                                        int32_t slot_begin, int32_t slot_count,
+                                                        int64_t *__restrict__ out_ids,
+                                                        float *__restrict__ out_dist) {
+    const int64_t qi = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t cnt = cand_cnt[qi];
+    const bool over = cnt > cap;
+    const uint64_t *cb = cand + (size_t)qi * cap;
+    const int32_t nc = over && out_ids ? k : min(cnt, cap);
+    uint64_t e = kEmptyKey, kth = kEmptyKey;
+    for (int32_t i0 = 0; i0 < nc; i0 += kWave) {
+        uint64_t key = (i0 + lane < nc) ? cb[i0 + lane] : kEmptyKey;
+        topk_offer(e, kth, key, key != kEmptyKey, k, lane);
+    }
+    if (over && out_ids) {
+        const uint64_t *base = slots + ((size_t)qi * nslots + slot_begin) * k;
+        const int64_t total = (int64_t)slot_count * k;
+        for (int64_t i0 = 0; i0 < total; i0 += kWave) {
+            uint64_t key = (i0 + lane < total) ? base[i0 + lane] : kEmptyKey;
+            topk_offer(e, kth, key, key != kEmptyKey, k, lane);
+        }
+    }
+    if (!out_ids) {
+        if (lane == 0 && kth != kEmptyKey) {
+            uint32_t kb = static_cast<uint32_t>(kth >> 32);
+            if (kb < tau[qi]) tau[qi] = kb;
+        }
+        return;
+    }
+    if (lane < k) {
+        int64_t id = -1;
+        float dist = INFINITY;
+        if (bad[qi]) {
+            dist = __uint_as_float(0x7fc00000u);
+        } else if (e != kEmptyKey) {
+            id = static_cast<int64_t>(e & 0xffffffffu);
+            dist = key_dist(e);
+        }
+        out_ids[qi * k + lane] = id;
+        out_dist[qi * k + lane] = dist;
+    }
+}
+
+__global__ void over_list_kernel(const int32_t *__restrict__ cand_cnt, int64_t nq, int32_t cap,
+                                 int32_t *__restrict__ over_list, int32_t *__restrict__ over_count) {
+    int64_t qi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (qi < nq && cand_cnt[qi] > cap) over_list[atomicAdd(over_count, 1)] = (int32_t)qi;
+}
+
+// ---------------------------------------------------------------------------
+// Tile path.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kTV = 32;       // vectors per LDS tile (half a vectorgroup)
+constexpr int kTW = 16;       // waves per workgroup
+constexpr int kQCap = 4096;   // survivor queue entries per tile in LDS
+constexpr int kGCap = 16384;  // further entries per workgroup in global memory
+
+__device__ __forceinline__ void cand_append(uint64_t *__restrict__ cand, int32_t *__restrict__ cnt, int32_t cap,
+                                            int64_t qi, float dist, uint32_t id) {
+    int32_t pos = atomicAdd(cnt + qi, 1);
+    if (pos < cap) cand[(size_t)qi * cap + pos] = make_key(dist, id);
+}
+
+__device__ __forceinline__ int lane_rank(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0));
+}
+
+// Full chunk c of the visit order for vector v of the LDS tile: 16 + 16
+// fused multiply-adds, per-lane query (metadata loaded 16 bytes at a time).
+__device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, const int32_t *__restrict__ po,
+                                            const float *__restrict__ qp, int v) {
+    const int4 *o4 = reinterpret_cast<const int4 *>(po);
+    const float4 *q4 = reinterpret_cast<const float4 *>(qp);
+    float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        int4 o = o4[u];
+        float4 qq = q4[u];
+        float t0 = qq.x - tile[o.x * kTV + v];
+        float t1 = qq.y - tile[o.y * kTV + v];
+        float t2 = qq.z - tile[o.z * kTV + v];
+        float t3 = qq.w - tile[o.w * kTV + v];
+        float &s = u < 4 ? lo : hi;
+        s = fmaf(t0, t0, s);
+        s = fmaf(t1, t1, s);
+        s = fmaf(t2, t2, s);
+        s = fmaf(t3, t3, s);
+    }
+    return lo + hi;
+}
+
+// One query's first visited chunk as this lane's half sees it: 16
+// dimensions and query values, the threshold and the non-finite flag.
+struct FirstChunk {
+    int4 o[4];
+    float4 q[4];
+    float tau;
+    int bad;
+    __device__ __forceinline__ void load(const int32_t *__restrict__ perm, const float *__restrict__ qperm,
+                                         const uint32_t *__restrict__ tau_all, const int32_t *__restrict__ bad_all,
+                                         int64_t qi, int32_t d, int half) {
+        const int4 *o4 = reinterpret_cast<const int4 *>(perm + qi * d + half * 16);
+        const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + half * 16);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            o[u] = o4[u];
+            q[u] = q4[u];
+        }
+        tau = __uint_as_float(tau_all[qi]);
+        bad = bad_all[qi];
+    }
+};
+
+__global__ __launch_bounds__(1024) void tile_kernel(
+    const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t t_begin, int32_t t_end, int64_t nq,
+    const int32_t *__restrict__ perm, const float *__restrict__ qperm, const uint32_t *__restrict__ tau,
+    const int32_t *__restrict__ bad, uint64_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int32_t cap,
+    uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters) {
+    extern __shared__ float4 smem4[];
+    float *tile = reinterpret_cast<float *>(smem4);                          // [d][32]
+    uint2 *queue = reinterpret_cast<uint2 *>(tile + (size_t)d * kTV);        // [kQCap]
+    __shared__ int32_t qcount, qhead;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int v = lane & 31;
+    const int half = lane >> 5;
+    const int32_t nchunks = d / 32;
+    uint64_t *gq = gqueue + (size_t)blockIdx.x * kGCap;  // this workgroup's overflow entries
+    unsigned long long live_vals = 0, lane_vals = 0;
+
+    for (int32_t t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
+        // stage 32 vectors x d dimensions: one 128-byte half row per dimension
+        const float *src = pdxd + (int64_t)(t >> 1) * d * kGroup + (t & 1) * kTV;
+        for (int32_t i = threadIdx.x; i < d * 8; i += blockDim.x) {
+            const int32_t row = i >> 3, part = i & 7;
+            reinterpret_cast<v4f *>(tile + row * kTV)[part] =
+                __builtin_nontemporal_load(reinterpret_cast<const v4f *>(src + (int64_t)row * kGroup + part * 4));
+        }
+        if (threadIdx.x == 0) {
+            qcount = 0;
+            qhead = 0;
+        }
+        __syncthreads();
+        const int64_t vid = (int64_t)t * kTV + v;
+        const bool valid = vid < n;
+
+        // Phase A: first chunk of every query, lanes = 32 vectors x 2 halves.
+        // The next query's first-chunk metadata is loaded while the current
+        // one is scanned (one query per wave in flight otherwise stalls on
+        // memory latency).
+        FirstChunk cur, nxt;
+        if (wave < nq) cur.load(perm, qperm, tau, bad, wave, d, half);
+        for (int64_t qi = wave; qi < nq; qi += kTW) {
+            const int64_t qn = qi + kTW;
+            if (qn < nq) nxt.load(perm, qperm, tau, bad, qn, d, half);
+            if (!cur.bad) {
+                float s = 0.0f;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    float t0 = cur.q[u].x - tile[cur.o[u].x * kTV + v];
+                    float t1 = cur.q[u].y - tile[cur.o[u].y * kTV + v];
+                    float t2 = cur.q[u].z - tile[cur.o[u].z * kTV + v];
+                    float t3 = cur.q[u].w - tile[cur.o[u].w * kTV + v];
+                    s = fmaf(t0, t0, s);
+                    s = fmaf(t1, t1, s);
+                    s = fmaf(t2, t2, s);
+                    s = fmaf(t3, t3, s);
+                }
+                const float partial = s + __shfl_xor(s, 32);  // (first 16) + (last 16)
+                const bool alive = half == 0 && valid && !(partial > cur.tau);
+                if (counters) {
+                    live_vals += 32ull * __popcll(__ballot(half == 0 && valid));
+                    lane_vals += 64ull * 16;
+                }
+                const unsigned long long m = __ballot(alive);
+                if (m != 0) {
+                    if (nchunks == 1) {
+                        if (alive) cand_append(cand, cand_cnt, cap, qi, partial, (uint32_t)vid);
+                    } else {
+                        int base = 0;
+                        if (lane == 0) base = atomicAdd(&qcount, __popcll(m));
+                        base = __shfl(base, 0);
+                        const int pos = base + lane_rank(m);
+                        bool own = false;  // both queues are full: finish this survivor here
+                        if (alive) {
+                            const uint32_t key = (static_cast<uint32_t>(qi) << 5) | static_cast<uint32_t>(v);
+                            if (pos < kQCap)
+                                queue[pos] = make_uint2(key, __float_as_uint(partial));
+                            else if (pos < kQCap + kGCap)
+                                gq[pos - kQCap] = (static_cast<uint64_t>(__float_as_uint(partial)) << 32) | key;
+                            else
+                                own = true;
+                        }
+                        if (__any(own)) {
+                            const int32_t *po = perm + qi * d;
+                            const float *qp = qperm + qi * d;
+                            float p = partial;
+                            for (int32_t c = 1; c < nchunks && __any(own); ++c) {
+                                if (own) {
+                                    p += tile_chunk(tile, po + c * 32, qp + c * 32, v);
+                                    own = !(p > cur.tau);
+                                }
+                            }
+                            if (own) cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)vid);
+                        }
+                    }
+                }
+            }
+            cur = nxt;
+        }
+        __syncthreads();
+
+        // Phase B: persistent lanes finish the queued (query, vector) pairs
+        const int32_t total = min(qcount, kQCap + kGCap);
+        bool act = false;
+        uint32_t qv = 0;
+        float p = 0.0f, tl = 0.0f;
+        int32_t c = 0;
+        while (true) {
+            const unsigned long long idle = __ballot(!act);
+            if (idle) {
+                int b = 0;
+                if (lane == 0) b = atomicAdd(&qhead, __popcll(idle));
+                b = __shfl(b, 0);
+                if (!act) {
+                    const int idx = b + lane_rank(idle);
+                    if (idx < total) {
+                        if (idx < kQCap) {
+                            const uint2 en = queue[idx];
+                            qv = en.x;
+                            p = __uint_as_float(en.y);
+                        } else {
+                            // written by other waves of this workgroup: read past the L1
+                            const uint64_t en = __hip_atomic_load(gq + (idx - kQCap), __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT);
+                            qv = static_cast<uint32_t>(en);
+                            p = __uint_as_float(static_cast<uint32_t>(en >> 32));
+                        }
+                        c = 1;
+                        act = true;
+                        tl = __uint_as_float(tau[qv >> 5]);
+                    }
+                }
+            }
+            const unsigned long long live = __ballot(act);
+            if (!live) break;
+            if (counters) {
+                live_vals += 32ull * __popcll(live);
+                lane_vals += 64ull * 32;
+            }
+            if (act) {
+                const int64_t qi = qv >> 5;
+                const int vv = qv & 31;
+                p += tile_chunk(tile, perm + qi * d + c * 32, qperm + qi * d + c * 32, vv);
+                ++c;
+                if (p > tl) {
+                    act = false;
+                } else if (c == nchunks) {
+                    cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)((int64_t)t * kTV + vv));
+                    act = false;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (counters && lane == 0) {
+        atomicAdd(counters, live_vals);
+        atomicAdd(counters + 1, lane_vals);
+    }
+}
+
 int32_t next_pow2(int32_t v) {
     int32_t p = 1;
     while (p < v) p <<= 1;
     return p;
+}
+
+constexpr int32_t kCandCap = 2048;  // candidates per query in the tile path
+constexpr int32_t kRounds = 8;      // threshold refreshes in the tile path
+
+size_t tile_lds_bytes(int32_t d) { return (size_t)d * kTV * sizeof(float) + kQCap * sizeof(uint2); }
+
+// Largest dynamic LDS a workgroup may request on the current device.
+size_t max_dynamic_lds() {
+    int dev = 0, optin = 0, plain = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
+    if (hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) plain = 0;
+    size_t m = (size_t)(optin > plain ? optin : plain);
+    return m > 64 ? m - 64 : 0;  // room for the kernel's static LDS
+}
+
+bool tile_path(const pdx_index *ix, const ExactPlan &pl) {
+    return pl.mode == PDX_MODE_BOND && pl.chunk == 32 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
+           pl.tiles_main > 0 && tile_lds_bytes(ix->d) <= max_dynamic_lds();
 }
 
 }  // namespace
@@ -249,13 +608,26 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.tiles_start = (pl.start_groups + pl.tile_groups - 1) / pl.tile_groups;
     pl.tiles_main = (ix->ngroups - pl.start_groups + pl.tile_groups - 1) / pl.tile_groups;
     pl.nslots = pl.tiles_start + pl.tiles_main;
+    pl.use_tiles = tile_path(ix, pl);
     size_t q = static_cast<size_t>(nq > 0 ? nq : 0);
     Carver c(ws);
     pl.tau = c.take<uint32_t>(q);
     pl.bad = c.take<int32_t>(q);
-    pl.perm_off = c.take<int32_t>(q * ix->d);
+    pl.perm = c.take<int32_t>(q * ix->d);
     pl.qperm = c.take<float>(q * ix->d);
     pl.slots = c.take<uint64_t>(q * pl.nslots * k);
+    if (pl.use_tiles) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        pl.tile_grid = cus;  // one workgroup per compute unit (the LDS tile fills the CU)
+        pl.gqueue = c.take<uint64_t>((size_t)cus * kGCap);
+        pl.cand = c.take<uint64_t>(q * kCandCap);
+        pl.cand_cnt = c.take<int32_t>(q);
+        pl.over_list = c.take<int32_t>(q);
+        pl.over_count = c.take<int32_t>(64);
+    }
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
     pl.counters = p ? p->counters : nullptr;
     if (plan) *plan = pl;
@@ -270,43 +642,79 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     auto mark = [&](int i) { return pl.events ? hipEventRecord(pl.events[i], s) : hipSuccess; };
     hipError_t err;
     if ((err = mark(0)) != hipSuccess) return err;
-    prep_kernel<<<dim3((unsigned)pl.nq), dim3(256), lds, s>>>(q, d, ix->means, pl.mode, pow2, pl.perm_off,
+    prep_kernel<<<dim3((unsigned)pl.nq), dim3(256), lds, s>>>(q, d, ix->means, pl.mode, pow2, pl.perm,
                                                               pl.qperm, pl.tau, pl.bad);
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     const int32_t nqb = (int32_t)((pl.nq + pl.qpb - 1) / pl.qpb);
-    auto scan = [&](bool prune, int32_t gb, int32_t ge, int32_t ntiles, int32_t slot0) {
+    auto scan = [&](bool prune, int32_t gb, int32_t ge, int32_t ntiles, int32_t slot0, unsigned long long *cnt) {
         unsigned grid = 8u * (unsigned)((ntiles + 7) / 8) * (unsigned)nqb;
         dim3 block(64 * pl.qpb);
         if (prune)
             scan_kernel<true><<<grid, block, 0, s>>>(ix->pdx, ix->n, d, gb, ge, pl.tile_groups, ntiles, nqb,
-                                                     pl.nq, pl.qpb, pl.perm_off, pl.qperm, pl.tau, pl.bad,
-                                                     pl.slots, pl.nslots, slot0, pl.k, pl.chunk,
-                                                     pl.counters ? pl.counters + 2 : nullptr);
+                                                     pl.nq, pl.qpb, pl.perm, pl.qperm, pl.tau, pl.bad,
+                                                     pl.slots, pl.nslots, slot0, pl.k, pl.chunk, cnt);
         else
             scan_kernel<false><<<grid, block, 0, s>>>(ix->pdx, ix->n, d, gb, ge, pl.tile_groups, ntiles, nqb,
-                                                      pl.nq, pl.qpb, pl.perm_off, pl.qperm, pl.tau, pl.bad,
-                                                      pl.slots, pl.nslots, slot0, pl.k, pl.chunk,
-                                                      pl.counters ? pl.counters + (slot0 == 0 && pl.tiles_start ? 0 : 2) : nullptr);
+                                                      pl.nq, pl.qpb, pl.perm, pl.qperm, pl.tau, pl.bad,
+                                                      pl.slots, pl.nslots, slot0, pl.k, pl.chunk, cnt);
         return hipGetLastError();
     };
+    const unsigned nqu = (unsigned)pl.nq;
     if (pl.tiles_start > 0) {
         // START (Section 4, PHASE 0): the first block without pruning, then
         // its k-th distance becomes the initial threshold.
-        if ((err = scan(false, 0, pl.start_groups, pl.tiles_start, 0)) != hipSuccess) return err;
-        merge_kernel<<<dim3((unsigned)pl.nq), dim3(64), 0, s>>>(pl.slots, pl.nslots, 0, pl.tiles_start, pl.k,
-                                                               pl.bad, pl.tau, nullptr, nullptr);
+        if ((err = scan(false, 0, pl.start_groups, pl.tiles_start, 0, pl.counters)) != hipSuccess) return err;
+        merge_kernel<<<nqu, 64, 0, s>>>(pl.slots, pl.nslots, 0, pl.tiles_start, pl.k, pl.bad, pl.tau, nullptr,
+                                        nullptr, pl.use_tiles ? pl.cand : nullptr, pl.cand_cnt, kCandCap);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     if ((err = mark(1)) != hipSuccess) return err;
-    if (pl.tiles_main > 0) {
-        bool prune = pl.mode == PDX_MODE_BOND;
-        if ((err = scan(prune, pl.start_groups, ix->ngroups, pl.tiles_main, pl.tiles_start)) != hipSuccess)
+    unsigned long long *cmain = pl.counters ? pl.counters + 2 : nullptr;
+    if (!pl.use_tiles) {
+        if (pl.tiles_main > 0) {
+            bool prune = pl.mode == PDX_MODE_BOND;
+            if ((err = scan(prune, pl.start_groups, ix->ngroups, pl.tiles_main, pl.tiles_start, cmain)) != hipSuccess)
+                return err;
+        }
+        if ((err = mark(2)) != hipSuccess) return err;
+        merge_kernel<<<nqu, 64, 0, s>>>(pl.slots, pl.nslots, 0, pl.nslots, pl.k, pl.bad, nullptr, out_ids, out_dist,
+                                        nullptr, nullptr, 0);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        return mark(3);
+    }
+    // tile path: rounds of 32-vector tiles, threshold refreshed in between
+    const size_t tile_lds = tile_lds_bytes(d);
+    if (tile_lds > 64 * 1024) {
+        if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(tile_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds)) != hipSuccess)
             return err;
     }
+    const int32_t t0 = 2 * pl.start_groups, t1 = 2 * ix->ngroups;
+    const int cus = pl.tile_grid;
+    for (int32_t r = 0; r < kRounds; ++r) {
+        const int32_t a = t0 + (int32_t)((int64_t)(t1 - t0) * r / kRounds);
+        const int32_t b = t0 + (int32_t)((int64_t)(t1 - t0) * (r + 1) / kRounds);
+        if (b <= a) continue;
+        const unsigned grid = (unsigned)min(b - a, cus);
+        tile_kernel<<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, d, a, b, pl.nq, pl.perm, pl.qperm, pl.tau, pl.bad,
+                                                 pl.cand, pl.cand_cnt, kCandCap, pl.gqueue, cmain);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (r + 1 < kRounds) {
+            cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, pl.k, pl.bad, pl.tau, nullptr, 0, 0,
+                                                 0, nullptr, nullptr);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
+    }
+    // queries whose buffer overflowed: group path over the main range
+    if ((err = launch_fill_i32(pl.over_count, 1, 0, s)) != hipSuccess) return err;
+    over_list_kernel<<<(nqu + 255) / 256, 256, 0, s>>>(pl.cand_cnt, pl.nq, kCandCap, pl.over_list, pl.over_count);
+    fallback_kernel<<<2048, 256, 0, s>>>(ix->pdx, ix->n, d, pl.start_groups, ix->ngroups, pl.tile_groups,
+                                         pl.tiles_main, pl.over_list, pl.over_count, pl.perm, pl.qperm, pl.tau,
+                                         pl.slots, pl.nslots, pl.tiles_start, pl.k, pl.chunk);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     if ((err = mark(2)) != hipSuccess) return err;
-    merge_kernel<<<dim3((unsigned)pl.nq), dim3(64), 0, s>>>(pl.slots, pl.nslots, 0, pl.nslots, pl.k, pl.bad,
-                                                           nullptr, out_ids, out_dist);
+    cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, pl.k, pl.bad, pl.tau, pl.slots, pl.nslots,
+                                         pl.tiles_start, pl.tiles_main, out_ids, out_dist);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return mark(3);
 }

@@ -83,12 +83,19 @@ struct ExactPlan {
     int32_t tiles_start;
     int32_t tiles_main;
     int32_t nslots;
+    bool use_tiles;        // LDS tile path (else the group path only)
     // workspace parts
     uint32_t *tau;
     int32_t *bad;
-    int32_t *perm_off;
-    float *qperm;
-    uint64_t *slots;
+    int32_t *perm;         // [nq][d] visited dimension order
+    float *qperm;          // [nq][d] query values in that order
+    uint64_t *slots;       // [nq][nslots][k] group-path k-best lists
+    uint64_t *cand;        // [nq][cap] tile-path candidates
+    int32_t *cand_cnt;     // [nq]
+    int32_t *over_list;    // [nq] queries whose candidates overflowed
+    int32_t *over_count;
+    int32_t tile_grid;     // tile-path workgroups per launch
+    uint64_t *gqueue;      // [tile_grid][overflow cap] survivor entries
     hipEvent_t *events;              // optional [4]
     unsigned long long *counters;    // optional [4]
 };

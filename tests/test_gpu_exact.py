@@ -152,3 +152,24 @@ def test_full_size_bond_sampled(pdx):
     # every query: ascending, distinct, valid
     assert (np.diff(gd, axis=1) >= 0).all()
     assert (gi >= 0).all() and (gi < x.shape[0]).all()
+
+
+def test_tile_path_ties_overflow_and_fallback(pdx):
+    """All rows tie with the queries: every vector survives, the LDS survivor
+    queue and the per-query candidate buffer overflow, and the group-path
+    fallback must still return the k lowest ids (distance 0)."""
+    x = np.zeros((20_000, 64), dtype=np.float32)
+    x[::7, 3] = 1.0
+    q = np.zeros((70, 64), dtype=np.float32)
+    print("tile path overflow", flush=True)
+    wi, wd = exact.knn_exact_c(x, q, 10)
+    _, gi, gd = _search(pdx, x, q, 10, mode="bond", start_rows=256)
+    check_knn(x, q, gi, gd, wi, wd, exact=True)
+
+
+def test_tile_path_binary_ties(pdx):
+    x, q = synth.integer_grid(30_000, 64, 40, lo=0, hi=1, seed=21)
+    print("tile path binary ties", flush=True)
+    wi, wd = exact.knn_exact_c(x, q, 16)
+    _, gi, gd = _search(pdx, x, q, 16, mode="bond", start_rows=1000)
+    check_knn(x, q, gi, gd, wi, wd, exact=True)
