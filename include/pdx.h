@@ -147,7 +147,8 @@ enum { PDX_DTYPE_F32 = 0, PDX_DTYPE_BF16 = 1, PDX_DTYPE_FP8 = 2 };
 
 typedef struct {
     int32_t kmeans_iters;   /* Lloyd iterations; 0 = 20 */
-    int32_t dtype;          /* extra low-precision copy of the rotated vectors */
+    int32_t lowp_mask;      /* extra low-precision copies of the rotated vectors:
+                               (1 << PDX_DTYPE_BF16) | (1 << PDX_DTYPE_FP8); 0 = none */
     /* Random numbers are drawn by the caller and passed in:             */
     const double *gaussian; /* [d][d] iid N(0,1) float64 device, rotated with
                                the Q of its QR (Haar sign fix); NULL = no rotation */
@@ -170,6 +171,12 @@ PDX_API size_t pdx_ivf_build_bytes(int64_t n, int32_t d, int32_t nlist, const pd
  * its previous centroid.  Section 2.1 / Figure "IVF-PDX": every bucket is
  * a PDX block.  Synchronous.
  *
+ * Low precision (lowp_mask): besides the f32 vectorgroups, the rotated rows
+ * can be stored as bfloat16 (round to nearest even) and/or float8 e4m3 with
+ * a per-dimension scale s_j = max_i |x_ij| / 448 (codes of x_ij / s_j, round
+ * to nearest even, saturating); a row-major f32 copy is kept for rerank.
+ * Compressed PDX blocks are the paper's future work (Section 7).
+ *
  * Returns PDX_EINVAL for bad sizes (nlist < 1 or nlist > n), null required
  * pointers, or non-finite data; PDX_EWORKSPACE if index_bytes is short. */
 PDX_API pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist,
@@ -186,8 +193,11 @@ typedef struct {
     float eps0;        /* ADSampling error bound (Section 6.1: 2.1);
                           +INFINITY: exact within the probed buckets */
     int32_t delta_d;   /* dimensions between tests; 0 = 32, D/4 if D < 128 */
-    int32_t dtype;     /* scan the PDX_DTYPE_* copy stored at build */
-    int32_t rerank;    /* low precision: candidates re-ranked in f32; 0 = 4k */
+    int32_t dtype;     /* PDX_DTYPE_* copy to scan (must have been stored) */
+    int32_t rerank;    /* BF16/FP8 scans: the R best by the scanned distance are
+                          re-ranked with exact f32 distances (k <= R <= PDX_MAX_K);
+                          0 = min(4k, PDX_MAX_K); -1 = no rerank (distances are
+                          then the scanned low-precision ones).  Ignored for F32. */
     /* Optional instrumentation (NULL = off); neither changes the result.   */
     void **phase_events; /* 4 hipEvent_t recorded on `stream`: at the start,
                             after rotation + bucket selection + START, after
@@ -209,7 +219,9 @@ PDX_API size_t pdx_search_ivf_workspace(const pdx_index *index, int64_t nq, int3
  * Section 2.3 (ADSampling): after d < D dimensions a vector is dropped when
  * partial*D/d > tau*(1 + eps0/sqrt(d))^2, tau the running k-th distance;
  * at d = D the comparison is exact.  Distances are reported in rotated
- * space (equal to the original up to rounding).
+ * space (equal to the original up to rounding).  Low-precision scans
+ * accumulate in f32 over the decoded values; with rerank the returned
+ * distances are exact f32 distances.
  *
  * Returns PDX_EINVAL (null pointers, k < 1, nprobe outside [1, nlist],
  * not an IVF index), PDX_EUNSUPPORTED (k > PDX_MAX_K, dtype not stored),

@@ -46,7 +46,7 @@ class pdx_search_params(ctypes.Structure):
 
 
 class pdx_ivf_params(ctypes.Structure):
-    _fields_ = [("kmeans_iters", c_int32), ("dtype", c_int32), ("gaussian", c_void_p),
+    _fields_ = [("kmeans_iters", c_int32), ("lowp_mask", c_int32), ("gaussian", c_void_p),
                 ("init_rows", c_void_p), ("rotation", c_void_p), ("centroids", c_void_p),
                 ("assign", c_void_p)]
 

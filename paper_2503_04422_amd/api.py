@@ -117,7 +117,7 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
 
 
 def pdx_ivf_build(x: torch.Tensor, nlist: int, gaussian: Optional[torch.Tensor],
-                  init_rows: Optional[torch.Tensor], kmeans_iters: int = 0, dtype: str = "f32",
+                  init_rows: Optional[torch.Tensor], kmeans_iters: int = 0, lowp: Tuple[str, ...] = (),
                   rotation: Optional[torch.Tensor] = None, centroids: Optional[torch.Tensor] = None,
                   assign: Optional[torch.Tensor] = None,
                   stream: Optional[torch.cuda.Stream] = None) -> PdxIndex:
@@ -132,8 +132,12 @@ def pdx_ivf_build(x: torch.Tensor, nlist: int, gaussian: Optional[torch.Tensor],
         raise TypeError("init_rows must be int64")
     if asg is not None and asg.dtype != torch.int32:
         raise TypeError("assign must be int32")
-    p = _lib.pdx_ivf_params(int(kmeans_iters), _DTYPES[dtype], _ptr(g), _ptr(ir), _ptr(rot), _ptr(cen),
-                            _ptr(asg))
+    mask = 0
+    for name in lowp:
+        if name not in ("bf16", "fp8"):
+            raise ValueError(f"unknown low-precision storage {name!r}")
+        mask |= 1 << _DTYPES[name]
+    p = _lib.pdx_ivf_params(int(kmeans_iters), mask, _ptr(g), _ptr(ir), _ptr(rot), _ptr(cen), _ptr(asg))
     nbytes = lib.pdx_ivf_build_bytes(n, d, nlist, ctypes.byref(p))
     if nbytes == 0:
         raise ValueError(f"unsupported IVF shape n={n} d={d} nlist={nlist}")
@@ -142,7 +146,7 @@ def pdx_ivf_build(x: torch.Tensor, nlist: int, gaussian: Optional[torch.Tensor],
     st = lib.pdx_ivf_build(_ptr(x), n, d, nlist, ctypes.byref(p), _ptr(mem), nbytes, _stream(stream),
                            ctypes.byref(h))
     check(st, "pdx_ivf_build")
-    return PdxIndex(h, mem, n, d, "ivf", nlist, dtype)
+    return PdxIndex(h, mem, n, d, "ivf", nlist, "+".join(("f32",) + tuple(lowp)))
 
 
 def pdx_ivf_export(index: PdxIndex, stream: Optional[torch.cuda.Stream] = None):

@@ -266,3 +266,79 @@ hipError_t launch_bucketize(const float *xrot, int64_t n, int32_t d, const int32
 }
 
 }  // namespace pdx
+
+// ---------------------------------------------------------------------------
+// Low-precision copies of the bucketed vectorgroups.
+// ---------------------------------------------------------------------------
+namespace pdx {
+namespace {
+
+// per-dimension max |x| (float bits of non-negative values order as unsigned)
+__global__ __launch_bounds__(256) void col_absmax_kernel(const float *__restrict__ x, int64_t n, int32_t d,
+                                                         int64_t rows_per, uint32_t *__restrict__ maxbits) {
+    int32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= d) return;
+    int64_t r0 = (int64_t)blockIdx.y * rows_per, r1 = min(r0 + rows_per, n);
+    float m = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) m = fmaxf(m, fabsf(x[r * d + j]));
+    atomicMax(maxbits + j, __float_as_uint(m));
+}
+
+__global__ void fp8_scale_kernel(const uint32_t *__restrict__ maxbits, int32_t d, float *__restrict__ scale) {
+    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d) return;
+    float m = __uint_as_float(maxbits[j]);
+    scale[j] = m == 0.0f ? 1.0f : m / 448.0f;
+}
+
+// as gather_pdx_kernel, writing codes: bfloat16 and/or e4m3(x / s_j)
+__global__ __launch_bounds__(256) void gather_lowp_kernel(const float *__restrict__ x, int32_t d,
+                                                          const int32_t *__restrict__ slot_id,
+                                                          const int32_t *__restrict__ stats,
+                                                          uint16_t *__restrict__ pdx16, uint8_t *__restrict__ pdx8,
+                                                          const float *__restrict__ scale) {
+    __shared__ float tile[64][65];
+    const int64_t g = blockIdx.x;
+    if (g >= stats[0]) return;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int32_t c0 = blockIdx.y * 64;
+#pragma unroll 4
+    for (int r = 0; r < 64; r += 4) {
+        int32_t row = slot_id[g * 64 + r + ty];
+        int32_t col = c0 + tx;
+        tile[r + ty][tx] = (row >= 0 && col < d) ? x[(int64_t)row * d + col] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < 64; c += 4) {
+        int32_t col = c0 + c + ty;
+        if (col >= d) continue;
+        const float v = tile[tx][c + ty];
+        const int64_t at = (g * d + col) * 64 + tx;
+        if (pdx16) pdx16[at] = bf16_encode(v);
+        if (pdx8) pdx8[at] = static_cast<uint8_t>(e4m3_encode(v / scale[col]));
+    }
+}
+
+}  // namespace
+
+hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int32_t *slot_id, const int32_t *stats,
+                             int64_t max_groups, uint16_t *pdx16, uint8_t *pdx8, float *scale, uint32_t *maxbits,
+                             hipStream_t s) {
+    hipError_t e;
+    if (pdx8) {
+        if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(maxbits), d, 0, s)) != hipSuccess) return e;
+        int64_t chunks = 256, rows_per = (n + chunks - 1) / chunks;
+        chunks = (n + rows_per - 1) / rows_per;
+        col_absmax_kernel<<<dim3((unsigned)((d + 255) / 256), (unsigned)chunks), 256, 0, s>>>(xrow, n, d, rows_per,
+                                                                                           maxbits);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        fp8_scale_kernel<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(maxbits, d, scale);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    gather_lowp_kernel<<<dim3((unsigned)max_groups, (unsigned)((d + 63) / 64)), 256, 0, s>>>(xrow, d, slot_id, stats,
+                                                                                           pdx16, pdx8, scale);
+    return hipGetLastError();
+}
+
+}  // namespace pdx

@@ -109,9 +109,19 @@ __global__ void item_scatter_kernel(const int32_t *__restrict__ probe, int64_t n
 // Scan of one bucket for one query per wave.  Work items are consecutive
 // per bucket; workgroup ids are mapped so each XCD takes a contiguous
 // range of items (and so of buckets).
-template <bool PRUNE>
+// Value of dimension j of the lane's vector in group g: f32, or a bfloat16 /
+// e4m3 code decoded to f32 (e4m3 times the dimension's scale).
+template <int STORE>
+__device__ __forceinline__ float load_val(const void *__restrict__ data, const float *__restrict__ scale, int64_t at,
+                                          int32_t j) {
+    if (STORE == PDX_DTYPE_F32) return static_cast<const float *>(data)[at];
+    if (STORE == PDX_DTYPE_BF16) return bf16_decode(static_cast<const uint16_t *>(data)[at]);
+    return e4m3_decode(static_cast<const uint8_t *>(data)[at]) * scale[j];
+}
+
+template <bool PRUNE, int STORE>
 __global__ __launch_bounds__(256) void ivf_scan_kernel(
-    const float *__restrict__ pdxd, int32_t d, const int32_t *__restrict__ slot_id,
+    const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nitems,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
     uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
@@ -144,7 +154,7 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
         }
         const int32_t vid = slot_id[(int64_t)g * kGroup + lane];
         bool alive = vid >= 0;
-        const float *gp = pdxd + (int64_t)g * d * kGroup + lane;
+        const int64_t gbase = (int64_t)g * d * kGroup + lane;
         float partial = 0.0f;
         for (int32_t c0 = 0; c0 < d; c0 += chunk) {
             if (PRUNE && !__any(alive)) break;
@@ -159,7 +169,7 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
                 for (; j + 8 <= c1; j += 8) {
                     float x[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) x[u] = gp[(int64_t)(j + u) * kGroup];
+                    for (int u = 0; u < 8; ++u) x[u] = load_val<STORE>(pdxd, scale, gbase + (int64_t)(j + u) * kGroup, j + u);
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         float t = qp[j + u] - x[u];
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
                     }
                 }
                 for (; j < c1; ++j) {
-                    float t = qp[j] - gp[(int64_t)j * kGroup];
+                    float t = qp[j] - load_val<STORE>(pdxd, scale, gbase + (int64_t)j * kGroup, j);
                     s = fmaf(t, t, s);
                 }
             }
@@ -202,7 +212,7 @@ __global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restric
                                                        const int32_t *__restrict__ bad,
                                                        uint32_t *__restrict__ tau,
                                                        int64_t *__restrict__ out_ids,
-                                                       float *__restrict__ out_dist) {
+                                                       float *__restrict__ out_dist, uint64_t *__restrict__ keys_out) {
     const int64_t qi = blockIdx.x;
     const int lane = threadIdx.x;
     const uint64_t *base = slots + ((size_t)qi * nprobe + r0) * k;
@@ -213,6 +223,7 @@ __global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restric
         topk_offer(e, kth, kk, kk != kEmptyKey, k, lane);
     }
     if (tau && lane == 0 && kth != kEmptyKey) tau[qi] = (uint32_t)(kth >> 32);
+    if (keys_out && lane < k) keys_out[qi * k + lane] = e;
     if (out_ids && lane < k) {
         int64_t id = -1;
         float dist = INFINITY;
@@ -224,6 +235,49 @@ __global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restric
         }
         out_ids[qi * k + lane] = id;
         out_dist[qi * k + lane] = dist;
+    }
+}
+
+// Rerank: the r best candidates of a query by the low-precision distance
+// get their exact f32 distance from the row-major f32 copy (same chunked
+// accumulation as the f32 scan: sequential fused multiply-adds per chunk,
+// chunk sums added in order); the k best of those are the result.
+__global__ __launch_bounds__(64) void rerank_kernel(const uint64_t *__restrict__ keys, int32_t r, int32_t k,
+                                                    const float *__restrict__ xrow, const float *__restrict__ qrot,
+                                                    int32_t d, int32_t chunk, const int32_t *__restrict__ bad,
+                                                    int64_t *__restrict__ out_ids, float *__restrict__ out_dist) {
+    const int64_t qi = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t key = lane < r ? keys[qi * r + lane] : kEmptyKey;
+    const bool has = key != kEmptyKey;
+    const uint32_t id = static_cast<uint32_t>(key & 0xffffffffu);
+    float dist = 0.0f;
+    if (has) {
+        const float *x = xrow + (int64_t)id * d;
+        const float *qp = qrot + qi * d;
+        for (int32_t c0 = 0; c0 < d; c0 += chunk) {
+            const int32_t c1 = min(c0 + chunk, d);
+            float s = 0.0f;
+            for (int32_t j = c0; j < c1; ++j) {
+                float t = qp[j] - x[j];
+                s = fmaf(t, t, s);
+            }
+            dist += s;
+        }
+    }
+    uint64_t e = kEmptyKey, kth = kEmptyKey;
+    topk_offer(e, kth, make_key(dist, id), has, k, lane);
+    if (lane < k) {
+        int64_t oid = -1;
+        float od = INFINITY;
+        if (bad[qi]) {
+            od = __uint_as_float(0x7fc00000u);
+        } else if (e != kEmptyKey) {
+            oid = (int64_t)(e & 0xffffffffu);
+            od = key_dist(e);
+        }
+        out_ids[qi * k + lane] = oid;
+        out_dist[qi * k + lane] = od;
     }
 }
 
@@ -242,6 +296,14 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.k = k;
     pl.nprobe = nprobe;
     pl.eps0 = p ? p->eps0 : 2.1f;
+    pl.dtype = p ? p->dtype : PDX_DTYPE_F32;
+    pl.rerank = 0;
+    if (pl.dtype != PDX_DTYPE_F32) {
+        int32_t r = p ? p->rerank : 0;
+        if (r == 0) r = min(4 * k, PDX_MAX_K);
+        pl.rerank = r < 0 ? 0 : max(r, k);
+    }
+    pl.kk = pl.rerank > 0 ? pl.rerank : k;
     int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
     pl.chunk = dd;
     size_t q = (size_t)(nq > 0 ? nq : 0);
@@ -255,7 +317,8 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.cnt1 = c.take<int32_t>(ix->nlist);
     pl.items0 = c.take<int2>(q);
     pl.items1 = c.take<int2>(q * (nprobe - 1 > 0 ? nprobe - 1 : 1));
-    pl.slots = c.take<uint64_t>(q * nprobe * k);
+    pl.slots = c.take<uint64_t>(q * nprobe * pl.kk);
+    pl.rkeys = pl.rerank > 0 ? c.take<uint64_t>(q * pl.kk) : nullptr;
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
     pl.counters = p ? p->counters : nullptr;
     if (plan) *plan = pl;
@@ -302,23 +365,49 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     };
     uint32_t nwg0, nwg1;
     unsigned grid0 = grid_of(n0, &nwg0), grid1 = grid_of(n1, &nwg1);
-    ivf_scan_kernel<false><<<grid0, 256, 0, s>>>(
-        ix->pdx, d, ix->slot_id, ix->list_goff, pl.items0, n0, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad,
-        pl.slots, pl.k, pl.chunk, pl.eps0, pl.counters, nwg0);
-    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, 1, pl.k, pl.bad, pl.tau, nullptr, nullptr);
+    const void *data = pl.dtype == PDX_DTYPE_BF16 ? static_cast<const void *>(ix->pdx_bf16)
+                       : pl.dtype == PDX_DTYPE_FP8 ? static_cast<const void *>(ix->pdx_fp8)
+                                                   : static_cast<const void *>(ix->pdx);
+    auto scan = [&](bool prune, unsigned grid, const int2 *items, int64_t nitems, unsigned long long *cnt,
+                    uint32_t nwg) {
+#define PDX_SCAN(P, S)                                                                                          \
+    ivf_scan_kernel<P, S><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, nitems, \
+                                               pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots, pl.kk,     \
+                                               pl.chunk, pl.eps0, cnt, nwg)
+        if (prune) {
+            if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16);
+            else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8);
+            else PDX_SCAN(true, PDX_DTYPE_F32);
+        } else {
+            if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(false, PDX_DTYPE_BF16);
+            else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(false, PDX_DTYPE_FP8);
+            else PDX_SCAN(false, PDX_DTYPE_F32);
+        }
+#undef PDX_SCAN
+        return hipGetLastError();
+    };
+    if ((e = scan(false, grid0, pl.items0, n0, pl.counters, nwg0)) != hipSuccess) return e;
+    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, 1, pl.kk, pl.bad, pl.tau, nullptr, nullptr,
+                                                nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark(1)) != hipSuccess) return e;
     // 5. pruned scan of the other probed buckets
     if (n1 > 0) {
-        ivf_scan_kernel<true><<<grid1, 256, 0, s>>>(
-            ix->pdx, d, ix->slot_id, ix->list_goff, pl.items1, n1, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad,
-            pl.slots, pl.k, pl.chunk, pl.eps0, pl.counters ? pl.counters + 2 : nullptr, nwg1);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan(true, grid1, pl.items1, n1, pl.counters ? pl.counters + 2 : nullptr, nwg1)) != hipSuccess)
+            return e;
     }
     if ((e = mark(2)) != hipSuccess) return e;
     // 6. merge
-    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, pl.k, pl.bad, nullptr, out_ids,
-                                                out_dist);
+    if (pl.rerank > 0) {
+        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, pl.kk, pl.bad, nullptr,
+                                                    nullptr, nullptr, pl.rkeys);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        rerank_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.rkeys, pl.kk, pl.k, ix->xrow, pl.qrot, d, pl.chunk, pl.bad,
+                                                 out_ids, out_dist);
+    } else {
+        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, pl.k, pl.bad, nullptr,
+                                                    out_ids, out_dist, nullptr);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return mark(3);
 }

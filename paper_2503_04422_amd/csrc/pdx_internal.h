@@ -41,6 +41,7 @@ struct pdx_index {
     uint16_t *pdx_bf16;  // [ngroups][d][64] (optional)
     uint8_t *pdx_fp8;    // [ngroups][d][64] (optional)
     float *fp8_scale;    // [d] per-dimension scale (optional)
+    float *xrow;         // [n][d] rotated rows, row-major (rerank)
     int32_t max_list;    // largest bucket, rows
 };
 
@@ -105,6 +106,9 @@ struct IvfPlan {
     int32_t k;
     int32_t nprobe;
     int32_t chunk;  // dimensions between ADSampling tests
+    int32_t dtype;  // storage scanned
+    int32_t rerank; // > 0: keep this many candidates and rerank them in f32
+    int32_t kk;     // list length kept per work item (k, or rerank)
     float eps0;
     float *qrot;       // [nq][d]
     float *cd;         // [nq][nlist]
@@ -113,7 +117,8 @@ struct IvfPlan {
     uint32_t *tau;     // [nq]
     int32_t *cnt0, *cnt1;  // [nlist] item cursors
     int2 *items0, *items1;
-    uint64_t *slots;   // [nq][nprobe][k]
+    uint64_t *slots;   // [nq][nprobe][kk]
+    uint64_t *rkeys;   // [nq][kk] candidates to rerank
     hipEvent_t *events;
     unsigned long long *counters;
 };
@@ -144,5 +149,51 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
                   void *ws, ExactPlan *plan);
 hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &plan,
                      int64_t *out_ids, float *out_dist, hipStream_t s);
+
+}  // namespace pdx
+
+namespace pdx {
+
+// ---- low-precision codes (round to nearest even) ----
+// bfloat16: upper 16 bits of the float32 pattern after rounding.
+__host__ __device__ inline uint16_t bf16_encode(float x) {
+    uint32_t b;
+    __builtin_memcpy(&b, &x, 4);
+    uint32_t lsb = (b >> 16) & 1u;
+    return static_cast<uint16_t>((b + 0x7fffu + lsb) >> 16);
+}
+__host__ __device__ inline float bf16_decode(uint32_t c) {
+    uint32_t b = c << 16;
+    float f;
+    __builtin_memcpy(&f, &b, 4);
+    return f;
+}
+// float8 e4m3 ("fn": no infinities, largest finite 448): 1 sign, 4 exponent
+// bits with bias 7, 3 mantissa bits, subnormals m * 2^-9; saturates at 448.
+__device__ inline uint32_t e4m3_encode(float v) {
+    const uint32_t b = __float_as_uint(v);
+    const uint32_t sign = (b >> 24) & 0x80u;
+    const float a = fabsf(v);
+    if (a == 0.0f) return sign;
+    if (a >= 448.0f) return sign | 0x7eu;
+    const uint32_t ab = __float_as_uint(a);
+    const int e = static_cast<int>(ab >> 23) - 127;
+    if (e < -6) return sign | static_cast<uint32_t>(rintf(a * 512.0f));  // multiples of 2^-9
+    const uint32_t mant = ab & 0x7fffffu;
+    uint32_t r = mant >> 20;
+    const uint32_t rem = mant & 0xfffffu;
+    if (rem > 0x80000u || (rem == 0x80000u && (r & 1u))) r += 1;  // carries into the exponent
+    uint32_t code = (static_cast<uint32_t>(e + 7) << 3) + r;
+    return sign | (code > 0x7eu ? 0x7eu : code);
+}
+__device__ inline float e4m3_decode(uint32_t c) {
+    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+    const float v = e == 0 ? static_cast<float>(m) * 0.001953125f : __uint_as_float(((e + 120u) << 23) | (m << 20));
+    return (c & 0x80u) ? -v : v;
+}
+
+hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int32_t *slot_id, const int32_t *stats,
+                             int64_t max_groups, uint16_t *pdx16, uint8_t *pdx8, float *scale, uint32_t *maxbits,
+                             hipStream_t s);
 
 }  // namespace pdx

@@ -12,7 +12,10 @@ constexpr int32_t kMaxNlist = 4096;
 constexpr int32_t kRowsPerBlock = 1024;
 
 struct IvfLayout {
-    float *rot, *centroids, *pdx, *xrot;
+    float *rot, *centroids, *pdx, *xrot, *fp8_scale;
+    uint16_t *pdx16;
+    uint8_t *pdx8;
+    uint32_t *maxbits;
     int32_t *list_size, *list_goff, *stats, *assign, *slot_id, *cnt, *blk_cnt, *flag;
     unsigned long long *best;
     double *sums, *acm, *qd, *v, *diag;
@@ -20,7 +23,7 @@ struct IvfLayout {
     size_t bytes;
 };
 
-IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, void *base) {
+IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, void *base) {
     IvfLayout l{};
     l.max_groups = (n + kGroup - 1) / kGroup + nlist;
     int64_t nblocks = (n + kRowsPerBlock - 1) / kRowsPerBlock;
@@ -34,8 +37,14 @@ IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, void *base) {
     l.assign = c.take<int32_t>(n);
     l.slot_id = c.take<int32_t>((size_t)l.max_groups * kGroup);
     l.pdx = c.take<float>((size_t)l.max_groups * d * kGroup);
+    l.xrot = c.take<float>((size_t)n * d);  // kept: rows for the f32 rerank
+    if (lowp_mask & (1 << PDX_DTYPE_BF16)) l.pdx16 = c.take<uint16_t>((size_t)l.max_groups * d * kGroup);
+    if (lowp_mask & (1 << PDX_DTYPE_FP8)) {
+        l.pdx8 = c.take<uint8_t>((size_t)l.max_groups * d * kGroup);
+        l.fp8_scale = c.take<float>(d);
+        l.maxbits = c.take<uint32_t>(d);
+    }
     // build scratch
-    l.xrot = c.take<float>((size_t)n * d);
     l.best = c.take<unsigned long long>(n);
     l.sums = c.take<double>((size_t)nlist * d);
     l.cnt = c.take<int32_t>(nlist);
@@ -82,7 +91,8 @@ extern "C" {
 size_t pdx_ivf_build_bytes(int64_t n, int32_t d, int32_t nlist, const pdx_ivf_params *params) {
     (void)params;
     if (!valid_shape(n, d, nlist)) return 0;
-    return ivf_layout(n, d, nlist, nullptr).bytes;
+    if (params && (params->lowp_mask & ~((1 << PDX_DTYPE_BF16) | (1 << PDX_DTYPE_FP8)))) return 0;
+    return ivf_layout(n, d, nlist, params ? params->lowp_mask : 0, nullptr).bytes;
 }
 
 pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, const pdx_ivf_params *params,
@@ -110,15 +120,15 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
         set_error("pdx_ivf_build: assign needs centroids");
         return PDX_EINVAL;
     }
-    if (params->dtype != PDX_DTYPE_F32) {
-        set_error("pdx_ivf_build: only f32 storage is implemented");
-        return PDX_EUNSUPPORTED;
+    if (params->lowp_mask & ~((1 << PDX_DTYPE_BF16) | (1 << PDX_DTYPE_FP8))) {
+        set_error("pdx_ivf_build: lowp_mask may only hold the bf16 and fp8 bits");
+        return PDX_EINVAL;
     }
     if (!aligned16(x) || !aligned16(index_mem)) {
         set_error("pdx_ivf_build: pointers must be 16-byte aligned");
         return PDX_EINVAL;
     }
-    IvfLayout L = ivf_layout(n, d, nlist, index_mem);
+    IvfLayout L = ivf_layout(n, d, nlist, params->lowp_mask, index_mem);
     if (index_bytes < L.bytes) {
         set_error("pdx_ivf_build: index buffer has %zu bytes, needs %zu", index_bytes, L.bytes);
         return PDX_EWORKSPACE;
@@ -184,6 +194,9 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     }
     TRY(launch_bucketize(L.xrot, n, d, L.assign, nlist, L.blk_cnt, L.list_size, L.list_goff, L.stats, L.slot_id,
                          L.max_groups * kGroup, L.pdx, L.max_groups, s));
+    if (L.pdx16 || L.pdx8)
+        TRY(launch_lowp_store(L.xrot, n, d, L.slot_id, L.stats, L.max_groups, L.pdx16, L.pdx8, L.fp8_scale, L.maxbits,
+                              s));
     int32_t hstats[2] = {0, 0};
     TRY(hipMemcpyAsync(hstats, L.stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
@@ -199,7 +212,11 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     ix->ngroups = hstats[0];
     ix->max_list = hstats[1];
     ix->nlist = nlist;
-    ix->dtype_mask = 1 << PDX_DTYPE_F32;
+    ix->dtype_mask = (1 << PDX_DTYPE_F32) | params->lowp_mask;
+    ix->pdx_bf16 = L.pdx16;
+    ix->pdx_fp8 = L.pdx8;
+    ix->fp8_scale = L.fp8_scale;
+    ix->xrow = L.xrot;
     ix->has_rot = has_rot;
     ix->rot = L.rot;
     ix->centroids = L.centroids;
@@ -258,8 +275,12 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
         set_error("pdx_search_ivf: need delta_d >= 0 and eps0 >= 0");
         return PDX_EINVAL;
     }
-    if (params && !((index->dtype_mask >> params->dtype) & 1)) {
-        set_error("pdx_search_ivf: dtype %d is not stored in this index", params->dtype);
+    if (params && (params->dtype < 0 || params->dtype > PDX_DTYPE_FP8 || !((index->dtype_mask >> params->dtype) & 1))) {
+        set_error("pdx_search_ivf: dtype %d is not stored in this index", params ? params->dtype : -1);
+        return PDX_EUNSUPPORTED;
+    }
+    if (params && params->dtype != PDX_DTYPE_F32 && params->rerank > PDX_MAX_K) {
+        set_error("pdx_search_ivf: rerank=%d above PDX_MAX_K=%d", params->rerank, PDX_MAX_K);
         return PDX_EUNSUPPORTED;
     }
     if (nq == 0) return PDX_OK;
