@@ -158,13 +158,63 @@ def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, tr
             "nprobe_at_recall_0.95": None if best is None else best["nprobe"]}
 
 
+def bench_lowp(pdx, torch, np, x_np, q_np, x_dev, q_dev, k, steps, warmup, truth_ids, nlist=2048, nprobe=32,
+               rerank=40, seed=42):
+    """IVF + ADSampling over f32, bfloat16 and float8 storage of the same
+    index; recall@10 and the distance error against the FP64 oracle."""
+    from oracle.exact import recall_at_k, sqdist
+    n, d = x_dev.shape
+    nq = q_dev.shape[0]
+    rng = np.random.default_rng(seed)
+    gauss = torch.from_numpy(rng.standard_normal((d, d))).cuda()
+    init = torch.from_numpy(rng.choice(n, nlist, replace=False).astype(np.int64)).cuda()
+    t0 = time.perf_counter()
+    ix = pdx.pdx_ivf_build(x_dev, nlist, gauss, init, kmeans_iters=20, lowp=("bf16", "fp8"))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    print(f"# ivf index (f32+bf16+fp8) built in {build_s:.1f}s", file=sys.stderr, flush=True)
+    rot = pdx.pdx_ivf_export(ix)[0].cpu().numpy().astype(np.float64)
+    s_n = 0 if truth_ids is None else truth_ids.shape[0]
+    qrot = q_np[:s_n].astype(np.float64) @ rot.T
+    res = {}
+    for dtype in ("f32", "bf16", "fp8"):
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, nprobe, dtype=dtype, rerank=rerank)),
+                         dtype=torch.uint8, device="cuda")
+        out = {}
+
+        def run(evs, dtype=dtype, ws=ws, out=out):
+            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, nprobe, eps0=2.1, dtype=dtype, rerank=rerank, workspace=ws,
+                                          phase_events=evs)
+
+        elapsed, ph = timed_steps(run, steps, warmup, torch, np)
+        ids = out["r"][0].cpu().numpy()
+        row = {"qps": round(nq * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
+               "phases_ms": {"prep_start": round(ph[0], 3), "pruned_scan": round(ph[1], 3), "merge_rerank": round(ph[2], 3)}}
+        if s_n:
+            row["recall@10"] = round(recall_at_k(truth_ids, ids[:s_n]), 4)
+            # distance error of the scanned (not re-ranked) low-precision distances
+            ai, ad = pdx.pdx_search_ivf(ix, q_dev[:s_n], k, nprobe, eps0=2.1, dtype=dtype, rerank=-1)
+            ai, ad = ai.cpu().numpy(), ad.cpu().numpy().astype(np.float64)
+            err = 0.0
+            for i in range(s_n):
+                ok = ai[i] >= 0
+                true = sqdist(x_np[ai[i][ok]].astype(np.float64) @ rot.T, qrot[i])
+                err = max(err, float(np.max(np.abs(ad[i][ok] - true) / np.maximum(true, 1e-30))))
+            row["max_rel_distance_error_scanned"] = err
+        print(f"# {dtype}: {row}", file=sys.stderr, flush=True)
+        res[dtype] = row
+        del ws
+    return {"nlist": nlist, "nprobe": nprobe, "rerank": rerank, "eps0": 2.1, "build_s": round(build_s, 2),
+            "bytes_per_vector": {"f32": 4 * d, "bf16": 2 * d, "fp8": d}, "recall_queries": s_n, "by_dtype": res}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bond_1m_d960",
-                    choices=["bond_1m_d960", "ivf_1m_d1536", "linear_10k_d128"])
+                    choices=["bond_1m_d960", "ivf_1m_d1536", "lowp_5m_d768", "linear_10k_d128"])
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--tile-groups", type=int, default=0)
     ap.add_argument("--qpb", type=int, default=0)
@@ -217,6 +267,18 @@ def main() -> int:
                "sample": f"first {done} of {nq} queries against all {n} x {d} vectors, FP64 brute force "
                          f"(C, OpenMP, {threads} threads), {tc:.1f}s"}
         print(f"# oracle sample {done} queries in {tc:.1f}s", file=sys.stderr, flush=True)
+
+    if args.workload == "lowp_5m_d768":
+        res = bench_lowp(pdx, torch, np, x_np, q_np, x, q, k, args.steps, args.warmup, truth)
+        out = {"metric": METRIC, "value": res["by_dtype"]["fp8"]["qps"], "unit": "queries/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["by_dtype"]["fp8"]["ms_per_step"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp8-e4m3 storage, f32 accumulate",
+               "data": "synthetic",
+               "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "index": "ivf", "nlist": 2048,
+                          "nprobe": 32, "rerank": 40, "exact": False},
+               "roofline": None, "cpu_baseline": cpu, "extra": {"lowp": res}}
+        print(json.dumps(out), flush=True)
+        return 0
 
     if args.workload == "ivf_1m_d1536":
         res = bench_ivf(pdx, torch, np, x, q, 1024, [8, 16, 32, 64], k, args.steps, args.warmup, truth)

@@ -186,11 +186,9 @@ __device__ inline uint32_t e4m3_encode(float v) {
     uint32_t code = (static_cast<uint32_t>(e + 7) << 3) + r;
     return sign | (code > 0x7eu ? 0x7eu : code);
 }
-__device__ inline float e4m3_decode(uint32_t c) {
-    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
-    const float v = e == 0 ? static_cast<float>(m) * 0.001953125f : __uint_as_float(((e + 120u) << 23) | (m << 20));
-    return (c & 0x80u) ? -v : v;
-}
+// Decoding is exact (every code is a float32 value); gfx950's conversion
+// instruction reads the OCP e4m3 format from the low byte.
+__device__ inline float e4m3_decode(uint32_t c) { return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(c), 0); }
 
 hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int32_t *slot_id, const int32_t *stats,
                              int64_t max_groups, uint16_t *pdx16, uint8_t *pdx8, float *scale, uint32_t *maxbits,
