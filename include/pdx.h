@@ -205,6 +205,15 @@ typedef struct {
     unsigned long long *counters; /* device [4], added to: [0] values evaluated
                             by START, [1] its lane slots, [2] values evaluated
                             by the pruned scan (live lanes), [3] its lane slots */
+    /* Learned early termination (see pdx_mlp_*; NULL = plain search).      */
+    const void *mlp;       /* network state; a query stops at a checkpoint when
+                              sigmoid(z) > mlp_threshold                      */
+    float mlp_threshold;
+    /* Checkpoint traces (NULL = off; the search then probes all nprobe
+     * buckets and records, for every query and checkpoint c < 5):          */
+    float *trace_features; /* [nq][5][72] network inputs                     */
+    int64_t *trace_ids;    /* [nq][5][k] k-best ids after the checkpoint's
+                              buckets (checkpoints at or beyond nprobe: -1)  */
 } pdx_ivf_search_params;
 
 PDX_API size_t pdx_search_ivf_workspace(const pdx_index *index, int64_t nq, int32_t k, int32_t nprobe,
@@ -229,6 +238,42 @@ PDX_API size_t pdx_search_ivf_workspace(const pdx_index *index, int64_t nq, int3
 PDX_API pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, int32_t k,
                           int32_t nprobe, const pdx_ivf_search_params *params, void *ws,
                           size_t ws_bytes, int64_t *out_ids, float *out_dist, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Learned early termination for the IVF search
+ *
+ * A small network decides, at probe checkpoints (after 2, 4, 8, 16 and 32
+ * probed buckets), whether a query can stop probing.  This is an addition
+ * beside the paper's fixed-nprobe IVF search (Section 2.1) and its
+ * ADSampling test (Section 2.3), which remain the fallback: with no network
+ * the search is the plain one.  Inputs (72): the first 64 rotated query
+ * coordinates, then tau/d_r, d_r/d_0, d_last/d_0, tau/d_0 and
+ * log2(r)/log2(nprobe), each ratio clamped to [0, 1e4] (tau: the k-th
+ * distance over the r buckets probed so far; d_i: the squared distance to
+ * the i-th probed centroid, d_r the next one), then 3 zeros.  Network:
+ * relu(64) -> relu(64) -> logit, float16 weights, float32 accumulation.
+ * State buffer (pdx_mlp_bytes): float32 parameters W1[64][72] b1[64]
+ * W2[64][64] b2[64] w3[64] b3 (8897 used, 8960 padded), Adam moments,
+ * gradient, and the float16 copy the search and pdx_mlp_forward use.
+ * ------------------------------------------------------------------ */
+
+PDX_API size_t pdx_mlp_bytes(void);
+/* Device workspace for pdx_mlp_grad / pdx_mlp_train_step over n samples. */
+PDX_API size_t pdx_mlp_workspace(int64_t n);
+/* Set the parameters to theta0 [8960] float32 device (random numbers drawn
+ * by the caller), zero the Adam moments, refresh the float16 copy. */
+PDX_API pdx_status pdx_mlp_init(void *mlp, const float *theta0, void *stream);
+/* z [n] = logits of x [n][72] with the float16 weights. */
+PDX_API pdx_status pdx_mlp_forward(const void *mlp, const float *x, int64_t n, float *z, void *stream);
+/* Gradient [8960] of L = (1/n) sum(-y log p - w0 (1-y) log(1-p)), p = sigmoid(z),
+ * with respect to the parameters, the network evaluated with its float16
+ * weights; loss (device float, may be NULL) receives L.  Deterministic. */
+PDX_API pdx_status pdx_mlp_grad(const void *mlp, const float *x, const float *y, int64_t n, float w0, void *ws,
+                                size_t ws_bytes, float *grad, float *loss, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on the
+ * full batch x [n][72], labels y [n] in {0,1}; refreshes the float16 copy. */
+PDX_API pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y, int64_t n, float w0, float lr,
+                                      int64_t step, void *ws, size_t ws_bytes, float *loss, void *stream);
 
 /* ---------------------------------------------------------------------
  * Handles and diagnostics

@@ -5,6 +5,7 @@ The search itself lives in ``libpdx.so`` (HIP kernels behind the C ABI of
 binding requires the built library; there is no CPU fallback.
 """
 from .api import (  # noqa: F401
+    MlpState,
     PdxIndex,
     pdx_build,
     pdx_ivf_build,

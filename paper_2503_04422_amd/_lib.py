@@ -30,6 +30,10 @@ PDX_DTYPE_F32 = 0
 PDX_DTYPE_BF16 = 1
 PDX_DTYPE_FP8 = 2
 
+MLP_IN = 72
+MLP_PARAMS = 8960
+MLP_CHECKPOINTS = 5
+
 c_void_p = ctypes.c_void_p
 c_int32 = ctypes.c_int32
 c_int64 = ctypes.c_int64
@@ -53,7 +57,9 @@ class pdx_ivf_params(ctypes.Structure):
 
 class pdx_ivf_search_params(ctypes.Structure):
     _fields_ = [("eps0", ctypes.c_float), ("delta_d", c_int32), ("dtype", c_int32),
-                ("rerank", c_int32), ("phase_events", c_void_p), ("counters", c_void_p)]
+                ("rerank", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
+                ("mlp", c_void_p), ("mlp_threshold", ctypes.c_float), ("trace_features", c_void_p),
+                ("trace_ids", c_void_p)]
 
 
 # name -> (restype, argtypes)
@@ -75,6 +81,14 @@ SIGNATURES = {
     "pdx_search_ivf": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32,
                                  ctypes.POINTER(pdx_ivf_search_params), c_void_p, c_size_t,
                                  c_void_p, c_void_p, c_void_p]),
+    "pdx_mlp_bytes": (c_size_t, []),
+    "pdx_mlp_workspace": (c_size_t, [c_int64]),
+    "pdx_mlp_init": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "pdx_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "pdx_mlp_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, c_void_p, c_size_t,
+                               c_void_p, c_void_p, c_void_p]),
+    "pdx_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, ctypes.c_float,
+                                     c_int64, c_void_p, c_size_t, c_void_p, c_void_p]),
     "pdx_free": (None, [c_void_p]),
     "pdx_last_error": (ctypes.c_char_p, []),
     "pdx_version": (ctypes.c_char_p, []),

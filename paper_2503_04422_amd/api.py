@@ -163,24 +163,75 @@ def pdx_ivf_export(index: PdxIndex, stream: Optional[torch.cuda.Stream] = None):
 
 def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delta_d: int = 0,
                              dtype: str = "f32", rerank: int = 0) -> int:
-    p = _lib.pdx_ivf_search_params(2.1, int(delta_d), _DTYPES[dtype], int(rerank), None, None)
+    p = _lib.pdx_ivf_search_params(2.1, int(delta_d), _DTYPES[dtype], int(rerank), None, None, None, 0.5, None,
+                                   None)
     return int(lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p)))
+
+
+class MlpState:
+    """Device state of the learned early-termination network (pdx_mlp_*)."""
+
+    def __init__(self, theta0: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+        if not theta0.is_cuda or theta0.dtype != torch.float32 or theta0.numel() != _lib.MLP_PARAMS:
+            raise TypeError(f"theta0 must be a float32 GPU tensor of {_lib.MLP_PARAMS} values")
+        self.mem = torch.empty(lib.pdx_mlp_bytes(), dtype=torch.uint8, device=theta0.device)
+        self._ws = None
+        check(lib.pdx_mlp_init(_ptr(self.mem), _ptr(theta0.contiguous()), _stream(stream)), "pdx_mlp_init")
+
+    def _workspace(self, n: int) -> torch.Tensor:
+        need = lib.pdx_mlp_workspace(n)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.mem.device)
+        return self._ws
+
+    def forward(self, x: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        x = _dev_f32(x, "x")
+        z = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        check(lib.pdx_mlp_forward(_ptr(self.mem), _ptr(x), x.shape[0], _ptr(z), _stream(stream)), "pdx_mlp_forward")
+        return z
+
+    def grad(self, x: torch.Tensor, y: torch.Tensor, w0: float, stream: Optional[torch.cuda.Stream] = None):
+        x = _dev_f32(x, "x")
+        y = y.contiguous()
+        g = torch.empty(_lib.MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        ws = self._workspace(x.shape[0])
+        check(lib.pdx_mlp_grad(_ptr(self.mem), _ptr(x), _ptr(y), x.shape[0], float(w0), _ptr(ws), ws.numel(),
+                               _ptr(g), _ptr(loss), _stream(stream)), "pdx_mlp_grad")
+        return g, loss
+
+    def train_step(self, x: torch.Tensor, y: torch.Tensor, w0: float, lr: float, step: int,
+                   loss: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> None:
+        x = _dev_f32(x, "x")
+        ws = self._workspace(x.shape[0])
+        check(lib.pdx_mlp_train_step(_ptr(self.mem), _ptr(x), _ptr(y.contiguous()), x.shape[0], float(w0),
+                                     float(lr), int(step), _ptr(ws), ws.numel(), _ptr(loss), _stream(stream)),
+              "pdx_mlp_train_step")
 
 
 def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1,
                    delta_d: int = 0, dtype: str = "f32", rerank: int = 0,
                    workspace: Optional[torch.Tensor] = None, phase_events=None,
-                   counters: Optional[torch.Tensor] = None,
+                   counters: Optional[torch.Tensor] = None, mlp: Optional[MlpState] = None,
+                   mlp_threshold: float = 0.5, trace: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                    stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
-    """Approximate k nearest neighbours (IVF + ADSampling)."""
+    """Approximate k nearest neighbours (IVF + ADSampling), optionally with the
+    learned early termination (mlp) or recording checkpoint traces
+    (trace = (features [nq, 5, 72] float32, ids [nq, 5, k] int64))."""
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     if q.shape[1] != index.d:
         raise ValueError("query dimension does not match the index")
+    tf, ti = (None, None) if trace is None else trace
+    if tf is not None and (tf.dtype != torch.float32 or tf.numel() != nq * _lib.MLP_CHECKPOINTS * _lib.MLP_IN):
+        raise TypeError("trace features must be float32 [nq, 5, 72]")
+    if ti is not None and (ti.dtype != torch.int64 or ti.numel() != nq * _lib.MLP_CHECKPOINTS * k):
+        raise TypeError("trace ids must be int64 [nq, 5, k]")
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
                                    _DTYPES[dtype], int(rerank),
                                    ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
-                                   _ptr(counters))
+                                   _ptr(counters), None if mlp is None else _ptr(mlp.mem), float(mlp_threshold),
+                                   _ptr(tf), _ptr(ti))
     ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
     need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))

@@ -13,6 +13,7 @@
 //     Section 2.3), at d = D when partial > tau; survivors enter the wave's
 //     k-best list, whose k-th distance tightens the query's threshold;
 //  6. merge of the per-item k-best lists.
+#include "mlp_device.h"
 #include "pdx_internal.h"
 #include "wave_topk.h"
 
@@ -63,15 +64,30 @@ __global__ __launch_bounds__(256) void select_probe_kernel(const float *__restri
 
 // items per bucket: count, exclusive prefix, scatter (START items r = 0 and
 // pruned items r >= 1 in two separate lists)
-__global__ void item_count_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe,
-                                  int32_t *__restrict__ cnt0, int32_t *__restrict__ cnt1) {
+// Probe ranks >= 1 are cut into stages at the checkpoints: items are grouped
+// by (stage, bucket), so each stage is one contiguous range of items.
+struct Stages {
+    int32_t n;         // number of stages of ranks >= 1
+    int32_t b[8];      // stage s covers ranks [b[s], b[s+1]); b[0] = 1, b[n] = nprobe
+};
+
+__device__ __forceinline__ int32_t stage_of(const Stages &st, int32_t r) {
+    int32_t s = 0;
+    while (s + 1 < st.n && r >= st.b[s + 1]) ++s;
+    return s;
+}
+
+__global__ void item_count_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe, int32_t nlist,
+                                  Stages st, int32_t *__restrict__ cnt0, int32_t *__restrict__ cnt1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq * nprobe) return;
     int32_t r = (int32_t)(i % nprobe);
-    atomicAdd((r == 0 ? cnt0 : cnt1) + probe[i], 1);
+    if (r == 0) atomicAdd(cnt0 + probe[i], 1);
+    else atomicAdd(cnt1 + (int64_t)stage_of(st, r) * nlist + probe[i], 1);
 }
 
 __global__ __launch_bounds__(1024) void item_prefix_kernel(int32_t *__restrict__ cnt, int32_t nlist) {
+    // (nlist here is the length of the count array)
     __shared__ int32_t s[1024];
     __shared__ int32_t carry;
     if (threadIdx.x == 0) carry = 0;
@@ -94,8 +110,8 @@ __global__ __launch_bounds__(1024) void item_prefix_kernel(int32_t *__restrict__
     }
 }
 
-__global__ void item_scatter_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe,
-                                    int32_t *__restrict__ cur0, int32_t *__restrict__ cur1,
+__global__ void item_scatter_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe, int32_t nlist,
+                                    Stages st, int32_t *__restrict__ cur0, int32_t *__restrict__ cur1,
                                     int2 *__restrict__ items0, int2 *__restrict__ items1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq * nprobe) return;
@@ -103,7 +119,7 @@ __global__ void item_scatter_kernel(const int32_t *__restrict__ probe, int64_t n
     int32_t qi = (int32_t)(i / nprobe);
     int32_t l = probe[i];
     if (r == 0) items0[atomicAdd(cur0 + l, 1)] = make_int2(qi, r);
-    else items1[atomicAdd(cur1 + l, 1)] = make_int2(qi, r);
+    else items1[atomicAdd(cur1 + (int64_t)stage_of(st, r) * nlist + l, 1)] = make_int2(qi, r);
 }
 
 // Scan of one bucket for one query per wave.  Work items are consecutive
@@ -125,7 +141,8 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nitems,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
     uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
-    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, uint32_t nwg) {
+    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, uint32_t nwg,
+    const int32_t *__restrict__ active) {
     // grid = 8 * ceil(nwg / 8): every (xcd, index) pair is launched once
     const uint32_t per_xcd = gridDim.x >> 3;
     const uint32_t wg = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -137,7 +154,7 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     const int64_t qi = item.x;
     const int32_t r = item.y;
     uint64_t *myslot = slots + ((size_t)qi * nprobe + r) * k;
-    if (bad[qi]) {
+    if (bad[qi] || (active && !active[qi])) {  // non-finite query, or it stopped probing
         if (lane < k) myslot[lane] = kEmptyKey;
         return;
     }
@@ -203,6 +220,66 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     if (counters && lane == 0) {
         atomicAdd(counters, live_vals);
         atomicAdd(counters + 1, lane_vals);
+    }
+}
+
+// Checkpoint after the first `cp` probed buckets: the k-best list over
+// those buckets (its last distance tightens the threshold for the later
+// buckets), the network's inputs (documented with pdx_mlp_* in
+// include/pdx.h), and optionally the trace and/or the stop decision.
+__global__ __launch_bounds__(64) void checkpoint_kernel(
+    int32_t cp, int32_t c, bool valid, const float *__restrict__ qrot, int32_t d, const float *__restrict__ cd,
+    int32_t nlist, const int32_t *__restrict__ probe, int32_t nprobe, uint32_t *__restrict__ tau,
+    const uint64_t *__restrict__ slots, int32_t kk, int32_t k, const int32_t *__restrict__ bad,
+    const __half *__restrict__ w16, float zthr, int32_t *__restrict__ active, float *__restrict__ trace_f,
+    int64_t *__restrict__ trace_ids) {
+    __shared__ float feat[kMlpIn];
+    const int64_t qi = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (!valid) {  // checkpoint at or beyond nprobe: trace only
+        if (trace_f)
+            for (int i = lane; i < kMlpIn; i += 64) trace_f[(qi * kMlpCheckpoints + c) * kMlpIn + i] = 0.0f;
+        if (trace_ids && lane < k) trace_ids[(qi * kMlpCheckpoints + c) * k + lane] = -1;
+        return;
+    }
+    // k-best over the buckets probed so far
+    const uint64_t *base = slots + (size_t)qi * nprobe * kk;
+    const int64_t total = (int64_t)cp * kk;
+    uint64_t e = kEmptyKey, kth = kEmptyKey;
+    for (int64_t i0 = 0; i0 < total; i0 += kWave) {
+        uint64_t key = (i0 + lane < total) ? base[i0 + lane] : kEmptyKey;
+        topk_offer(e, kth, key, key != kEmptyKey, kk, lane);
+    }
+    float t = INFINITY;
+    if (kth != kEmptyKey) {
+        t = key_dist(kth);
+        if (lane == 0 && static_cast<uint32_t>(kth >> 32) < tau[qi]) tau[qi] = static_cast<uint32_t>(kth >> 32);
+    }
+    if (trace_ids && lane < k)
+        trace_ids[(qi * kMlpCheckpoints + c) * k + lane] = (bad[qi] || e == kEmptyKey) ? -1 : (int64_t)(e & 0xffffffffu);
+    if (!trace_f && !w16) return;
+    const float *cq = cd + qi * nlist;
+    const int32_t *pq = probe + qi * nprobe;
+    const float d0 = cq[pq[0]] + 1e-20f;
+    const float dr = cq[pq[cp]] + 1e-20f;
+    const float dl = cq[pq[nprobe - 1]] + 1e-20f;
+    auto clampr = [](float v) { return fminf(fmaxf(v, 0.0f), 1.0e4f); };
+    feat[lane] = lane < d ? qrot[qi * d + lane] : 0.0f;
+    if (lane < kMlpIn - 64) {
+        float v = 0.0f;
+        if (lane == 0) v = clampr(t / dr);
+        else if (lane == 1) v = clampr(dr / d0);
+        else if (lane == 2) v = clampr(dl / d0);
+        else if (lane == 3) v = clampr(t / d0);
+        else if (lane == 4) v = log2f((float)cp) / log2f((float)nprobe);
+        feat[64 + lane] = v;
+    }
+    __syncthreads();
+    if (trace_f)
+        for (int i = lane; i < kMlpIn; i += 64) trace_f[(qi * kMlpCheckpoints + c) * kMlpIn + i] = feat[i];
+    if (w16 && active[qi] && !bad[qi]) {
+        const float z = mlp_forward_wave(w16, feat, lane, nullptr, nullptr, nullptr, nullptr);
+        if (lane == 0 && z > zthr) active[qi] = 0;
     }
 }
 
@@ -304,6 +381,23 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         pl.rerank = r < 0 ? 0 : max(r, k);
     }
     pl.kk = pl.rerank > 0 ? pl.rerank : k;
+    pl.w16 = (p && p->mlp) ? mlp_layout(const_cast<void *>(p->mlp)).w16 : nullptr;
+    pl.trace_f = p ? p->trace_features : nullptr;
+    pl.trace_ids = p ? p->trace_ids : nullptr;
+    if (pl.trace_f || pl.trace_ids) pl.w16 = nullptr;  // traces probe every bucket
+    {
+        float th = p ? p->mlp_threshold : 0.5f;
+        th = fminf(fmaxf(th, 1e-7f), 1.0f - 1e-7f);
+        pl.zthr = logf(th / (1.0f - th));
+    }
+    pl.nstages = 1;
+    pl.stage_b[0] = 1;
+    if (pl.w16 || pl.trace_f || pl.trace_ids) {
+        const int32_t cps[kMlpCheckpoints] = {2, 4, 8, 16, 32};
+        for (int32_t c = 0; c < kMlpCheckpoints; ++c)
+            if (cps[c] < nprobe) pl.stage_b[pl.nstages++] = cps[c];
+    }
+    pl.stage_b[pl.nstages] = nprobe;
     int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
     pl.chunk = dd;
     size_t q = (size_t)(nq > 0 ? nq : 0);
@@ -314,7 +408,8 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.bad = c.take<int32_t>(q);
     pl.tau = c.take<uint32_t>(q);
     pl.cnt0 = c.take<int32_t>(ix->nlist);
-    pl.cnt1 = c.take<int32_t>(ix->nlist);
+    pl.cnt1 = c.take<int32_t>((size_t)ix->nlist * 8);
+    pl.active = c.take<int32_t>(q);
     pl.items0 = c.take<int2>(q);
     pl.items1 = c.take<int2>(q * (nprobe - 1 > 0 ? nprobe - 1 : 1));
     pl.slots = c.take<uint64_t>(q * nprobe * pl.kk);
@@ -348,14 +443,20 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                                          pl.probe, pl.bad, pl.tau);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 3. work items grouped by bucket
+    Stages st{};
+    st.n = pl.nstages;
+    for (int32_t i = 0; i <= pl.nstages; ++i) st.b[i] = pl.stage_b[i];
+    const int32_t ncnt1 = ix->nlist * pl.nstages;
     if ((e = launch_fill_i32(pl.cnt0, ix->nlist, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(pl.cnt1, ix->nlist, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(pl.cnt1, ncnt1, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(pl.active, nq, 1, s)) != hipSuccess) return e;
     int64_t tot = nq * pl.nprobe;
     unsigned gb = (unsigned)((tot + 255) / 256);
-    item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, pl.cnt0, pl.cnt1);
+    item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, ix->nlist, st, pl.cnt0, pl.cnt1);
     item_prefix_kernel<<<1, 1024, 0, s>>>(pl.cnt0, ix->nlist);
-    item_prefix_kernel<<<1, 1024, 0, s>>>(pl.cnt1, ix->nlist);
-    item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, pl.cnt0, pl.cnt1, pl.items0, pl.items1);
+    item_prefix_kernel<<<1, 1024, 0, s>>>(pl.cnt1, ncnt1);
+    item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, ix->nlist, st, pl.cnt0, pl.cnt1, pl.items0,
+                                          pl.items1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. START
     int64_t n0 = nq, n1 = nq * (pl.nprobe - 1);
@@ -369,11 +470,11 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                        : pl.dtype == PDX_DTYPE_FP8 ? static_cast<const void *>(ix->pdx_fp8)
                                                    : static_cast<const void *>(ix->pdx);
     auto scan = [&](bool prune, unsigned grid, const int2 *items, int64_t nitems, unsigned long long *cnt,
-                    uint32_t nwg) {
+                    uint32_t nwg, const int32_t *act) {
 #define PDX_SCAN(P, S)                                                                                          \
     ivf_scan_kernel<P, S><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, nitems, \
                                                pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots, pl.kk,     \
-                                               pl.chunk, pl.eps0, cnt, nwg)
+                                               pl.chunk, pl.eps0, cnt, nwg, act)
         if (prune) {
             if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16);
             else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8);
@@ -386,15 +487,42 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
 #undef PDX_SCAN
         return hipGetLastError();
     };
-    if ((e = scan(false, grid0, pl.items0, n0, pl.counters, nwg0)) != hipSuccess) return e;
+    if ((e = scan(false, grid0, pl.items0, n0, pl.counters, nwg0, nullptr)) != hipSuccess) return e;
     ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, 1, pl.kk, pl.bad, pl.tau, nullptr, nullptr,
                                                 nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark(1)) != hipSuccess) return e;
-    // 5. pruned scan of the other probed buckets
-    if (n1 > 0) {
-        if ((e = scan(true, grid1, pl.items1, n1, pl.counters ? pl.counters + 2 : nullptr, nwg1)) != hipSuccess)
+    // 5. pruned scan of the other probed buckets, stage by stage; between
+    //    stages the checkpoint (trace and/or learned stop decision)
+    (void)grid1;
+    (void)nwg1;
+    const bool staged = pl.w16 || pl.trace_f || pl.trace_ids;
+    for (int32_t sg = 0; sg < pl.nstages && n1 > 0; ++sg) {
+        if (sg > 0 && staged) {
+            const int32_t cp = pl.stage_b[sg];
+            int32_t c = 0;
+            while (c < kMlpCheckpoints && (2 << c) != cp) ++c;
+            checkpoint_kernel<<<(unsigned)nq, 64, 0, s>>>(cp, c, true, pl.qrot, d, pl.cd, ix->nlist, pl.probe,
+                                                          pl.nprobe, pl.tau, pl.slots, pl.kk, pl.k, pl.bad, pl.w16,
+                                                          pl.zthr, pl.active, pl.trace_f, pl.trace_ids);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const int64_t i0 = nq * (int64_t)(pl.stage_b[sg] - 1), i1 = nq * (int64_t)(pl.stage_b[sg + 1] - 1);
+        if (i1 <= i0) continue;
+        uint32_t nwg;
+        unsigned grid = grid_of(i1 - i0, &nwg);
+        if ((e = scan(true, grid, pl.items1 + i0, i1 - i0, pl.counters ? pl.counters + 2 : nullptr, nwg,
+                      pl.w16 ? pl.active : nullptr)) != hipSuccess)
             return e;
+    }
+    if (pl.trace_f || pl.trace_ids) {  // checkpoints at or beyond nprobe
+        for (int32_t c = 0; c < kMlpCheckpoints; ++c) {
+            if ((2 << c) < pl.nprobe) continue;
+            checkpoint_kernel<<<(unsigned)nq, 64, 0, s>>>(2 << c, c, false, pl.qrot, d, pl.cd, ix->nlist, pl.probe,
+                                                          pl.nprobe, pl.tau, pl.slots, pl.kk, pl.k, pl.bad, nullptr,
+                                                          pl.zthr, pl.active, pl.trace_f, pl.trace_ids);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     if ((e = mark(2)) != hipSuccess) return e;
     // 6. merge

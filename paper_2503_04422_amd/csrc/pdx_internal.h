@@ -1,6 +1,7 @@
 // Internal declarations shared by the libpdx translation units.
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -117,6 +118,13 @@ struct IvfPlan {
     uint32_t *tau;     // [nq]
     int32_t *cnt0, *cnt1;  // [nlist] item cursors
     int2 *items0, *items1;
+    int32_t *active;   // [nq] 0 once the learned stop fired
+    const __half *w16; // network weights (null: plain search)
+    float zthr;        // stop when the logit exceeds this
+    float *trace_f;
+    int64_t *trace_ids;
+    int32_t nstages;
+    int32_t stage_b[8];
     uint64_t *slots;   // [nq][nprobe][kk]
     uint64_t *rkeys;   // [nq][kk] candidates to rerank
     hipEvent_t *events;
@@ -193,5 +201,29 @@ __device__ inline float e4m3_decode(uint32_t c) { return __builtin_amdgcn_cvt_f3
 hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int32_t *slot_id, const int32_t *stats,
                              int64_t max_groups, uint16_t *pdx16, uint8_t *pdx8, float *scale, uint32_t *maxbits,
                              hipStream_t s);
+
+}  // namespace pdx
+
+namespace pdx {
+
+// ---- learned early-termination network ----
+constexpr int kMlpIn = 72;     // inputs: 64 query coordinates + 5 ratios + 3 zero pads
+constexpr int kMlpH = 64;      // hidden width (= wave width)
+constexpr int kMlpPad = 8960;  // padded parameter count
+constexpr int kMlpCheckpoints = 5;  // after 2, 4, 8, 16, 32 probed buckets
+
+struct MlpLayout {
+    float *theta, *m, *v, *g;
+    __half *w16;
+    float *loss;
+    size_t bytes;
+};
+MlpLayout mlp_layout(void *base);
+hipError_t launch_mlp_init(const MlpLayout &L, const float *theta0, hipStream_t s);
+hipError_t launch_mlp_forward(const __half *w16, const float *x, int64_t n, float *z, hipStream_t s);
+hipError_t launch_mlp_grad(const MlpLayout &L, const float *x, const float *y, int64_t n, float w0, float *work,
+                           float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(const MlpLayout &L, float lr, int64_t step, hipStream_t s);
+size_t mlp_work_floats(int64_t n);
 
 }  // namespace pdx
