@@ -119,18 +119,23 @@ def oracle_sample(x_np, q_np, k, budget_s, np):
     return done, tc, threads, np.concatenate(ids), np.concatenate(dist)
 
 
-def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, truth_ids, seed=42):
-    from oracle.exact import recall_at_k
+def build_ivf(pdx, torch, np, x_dev, nlist, seed=42, **kw):
     n, d = x_dev.shape
-    nq = q_dev.shape[0]
     rng = np.random.default_rng(seed)
     gauss = torch.from_numpy(rng.standard_normal((d, d))).cuda()
     init = torch.from_numpy(rng.choice(n, nlist, replace=False).astype(np.int64)).cuda()
     t0 = time.perf_counter()
-    ix = pdx.pdx_ivf_build(x_dev, nlist, gauss, init, kmeans_iters=20)
+    ix = pdx.pdx_ivf_build(x_dev, nlist, gauss, init, kmeans_iters=20, **kw)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     print(f"# ivf index built in {build_s:.1f}s", file=sys.stderr, flush=True)
+    return ix, build_s
+
+
+def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, truth_ids, seed=42, index=None):
+    from oracle.exact import recall_at_k
+    nq = q_dev.shape[0]
+    ix, build_s = index if index is not None else build_ivf(pdx, torch, np, x_dev, nlist, seed)
     sizes = pdx.pdx_ivf_export(ix)[3].cpu().numpy()
     sweep = []
     best = None
@@ -156,6 +161,98 @@ def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, tr
             "sweep": sweep, "recall_queries": None if truth_ids is None else int(truth_ids.shape[0]),
             "qps_at_recall_0.95": None if best is None else best["qps"],
             "nprobe_at_recall_0.95": None if best is None else best["nprobe"]}
+
+
+def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu_seconds, target=0.95,
+                  nprobe_max=32, n_train=8000, n_val=2000, seed_train=43, seed_eval=44):
+    """Learned early termination against plain IVF + ADSampling at equal
+    recall@10 on the same index.  Training queries (seed 43) are split into
+    traces (first n_train) and validation (last n_val); the operating point
+    of each method (plain: the smallest nprobe; learned: the most aggressive
+    stop threshold) is the cheapest one reaching `target` recall on the
+    validation queries, then both are timed and scored on 10,000 fresh
+    evaluation queries (seed 44).  Ground truth: the exact search, checked
+    against the FP64 oracle on a sample of the evaluation queries."""
+    from oracle.exact import recall_at_k
+    from tests.parity import check_knn
+    learn = pdx.learn
+    qt_np = mix.queries(n_train + n_val, seed_train)
+    qe_np = mix.queries(10_000, seed_eval)
+    qt, qe = torch.from_numpy(qt_np).cuda(), torch.from_numpy(qe_np).cuda()
+    qv = qt[n_train:]
+    tv = pdx.pdx_search_exact(exact_ix, qv, k, mode="bond")[0].cpu().numpy()
+    te, te_d = (t.cpu().numpy() for t in pdx.pdx_search_exact(exact_ix, qe, k, mode="bond"))
+    done, o_ids = 0, None
+    if cpu_seconds > 0:
+        done, _, _, o_ids, o_d = oracle_sample(x_np, qe_np, k, cpu_seconds, np)
+        check_knn(x_np, qe_np[:done], te[:done], te_d[:done], o_ids, o_d)
+    print(f"# exact truth for {qe_np.shape[0]} evaluation queries; the oracle agrees on the first {done}",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    feats, labels, tstats = learn.stop_traces(ix, qt[:n_train], k, nprobe_max)
+    torch.cuda.synchronize()
+    trace_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, info = learn.train_stop_network(feats, labels)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    print(f"# traces {tstats['samples']} samples ({trace_s:.2f}s), training {train_s:.2f}s: {info}",
+          file=sys.stderr, flush=True)
+
+    cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+
+    def search(qd, **kw):
+        cnt.zero_()
+        i, _ = pdx.pdx_search_ivf(ix, qd, k, eps0=2.1, counters=cnt, **kw)
+        c = cnt.cpu().numpy()
+        return i.cpu().numpy(), float(c[0] + c[2]) / qd.shape[0]
+
+    plain_np = [2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32]
+    thresholds = [0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.98, 0.99]
+    val = {"plain": [], "learned": []}
+    pick_p = pick_t = None
+    for p in plain_np:
+        ids, work = search(qv, nprobe=p)
+        r = recall_at_k(tv, ids)
+        val["plain"].append({"nprobe": p, "recall@10": round(r, 4), "values_per_query": round(work)})
+        if pick_p is None and r >= target:
+            pick_p = p
+    for t in thresholds:
+        ids, work = search(qv, nprobe=nprobe_max, mlp=net, mlp_threshold=t)
+        r = recall_at_k(tv, ids)
+        val["learned"].append({"threshold": t, "recall@10": round(r, 4), "values_per_query": round(work)})
+        if pick_t is None and r >= target:
+            pick_t = t
+    print(f"# validation picks: plain nprobe {pick_p}, learned threshold {pick_t}", file=sys.stderr, flush=True)
+
+    def timed(**kw):
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, qe.shape[0], k, kw["nprobe"])),
+                         dtype=torch.uint8, device="cuda")
+        out = {}
+
+        def run(evs):
+            out["r"] = pdx.pdx_search_ivf(ix, qe, k, eps0=2.1, workspace=ws, phase_events=evs, **kw)
+
+        elapsed, _ = timed_steps(run, steps, warmup, torch, np)
+        ids = out["r"][0].cpu().numpy()
+        _, work = search(qe, **kw)
+        return {"qps": round(qe.shape[0] * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
+                "recall@10": round(recall_at_k(te, ids), 4),
+                "recall@10_oracle_sample": round(recall_at_k(o_ids, ids[:done]), 4) if done else None,
+                "values_per_query": round(work)}
+
+    res = {"target_recall": target, "nprobe_max": nprobe_max, "train_queries": n_train, "val_queries": n_val,
+           "eval_queries": int(qe.shape[0]), "oracle_checked_eval_queries": done,
+           "traces": tstats, "trace_s": round(trace_s, 3), "train": info, "train_s": round(train_s, 3),
+           "validation": val}
+    if pick_p is not None:
+        res["plain"] = dict(nprobe=pick_p, **timed(nprobe=pick_p))
+    if pick_t is not None:
+        res["learned"] = dict(threshold=pick_t, **timed(nprobe=nprobe_max, mlp=net, mlp_threshold=pick_t))
+    if "plain" in res and "learned" in res:
+        res["speedup_qps"] = round(res["learned"]["qps"] / res["plain"]["qps"], 3)
+    print(f"# learned: {res.get('plain')} vs {res.get('learned')}", file=sys.stderr, flush=True)
+    return res
 
 
 def bench_lowp(pdx, torch, np, x_np, q_np, x_dev, q_dev, k, steps, warmup, truth_ids, nlist=2048, nprobe=32,
@@ -223,6 +320,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-linear", action="store_true", help="skip the unpruned comparison run")
     ap.add_argument("--no-ivf", action="store_true", help="skip the IVF + ADSampling leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned early-termination leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -251,7 +349,7 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    x_np, q_np, _ = synth.workload(args.workload)
+    x_np, q_np, mix = synth.workload(args.workload)
     n, d = x_np.shape
     nq = q_np.shape[0]
     k = args.k
@@ -364,7 +462,11 @@ def main() -> int:
                                     "note": "same kernels, no pruning (PDX linear scan)"}
     del ws
     if mode == "bond" and not args.no_ivf:
-        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, [2, 4, 8, 16, 32, 64], k, 3, 1, truth)
+        ivf_ix = build_ivf(pdx, torch, np, x, 1024)
+        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, [2, 4, 8, 16, 32, 64], k, 3, 1, truth, index=ivf_ix)
+        if not args.no_learned:
+            extra["learned_stop"] = bench_learned(pdx, torch, np, ivf_ix[0], ix, x_np, mix, k, 3, 1,
+                                                  0 if args.no_cpu_baseline else args.cpu_seconds / 2)
 
     out = {
         "metric": METRIC,

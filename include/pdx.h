@@ -274,6 +274,9 @@ PDX_API pdx_status pdx_mlp_grad(const void *mlp, const float *x, const float *y,
  * full batch x [n][72], labels y [n] in {0,1}; refreshes the float16 copy. */
 PDX_API pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y, int64_t n, float w0, float lr,
                                       int64_t step, void *ws, size_t ws_bytes, float *loss, void *stream);
+/* Copy the float32 parameters [8960] to theta (device), e.g. to save them;
+ * pdx_mlp_init with the same vector restores the network. */
+PDX_API pdx_status pdx_mlp_export(const void *mlp, float *theta, void *stream);
 
 /* ---------------------------------------------------------------------
  * Handles and diagnostics

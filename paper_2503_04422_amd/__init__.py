@@ -16,3 +16,4 @@ from .api import (  # noqa: F401
     pdx_search_ivf_workspace,
     pdx_version,
 )
+from . import learn  # noqa: F401,E402

@@ -87,6 +87,7 @@ SIGNATURES = {
     "pdx_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "pdx_mlp_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, c_void_p, c_size_t,
                                c_void_p, c_void_p, c_void_p]),
+    "pdx_mlp_export": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "pdx_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, ctypes.c_float,
                                      c_int64, c_void_p, c_size_t, c_void_p, c_void_p]),
     "pdx_free": (None, [c_void_p]),

@@ -200,6 +200,12 @@ class MlpState:
                                _ptr(g), _ptr(loss), _stream(stream)), "pdx_mlp_grad")
         return g, loss
 
+    def theta(self, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """The float32 parameters [8960] (a copy)."""
+        t = torch.empty(_lib.MLP_PARAMS, dtype=torch.float32, device=self.mem.device)
+        check(lib.pdx_mlp_export(_ptr(self.mem), _ptr(t), _stream(stream)), "pdx_mlp_export")
+        return t
+
     def train_step(self, x: torch.Tensor, y: torch.Tensor, w0: float, lr: float, step: int,
                    loss: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> None:
         x = _dev_f32(x, "x")

@@ -78,4 +78,16 @@ pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y, int64_t
     return PDX_OK;
 }
 
+pdx_status pdx_mlp_export(const void *mlp, float *theta, void *stream) {
+    const char *what = "pdx_mlp_export";
+    if (!mlp || !theta) {
+        set_error("pdx_mlp_export: null pointer");
+        return PDX_EINVAL;
+    }
+    MlpLayout L = mlp_layout(const_cast<void *>(mlp));
+    TRY(hipMemcpyAsync(theta, L.theta, sizeof(float) * kMlpPad, hipMemcpyDeviceToDevice,
+                       static_cast<hipStream_t>(stream)));
+    return PDX_OK;
+}
+
 }  // extern "C"

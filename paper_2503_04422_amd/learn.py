@@ -1,0 +1,103 @@
+"""Training driver of the learned early termination (pdx_mlp_*).
+
+The network decides at probe checkpoints (after 2, 4, 8, 16, 32 probed
+buckets) whether a query of the IVF search may stop probing.  It learns from
+traces the search itself records:
+
+* a traced search (every probed bucket scanned, ADSampling as deployed)
+  writes, per query and checkpoint, the network's 72 inputs and the k-best
+  ids over the buckets probed so far;
+* label 1 ("stopping here loses nothing") iff that id set equals the final
+  result's id set, i.e. no vector of a later bucket enters the top-k;
+* training: Adam on minibatches of the shuffled samples, forward, backward
+  and update in the library's kernels; negatives weighted by w0 because a
+  wrong stop costs recall while a late stop only costs time.
+
+The IVF search of Section 2.1 with the ADSampling test of Section 2.3 stays
+the fallback: a query the network never stops is searched exactly as
+without it.  Host code here only arranges tensors (shuffling, slicing,
+label comparison); every forward, backward and update runs on the GPU.
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+from .api import MlpState, PdxIndex, pdx_search_ivf
+
+CHECKPOINTS = (2, 4, 8, 16, 32)
+
+
+def stop_traces(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1
+                ) -> Tuple[torch.Tensor, torch.Tensor, Dict[str, float]]:
+    """Traced search of queries q; returns (features [m, 72] float32 device,
+    labels [m] float32 device, stats) over the checkpoints below nprobe."""
+    nq = q.shape[0]
+    tf = torch.empty((nq, _lib.MLP_CHECKPOINTS, _lib.MLP_IN), dtype=torch.float32, device=q.device)
+    ti = torch.empty((nq, _lib.MLP_CHECKPOINTS, k), dtype=torch.int64, device=q.device)
+    ids, _ = pdx_search_ivf(index, q, k, nprobe, eps0=eps0, trace=(tf, ti))
+    valid = [c for c, cp in enumerate(CHECKPOINTS) if cp < nprobe]
+    if not valid:
+        raise ValueError("nprobe must exceed the first checkpoint (2)")
+    tih = np.sort(ti.cpu().numpy()[:, valid], axis=2)
+    fin = np.sort(ids.cpu().numpy(), axis=1)
+    y = np.all(tih == fin[:, None, :], axis=2).astype(np.float32)
+    feats = tf[:, valid].reshape(-1, _lib.MLP_IN).contiguous()
+    stats = {"samples": int(y.size), "positive_rate": float(y.mean()),
+             "positive_rate_by_checkpoint": {CHECKPOINTS[c]: float(y[:, i].mean()) for i, c in enumerate(valid)}}
+    return feats, torch.from_numpy(y.reshape(-1)).to(q.device), stats
+
+
+def initial_theta(seed: int = 0) -> np.ndarray:
+    """He-scaled Gaussian weights, zero biases, in the parameter layout
+    W1 [64][72] | b1 | W2 [64][64] | b2 | w3 | b3 (padded to 8960)."""
+    rng = np.random.default_rng(seed)
+    f, h = _lib.MLP_IN, 64
+    th = np.zeros(_lib.MLP_PARAMS, dtype=np.float32)
+    o = 0
+    th[o:o + h * f] = rng.standard_normal(h * f) * np.sqrt(2.0 / f)
+    o += h * f + h
+    th[o:o + h * h] = rng.standard_normal(h * h) * np.sqrt(2.0 / h)
+    o += h * h + h
+    th[o:o + h] = rng.standard_normal(h) * np.sqrt(1.0 / h)
+    return th
+
+
+def train_stop_network(feats: torch.Tensor, labels: torch.Tensor, steps: int = 2000, batch: int = 4096,
+                       lr: float = 2e-3, w0: float = 4.0, seed: int = 0,
+                       stream: Optional[torch.cuda.Stream] = None) -> Tuple[MlpState, Dict[str, float]]:
+    """Adam on minibatches of the shuffled samples; returns the trained
+    state and the first / last minibatch loss."""
+    n = feats.shape[0]
+    if n == 0:
+        raise ValueError("no training samples")
+    perm = torch.from_numpy(np.random.default_rng(seed).permutation(n)).to(feats.device)
+    x = feats.index_select(0, perm).contiguous()
+    y = labels.index_select(0, perm).contiguous()
+    st = MlpState(torch.from_numpy(initial_theta(seed)).to(feats.device), stream=stream)
+    loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+    b = min(batch, n)
+    first = last = None
+    for step in range(1, steps + 1):
+        lo = ((step - 1) * b) % n
+        hi = min(lo + b, n)
+        st.train_step(x[lo:hi], y[lo:hi], w0, lr, step, loss=loss, stream=stream)
+        if step == 1:
+            first = float(loss.item())
+    last = float(loss.item())
+    return st, {"steps": steps, "batch": b, "lr": lr, "w0": w0, "loss_first": first, "loss_last": last}
+
+
+def save_theta(state: MlpState, path: str) -> None:
+    """Parameters as 8960 little-endian float32 values."""
+    state.theta().cpu().numpy().astype("<f4").tofile(path)
+
+
+def load_theta(path: str, device: str = "cuda") -> MlpState:
+    th = np.fromfile(path, dtype="<f4")
+    if th.size != _lib.MLP_PARAMS:
+        raise ValueError(f"{path}: expected {_lib.MLP_PARAMS} float32 values, found {th.size}")
+    return MlpState(torch.from_numpy(th.astype(np.float32)).to(device))
