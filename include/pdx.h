@@ -214,6 +214,15 @@ typedef struct {
     float *trace_features; /* [nq][5][72] network inputs                     */
     int64_t *trace_ids;    /* [nq][5][k] k-best ids after the checkpoint's
                               buckets (checkpoints at or beyond nprobe: -1)  */
+    /* Scan schedule; neither changes the exact (eps0 = INF) result.        */
+    int32_t queries_per_wave; /* queries of one bucket scanned together by
+                                 one wave, each loaded value reused across
+                                 them: 1, 2, 4, 8 or 16; 0 = 8              */
+    int32_t bucket_order;     /* 0: larger buckets first (their work items
+                                 start first); 1: by bucket id              */
+    int32_t engine;           /* 0 = 1: vector ALU (queries_per_wave);
+                                 2: matrix cores, 16 queries per wave, the
+                                 dot products of each chunk as MFMA tiles   */
 } pdx_ivf_search_params;
 
 PDX_API size_t pdx_search_ivf_workspace(const pdx_index *index, int64_t nq, int32_t k, int32_t nprobe,

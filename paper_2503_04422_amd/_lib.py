@@ -59,7 +59,8 @@ class pdx_ivf_search_params(ctypes.Structure):
     _fields_ = [("eps0", ctypes.c_float), ("delta_d", c_int32), ("dtype", c_int32),
                 ("rerank", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
                 ("mlp", c_void_p), ("mlp_threshold", ctypes.c_float), ("trace_features", c_void_p),
-                ("trace_ids", c_void_p)]
+                ("trace_ids", c_void_p), ("queries_per_wave", c_int32), ("bucket_order", c_int32),
+                ("engine", c_int32)]
 
 
 # name -> (restype, argtypes)

@@ -86,26 +86,65 @@ __global__ void item_count_kernel(const int32_t *__restrict__ probe, int64_t nq,
     else atomicAdd(cnt1 + (int64_t)stage_of(st, r) * nlist + probe[i], 1);
 }
 
-__global__ __launch_bounds__(1024) void item_prefix_kernel(int32_t *__restrict__ cnt, int32_t nlist) {
-    // (nlist here is the length of the count array)
-    __shared__ int32_t s[1024];
+// Cursor where each bucket's items start, per segment (block 0: START
+// items; block 1 + s: stage s).  A bucket's item count is rounded up to a
+// multiple of qb so that every batch of qb consecutive items belongs to one
+// bucket (the rounding slots stay padding, query id -1).  Buckets are laid
+// out by id, or larger first so their long batches start early and the
+// launch drains evenly; keys (size descending, id) are sorted in LDS.
+struct SegBase {
+    int32_t b[8];  // first item of stage s in items1
+};
+
+__global__ __launch_bounds__(1024) void batch_prefix_kernel(int32_t *__restrict__ cnt0, int32_t *__restrict__ cnt1,
+                                                            int32_t nlist, int32_t pow2,
+                                                            const int32_t *__restrict__ list_size, int32_t qb,
+                                                            int32_t by_size, SegBase sb) {
+    extern __shared__ uint64_t order[];  // pow2 keys
+    __shared__ int32_t part[1024];
     __shared__ int32_t carry;
+    int32_t *cnt = blockIdx.x == 0 ? cnt0 : cnt1 + (int64_t)(blockIdx.x - 1) * nlist;
+    const int32_t base = blockIdx.x == 0 ? 0 : sb.b[blockIdx.x - 1];
+    for (int32_t l = threadIdx.x; l < pow2; l += blockDim.x) {
+        uint64_t key = kEmptyKey;
+        if (l < nlist)
+            key = by_size ? (static_cast<uint64_t>(0x7fffffffu - static_cast<uint32_t>(list_size[l])) << 32) | (uint32_t)l
+                          : (uint64_t)l;
+        order[l] = key;
+    }
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int32_t base = 0; base < nlist; base += 1024) {
-        int32_t l = base + threadIdx.x;
-        int32_t c = l < nlist ? cnt[l] : 0;
-        s[threadIdx.x] = c;
+    if (by_size)
+        for (int k2 = 2; k2 <= pow2; k2 <<= 1)
+            for (int j2 = k2 >> 1; j2 > 0; j2 >>= 1) {
+                for (int i = threadIdx.x; i < pow2; i += blockDim.x) {
+                    int ixj = i ^ j2;
+                    if (ixj > i) {
+                        uint64_t a = order[i], b = order[ixj];
+                        bool up = (i & k2) == 0;
+                        if ((a > b) == up) {
+                            order[i] = b;
+                            order[ixj] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+    for (int32_t i0 = 0; i0 < nlist; i0 += 1024) {
+        const int32_t i = i0 + threadIdx.x;
+        const int32_t l = i < nlist ? (int32_t)(order[i] & 0xffffffffu) : -1;
+        const int32_t c = l >= 0 ? (cnt[l] + qb - 1) / qb * qb : 0;
+        part[threadIdx.x] = c;
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
-            int32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+            int32_t t = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
             __syncthreads();
-            s[threadIdx.x] += t;
+            part[threadIdx.x] += t;
             __syncthreads();
         }
-        if (l < nlist) cnt[l] = carry + s[threadIdx.x] - c;  // exclusive -> becomes a cursor
+        if (l >= 0) cnt[l] = base + carry + part[threadIdx.x] - c;
         __syncthreads();
-        if (threadIdx.x == 1023) carry += s[1023];
+        if (threadIdx.x == 1023) carry += part[1023];
         __syncthreads();
     }
 }
@@ -223,6 +262,146 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     }
 }
 
+// Scan of one bucket for a batch of QB queries per wave (the batch's
+// items are QB consecutive slots of one bucket; padding slots have query
+// id -1).  Lane = vector of the current vectorgroup; each value loaded
+// (and decoded) once serves all queries of the batch.  Per query and lane:
+// partial distance, alive bit, and the query's own k-best list; a query
+// with no alive lane in the group skips its arithmetic (wave-uniform
+// branch), and the group ends early once no (query, lane) pair is alive.
+// Summation per (query, vector): each chunk summed sequentially, then
+// added to the partial, as in the one-query kernel.
+template <bool PRUNE, int STORE, int QB>
+__global__ __launch_bounds__(256) void ivf_bscan_kernel(
+    const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
+    const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nbatch,
+    const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
+    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, const int32_t *__restrict__ active) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= nbatch) return;
+    const int2 mine = lane < QB ? items[b * QB + lane] : make_int2(-1, 0);
+    int32_t qid[QB], rk[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        qid[q] = __builtin_amdgcn_readlane(mine.x, q);
+        rk[q] = __builtin_amdgcn_readlane(mine.y, q);
+    }
+    if (qid[0] < 0) return;  // a batch starts with a real item unless it is unused capacity
+    const int32_t l = probe[(int64_t)qid[0] * nprobe + rk[0]];
+    uint32_t use = 0;
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        if (qid[q] < 0) continue;
+        if (bad[qid[q]] || (active && !active[qid[q]])) {  // non-finite query, or it stopped probing
+            if (lane < k) slots[((size_t)qid[q] * nprobe + rk[q]) * k + lane] = kEmptyKey;
+        } else {
+            use |= 1u << q;
+        }
+    }
+    if (!use) return;
+    uint64_t e[QB], kth[QB];
+    float part[QB], s[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) e[q] = kth[q] = kEmptyKey;
+    unsigned long long live_vals = 0, lane_vals = 0;
+    for (int32_t g = goff[l]; g < goff[l + 1]; ++g) {
+        float teff[QB];
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            teff[q] = INFINITY;
+            if (PRUNE && ((use >> q) & 1)) {
+                uint32_t tg = __hip_atomic_load(tau + qid[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                float tl = kth[q] == kEmptyKey ? INFINITY : key_dist(kth[q]);
+                teff[q] = fminf(__uint_as_float(tg), tl);
+            }
+            part[q] = 0.0f;
+        }
+        const int32_t vid = slot_id[(int64_t)g * kGroup + lane];
+        uint32_t am = vid >= 0 ? use : 0u;  // bit q: lane alive for query q
+        uint32_t qa = use;                  // wave-uniform: queries with an alive lane
+        const int64_t gbase = (int64_t)g * d * kGroup + lane;
+        for (int32_t c0 = 0; c0 < d; c0 += chunk) {
+            if (PRUNE) {
+                qa = 0;
+#pragma unroll
+                for (int q = 0; q < QB; ++q) qa |= (__ballot((am >> q) & 1u) != 0ull ? 1u : 0u) << q;
+                if (!qa) break;
+            }
+            const int32_t c1 = min(c0 + chunk, d);
+            if (counters) {
+#pragma unroll
+                for (int q = 0; q < QB; ++q)
+                    if ((qa >> q) & 1u) {
+                        live_vals += (unsigned long long)__popcll(__ballot((am >> q) & 1u)) * (c1 - c0);
+                        lane_vals += 64ull * (c1 - c0);
+                    }
+            }
+#pragma unroll
+            for (int q = 0; q < QB; ++q) s[q] = 0.0f;
+            int32_t j = c0;
+            for (; j + 8 <= c1; j += 8) {
+                float x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = load_val<STORE>(pdxd, scale, gbase + (int64_t)(j + u) * kGroup, j + u);
+#pragma unroll
+                for (int q = 0; q < QB; ++q) {
+                    if ((qa >> q) & 1u) {
+                        const float *qp = qrot + (int64_t)qid[q] * d + j;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            float t = qp[u] - x[u];
+                            s[q] = fmaf(t, t, s[q]);
+                        }
+                    }
+                }
+            }
+            for (; j < c1; ++j) {
+                const float x = load_val<STORE>(pdxd, scale, gbase + (int64_t)j * kGroup, j);
+#pragma unroll
+                for (int q = 0; q < QB; ++q) {
+                    if ((qa >> q) & 1u) {
+                        float t = qrot[(int64_t)qid[q] * d + j] - x;
+                        s[q] = fmaf(t, t, s[q]);
+                    }
+                }
+            }
+            float fac = 1.0f;
+            if (PRUNE && c1 < d) {
+                const float dc = (float)c1;
+                const float f = 1.0f + eps0 / sqrtf(dc);
+                fac = (dc / (float)d) * f * f;
+            }
+#pragma unroll
+            for (int q = 0; q < QB; ++q) {
+                if ((qa >> q) & 1u) {
+                    part[q] += s[q];
+                    // ADSampling test after c1 of d dimensions (exact at c1 = d)
+                    if (PRUNE && part[q] > teff[q] * fac) am &= ~(1u << q);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            if (!((use >> q) & 1u)) continue;
+            const bool cand = (am >> q) & 1u;
+            if (__ballot(cand)) topk_offer(e[q], kth[q], make_key(part[q], (uint32_t)vid), cand, k, lane);
+            if (PRUNE && kth[q] != kEmptyKey) {
+                const float kt = key_dist(kth[q]);
+                if (kt < teff[q] && lane == 0) atomicMin(tau + qid[q], __float_as_uint(kt));
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+        if (((use >> q) & 1u) && lane < k) slots[((size_t)qid[q] * nprobe + rk[q]) * k + lane] = e[q];
+    if (counters && lane == 0) {
+        atomicAdd(counters, live_vals);
+        atomicAdd(counters + 1, lane_vals);
+    }
+}
+
 // Checkpoint after the first `cp` probed buckets: the k-best list over
 // those buckets (its last distance tightens the threshold for the later
 // buckets), the network's inputs (documented with pdx_mlp_* in
@@ -319,31 +498,42 @@ __global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restric
 // get their exact f32 distance from the row-major f32 copy (same chunked
 // accumulation as the f32 scan: sequential fused multiply-adds per chunk,
 // chunk sums added in order); the k best of those are the result.
-__global__ __launch_bounds__(64) void rerank_kernel(const uint64_t *__restrict__ keys, int32_t r, int32_t k,
-                                                    const float *__restrict__ xrow, const float *__restrict__ qrot,
-                                                    int32_t d, int32_t chunk, const int32_t *__restrict__ bad,
-                                                    int64_t *__restrict__ out_ids, float *__restrict__ out_dist) {
-    const int64_t qi = blockIdx.x;
-    const int lane = threadIdx.x;
-    const uint64_t key = lane < r ? keys[qi * r + lane] : kEmptyKey;
-    const bool has = key != kEmptyKey;
-    const uint32_t id = static_cast<uint32_t>(key & 0xffffffffu);
-    float dist = 0.0f;
-    if (has) {
+// Exact f32 distances of a query's r candidates (keys [nq][r], ordered by
+// the scanned distance) from the row-major rotated rows, then the k best by
+// (exact distance, id).  One wave per query: the 64 lanes split each
+// candidate's dimensions (coalesced row reads), a butterfly sums them.
+__global__ __launch_bounds__(256) void rerank_kernel(const uint64_t *__restrict__ keys, int32_t r, int32_t k,
+                                                     const float *__restrict__ xrow, const float *__restrict__ qrot,
+                                                     int32_t d, const int32_t *__restrict__ bad, int64_t nq,
+                                                     int64_t *__restrict__ out_ids, float *__restrict__ out_dist) {
+    const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (qi >= nq) return;
+    const float *qp = qrot + qi * d;
+    uint64_t mine = kEmptyKey;
+    for (int32_t i = 0; i < r; ++i) {
+        const uint64_t key = keys[qi * r + i];
+        if (key == kEmptyKey) break;  // the list is sorted: the rest is empty too
+        const uint32_t id = static_cast<uint32_t>(key & 0xffffffffu);
         const float *x = xrow + (int64_t)id * d;
-        const float *qp = qrot + qi * d;
-        for (int32_t c0 = 0; c0 < d; c0 += chunk) {
-            const int32_t c1 = min(c0 + chunk, d);
-            float s = 0.0f;
-            for (int32_t j = c0; j < c1; ++j) {
-                float t = qp[j] - x[j];
-                s = fmaf(t, t, s);
-            }
-            dist += s;
+        float s0 = 0.0f, s1 = 0.0f;
+        int32_t j = lane;
+        for (; j + 64 < d; j += 128) {
+            const float t0 = qp[j] - x[j], t1 = qp[j + 64] - x[j + 64];
+            s0 = fmaf(t0, t0, s0);
+            s1 = fmaf(t1, t1, s1);
         }
+        if (j < d) {
+            const float t0 = qp[j] - x[j];
+            s0 = fmaf(t0, t0, s0);
+        }
+        float s = s0 + s1;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == i) mine = make_key(s, id);
     }
     uint64_t e = kEmptyKey, kth = kEmptyKey;
-    topk_offer(e, kth, make_key(dist, id), has, k, lane);
+    topk_offer(e, kth, mine, mine != kEmptyKey, k, lane);
     if (lane < k) {
         int64_t oid = -1;
         float od = INFINITY;
@@ -380,6 +570,9 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         if (r == 0) r = min(4 * k, PDX_MAX_K);
         pl.rerank = r < 0 ? 0 : max(r, k);
     }
+    pl.matrix = (p && p->engine == 2) ? 1 : 0;
+    // matrix-core scans report exact f32 distances of their k best
+    if (pl.matrix && pl.dtype == PDX_DTYPE_F32) pl.rerank = k;
     pl.kk = pl.rerank > 0 ? pl.rerank : k;
     pl.w16 = (p && p->mlp) ? mlp_layout(const_cast<void *>(p->mlp)).w16 : nullptr;
     pl.trace_f = p ? p->trace_features : nullptr;
@@ -398,6 +591,15 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
             if (cps[c] < nprobe) pl.stage_b[pl.nstages++] = cps[c];
     }
     pl.stage_b[pl.nstages] = nprobe;
+    pl.qb = pl.matrix ? 16 : (p && p->queries_per_wave > 0) ? p->queries_per_wave : kDefaultQueriesPerWave;
+    pl.by_size = !(p && p->bucket_order == 1);
+    pl.cap0 = ivf_item_capacity(nq, 1, pl.qb, ix->nlist);
+    pl.cap1 = 0;
+    for (int32_t sg = 0; sg < pl.nstages; ++sg) {
+        pl.sbase[sg] = pl.cap1;
+        pl.cap[sg] = ivf_item_capacity(nq, pl.stage_b[sg + 1] - pl.stage_b[sg], pl.qb, ix->nlist);
+        pl.cap1 += pl.cap[sg];
+    }
     int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
     pl.chunk = dd;
     size_t q = (size_t)(nq > 0 ? nq : 0);
@@ -410,8 +612,8 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.cnt0 = c.take<int32_t>(ix->nlist);
     pl.cnt1 = c.take<int32_t>((size_t)ix->nlist * 8);
     pl.active = c.take<int32_t>(q);
-    pl.items0 = c.take<int2>(q);
-    pl.items1 = c.take<int2>(q * (nprobe - 1 > 0 ? nprobe - 1 : 1));
+    pl.items0 = c.take<int2>((size_t)pl.cap0);
+    pl.items1 = c.take<int2>((size_t)(pl.cap1 > 0 ? pl.cap1 : 1));
     pl.slots = c.take<uint64_t>(q * nprobe * pl.kk);
     pl.rkeys = pl.rerank > 0 ? c.take<uint64_t>(q * pl.kk) : nullptr;
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
@@ -450,54 +652,92 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     if ((e = launch_fill_i32(pl.cnt0, ix->nlist, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(pl.cnt1, ncnt1, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(pl.active, nq, 1, s)) != hipSuccess) return e;
+    if (pl.qb > 1) {  // padding slots: query id -1
+        const unsigned long long pad = 0x00000000ffffffffull;
+        if ((e = launch_fill_u64(reinterpret_cast<unsigned long long *>(pl.items0), pl.cap0, pad, s)) != hipSuccess)
+            return e;
+        if (pl.cap1 > 0 &&
+            (e = launch_fill_u64(reinterpret_cast<unsigned long long *>(pl.items1), pl.cap1, pad, s)) != hipSuccess)
+            return e;
+    }
     int64_t tot = nq * pl.nprobe;
     unsigned gb = (unsigned)((tot + 255) / 256);
     item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, ix->nlist, st, pl.cnt0, pl.cnt1);
-    item_prefix_kernel<<<1, 1024, 0, s>>>(pl.cnt0, ix->nlist);
-    item_prefix_kernel<<<1, 1024, 0, s>>>(pl.cnt1, ncnt1);
+    {
+        SegBase sb{};
+        for (int32_t sg = 0; sg < pl.nstages; ++sg) sb.b[sg] = (int32_t)pl.sbase[sg];
+        batch_prefix_kernel<<<1 + pl.nstages, 1024, pow2 * sizeof(uint64_t), s>>>(
+            pl.cnt0, pl.cnt1, ix->nlist, pow2, ix->list_size, pl.qb, pl.by_size, sb);
+    }
     item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, ix->nlist, st, pl.cnt0, pl.cnt1, pl.items0,
                                           pl.items1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. START
-    int64_t n0 = nq, n1 = nq * (pl.nprobe - 1);
-    auto grid_of = [](int64_t items, uint32_t *nwg) {
-        *nwg = (uint32_t)((items + 3) / 4);
-        return 8u * ((*nwg + 7u) / 8u);
-    };
-    uint32_t nwg0, nwg1;
-    unsigned grid0 = grid_of(n0, &nwg0), grid1 = grid_of(n1, &nwg1);
     const void *data = pl.dtype == PDX_DTYPE_BF16 ? static_cast<const void *>(ix->pdx_bf16)
                        : pl.dtype == PDX_DTYPE_FP8 ? static_cast<const void *>(ix->pdx_fp8)
                                                    : static_cast<const void *>(ix->pdx);
-    auto scan = [&](bool prune, unsigned grid, const int2 *items, int64_t nitems, unsigned long long *cnt,
-                    uint32_t nwg, const int32_t *act) {
+    // `cap` item slots starting at `items`: one item per wave (qb = 1), or
+    // cap / qb batches of qb items
+    auto scan = [&](bool prune, const int2 *items, int64_t cap, unsigned long long *cnt, const int32_t *act) {
+        if (cap <= 0) return hipSuccess;
+        if (pl.qb == 1) {
+            const uint32_t nwg = (uint32_t)((cap + 3) / 4);
+            const unsigned grid = 8u * ((nwg + 7u) / 8u);
 #define PDX_SCAN(P, S)                                                                                          \
-    ivf_scan_kernel<P, S><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, nitems, \
+    ivf_scan_kernel<P, S><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, cap,  \
                                                pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots, pl.kk,     \
                                                pl.chunk, pl.eps0, cnt, nwg, act)
-        if (prune) {
-            if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16);
-            else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8);
-            else PDX_SCAN(true, PDX_DTYPE_F32);
-        } else {
-            if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(false, PDX_DTYPE_BF16);
-            else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(false, PDX_DTYPE_FP8);
-            else PDX_SCAN(false, PDX_DTYPE_F32);
-        }
+            if (prune) {
+                if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16);
+                else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8);
+                else PDX_SCAN(true, PDX_DTYPE_F32);
+            } else {
+                if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(false, PDX_DTYPE_BF16);
+                else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(false, PDX_DTYPE_FP8);
+                else PDX_SCAN(false, PDX_DTYPE_F32);
+            }
 #undef PDX_SCAN
+            return hipGetLastError();
+        }
+        const int64_t nb = cap / pl.qb;
+        if (pl.matrix)
+            return launch_ivf_mscan(prune, pl.dtype, data, ix->fp8_scale, d, ix->slot_id, ix->list_goff,
+                                    ix->centroids, items, nb, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots,
+                                    pl.kk, pl.chunk, pl.eps0, cnt, act, s);
+        const unsigned grid = (unsigned)((nb + 3) / 4);
+#define PDX_BSCAN(P, S, Q)                                                                                        \
+    ivf_bscan_kernel<P, S, Q><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, nb, \
+                                                   pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots, pl.kk,   \
+                                                   pl.chunk, pl.eps0, cnt, act)
+#define PDX_BSCAN_Q(P, S)                      \
+    switch (pl.qb) {                           \
+        case 2: PDX_BSCAN(P, S, 2); break;     \
+        case 4: PDX_BSCAN(P, S, 4); break;     \
+        case 8: PDX_BSCAN(P, S, 8); break;     \
+        default: PDX_BSCAN(P, S, 16); break;   \
+    }
+        if (prune) {
+            if (pl.dtype == PDX_DTYPE_BF16) PDX_BSCAN_Q(true, PDX_DTYPE_BF16)
+            else if (pl.dtype == PDX_DTYPE_FP8) PDX_BSCAN_Q(true, PDX_DTYPE_FP8)
+            else PDX_BSCAN_Q(true, PDX_DTYPE_F32)
+        } else {
+            if (pl.dtype == PDX_DTYPE_BF16) PDX_BSCAN_Q(false, PDX_DTYPE_BF16)
+            else if (pl.dtype == PDX_DTYPE_FP8) PDX_BSCAN_Q(false, PDX_DTYPE_FP8)
+            else PDX_BSCAN_Q(false, PDX_DTYPE_F32)
+        }
+#undef PDX_BSCAN_Q
+#undef PDX_BSCAN
         return hipGetLastError();
     };
-    if ((e = scan(false, grid0, pl.items0, n0, pl.counters, nwg0, nullptr)) != hipSuccess) return e;
+    if ((e = scan(false, pl.items0, pl.cap0, pl.counters, nullptr)) != hipSuccess) return e;
     ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, 1, pl.kk, pl.bad, pl.tau, nullptr, nullptr,
                                                 nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark(1)) != hipSuccess) return e;
     // 5. pruned scan of the other probed buckets, stage by stage; between
     //    stages the checkpoint (trace and/or learned stop decision)
-    (void)grid1;
-    (void)nwg1;
     const bool staged = pl.w16 || pl.trace_f || pl.trace_ids;
-    for (int32_t sg = 0; sg < pl.nstages && n1 > 0; ++sg) {
+    for (int32_t sg = 0; sg < pl.nstages && pl.nprobe > 1; ++sg) {
         if (sg > 0 && staged) {
             const int32_t cp = pl.stage_b[sg];
             int32_t c = 0;
@@ -507,11 +747,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                           pl.zthr, pl.active, pl.trace_f, pl.trace_ids);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        const int64_t i0 = nq * (int64_t)(pl.stage_b[sg] - 1), i1 = nq * (int64_t)(pl.stage_b[sg + 1] - 1);
-        if (i1 <= i0) continue;
-        uint32_t nwg;
-        unsigned grid = grid_of(i1 - i0, &nwg);
-        if ((e = scan(true, grid, pl.items1 + i0, i1 - i0, pl.counters ? pl.counters + 2 : nullptr, nwg,
+        if ((e = scan(true, pl.items1 + pl.sbase[sg], pl.cap[sg], pl.counters ? pl.counters + 2 : nullptr,
                       pl.w16 ? pl.active : nullptr)) != hipSuccess)
             return e;
     }
@@ -530,8 +766,8 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, pl.kk, pl.bad, nullptr,
                                                     nullptr, nullptr, pl.rkeys);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        rerank_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.rkeys, pl.kk, pl.k, ix->xrow, pl.qrot, d, pl.chunk, pl.bad,
-                                                 out_ids, out_dist);
+        rerank_kernel<<<(unsigned)((nq + 3) / 4), 256, 0, s>>>(pl.rkeys, pl.kk, pl.k, ix->xrow, pl.qrot, d, pl.bad,
+                                                               nq, out_ids, out_dist);
     } else {
         ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, pl.k, pl.bad, nullptr,
                                                     out_ids, out_dist, nullptr);

@@ -125,11 +125,35 @@ struct IvfPlan {
     int64_t *trace_ids;
     int32_t nstages;
     int32_t stage_b[8];
+    int32_t matrix;    // bucket scan on the matrix cores (16 queries per wave)
+    int32_t qb;        // queries per wave in the bucket scan
+    int32_t by_size;   // lay buckets out larger first
+    int64_t cap0;      // START item slots (counts rounded up to qb per bucket)
+    int64_t cap[8];    // item slots of stage s, at items1 + sbase[s]
+    int64_t sbase[8];
+    int64_t cap1;
     uint64_t *slots;   // [nq][nprobe][kk]
     uint64_t *rkeys;   // [nq][kk] candidates to rerank
     hipEvent_t *events;
     unsigned long long *counters;
 };
+
+constexpr int32_t kDefaultQueriesPerWave = 4;
+
+// Bucket scan of 16-query batches on the matrix cores (k_ivf_mscan.hip).
+hipError_t launch_ivf_mscan(bool prune, int32_t store, const void *data, const float *scale, int32_t d,
+                            const int32_t *slot_id, const int32_t *goff, const float *cen, const int2 *items,
+                            int64_t nbatch, const int32_t *probe, int32_t nprobe, const float *qrot, uint32_t *tau,
+                            const int32_t *bad, uint64_t *slots, int32_t k, int32_t chunk, float eps0,
+                            unsigned long long *counters, const int32_t *active, hipStream_t s);
+
+// Item slots for nq queries x `ranks` probe ranks when every bucket's count
+// is rounded up to a multiple of qb (at most qb - 1 padding slots per bucket).
+inline int64_t ivf_item_capacity(int64_t nq, int32_t ranks, int32_t qb, int32_t nlist) {
+    if (ranks <= 0) return 0;
+    const int64_t c = nq * ranks + (int64_t)(qb - 1) * nlist;
+    return (c + qb - 1) / qb * qb;
+}
 
 size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, const pdx_ivf_search_params *p,
                 void *ws, IvfPlan *plan);

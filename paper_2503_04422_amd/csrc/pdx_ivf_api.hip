@@ -292,7 +292,21 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
         set_error("pdx_search_ivf: pointers must be 16-byte aligned");
         return PDX_EINVAL;
     }
-    if (nq * (int64_t)nprobe >= (int64_t(1) << 31)) {
+    if (params && params->queries_per_wave != 0 && params->queries_per_wave != 1 && params->queries_per_wave != 2 &&
+        params->queries_per_wave != 4 && params->queries_per_wave != 8 && params->queries_per_wave != 16) {
+        set_error("pdx_search_ivf: queries_per_wave must be 0, 1, 2, 4, 8 or 16 (got %d)", params->queries_per_wave);
+        return PDX_EINVAL;
+    }
+    if (params && (params->engine < 0 || params->engine > 2)) {
+        set_error("pdx_search_ivf: engine must be 0, 1 or 2");
+        return PDX_EINVAL;
+    }
+    if (params && (params->bucket_order < 0 || params->bucket_order > 1)) {
+        set_error("pdx_search_ivf: bucket_order must be 0 or 1");
+        return PDX_EINVAL;
+    }
+    // item slots, padding included (at most 15 per bucket and segment of 6)
+    if (nq * (int64_t)nprobe + (int64_t)15 * 6 * index->nlist + 16 >= (int64_t(1) << 31)) {
         set_error("pdx_search_ivf: nq * nprobe too large");
         return PDX_EINVAL;
     }

@@ -91,19 +91,30 @@ def test_kmeans_build_invariants(pdx):
     assert np.einsum("ij,ij->i", diff, diff).sum() <= d_init.sum()
 
 
-@pytest.mark.parametrize("n,d,nlist,k", [(20_000, 128, 50, 10), (9_000, 37, 16, 5), (6_000, 1536, 24, 10)])
-def test_eps_inf_equals_ivf_flat(pdx, n, d, nlist, k):
+@pytest.mark.parametrize("n,d,nlist,k,qpw,order,engine", [
+    (20_000, 128, 50, 10, 0, 0, 0), (20_000, 128, 50, 10, 1, 0, 0), (20_000, 128, 50, 10, 2, 1, 0),
+    (20_000, 128, 50, 10, 8, 0, 0), (20_000, 128, 50, 10, 16, 1, 0), (20_000, 128, 50, 10, 0, 0, 2),
+    (9_000, 37, 16, 5, 0, 0, 0), (9_000, 37, 16, 5, 1, 1, 0), (9_000, 37, 16, 5, 16, 0, 0),
+    (9_000, 37, 16, 5, 0, 1, 2),
+    (6_000, 1536, 24, 10, 0, 0, 0), (6_000, 1536, 24, 10, 1, 0, 0), (6_000, 1536, 24, 10, 16, 0, 0),
+    (6_000, 1536, 24, 10, 0, 0, 2)])
+def test_eps_inf_equals_ivf_flat(pdx, n, d, nlist, k, qpw, order, engine):
+    """Also for every scan schedule: queries per wave 1 (one-query kernel),
+    2, 4 (default), 8, 16, buckets by size or by id, and the matrix-core
+    scan (engine 2)."""
     mix = synth.anisotropic_unit_mixture(d, 32, n % 97)
     x = mix.data(n)
     q = mix.queries(40)
-    print(f"ivf-flat parity n={n} d={d} nlist={nlist}", flush=True)
+    print(f"ivf-flat parity n={n} d={d} nlist={nlist} queries_per_wave={qpw} bucket_order={order} engine={engine}",
+          flush=True)
     g, r32, xr, c, lab = _oracle_index(x, nlist, n)
     lists = kmeans.lists_from_labels(lab, nlist)
     ix = pdx.pdx_ivf_build(_dev(x), nlist, None, None, rotation=_dev(r32), centroids=_dev(c.astype(np.float32)),
                            assign=_dev(lab.astype(np.int32)))
     qr = rotation.rotate_rows(q, r32.astype(np.float64))
     for nprobe in (1, 3, nlist):
-        gi, gd = pdx.pdx_search_ivf(ix, _dev(q), k, nprobe, eps0=float("inf"))
+        gi, gd = pdx.pdx_search_ivf(ix, _dev(q), k, nprobe, eps0=float("inf"), queries_per_wave=qpw,
+                                    bucket_order=order, engine=engine)
         gi, gd = _np(gi), _np(gd)
         keep = [i for i in range(q.shape[0]) if not _probe_tied(c.astype(np.float32), qr[i], nprobe)]
         want = [px.ivf_flat(xr, lists, c.astype(np.float32), qr[i], k, nprobe) for i in keep]
@@ -132,7 +143,14 @@ def test_ads_recall_band_and_monotone(pdx):
     for nprobe in (2, 4, 8, 16):
         fi, _ = pdx.pdx_search_ivf(ix, _dev(q), 10, nprobe, eps0=float("inf"))
         ai, ad = pdx.pdx_search_ivf(ix, _dev(q), 10, nprobe, eps0=2.1)
-        fi, ai, ad = _np(fi), _np(ai), _np(ad)
+        a1, _ = pdx.pdx_search_ivf(ix, _dev(q), 10, nprobe, eps0=2.1, queries_per_wave=1)
+        am, amd = pdx.pdx_search_ivf(ix, _dev(q), 10, nprobe, eps0=2.1, engine=2)
+        fi, ai, ad, a1, am, amd = _np(fi), _np(ai), _np(ad), _np(a1), _np(am), _np(amd)
+        assert exact.recall_at_k(fi, a1) >= min(0.99, exact.recall_at_k(fi, ai) - 0.02)
+        assert exact.recall_at_k(fi, am) >= min(0.99, exact.recall_at_k(fi, ai) - 0.02)
+        for i in range(0, q.shape[0], 17):
+            ok = am[i] >= 0
+            np.testing.assert_allclose(amd[i][ok], exact.sqdist(xr[am[i][ok]], qr[i]), rtol=1e-5)
         oi = np.stack([px.ads_ivf_search(xr, lists, c32, qr[i], 10, nprobe, eps0=2.1)[0] for i in range(q.shape[0])])
         r_gpu = exact.recall_at_k(fi, ai)
         r_orc = exact.recall_at_k(fi, oi)
@@ -155,15 +173,27 @@ def test_ivf_edge_cases(pdx):
     g, r32, xr, c, lab = _oracle_index(x, nlist, 5)
     ix = pdx.pdx_ivf_build(_dev(x), nlist, None, None, rotation=_dev(r32), centroids=_dev(c.astype(np.float32)),
                            assign=_dev(lab.astype(np.int32)))
-    # k above the probed rows: padded
+    # k above the probed rows: padded (same result for every schedule)
     gi, gd = pdx.pdx_search_ivf(ix, _dev(q), 64, 1, eps0=float("inf"))
     gi, gd = _np(gi), _np(gd)
+    for qpw in (1, 2, 16):
+        g2, d2 = pdx.pdx_search_ivf(ix, _dev(q), 64, 1, eps0=float("inf"), queries_per_wave=qpw)
+        assert np.array_equal(_np(g2), gi) and np.array_equal(_np(d2), gd)
     sizes = np.bincount(lab, minlength=nlist)
     qr = rotation.rotate_rows(q, r32.astype(np.float64))
     for i in range(q.shape[0]):
         p0 = px.ivf_probe_order(c.astype(np.float32), qr[i], 1)[0]
         m = min(64, sizes[p0])
         assert (gi[i, :m] >= 0).all() and (gi[i, m:] == -1).all()
+    # matrix-core scan: the same padding, the oracle's IVF-flat under the tie rule
+    g2, d2 = pdx.pdx_search_ivf(ix, _dev(q), 64, 1, eps0=float("inf"), engine=2)
+    g2, d2 = _np(g2), _np(d2)
+    assert np.array_equal(g2 < 0, gi < 0)
+    lists = kmeans.lists_from_labels(lab, nlist)
+    for i in range(q.shape[0]):
+        m = int((gi[i] >= 0).sum())
+        wi, wd = px.ivf_flat(xr, lists, c.astype(np.float32), qr[i], m, 1)
+        check_knn(xr, qr[i:i + 1], g2[i:i + 1, :m], d2[i:i + 1, :m], wi[None], wd[None])
     # non-finite query, nq = 0, nprobe out of range
     q2 = q.copy()
     q2[1, 3] = np.inf
@@ -172,6 +202,12 @@ def test_ivf_edge_cases(pdx):
     assert (gi[1] == -1).all() and np.isnan(gd[1]).all()
     ids, _ = pdx.pdx_search_ivf(ix, torch.empty((0, 24), device="cuda"), 5, 2)
     assert ids.shape == (0, 5)
+    with pytest.raises(PdxError):
+        pdx.pdx_search_ivf(ix, _dev(q), 5, 2, queries_per_wave=3)
+    with pytest.raises(PdxError):
+        pdx.pdx_search_ivf(ix, _dev(q), 5, 2, bucket_order=2)
+    with pytest.raises(PdxError):
+        pdx.pdx_search_ivf(ix, _dev(q), 5, 2, engine=3)
     with pytest.raises(PdxError):
         pdx.pdx_search_ivf(ix, _dev(q), 5, nlist + 1)
     with pytest.raises(PdxError):

@@ -63,12 +63,13 @@ def _probed_rows(st, qv, nprobe):
     return np.concatenate([st["lists"][p] for p in probe])
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
-def test_lowp_scan_exact_over_decoded(pdx, setup, dtype):
+@pytest.mark.parametrize("dtype,engine", [("bf16", 0), ("fp8", 0), ("bf16", 2), ("fp8", 2)])
+def test_lowp_scan_exact_over_decoded(pdx, setup, dtype, engine):
     st = setup
-    print(f"lowp scan parity {dtype}", flush=True)
+    print(f"lowp scan parity {dtype} engine {engine}", flush=True)
     for nprobe in (1, 5):
-        gi, gd = pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, nprobe, eps0=float("inf"), dtype=dtype, rerank=-1)
+        gi, gd = pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, nprobe, eps0=float("inf"), dtype=dtype, rerank=-1,
+                                    engine=engine)
         gi, gd = _np(gi), _np(gd)
         xd = st["dec"][dtype]
         want = [exact.topk_by_dist_then_id(exact.sqdist(xd[r], st["q"][i]), r, 10)
