@@ -140,17 +140,23 @@ def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, tr
     sweep = []
     best = None
     for p in nprobes:
-        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, p)), dtype=torch.uint8, device="cuda")
+        t0 = time.perf_counter()
+        sched, _ = pdx.pdx_ivf_tune(ix, q_dev, k, p, eps0=2.1, reps=2)
+        tune_s = time.perf_counter() - t0
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, p, delta_d=sched["delta_d"],
+                                                             queries_per_wave=sched["queries_per_wave"],
+                                                             engine=sched["engine"])),
+                         dtype=torch.uint8, device="cuda")
         out = {}
 
-        def run(evs, p=p, ws=ws, out=out):
-            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, p, eps0=2.1, workspace=ws, phase_events=evs)
+        def run(evs, p=p, ws=ws, out=out, sched=sched):
+            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, p, eps0=2.1, workspace=ws, phase_events=evs, **sched)
 
         elapsed, ph = timed_steps(run, steps, warmup, torch, np)
         ids = out["r"][0].cpu().numpy()
         rec = recall_at_k(truth_ids, ids[: truth_ids.shape[0]]) if truth_ids is not None else None
         row = {"nprobe": p, "qps": round(nq * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
-               "recall@10": None if rec is None else round(rec, 4),
+               "recall@10": None if rec is None else round(rec, 4), "schedule": sched, "tune_s": round(tune_s, 2),
                "phases_ms": {"prep_start": round(ph[0], 3), "pruned_scan": round(ph[1], 3), "merge": round(ph[2], 3)}}
         print(f"# nprobe {p}: {row['qps']} qps recall {row['recall@10']}", file=sys.stderr, flush=True)
         sweep.append(row)
@@ -208,7 +214,7 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
         return i.cpu().numpy(), float(c[0] + c[2]) / qd.shape[0]
 
     plain_np = [2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32]
-    thresholds = [0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.98, 0.99]
+    thresholds = [0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.98, 0.99, 0.995, 0.999]
     val = {"plain": [], "learned": []}
     pick_p = pick_t = None
     for p in plain_np:
@@ -226,7 +232,7 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
     print(f"# validation picks: plain nprobe {pick_p}, learned threshold {pick_t}", file=sys.stderr, flush=True)
 
     def timed(**kw):
-        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, qe.shape[0], k, kw["nprobe"])),
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, qe.shape[0], k, kw["nprobe"], mlp=kw.get("mlp"))),
                          dtype=torch.uint8, device="cuda")
         out = {}
 

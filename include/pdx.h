@@ -206,24 +206,58 @@ typedef struct {
                             by START, [1] its lane slots, [2] values evaluated
                             by the pruned scan (live lanes), [3] its lane slots */
     /* Learned early termination (see pdx_mlp_*; NULL = plain search).      */
-    const void *mlp;       /* network state; a query stops at a checkpoint when
-                              sigmoid(z) > mlp_threshold                      */
+    const void *mlp;       /* network state: after START the query probes the
+                              smallest r in 1..nprobe-1 with sigmoid(z_r) >
+                              mlp_threshold, else all nprobe buckets        */
     float mlp_threshold;
-    /* Checkpoint traces (NULL = off; the search then probes all nprobe
-     * buckets and records, for every query and checkpoint c < 5):          */
-    float *trace_features; /* [nq][5][72] network inputs                     */
-    int64_t *trace_ids;    /* [nq][5][k] k-best ids after the checkpoint's
-                              buckets (checkpoints at or beyond nprobe: -1)  */
+    /* Traces for training (NULL = off; the search then ignores mlp):       */
+    float *trace_features; /* [nq][nprobe][72]: row r - 1 = the network's
+                              inputs for "stop after r buckets", r < nprobe;
+                              the last row zero                             */
+    int32_t *trace_need;   /* [nq]: buckets the result needed, 1 + the
+                              largest probe rank holding one of the returned
+                              ids (0: no result); stopping after r buckets
+                              loses nothing exactly when r >= this          */
     /* Scan schedule; neither changes the exact (eps0 = INF) result.        */
     int32_t queries_per_wave; /* queries of one bucket scanned together by
                                  one wave, each loaded value reused across
                                  them: 1, 2, 4, 8 or 16; 0 = 8              */
     int32_t bucket_order;     /* 0: larger buckets first (their work items
                                  start first); 1: by bucket id              */
-    int32_t engine;           /* 0 = 1: vector ALU (queries_per_wave);
+    int32_t engine;           /* 1: vector ALU (queries_per_wave);
                                  2: matrix cores, 16 queries per wave, the
-                                 dot products of each chunk as MFMA tiles   */
+                                 dot products of each chunk as MFMA tiles
+                                 (F32: the k reported distances recomputed
+                                 exactly); 0: automatic, 2 when
+                                 queries_per_wave is 0 and nq * nprobe >=
+                                 8 * nlist, else 1                         */
 } pdx_ivf_search_params;
+
+/* pdx_ivf_tune -- pick the fastest scan schedule for a workload.
+ *
+ * Times pdx_search_ivf on the caller's queries (one warm-up, then the best
+ * of `reps` timed runs, HIP events on `stream`, synchronous) for each
+ * candidate schedule: vector ALU with 1, 2, 4 or 8 queries per wave, or
+ * matrix cores; buckets by size or by id; and, when tune_delta_d is set
+ * and eps0 is finite, ADSampling test intervals delta_d of 32 and 64
+ * dimensions (a longer interval tests less often, each test on more
+ * dimensions).  The vectorgroup stays 64 vectors: one per lane of a wave.
+ * params: in, the search to tune (eps0, dtype, rerank; mlp and traces must
+ * be NULL); out, engine, queries_per_wave, bucket_order and delta_d set to
+ * the fastest candidate.  table (may be NULL): PDX_TUNE_CANDIDATES entries,
+ * filled in candidate order (ms < 0: candidate skipped).  ws: at least
+ * pdx_ivf_tune_workspace bytes, 16-byte aligned.  Errors as pdx_search_ivf. */
+#define PDX_TUNE_CANDIDATES 14
+typedef struct {
+    int32_t engine, queries_per_wave, bucket_order, delta_d;
+    float ms; /* best timed run */
+} pdx_ivf_schedule;
+
+PDX_API size_t pdx_ivf_tune_workspace(const pdx_index *index, int64_t nq, int32_t k, int32_t nprobe,
+                                      const pdx_ivf_search_params *params);
+PDX_API pdx_status pdx_ivf_tune(const pdx_index *index, const float *q, int64_t nq, int32_t k, int32_t nprobe,
+                                pdx_ivf_search_params *params, int32_t tune_delta_d, int32_t reps,
+                                pdx_ivf_schedule *table, void *ws, size_t ws_bytes, void *stream);
 
 PDX_API size_t pdx_search_ivf_workspace(const pdx_index *index, int64_t nq, int32_t k, int32_t nprobe,
                                 const pdx_ivf_search_params *params);
@@ -251,15 +285,17 @@ PDX_API pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_
 /* ---------------------------------------------------------------------
  * Learned early termination for the IVF search
  *
- * A small network decides, at probe checkpoints (after 2, 4, 8, 16 and 32
- * probed buckets), whether a query can stop probing.  This is an addition
- * beside the paper's fixed-nprobe IVF search (Section 2.1) and its
- * ADSampling test (Section 2.3), which remain the fallback: with no network
- * the search is the plain one.  Inputs (72): the first 64 rotated query
- * coordinates, then tau/d_r, d_r/d_0, d_last/d_0, tau/d_0 and
+ * A small network sets, per query, how many of its nprobe buckets it
+ * probes.  This is an addition beside the paper's fixed-nprobe IVF search
+ * (Section 2.1) and its ADSampling test (Section 2.3), which remain the
+ * fallback: with no network (or a network that never fires) the search is
+ * the plain one.  After START (the nearest bucket, scanned whole) the
+ * network is evaluated for r = 1 .. nprobe-1 on inputs (72): the first 64
+ * rotated query coordinates, then tau/d_r, d_r/d_0, d_last/d_0, tau/d_0 and
  * log2(r)/log2(nprobe), each ratio clamped to [0, 1e4] (tau: the k-th
- * distance over the r buckets probed so far; d_i: the squared distance to
- * the i-th probed centroid, d_r the next one), then 3 zeros.  Network:
+ * distance in the START bucket; d_i: the squared distance to the i-th
+ * nearest centroid, 0-based, so d_r is the first bucket not probed), then
+ * 3 zeros.  The query probes the smallest r whose output fires.  Network:
  * relu(64) -> relu(64) -> logit, float16 weights, float32 accumulation.
  * State buffer (pdx_mlp_bytes): float32 parameters W1[64][72] b1[64]
  * W2[64][64] b2[64] w3[64] b3 (8897 used, 8960 padded), Adam moments,

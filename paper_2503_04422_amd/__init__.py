@@ -10,6 +10,7 @@ from .api import (  # noqa: F401
     pdx_build,
     pdx_ivf_build,
     pdx_ivf_export,
+    pdx_ivf_tune,
     pdx_search_exact,
     pdx_search_exact_workspace,
     pdx_search_ivf,

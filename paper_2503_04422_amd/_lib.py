@@ -32,7 +32,6 @@ PDX_DTYPE_FP8 = 2
 
 MLP_IN = 72
 MLP_PARAMS = 8960
-MLP_CHECKPOINTS = 5
 
 c_void_p = ctypes.c_void_p
 c_int32 = ctypes.c_int32
@@ -59,9 +58,16 @@ class pdx_ivf_search_params(ctypes.Structure):
     _fields_ = [("eps0", ctypes.c_float), ("delta_d", c_int32), ("dtype", c_int32),
                 ("rerank", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
                 ("mlp", c_void_p), ("mlp_threshold", ctypes.c_float), ("trace_features", c_void_p),
-                ("trace_ids", c_void_p), ("queries_per_wave", c_int32), ("bucket_order", c_int32),
+                ("trace_need", c_void_p), ("queries_per_wave", c_int32), ("bucket_order", c_int32),
                 ("engine", c_int32)]
 
+
+class pdx_ivf_schedule(ctypes.Structure):
+    _fields_ = [("engine", c_int32), ("queries_per_wave", c_int32), ("bucket_order", c_int32),
+                ("delta_d", c_int32), ("ms", ctypes.c_float)]
+
+
+TUNE_CANDIDATES = 14
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -82,6 +88,11 @@ SIGNATURES = {
     "pdx_search_ivf": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32,
                                  ctypes.POINTER(pdx_ivf_search_params), c_void_p, c_size_t,
                                  c_void_p, c_void_p, c_void_p]),
+    "pdx_ivf_tune_workspace": (c_size_t, [c_void_p, c_int64, c_int32, c_int32,
+                                          ctypes.POINTER(pdx_ivf_search_params)]),
+    "pdx_ivf_tune": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32,
+                               ctypes.POINTER(pdx_ivf_search_params), c_int32, c_int32,
+                               ctypes.POINTER(pdx_ivf_schedule), c_void_p, c_size_t, c_void_p]),
     "pdx_mlp_bytes": (c_size_t, []),
     "pdx_mlp_workspace": (c_size_t, [c_int64]),
     "pdx_mlp_init": (c_int32, [c_void_p, c_void_p, c_void_p]),

@@ -163,9 +163,12 @@ def pdx_ivf_export(index: PdxIndex, stream: Optional[torch.cuda.Stream] = None):
 
 def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delta_d: int = 0,
                              dtype: str = "f32", rerank: int = 0, queries_per_wave: int = 0,
-                             engine: int = 0) -> int:
-    p = _lib.pdx_ivf_search_params(2.1, int(delta_d), _DTYPES[dtype], int(rerank), None, None, None, 0.5, None,
-                                   None, int(queries_per_wave), 0, int(engine))
+                             engine: int = 0, mlp: Optional["MlpState"] = None) -> int:
+    """Workspace bytes of pdx_search_ivf with the same arguments (the
+    learned stop adds stages, and so item padding)."""
+    p = _lib.pdx_ivf_search_params(2.1, int(delta_d), _DTYPES[dtype], int(rerank), None, None,
+                                   None if mlp is None else _ptr(mlp.mem), 0.5, None, None,
+                                   int(queries_per_wave), 0, int(engine))
     return int(lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p)))
 
 
@@ -224,17 +227,18 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                    queries_per_wave: int = 0, bucket_order: int = 0, engine: int = 0,
                    stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Approximate k nearest neighbours (IVF + ADSampling), optionally with the
-    learned early termination (mlp) or recording checkpoint traces
-    (trace = (features [nq, 5, 72] float32, ids [nq, 5, k] int64))."""
+    learned probe budget (mlp) or recording its training traces
+    (trace = (features [nq, nprobe, 72] float32, need [nq] int32))."""
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     if q.shape[1] != index.d:
         raise ValueError("query dimension does not match the index")
     tf, ti = (None, None) if trace is None else trace
-    if tf is not None and (tf.dtype != torch.float32 or tf.numel() != nq * _lib.MLP_CHECKPOINTS * _lib.MLP_IN):
-        raise TypeError("trace features must be float32 [nq, 5, 72]")
-    if ti is not None and (ti.dtype != torch.int64 or ti.numel() != nq * _lib.MLP_CHECKPOINTS * k):
-        raise TypeError("trace ids must be int64 [nq, 5, k]")
+    if tf is not None and (tf.dtype != torch.float32 or tf.numel() != nq * nprobe * _lib.MLP_IN
+                           or not tf.is_contiguous()):
+        raise TypeError("trace features must be contiguous float32 [nq, nprobe, 72]")
+    if ti is not None and (ti.dtype != torch.int32 or ti.numel() != nq or not ti.is_contiguous()):
+        raise TypeError("trace need must be contiguous int32 [nq]")
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
                                    _DTYPES[dtype], int(rerank),
                                    ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
@@ -249,6 +253,30 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                             workspace.numel(), _ptr(ids), _ptr(dist), _stream(stream))
     check(st, "pdx_search_ivf")
     return ids, dist
+
+
+def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1, delta_d: int = 0,
+                 dtype: str = "f32", rerank: int = 0, tune_delta_d: bool = True, reps: int = 3,
+                 stream: Optional[torch.cuda.Stream] = None):
+    """Fastest scan schedule for this workload (pdx_ivf_tune).  Returns
+    (schedule, table): schedule = keyword arguments for pdx_search_ivf
+    (engine, queries_per_wave, bucket_order, delta_d); table = every
+    candidate with its best time in ms (-1: skipped)."""
+    q = _dev_f32(q, "q")
+    nq = q.shape[0]
+    p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
+                                   _DTYPES[dtype], int(rerank), None, None, None, 0.5, None, None, 0, 0, 0)
+    need = lib.pdx_ivf_tune_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
+    table = (_lib.pdx_ivf_schedule * _lib.TUNE_CANDIDATES)()
+    st = lib.pdx_ivf_tune(index.handle, _ptr(q), nq, k, nprobe, ctypes.byref(p), int(bool(tune_delta_d)), int(reps),
+                          table, _ptr(ws), ws.numel(), _stream(stream))
+    check(st, "pdx_ivf_tune")
+    sched = {"engine": p.engine, "queries_per_wave": p.queries_per_wave, "bucket_order": p.bucket_order,
+             "delta_d": p.delta_d}
+    rows = [{"engine": t.engine, "queries_per_wave": t.queries_per_wave, "bucket_order": t.bucket_order,
+             "delta_d": t.delta_d, "ms": round(float(t.ms), 4)} for t in table]
+    return sched, rows
 
 
 def pdx_version() -> str:

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
     uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
-    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, const int32_t *__restrict__ active) {
+    int32_t chunk, float eps0, unsigned long long *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -59,9 +59,9 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     const int32_t q0 = __builtin_amdgcn_readfirstlane(mine.x);
     if (q0 < 0) return;  // unused capacity (a batch otherwise starts with a real item)
     const int32_t l = probe[(int64_t)q0 * nprobe + __builtin_amdgcn_readfirstlane(mine.y)];
-    bool row_ok = mine.x >= 0 && !bad[mine.x] && !(active && !active[mine.x]);
+    bool row_ok = mine.x >= 0 && !bad[mine.x];
     const uint32_t use = (uint32_t)(__ballot(row_ok) & 0xffffull);  // bit m: query slot m is scanned
-    // items of stopped or non-finite queries get an empty list
+    // items of non-finite queries get an empty list
     if (mine.x >= 0 && !row_ok && kq == 0)
         for (int i = 0; i < k; ++i) slots[((size_t)mine.x * nprobe + mine.y) * k + i] = kEmptyKey;
     if (!use) return;
@@ -228,12 +228,12 @@ hipError_t launch_ivf_mscan(bool prune, int32_t store, const void *data, const f
                             const int32_t *slot_id, const int32_t *goff, const float *cen, const int2 *items,
                             int64_t nbatch, const int32_t *probe, int32_t nprobe, const float *qrot, uint32_t *tau,
                             const int32_t *bad, uint64_t *slots, int32_t k, int32_t chunk, float eps0,
-                            unsigned long long *counters, const int32_t *active, hipStream_t s) {
+                            unsigned long long *counters, hipStream_t s) {
     if (nbatch <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((nbatch + 3) / 4);
 #define PDX_MSCAN(P, S)                                                                                            \
     ivf_mscan_kernel<P, S><<<grid, 256, 0, s>>>(data, scale, d, slot_id, goff, cen, items, nbatch, probe, nprobe, \
-                                                qrot, tau, bad, slots, k, chunk, eps0, counters, active)
+                                                qrot, tau, bad, slots, k, chunk, eps0, counters)
     if (prune) {
         if (store == PDX_DTYPE_BF16) PDX_MSCAN(true, PDX_DTYPE_BF16);
         else if (store == PDX_DTYPE_FP8) PDX_MSCAN(true, PDX_DTYPE_FP8);

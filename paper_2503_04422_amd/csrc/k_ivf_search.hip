@@ -62,49 +62,38 @@ __global__ __launch_bounds__(256) void select_probe_kernel(const float *__restri
     }
 }
 
-// items per bucket: count, exclusive prefix, scatter (START items r = 0 and
-// pruned items r >= 1 in two separate lists)
-// Probe ranks >= 1 are cut into stages at the checkpoints: items are grouped
-// by (stage, bucket), so each stage is one contiguous range of items.
-struct Stages {
-    int32_t n;         // number of stages of ranks >= 1
-    int32_t b[8];      // stage s covers ranks [b[s], b[s+1]); b[0] = 1, b[n] = nprobe
-};
-
-__device__ __forceinline__ int32_t stage_of(const Stages &st, int32_t r) {
-    int32_t s = 0;
-    while (s + 1 < st.n && r >= st.b[s + 1]) ++s;
-    return s;
+// items per bucket: count, padded exclusive prefix, scatter (START items
+// r = 0 and the other ranks r >= 1 in two separate lists).  Only ranks in
+// [rlo, rhi) below the query's budget (if any) become items.
+__device__ __forceinline__ bool item_wanted(int32_t r, int32_t rlo, int32_t rhi, const int32_t *budget,
+                                            int64_t qi) {
+    return r >= rlo && r < rhi && !(budget && r >= budget[qi]);
 }
 
-__global__ void item_count_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe, int32_t nlist,
-                                  Stages st, int32_t *__restrict__ cnt0, int32_t *__restrict__ cnt1) {
+__global__ void item_count_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe, int32_t rlo,
+                                  int32_t rhi, const int32_t *__restrict__ budget, int32_t *__restrict__ cnt0,
+                                  int32_t *__restrict__ cnt1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq * nprobe) return;
     int32_t r = (int32_t)(i % nprobe);
-    if (r == 0) atomicAdd(cnt0 + probe[i], 1);
-    else atomicAdd(cnt1 + (int64_t)stage_of(st, r) * nlist + probe[i], 1);
+    if (!item_wanted(r, rlo, rhi, budget, i / nprobe)) return;
+    atomicAdd((r == 0 ? cnt0 : cnt1) + probe[i], 1);
 }
 
-// Cursor where each bucket's items start, per segment (block 0: START
-// items; block 1 + s: stage s).  A bucket's item count is rounded up to a
+// Cursor where each bucket's items start, per count array (block b of the
+// grid: cnt[b]).  A bucket's item count is rounded up to a
 // multiple of qb so that every batch of qb consecutive items belongs to one
 // bucket (the rounding slots stay padding, query id -1).  Buckets are laid
 // out by id, or larger first so their long batches start early and the
 // launch drains evenly; keys (size descending, id) are sorted in LDS.
-struct SegBase {
-    int32_t b[8];  // first item of stage s in items1
-};
-
 __global__ __launch_bounds__(1024) void batch_prefix_kernel(int32_t *__restrict__ cnt0, int32_t *__restrict__ cnt1,
                                                             int32_t nlist, int32_t pow2,
                                                             const int32_t *__restrict__ list_size, int32_t qb,
-                                                            int32_t by_size, SegBase sb) {
+                                                            int32_t by_size) {
     extern __shared__ uint64_t order[];  // pow2 keys
     __shared__ int32_t part[1024];
     __shared__ int32_t carry;
-    int32_t *cnt = blockIdx.x == 0 ? cnt0 : cnt1 + (int64_t)(blockIdx.x - 1) * nlist;
-    const int32_t base = blockIdx.x == 0 ? 0 : sb.b[blockIdx.x - 1];
+    int32_t *cnt = blockIdx.x == 0 ? cnt0 : cnt1;
     for (int32_t l = threadIdx.x; l < pow2; l += blockDim.x) {
         uint64_t key = kEmptyKey;
         if (l < nlist)
@@ -142,23 +131,25 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(int32_t *__restrict_
             part[threadIdx.x] += t;
             __syncthreads();
         }
-        if (l >= 0) cnt[l] = base + carry + part[threadIdx.x] - c;
+        if (l >= 0) cnt[l] = carry + part[threadIdx.x] - c;
         __syncthreads();
         if (threadIdx.x == 1023) carry += part[1023];
         __syncthreads();
     }
 }
 
-__global__ void item_scatter_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe, int32_t nlist,
-                                    Stages st, int32_t *__restrict__ cur0, int32_t *__restrict__ cur1,
-                                    int2 *__restrict__ items0, int2 *__restrict__ items1) {
+__global__ void item_scatter_kernel(const int32_t *__restrict__ probe, int64_t nq, int32_t nprobe, int32_t rlo,
+                                    int32_t rhi, const int32_t *__restrict__ budget, int32_t *__restrict__ cur0,
+                                    int32_t *__restrict__ cur1, int2 *__restrict__ items0,
+                                    int2 *__restrict__ items1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq * nprobe) return;
     int32_t r = (int32_t)(i % nprobe);
     int32_t qi = (int32_t)(i / nprobe);
+    if (!item_wanted(r, rlo, rhi, budget, qi)) return;
     int32_t l = probe[i];
     if (r == 0) items0[atomicAdd(cur0 + l, 1)] = make_int2(qi, r);
-    else items1[atomicAdd(cur1 + (int64_t)stage_of(st, r) * nlist + l, 1)] = make_int2(qi, r);
+    else items1[atomicAdd(cur1 + l, 1)] = make_int2(qi, r);
 }
 
 // Scan of one bucket for one query per wave.  Work items are consecutive
@@ -180,8 +171,7 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nitems,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
     uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
-    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, uint32_t nwg,
-    const int32_t *__restrict__ active) {
+    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, uint32_t nwg) {
     // grid = 8 * ceil(nwg / 8): every (xcd, index) pair is launched once
     const uint32_t per_xcd = gridDim.x >> 3;
     const uint32_t wg = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -193,7 +183,7 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     const int64_t qi = item.x;
     const int32_t r = item.y;
     uint64_t *myslot = slots + ((size_t)qi * nprobe + r) * k;
-    if (bad[qi] || (active && !active[qi])) {  // non-finite query, or it stopped probing
+    if (bad[qi]) {  // non-finite query
         if (lane < k) myslot[lane] = kEmptyKey;
         return;
     }
@@ -277,7 +267,7 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
     uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
-    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, const int32_t *__restrict__ active) {
+    int32_t chunk, float eps0, unsigned long long *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= nbatch) return;
@@ -294,7 +284,7 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
         if (qid[q] < 0) continue;
-        if (bad[qid[q]] || (active && !active[qid[q]])) {  // non-finite query, or it stopped probing
+        if (bad[qid[q]]) {  // non-finite query
             if (lane < k) slots[((size_t)qid[q] * nprobe + rk[q]) * k + lane] = kEmptyKey;
         } else {
             use |= 1u << q;
@@ -402,75 +392,94 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
     }
 }
 
-// Checkpoint after the first `cp` probed buckets: the k-best list over
-// those buckets (its last distance tightens the threshold for the later
-// buckets), the network's inputs (documented with pdx_mlp_* in
-// include/pdx.h), and optionally the trace and/or the stop decision.
-__global__ __launch_bounds__(64) void checkpoint_kernel(
-    int32_t cp, int32_t c, bool valid, const float *__restrict__ qrot, int32_t d, const float *__restrict__ cd,
-    int32_t nlist, const int32_t *__restrict__ probe, int32_t nprobe, uint32_t *__restrict__ tau,
-    const uint64_t *__restrict__ slots, int32_t kk, int32_t k, const int32_t *__restrict__ bad,
-    const __half *__restrict__ w16, float zthr, int32_t *__restrict__ active, float *__restrict__ trace_f,
-    int64_t *__restrict__ trace_ids) {
+// Learned probe budget, after START: for r = 1 .. nprobe-1 the network's
+// inputs (documented with pdx_mlp_* in include/pdx.h) for "stop after r
+// buckets", tau being the k-th distance of the START bucket; the query
+// probes the smallest r whose logit exceeds zthr (else all nprobe).  With
+// trace_f, every r's inputs are recorded ([nq][nprobe][72], row r - 1; the
+// last row zero) and no budget is set.
+__global__ __launch_bounds__(64) void budget_kernel(const float *__restrict__ qrot, int32_t d,
+                                                    const float *__restrict__ cd, int32_t nlist,
+                                                    const int32_t *__restrict__ probe, int32_t nprobe,
+                                                    const uint32_t *__restrict__ tau, const int32_t *__restrict__ bad,
+                                                    const __half *__restrict__ w16, float zthr,
+                                                    int32_t *__restrict__ budget, float *__restrict__ trace_f) {
     __shared__ float feat[kMlpIn];
     const int64_t qi = blockIdx.x;
     const int lane = threadIdx.x;
-    if (!valid) {  // checkpoint at or beyond nprobe: trace only
-        if (trace_f)
-            for (int i = lane; i < kMlpIn; i += 64) trace_f[(qi * kMlpCheckpoints + c) * kMlpIn + i] = 0.0f;
-        if (trace_ids && lane < k) trace_ids[(qi * kMlpCheckpoints + c) * k + lane] = -1;
-        return;
-    }
-    // k-best over the buckets probed so far
-    const uint64_t *base = slots + (size_t)qi * nprobe * kk;
-    const int64_t total = (int64_t)cp * kk;
-    uint64_t e = kEmptyKey, kth = kEmptyKey;
-    for (int64_t i0 = 0; i0 < total; i0 += kWave) {
-        uint64_t key = (i0 + lane < total) ? base[i0 + lane] : kEmptyKey;
-        topk_offer(e, kth, key, key != kEmptyKey, kk, lane);
-    }
-    float t = INFINITY;
-    if (kth != kEmptyKey) {
-        t = key_dist(kth);
-        if (lane == 0 && static_cast<uint32_t>(kth >> 32) < tau[qi]) tau[qi] = static_cast<uint32_t>(kth >> 32);
-    }
-    if (trace_ids && lane < k)
-        trace_ids[(qi * kMlpCheckpoints + c) * k + lane] = (bad[qi] || e == kEmptyKey) ? -1 : (int64_t)(e & 0xffffffffu);
-    if (!trace_f && !w16) return;
     const float *cq = cd + qi * nlist;
     const int32_t *pq = probe + qi * nprobe;
+    const float t = __uint_as_float(tau[qi]);
     const float d0 = cq[pq[0]] + 1e-20f;
-    const float dr = cq[pq[cp]] + 1e-20f;
     const float dl = cq[pq[nprobe - 1]] + 1e-20f;
     auto clampr = [](float v) { return fminf(fmaxf(v, 0.0f), 1.0e4f); };
     feat[lane] = lane < d ? qrot[qi * d + lane] : 0.0f;
-    if (lane < kMlpIn - 64) {
-        float v = 0.0f;
-        if (lane == 0) v = clampr(t / dr);
-        else if (lane == 1) v = clampr(dr / d0);
-        else if (lane == 2) v = clampr(dl / d0);
-        else if (lane == 3) v = clampr(t / d0);
-        else if (lane == 4) v = log2f((float)cp) / log2f((float)nprobe);
-        feat[64 + lane] = v;
+    const bool decide = w16 && !trace_f && !bad[qi];
+    int32_t chosen = nprobe;
+    for (int32_t r = 1; r < nprobe; ++r) {
+        const float dr = cq[pq[r]] + 1e-20f;
+        if (lane < kMlpIn - 64) {
+            float v = 0.0f;
+            if (lane == 0) v = clampr(t / dr);
+            else if (lane == 1) v = clampr(dr / d0);
+            else if (lane == 2) v = clampr(dl / d0);
+            else if (lane == 3) v = clampr(t / d0);
+            else if (lane == 4) v = log2f((float)r) / log2f((float)nprobe);
+            feat[64 + lane] = v;
+        }
+        __syncthreads();
+        if (trace_f)
+            for (int i = lane; i < kMlpIn; i += 64) trace_f[(qi * nprobe + (r - 1)) * kMlpIn + i] = feat[i];
+        if (decide) {
+            const float z = mlp_forward_wave(w16, feat, lane, nullptr, nullptr, nullptr, nullptr);
+            if (z > zthr) {  // z is the same in every lane
+                chosen = r;
+                break;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (trace_f)
-        for (int i = lane; i < kMlpIn; i += 64) trace_f[(qi * kMlpCheckpoints + c) * kMlpIn + i] = feat[i];
-    if (w16 && active[qi] && !bad[qi]) {
-        const float z = mlp_forward_wave(w16, feat, lane, nullptr, nullptr, nullptr, nullptr);
-        if (lane == 0 && z > zthr) active[qi] = 0;
+        for (int i = lane; i < kMlpIn; i += 64) trace_f[(qi * nprobe + (nprobe - 1)) * kMlpIn + i] = 0.0f;
+    if (decide && lane == 0) budget[qi] = chosen;
+}
+
+// Buckets a query needed: 1 + the largest probe rank among the buckets of
+// its final ids (0 when it has none); stopping after r buckets loses
+// nothing of the result exactly when r >= this.
+__global__ __launch_bounds__(64) void need_kernel(const int64_t *__restrict__ ids, int32_t k,
+                                                  const int32_t *__restrict__ assign,
+                                                  const int32_t *__restrict__ probe, int32_t nprobe,
+                                                  int32_t *__restrict__ need) {
+    const int64_t qi = blockIdx.x;
+    const int lane = threadIdx.x;
+    int32_t mine = 0;
+    if (lane < k) {
+        const int64_t id = ids[qi * k + lane];
+        if (id >= 0) {
+            const int32_t l = assign[id];
+            for (int32_t r = 0; r < nprobe; ++r)
+                if (probe[qi * nprobe + r] == l) {
+                    mine = r + 1;
+                    break;
+                }
+        }
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mine = max(mine, __shfl_xor(mine, off));
+    if (lane == 0) need[qi] = mine;
 }
 
 // k-best over a query's probe slots [r0, r1); optional threshold / result
 __global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restrict__ slots, int32_t nprobe,
-                                                       int32_t r0, int32_t r1, int32_t k,
-                                                       const int32_t *__restrict__ bad,
+                                                       int32_t r0, int32_t r1, const int32_t *__restrict__ budget,
+                                                       int32_t k, const int32_t *__restrict__ bad,
                                                        uint32_t *__restrict__ tau,
                                                        int64_t *__restrict__ out_ids,
                                                        float *__restrict__ out_dist, uint64_t *__restrict__ keys_out) {
     const int64_t qi = blockIdx.x;
     const int lane = threadIdx.x;
+    if (budget) r1 = min(r1, budget[qi]);  // ranks at or past the budget were not scanned
     const uint64_t *base = slots + ((size_t)qi * nprobe + r0) * k;
     const int64_t total = (int64_t)(r1 - r0) * k;
     uint64_t e = kEmptyKey, kth = kEmptyKey;
@@ -500,37 +509,41 @@ __global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restric
 // chunk sums added in order); the k best of those are the result.
 // Exact f32 distances of a query's r candidates (keys [nq][r], ordered by
 // the scanned distance) from the row-major rotated rows, then the k best by
-// (exact distance, id).  One wave per query: the 64 lanes split each
-// candidate's dimensions (coalesced row reads), a butterfly sums them.
+// (exact distance, id).  The summation order is the vector scans' (each
+// chunk of `chunk` dimensions summed sequentially, the chunk sums added in
+// order), so every engine reports the same distance for a vector.  One
+// wave per query: lane c sums chunk c, the chunk sums are added in order.
 __global__ __launch_bounds__(256) void rerank_kernel(const uint64_t *__restrict__ keys, int32_t r, int32_t k,
                                                      const float *__restrict__ xrow, const float *__restrict__ qrot,
-                                                     int32_t d, const int32_t *__restrict__ bad, int64_t nq,
-                                                     int64_t *__restrict__ out_ids, float *__restrict__ out_dist) {
+                                                     int32_t d, int32_t chunk, const int32_t *__restrict__ bad,
+                                                     int64_t nq, int64_t *__restrict__ out_ids,
+                                                     float *__restrict__ out_dist) {
     const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (qi >= nq) return;
     const float *qp = qrot + qi * d;
+    const int32_t nch = (d + chunk - 1) / chunk;
     uint64_t mine = kEmptyKey;
     for (int32_t i = 0; i < r; ++i) {
         const uint64_t key = keys[qi * r + i];
         if (key == kEmptyKey) break;  // the list is sorted: the rest is empty too
         const uint32_t id = static_cast<uint32_t>(key & 0xffffffffu);
         const float *x = xrow + (int64_t)id * d;
-        float s0 = 0.0f, s1 = 0.0f;
-        int32_t j = lane;
-        for (; j + 64 < d; j += 128) {
-            const float t0 = qp[j] - x[j], t1 = qp[j + 64] - x[j + 64];
-            s0 = fmaf(t0, t0, s0);
-            s1 = fmaf(t1, t1, s1);
+        float partial = 0.0f;
+        for (int32_t base = 0; base < nch; base += 64) {
+            float s = 0.0f;
+            const int32_t c = base + lane;
+            if (c < nch) {
+                const int32_t j1 = min((c + 1) * chunk, d);
+                for (int32_t j = c * chunk; j < j1; ++j) {
+                    const float t = qp[j] - x[j];
+                    s = fmaf(t, t, s);
+                }
+            }
+            const int32_t cnt = min(64, nch - base);
+            for (int32_t u = 0; u < cnt; ++u) partial += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s), u));
         }
-        if (j < d) {
-            const float t0 = qp[j] - x[j];
-            s0 = fmaf(t0, t0, s0);
-        }
-        float s = s0 + s1;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == i) mine = make_key(s, id);
+        if (lane == i) mine = make_key(partial, id);
     }
     uint64_t e = kEmptyKey, kth = kEmptyKey;
     topk_offer(e, kth, mine, mine != kEmptyKey, k, lane);
@@ -570,36 +583,28 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         if (r == 0) r = min(4 * k, PDX_MAX_K);
         pl.rerank = r < 0 ? 0 : max(r, k);
     }
-    pl.matrix = (p && p->engine == 2) ? 1 : 0;
+    {
+        int32_t eng = p ? p->engine : 0;
+        if (eng == 0)  // automatic: matrix cores once buckets see enough queries to fill 16-row tiles
+            eng = (!(p && p->queries_per_wave > 0) && (double)nq * nprobe >= 8.0 * ix->nlist) ? 2 : 1;
+        pl.matrix = eng == 2 ? 1 : 0;
+    }
     // matrix-core scans report exact f32 distances of their k best
     if (pl.matrix && pl.dtype == PDX_DTYPE_F32) pl.rerank = k;
     pl.kk = pl.rerank > 0 ? pl.rerank : k;
     pl.w16 = (p && p->mlp) ? mlp_layout(const_cast<void *>(p->mlp)).w16 : nullptr;
     pl.trace_f = p ? p->trace_features : nullptr;
-    pl.trace_ids = p ? p->trace_ids : nullptr;
-    if (pl.trace_f || pl.trace_ids) pl.w16 = nullptr;  // traces probe every bucket
+    pl.trace_need = p ? p->trace_need : nullptr;
+    if (pl.trace_f || pl.trace_need) pl.w16 = nullptr;  // traces probe every bucket
     {
         float th = p ? p->mlp_threshold : 0.5f;
         th = fminf(fmaxf(th, 1e-7f), 1.0f - 1e-7f);
         pl.zthr = logf(th / (1.0f - th));
     }
-    pl.nstages = 1;
-    pl.stage_b[0] = 1;
-    if (pl.w16 || pl.trace_f || pl.trace_ids) {
-        const int32_t cps[kMlpCheckpoints] = {2, 4, 8, 16, 32};
-        for (int32_t c = 0; c < kMlpCheckpoints; ++c)
-            if (cps[c] < nprobe) pl.stage_b[pl.nstages++] = cps[c];
-    }
-    pl.stage_b[pl.nstages] = nprobe;
     pl.qb = pl.matrix ? 16 : (p && p->queries_per_wave > 0) ? p->queries_per_wave : kDefaultQueriesPerWave;
     pl.by_size = !(p && p->bucket_order == 1);
     pl.cap0 = ivf_item_capacity(nq, 1, pl.qb, ix->nlist);
-    pl.cap1 = 0;
-    for (int32_t sg = 0; sg < pl.nstages; ++sg) {
-        pl.sbase[sg] = pl.cap1;
-        pl.cap[sg] = ivf_item_capacity(nq, pl.stage_b[sg + 1] - pl.stage_b[sg], pl.qb, ix->nlist);
-        pl.cap1 += pl.cap[sg];
-    }
+    pl.cap1 = ivf_item_capacity(nq, nprobe - 1, pl.qb, ix->nlist);
     int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
     pl.chunk = dd;
     size_t q = (size_t)(nq > 0 ? nq : 0);
@@ -610,8 +615,8 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.bad = c.take<int32_t>(q);
     pl.tau = c.take<uint32_t>(q);
     pl.cnt0 = c.take<int32_t>(ix->nlist);
-    pl.cnt1 = c.take<int32_t>((size_t)ix->nlist * 8);
-    pl.active = c.take<int32_t>(q);
+    pl.cnt1 = c.take<int32_t>(ix->nlist);
+    pl.budget = c.take<int32_t>(q);
     pl.items0 = c.take<int2>((size_t)pl.cap0);
     pl.items1 = c.take<int2>((size_t)(pl.cap1 > 0 ? pl.cap1 : 1));
     pl.slots = c.take<uint64_t>(q * nprobe * pl.kk);
@@ -645,13 +650,9 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                                          pl.probe, pl.bad, pl.tau);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 3. work items grouped by bucket
-    Stages st{};
-    st.n = pl.nstages;
-    for (int32_t i = 0; i <= pl.nstages; ++i) st.b[i] = pl.stage_b[i];
-    const int32_t ncnt1 = ix->nlist * pl.nstages;
     if ((e = launch_fill_i32(pl.cnt0, ix->nlist, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(pl.cnt1, ncnt1, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(pl.active, nq, 1, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(pl.cnt1, ix->nlist, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(pl.budget, nq, pl.nprobe, s)) != hipSuccess) return e;
     if (pl.qb > 1) {  // padding slots: query id -1
         const unsigned long long pad = 0x00000000ffffffffull;
         if ((e = launch_fill_u64(reinterpret_cast<unsigned long long *>(pl.items0), pl.cap0, pad, s)) != hipSuccess)
@@ -662,14 +663,13 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     }
     int64_t tot = nq * pl.nprobe;
     unsigned gb = (unsigned)((tot + 255) / 256);
-    item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, ix->nlist, st, pl.cnt0, pl.cnt1);
-    {
-        SegBase sb{};
-        for (int32_t sg = 0; sg < pl.nstages; ++sg) sb.b[sg] = (int32_t)pl.sbase[sg];
-        batch_prefix_kernel<<<1 + pl.nstages, 1024, pow2 * sizeof(uint64_t), s>>>(
-            pl.cnt0, pl.cnt1, ix->nlist, pow2, ix->list_size, pl.qb, pl.by_size, sb);
-    }
-    item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, ix->nlist, st, pl.cnt0, pl.cnt1, pl.items0,
+    // with a learned budget the items of ranks >= 1 are built once it is known
+    const bool later = pl.w16 != nullptr;
+    const int32_t rhi0 = later ? 1 : pl.nprobe;
+    item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 0, rhi0, nullptr, pl.cnt0, pl.cnt1);
+    batch_prefix_kernel<<<later ? 1 : 2, 1024, pow2 * sizeof(uint64_t), s>>>(pl.cnt0, pl.cnt1, ix->nlist, pow2,
+                                                                             ix->list_size, pl.qb, pl.by_size);
+    item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 0, rhi0, nullptr, pl.cnt0, pl.cnt1, pl.items0,
                                           pl.items1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. START
@@ -678,7 +678,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                    : static_cast<const void *>(ix->pdx);
     // `cap` item slots starting at `items`: one item per wave (qb = 1), or
     // cap / qb batches of qb items
-    auto scan = [&](bool prune, const int2 *items, int64_t cap, unsigned long long *cnt, const int32_t *act) {
+    auto scan = [&](bool prune, const int2 *items, int64_t cap, unsigned long long *cnt) {
         if (cap <= 0) return hipSuccess;
         if (pl.qb == 1) {
             const uint32_t nwg = (uint32_t)((cap + 3) / 4);
@@ -686,7 +686,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
 #define PDX_SCAN(P, S)                                                                                          \
     ivf_scan_kernel<P, S><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, cap,  \
                                                pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots, pl.kk,     \
-                                               pl.chunk, pl.eps0, cnt, nwg, act)
+                                               pl.chunk, pl.eps0, cnt, nwg)
             if (prune) {
                 if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16);
                 else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8);
@@ -703,12 +703,12 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         if (pl.matrix)
             return launch_ivf_mscan(prune, pl.dtype, data, ix->fp8_scale, d, ix->slot_id, ix->list_goff,
                                     ix->centroids, items, nb, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots,
-                                    pl.kk, pl.chunk, pl.eps0, cnt, act, s);
+                                    pl.kk, pl.chunk, pl.eps0, cnt, s);
         const unsigned grid = (unsigned)((nb + 3) / 4);
 #define PDX_BSCAN(P, S, Q)                                                                                        \
     ivf_bscan_kernel<P, S, Q><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, nb, \
                                                    pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots, pl.kk,   \
-                                                   pl.chunk, pl.eps0, cnt, act)
+                                                   pl.chunk, pl.eps0, cnt)
 #define PDX_BSCAN_Q(P, S)                      \
     switch (pl.qb) {                           \
         case 2: PDX_BSCAN(P, S, 2); break;     \
@@ -729,50 +729,48 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
 #undef PDX_BSCAN
         return hipGetLastError();
     };
-    if ((e = scan(false, pl.items0, pl.cap0, pl.counters, nullptr)) != hipSuccess) return e;
-    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, 1, pl.kk, pl.bad, pl.tau, nullptr, nullptr,
-                                                nullptr);
+    if ((e = scan(false, pl.items0, pl.cap0, pl.counters)) != hipSuccess) return e;
+    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, 1, nullptr, pl.kk, pl.bad, pl.tau, nullptr,
+                                                nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark(1)) != hipSuccess) return e;
-    // 5. pruned scan of the other probed buckets, stage by stage; between
-    //    stages the checkpoint (trace and/or learned stop decision)
-    const bool staged = pl.w16 || pl.trace_f || pl.trace_ids;
-    for (int32_t sg = 0; sg < pl.nstages && pl.nprobe > 1; ++sg) {
-        if (sg > 0 && staged) {
-            const int32_t cp = pl.stage_b[sg];
-            int32_t c = 0;
-            while (c < kMlpCheckpoints && (2 << c) != cp) ++c;
-            checkpoint_kernel<<<(unsigned)nq, 64, 0, s>>>(cp, c, true, pl.qrot, d, pl.cd, ix->nlist, pl.probe,
-                                                          pl.nprobe, pl.tau, pl.slots, pl.kk, pl.k, pl.bad, pl.w16,
-                                                          pl.zthr, pl.active, pl.trace_f, pl.trace_ids);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        if ((e = scan(true, pl.items1 + pl.sbase[sg], pl.cap[sg], pl.counters ? pl.counters + 2 : nullptr,
-                      pl.w16 ? pl.active : nullptr)) != hipSuccess)
-            return e;
+    // 5. learned probe budget (or the traces of its inputs), then the
+    //    pruned scan of the other probed buckets
+    if ((pl.w16 || pl.trace_f) && pl.nprobe > 1) {
+        budget_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.qrot, d, pl.cd, ix->nlist, pl.probe, pl.nprobe, pl.tau, pl.bad,
+                                                  pl.w16, pl.zthr, pl.budget, pl.trace_f);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (pl.trace_f || pl.trace_ids) {  // checkpoints at or beyond nprobe
-        for (int32_t c = 0; c < kMlpCheckpoints; ++c) {
-            if ((2 << c) < pl.nprobe) continue;
-            checkpoint_kernel<<<(unsigned)nq, 64, 0, s>>>(2 << c, c, false, pl.qrot, d, pl.cd, ix->nlist, pl.probe,
-                                                          pl.nprobe, pl.tau, pl.slots, pl.kk, pl.k, pl.bad, nullptr,
-                                                          pl.zthr, pl.active, pl.trace_f, pl.trace_ids);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
+    if (later) {  // items of ranks 1 .. budget - 1
+        item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 1, pl.nprobe, pl.budget, pl.cnt0, pl.cnt1);
+        batch_prefix_kernel<<<1, 1024, pow2 * sizeof(uint64_t), s>>>(pl.cnt1, nullptr, ix->nlist, pow2,
+                                                                     ix->list_size, pl.qb, pl.by_size);
+        item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 1, pl.nprobe, pl.budget, pl.cnt0, pl.cnt1,
+                                              pl.items0, pl.items1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (pl.trace_f && pl.nprobe == 1)
+        if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(pl.trace_f), nq * kMlpIn, 0, s)) != hipSuccess) return e;
+    if (pl.nprobe > 1 &&
+        (e = scan(true, pl.items1, pl.cap1, pl.counters ? pl.counters + 2 : nullptr)) != hipSuccess)
+        return e;
     if ((e = mark(2)) != hipSuccess) return e;
     // 6. merge
     if (pl.rerank > 0) {
-        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, pl.kk, pl.bad, nullptr,
-                                                    nullptr, nullptr, pl.rkeys);
+        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, later ? pl.budget : nullptr,
+                                                    pl.kk, pl.bad, nullptr, nullptr, nullptr, pl.rkeys);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        rerank_kernel<<<(unsigned)((nq + 3) / 4), 256, 0, s>>>(pl.rkeys, pl.kk, pl.k, ix->xrow, pl.qrot, d, pl.bad,
-                                                               nq, out_ids, out_dist);
+        rerank_kernel<<<(unsigned)((nq + 3) / 4), 256, 0, s>>>(pl.rkeys, pl.kk, pl.k, ix->xrow, pl.qrot, d,
+                                                               pl.chunk, pl.bad, nq, out_ids, out_dist);
     } else {
-        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, pl.k, pl.bad, nullptr,
-                                                    out_ids, out_dist, nullptr);
+        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, later ? pl.budget : nullptr,
+                                                    pl.k, pl.bad, nullptr, out_ids, out_dist, nullptr);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (pl.trace_need) {
+        need_kernel<<<(unsigned)nq, 64, 0, s>>>(out_ids, pl.k, ix->assign, pl.probe, pl.nprobe, pl.trace_need);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     return mark(3);
 }
 

@@ -118,20 +118,16 @@ struct IvfPlan {
     uint32_t *tau;     // [nq]
     int32_t *cnt0, *cnt1;  // [nlist] item cursors
     int2 *items0, *items1;
-    int32_t *active;   // [nq] 0 once the learned stop fired
+    int32_t *budget;   // [nq] buckets the query probes (learned; else nprobe)
     const __half *w16; // network weights (null: plain search)
     float zthr;        // stop when the logit exceeds this
     float *trace_f;
-    int64_t *trace_ids;
-    int32_t nstages;
-    int32_t stage_b[8];
+    int32_t *trace_need;
     int32_t matrix;    // bucket scan on the matrix cores (16 queries per wave)
     int32_t qb;        // queries per wave in the bucket scan
     int32_t by_size;   // lay buckets out larger first
     int64_t cap0;      // START item slots (counts rounded up to qb per bucket)
-    int64_t cap[8];    // item slots of stage s, at items1 + sbase[s]
-    int64_t sbase[8];
-    int64_t cap1;
+    int64_t cap1;      // item slots of ranks >= 1
     uint64_t *slots;   // [nq][nprobe][kk]
     uint64_t *rkeys;   // [nq][kk] candidates to rerank
     hipEvent_t *events;
@@ -145,7 +141,7 @@ hipError_t launch_ivf_mscan(bool prune, int32_t store, const void *data, const f
                             const int32_t *slot_id, const int32_t *goff, const float *cen, const int2 *items,
                             int64_t nbatch, const int32_t *probe, int32_t nprobe, const float *qrot, uint32_t *tau,
                             const int32_t *bad, uint64_t *slots, int32_t k, int32_t chunk, float eps0,
-                            unsigned long long *counters, const int32_t *active, hipStream_t s);
+                            unsigned long long *counters, hipStream_t s);
 
 // Item slots for nq queries x `ranks` probe ranks when every bucket's count
 // is rounded up to a multiple of qb (at most qb - 1 padding slots per bucket).
@@ -234,7 +230,6 @@ namespace pdx {
 constexpr int kMlpIn = 72;     // inputs: 64 query coordinates + 5 ratios + 3 zero pads
 constexpr int kMlpH = 64;      // hidden width (= wave width)
 constexpr int kMlpPad = 8960;  // padded parameter count
-constexpr int kMlpCheckpoints = 5;  // after 2, 4, 8, 16, 32 probed buckets
 
 struct MlpLayout {
     float *theta, *m, *v, *g;

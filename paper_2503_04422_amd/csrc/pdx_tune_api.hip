@@ -1,0 +1,133 @@
+// Scan-schedule autotuner for the IVF search (pdx_ivf_tune, include/pdx.h).
+#include <cmath>
+
+#include "pdx_internal.h"
+
+namespace {
+
+struct Candidate {
+    int32_t engine, qpw, order, delta_d;  // delta_d 0: the search's own
+};
+
+// candidate order is part of the interface (the table is filled in it)
+constexpr Candidate kCandidates[PDX_TUNE_CANDIDATES] = {
+    {1, 1, 0, 0}, {1, 1, 1, 0}, {1, 2, 0, 0}, {1, 4, 0, 0}, {1, 8, 0, 0}, {2, 0, 0, 0}, {2, 0, 1, 0},
+    {1, 1, 0, 64}, {1, 1, 1, 64}, {1, 2, 0, 64}, {1, 4, 0, 64}, {1, 8, 0, 64}, {2, 0, 0, 64}, {2, 0, 1, 64},
+};
+
+pdx_ivf_search_params with(const pdx_ivf_search_params &base, const Candidate &c) {
+    pdx_ivf_search_params p = base;
+    p.engine = c.engine;
+    p.queries_per_wave = c.qpw;
+    p.bucket_order = c.order;
+    if (c.delta_d) p.delta_d = c.delta_d;
+    p.phase_events = nullptr;
+    p.counters = nullptr;
+    return p;
+}
+
+bool usable(const pdx_index *index, const pdx_ivf_search_params &base, int32_t tune_delta_d, const Candidate &c) {
+    if (!c.delta_d) return true;
+    return tune_delta_d && std::isfinite(base.eps0) && c.delta_d < index->d;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pdx_ivf_tune_workspace(const pdx_index *index, int64_t nq, int32_t k, int32_t nprobe,
+                              const pdx_ivf_search_params *params) {
+    if (!index || !params || nq < 0 || k < 1) return 0;
+    size_t need = 0;
+    for (const Candidate &c : kCandidates) {
+        const pdx_ivf_search_params p = with(*params, c);
+        const size_t w = pdx_search_ivf_workspace(index, nq, k, nprobe, &p);
+        if (w > need) need = w;
+    }
+    // result buffers after the search workspace
+    return pdx::align_up(need, 256) + pdx::align_up((size_t)nq * k * sizeof(int64_t), 256) +
+           pdx::align_up((size_t)nq * k * sizeof(float), 256);
+}
+
+pdx_status pdx_ivf_tune(const pdx_index *index, const float *q, int64_t nq, int32_t k, int32_t nprobe,
+                        pdx_ivf_search_params *params, int32_t tune_delta_d, int32_t reps, pdx_ivf_schedule *table,
+                        void *ws, size_t ws_bytes, void *stream) {
+    if (!index || !params || !q || !ws || nq < 1 || reps < 1) {
+        pdx::set_error("pdx_ivf_tune: need index, params, queries, workspace, nq >= 1 and reps >= 1");
+        return PDX_EINVAL;
+    }
+    if (params->mlp || params->trace_features || params->trace_need) {
+        pdx::set_error("pdx_ivf_tune: tune the search without the network or traces");
+        return PDX_EINVAL;
+    }
+    const size_t need = pdx_ivf_tune_workspace(index, nq, k, nprobe, params);
+    if (need == 0) {
+        pdx::set_error("pdx_ivf_tune: invalid index or sizes");
+        return PDX_EINVAL;
+    }
+    if (ws_bytes < need) {
+        pdx::set_error("pdx_ivf_tune: workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return PDX_EWORKSPACE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t search_bytes = 0;
+    for (const Candidate &c : kCandidates) {
+        const pdx_ivf_search_params p = with(*params, c);
+        const size_t w = pdx_search_ivf_workspace(index, nq, k, nprobe, &p);
+        if (w > search_bytes) search_bytes = w;
+    }
+    char *base = static_cast<char *>(ws);
+    const size_t off_ids = pdx::align_up(search_bytes, 256);
+    int64_t *ids = reinterpret_cast<int64_t *>(base + off_ids);
+    float *dist = reinterpret_cast<float *>(base + off_ids + pdx::align_up((size_t)nq * k * sizeof(int64_t), 256));
+    hipEvent_t ev[2];
+    if (hipEventCreate(&ev[0]) != hipSuccess) {
+        pdx::set_error("pdx_ivf_tune: hipEventCreate failed");
+        return PDX_EHIP;
+    }
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        pdx::set_error("pdx_ivf_tune: hipEventCreate failed");
+        return PDX_EHIP;
+    }
+    pdx_status st = PDX_OK;
+    bool event_failed = false;
+    int best = -1;
+    float best_ms = INFINITY;
+    for (int ci = 0; ci < PDX_TUNE_CANDIDATES && st == PDX_OK; ++ci) {
+        const Candidate &c = kCandidates[ci];
+        float ms = -1.0f;
+        if (usable(index, *params, tune_delta_d, c)) {
+            const pdx_ivf_search_params p = with(*params, c);
+            st = pdx_search_ivf(index, q, nq, k, nprobe, &p, ws, search_bytes, ids, dist, stream);  // warm-up
+            for (int r = 0; r < reps && st == PDX_OK; ++r) {
+                float t = 0.0f;
+                if (hipEventRecord(ev[0], s) != hipSuccess) event_failed = true;
+                if (!event_failed) st = pdx_search_ivf(index, q, nq, k, nprobe, &p, ws, search_bytes, ids, dist, stream);
+                if (st == PDX_OK && !event_failed &&
+                    (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                     hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess))
+                    event_failed = true;
+                if (event_failed) st = PDX_EHIP;
+                if (st == PDX_OK && (ms < 0.0f || t < ms)) ms = t;
+            }
+            if (st == PDX_OK && ms < best_ms) {
+                best_ms = ms;
+                best = ci;
+            }
+        }
+        if (table) table[ci] = pdx_ivf_schedule{c.engine, c.qpw, c.order, c.delta_d ? c.delta_d : params->delta_d, ms};
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (event_failed) pdx::set_error("pdx_ivf_tune: a HIP event call failed");
+    if (st != PDX_OK) return st;
+    const Candidate &c = kCandidates[best];
+    params->engine = c.engine;
+    params->queries_per_wave = c.qpw;
+    params->bucket_order = c.order;
+    if (c.delta_d) params->delta_d = c.delta_d;
+    return PDX_OK;
+}
+
+}  // extern "C"

@@ -1,22 +1,23 @@
-"""Training driver of the learned early termination (pdx_mlp_*).
+"""Training driver of the learned probe budget (pdx_mlp_*).
 
-The network decides at probe checkpoints (after 2, 4, 8, 16, 32 probed
-buckets) whether a query of the IVF search may stop probing.  It learns from
-traces the search itself records:
+After START the network decides, for every r = 1 .. nprobe-1, whether a
+query of the IVF search may stop after r buckets; the query probes the
+smallest accepted r.  It learns from traces the search itself records:
 
 * a traced search (every probed bucket scanned, ADSampling as deployed)
-  writes, per query and checkpoint, the network's 72 inputs and the k-best
-  ids over the buckets probed so far;
-* label 1 ("stopping here loses nothing") iff that id set equals the final
-  result's id set, i.e. no vector of a later bucket enters the top-k;
+  writes, per query, the network's 72 inputs for each r and the number of
+  buckets the result needed (1 + the largest probe rank holding one of its
+  ids);
+* label of (query, r) = 1 ("stopping after r buckets loses nothing")
+  iff r >= that number, i.e. no vector of a later bucket is in the result;
 * training: Adam on minibatches of the shuffled samples, forward, backward
   and update in the library's kernels; negatives weighted by w0 because a
   wrong stop costs recall while a late stop only costs time.
 
 The IVF search of Section 2.1 with the ADSampling test of Section 2.3 stays
 the fallback: a query the network never stops is searched exactly as
-without it.  Host code here only arranges tensors (shuffling, slicing,
-label comparison); every forward, backward and update runs on the GPU.
+without it.  Labels and shuffling are plain tensor operations; every
+forward, backward and update of the network runs in the library's kernels.
 """
 from __future__ import annotations
 
@@ -28,27 +29,25 @@ import torch
 from . import _lib
 from .api import MlpState, PdxIndex, pdx_search_ivf
 
-CHECKPOINTS = (2, 4, 8, 16, 32)
 
-
-def stop_traces(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1
+def stop_traces(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1, **schedule
                 ) -> Tuple[torch.Tensor, torch.Tensor, Dict[str, float]]:
-    """Traced search of queries q; returns (features [m, 72] float32 device,
-    labels [m] float32 device, stats) over the checkpoints below nprobe."""
+    """Traced search of queries q; returns (features [nq * (nprobe-1), 72]
+    float32 device, labels [nq * (nprobe-1)] float32 device, stats)."""
+    if nprobe < 2:
+        raise ValueError("nprobe must be at least 2")
     nq = q.shape[0]
-    tf = torch.empty((nq, _lib.MLP_CHECKPOINTS, _lib.MLP_IN), dtype=torch.float32, device=q.device)
-    ti = torch.empty((nq, _lib.MLP_CHECKPOINTS, k), dtype=torch.int64, device=q.device)
-    ids, _ = pdx_search_ivf(index, q, k, nprobe, eps0=eps0, trace=(tf, ti))
-    valid = [c for c, cp in enumerate(CHECKPOINTS) if cp < nprobe]
-    if not valid:
-        raise ValueError("nprobe must exceed the first checkpoint (2)")
-    tih = np.sort(ti.cpu().numpy()[:, valid], axis=2)
-    fin = np.sort(ids.cpu().numpy(), axis=1)
-    y = np.all(tih == fin[:, None, :], axis=2).astype(np.float32)
-    feats = tf[:, valid].reshape(-1, _lib.MLP_IN).contiguous()
-    stats = {"samples": int(y.size), "positive_rate": float(y.mean()),
-             "positive_rate_by_checkpoint": {CHECKPOINTS[c]: float(y[:, i].mean()) for i, c in enumerate(valid)}}
-    return feats, torch.from_numpy(y.reshape(-1)).to(q.device), stats
+    tf = torch.empty((nq, nprobe, _lib.MLP_IN), dtype=torch.float32, device=q.device)
+    need = torch.empty(nq, dtype=torch.int32, device=q.device)
+    pdx_search_ivf(index, q, k, nprobe, eps0=eps0, trace=(tf, need), **schedule)
+    r = torch.arange(1, nprobe, device=q.device, dtype=torch.int32)
+    y = (r[None, :] >= need[:, None]).to(torch.float32)  # [nq, nprobe-1]
+    feats = tf[:, : nprobe - 1].reshape(-1, _lib.MLP_IN).contiguous()
+    nh = need.cpu().numpy()
+    stats = {"samples": int(y.numel()), "positive_rate": float(y.mean().item()),
+             "mean_buckets_needed": float(nh.mean()),
+             "needed_quantiles": {str(p): float(np.quantile(nh, p)) for p in (0.5, 0.9, 0.95, 0.99)}}
+    return feats, y.reshape(-1).contiguous(), stats
 
 
 def initial_theta(seed: int = 0) -> np.ndarray:

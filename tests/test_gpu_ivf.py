@@ -185,10 +185,14 @@ def test_ivf_edge_cases(pdx):
         p0 = px.ivf_probe_order(c.astype(np.float32), qr[i], 1)[0]
         m = min(64, sizes[p0])
         assert (gi[i, :m] >= 0).all() and (gi[i, m:] == -1).all()
-    # matrix-core scan: the same padding, the oracle's IVF-flat under the tie rule
+    # matrix-core scan: the same padding, the oracle's IVF-flat under the tie rule, and
+    # (reported distances use the vector scans' summation order) the same distance for an id
     g2, d2 = pdx.pdx_search_ivf(ix, _dev(q), 64, 1, eps0=float("inf"), engine=2)
     g2, d2 = _np(g2), _np(d2)
     assert np.array_equal(g2 < 0, gi < 0)
+    for i in range(q.shape[0]):
+        same = {a: b for a, b in zip(gi[i], gd[i]) if a >= 0}
+        assert all(same[a] == b for a, b in zip(g2[i], d2[i]) if a in same)
     lists = kmeans.lists_from_labels(lab, nlist)
     for i in range(q.shape[0]):
         m = int((gi[i] >= 0).sum())
@@ -212,3 +216,26 @@ def test_ivf_edge_cases(pdx):
         pdx.pdx_search_ivf(ix, _dev(q), 5, nlist + 1)
     with pytest.raises(PdxError):
         pdx.pdx_ivf_build(_dev(x), nlist, None, _dev(np.array([0, 1, 2, 3, 4, 5, 9999], np.int64)))
+
+
+def test_tuner_picks_a_measured_candidate(pdx):
+    n, d, nlist = 20_000, 128, 40
+    mix = synth.anisotropic_unit_mixture(d, 16, 21)
+    x = mix.data(n)
+    q = mix.queries(300)
+    print("tuner 20000 x 128", flush=True)
+    g, r32, xr, c, lab = _oracle_index(x, nlist, 7)
+    ix = pdx.pdx_ivf_build(_dev(x), nlist, None, None, rotation=_dev(r32), centroids=_dev(c.astype(np.float32)),
+                           assign=_dev(lab.astype(np.int32)))
+    sched, table = pdx.pdx_ivf_tune(ix, _dev(q), 10, 6, eps0=2.1, reps=2)
+    assert len(table) == 14
+    measured = [t for t in table if t["ms"] >= 0]
+    assert len(measured) == 14  # eps0 finite and d > 64: every candidate runs
+    best = min(measured, key=lambda t: t["ms"])
+    assert sched == {kk: best[kk] for kk in ("engine", "queries_per_wave", "bucket_order", "delta_d")}
+    sched_inf, table_inf = pdx.pdx_ivf_tune(ix, _dev(q), 10, 6, eps0=float("inf"), reps=1)
+    assert sum(t["ms"] >= 0 for t in table_inf) == 7 and sched_inf["delta_d"] == 0
+    # the tuned schedule is a valid search
+    ai, _ = pdx.pdx_search_ivf(ix, _dev(q), 10, 6, eps0=2.1, **sched)
+    fi, _ = pdx.pdx_search_ivf(ix, _dev(q), 10, 6, eps0=float("inf"))
+    assert exact.recall_at_k(_np(fi), _np(ai)) >= 0.97
