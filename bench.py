@@ -132,7 +132,34 @@ def build_ivf(pdx, torch, np, x_dev, nlist, seed=42, **kw):
     return ix, build_s
 
 
-def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, truth_ids, seed=42, index=None):
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def ivf_roofline(pdx, torch, ix, q_dev, k, nprobe, sched, scan_ms, profile_md=None):
+    """Roofline of the pruned bucket scan (the dominant kernel) at one
+    operating point: algorithmic flops = 2 per live (query, vector,
+    dimension) value (one multiply-add of the chunk dot product) from the
+    kernel's counters, over the scan's event-timed duration."""
+    cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+    pdx.pdx_search_ivf(ix, q_dev, k, nprobe, eps0=2.1, counters=cnt, **sched)
+    torch.cuda.synchronize()
+    c = [float(v) for v in cnt.cpu().tolist()]
+    matrix = sched.get("engine") == 2
+    flops = 2.0 * c[2]
+    achieved = flops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else 0.0
+    peak = MFMA_F32_PEAK_TFLOPS if matrix else ALU_PEAK_TFLOPS
+    traffic, src = (profiled_traffic(profile_md) if profile_md else (None, "not profiled for this workload"))
+    return {"bound": "mfma" if matrix else "alu",
+            "kernel": "ivf_mscan_kernel (matrix-core bucket scan)" if matrix else "ivf_bscan_kernel (vector ALU)",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": traffic, "traffic_source": src, "launches_per_step": 1,
+            "algorithmic_flops_per_launch": flops, "live_values_per_launch": c[2],
+            "computed_values_per_launch": c[3], "kernel_ms_per_launch": round(scan_ms, 4),
+            "issued_frac": round(2.0 * c[3] / (scan_ms * 1e-3) / 1e12 / peak, 4) if scan_ms > 0 else None}
+
+
+def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, truth_ids, seed=42, index=None,
+              profile_md=None, schedule=None):
     from oracle.exact import recall_at_k
     nq = q_dev.shape[0]
     ix, build_s = index if index is not None else build_ivf(pdx, torch, np, x_dev, nlist, seed)
@@ -141,7 +168,10 @@ def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, tr
     best = None
     for p in nprobes:
         t0 = time.perf_counter()
-        sched, _ = pdx.pdx_ivf_tune(ix, q_dev, k, p, eps0=2.1, reps=2)
+        if schedule is None:
+            sched, _ = pdx.pdx_ivf_tune(ix, q_dev, k, p, eps0=2.1, reps=2)
+        else:
+            sched = dict(schedule)
         tune_s = time.perf_counter() - t0
         ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, p, delta_d=sched["delta_d"],
                                                              queries_per_wave=sched["queries_per_wave"],
@@ -162,11 +192,13 @@ def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, tr
         sweep.append(row)
         if rec is not None and rec >= 0.95 and best is None:
             best = row
+            best["roofline"] = ivf_roofline(pdx, torch, ix, q_dev, k, p, sched, ph[1], profile_md)
     return {"nlist": nlist, "kmeans_iters": 20, "build_s": round(build_s, 2), "eps0": 2.1, "delta_d": 32,
             "list_sizes": {"min": int(sizes.min()), "median": int(np.median(sizes)), "max": int(sizes.max())},
             "sweep": sweep, "recall_queries": None if truth_ids is None else int(truth_ids.shape[0]),
             "qps_at_recall_0.95": None if best is None else best["qps"],
-            "nprobe_at_recall_0.95": None if best is None else best["nprobe"]}
+            "nprobe_at_recall_0.95": None if best is None else best["nprobe"],
+            "roofline_at_recall_0.95": None if best is None else best.pop("roofline")}
 
 
 def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu_seconds, target=0.95,
@@ -327,6 +359,11 @@ def main() -> int:
     ap.add_argument("--no-linear", action="store_true", help="skip the unpruned comparison run")
     ap.add_argument("--no-ivf", action="store_true", help="skip the IVF + ADSampling leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned early-termination leg")
+    ap.add_argument("--nprobe", type=int, nargs="*", default=None, help="IVF workloads: nprobe values to run")
+    ap.add_argument("--schedule", type=lambda v: dict(zip(("engine", "queries_per_wave", "bucket_order", "delta_d"),
+                                                         map(int, v.split(",")))),
+                    default=None, help="IVF: fixed scan schedule engine,queries_per_wave,bucket_order,delta_d "
+                                       "instead of the autotuner")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -385,14 +422,17 @@ def main() -> int:
         return 0
 
     if args.workload == "ivf_1m_d1536":
-        res = bench_ivf(pdx, torch, np, x, q, 1024, [8, 16, 32, 64], k, args.steps, args.warmup, truth)
+        sweep = args.nprobe or [8, 16, 32, 64]
+        res = bench_ivf(pdx, torch, np, x, q, 1024, sweep, k, args.steps, args.warmup, truth,
+                        profile_md="ivf_mscan_ivf_1m_d1536.md", schedule=args.schedule)
         best = res["qps_at_recall_0.95"]
+        ms = next((r["ms_per_step"] for r in res["sweep"] if r["qps"] == best), None)
         out = {"metric": METRIC, "value": best, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
-               "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+               "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "index": "ivf",
-                          "nlist": 1024, "nprobe_sweep": [8, 16, 32, 64], "exact": False},
-               "roofline": None, "cpu_baseline": cpu, "extra": {"approx": res}}
+                          "nlist": 1024, "nprobe_sweep": sweep, "exact": False},
+               "roofline": res.pop("roofline_at_recall_0.95"), "cpu_baseline": cpu, "extra": {"approx": res}}
         print(json.dumps(out), flush=True)
         return 0
 
