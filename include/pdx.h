@@ -231,6 +231,11 @@ typedef struct {
                                  exactly); 0: automatic, 2 when
                                  queries_per_wave is 0 and nq * nprobe >=
                                  8 * nlist, else 1                         */
+    int32_t bucket_split;     /* matrix cores: waves sharing one (query,
+                                 bucket) item, each scanning every split-th
+                                 vectorgroup with its own k-best list: 1, 2,
+                                 4 or 8; 0: automatic (about 8 waves per SIMD
+                                 for each phase)                           */
 } pdx_ivf_search_params;
 
 /* pdx_ivf_tune -- pick the fastest scan schedule for a workload.

@@ -617,10 +617,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.qperm = c.take<float>(q * ix->d);
     pl.slots = c.take<uint64_t>(q * pl.nslots * k);
     if (pl.use_tiles) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 256;
+        const int32_t cus = device_cus();
         pl.tile_grid = cus;  // one workgroup per compute unit (the LDS tile fills the CU)
         pl.gqueue = c.take<uint64_t>((size_t)cus * kGCap);
         pl.cand = c.take<uint64_t>(q * kCandCap);

@@ -49,11 +49,16 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
-    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
-    int32_t chunk, float eps0, unsigned long long *__restrict__ counters) {
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, float eps0,
+    unsigned long long *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
-    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int32_t k = slots.kk;
+    // wave -> (batch, part): slots.parts waves share a batch, part p scans
+    // vectorgroups p, p + parts, ... of the bucket
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t b = wid / slots.parts;
+    const int32_t part = (int32_t)(wid - b * slots.parts);
     if (b >= nbatch) return;
     const int2 mine = items[b * 16 + col];  // query slot col (same in the 4 lane rows)
     const int32_t q0 = __builtin_amdgcn_readfirstlane(mine.x);
@@ -63,7 +68,7 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     const uint32_t use = (uint32_t)(__ballot(row_ok) & 0xffffull);  // bit m: query slot m is scanned
     // items of non-finite queries get an empty list
     if (mine.x >= 0 && !row_ok && kq == 0)
-        for (int i = 0; i < k; ++i) slots[((size_t)mine.x * nprobe + mine.y) * k + i] = kEmptyKey;
+        for (int i = 0; i < k; ++i) slots.at(mine.x, mine.y, part)[i] = kEmptyKey;
     if (!use) return;
     const float *qrow = qrot + (int64_t)(row_ok ? mine.x : q0) * d;
     const float *crow = cen + (int64_t)l * d;
@@ -84,7 +89,7 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     const bool vec_ok = (d & 3) == 0;
     unsigned long long live_vals = 0, lane_vals = 0;
 
-    for (int32_t g = goff[l]; g < goff[l + 1]; ++g) {
+    for (int32_t g = goff[l] + part; g < goff[l + 1]; g += slots.parts) {
         const int4 vq = *reinterpret_cast<const int4 *>(slot_id + (int64_t)g * kGroup + 4 * col);
         const int32_t vid[4] = {vq.x, vq.y, vq.z, vq.w};
         float teff[4];
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     for (int m = 0; m < 16; ++m) {
         if (!((use >> m) & 1u)) continue;
         const int32_t qm = __builtin_amdgcn_readlane(mine.x, m), rm = __builtin_amdgcn_readlane(mine.y, m);
-        if (lane < k) slots[((size_t)qm * nprobe + rm) * k + lane] = e[m];
+        if (lane < k) slots.at(qm, rm, part)[lane] = e[m];
     }
     if (counters && lane == 0) {
         atomicAdd(counters, live_vals);
@@ -227,13 +232,13 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
 hipError_t launch_ivf_mscan(bool prune, int32_t store, const void *data, const float *scale, int32_t d,
                             const int32_t *slot_id, const int32_t *goff, const float *cen, const int2 *items,
                             int64_t nbatch, const int32_t *probe, int32_t nprobe, const float *qrot, uint32_t *tau,
-                            const int32_t *bad, uint64_t *slots, int32_t k, int32_t chunk, float eps0,
+                            const int32_t *bad, SlotMap slots, int32_t chunk, float eps0,
                             unsigned long long *counters, hipStream_t s) {
     if (nbatch <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((nbatch + 3) / 4);
+    const unsigned grid = (unsigned)((nbatch * slots.parts + 3) / 4);
 #define PDX_MSCAN(P, S)                                                                                            \
     ivf_mscan_kernel<P, S><<<grid, 256, 0, s>>>(data, scale, d, slot_id, goff, cen, items, nbatch, probe, nprobe, \
-                                                qrot, tau, bad, slots, k, chunk, eps0, counters)
+                                                qrot, tau, bad, slots, chunk, eps0, counters)
     if (prune) {
         if (store == PDX_DTYPE_BF16) PDX_MSCAN(true, PDX_DTYPE_BF16);
         else if (store == PDX_DTYPE_FP8) PDX_MSCAN(true, PDX_DTYPE_FP8);

@@ -170,8 +170,8 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nitems,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
-    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
-    int32_t chunk, float eps0, unsigned long long *__restrict__ counters, uint32_t nwg) {
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, float eps0,
+    unsigned long long *__restrict__ counters, uint32_t nwg) {
     // grid = 8 * ceil(nwg / 8): every (xcd, index) pair is launched once
     const uint32_t per_xcd = gridDim.x >> 3;
     const uint32_t wg = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -182,7 +182,8 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     const int2 item = items[it];
     const int64_t qi = item.x;
     const int32_t r = item.y;
-    uint64_t *myslot = slots + ((size_t)qi * nprobe + r) * k;
+    const int32_t k = slots.kk;
+    uint64_t *myslot = slots.at(qi, r, 0);
     if (bad[qi]) {  // non-finite query
         if (lane < k) myslot[lane] = kEmptyKey;
         return;
@@ -266,9 +267,10 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
-    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k,
-    int32_t chunk, float eps0, unsigned long long *__restrict__ counters) {
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, float eps0,
+    unsigned long long *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
+    const int32_t k = slots.kk;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= nbatch) return;
     const int2 mine = lane < QB ? items[b * QB + lane] : make_int2(-1, 0);
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
     for (int q = 0; q < QB; ++q) {
         if (qid[q] < 0) continue;
         if (bad[qid[q]]) {  // non-finite query
-            if (lane < k) slots[((size_t)qid[q] * nprobe + rk[q]) * k + lane] = kEmptyKey;
+            if (lane < k) slots.at(qid[q], rk[q], 0)[lane] = kEmptyKey;
         } else {
             use |= 1u << q;
         }
@@ -385,7 +387,7 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q)
-        if (((use >> q) & 1u) && lane < k) slots[((size_t)qid[q] * nprobe + rk[q]) * k + lane] = e[q];
+        if (((use >> q) & 1u) && lane < k) slots.at(qid[q], rk[q], 0)[lane] = e[q];
     if (counters && lane == 0) {
         atomicAdd(counters, live_vals);
         atomicAdd(counters + 1, lane_vals);
@@ -470,22 +472,27 @@ __global__ __launch_bounds__(64) void need_kernel(const int64_t *__restrict__ id
     if (lane == 0) need[qi] = mine;
 }
 
-// k-best over a query's probe slots [r0, r1); optional threshold / result
-__global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restrict__ slots, int32_t nprobe,
-                                                       int32_t r0, int32_t r1, const int32_t *__restrict__ budget,
-                                                       int32_t k, const int32_t *__restrict__ bad,
+// k-best over a query's item lists: the START lists (if use0) and the lists
+// of ranks 1 .. r1-1 (cut at the query's learned budget, if any); optional
+// threshold / result / keys.  Each run of lists is contiguous per query.
+__global__ __launch_bounds__(64) void ivf_merge_kernel(SlotMap s0, bool use0, SlotMap s1, int32_t r1,
+                                                       const int32_t *__restrict__ budget, int32_t k,
+                                                       const int32_t *__restrict__ bad,
                                                        uint32_t *__restrict__ tau,
                                                        int64_t *__restrict__ out_ids,
                                                        float *__restrict__ out_dist, uint64_t *__restrict__ keys_out) {
     const int64_t qi = blockIdx.x;
     const int lane = threadIdx.x;
     if (budget) r1 = min(r1, budget[qi]);  // ranks at or past the budget were not scanned
-    const uint64_t *base = slots + ((size_t)qi * nprobe + r0) * k;
-    const int64_t total = (int64_t)(r1 - r0) * k;
     uint64_t e = kEmptyKey, kth = kEmptyKey;
-    for (int64_t i0 = 0; i0 < total; i0 += kWave) {
-        uint64_t kk = (i0 + lane < total) ? base[i0 + lane] : kEmptyKey;
-        topk_offer(e, kth, kk, kk != kEmptyKey, k, lane);
+    for (int run = 0; run < 2; ++run) {
+        const uint64_t *base = run == 0 ? s0.at(qi, 0, 0) : s1.at(qi, 1, 0);
+        const int64_t total = run == 0 ? (use0 ? (int64_t)s0.parts * s0.kk : 0)
+                                       : (r1 > 1 ? (int64_t)(r1 - 1) * s1.parts * s1.kk : 0);
+        for (int64_t i0 = 0; i0 < total; i0 += kWave) {
+            uint64_t kk = (i0 + lane < total) ? base[i0 + lane] : kEmptyKey;
+            topk_offer(e, kth, kk, kk != kEmptyKey, k, lane);
+        }
     }
     if (tau && lane == 0 && kth != kEmptyKey) tau[qi] = (uint32_t)(kth >> 32);
     if (keys_out && lane < k) keys_out[qi * k + lane] = e;
@@ -503,47 +510,80 @@ __global__ __launch_bounds__(64) void ivf_merge_kernel(const uint64_t *__restric
     }
 }
 
-// Rerank: the r best candidates of a query by the low-precision distance
-// get their exact f32 distance from the row-major f32 copy (same chunked
-// accumulation as the f32 scan: sequential fused multiply-adds per chunk,
-// chunk sums added in order); the k best of those are the result.
 // Exact f32 distances of a query's r candidates (keys [nq][r], ordered by
 // the scanned distance) from the row-major rotated rows, then the k best by
 // (exact distance, id).  The summation order is the vector scans' (each
 // chunk of `chunk` dimensions summed sequentially, the chunk sums added in
 // order), so every engine reports the same distance for a vector.  One
-// wave per query: lane c sums chunk c, the chunk sums are added in order.
+// wave per query: lane c sums chunk c of 4 candidates at a time (loads
+// issued 8 dimensions ahead), then the chunk sums are added in order.
 __global__ __launch_bounds__(256) void rerank_kernel(const uint64_t *__restrict__ keys, int32_t r, int32_t k,
                                                      const float *__restrict__ xrow, const float *__restrict__ qrot,
                                                      int32_t d, int32_t chunk, const int32_t *__restrict__ bad,
                                                      int64_t nq, int64_t *__restrict__ out_ids,
                                                      float *__restrict__ out_dist) {
+    constexpr int U = 4;  // candidates in flight
     const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (qi >= nq) return;
     const float *qp = qrot + qi * d;
     const int32_t nch = (d + chunk - 1) / chunk;
     uint64_t mine = kEmptyKey;
-    for (int32_t i = 0; i < r; ++i) {
-        const uint64_t key = keys[qi * r + i];
-        if (key == kEmptyKey) break;  // the list is sorted: the rest is empty too
-        const uint32_t id = static_cast<uint32_t>(key & 0xffffffffu);
-        const float *x = xrow + (int64_t)id * d;
-        float partial = 0.0f;
+    for (int32_t i0 = 0; i0 < r; i0 += U) {
+        uint64_t key[U];
+        const float *x[U];
+        float partial[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            key[u] = i0 + u < r ? keys[qi * r + i0 + u] : kEmptyKey;
+            // an empty key reads row 0, whose sum is discarded
+            x[u] = xrow + (key[u] == kEmptyKey ? 0 : (int64_t)(key[u] & 0xffffffffu) * d);
+            partial[u] = 0.0f;
+        }
+        if (key[0] == kEmptyKey) break;  // the list is sorted: the rest is empty too
         for (int32_t base = 0; base < nch; base += 64) {
-            float s = 0.0f;
+            float s[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) s[u] = 0.0f;
             const int32_t c = base + lane;
             if (c < nch) {
                 const int32_t j1 = min((c + 1) * chunk, d);
-                for (int32_t j = c * chunk; j < j1; ++j) {
-                    const float t = qp[j] - x[j];
-                    s = fmaf(t, t, s);
+                int32_t j = c * chunk;
+                for (; j + 8 <= j1; j += 8) {
+                    float qv[8], xv[U][8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) qv[t] = qp[j + t];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) xv[u][t] = x[u][j + t];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) {
+                            const float dlt = qv[t] - xv[u][t];
+                            s[u] = fmaf(dlt, dlt, s[u]);
+                        }
+                }
+                for (; j < j1; ++j) {
+                    const float qv = qp[j];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const float dlt = qv - x[u][j];
+                        s[u] = fmaf(dlt, dlt, s[u]);
+                    }
                 }
             }
             const int32_t cnt = min(64, nch - base);
-            for (int32_t u = 0; u < cnt; ++u) partial += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s), u));
+            for (int32_t v = 0; v < cnt; ++v)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    partial[u] += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s[u]), v));
         }
-        if (lane == i) mine = make_key(partial, id);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (lane == i0 + u && key[u] != kEmptyKey)
+                mine = make_key(partial[u], static_cast<uint32_t>(key[u] & 0xffffffffu));
     }
     uint64_t e = kEmptyKey, kth = kEmptyKey;
     topk_offer(e, kth, mine, mine != kEmptyKey, k, lane);
@@ -619,7 +659,22 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.budget = c.take<int32_t>(q);
     pl.items0 = c.take<int2>((size_t)pl.cap0);
     pl.items1 = c.take<int2>((size_t)(pl.cap1 > 0 ? pl.cap1 : 1));
-    pl.slots = c.take<uint64_t>(q * nprobe * pl.kk);
+    {
+        // waves per item: enough waves to fill the chip (about 8 per SIMD)
+        // when a phase has few batches; matrix-core scans only
+        auto parts_for = [&](int64_t items) -> int32_t {
+            if (!pl.matrix || items <= 0) return 1;
+            if (p && p->bucket_split > 0) return p->bucket_split;
+            const int64_t batches = (items + 15) / 16, want = 8 * 4 * (int64_t)device_cus();
+            int32_t s_ = 1;
+            while (s_ < kMaxSplit && batches * s_ < want) s_ <<= 1;
+            return s_;
+        };
+        const int32_t s0 = parts_for(nq), s1 = parts_for(nq * (int64_t)(nprobe - 1));
+        pl.slots0 = SlotMap{c.take<uint64_t>(q * s0 * pl.kk), 1, 0, s0, pl.kk};
+        pl.slots1 = SlotMap{c.take<uint64_t>(q * (nprobe > 1 ? nprobe - 1 : 1) * s1 * pl.kk), nprobe - 1, 1, s1,
+                            pl.kk};
+    }
     pl.rkeys = pl.rerank > 0 ? c.take<uint64_t>(q * pl.kk) : nullptr;
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
     pl.counters = p ? p->counters : nullptr;
@@ -678,15 +733,15 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                    : static_cast<const void *>(ix->pdx);
     // `cap` item slots starting at `items`: one item per wave (qb = 1), or
     // cap / qb batches of qb items
-    auto scan = [&](bool prune, const int2 *items, int64_t cap, unsigned long long *cnt) {
+    auto scan = [&](bool prune, const int2 *items, int64_t cap, const SlotMap &sm, unsigned long long *cnt) {
         if (cap <= 0) return hipSuccess;
         if (pl.qb == 1) {
             const uint32_t nwg = (uint32_t)((cap + 3) / 4);
             const unsigned grid = 8u * ((nwg + 7u) / 8u);
 #define PDX_SCAN(P, S)                                                                                          \
     ivf_scan_kernel<P, S><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, cap,  \
-                                               pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots, pl.kk,     \
-                                               pl.chunk, pl.eps0, cnt, nwg)
+                                               pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm, pl.chunk,        \
+                                               pl.eps0, cnt, nwg)
             if (prune) {
                 if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16);
                 else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8);
@@ -702,13 +757,13 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         const int64_t nb = cap / pl.qb;
         if (pl.matrix)
             return launch_ivf_mscan(prune, pl.dtype, data, ix->fp8_scale, d, ix->slot_id, ix->list_goff,
-                                    ix->centroids, items, nb, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots,
-                                    pl.kk, pl.chunk, pl.eps0, cnt, s);
+                                    ix->centroids, items, nb, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm,
+                                    pl.chunk, pl.eps0, cnt, s);
         const unsigned grid = (unsigned)((nb + 3) / 4);
 #define PDX_BSCAN(P, S, Q)                                                                                        \
     ivf_bscan_kernel<P, S, Q><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, nb, \
-                                                   pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots, pl.kk,   \
-                                                   pl.chunk, pl.eps0, cnt)
+                                                   pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm, pl.chunk,      \
+                                                   pl.eps0, cnt)
 #define PDX_BSCAN_Q(P, S)                      \
     switch (pl.qb) {                           \
         case 2: PDX_BSCAN(P, S, 2); break;     \
@@ -729,9 +784,9 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
 #undef PDX_BSCAN
         return hipGetLastError();
     };
-    if ((e = scan(false, pl.items0, pl.cap0, pl.counters)) != hipSuccess) return e;
-    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, 1, nullptr, pl.kk, pl.bad, pl.tau, nullptr,
-                                                nullptr, nullptr);
+    if ((e = scan(false, pl.items0, pl.cap0, pl.slots0, pl.counters)) != hipSuccess) return e;
+    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots0, true, pl.slots1, 1, nullptr, pl.kk, pl.bad, pl.tau,
+                                                nullptr, nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark(1)) != hipSuccess) return e;
     // 5. learned probe budget (or the traces of its inputs), then the
@@ -752,19 +807,21 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     if (pl.trace_f && pl.nprobe == 1)
         if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(pl.trace_f), nq * kMlpIn, 0, s)) != hipSuccess) return e;
     if (pl.nprobe > 1 &&
-        (e = scan(true, pl.items1, pl.cap1, pl.counters ? pl.counters + 2 : nullptr)) != hipSuccess)
+        (e = scan(true, pl.items1, pl.cap1, pl.slots1, pl.counters ? pl.counters + 2 : nullptr)) != hipSuccess)
         return e;
     if ((e = mark(2)) != hipSuccess) return e;
     // 6. merge
     if (pl.rerank > 0) {
-        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, later ? pl.budget : nullptr,
-                                                    pl.kk, pl.bad, nullptr, nullptr, nullptr, pl.rkeys);
+        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots0, true, pl.slots1, pl.nprobe,
+                                                    later ? pl.budget : nullptr, pl.kk, pl.bad, nullptr, nullptr,
+                                                    nullptr, pl.rkeys);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         rerank_kernel<<<(unsigned)((nq + 3) / 4), 256, 0, s>>>(pl.rkeys, pl.kk, pl.k, ix->xrow, pl.qrot, d,
                                                                pl.chunk, pl.bad, nq, out_ids, out_dist);
     } else {
-        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots, pl.nprobe, 0, pl.nprobe, later ? pl.budget : nullptr,
-                                                    pl.k, pl.bad, nullptr, out_ids, out_dist, nullptr);
+        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots0, true, pl.slots1, pl.nprobe,
+                                                    later ? pl.budget : nullptr, pl.k, pl.bad, nullptr, out_ids,
+                                                    out_dist, nullptr);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (pl.trace_need) {

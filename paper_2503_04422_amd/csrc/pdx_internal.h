@@ -102,6 +102,32 @@ struct ExactPlan {
     unsigned long long *counters;    // optional [4]
 };
 
+constexpr int32_t kDefaultQueriesPerWave = 4;
+constexpr int32_t kMaxSplit = 8;
+
+// Compute units of the current device (256, the MI355X count, if the query fails).
+inline int32_t device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    return cus;
+}
+
+// Where the scans put each work item's k-best list: [nq][ranks][parts][kk]
+// keys, `parts` waves sharing one (query, rank) item (each scans every
+// parts-th vectorgroup of the bucket and keeps its own list).
+struct SlotMap {
+    uint64_t *base;
+    int32_t ranks;  // probe ranks held
+    int32_t r0;     // first rank held
+    int32_t parts;
+    int32_t kk;     // list length
+    __host__ __device__ uint64_t *at(int64_t q, int32_t r, int32_t part) const {
+        return base + (((size_t)q * ranks + (r - r0)) * parts + part) * kk;
+    }
+};
+
 struct IvfPlan {
     int64_t nq;
     int32_t k;
@@ -128,19 +154,18 @@ struct IvfPlan {
     int32_t by_size;   // lay buckets out larger first
     int64_t cap0;      // START item slots (counts rounded up to qb per bucket)
     int64_t cap1;      // item slots of ranks >= 1
-    uint64_t *slots;   // [nq][nprobe][kk]
+    SlotMap slots0;    // START lists [nq][1][s0][kk]
+    SlotMap slots1;    // lists of ranks >= 1 [nq][nprobe-1][s1][kk]
     uint64_t *rkeys;   // [nq][kk] candidates to rerank
     hipEvent_t *events;
     unsigned long long *counters;
 };
 
-constexpr int32_t kDefaultQueriesPerWave = 4;
-
 // Bucket scan of 16-query batches on the matrix cores (k_ivf_mscan.hip).
 hipError_t launch_ivf_mscan(bool prune, int32_t store, const void *data, const float *scale, int32_t d,
                             const int32_t *slot_id, const int32_t *goff, const float *cen, const int2 *items,
                             int64_t nbatch, const int32_t *probe, int32_t nprobe, const float *qrot, uint32_t *tau,
-                            const int32_t *bad, uint64_t *slots, int32_t k, int32_t chunk, float eps0,
+                            const int32_t *bad, SlotMap slots, int32_t chunk, float eps0,
                             unsigned long long *counters, hipStream_t s);
 
 // Item slots for nq queries x `ranks` probe ranks when every bucket's count

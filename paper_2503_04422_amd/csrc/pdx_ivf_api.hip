@@ -297,6 +297,11 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
         set_error("pdx_search_ivf: queries_per_wave must be 0, 1, 2, 4, 8 or 16 (got %d)", params->queries_per_wave);
         return PDX_EINVAL;
     }
+    if (params && params->bucket_split != 0 && params->bucket_split != 1 && params->bucket_split != 2 &&
+        params->bucket_split != 4 && params->bucket_split != 8) {
+        set_error("pdx_search_ivf: bucket_split must be 0, 1, 2, 4 or 8 (got %d)", params->bucket_split);
+        return PDX_EINVAL;
+    }
     if (params && (params->engine < 0 || params->engine > 2)) {
         set_error("pdx_search_ivf: engine must be 0, 1 or 2");
         return PDX_EINVAL;

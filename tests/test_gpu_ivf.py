@@ -239,3 +239,34 @@ def test_tuner_picks_a_measured_candidate(pdx):
     ai, _ = pdx.pdx_search_ivf(ix, _dev(q), 10, 6, eps0=2.1, **sched)
     fi, _ = pdx.pdx_search_ivf(ix, _dev(q), 10, 6, eps0=float("inf"))
     assert exact.recall_at_k(_np(fi), _np(ai)) >= 0.97
+
+
+def test_matrix_scan_split_is_invisible(pdx):
+    """Several waves sharing a (query, bucket) item (bucket_split) change
+    only the schedule: at eps0 = inf the result is bit-identical for every
+    split and equals the oracle's IVF-flat."""
+    n, d, nlist, k = 20_000, 128, 50, 10
+    mix = synth.anisotropic_unit_mixture(d, 32, 5)
+    x = mix.data(n)
+    q = mix.queries(60)
+    g, r32, xr, c, lab = _oracle_index(x, nlist, 11)
+    ix = pdx.pdx_ivf_build(_dev(x), nlist, None, None, rotation=_dev(r32), centroids=_dev(c.astype(np.float32)),
+                           assign=_dev(lab.astype(np.int32)))
+    qr = rotation.rotate_rows(q, r32.astype(np.float64))
+    lists = kmeans.lists_from_labels(lab, nlist)
+    for nprobe in (1, 4):
+        ref = None
+        for split in (0, 1, 2, 4, 8):
+            print(f"split {split} nprobe {nprobe}", flush=True)
+            gi, gd = (_np(t) for t in pdx.pdx_search_ivf(ix, _dev(q), k, nprobe, eps0=float("inf"), engine=2,
+                                                          bucket_split=split))
+            if ref is None:
+                ref = (gi, gd)
+                keep = [i for i in range(q.shape[0]) if not _probe_tied(c.astype(np.float32), qr[i], nprobe)]
+                want = [px.ivf_flat(xr, lists, c.astype(np.float32), qr[i], k, nprobe) for i in keep]
+                check_knn(xr, qr[keep], gi[keep], gd[keep], np.stack([w[0] for w in want]),
+                          np.stack([w[1] for w in want]))
+            else:
+                assert np.array_equal(gi, ref[0]) and np.array_equal(gd, ref[1])
+    with pytest.raises(Exception):
+        pdx.pdx_search_ivf(ix, _dev(q), k, 4, engine=2, bucket_split=3)
