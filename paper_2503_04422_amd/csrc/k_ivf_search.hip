@@ -691,7 +691,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     if ((e = mark(0)) != hipSuccess) return e;
     // 1. rotation and centroid distances
     if (ix->has_rot) {
-        if ((e = launch_pair(0, 0, q, nq, ix->rot, d, d, pl.qrot, d, nullptr, s)) != hipSuccess) return e;
+        if ((e = launch_gemm_abt(q, nq, ix->rot, d, d, pl.qrot, d, s)) != hipSuccess) return e;
     } else {
         if ((e = hipMemcpyAsync(pl.qrot, q, sizeof(float) * nq * d, hipMemcpyDeviceToDevice, s)) != hipSuccess)
             return e;

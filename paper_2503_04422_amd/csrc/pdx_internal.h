@@ -184,6 +184,9 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &plan, int
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
+// C = A B^T on the matrix cores (A [m][k], B [n][k], C [m][ldc]).
+hipError_t launch_gemm_abt(const float *A, int64_t m, const float *B, int64_t n, int32_t k, float *C, int64_t ldc,
+                           hipStream_t s);
 hipError_t launch_pair(int mode, int out, const float *A, int64_t m, const float *B, int64_t nb, int32_t k,
                        float *C, int64_t ldc, unsigned long long *best, hipStream_t s);
 hipError_t launch_qr_rotation(const double *gauss, int32_t d, double *acm, double *q, double *v, double *diag,

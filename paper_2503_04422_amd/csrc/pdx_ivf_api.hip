@@ -158,7 +158,7 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
         TRY(hipGetLastError());
     }
     if (has_rot)
-        TRY(launch_pair(0, 0, x, n, L.rot, d, d, L.xrot, d, nullptr, s));
+        TRY(launch_gemm_abt(x, n, L.rot, d, d, L.xrot, d, s));
     else
         TRY(hipMemcpyAsync(L.xrot, x, sizeof(float) * n * d, hipMemcpyDeviceToDevice, s));
     // centroids: given, or Lloyd iterations from the seed rows
