@@ -128,6 +128,14 @@ PDX_API size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, in
  * answer; partial sums are accumulated chunk by chunk in a fixed order per
  * (query, vector), so the result does not depend on scheduling.
  *
+ * index: flat (pdx_build), or IVF (pdx_ivf_build), whose rows are stored
+ * bucket by bucket.  On the bucket layout the scan still visits every
+ * vector (the answer is the exact k-NN of all n rows), but a query's own
+ * cluster arrives as whole vectorgroups, and START scans the query's
+ * nearest bucket (Section 2.1 probe order) instead of the first rows; the
+ * BOND means are those of the stored rows; a rotated index rotates the
+ * queries first and reports distances in rotated space.
+ *
  * q         [nq][d] float32 device.
  * ws        device workspace of ws_bytes >= pdx_search_exact_workspace(...).
  * out_ids   [nq][k] int64 device;  out_dist [nq][k] float32 device.

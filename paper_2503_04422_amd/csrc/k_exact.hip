@@ -140,7 +140,8 @@ __device__ __forceinline__ float chunk_sum(const float *__restrict__ gp, const i
 // One wave scans groups [g0, g1) for query qi and writes its k-best list to
 // myslot.  PRUNE: drop lanes whose partial exceeds the threshold.
 template <bool PRUNE>
-__device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t g0,
+__device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int64_t n,
+                                            const int32_t *__restrict__ slot_id, int32_t d, int32_t g0,
                                             int32_t g1, int64_t qi, const int32_t *__restrict__ perm,
                                             const float *__restrict__ qperm, uint32_t *__restrict__ tau,
                                             uint64_t *__restrict__ myslot, int32_t k, int32_t chunk,
@@ -159,7 +160,9 @@ __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int6
             tau_eff = fminf(__uint_as_float(tg), tl);
         }
         const int64_t v = (int64_t)g * kGroup + lane;
-        bool alive = v < n;
+        // row id of this slot: the slot itself (flat), or the bucket layout's table (IVF; -1 = padding)
+        const int32_t rid = slot_id ? slot_id[v] : (v < n ? (int32_t)v : -1);
+        bool alive = rid >= 0;
         const float *gp = pdxd + (int64_t)g * d * kGroup + lane;
         float partial = 0.0f;
         for (int32_t c0 = 0; c0 < d; c0 += chunk) {
@@ -174,7 +177,7 @@ __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int6
             partial += s;
             if (PRUNE) alive = alive && !(partial > tau_eff);
         }
-        topk_offer(e, kth, make_key(partial, static_cast<uint32_t>(v)), alive, k, lane);
+        topk_offer(e, kth, make_key(partial, static_cast<uint32_t>(rid)), alive, k, lane);
         if (PRUNE && kth != kEmptyKey) {
             float kt = key_dist(kth);
             if (kt < tau_eff && lane == 0) atomicMin(tau + qi, __float_as_uint(kt));
@@ -196,7 +199,8 @@ __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int6
 // ---------------------------------------------------------------------------
 template <bool PRUNE>
 __global__ __launch_bounds__(512) void scan_kernel(
-    const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t g_begin, int32_t g_end,
+    const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t g_begin,
+    int32_t g_end,
     int32_t tile_groups, int32_t ntiles, int32_t nqb, int64_t nq, int32_t qpb,
     const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t nslots, int32_t slot0,
@@ -218,13 +222,59 @@ __global__ __launch_bounds__(512) void scan_kernel(
     }
     const int32_t g0 = g_begin + tile * tile_groups;
     const int32_t g1 = min(g0 + tile_groups, g_end);
-    scan_groups<PRUNE>(pdxd, n, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
+    scan_groups<PRUNE>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
+}
+
+// Nearest bucket of each query (distances [nq][nlist]; ties to the lower
+// bucket id), one wave per query.
+__global__ __launch_bounds__(64) void nearest_kernel(const float *__restrict__ cd, int32_t nlist,
+                                                     int32_t *__restrict__ nearest) {
+    const int64_t qi = blockIdx.x;
+    const int lane = threadIdx.x;
+    uint64_t best = kEmptyKey;
+    for (int32_t l = lane; l < nlist; l += kWave) {
+        const uint64_t key = make_key(cd[qi * nlist + l], (uint32_t)l);
+        best = key < best ? key : best;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = (static_cast<uint64_t>(__shfl_xor(static_cast<uint32_t>(best >> 32), off)) << 32) |
+                           __shfl_xor(static_cast<uint32_t>(best), off);
+        best = o < best ? o : best;
+    }
+    if (lane == 0) nearest[qi] = static_cast<int32_t>(best & 0xffffffffu);
+}
+
+// START on a bucket layout (Section 4, PHASE 0 on the query's nearest
+// bucket instead of the first rows): `parts` waves per query share the
+// bucket's groups, each writing its own k-best list.
+__global__ __launch_bounds__(256) void start_bucket_kernel(
+    const float *__restrict__ pdxd, const int32_t *__restrict__ slot_id, int32_t d,
+    const int32_t *__restrict__ goff, const int32_t *__restrict__ nearest, int64_t nq, int32_t parts,
+    const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
+    const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k, int32_t chunk,
+    unsigned long long *__restrict__ counters) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t qi = w / parts;
+    const int32_t part = (int32_t)(w - qi * parts);
+    const int lane = threadIdx.x & 63;
+    if (qi >= nq) return;
+    uint64_t *myslot = slots + ((size_t)qi * parts + part) * k;
+    if (bad[qi]) {
+        if (lane < k) myslot[lane] = kEmptyKey;
+        return;
+    }
+    const int32_t l = nearest[qi];
+    const int32_t a = goff[l], len = goff[l + 1] - a;
+    const int32_t g0 = a + (int32_t)((int64_t)len * part / parts), g1 = a + (int32_t)((int64_t)len * (part + 1) / parts);
+    scan_groups<false>(pdxd, 0, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
 }
 
 // Group path for the queries whose candidate buffer overflowed in the tile
 // path: every (listed query, group tile) pair, grid-stride.
 __global__ __launch_bounds__(256) void fallback_kernel(
-    const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t g_begin, int32_t g_end, int32_t tile_groups,
+    const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t g_begin,
+    int32_t g_end, int32_t tile_groups,
     int32_t ntiles, const int32_t *__restrict__ over_list, const int32_t *__restrict__ over_count,
     const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
     uint64_t *__restrict__ slots, int32_t nslots, int32_t slot0, int32_t k, int32_t chunk) {
@@ -235,8 +285,8 @@ __global__ __launch_bounds__(256) void fallback_kernel(
         const int32_t tile = (int32_t)(it % ntiles);
         const int32_t g0 = g_begin + tile * tile_groups;
         const int32_t g1 = min(g0 + tile_groups, g_end);
-        scan_groups<true>(pdxd, n, d, g0, g1, qi, perm, qperm, tau, slots + ((size_t)qi * nslots + slot0 + tile) * k,
-                          k, chunk, nullptr);
+        scan_groups<true>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau,
+                          slots + ((size_t)qi * nslots + slot0 + tile) * k, k, chunk, nullptr);
     }
 }
 
@@ -404,8 +454,15 @@ struct FirstChunk {
     }
 };
 
+constexpr int kDense = 8;  // survivors of the first chunk from which a (query, tile) pair stays in its wave
+
+// DENSE (bucket layout, where a query's own cluster fills whole tiles): a
+// (query, tile) pair with at least kDense first-chunk survivors is finished
+// by its wave; other survivors go to the queue.
+template <bool DENSE>
 __global__ __launch_bounds__(1024) void tile_kernel(
-    const float *__restrict__ pdxd, int64_t n, int32_t d, int32_t t_begin, int32_t t_end, int64_t nq,
+    const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t t_begin,
+    int32_t t_end, int64_t nq,
     const int32_t *__restrict__ perm, const float *__restrict__ qperm, const uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, uint64_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int32_t cap,
     uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters) {
@@ -435,7 +492,8 @@ __global__ __launch_bounds__(1024) void tile_kernel(
         }
         __syncthreads();
         const int64_t vid = (int64_t)t * kTV + v;
-        const bool valid = vid < n;
+        const int32_t rid = slot_id ? slot_id[vid] : (vid < n ? (int32_t)vid : -1);  // row id (-1: padding)
+        const bool valid = rid >= 0;
 
         // Phase A: first chunk of every query, lanes = 32 vectors x 2 halves.
         // The next query's first-chunk metadata is loaded while the current
@@ -466,9 +524,45 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                     lane_vals += 64ull * 16;
                 }
                 const unsigned long long m = __ballot(alive);
-                if (m != 0) {
+                if (DENSE && m != 0 && nchunks > 1 && __popcll(m) >= kDense) {
+                    // dense pair: this wave finishes the query on the tile,
+                    // lanes = 32 vectors x 2 half-chunks as in the first chunk
+                    bool al = (m >> v) & 1ull;
+                    float p = partial;
+                    const int4 *o4 = reinterpret_cast<const int4 *>(perm + qi * d + half * 16);
+                    const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + half * 16);
+                    for (int32_t c = 1; c < nchunks; ++c) {
+                        if (!__any(al)) break;
+                        int4 oc[4];
+                        float4 qc[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            oc[u] = o4[8 * c + u];
+                            qc[u] = q4[8 * c + u];
+                        }
+                        float s2 = 0.0f;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            float t0 = qc[u].x - tile[oc[u].x * kTV + v];
+                            float t1 = qc[u].y - tile[oc[u].y * kTV + v];
+                            float t2 = qc[u].z - tile[oc[u].z * kTV + v];
+                            float t3 = qc[u].w - tile[oc[u].w * kTV + v];
+                            s2 = fmaf(t0, t0, s2);
+                            s2 = fmaf(t1, t1, s2);
+                            s2 = fmaf(t2, t2, s2);
+                            s2 = fmaf(t3, t3, s2);
+                        }
+                        p += s2 + __shfl_xor(s2, 32);  // (first 16) + (last 16), then onto the partial
+                        al = al && !(p > cur.tau);
+                        if (counters) {
+                            live_vals += 32ull * __popcll(__ballot(half == 0 && al));
+                            lane_vals += 64ull * 16;
+                        }
+                    }
+                    if (half == 0 && al) cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)rid);
+                } else if (m != 0) {
                     if (nchunks == 1) {
-                        if (alive) cand_append(cand, cand_cnt, cap, qi, partial, (uint32_t)vid);
+                        if (alive) cand_append(cand, cand_cnt, cap, qi, partial, (uint32_t)rid);
                     } else {
                         int base = 0;
                         if (lane == 0) base = atomicAdd(&qcount, __popcll(m));
@@ -494,7 +588,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                                     own = !(p > cur.tau);
                                 }
                             }
-                            if (own) cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)vid);
+                            if (own) cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)rid);
                         }
                     }
                 }
@@ -549,7 +643,8 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                 if (p > tl) {
                     act = false;
                 } else if (c == nchunks) {
-                    cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)((int64_t)t * kTV + vv));
+                    const int64_t sv = (int64_t)t * kTV + vv;
+                    cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)(slot_id ? slot_id[sv] : sv));
                     act = false;
                 }
             }
@@ -599,7 +694,10 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.chunk = (p && p->chunk > 0) ? p->chunk : 32;
     pl.tile_groups = (p && p->tile_groups > 0) ? p->tile_groups : 16;
     pl.qpb = (p && p->queries_per_block > 0) ? p->queries_per_block : 4;
-    if (pl.mode == PDX_MODE_BOND) {
+    pl.ivf = ix->kind == kIvf;
+    if (pl.ivf) {
+        pl.start_groups = 0;  // START is each query's nearest bucket
+    } else if (pl.mode == PDX_MODE_BOND) {
         int32_t sg = (ix->start_rows + kGroup - 1) / kGroup;
         pl.start_groups = sg < ix->ngroups ? sg : ix->ngroups;
     } else {
@@ -616,6 +714,13 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.perm = c.take<int32_t>(q * ix->d);
     pl.qperm = c.take<float>(q * ix->d);
     pl.slots = c.take<uint64_t>(q * pl.nslots * k);
+    if (pl.ivf) {
+        pl.start_parts = 4;
+        pl.qrot = ix->has_rot ? c.take<float>(q * ix->d) : nullptr;
+        pl.cd = pl.mode == PDX_MODE_BOND ? c.take<float>(q * ix->nlist) : nullptr;
+        pl.nearest = pl.mode == PDX_MODE_BOND ? c.take<int32_t>(q) : nullptr;
+        pl.start_slots = pl.mode == PDX_MODE_BOND ? c.take<uint64_t>(q * pl.start_parts * k) : nullptr;
+    }
     if (pl.use_tiles) {
         const int32_t cus = device_cus();
         pl.tile_grid = cus;  // one workgroup per compute unit (the LDS tile fills the CU)
@@ -639,7 +744,13 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     auto mark = [&](int i) { return pl.events ? hipEventRecord(pl.events[i], s) : hipSuccess; };
     hipError_t err;
     if ((err = mark(0)) != hipSuccess) return err;
-    prep_kernel<<<dim3((unsigned)pl.nq), dim3(256), lds, s>>>(q, d, ix->means, pl.mode, pow2, pl.perm,
+    const int32_t *sid = pl.ivf ? ix->slot_id : nullptr;  // slot -> row id on the bucket layout
+    const float *qs = q;
+    if (pl.ivf && ix->has_rot) {  // the bucket layout stores rotated rows
+        if ((err = launch_gemm_abt(q, pl.nq, ix->rot, d, d, pl.qrot, d, s)) != hipSuccess) return err;
+        qs = pl.qrot;
+    }
+    prep_kernel<<<dim3((unsigned)pl.nq), dim3(256), lds, s>>>(qs, d, ix->means, pl.mode, pow2, pl.perm,
                                                               pl.qperm, pl.tau, pl.bad);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     const int32_t nqb = (int32_t)((pl.nq + pl.qpb - 1) / pl.qpb);
@@ -647,16 +758,32 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         unsigned grid = 8u * (unsigned)((ntiles + 7) / 8) * (unsigned)nqb;
         dim3 block(64 * pl.qpb);
         if (prune)
-            scan_kernel<true><<<grid, block, 0, s>>>(ix->pdx, ix->n, d, gb, ge, pl.tile_groups, ntiles, nqb,
+            scan_kernel<true><<<grid, block, 0, s>>>(ix->pdx, ix->n, sid, d, gb, ge, pl.tile_groups, ntiles, nqb,
                                                      pl.nq, pl.qpb, pl.perm, pl.qperm, pl.tau, pl.bad,
                                                      pl.slots, pl.nslots, slot0, pl.k, pl.chunk, cnt);
         else
-            scan_kernel<false><<<grid, block, 0, s>>>(ix->pdx, ix->n, d, gb, ge, pl.tile_groups, ntiles, nqb,
+            scan_kernel<false><<<grid, block, 0, s>>>(ix->pdx, ix->n, sid, d, gb, ge, pl.tile_groups, ntiles, nqb,
                                                       pl.nq, pl.qpb, pl.perm, pl.qperm, pl.tau, pl.bad,
                                                       pl.slots, pl.nslots, slot0, pl.k, pl.chunk, cnt);
         return hipGetLastError();
     };
     const unsigned nqu = (unsigned)pl.nq;
+    if (pl.ivf && pl.mode == PDX_MODE_BOND) {
+        // START on the nearest bucket: its k-th distance is the initial
+        // threshold (its rows are found again by the main scan)
+        if ((err = launch_pair(1, 0, qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) !=
+            hipSuccess)
+            return err;
+        nearest_kernel<<<nqu, 64, 0, s>>>(pl.cd, ix->nlist, pl.nearest);
+        const int64_t waves = pl.nq * pl.start_parts;
+        start_bucket_kernel<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
+            ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest, pl.nq, pl.start_parts, pl.perm, pl.qperm, pl.tau,
+            pl.bad, pl.start_slots, pl.k, pl.chunk, pl.counters);
+        merge_kernel<<<nqu, 64, 0, s>>>(pl.start_slots, pl.start_parts, 0, pl.start_parts, pl.k, pl.bad, pl.tau,
+                                        nullptr, nullptr, nullptr, nullptr, 0);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (pl.use_tiles && (err = launch_fill_i32(pl.cand_cnt, pl.nq, 0, s)) != hipSuccess) return err;
+    }
     if (pl.tiles_start > 0) {
         // START (Section 4, PHASE 0): the first block without pruning, then
         // its k-th distance becomes the initial threshold.
@@ -681,9 +808,10 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     }
     // tile path: rounds of 32-vector tiles, threshold refreshed in between
     const size_t tile_lds = tile_lds_bytes(d);
+    const void *tk = pl.ivf ? reinterpret_cast<const void *>(tile_kernel<true>)
+                            : reinterpret_cast<const void *>(tile_kernel<false>);
     if (tile_lds > 64 * 1024) {
-        if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(tile_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds)) != hipSuccess)
+        if ((err = hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds)) != hipSuccess)
             return err;
     }
     const int32_t t0 = 2 * pl.start_groups, t1 = 2 * ix->ngroups;
@@ -693,8 +821,14 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         const int32_t b = t0 + (int32_t)((int64_t)(t1 - t0) * (r + 1) / kRounds);
         if (b <= a) continue;
         const unsigned grid = (unsigned)min(b - a, cus);
-        tile_kernel<<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, d, a, b, pl.nq, pl.perm, pl.qperm, pl.tau, pl.bad,
-                                                 pl.cand, pl.cand_cnt, kCandCap, pl.gqueue, cmain);
+        if (pl.ivf)
+            tile_kernel<true><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.perm, pl.qperm,
+                                                           pl.tau, pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue,
+                                                           cmain);
+        else
+            tile_kernel<false><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.perm, pl.qperm,
+                                                            pl.tau, pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue,
+                                                            cmain);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         if (r + 1 < kRounds) {
             cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, pl.k, pl.bad, pl.tau, nullptr, 0, 0,
@@ -705,7 +839,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     // queries whose buffer overflowed: group path over the main range
     if ((err = launch_fill_i32(pl.over_count, 1, 0, s)) != hipSuccess) return err;
     over_list_kernel<<<(nqu + 255) / 256, 256, 0, s>>>(pl.cand_cnt, pl.nq, kCandCap, pl.over_list, pl.over_count);
-    fallback_kernel<<<2048, 256, 0, s>>>(ix->pdx, ix->n, d, pl.start_groups, ix->ngroups, pl.tile_groups,
+    fallback_kernel<<<2048, 256, 0, s>>>(ix->pdx, ix->n, sid, d, pl.start_groups, ix->ngroups, pl.tile_groups,
                                          pl.tiles_main, pl.over_list, pl.over_count, pl.perm, pl.qperm, pl.tau,
                                          pl.slots, pl.nslots, pl.tiles_start, pl.k, pl.chunk);
     if ((err = hipGetLastError()) != hipSuccess) return err;

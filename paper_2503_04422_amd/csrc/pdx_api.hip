@@ -133,15 +133,15 @@ pdx_status pdx_build(const float *x, int64_t n, int32_t d, const pdx_build_param
 
 size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, int32_t k,
                                   const pdx_search_params *params) {
-    if (!index || index->kind != kFlat || nq < 0 || k < 1 || k > PDX_MAX_K) return 0;
+    if (!index || (index->kind != kFlat && index->kind != kIvf) || nq < 0 || k < 1 || k > PDX_MAX_K) return 0;
     return exact_plan(index, nq, k, params, nullptr, nullptr);
 }
 
 pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, int32_t k,
                             const pdx_search_params *params, void *ws, size_t ws_bytes,
                             int64_t *out_ids, float *out_dist, void *stream) {
-    if (!index || index->kind != kFlat) {
-        set_error("pdx_search_exact: not a flat index");
+    if (!index || (index->kind != kFlat && index->kind != kIvf)) {
+        set_error("pdx_search_exact: not an index built by pdx_build or pdx_ivf_build");
         return PDX_EINVAL;
     }
     if (nq < 0 || k < 1) {

@@ -86,6 +86,8 @@ struct ExactPlan {
     int32_t tiles_main;
     int32_t nslots;
     bool use_tiles;        // LDS tile path (else the group path only)
+    bool ivf;              // bucket layout (IVF index): rows in bucket order, ids through slot_id
+    int32_t start_parts;   // bucket layout: waves per query in START
     // workspace parts
     uint32_t *tau;
     int32_t *bad;
@@ -98,6 +100,10 @@ struct ExactPlan {
     int32_t *over_count;
     int32_t tile_grid;     // tile-path workgroups per launch
     uint64_t *gqueue;      // [tile_grid][overflow cap] survivor entries
+    float *qrot;           // bucket layout, rotated: [nq][d] rotated queries
+    float *cd;             // bucket layout: [nq][nlist] centroid distances
+    int32_t *nearest;      // bucket layout: [nq] START bucket
+    uint64_t *start_slots; // bucket layout: [nq][start_parts][k] START lists
     hipEvent_t *events;              // optional [4]
     unsigned long long *counters;    // optional [4]
 };

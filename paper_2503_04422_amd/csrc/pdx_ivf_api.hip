@@ -10,15 +10,16 @@ namespace {
 
 constexpr int32_t kMaxNlist = 4096;
 constexpr int32_t kRowsPerBlock = 1024;
+constexpr int32_t kMeanChunksIvf = 256;
 
 struct IvfLayout {
-    float *rot, *centroids, *pdx, *xrot, *fp8_scale;
+    float *rot, *centroids, *pdx, *xrot, *fp8_scale, *means;
     uint16_t *pdx16;
     uint8_t *pdx8;
     uint32_t *maxbits;
     int32_t *list_size, *list_goff, *stats, *assign, *slot_id, *cnt, *blk_cnt, *flag;
     unsigned long long *best;
-    double *sums, *acm, *qd, *v, *diag;
+    double *sums, *acm, *qd, *v, *diag, *mean_partial;
     int64_t max_groups;
     size_t bytes;
 };
@@ -38,6 +39,7 @@ IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, voi
     l.slot_id = c.take<int32_t>((size_t)l.max_groups * kGroup);
     l.pdx = c.take<float>((size_t)l.max_groups * d * kGroup);
     l.xrot = c.take<float>((size_t)n * d);  // kept: rows for the f32 rerank
+    l.means = c.take<float>(d);             // per-dimension means of the stored rows (exact search order)
     if (lowp_mask & (1 << PDX_DTYPE_BF16)) l.pdx16 = c.take<uint16_t>((size_t)l.max_groups * d * kGroup);
     if (lowp_mask & (1 << PDX_DTYPE_FP8)) {
         l.pdx8 = c.take<uint8_t>((size_t)l.max_groups * d * kGroup);
@@ -54,6 +56,7 @@ IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, voi
     l.v = c.take<double>(d);
     l.diag = c.take<double>(d);
     l.flag = c.take<int32_t>(64);
+    l.mean_partial = c.take<double>((size_t)kMeanChunksIvf * d);
     l.bytes = c.bytes();
     return l;
 }
@@ -161,6 +164,7 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
         TRY(launch_gemm_abt(x, n, L.rot, d, d, L.xrot, d, s));
     else
         TRY(hipMemcpyAsync(L.xrot, x, sizeof(float) * n * d, hipMemcpyDeviceToDevice, s));
+    TRY(launch_column_means(L.xrot, n, d, L.mean_partial, kMeanChunksIvf, L.means, s));
     // centroids: given, or Lloyd iterations from the seed rows
     if (params->centroids) {
         TRY(hipMemcpyAsync(L.centroids, params->centroids, sizeof(float) * nlist * d, hipMemcpyDeviceToDevice, s));
@@ -225,6 +229,7 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     ix->slot_id = L.slot_id;
     ix->assign = L.assign;
     ix->pdx = L.pdx;
+    ix->means = L.means;
     *out = ix;
     return PDX_OK;
 }
