@@ -6,20 +6,26 @@ skewed Gaussian mixture standing in for GIST/960), 1,000 queries, K = 10.
 
 * value: exact PDX-BOND queries per second.  One step = one
   pdx_search_exact call over the whole query batch, inputs resident in HBM:
-  query preparation (distance-to-means order), START over the first block,
-  the pruned chunked scan, the k-best merge.
-* extra.approx: IVF + ADSampling over the same vectors (nlist 1024):
-  queries per second and recall@10 per nprobe, and the throughput at the
-  smallest nprobe reaching recall@10 >= 0.95 (recall measured against the
-  FP64 oracle on the sample of queries the CPU baseline leg computes).
-* roofline: the dominant kernel (the pruned scan): algorithmic bytes (values
-  the method evaluates x 4 B, from the library's counters) over that
-  kernel's time (HIP events recorded on the search stream), against 8 TB/s.
+  query preparation (distance-to-means order), START (each query's nearest
+  bucket of the bucket layout), the pruned chunked scan over every row, the
+  k-best merge.  The rows are stored bucket by bucket (k-means, 1,024
+  buckets, built before timing); extra.flat_layout times the same search
+  over the rows in their original order (START = the first 10,000 rows).
+* extra.approx: IVF + ADSampling over the same vectors (nlist 1024, random
+  rotation): queries per second and recall@10 per nprobe (scan schedule
+  from the autotuner), and the throughput at the smallest nprobe reaching
+  recall@10 >= 0.95 (recall against the FP64 oracle on the CPU leg's
+  sample).  extra.learned_stop: plain ADSampling against the learned probe
+  budget at recall@10 >= 0.95 on 10,000 evaluation queries.
+* roofline: the dominant kernel (the LDS-tile scan, 8 launches per step):
+  algorithmic flops (3 per evaluated value, from the library's counters)
+  over its event-timed duration, against the vector-ALU ceiling.
 * cpu_baseline: the FP64 oracle timed on a bounded sample of the same
   queries with every host core.
 
 Other workloads: ``ivf_1m_d1536`` (IVF + ADSampling, 10,000 queries, value
-= queries/s at recall@10 >= 0.95), ``linear_10k_d128`` (exact linear scan).
+= queries/s at recall@10 >= 0.95, matrix-core roofline), ``lowp_5m_d768``
+(f32 / bf16 / fp8 storage), ``linear_10k_d128`` (exact linear scan).
 Prints ONE JSON line.
 """
 from __future__ import annotations
@@ -360,6 +366,9 @@ def main() -> int:
     ap.add_argument("--no-ivf", action="store_true", help="skip the IVF + ADSampling leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned early-termination leg")
     ap.add_argument("--nprobe", type=int, nargs="*", default=None, help="IVF workloads: nprobe values to run")
+    ap.add_argument("--flat", action="store_true", help="exact search on the flat layout instead of buckets")
+    ap.add_argument("--exact-nlist", type=int, default=1024, help="buckets of the exact search's layout")
+    ap.add_argument("--no-flat-ref", action="store_true", help="skip the flat-layout reference timing")
     ap.add_argument("--schedule", type=lambda v: dict(zip(("engine", "queries_per_wave", "bucket_order", "delta_d"),
                                                          map(int, v.split(",")))),
                     default=None, help="IVF: fixed scan schedule engine,queries_per_wave,bucket_order,delta_d "
@@ -437,9 +446,21 @@ def main() -> int:
         return 0
 
     mode = "linear" if args.workload == "linear_10k_d128" else "bond"
-    ix = pdx.pdx_build(x)
+    layout = "flat" if (mode == "linear" or args.flat) else "buckets"
+    build_s = None
+    if layout == "flat":
+        ix = pdx.pdx_build(x)
+    else:
+        # rows stored bucket by bucket (k-means, no rotation): a query's own
+        # cluster arrives as whole tiles; the search still visits every row
+        rng = np.random.default_rng(42)
+        init = torch.from_numpy(rng.choice(n, args.exact_nlist, replace=False).astype(np.int64)).cuda()
+        t0 = time.perf_counter()
+        ix = pdx.pdx_ivf_build(x, args.exact_nlist, None, init, kmeans_iters=20)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
     torch.cuda.synchronize()
-    print("# index built", file=sys.stderr, flush=True)
+    print(f"# index built ({layout} layout)", file=sys.stderr, flush=True)
     kw = dict(mode=mode, tile_groups=args.tile_groups, queries_per_block=args.qpb)
     ws = torch.empty(max(1, pdx.pdx_search_exact_workspace(ix, nq, k, **kw)), dtype=torch.uint8, device="cuda")
     ids = torch.empty((nq, k), dtype=torch.int64, device="cuda")
@@ -475,7 +496,7 @@ def main() -> int:
         flops = 3.0 * c[2] / launches
         launch_ms = kern_ms / launches
         achieved = flops / (launch_ms * 1e-3) / 1e12 if launch_ms > 0 else 0.0
-        traffic, traffic_src = (profiled_traffic("tile_scan_bond_1m_d960.md")
+        traffic, traffic_src = (profiled_traffic(f"tile_scan_bond_1m_d960_{layout}.md")
                                 if (args.workload, k) == ("bond_1m_d960", 10) else (None, "n/a"))
         roofline = {"bound": "alu", "kernel": "tile_kernel (pruned chunked scan, LDS tiles)",
                     "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
@@ -491,9 +512,25 @@ def main() -> int:
                     "traffic": None, "traffic_source": "not profiled for this workload",
                     "algorithmic_bytes_per_launch": scan_bytes, "kernel_ms": round(kern_ms, 4),
                     "lane_efficiency": round(c[2] / c[3], 4) if c[3] else None}
-    extra = {"phases_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
+    extra = {"layout": layout, "phases_ms": {kk: round(v, 4) for kk, v in phase_ms.items()},
              "values_evaluated": {"start": c[0], "scan": c[2],
                                   "pruning_power": round(1.0 - (c[0] + c[2]) / (nq * n * d), 5)}}
+    if layout == "buckets":
+        extra["bucket_layout"] = {"nlist": args.exact_nlist, "kmeans_iters": 20, "build_s": round(build_s, 2)}
+        if not args.no_flat_ref:  # the same search over the rows in their original order
+            fx = pdx.pdx_build(x)
+            fws = torch.empty(max(1, pdx.pdx_search_exact_workspace(fx, nq, k, mode="bond")), dtype=torch.uint8,
+                              device="cuda")
+            fout = {}
+
+            def fstep(events=None):
+                fout["r"] = pdx.pdx_search_exact(fx, q, k, mode="bond", workspace=fws, phase_events=events)
+
+            fel, _ = timed_steps(fstep, args.steps, args.warmup, torch, np)
+            same = float((fout["r"][0].cpu().numpy() == got_ids).mean())
+            extra["flat_layout"] = {"qps": round(nq * args.steps / fel, 1), "ms_per_step": round(1e3 * fel / args.steps, 3),
+                                    "ids_equal_to_bucket_layout": same}
+            del fx, fws, fout
 
     if mode == "bond" and not args.no_linear:
         lin_ws = torch.empty(max(1, pdx.pdx_search_exact_workspace(ix, nq, k, mode="linear")), dtype=torch.uint8,
@@ -527,8 +564,9 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "mode": mode,
-                   "chunk": 32, "start_rows": 10000, "exact": True},
+        "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "mode": mode, "layout": layout,
+                   "chunk": 32, "start": "first 10,000 rows" if layout == "flat" else "nearest bucket",
+                   "exact": True},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -229,12 +229,13 @@ typedef struct {
     /* Scan schedule; neither changes the exact (eps0 = INF) result.        */
     int32_t queries_per_wave; /* queries of one bucket scanned together by
                                  one wave, each loaded value reused across
-                                 them: 1, 2, 4, 8 or 16; 0 = 8              */
+                                 them: vector ALU 1, 2, 4, 8 or 16 (0 = 4);
+                                 matrix cores 16 or 32 (0 = 16)           */
     int32_t bucket_order;     /* 0: larger buckets first (their work items
                                  start first); 1: by bucket id              */
     int32_t engine;           /* 1: vector ALU (queries_per_wave);
-                                 2: matrix cores, 16 queries per wave, the
-                                 dot products of each chunk as MFMA tiles
+                                 2: matrix cores, 16 or 32 queries per wave,
+                                 the dot products of each chunk as MFMA tiles
                                  (F32: the k reported distances recomputed
                                  exactly); 0: automatic, 2 when
                                  queries_per_wave is 0 and nq * nprobe >=

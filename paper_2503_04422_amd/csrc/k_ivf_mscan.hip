@@ -44,116 +44,143 @@ __device__ __forceinline__ v4f load_quad(const void *__restrict__ data, const fl
                __builtin_amdgcn_cvt_f32_fp8(u, 2) * sc, __builtin_amdgcn_cvt_f32_fp8(u, 3) * sc};
 }
 
-template <bool PRUNE, int STORE>
-__global__ __launch_bounds__(256) void ivf_mscan_kernel(
+// One (batch, part) work unit: MT tiles of 16 queries (a batch of 16 MT
+// items) share every loaded value of the bucket; part p of the slots.parts
+// waves sharing a batch scans vectorgroups p, p + parts, ... of the bucket.
+// The queries' k-best lists live in LDS (list m, lane i = its i-th entry)
+// and are read into a register only when they get offers.
+template <bool PRUNE, int STORE, int MT>
+__device__ __forceinline__ void mscan_unit(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
-    const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t nbatch,
-    const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
-    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, float eps0,
-    unsigned long long *__restrict__ counters) {
+    const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t b,
+    int32_t part, const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, const SlotMap &slots, int32_t chunk, float eps0,
+    unsigned long long *__restrict__ counters, uint64_t (*lists)[kWave]) {
+    constexpr int NQ = 16 * MT;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
     const int32_t k = slots.kk;
-    // wave -> (batch, part): slots.parts waves share a batch, part p scans
-    // vectorgroups p, p + parts, ... of the bucket
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t b = wid / slots.parts;
-    const int32_t part = (int32_t)(wid - b * slots.parts);
-    if (b >= nbatch) return;
-    const int2 mine = items[b * 16 + col];  // query slot col (same in the 4 lane rows)
-    const int32_t q0 = __builtin_amdgcn_readfirstlane(mine.x);
+    int2 mine[MT];  // query slot 16 mt + col (same in the 4 lane rows)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) mine[mt] = items[b * NQ + 16 * mt + col];
+    const int32_t q0 = __builtin_amdgcn_readfirstlane(mine[0].x);
     if (q0 < 0) return;  // unused capacity (a batch otherwise starts with a real item)
-    const int32_t l = probe[(int64_t)q0 * nprobe + __builtin_amdgcn_readfirstlane(mine.y)];
-    bool row_ok = mine.x >= 0 && !bad[mine.x];
-    const uint32_t use = (uint32_t)(__ballot(row_ok) & 0xffffull);  // bit m: query slot m is scanned
-    // items of non-finite queries get an empty list
-    if (mine.x >= 0 && !row_ok && kq == 0)
-        for (int i = 0; i < k; ++i) slots.at(mine.x, mine.y, part)[i] = kEmptyKey;
+    const int32_t l = probe[(int64_t)q0 * nprobe + __builtin_amdgcn_readfirstlane(mine[0].y)];
+    bool row_ok[MT];
+    uint32_t use = 0;  // bit 16 mt + m: query slot m of tile mt is scanned
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        row_ok[mt] = mine[mt].x >= 0 && !bad[mine[mt].x];
+        use |= (uint32_t)(__ballot(row_ok[mt]) & 0xffffull) << (16 * mt);
+        // items of non-finite queries get an empty list
+        if (mine[mt].x >= 0 && !row_ok[mt] && kq == 0)
+            for (int i = 0; i < k; ++i) slots.at(mine[mt].x, mine[mt].y, part)[i] = kEmptyKey;
+    }
     if (!use) return;
-    const float *qrow = qrot + (int64_t)(row_ok ? mine.x : q0) * d;
+    const float *qrow[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) qrow[mt] = qrot + (int64_t)(row_ok[mt] ? mine[mt].x : q0) * d;
     const float *crow = cen + (int64_t)l * d;
     // query slots of this lane's D rows
-    int32_t rowq[4];
-    bool rowuse[4];
+    int32_t rowq[MT][4];
+    bool rowuse[MT][4];
+    float kthr[MT][4];  // k-th distance of the query in D row 4 kq + r of tile mt
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        rowq[r] = __shfl(mine.x, 4 * kq + r);
-        rowuse[r] = (use >> (4 * kq + r)) & 1u;
-    }
-    uint64_t e[16];
-    float kthr[4];  // k-th distance of the query in D row 4 * kq + r
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int m = 0; m < 16; ++m) e[m] = kEmptyKey;
+        for (int r = 0; r < 4; ++r) {
+            rowq[mt][r] = __shfl(mine[mt].x, 4 * kq + r);
+            rowuse[mt][r] = (use >> (16 * mt + 4 * kq + r)) & 1u;
+            kthr[mt][r] = INFINITY;
+        }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) kthr[r] = INFINITY;
+    for (int m = 0; m < NQ; ++m) lists[m][lane] = kEmptyKey;
     const bool vec_ok = (d & 3) == 0;
     unsigned long long live_vals = 0, lane_vals = 0;
 
     for (int32_t g = goff[l] + part; g < goff[l + 1]; g += slots.parts) {
         const int4 vq = *reinterpret_cast<const int4 *>(slot_id + (int64_t)g * kGroup + 4 * col);
         const int32_t vid[4] = {vq.x, vq.y, vq.z, vq.w};
-        float teff[4];
-        uint32_t alive = 0;  // bit 4 r + t: (row r, vector quad t) alive
+        float teff[MT][4];
+        uint32_t alive = 0;  // bit 16 mt + 4 r + t: (tile mt, row r, vector quad t) alive
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            teff[r] = INFINITY;
-            if (PRUNE && rowuse[r]) {
-                const uint32_t tg = __hip_atomic_load(tau + rowq[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                teff[r] = fminf(__uint_as_float(tg), kthr[r]);
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                teff[mt][r] = INFINITY;
+                if (PRUNE && rowuse[mt][r]) {
+                    const uint32_t tg =
+                        __hip_atomic_load(tau + rowq[mt][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    teff[mt][r] = fminf(__uint_as_float(tg), kthr[mt][r]);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (rowuse[mt][r] && vid[t] >= 0) alive |= 1u << (16 * mt + 4 * r + t);
             }
+        float part_[MT][4][4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (rowuse[r] && vid[t] >= 0) alive |= 1u << (4 * r + t);
-        }
-        float part[4][4];
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) part[r][t] = 0.0f;
+                for (int t = 0; t < 4; ++t) part_[mt][r][t] = 0.0f;
         const int64_t gbase = (int64_t)g * d;
         for (int32_t c0 = 0; c0 < d; c0 += chunk) {
-            if (PRUNE && !__any(alive != 0u)) break;
+            // tiles with a live pair (wave-uniform); the others skip their MFMAs
+            uint32_t tl = 0;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) tl |= (__ballot(((alive >> (16 * mt)) & 0xffffu) != 0u) ? 1u : 0u) << mt;
+            if (PRUNE && !tl) break;
             const int32_t c1 = min(c0 + chunk, d);
-            if (counters) {  // live (query, vector) pairs, and the 1024 pairs the MFMAs compute
+            if (counters) {  // live (query, vector) pairs, and the pairs the MFMAs compute
                 int pairs = __popc(alive);
 #pragma unroll
                 for (int off = 1; off < 64; off <<= 1) pairs += __shfl_xor(pairs, off);
                 live_vals += (unsigned long long)pairs * (c1 - c0);
-                lane_vals += 1024ull * (c1 - c0);
+                lane_vals += 1024ull * __popc(tl) * (c1 - c0);
             }
-            v4f acc[4];
+            v4f acc[MT][4];
+            float qq[MT];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            float qq = 0.0f;
+            for (int mt = 0; mt < MT; ++mt) {
+                qq[mt] = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[mt][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            }
             float xx[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             for (int32_t j0 = c0; j0 < c1; j0 += 32) {
                 const int32_t jl = j0 + 8 * kq;  // this lane's first dimension of the sub-chunk
-                float cv[8], a[8];
+                float cv[8], a[MT][8];
                 v4f bx[8];
                 if (j0 + 32 <= c1 && vec_ok && (j0 & 3) == 0) {
-                    const v4f c_lo = *reinterpret_cast<const v4f *>(crow + jl);
-                    const v4f c_hi = *reinterpret_cast<const v4f *>(crow + jl + 4);
-                    const v4f q_lo = *reinterpret_cast<const v4f *>(qrow + jl);
-                    const v4f q_hi = *reinterpret_cast<const v4f *>(qrow + jl + 4);
 #pragma unroll
                     for (int s = 0; s < 8; ++s)
                         bx[s] = load_quad<STORE>(pdxd, scale, (gbase + jl + s) * kGroup + 4 * col, jl + s);
+                    const v4f c_lo = *reinterpret_cast<const v4f *>(crow + jl);
+                    const v4f c_hi = *reinterpret_cast<const v4f *>(crow + jl + 4);
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
                         cv[s] = c_lo[s];
                         cv[s + 4] = c_hi[s];
-                        a[s] = q_lo[s];
-                        a[s + 4] = q_hi[s];
                     }
 #pragma unroll
-                    for (int s = 0; s < 8; ++s) a[s] = row_ok ? a[s] - cv[s] : 0.0f;
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const v4f q_lo = *reinterpret_cast<const v4f *>(qrow[mt] + jl);
+                        const v4f q_hi = *reinterpret_cast<const v4f *>(qrow[mt] + jl + 4);
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            a[mt][s] = row_ok[mt] ? q_lo[s] - cv[s] : 0.0f;
+                            a[mt][s + 4] = row_ok[mt] ? q_hi[s] - cv[s + 4] : 0.0f;
+                        }
+                    }
                 } else {
 #pragma unroll
                     for (int s = 0; s < 8; ++s) {
                         const int32_t j = jl + s;
                         const bool ok = j < c1;
                         cv[s] = ok ? crow[j] : 0.0f;
-                        a[s] = (ok && row_ok) ? qrow[j] - cv[s] : 0.0f;
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) a[mt][s] = (ok && row_ok[mt]) ? qrow[mt][j] - cv[s] : 0.0f;
                         bx[s] = ok ? load_quad<STORE>(pdxd, scale, (gbase + j) * kGroup + 4 * col, j)
                                    : v4f{cv[s], cv[s], cv[s], cv[s]};
                     }
@@ -161,17 +188,19 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
                     const v4f bs = bx[s] - cv[s];
-                    qq = fmaf(a[s], a[s], qq);
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        xx[t] = fmaf(bs[t], bs[t], xx[t]);
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bs[t], acc[t], 0, 0, 0);
+                    for (int t = 0; t < 4; ++t) xx[t] = fmaf(bs[t], bs[t], xx[t]);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        if (!((tl >> mt) & 1u)) continue;
+                        qq[mt] = fmaf(a[mt][s], a[mt][s], qq[mt]);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt][s], bs[t], acc[mt][t], 0, 0, 0);
                     }
                 }
             }
-            // |a|^2 per query slot and |b|^2 per vector over the chunk: sum the 4 k rows
-            qq += __shfl_xor(qq, 16);
-            qq += __shfl_xor(qq, 32);
+            // |b|^2 per vector and |a|^2 per query slot over the chunk: sum the 4 k rows
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 xx[t] += __shfl_xor(xx[t], 16);
@@ -184,42 +213,58 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
                 fac = (dc / (float)d) * f * f;
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float qn = __shfl(qq, 4 * kq + r);
+            for (int mt = 0; mt < MT; ++mt) {
+                if (!((tl >> mt) & 1u)) continue;
+                qq[mt] += __shfl_xor(qq[mt], 16);
+                qq[mt] += __shfl_xor(qq[mt], 32);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    part[r][t] += fmaxf(qn + xx[t] - 2.0f * acc[t][r], 0.0f);
-                    // ADSampling test after c1 of d dimensions (exact at c1 = d)
-                    if (PRUNE && part[r][t] > teff[r] * fac) alive &= ~(1u << (4 * r + t));
+                for (int r = 0; r < 4; ++r) {
+                    const float qn = __shfl(qq[mt], 4 * kq + r);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        part_[mt][r][t] += fmaxf(qn + xx[t] - 2.0f * acc[mt][t][r], 0.0f);
+                        // ADSampling test after c1 of d dimensions (exact at c1 = d)
+                        if (PRUNE && part_[mt][r][t] > teff[mt][r] * fac) alive &= ~(1u << (16 * mt + 4 * r + t));
+                    }
                 }
             }
         }
         // survivors enter their query's k-best list
         if (__any(alive != 0u)) {
 #pragma unroll
-            for (int m = 0; m < 16; ++m) {
+            for (int m = 0; m < NQ; ++m) {
                 if (!((use >> m) & 1u)) continue;
-                const int r = m & 3;
-                const bool myrow = kq == (m >> 2);
-                uint64_t kth = readlane64(e[m], k - 1);
+                const int mt = m >> 4, mm = m & 15;
+                const int r = mm & 3;
+                const bool myrow = kq == (mm >> 2);
+                unsigned long long any = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) any |= __ballot(myrow && ((alive >> (16 * mt + 4 * r + t)) & 1u));
+                if (!any) continue;
+                uint64_t em = lists[m][lane];
+                uint64_t kth = readlane64(em, k - 1);
                 const uint64_t before = kth;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const bool want = myrow && ((alive >> (4 * r + t)) & 1u);
-                    if (__ballot(want)) topk_offer(e[m], kth, make_key(part[r][t], (uint32_t)vid[t]), want, k, lane);
+                    const bool want = myrow && ((alive >> (16 * mt + 4 * r + t)) & 1u);
+                    if (__ballot(want))
+                        topk_offer(em, kth, make_key(part_[mt][r][t], (uint32_t)vid[t]), want, k, lane);
                 }
+                lists[m][lane] = em;
                 if (kth != before) {
-                    if (myrow) kthr[r] = key_dist(kth);
-                    if (PRUNE && lane == 0) atomicMin(tau + __builtin_amdgcn_readlane(mine.x, m), (uint32_t)(kth >> 32));
+                    if (myrow) kthr[mt][r] = key_dist(kth);
+                    if (PRUNE && lane == 0)
+                        atomicMin(tau + __builtin_amdgcn_readlane(mine[mt].x, mm), (uint32_t)(kth >> 32));
                 }
             }
         }
     }
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < NQ; ++m) {
         if (!((use >> m) & 1u)) continue;
-        const int32_t qm = __builtin_amdgcn_readlane(mine.x, m), rm = __builtin_amdgcn_readlane(mine.y, m);
-        if (lane < k) slots.at(qm, rm, part)[lane] = e[m];
+        const int mt = m >> 4, mm = m & 15;
+        const int32_t qm = __builtin_amdgcn_readlane(mine[mt].x, mm), rm = __builtin_amdgcn_readlane(mine[mt].y, mm);
+        if (lane < k) slots.at(qm, rm, part)[lane] = lists[m][lane];
     }
     if (counters && lane == 0) {
         atomicAdd(counters, live_vals);
@@ -227,27 +272,66 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     }
 }
 
+// Work units of XCD x (blockIdx.x % 8; workgroups are dealt to the XCDs
+// round-robin) are the batches in [xcd_range[x], xcd_range[x + 1]) / 16 MT:
+// all batches of a bucket run on one XCD and share its L2.  Each wave
+// strides over its XCD's units.  Without xcd_range: unit = global wave index.
+template <bool PRUNE, int STORE, int MT>
+__global__ __launch_bounds__(256) void ivf_mscan_kernel(
+    const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
+    const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t nbatch,
+    const int32_t *__restrict__ xcd_range, const int32_t *__restrict__ probe, int32_t nprobe,
+    const float *__restrict__ qrot, uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots,
+    int32_t chunk, float eps0, unsigned long long *__restrict__ counters) {
+    __shared__ uint64_t lists[4][16 * MT][kWave];
+    const int wave = threadIdx.x >> 6;
+    const int64_t parts = slots.parts;
+    if (!xcd_range) {
+        const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
+        const int64_t b = wid / parts;
+        if (b < nbatch)
+            mscan_unit<PRUNE, STORE, MT>(pdxd, scale, d, slot_id, goff, cen, items, b, (int32_t)(wid - b * parts),
+                                         probe, nprobe, qrot, tau, bad, slots, chunk, eps0, counters, lists[wave]);
+        return;
+    }
+    const int32_t x = blockIdx.x & 7;
+    const int64_t b0 = xcd_range[x] / (16 * MT), nb = xcd_range[x + 1] / (16 * MT) - b0;
+    const int64_t stride = (int64_t)(gridDim.x >> 3) * 4;
+    for (int64_t w = (int64_t)(blockIdx.x >> 3) * 4 + wave; w < nb * parts; w += stride) {
+        const int64_t b = w / parts;
+        mscan_unit<PRUNE, STORE, MT>(pdxd, scale, d, slot_id, goff, cen, items, b0 + b, (int32_t)(w - b * parts),
+                                     probe, nprobe, qrot, tau, bad, slots, chunk, eps0, counters, lists[wave]);
+    }
+}
+
 }  // namespace
 
-hipError_t launch_ivf_mscan(bool prune, int32_t store, const void *data, const float *scale, int32_t d,
-                            const int32_t *slot_id, const int32_t *goff, const float *cen, const int2 *items,
-                            int64_t nbatch, const int32_t *probe, int32_t nprobe, const float *qrot, uint32_t *tau,
-                            const int32_t *bad, SlotMap slots, int32_t chunk, float eps0,
-                            unsigned long long *counters, hipStream_t s) {
+hipError_t launch_ivf_mscan(bool prune, int32_t store, int32_t tiles, const void *data, const float *scale,
+                            int32_t d, const int32_t *slot_id, const int32_t *goff, const float *cen,
+                            const int2 *items, int64_t nbatch, const int32_t *xcd_range, const int32_t *probe,
+                            int32_t nprobe, const float *qrot, uint32_t *tau, const int32_t *bad, SlotMap slots,
+                            int32_t chunk, float eps0, unsigned long long *counters, hipStream_t s) {
     if (nbatch <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((nbatch * slots.parts + 3) / 4);
-#define PDX_MSCAN(P, S)                                                                                            \
-    ivf_mscan_kernel<P, S><<<grid, 256, 0, s>>>(data, scale, d, slot_id, goff, cen, items, nbatch, probe, nprobe, \
-                                                qrot, tau, bad, slots, chunk, eps0, counters)
+    // one wave per unit, or (XCD ranges) 8 equal sets of workgroups, an
+    // eighth of the units each plus slack for uneven ranges
+    const int64_t units = nbatch * slots.parts;
+    const unsigned grid = xcd_range ? 8u * (unsigned)((units / 8 + 3) / 4 + 64) : (unsigned)((units + 3) / 4);
+#define PDX_MSCAN(P, S, M)                                                                                          \
+    ivf_mscan_kernel<P, S, M><<<grid, 256, 0, s>>>(data, scale, d, slot_id, goff, cen, items, nbatch, xcd_range,  \
+                                                   probe, nprobe, qrot, tau, bad, slots, chunk, eps0, counters)
+#define PDX_MSCAN_T(P, S)          \
+    if (tiles == 2) PDX_MSCAN(P, S, 2); \
+    else PDX_MSCAN(P, S, 1);
     if (prune) {
-        if (store == PDX_DTYPE_BF16) PDX_MSCAN(true, PDX_DTYPE_BF16);
-        else if (store == PDX_DTYPE_FP8) PDX_MSCAN(true, PDX_DTYPE_FP8);
-        else PDX_MSCAN(true, PDX_DTYPE_F32);
+        if (store == PDX_DTYPE_BF16) { PDX_MSCAN_T(true, PDX_DTYPE_BF16) }
+        else if (store == PDX_DTYPE_FP8) { PDX_MSCAN_T(true, PDX_DTYPE_FP8) }
+        else { PDX_MSCAN_T(true, PDX_DTYPE_F32) }
     } else {
-        if (store == PDX_DTYPE_BF16) PDX_MSCAN(false, PDX_DTYPE_BF16);
-        else if (store == PDX_DTYPE_FP8) PDX_MSCAN(false, PDX_DTYPE_FP8);
-        else PDX_MSCAN(false, PDX_DTYPE_F32);
+        if (store == PDX_DTYPE_BF16) { PDX_MSCAN_T(false, PDX_DTYPE_BF16) }
+        else if (store == PDX_DTYPE_FP8) { PDX_MSCAN_T(false, PDX_DTYPE_FP8) }
+        else { PDX_MSCAN_T(false, PDX_DTYPE_F32) }
     }
+#undef PDX_MSCAN_T
 #undef PDX_MSCAN
     return hipGetLastError();
 }

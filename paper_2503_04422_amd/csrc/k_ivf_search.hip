@@ -86,14 +86,22 @@ __global__ void item_count_kernel(const int32_t *__restrict__ probe, int64_t nq,
 // bucket (the rounding slots stay padding, query id -1).  Buckets are laid
 // out by id, or larger first so their long batches start early and the
 // launch drains evenly; keys (size descending, id) are sorted in LDS.
-__global__ __launch_bounds__(1024) void batch_prefix_kernel(int32_t *__restrict__ cnt0, int32_t *__restrict__ cnt1,
-                                                            int32_t nlist, int32_t pow2,
-                                                            const int32_t *__restrict__ list_size, int32_t qb,
+// With xcd (non-null, 9 entries), the buckets are dealt to
+// the 8 XCDs round-robin in that order and laid out XCD by XCD; xcd[x] is
+// the first item of XCD x's range and xcd[8] the end, so a scan can keep
+// every batch of a bucket on one XCD (one L2).
+__global__ __launch_bounds__(1024) void batch_prefix_kernel(int32_t *__restrict__ cnt0, int32_t qb0,
+                                                            int32_t *__restrict__ xcd0, int32_t *__restrict__ cnt1,
+                                                            int32_t qb1, int32_t *__restrict__ xcd1, int32_t nlist,
+                                                            int32_t pow2, const int32_t *__restrict__ list_size,
                                                             int32_t by_size) {
-    extern __shared__ uint64_t order[];  // pow2 keys
+    extern __shared__ uint64_t order[];  // pow2 keys, then (xcd layout) nlist bucket ids
     __shared__ int32_t part[1024];
     __shared__ int32_t carry;
     int32_t *cnt = blockIdx.x == 0 ? cnt0 : cnt1;
+    const int32_t qb = blockIdx.x == 0 ? qb0 : qb1;
+    int32_t *xcd = blockIdx.x == 0 ? xcd0 : xcd1;
+    int32_t *lay = reinterpret_cast<int32_t *>(order + pow2);
     for (int32_t l = threadIdx.x; l < pow2; l += blockDim.x) {
         uint64_t key = kEmptyKey;
         if (l < nlist)
@@ -119,9 +127,20 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(int32_t *__restrict_
                 }
                 __syncthreads();
             }
+    // bucket at layout position i
+    auto base_of = [&](int32_t x) {  // first layout position of XCD x: sum of the earlier XCDs' shares
+        int32_t b = 0;
+        for (int32_t y = 0; y < x; ++y) b += (nlist - y + 7) / 8;
+        return b;
+    };
+    if (xcd) {
+        for (int32_t p = threadIdx.x; p < nlist; p += blockDim.x)
+            lay[base_of(p & 7) + (p >> 3)] = (int32_t)(order[p] & 0xffffffffu);
+        __syncthreads();
+    }
     for (int32_t i0 = 0; i0 < nlist; i0 += 1024) {
         const int32_t i = i0 + threadIdx.x;
-        const int32_t l = i < nlist ? (int32_t)(order[i] & 0xffffffffu) : -1;
+        const int32_t l = i < nlist ? (xcd ? lay[i] : (int32_t)(order[i] & 0xffffffffu)) : -1;
         const int32_t c = l >= 0 ? (cnt[l] + qb - 1) / qb * qb : 0;
         part[threadIdx.x] = c;
         __syncthreads();
@@ -135,6 +154,10 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(int32_t *__restrict_
         __syncthreads();
         if (threadIdx.x == 1023) carry += part[1023];
         __syncthreads();
+    }
+    if (xcd && threadIdx.x < 9) {
+        const int32_t b = base_of(threadIdx.x);
+        xcd[threadIdx.x] = (threadIdx.x < 8 && b < nlist) ? cnt[lay[b]] : carry;
     }
 }
 
@@ -641,10 +664,18 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         th = fminf(fmaxf(th, 1e-7f), 1.0f - 1e-7f);
         pl.zthr = logf(th / (1.0f - th));
     }
-    pl.qb = pl.matrix ? 16 : (p && p->queries_per_wave > 0) ? p->queries_per_wave : kDefaultQueriesPerWave;
+    if (pl.matrix) {
+        // 16 queries per MFMA tile; two tiles per wave on request (each
+        // loaded value then serves 32 queries, but the wave needs about
+        // 330 registers: one wave per SIMD)
+        const int32_t tiles = (p && p->queries_per_wave == 32) ? 2 : 1;
+        pl.qb0 = pl.qb1 = 16 * tiles;
+    } else {
+        pl.qb0 = pl.qb1 = (p && p->queries_per_wave > 0) ? p->queries_per_wave : kDefaultQueriesPerWave;
+    }
     pl.by_size = !(p && p->bucket_order == 1);
-    pl.cap0 = ivf_item_capacity(nq, 1, pl.qb, ix->nlist);
-    pl.cap1 = ivf_item_capacity(nq, nprobe - 1, pl.qb, ix->nlist);
+    pl.cap0 = ivf_item_capacity(nq, 1, pl.qb0, ix->nlist);
+    pl.cap1 = ivf_item_capacity(nq, nprobe - 1, pl.qb1, ix->nlist);
     int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
     pl.chunk = dd;
     size_t q = (size_t)(nq > 0 ? nq : 0);
@@ -657,20 +688,21 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.cnt0 = c.take<int32_t>(ix->nlist);
     pl.cnt1 = c.take<int32_t>(ix->nlist);
     pl.budget = c.take<int32_t>(q);
+    pl.xcd = pl.matrix ? c.take<int32_t>(18) : nullptr;  // XCD ranges of the START and later-rank items
     pl.items0 = c.take<int2>((size_t)pl.cap0);
     pl.items1 = c.take<int2>((size_t)(pl.cap1 > 0 ? pl.cap1 : 1));
     {
         // waves per item: enough waves to fill the chip (about 8 per SIMD)
         // when a phase has few batches; matrix-core scans only
-        auto parts_for = [&](int64_t items) -> int32_t {
+        auto parts_for = [&](int64_t items, int32_t qb_phase) -> int32_t {
             if (!pl.matrix || items <= 0) return 1;
             if (p && p->bucket_split > 0) return p->bucket_split;
-            const int64_t batches = (items + 15) / 16, want = 8 * 4 * (int64_t)device_cus();
+            const int64_t batches = (items + 15) / 16 / (qb_phase / 16), want = 8 * 4 * (int64_t)device_cus();
             int32_t s_ = 1;
             while (s_ < kMaxSplit && batches * s_ < want) s_ <<= 1;
             return s_;
         };
-        const int32_t s0 = parts_for(nq), s1 = parts_for(nq * (int64_t)(nprobe - 1));
+        const int32_t s0 = parts_for(nq, pl.qb0), s1 = parts_for(nq * (int64_t)(nprobe - 1), pl.qb1);
         pl.slots0 = SlotMap{c.take<uint64_t>(q * s0 * pl.kk), 1, 0, s0, pl.kk};
         pl.slots1 = SlotMap{c.take<uint64_t>(q * (nprobe > 1 ? nprobe - 1 : 1) * s1 * pl.kk), nprobe - 1, 1, s1,
                             pl.kk};
@@ -708,11 +740,12 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     if ((e = launch_fill_i32(pl.cnt0, ix->nlist, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(pl.cnt1, ix->nlist, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(pl.budget, nq, pl.nprobe, s)) != hipSuccess) return e;
-    if (pl.qb > 1) {  // padding slots: query id -1
+    {  // padding slots: query id -1
         const unsigned long long pad = 0x00000000ffffffffull;
-        if ((e = launch_fill_u64(reinterpret_cast<unsigned long long *>(pl.items0), pl.cap0, pad, s)) != hipSuccess)
+        if (pl.qb0 > 1 &&
+            (e = launch_fill_u64(reinterpret_cast<unsigned long long *>(pl.items0), pl.cap0, pad, s)) != hipSuccess)
             return e;
-        if (pl.cap1 > 0 &&
+        if (pl.qb1 > 1 && pl.cap1 > 0 &&
             (e = launch_fill_u64(reinterpret_cast<unsigned long long *>(pl.items1), pl.cap1, pad, s)) != hipSuccess)
             return e;
     }
@@ -722,8 +755,9 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     const bool later = pl.w16 != nullptr;
     const int32_t rhi0 = later ? 1 : pl.nprobe;
     item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 0, rhi0, nullptr, pl.cnt0, pl.cnt1);
-    batch_prefix_kernel<<<later ? 1 : 2, 1024, pow2 * sizeof(uint64_t), s>>>(pl.cnt0, pl.cnt1, ix->nlist, pow2,
-                                                                             ix->list_size, pl.qb, pl.by_size);
+    batch_prefix_kernel<<<later ? 1 : 2, 1024, pow2 * sizeof(uint64_t) + ix->nlist * sizeof(int32_t), s>>>(
+        pl.cnt0, pl.qb0, pl.xcd, pl.cnt1, pl.qb1, pl.xcd ? pl.xcd + 9 : nullptr, ix->nlist, pow2, ix->list_size,
+        pl.by_size);
     item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 0, rhi0, nullptr, pl.cnt0, pl.cnt1, pl.items0,
                                           pl.items1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -733,9 +767,10 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                    : static_cast<const void *>(ix->pdx);
     // `cap` item slots starting at `items`: one item per wave (qb = 1), or
     // cap / qb batches of qb items
-    auto scan = [&](bool prune, const int2 *items, int64_t cap, const SlotMap &sm, unsigned long long *cnt) {
+    auto scan = [&](bool prune, const int2 *items, int64_t cap, int32_t qb, const SlotMap &sm,
+                    unsigned long long *cnt, const int32_t *xr) {
         if (cap <= 0) return hipSuccess;
-        if (pl.qb == 1) {
+        if (qb == 1) {
             const uint32_t nwg = (uint32_t)((cap + 3) / 4);
             const unsigned grid = 8u * ((nwg + 7u) / 8u);
 #define PDX_SCAN(P, S)                                                                                          \
@@ -754,10 +789,10 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
 #undef PDX_SCAN
             return hipGetLastError();
         }
-        const int64_t nb = cap / pl.qb;
+        const int64_t nb = cap / qb;
         if (pl.matrix)
-            return launch_ivf_mscan(prune, pl.dtype, data, ix->fp8_scale, d, ix->slot_id, ix->list_goff,
-                                    ix->centroids, items, nb, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm,
+            return launch_ivf_mscan(prune, pl.dtype, qb / 16, data, ix->fp8_scale, d, ix->slot_id, ix->list_goff,
+                                    ix->centroids, items, nb, xr, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm,
                                     pl.chunk, pl.eps0, cnt, s);
         const unsigned grid = (unsigned)((nb + 3) / 4);
 #define PDX_BSCAN(P, S, Q)                                                                                        \
@@ -765,7 +800,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                    pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm, pl.chunk,      \
                                                    pl.eps0, cnt)
 #define PDX_BSCAN_Q(P, S)                      \
-    switch (pl.qb) {                           \
+    switch (qb) {                              \
         case 2: PDX_BSCAN(P, S, 2); break;     \
         case 4: PDX_BSCAN(P, S, 4); break;     \
         case 8: PDX_BSCAN(P, S, 8); break;     \
@@ -784,7 +819,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
 #undef PDX_BSCAN
         return hipGetLastError();
     };
-    if ((e = scan(false, pl.items0, pl.cap0, pl.slots0, pl.counters)) != hipSuccess) return e;
+    if ((e = scan(false, pl.items0, pl.cap0, pl.qb0, pl.slots0, pl.counters, pl.xcd)) != hipSuccess) return e;
     ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots0, true, pl.slots1, 1, nullptr, pl.kk, pl.bad, pl.tau,
                                                 nullptr, nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -798,8 +833,9 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     }
     if (later) {  // items of ranks 1 .. budget - 1
         item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 1, pl.nprobe, pl.budget, pl.cnt0, pl.cnt1);
-        batch_prefix_kernel<<<1, 1024, pow2 * sizeof(uint64_t), s>>>(pl.cnt1, nullptr, ix->nlist, pow2,
-                                                                     ix->list_size, pl.qb, pl.by_size);
+        batch_prefix_kernel<<<1, 1024, pow2 * sizeof(uint64_t) + ix->nlist * sizeof(int32_t), s>>>(
+            pl.cnt1, pl.qb1, pl.xcd ? pl.xcd + 9 : nullptr, nullptr, 0, nullptr, ix->nlist, pow2, ix->list_size,
+            pl.by_size);
         item_scatter_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 1, pl.nprobe, pl.budget, pl.cnt0, pl.cnt1,
                                               pl.items0, pl.items1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -807,7 +843,8 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     if (pl.trace_f && pl.nprobe == 1)
         if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(pl.trace_f), nq * kMlpIn, 0, s)) != hipSuccess) return e;
     if (pl.nprobe > 1 &&
-        (e = scan(true, pl.items1, pl.cap1, pl.slots1, pl.counters ? pl.counters + 2 : nullptr)) != hipSuccess)
+        (e = scan(true, pl.items1, pl.cap1, pl.qb1, pl.slots1, pl.counters ? pl.counters + 2 : nullptr,
+                  pl.xcd ? pl.xcd + 9 : nullptr)) != hipSuccess)
         return e;
     if ((e = mark(2)) != hipSuccess) return e;
     // 6. merge

@@ -151,12 +151,13 @@ struct IvfPlan {
     int32_t *cnt0, *cnt1;  // [nlist] item cursors
     int2 *items0, *items1;
     int32_t *budget;   // [nq] buckets the query probes (learned; else nprobe)
+    int32_t *xcd;      // matrix engine: [2][9] item ranges per XCD (START, later ranks)
     const __half *w16; // network weights (null: plain search)
     float zthr;        // stop when the logit exceeds this
     float *trace_f;
     int32_t *trace_need;
     int32_t matrix;    // bucket scan on the matrix cores (16 queries per wave)
-    int32_t qb;        // queries per wave in the bucket scan
+    int32_t qb0, qb1;  // queries per wave in the START / later bucket scans
     int32_t by_size;   // lay buckets out larger first
     int64_t cap0;      // START item slots (counts rounded up to qb per bucket)
     int64_t cap1;      // item slots of ranks >= 1
@@ -167,12 +168,13 @@ struct IvfPlan {
     unsigned long long *counters;
 };
 
-// Bucket scan of 16-query batches on the matrix cores (k_ivf_mscan.hip).
-hipError_t launch_ivf_mscan(bool prune, int32_t store, const void *data, const float *scale, int32_t d,
-                            const int32_t *slot_id, const int32_t *goff, const float *cen, const int2 *items,
-                            int64_t nbatch, const int32_t *probe, int32_t nprobe, const float *qrot, uint32_t *tau,
-                            const int32_t *bad, SlotMap slots, int32_t chunk, float eps0,
-                            unsigned long long *counters, hipStream_t s);
+// Bucket scan on the matrix cores (k_ivf_mscan.hip): batches of 16 * tiles
+// queries (tiles = 1 or 2) per wave.
+hipError_t launch_ivf_mscan(bool prune, int32_t store, int32_t tiles, const void *data, const float *scale,
+                            int32_t d, const int32_t *slot_id, const int32_t *goff, const float *cen,
+                            const int2 *items, int64_t nbatch, const int32_t *xcd_range, const int32_t *probe,
+                            int32_t nprobe, const float *qrot, uint32_t *tau, const int32_t *bad, SlotMap slots,
+                            int32_t chunk, float eps0, unsigned long long *counters, hipStream_t s);
 
 // Item slots for nq queries x `ranks` probe ranks when every bucket's count
 // is rounded up to a multiple of qb (at most qb - 1 padding slots per bucket).

@@ -298,8 +298,10 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
         return PDX_EINVAL;
     }
     if (params && params->queries_per_wave != 0 && params->queries_per_wave != 1 && params->queries_per_wave != 2 &&
-        params->queries_per_wave != 4 && params->queries_per_wave != 8 && params->queries_per_wave != 16) {
-        set_error("pdx_search_ivf: queries_per_wave must be 0, 1, 2, 4, 8 or 16 (got %d)", params->queries_per_wave);
+        params->queries_per_wave != 4 && params->queries_per_wave != 8 && params->queries_per_wave != 16 &&
+        !(params->queries_per_wave == 32 && params->engine == 2)) {
+        set_error("pdx_search_ivf: queries_per_wave must be 0, 1, 2, 4, 8, 16 (or 32 with engine 2), got %d",
+                  params->queries_per_wave);
         return PDX_EINVAL;
     }
     if (params && params->bucket_split != 0 && params->bucket_split != 1 && params->bucket_split != 2 &&

@@ -94,6 +94,7 @@ def test_kmeans_build_invariants(pdx):
 @pytest.mark.parametrize("n,d,nlist,k,qpw,order,engine", [
     (20_000, 128, 50, 10, 0, 0, 0), (20_000, 128, 50, 10, 1, 0, 0), (20_000, 128, 50, 10, 2, 1, 0),
     (20_000, 128, 50, 10, 8, 0, 0), (20_000, 128, 50, 10, 16, 1, 0), (20_000, 128, 50, 10, 0, 0, 2),
+    (20_000, 128, 50, 10, 32, 0, 2), (9_000, 37, 16, 5, 32, 1, 2), (6_000, 1536, 24, 10, 32, 0, 2),
     (9_000, 37, 16, 5, 0, 0, 0), (9_000, 37, 16, 5, 1, 1, 0), (9_000, 37, 16, 5, 16, 0, 0),
     (9_000, 37, 16, 5, 0, 1, 2),
     (6_000, 1536, 24, 10, 0, 0, 0), (6_000, 1536, 24, 10, 1, 0, 0), (6_000, 1536, 24, 10, 16, 0, 0),
@@ -101,7 +102,7 @@ def test_kmeans_build_invariants(pdx):
 def test_eps_inf_equals_ivf_flat(pdx, n, d, nlist, k, qpw, order, engine):
     """Also for every scan schedule: queries per wave 1 (one-query kernel),
     2, 4 (default), 8, 16, buckets by size or by id, and the matrix-core
-    scan (engine 2)."""
+    scan (engine 2) with 16 or 32 queries per wave."""
     mix = synth.anisotropic_unit_mixture(d, 32, n % 97)
     x = mix.data(n)
     q = mix.queries(40)
