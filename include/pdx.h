@@ -245,6 +245,16 @@ typedef struct {
                                  vectorgroup with its own k-best list: 1, 2,
                                  4 or 8; 0: automatic (about 8 waves per SIMD
                                  for each phase)                           */
+    int32_t bound;            /* 0: the ADSampling test (Section 2.3; its
+                                 statistics assume a rotated index);
+                                 1: PDX-BOND (Section 5) inside the probed
+                                 buckets: each query visits dimensions by
+                                 |q'_j - mean_j| descending and drops a
+                                 vector once its partial distance exceeds
+                                 the running k-th distance, so the result
+                                 is exact within the probed buckets (eps0,
+                                 engine and queries_per_wave are ignored;
+                                 f32 storage only)                          */
 } pdx_ivf_search_params;
 
 /* pdx_ivf_tune -- pick the fastest scan schedule for a workload.

@@ -59,7 +59,7 @@ class pdx_ivf_search_params(ctypes.Structure):
                 ("rerank", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
                 ("mlp", c_void_p), ("mlp_threshold", ctypes.c_float), ("trace_features", c_void_p),
                 ("trace_need", c_void_p), ("queries_per_wave", c_int32), ("bucket_order", c_int32),
-                ("engine", c_int32), ("bucket_split", c_int32)]
+                ("engine", c_int32), ("bucket_split", c_int32), ("bound", c_int32)]
 
 
 class pdx_ivf_schedule(ctypes.Structure):

@@ -35,6 +35,7 @@ def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 _MODES = {"linear": _lib.PDX_MODE_LINEAR, "bond": _lib.PDX_MODE_BOND}
+_BOUNDS = {"ads": 0, "bond": 1}
 _DTYPES = {"f32": _lib.PDX_DTYPE_F32, "bf16": _lib.PDX_DTYPE_BF16, "fp8": _lib.PDX_DTYPE_FP8}
 
 
@@ -163,12 +164,13 @@ def pdx_ivf_export(index: PdxIndex, stream: Optional[torch.cuda.Stream] = None):
 
 def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delta_d: int = 0,
                              dtype: str = "f32", rerank: int = 0, queries_per_wave: int = 0,
-                             engine: int = 0, mlp: Optional["MlpState"] = None, bucket_split: int = 0) -> int:
+                             engine: int = 0, mlp: Optional["MlpState"] = None, bucket_split: int = 0,
+                             bound: str = "ads") -> int:
     """Workspace bytes of pdx_search_ivf with the same arguments (the
     learned stop adds stages, and so item padding)."""
     p = _lib.pdx_ivf_search_params(2.1, int(delta_d), _DTYPES[dtype], int(rerank), None, None,
                                    None if mlp is None else _ptr(mlp.mem), 0.5, None, None,
-                                   int(queries_per_wave), 0, int(engine), int(bucket_split))
+                                   int(queries_per_wave), 0, int(engine), int(bucket_split), _BOUNDS[bound])
     return int(lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p)))
 
 
@@ -225,7 +227,7 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                    counters: Optional[torch.Tensor] = None, mlp: Optional[MlpState] = None,
                    mlp_threshold: float = 0.5, trace: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                    queries_per_wave: int = 0, bucket_order: int = 0, engine: int = 0, bucket_split: int = 0,
-                   stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+                   bound: str = "ads", stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Approximate k nearest neighbours (IVF + ADSampling), optionally with the
     learned probe budget (mlp) or recording its training traces
     (trace = (features [nq, nprobe, 72] float32, need [nq] int32))."""
@@ -244,7 +246,7 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                                    ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
                                    _ptr(counters), None if mlp is None else _ptr(mlp.mem), float(mlp_threshold),
                                    _ptr(tf), _ptr(ti), int(queries_per_wave), int(bucket_order), int(engine),
-                                   int(bucket_split))
+                                   int(bucket_split), _BOUNDS[bound])
     ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
     need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
@@ -266,7 +268,7 @@ def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: fl
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
-                                   _DTYPES[dtype], int(rerank), None, None, None, 0.5, None, None, 0, 0, 0, 0)
+                                   _DTYPES[dtype], int(rerank), None, None, None, 0.5, None, None, 0, 0, 0, 0, 0)
     need = lib.pdx_ivf_tune_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
     table = (_lib.pdx_ivf_schedule * _lib.TUNE_CANDIDATES)()

@@ -683,6 +683,34 @@ bool tile_path(const pdx_index *ix, const ExactPlan &pl) {
            pl.tiles_main > 0 && tile_lds_bytes(ix->d) <= max_dynamic_lds();
 }
 
+// PDX-BOND inside IVF: one wave per (query, probe rank) work item scans
+// the item's bucket in the query's BOND order (scan_groups), writing the
+// item's k-best list; PRUNE drops a vector once its partial distance
+// exceeds the threshold (exact within the probed buckets).  Items are
+// grouped by bucket; workgroup ids map to XCD-contiguous ranges of items.
+template <bool PRUNE>
+__global__ __launch_bounds__(256) void bond_item_kernel(
+    const float *__restrict__ pdxd, const int32_t *__restrict__ slot_id, int32_t d, const int32_t *__restrict__ goff,
+    const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ probe, int32_t nprobe,
+    const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
+    const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, unsigned long long *__restrict__ counters,
+    uint32_t nwg) {
+    const uint32_t per_xcd = gridDim.x >> 3;
+    const uint32_t wg = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int lane = threadIdx.x & 63;
+    const int64_t it = (int64_t)wg * 4 + (threadIdx.x >> 6);
+    if (wg >= nwg || it >= nitems) return;
+    const int2 item = items[it];
+    uint64_t *myslot = slots.at(item.x, item.y, 0);
+    if (bad[item.x]) {
+        if (lane < slots.kk) myslot[lane] = kEmptyKey;
+        return;
+    }
+    const int32_t l = probe[(int64_t)item.x * nprobe + item.y];
+    scan_groups<PRUNE>(pdxd, 0, slot_id, d, goff[l], goff[l + 1], item.x, perm, qperm, tau, myslot, slots.kk, chunk,
+                       counters);
+}
+
 }  // namespace
 
 size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_params *p,
@@ -848,6 +876,34 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
                                          pl.tiles_start, pl.tiles_main, out_ids, out_dist);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return mark(3);
+}
+
+// ---------------------------------------------------------------------------
+// PDX-BOND inside IVF (pdx_search_ivf with the BOND bound)
+// ---------------------------------------------------------------------------
+hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *means, int32_t *perm, float *qperm,
+                            uint32_t *tau, int32_t *bad, hipStream_t s) {
+    if (nq <= 0) return hipSuccess;
+    const int32_t pow2 = next_pow2(d);
+    const size_t lds = pow2 * sizeof(uint64_t) + d * sizeof(float);
+    prep_kernel<<<dim3((unsigned)nq), dim3(256), lds, s>>>(q, d, means, PDX_MODE_BOND, pow2, perm, qperm, tau, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_bond_items(bool prune, const pdx_index *ix, const int2 *items, int64_t nitems,
+                             const int32_t *probe, int32_t nprobe, const int32_t *perm, const float *qperm,
+                             uint32_t *tau, const int32_t *bad, SlotMap slots, int32_t chunk,
+                             unsigned long long *counters, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const uint32_t nwg = (uint32_t)((nitems + 3) / 4);
+    const unsigned grid = 8u * ((nwg + 7u) / 8u);
+    if (prune)
+        bond_item_kernel<true><<<grid, 256, 0, s>>>(ix->pdx, ix->slot_id, ix->d, ix->list_goff, items, nitems, probe,
+                                                    nprobe, perm, qperm, tau, bad, slots, chunk, counters, nwg);
+    else
+        bond_item_kernel<false><<<grid, 256, 0, s>>>(ix->pdx, ix->slot_id, ix->d, ix->list_goff, items, nitems, probe,
+                                                     nprobe, perm, qperm, tau, bad, slots, chunk, counters, nwg);
+    return hipGetLastError();
 }
 
 }  // namespace pdx

@@ -646,11 +646,12 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         if (r == 0) r = min(4 * k, PDX_MAX_K);
         pl.rerank = r < 0 ? 0 : max(r, k);
     }
+    pl.bond = (p && p->bound == 1) ? 1 : 0;
     {
         int32_t eng = p ? p->engine : 0;
         if (eng == 0)  // automatic: matrix cores once buckets see enough queries to fill 16-row tiles
             eng = (!(p && p->queries_per_wave > 0) && (double)nq * nprobe >= 8.0 * ix->nlist) ? 2 : 1;
-        pl.matrix = eng == 2 ? 1 : 0;
+        pl.matrix = (eng == 2 && !pl.bond) ? 1 : 0;  // the BOND scan gathers per-query dimensions: vector ALU
     }
     // matrix-core scans report exact f32 distances of their k best
     if (pl.matrix && pl.dtype == PDX_DTYPE_F32) pl.rerank = k;
@@ -670,6 +671,8 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         // 330 registers: one wave per SIMD)
         const int32_t tiles = (p && p->queries_per_wave == 32) ? 2 : 1;
         pl.qb0 = pl.qb1 = 16 * tiles;
+    } else if (pl.bond) {
+        pl.qb0 = pl.qb1 = 1;  // one query per wave: each query visits its own dimension order
     } else {
         pl.qb0 = pl.qb1 = (p && p->queries_per_wave > 0) ? p->queries_per_wave : kDefaultQueriesPerWave;
     }
@@ -689,6 +692,8 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.cnt1 = c.take<int32_t>(ix->nlist);
     pl.budget = c.take<int32_t>(q);
     pl.xcd = pl.matrix ? c.take<int32_t>(18) : nullptr;  // XCD ranges of the START and later-rank items
+    pl.perm = pl.bond ? c.take<int32_t>(q * ix->d) : nullptr;
+    pl.qperm = pl.bond ? c.take<float>(q * ix->d) : nullptr;
     pl.items0 = c.take<int2>((size_t)pl.cap0);
     pl.items1 = c.take<int2>((size_t)(pl.cap1 > 0 ? pl.cap1 : 1));
     {
@@ -736,6 +741,9 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     select_probe_kernel<<<(unsigned)nq, 256, pow2 * sizeof(uint64_t), s>>>(pl.cd, ix->nlist, pow2, q, d, pl.nprobe,
                                                                          pl.probe, pl.bad, pl.tau);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // PDX-BOND: each query's dimension order by |q'_j - mean_j| (Section 5)
+    if (pl.bond && (e = launch_bond_prep(pl.qrot, nq, d, ix->means, pl.perm, pl.qperm, pl.tau, pl.bad, s)) != hipSuccess)
+        return e;
     // 3. work items grouped by bucket
     if ((e = launch_fill_i32(pl.cnt0, ix->nlist, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(pl.cnt1, ix->nlist, 0, s)) != hipSuccess) return e;
@@ -770,6 +778,9 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     auto scan = [&](bool prune, const int2 *items, int64_t cap, int32_t qb, const SlotMap &sm,
                     unsigned long long *cnt, const int32_t *xr) {
         if (cap <= 0) return hipSuccess;
+        if (pl.bond)
+            return launch_bond_items(prune, ix, items, cap, pl.probe, pl.nprobe, pl.perm, pl.qperm, pl.tau, pl.bad,
+                                     sm, pl.chunk, cnt, s);
         if (qb == 1) {
             const uint32_t nwg = (uint32_t)((cap + 3) / 4);
             const unsigned grid = 8u * ((nwg + 7u) / 8u);

@@ -158,6 +158,9 @@ struct IvfPlan {
     int32_t *trace_need;
     int32_t matrix;    // bucket scan on the matrix cores (16 queries per wave)
     int32_t qb0, qb1;  // queries per wave in the START / later bucket scans
+    int32_t bond;      // PDX-BOND bound instead of ADSampling
+    int32_t *perm;     // bond: [nq][d] visited dimension order
+    float *qperm;      // bond: [nq][d] rotated query values in that order
     int32_t by_size;   // lay buckets out larger first
     int64_t cap0;      // START item slots (counts rounded up to qb per bucket)
     int64_t cap1;      // item slots of ranks >= 1
@@ -167,6 +170,14 @@ struct IvfPlan {
     hipEvent_t *events;
     unsigned long long *counters;
 };
+
+// PDX-BOND inside IVF (k_exact.hip): query order and per-item bucket scans.
+hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *means, int32_t *perm, float *qperm,
+                            uint32_t *tau, int32_t *bad, hipStream_t s);
+hipError_t launch_bond_items(bool prune, const pdx_index *ix, const int2 *items, int64_t nitems,
+                             const int32_t *probe, int32_t nprobe, const int32_t *perm, const float *qperm,
+                             uint32_t *tau, const int32_t *bad, SlotMap slots, int32_t chunk,
+                             unsigned long long *counters, hipStream_t s);
 
 // Bucket scan on the matrix cores (k_ivf_mscan.hip): batches of 16 * tiles
 // queries (tiles = 1 or 2) per wave.

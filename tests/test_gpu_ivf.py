@@ -271,3 +271,35 @@ def test_matrix_scan_split_is_invisible(pdx):
                 assert np.array_equal(gi, ref[0]) and np.array_equal(gd, ref[1])
     with pytest.raises(Exception):
         pdx.pdx_search_ivf(ix, _dev(q), k, 4, engine=2, bucket_split=3)
+
+
+@pytest.mark.parametrize("n,d,nlist,k,rotated", [(20_000, 128, 50, 10, True), (9_000, 37, 16, 5, False),
+                                                 (6_000, 1536, 24, 10, True), (30_000, 96, 40, 64, False)])
+def test_bond_bound_exact_within_probed_buckets(pdx, n, d, nlist, k, rotated):
+    """PDX-BOND inside IVF: at every nprobe the result is the exact k-NN of
+    the probed buckets (the oracle's IVF-flat), with all buckets the exact
+    k-NN; rotated and unrotated indexes."""
+    from paper_2503_04422_amd._lib import PdxError
+    mix = synth.skewed_mixture(d, 16, 8.0, 4.0, n % 89)
+    x = mix.data(n)
+    q = mix.queries(40)
+    print(f"bond inside ivf n={n} d={d} nlist={nlist} k={k} rotated={rotated}", flush=True)
+    g, r32, xr, c, lab = _oracle_index(x, nlist, n)
+    if not rotated:
+        r32 = np.eye(d, dtype=np.float32)
+        xr = x.astype(np.float64)
+        c, lab, _ = kmeans.lloyd(x, np.random.default_rng(n).choice(n, nlist, replace=False), 5)
+    lists = kmeans.lists_from_labels(lab, nlist)
+    ix = pdx.pdx_ivf_build(_dev(x), nlist, None, None, rotation=_dev(r32) if rotated else None,
+                           centroids=_dev(c.astype(np.float32)), assign=_dev(lab.astype(np.int32)))
+    qr = rotation.rotate_rows(q, r32.astype(np.float64)) if rotated else q.astype(np.float64)
+    for nprobe in (1, 3, nlist):
+        gi, gd = (_np(t) for t in pdx.pdx_search_ivf(ix, _dev(q), k, nprobe, bound="bond"))
+        keep = [i for i in range(q.shape[0]) if not _probe_tied(c.astype(np.float32), qr[i], nprobe)]
+        want = [px.ivf_flat(xr, lists, c.astype(np.float32), qr[i], k, nprobe) for i in keep]
+        check_knn(xr, qr[keep], gi[keep], gd[keep], np.stack([w[0] for w in want]), np.stack([w[1] for w in want]))
+        if nprobe == nlist:
+            ei, ed = exact.knn_exact(xr, qr, k)
+            check_knn(xr, qr, gi, gd, ei, ed)
+    with pytest.raises(PdxError):
+        pdx.pdx_search_ivf(ix, _dev(q), k, 2, bound="bond", dtype="bf16")
