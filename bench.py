@@ -15,8 +15,10 @@ skewed Gaussian mixture standing in for GIST/960), 1,000 queries, K = 10.
   rotation): queries per second and recall@10 per nprobe (scan schedule
   from the autotuner), and the throughput at the smallest nprobe reaching
   recall@10 >= 0.95 (recall against the FP64 oracle on the CPU leg's
-  sample).  extra.learned_stop: plain ADSampling against the learned probe
-  budget at recall@10 >= 0.95 on 10,000 evaluation queries.
+  sample).  extra.approx_bond_bound: the same index with PDX-BOND as the
+  bound inside the probed buckets.  extra.learned_stop: plain ADSampling
+  against the learned probe budget, and against the learned prune
+  multiplier, at recall@10 >= 0.95 on 10,000 evaluation queries.
 * roofline: the dominant kernel (the LDS-tile scan, 8 launches per step):
   algorithmic flops (3 per evaluated value, from the library's counters)
   over its event-timed duration, against the vector-ALU ceiling.
@@ -207,8 +209,40 @@ def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, tr
             "roofline_at_recall_0.95": None if best is None else best.pop("roofline")}
 
 
+def bench_bond_ivf(pdx, torch, np, ix, q_dev, nprobes, k, steps, warmup, truth_ids):
+    """PDX-BOND as the bound inside IVF: every probed bucket scanned in the
+    query's BOND order with strict pruning (exact within the probed
+    buckets), on the same index and queries as the ADSampling sweep."""
+    from oracle.exact import recall_at_k
+    nq = q_dev.shape[0]
+    rows = []
+    for p in nprobes:
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, p, bound="bond")), dtype=torch.uint8,
+                         device="cuda")
+        out = {}
+
+        def run(evs, p=p, ws=ws, out=out):
+            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, p, workspace=ws, phase_events=evs, bound="bond")
+
+        elapsed, ph = timed_steps(run, steps, warmup, torch, np)
+        ids = out["r"][0].cpu().numpy()
+        rec = recall_at_k(truth_ids, ids[: truth_ids.shape[0]]) if truth_ids is not None else None
+        cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+        pdx.pdx_search_ivf(ix, q_dev, k, p, counters=cnt, bound="bond")
+        c = [float(v) for v in cnt.cpu().tolist()]
+        rows.append({"nprobe": p, "qps": round(nq * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
+                     "recall@10": None if rec is None else round(rec, 4),
+                     "phases_ms": {"prep_start": round(ph[0], 3), "pruned_scan": round(ph[1], 3),
+                                   "merge": round(ph[2], 3)},
+                     "live_values": c[2], "computed_values": c[3]})
+        print(f"# bond-in-ivf nprobe {p}: {rows[-1]['qps']} qps recall {rows[-1]['recall@10']}", file=sys.stderr,
+              flush=True)
+    return {"bound": "PDX-BOND (exact within the probed buckets)", "sweep": rows}
+
+
 def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu_seconds, target=0.95,
-                  nprobe_max=32, n_train=8000, n_val=2000, seed_train=43, seed_eval=44):
+                  nprobe_max=32, n_train=8000, n_val=2000, seed_train=43, seed_eval=44, prune_levels=(0.99, 0.998),
+                  prune_scales=(0.95, 1.0, 1.1, 1.25)):
     """Learned early termination against plain IVF + ADSampling at equal
     recall@10 on the same index.  Training queries (seed 43) are split into
     traces (first n_train) and validation (last n_val); the operating point
@@ -270,7 +304,8 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
     print(f"# validation picks: plain nprobe {pick_p}, learned threshold {pick_t}", file=sys.stderr, flush=True)
 
     def timed(**kw):
-        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, qe.shape[0], k, kw["nprobe"], mlp=kw.get("mlp"))),
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, qe.shape[0], k, kw["nprobe"], mlp=kw.get("mlp"),
+                                                             prune_mlp=kw.get("prune_mlp"))),
                          dtype=torch.uint8, device="cuda")
         out = {}
 
@@ -296,6 +331,45 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
     if "plain" in res and "learned" in res:
         res["speedup_qps"] = round(res["learned"]["qps"] / res["plain"]["qps"], 3)
     print(f"# learned: {res.get('plain')} vs {res.get('learned')}", file=sys.stderr, flush=True)
+
+    # learned prune multiplier in place of ADSampling's (1 + eps0/sqrt(d))^2:
+    # traces of a search exact within nprobe_max buckets, pinball training,
+    # then the cheapest (nprobe, scale) reaching the target on validation
+    t0 = time.perf_counter()
+    pfeats, ptargets, pstats = learn.prune_traces(ix, qt[:n_train], k, nprobe_max)
+    torch.cuda.synchronize()
+    ptrace_s = time.perf_counter() - t0
+    nets, pinfo, ptrain_s = {}, {}, {}
+    for level in prune_levels:
+        t0 = time.perf_counter()
+        nets[level], pinfo[level] = learn.train_prune_network(pfeats, ptargets, level=level)
+        torch.cuda.synchronize()
+        ptrain_s[level] = round(time.perf_counter() - t0, 3)
+    del pfeats, ptargets
+    print(f"# prune traces {pstats['samples']} samples ({ptrace_s:.2f}s), training {ptrain_s}s: {pinfo}",
+          file=sys.stderr, flush=True)
+    lo = max(2, (pick_p or 14) - 4)
+    grid_np = [p for p in plain_np if lo <= p <= min(nprobe_max, (pick_p or 14) + 6)]
+    pval, best = [], None
+    for level, net_l in nets.items():
+        for p in grid_np:
+            for sc in prune_scales:
+                ids, work = search(qv, nprobe=p, prune_mlp=net_l, prune_scale=sc)
+                r = recall_at_k(tv, ids)
+                pval.append({"level": level, "nprobe": p, "scale": sc, "recall@10": round(r, 4),
+                             "values_per_query": round(work)})
+                if r >= target and (best is None or work < best[0]):
+                    best = (work, level, p, sc)
+    pres = {"levels": list(prune_levels), "traces": pstats, "trace_s": round(ptrace_s, 3),
+            "train": {str(k_): v for k_, v in pinfo.items()}, "train_s": {str(k_): v for k_, v in ptrain_s.items()},
+            "validation": pval}
+    if best is not None:
+        pres["learned"] = dict(level=best[1], nprobe=best[2], scale=best[3],
+                               **timed(nprobe=best[2], prune_mlp=nets[best[1]], prune_scale=best[3]))
+        if "plain" in res:
+            pres["speedup_qps"] = round(pres["learned"]["qps"] / res["plain"]["qps"], 3)
+    print(f"# learned prune: {pres.get('learned')}", file=sys.stderr, flush=True)
+    res["prune_multiplier"] = pres
     return res
 
 
@@ -547,6 +621,7 @@ def main() -> int:
     if mode == "bond" and not args.no_ivf:
         ivf_ix = build_ivf(pdx, torch, np, x, 1024)
         extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, [2, 4, 8, 16, 32, 64], k, 3, 1, truth, index=ivf_ix)
+        extra["approx_bond_bound"] = bench_bond_ivf(pdx, torch, np, ivf_ix[0], q, [8, 16, 32], k, 3, 1, truth)
         if not args.no_learned:
             extra["learned_stop"] = bench_learned(pdx, torch, np, ivf_ix[0], ix, x_np, mix, k, 3, 1,
                                                   0 if args.no_cpu_baseline else args.cpu_seconds / 2)

@@ -255,6 +255,30 @@ typedef struct {
                                  is exact within the probed buckets (eps0,
                                  engine and queries_per_wave are ignored;
                                  f32 storage only)                          */
+    /* Learned prune multiplier (see pdx_mlp_*; NULL = ADSampling's).       */
+    const void *prune_mlp;    /* network state: after START, every (query,
+                                 rank r >= 1, test point c) gets the
+                                 multiplier m = prune_scale * exp(z) in
+                                 place of (1 + eps0/sqrt(c1))^2 (bound 0
+                                 only; eps0 is then unused)                 */
+    float prune_scale;        /* > 0; 0 = 1                                 */
+    float *prune_table;       /* optional out, [nq][nprobe-1][C]: m of rank
+                                 r (row r - 1) at test point c; needs
+                                 prune_mlp                                   */
+    /* Prune-network traces (NULL = off; the search itself is unchanged):   */
+    float *trace_prune_features; /* [nq][k][C][72]: the inputs for (query,
+                                    rank of the bucket of the i-th returned
+                                    id, c)                                   */
+    float *trace_prune_target;   /* [nq][k][C]: ln(partial * D/(c1 tau_k))
+                                    of the i-th returned id after c1
+                                    dimensions (partial in the rotated
+                                    space, dimensions in natural order);
+                                    NaN where there is no sample: no id,
+                                    an id of the START bucket, or tau_k not
+                                    positive and finite.  Labels hold for
+                                    the exact result when the search is
+                                    exact within the probed buckets
+                                    (eps0 = +INFINITY or bound 1)            */
 } pdx_ivf_search_params;
 
 /* pdx_ivf_tune -- pick the fastest scan schedule for a workload.
@@ -266,8 +290,9 @@ typedef struct {
  * and eps0 is finite, ADSampling test intervals delta_d of 32 and 64
  * dimensions (a longer interval tests less often, each test on more
  * dimensions).  The vectorgroup stays 64 vectors: one per lane of a wave.
- * params: in, the search to tune (eps0, dtype, rerank; mlp and traces must
- * be NULL); out, engine, queries_per_wave, bucket_order and delta_d set to
+ * params: in, the search to tune (eps0, dtype, rerank; mlp, prune_mlp,
+ * prune_table and every trace must be NULL); out, engine,
+ * queries_per_wave, bucket_order and delta_d set to
  * the fastest candidate.  table (may be NULL): PDX_TUNE_CANDIDATES entries,
  * filled in candidate order (ms < 0: candidate skipped).  ws: at least
  * pdx_ivf_tune_workspace bytes, 16-byte aligned.  Errors as pdx_search_ivf. */
@@ -307,24 +332,47 @@ PDX_API pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_
                           size_t ws_bytes, int64_t *out_ids, float *out_dist, void *stream);
 
 /* ---------------------------------------------------------------------
- * Learned early termination for the IVF search
+ * Learned networks for the IVF search
  *
- * A small network sets, per query, how many of its nprobe buckets it
- * probes.  This is an addition beside the paper's fixed-nprobe IVF search
- * (Section 2.1) and its ADSampling test (Section 2.3), which remain the
- * fallback: with no network (or a network that never fires) the search is
- * the plain one.  After START (the nearest bucket, scanned whole) the
- * network is evaluated for r = 1 .. nprobe-1 on inputs (72): the first 64
- * rotated query coordinates, then tau/d_r, d_r/d_0, d_last/d_0, tau/d_0 and
- * log2(r)/log2(nprobe), each ratio clamped to [0, 1e4] (tau: the k-th
- * distance in the START bucket; d_i: the squared distance to the i-th
- * nearest centroid, 0-based, so d_r is the first bucket not probed), then
- * 3 zeros.  The query probes the smallest r whose output fires.  Network:
- * relu(64) -> relu(64) -> logit, float16 weights, float32 accumulation.
+ * Two small networks of one architecture are additions beside the paper's
+ * fixed-nprobe IVF search (Section 2.1) and its ADSampling test (Section
+ * 2.3), which remain the fallback: with no network the search is the plain
+ * one.  Architecture: x (72) -> relu(64) -> relu(64) -> z, float16
+ * weights, float32 accumulation.  In the inputs below, tau is the k-th
+ * distance in the START bucket (the nearest bucket, scanned whole), d_i
+ * the squared distance to the i-th nearest centroid (0-based), and each
+ * ratio is clamped to [0, 1e4].
+ *
+ * Probe budget (pdx_ivf_search_params.mlp).  After START the network is
+ * evaluated for r = 1 .. nprobe-1 on: the first 64 rotated query
+ * coordinates (zero-padded when D < 64), then tau/d_r, d_r/d_0,
+ * d_last/d_0, tau/d_0 and log2(r)/log2(nprobe) (d_r: the first bucket not
+ * probed), then 3 zeros; z is a logit.  The query probes the smallest r
+ * whose output fires.
+ *
+ * Prune multiplier (pdx_ivf_search_params.prune_mlp).  For each bucket of
+ * probe rank r >= 1 and each test point c (after c1 = (c + 1) delta_d < D
+ * dimensions; C = ceil(D / delta_d) - 1 points) the network sees: the same
+ * 64 coordinates, then tau/d_r, d_r/d_0, tau/d_0, log2(r)/log2(nprobe),
+ * c1/D and 1/sqrt(c1) (d_r: the bucket being scanned), then 2 zeros; the
+ * multiplier is m = prune_scale * exp(z), capped at 1e30.  A vector of
+ * that bucket is dropped after c1 dimensions when partial * D/c1 >
+ * tau_now * m, in place of ADSampling's (1 + eps0/sqrt(c1))^2; the test
+ * after all D dimensions stays exact.  Its training target for a returned
+ * neighbour (outside the START bucket) is ln(partial * D / (c1 * tau_k)),
+ * tau_k being the search's final k-th distance: a multiplier at or above
+ * it keeps that neighbour whatever the running threshold, so the network
+ * is trained for a high quantile of it (PDX_LOSS_PINBALL).
+ *
  * State buffer (pdx_mlp_bytes): float32 parameters W1[64][72] b1[64]
  * W2[64][64] b2[64] w3[64] b3 (8897 used, 8960 padded), Adam moments,
  * gradient, and the float16 copy the search and pdx_mlp_forward use.
  * ------------------------------------------------------------------ */
+
+#define PDX_LOSS_BCE 0     /* L = (1/n) sum(-y log p - w (1-y) log(1-p)), p = sigmoid(z),
+                              y in {0, 1}, w >= 0 weighting the negatives */
+#define PDX_LOSS_PINBALL 1 /* L = (1/n) sum(u (w - [u < 0])), u = y - z, level w in (0, 1):
+                              z estimates the w-quantile of y; dL/dz = ([z > y] - w)/n */
 
 PDX_API size_t pdx_mlp_bytes(void);
 /* Device workspace for pdx_mlp_grad / pdx_mlp_train_step over n samples. */
@@ -332,17 +380,19 @@ PDX_API size_t pdx_mlp_workspace(int64_t n);
 /* Set the parameters to theta0 [8960] float32 device (random numbers drawn
  * by the caller), zero the Adam moments, refresh the float16 copy. */
 PDX_API pdx_status pdx_mlp_init(void *mlp, const float *theta0, void *stream);
-/* z [n] = logits of x [n][72] with the float16 weights. */
+/* z [n] = outputs for x [n][72] with the float16 weights. */
 PDX_API pdx_status pdx_mlp_forward(const void *mlp, const float *x, int64_t n, float *z, void *stream);
-/* Gradient [8960] of L = (1/n) sum(-y log p - w0 (1-y) log(1-p)), p = sigmoid(z),
- * with respect to the parameters, the network evaluated with its float16
- * weights; loss (device float, may be NULL) receives L.  Deterministic. */
-PDX_API pdx_status pdx_mlp_grad(const void *mlp, const float *x, const float *y, int64_t n, float w0, void *ws,
-                                size_t ws_bytes, float *grad, float *loss, void *stream);
+/* Gradient [8960] of the loss PDX_LOSS_* (parameter w) over samples x [n][72],
+ * targets y [n], with respect to the parameters, the network evaluated with
+ * its float16 weights; loss (device float, may be NULL) receives L.
+ * Deterministic.  PDX_EINVAL for an unknown loss or w out of its range. */
+PDX_API pdx_status pdx_mlp_grad(const void *mlp, const float *x, const float *y, int64_t n, int32_t loss_kind,
+                                float w, void *ws, size_t ws_bytes, float *grad, float *loss, void *stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on the
- * full batch x [n][72], labels y [n] in {0,1}; refreshes the float16 copy. */
-PDX_API pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y, int64_t n, float w0, float lr,
-                                      int64_t step, void *ws, size_t ws_bytes, float *loss, void *stream);
+ * full batch x [n][72], targets y [n]; refreshes the float16 copy. */
+PDX_API pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y, int64_t n, int32_t loss_kind,
+                                      float w, float lr, int64_t step, void *ws, size_t ws_bytes, float *loss,
+                                      void *stream);
 /* Copy the float32 parameters [8960] to theta (device), e.g. to save them;
  * pdx_mlp_init with the same vector restores the network. */
 PDX_API pdx_status pdx_mlp_export(const void *mlp, float *theta, void *stream);

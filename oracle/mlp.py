@@ -1,16 +1,29 @@
-"""The learned early-termination network, forward and backward in float64 --
+"""The search's learned networks, forward and backward in float64 --
 oracle (test infrastructure).
 
-The paper prunes with fixed rules; this network is an addition beside the
-ADSampling test (a learned stop decision per query and probe checkpoint).
+The paper prunes with fixed rules; these networks are additions beside the
+ADSampling test (Section 2.3) and the fixed-nprobe IVF search (Section
+2.1): a per-query probe budget (a stop decision per probe count) and a
+per-(query, bucket, test point) prune multiplier.
 Architecture: x (F = 72 inputs) -> h1 = relu(W1 x + b1) (64)
--> h2 = relu(W2 h1 + b2) (64) -> z = w3 . h2 + b3, p = sigmoid(z) is the
-probability that stopping here loses nothing.  The search uses the weights
-rounded to float16, so the oracle evaluates the same rounded weights.
+-> h2 = relu(W2 h1 + b2) (64) -> z = w3 . h2 + b3.  The search uses the
+weights rounded to float16, so the oracle evaluates the same rounded
+weights.
 
-Loss (mean over n samples, y in {0, 1}, negatives weighted by w0 because a
-wrong stop costs recall):
-    L = (1/n) sum( -y log p - w0 (1 - y) log(1 - p) ),  dL/dz = (1/n)(-y (1-p) + w0 (1-y) p).
+Losses (mean over n samples):
+* "bce", stop decision, y in {0, 1}, p = sigmoid(z) the probability that
+  stopping loses nothing, negatives weighted by w0 because a wrong stop
+  costs recall:
+      L = (1/n) sum( -y log p - w0 (1 - y) log(1 - p) ),
+      dL/dz = (1/n)(-y (1-p) + w0 (1-y) p);
+* "pinball" at level w in (0, 1), prune multiplier, y a real target, z
+  then estimates the w-quantile of y (quantile regression):
+      L = (1/n) sum( u (w - [u < 0]) ),  u = y - z,
+      dL/dz = (1/n)([z > y] - w).
+
+Prune multiplier: for a bucket of probe rank r >= 1 after c1 of D
+dimensions, m = scale * exp(z) (capped at 1e30) replaces
+(1 + eps0/sqrt(c1))^2 in the test partial * D/c1 > tau * m.
 
 Parameter vector layout (float32 on the device, float64 here):
 W1 [64][72] | b1 [64] | W2 [64][64] | b2 [64] | w3 [64] | b3 [1], padded to 8960.
@@ -66,23 +79,33 @@ def sigmoid(z: np.ndarray) -> np.ndarray:
     return 1.0 / (1.0 + np.exp(-z))
 
 
-def loss(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float) -> float:
+def loss(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float, kind: str = "bce") -> float:
     z, _ = forward(theta, x)
     y = np.asarray(y, dtype=np.float64)
+    if kind == "pinball":
+        u = y - z
+        return float(np.mean(u * (w0 - (u < 0))))
     # log p = -softplus(-z), log(1-p) = -softplus(z)
     sp_neg = np.logaddexp(0.0, -z)
     sp_pos = np.logaddexp(0.0, z)
     return float(np.mean(y * sp_neg + w0 * (1.0 - y) * sp_pos))
 
 
-def grad(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float) -> np.ndarray:
+def dloss_dz(z: np.ndarray, y: np.ndarray, w0: float, kind: str = "bce") -> np.ndarray:
+    """Per-sample derivative of :func:`loss` with respect to z (already divided by n)."""
+    n = z.shape[0]
+    if kind == "pinball":
+        return ((z > y).astype(np.float64) - w0) / n
+    s = sigmoid(z)
+    return (-y * (1.0 - s) + w0 * (1.0 - y) * s) / n
+
+
+def grad(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float, kind: str = "bce") -> np.ndarray:
     """Analytic gradient of :func:`loss` (backpropagation by the chain rule)."""
     z, c = forward(theta, x)
     p = unpack(theta)
     y = np.asarray(y, dtype=np.float64)
-    n = x.shape[0]
-    s = sigmoid(z)
-    dz = (-y * (1.0 - s) + w0 * (1.0 - y) * s) / n
+    dz = dloss_dz(z, y, w0, kind)
     g = {"w3": c["h2"].T @ dz, "b3": np.array([dz.sum()])}
     dh2 = np.outer(dz, p["w3"]) * (c["a2"] > 0)
     g["W2"] = dh2.T @ c["h1"]
@@ -93,7 +116,8 @@ def grad(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float) -> np.ndarr
     return pack(g)
 
 
-def numeric_grad(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float, idx, h: float = 1e-6) -> np.ndarray:
+def numeric_grad(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float, idx, h: float = 1e-6,
+                 kind: str = "bce") -> np.ndarray:
     """Central finite differences of :func:`loss` at the given parameter indices."""
     out = np.empty(len(idx))
     for t, i in enumerate(idx):
@@ -101,5 +125,58 @@ def numeric_grad(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float, idx
         tm = theta.copy()
         tp[i] += h
         tm[i] -= h
-        out[t] = (loss(tp, x, y, w0) - loss(tm, x, y, w0)) / (2 * h)
+        out[t] = (loss(tp, x, y, w0, kind) - loss(tm, x, y, w0, kind)) / (2 * h)
+    return out
+
+
+# --------------------------------------------------------------------------
+# prune multiplier: inputs, multipliers, training targets
+# --------------------------------------------------------------------------
+
+def prune_inputs(qrot: np.ndarray, tau: float, cd: np.ndarray, r: int, nprobe: int, c1: int) -> np.ndarray:
+    """The 72 inputs for a bucket of probe rank r >= 1 after c1 dimensions:
+    the first 64 rotated query coordinates (zero-padded), then tau/d_r,
+    d_r/d_0, tau/d_0 (each clamped to [0, 1e4]), log2(r)/log2(nprobe), c1/D,
+    1/sqrt(c1), then 2 zeros.  tau: the k-th distance in the START bucket;
+    cd: squared centroid distances of the probed buckets, nearest first."""
+    d = qrot.shape[0]
+    x = np.zeros(F_IN, dtype=np.float64)
+    m = min(d, 64)
+    x[:m] = qrot[:m]
+    d0, dr = max(cd[0], 1e-20), max(cd[r], 1e-20)  # a zero distance is read as 1e-20
+    ratios = np.array([tau / dr, dr / d0, tau / d0], dtype=np.float64)
+    x[64:67] = np.clip(ratios, 0.0, 1e4)
+    x[67] = np.log2(r) / np.log2(nprobe)
+    x[68] = c1 / d
+    x[69] = 1.0 / np.sqrt(c1)
+    return x
+
+
+def test_points(d: int, delta_d: int):
+    """The dimension counts c1 = delta_d, 2 delta_d, ... below D after which
+    the prune test runs (the test after all D dimensions is exact)."""
+    return list(range(delta_d, d, delta_d))
+
+
+def prune_multipliers(theta: np.ndarray, qrot: np.ndarray, tau: float, cd: np.ndarray, nprobe: int,
+                      delta_d: int, scale: float = 1.0) -> np.ndarray:
+    """m [nprobe - 1][C] of one query: row r - 1 for probe rank r."""
+    pts = test_points(qrot.shape[0], delta_d)
+    rows = [prune_inputs(qrot, tau, cd, r, nprobe, c1) for r in range(1, nprobe) for c1 in pts]
+    if not rows:
+        return np.zeros((max(nprobe - 1, 0), len(pts)))
+    z, _ = forward(theta, np.stack(rows))
+    return np.minimum(scale * np.exp(z), 1e30).reshape(nprobe - 1, len(pts))
+
+
+def prune_targets(xrot: np.ndarray, qrot: np.ndarray, ids: np.ndarray, tau_k: float, delta_d: int) -> np.ndarray:
+    """[len(ids)][C] targets ln(max(partial(c1) * D / (c1 tau_k), 1e-30)),
+    partial(c1) the squared distance over the first c1 rotated dimensions."""
+    d = qrot.shape[0]
+    pts = test_points(d, delta_d)
+    diff = np.asarray(xrot, dtype=np.float64)[np.asarray(ids, dtype=np.int64)] - qrot[None, :]
+    pref = np.cumsum(diff * diff, axis=1)
+    out = np.empty((len(ids), len(pts)))
+    for c, c1 in enumerate(pts):
+        out[:, c] = np.log(np.maximum(pref[:, c1 - 1] * d / (c1 * tau_k), 1e-30))
     return out

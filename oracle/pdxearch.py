@@ -139,6 +139,8 @@ def pdxearch(x: np.ndarray, q: np.ndarray, k: int, blocks: Sequence[np.ndarray],
              stats: Optional[SearchStats] = None) -> Tuple[np.ndarray, np.ndarray]:
     """PDXearch over ``blocks`` (arrays of row ids) with a fixed dimension
     chunking ``chunks`` (arrays of dimension indices covering 0..D-1 once).
+    ``prune`` is one predicate for every block, or a sequence with one per
+    block.
 
     Returns (ids [k], dist [k]) ordered by (dist, id); pads with (-1, inf).
     """
@@ -147,7 +149,8 @@ def pdxearch(x: np.ndarray, q: np.ndarray, k: int, blocks: Sequence[np.ndarray],
     d = x.shape[1]
     best = _KBest(k)
     st = stats if stats is not None else SearchStats()
-    for rows in blocks:
+    prunes = list(prune) if isinstance(prune, (list, tuple)) else [prune] * len(blocks)
+    for rows, prune_b in zip(blocks, prunes):
         rows = np.asarray(rows, dtype=np.int64)
         if rows.size == 0:
             continue
@@ -169,7 +172,7 @@ def pdxearch(x: np.ndarray, q: np.ndarray, k: int, blocks: Sequence[np.ndarray],
             partial[comp] += np.einsum("ij,ij->i", diff, diff)
             st.values_computed += int(comp.sum()) * ch.size
             seen += ch.size
-            alive &= ~prune(partial, tau, seen, d)
+            alive &= ~prune_b(partial, tau, seen, d)
             st.survivors_per_chunk.append(int(alive.sum()))
             if warmup and alive.mean() < switch:
                 warmup = False
@@ -237,3 +240,31 @@ def ads_ivf_search(xrot: np.ndarray, lists: Sequence[np.ndarray], centroids: np.
     blocks = [np.asarray(lists[p], dtype=np.int64) for p in probe]
     return pdxearch(xrot, qrot, k, blocks, fixed_chunks(np.arange(d), dd),
                     make_ads_prunes(eps0), switch, stats)
+
+
+def make_table_prunes(mult_row: np.ndarray, delta_d: int) -> Callable[[np.ndarray, float, int, int], np.ndarray]:
+    """The ADSampling-shaped test with a multiplier per test point in place
+    of (1 + eps0/sqrt(d))^2: after dims_seen = (c + 1) delta_d < D
+    dimensions, drop iff partial * D/dims_seen > tau * mult_row[c]; exact
+    after all D dimensions."""
+
+    def prune(partial: np.ndarray, tau: float, dims_seen: int, d: int) -> np.ndarray:
+        if dims_seen >= d:
+            return partial > tau
+        return partial * (d / dims_seen) > tau * mult_row[dims_seen // delta_d - 1]
+
+    return prune
+
+
+def learned_ivf_search(xrot: np.ndarray, lists: Sequence[np.ndarray], centroids: np.ndarray,
+                       qrot: np.ndarray, k: int, nprobe: int, mult: np.ndarray, delta_d: int,
+                       switch: float = 0.2, stats: Optional[SearchStats] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """:func:`ads_ivf_search` with the learned multipliers mult [nprobe-1][C]
+    (row r - 1 for the bucket of probe rank r; the START bucket, rank 0, is
+    scanned whole)."""
+    xrot = np.asarray(xrot)
+    d = xrot.shape[1]
+    probe = ivf_probe_order(centroids, qrot, nprobe)
+    blocks = [np.asarray(lists[p], dtype=np.int64) for p in probe]
+    prunes = [never_prunes] + [make_table_prunes(mult[r - 1], delta_d) for r in range(1, len(blocks))]
+    return pdxearch(xrot, qrot, k, blocks, fixed_chunks(np.arange(d), delta_d), prunes, switch, stats)

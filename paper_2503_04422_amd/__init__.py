@@ -7,6 +7,7 @@ binding requires the built library; there is no CPU fallback.
 from .api import (  # noqa: F401
     MlpState,
     PdxIndex,
+    ivf_test_points,
     pdx_build,
     pdx_ivf_build,
     pdx_ivf_export,

@@ -30,6 +30,9 @@ PDX_DTYPE_F32 = 0
 PDX_DTYPE_BF16 = 1
 PDX_DTYPE_FP8 = 2
 
+PDX_LOSS_BCE = 0
+PDX_LOSS_PINBALL = 1
+
 MLP_IN = 72
 MLP_PARAMS = 8960
 
@@ -59,7 +62,9 @@ class pdx_ivf_search_params(ctypes.Structure):
                 ("rerank", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
                 ("mlp", c_void_p), ("mlp_threshold", ctypes.c_float), ("trace_features", c_void_p),
                 ("trace_need", c_void_p), ("queries_per_wave", c_int32), ("bucket_order", c_int32),
-                ("engine", c_int32), ("bucket_split", c_int32), ("bound", c_int32)]
+                ("engine", c_int32), ("bucket_split", c_int32), ("bound", c_int32),
+                ("prune_mlp", c_void_p), ("prune_scale", ctypes.c_float), ("prune_table", c_void_p),
+                ("trace_prune_features", c_void_p), ("trace_prune_target", c_void_p)]
 
 
 class pdx_ivf_schedule(ctypes.Structure):
@@ -97,11 +102,11 @@ SIGNATURES = {
     "pdx_mlp_workspace": (c_size_t, [c_int64]),
     "pdx_mlp_init": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "pdx_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
-    "pdx_mlp_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, c_void_p, c_size_t,
-                               c_void_p, c_void_p, c_void_p]),
+    "pdx_mlp_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, ctypes.c_float, c_void_p,
+                               c_size_t, c_void_p, c_void_p, c_void_p]),
     "pdx_mlp_export": (c_int32, [c_void_p, c_void_p, c_void_p]),
-    "pdx_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, ctypes.c_float,
-                                     c_int64, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "pdx_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, ctypes.c_float,
+                                     ctypes.c_float, c_int64, c_void_p, c_size_t, c_void_p, c_void_p]),
     "pdx_free": (None, [c_void_p]),
     "pdx_last_error": (ctypes.c_char_p, []),
     "pdx_version": (ctypes.c_char_p, []),

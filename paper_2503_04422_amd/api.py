@@ -162,20 +162,37 @@ def pdx_ivf_export(index: PdxIndex, stream: Optional[torch.cuda.Stream] = None):
     return rot, cen, asg, sizes
 
 
+def ivf_test_points(d: int, delta_d: int = 0) -> int:
+    """Prune-test points per bucket, C = ceil(D / delta_d) - 1 (the tests
+    after c1 = (c + 1) delta_d < D dimensions); delta_d 0 = the library's
+    default (32, or D/4 when D < 128)."""
+    dd = delta_d if delta_d > 0 else (32 if d >= 128 else max(d // 4, 1))
+    return (d + dd - 1) // dd - 1 if dd < d else 0
+
+
 def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delta_d: int = 0,
                              dtype: str = "f32", rerank: int = 0, queries_per_wave: int = 0,
                              engine: int = 0, mlp: Optional["MlpState"] = None, bucket_split: int = 0,
-                             bound: str = "ads") -> int:
+                             bound: str = "ads", prune_mlp: Optional["MlpState"] = None,
+                             prune_trace: bool = False) -> int:
     """Workspace bytes of pdx_search_ivf with the same arguments (the
-    learned stop adds stages, and so item padding)."""
+    learned stop adds stages, and so item padding; the prune multipliers
+    and their traces add per-query tables)."""
     p = _lib.pdx_ivf_search_params(2.1, int(delta_d), _DTYPES[dtype], int(rerank), None, None,
                                    None if mlp is None else _ptr(mlp.mem), 0.5, None, None,
-                                   int(queries_per_wave), 0, int(engine), int(bucket_split), _BOUNDS[bound])
+                                   int(queries_per_wave), 0, int(engine), int(bucket_split), _BOUNDS[bound],
+                                   None if prune_mlp is None else _ptr(prune_mlp.mem), 1.0, None,
+                                   1 if prune_trace else None, 1 if prune_trace else None)
     return int(lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p)))
 
 
+_LOSSES = {"bce": _lib.PDX_LOSS_BCE, "pinball": _lib.PDX_LOSS_PINBALL}
+
+
 class MlpState:
-    """Device state of the learned early-termination network (pdx_mlp_*)."""
+    """Device state of one of the search's networks (pdx_mlp_*): the probe
+    budget (weighted cross-entropy, kind "bce", w = the negatives' weight)
+    or the prune multiplier (kind "pinball", w = the quantile level)."""
 
     def __init__(self, theta0: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
         if not theta0.is_cuda or theta0.dtype != torch.float32 or theta0.numel() != _lib.MLP_PARAMS:
@@ -196,14 +213,15 @@ class MlpState:
         check(lib.pdx_mlp_forward(_ptr(self.mem), _ptr(x), x.shape[0], _ptr(z), _stream(stream)), "pdx_mlp_forward")
         return z
 
-    def grad(self, x: torch.Tensor, y: torch.Tensor, w0: float, stream: Optional[torch.cuda.Stream] = None):
+    def grad(self, x: torch.Tensor, y: torch.Tensor, w: float, kind: str = "bce",
+             stream: Optional[torch.cuda.Stream] = None):
         x = _dev_f32(x, "x")
         y = y.contiguous()
         g = torch.empty(_lib.MLP_PARAMS, dtype=torch.float32, device=x.device)
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
         ws = self._workspace(x.shape[0])
-        check(lib.pdx_mlp_grad(_ptr(self.mem), _ptr(x), _ptr(y), x.shape[0], float(w0), _ptr(ws), ws.numel(),
-                               _ptr(g), _ptr(loss), _stream(stream)), "pdx_mlp_grad")
+        check(lib.pdx_mlp_grad(_ptr(self.mem), _ptr(x), _ptr(y), x.shape[0], _LOSSES[kind], float(w), _ptr(ws),
+                               ws.numel(), _ptr(g), _ptr(loss), _stream(stream)), "pdx_mlp_grad")
         return g, loss
 
     def theta(self, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
@@ -212,13 +230,14 @@ class MlpState:
         check(lib.pdx_mlp_export(_ptr(self.mem), _ptr(t), _stream(stream)), "pdx_mlp_export")
         return t
 
-    def train_step(self, x: torch.Tensor, y: torch.Tensor, w0: float, lr: float, step: int,
-                   loss: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> None:
+    def train_step(self, x: torch.Tensor, y: torch.Tensor, w: float, lr: float, step: int,
+                   loss: Optional[torch.Tensor] = None, kind: str = "bce",
+                   stream: Optional[torch.cuda.Stream] = None) -> None:
         x = _dev_f32(x, "x")
         ws = self._workspace(x.shape[0])
-        check(lib.pdx_mlp_train_step(_ptr(self.mem), _ptr(x), _ptr(y.contiguous()), x.shape[0], float(w0),
-                                     float(lr), int(step), _ptr(ws), ws.numel(), _ptr(loss), _stream(stream)),
-              "pdx_mlp_train_step")
+        check(lib.pdx_mlp_train_step(_ptr(self.mem), _ptr(x), _ptr(y.contiguous()), x.shape[0], _LOSSES[kind],
+                                     float(w), float(lr), int(step), _ptr(ws), ws.numel(), _ptr(loss),
+                                     _stream(stream)), "pdx_mlp_train_step")
 
 
 def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1,
@@ -227,10 +246,17 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                    counters: Optional[torch.Tensor] = None, mlp: Optional[MlpState] = None,
                    mlp_threshold: float = 0.5, trace: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
                    queries_per_wave: int = 0, bucket_order: int = 0, engine: int = 0, bucket_split: int = 0,
-                   bound: str = "ads", stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+                   bound: str = "ads", prune_mlp: Optional[MlpState] = None, prune_scale: float = 1.0,
+                   prune_table: Optional[torch.Tensor] = None,
+                   prune_trace: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                   stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Approximate k nearest neighbours (IVF + ADSampling), optionally with the
     learned probe budget (mlp) or recording its training traces
-    (trace = (features [nq, nprobe, 72] float32, need [nq] int32))."""
+    (trace = (features [nq, nprobe, 72] float32, need [nq] int32)), and
+    with the learned prune multiplier (prune_mlp, prune_scale; prune_table
+    receives the multipliers [nq, nprobe - 1, C]) or recording its traces
+    (prune_trace = (features [nq, k, C, 72], target [nq, k, C]) float32);
+    C = ivf_test_points(D, delta_d)."""
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     if q.shape[1] != index.d:
@@ -241,12 +267,24 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
         raise TypeError("trace features must be contiguous float32 [nq, nprobe, 72]")
     if ti is not None and (ti.dtype != torch.int32 or ti.numel() != nq or not ti.is_contiguous()):
         raise TypeError("trace need must be contiguous int32 [nq]")
+    npt = ivf_test_points(index.d, delta_d)
+    if prune_table is not None and (prune_table.dtype != torch.float32 or not prune_table.is_contiguous()
+                                    or prune_table.numel() != nq * max(nprobe - 1, 0) * npt):
+        raise TypeError(f"prune_table must be contiguous float32 [nq, nprobe - 1, {npt}]")
+    pf, pt = (None, None) if prune_trace is None else prune_trace
+    if pf is not None and (pf.dtype != torch.float32 or not pf.is_contiguous()
+                           or pf.numel() != nq * k * npt * _lib.MLP_IN):
+        raise TypeError(f"prune trace features must be contiguous float32 [nq, k, {npt}, 72]")
+    if pt is not None and (pt.dtype != torch.float32 or not pt.is_contiguous() or pt.numel() != nq * k * npt):
+        raise TypeError(f"prune trace targets must be contiguous float32 [nq, k, {npt}]")
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
                                    _DTYPES[dtype], int(rerank),
                                    ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
                                    _ptr(counters), None if mlp is None else _ptr(mlp.mem), float(mlp_threshold),
                                    _ptr(tf), _ptr(ti), int(queries_per_wave), int(bucket_order), int(engine),
-                                   int(bucket_split), _BOUNDS[bound])
+                                   int(bucket_split), _BOUNDS[bound],
+                                   None if prune_mlp is None else _ptr(prune_mlp.mem), float(prune_scale),
+                                   _ptr(prune_table), _ptr(pf), _ptr(pt))
     ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
     need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
@@ -268,7 +306,8 @@ def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: fl
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
-                                   _DTYPES[dtype], int(rerank), None, None, None, 0.5, None, None, 0, 0, 0, 0, 0)
+                                   _DTYPES[dtype], int(rerank), None, None, None, 0.5, None, None, 0, 0, 0, 0, 0,
+                                   None, 1.0, None, None, None)
     need = lib.pdx_ivf_tune_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
     table = (_lib.pdx_ivf_schedule * _lib.TUNE_CANDIDATES)()

@@ -1,7 +1,8 @@
 // IVF bucket scan on the matrix cores: 16 queries x one vectorgroup (64
 // vectors) per wave, the chunk's dot products as v_mfma_f32_16x16x4f32.
 //
-// Same work items, thresholds, ADSampling test and per-item k-best output
+// Same work items, thresholds, prune test (ADSampling or the learned
+// multipliers) and per-item k-best output
 // as the vector-ALU scans (k_ivf_search.hip); only the arithmetic of the
 // partial distances differs.  Per chunk of dimensions C,
 //     sum_{j in C} (q_j - x_j)^2 = |a|^2 + |b|^2 - 2 a.b,
@@ -54,8 +55,8 @@ __device__ __forceinline__ void mscan_unit(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t b,
     int32_t part, const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
-    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, const SlotMap &slots, int32_t chunk, float eps0,
-    unsigned long long *__restrict__ counters, uint64_t (*lists)[kWave]) {
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, const SlotMap &slots, int32_t chunk,
+    const PruneRule &rule, unsigned long long *__restrict__ counters, uint64_t (*lists)[kWave]) {
     constexpr int NQ = 16 * MT;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
@@ -82,7 +83,7 @@ __device__ __forceinline__ void mscan_unit(
     for (int mt = 0; mt < MT; ++mt) qrow[mt] = qrot + (int64_t)(row_ok[mt] ? mine[mt].x : q0) * d;
     const float *crow = cen + (int64_t)l * d;
     // query slots of this lane's D rows
-    int32_t rowq[MT][4];
+    int32_t rowq[MT][4], rowr[MT][4];
     bool rowuse[MT][4];
     float kthr[MT][4];  // k-th distance of the query in D row 4 kq + r of tile mt
 #pragma unroll
@@ -90,6 +91,7 @@ __device__ __forceinline__ void mscan_unit(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             rowq[mt][r] = __shfl(mine[mt].x, 4 * kq + r);
+            rowr[mt][r] = __shfl(mine[mt].y, 4 * kq + r);
             rowuse[mt][r] = (use >> (16 * mt + 4 * kq + r)) & 1u;
             kthr[mt][r] = INFINITY;
         }
@@ -207,11 +209,8 @@ __device__ __forceinline__ void mscan_unit(
                 xx[t] += __shfl_xor(xx[t], 32);
             }
             float fac = 1.0f;
-            if (PRUNE && c1 < d) {
-                const float dc = (float)c1;
-                const float f = 1.0f + eps0 / sqrtf(dc);
-                fac = (dc / (float)d) * f * f;
-            }
+            const bool learned = PRUNE && c1 < d && rule.fac;
+            if (PRUNE && c1 < d && !rule.fac) fac = rule.ads(c1, d);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 if (!((tl >> mt) & 1u)) continue;
@@ -220,11 +219,13 @@ __device__ __forceinline__ void mscan_unit(
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float qn = __shfl(qq[mt], 4 * kq + r);
+                    const float fr = (learned && rowuse[mt][r])
+                                         ? rule.learned(rowq[mt][r], rowr[mt][r], nprobe, c0 / chunk) : fac;
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         part_[mt][r][t] += fmaxf(qn + xx[t] - 2.0f * acc[mt][t][r], 0.0f);
-                        // ADSampling test after c1 of d dimensions (exact at c1 = d)
-                        if (PRUNE && part_[mt][r][t] > teff[mt][r] * fac) alive &= ~(1u << (16 * mt + 4 * r + t));
+                        // the prune test after c1 of d dimensions (exact at c1 = d)
+                        if (PRUNE && part_[mt][r][t] > teff[mt][r] * fr) alive &= ~(1u << (16 * mt + 4 * r + t));
                     }
                 }
             }
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ xcd_range, const int32_t *__restrict__ probe, int32_t nprobe,
     const float *__restrict__ qrot, uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots,
-    int32_t chunk, float eps0, unsigned long long *__restrict__ counters) {
+    int32_t chunk, PruneRule rule, unsigned long long *__restrict__ counters) {
     __shared__ uint64_t lists[4][16 * MT][kWave];
     const int wave = threadIdx.x >> 6;
     const int64_t parts = slots.parts;
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
         const int64_t b = wid / parts;
         if (b < nbatch)
             mscan_unit<PRUNE, STORE, MT>(pdxd, scale, d, slot_id, goff, cen, items, b, (int32_t)(wid - b * parts),
-                                         probe, nprobe, qrot, tau, bad, slots, chunk, eps0, counters, lists[wave]);
+                                         probe, nprobe, qrot, tau, bad, slots, chunk, rule, counters, lists[wave]);
         return;
     }
     const int32_t x = blockIdx.x & 7;
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(256) void ivf_mscan_kernel(
     for (int64_t w = (int64_t)(blockIdx.x >> 3) * 4 + wave; w < nb * parts; w += stride) {
         const int64_t b = w / parts;
         mscan_unit<PRUNE, STORE, MT>(pdxd, scale, d, slot_id, goff, cen, items, b0 + b, (int32_t)(w - b * parts),
-                                     probe, nprobe, qrot, tau, bad, slots, chunk, eps0, counters, lists[wave]);
+                                     probe, nprobe, qrot, tau, bad, slots, chunk, rule, counters, lists[wave]);
     }
 }
 
@@ -310,7 +311,7 @@ hipError_t launch_ivf_mscan(bool prune, int32_t store, int32_t tiles, const void
                             int32_t d, const int32_t *slot_id, const int32_t *goff, const float *cen,
                             const int2 *items, int64_t nbatch, const int32_t *xcd_range, const int32_t *probe,
                             int32_t nprobe, const float *qrot, uint32_t *tau, const int32_t *bad, SlotMap slots,
-                            int32_t chunk, float eps0, unsigned long long *counters, hipStream_t s) {
+                            int32_t chunk, PruneRule rule, unsigned long long *counters, hipStream_t s) {
     if (nbatch <= 0) return hipSuccess;
     // one wave per unit, or (XCD ranges) 8 equal sets of workgroups, an
     // eighth of the units each plus slack for uneven ranges
@@ -318,7 +319,7 @@ hipError_t launch_ivf_mscan(bool prune, int32_t store, int32_t tiles, const void
     const unsigned grid = xcd_range ? 8u * (unsigned)((units / 8 + 3) / 4 + 64) : (unsigned)((units + 3) / 4);
 #define PDX_MSCAN(P, S, M)                                                                                          \
     ivf_mscan_kernel<P, S, M><<<grid, 256, 0, s>>>(data, scale, d, slot_id, goff, cen, items, nbatch, xcd_range,  \
-                                                   probe, nprobe, qrot, tau, bad, slots, chunk, eps0, counters)
+                                                   probe, nprobe, qrot, tau, bad, slots, chunk, rule, counters)
 #define PDX_MSCAN_T(P, S)          \
     if (tiles == 2) PDX_MSCAN(P, S, 2); \
     else PDX_MSCAN(P, S, 1);

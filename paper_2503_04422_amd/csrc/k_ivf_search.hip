@@ -10,8 +10,9 @@
 //  5. the other probed buckets are scanned chunk by chunk in the rotated
 //     (natural) dimension order; after d < D dimensions a vector is dropped
 //     when partial * D/d > tau * (1 + eps0/sqrt(d))^2 (ADSampling test of
-//     Section 2.3), at d = D when partial > tau; survivors enter the wave's
-//     k-best list, whose k-th distance tightens the query's threshold;
+//     Section 2.3), or > tau * m with m from the learned multiplier table,
+//     at d = D when partial > tau; survivors enter the wave's k-best list,
+//     whose k-th distance tightens the query's threshold;
 //  6. merge of the per-item k-best lists.
 #include "mlp_device.h"
 #include "pdx_internal.h"
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nitems,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
-    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, float eps0,
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, PruneRule rule,
     unsigned long long *__restrict__ counters, uint32_t nwg) {
     // grid = 8 * ceil(nwg / 8): every (xcd, index) pair is launched once
     const uint32_t per_xcd = gridDim.x >> 3;
@@ -253,13 +254,9 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
             }
             partial += s;
             if (PRUNE) {
-                // ADSampling test after c1 of d dimensions
+                // the prune test after c1 of d dimensions (exact at c1 = d)
                 float thr = tau_eff;
-                if (c1 < d) {
-                    float dc = (float)c1;
-                    float f = 1.0f + eps0 / sqrtf(dc);
-                    thr = tau_eff * (dc / (float)d) * f * f;
-                }
+                if (c1 < d) thr = tau_eff * (rule.fac ? rule.learned(qi, r, nprobe, c0 / chunk) : rule.ads(c1, d));
                 alive = alive && !(partial > thr);
             }
         }
@@ -290,7 +287,7 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
-    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, float eps0,
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, PruneRule rule,
     unsigned long long *__restrict__ counters) {
     const int lane = threadIdx.x & 63;
     const int32_t k = slots.kk;
@@ -383,17 +380,15 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
                 }
             }
             float fac = 1.0f;
-            if (PRUNE && c1 < d) {
-                const float dc = (float)c1;
-                const float f = 1.0f + eps0 / sqrtf(dc);
-                fac = (dc / (float)d) * f * f;
-            }
+            const bool learned = PRUNE && c1 < d && rule.fac;
+            if (PRUNE && c1 < d && !rule.fac) fac = rule.ads(c1, d);
 #pragma unroll
             for (int q = 0; q < QB; ++q) {
                 if ((qa >> q) & 1u) {
                     part[q] += s[q];
-                    // ADSampling test after c1 of d dimensions (exact at c1 = d)
-                    if (PRUNE && part[q] > teff[q] * fac) am &= ~(1u << q);
+                    // the prune test after c1 of d dimensions (exact at c1 = d)
+                    const float fq = learned ? rule.learned(qid[q], rk[q], nprobe, c0 / chunk) : fac;
+                    if (PRUNE && part[q] > teff[q] * fq) am &= ~(1u << q);
                 }
             }
         }
@@ -493,6 +488,181 @@ __global__ __launch_bounds__(64) void need_kernel(const int64_t *__restrict__ id
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mine = max(mine, __shfl_xor(mine, off));
     if (lane == 0) need[qi] = mine;
+}
+
+// Inputs 64 .. 71 of the prune-multiplier network for a bucket of probe
+// rank r >= 1 after c1 dimensions (inputs 0 .. 63: the rotated query's
+// first coordinates); the same in every lane.
+__device__ __forceinline__ void prune_inputs(float t, float d0, float dr, int32_t r, int32_t nprobe, int32_t c1,
+                                             int32_t d, float (&x)[8]) {
+    auto clampr = [](float v) { return fminf(fmaxf(v, 0.0f), 1.0e4f); };
+    x[0] = clampr(t / dr);
+    x[1] = clampr(dr / d0);
+    x[2] = clampr(t / d0);
+    x[3] = log2f((float)r) / log2f((float)nprobe);
+    x[4] = (float)c1 / (float)d;
+    x[5] = 1.0f / sqrtf((float)c1);
+    x[6] = 0.0f;
+    x[7] = 0.0f;
+}
+
+// Learned prune factors after START: one wave per (query, rank r >= 1).
+// The first layer's query part is evaluated once; then, for groups of
+// kPtGroup test points (c1 = (c + 1) chunk < d), the hidden layer of every
+// point goes to LDS and lane j accumulates unit j of the second layer over
+// all points of the group, in the same order as the one-sample forward
+// pass (so each value equals pdx_mlp_forward on the same inputs).  fac
+// receives (c1/d) m, m = min(scale exp(z), 1e30); table (optional)
+// receives m.  Also records the START threshold in tau0.  Non-finite
+// queries are not scanned: their rows hold NaN in `table`.
+constexpr int kPtGroup = 8;
+
+__device__ __forceinline__ void wave_lds_handoff() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void prune_table_kernel(
+    const float *__restrict__ qrot, int32_t d, const float *__restrict__ cd, int32_t nlist,
+    const int32_t *__restrict__ probe, int32_t nprobe, const uint32_t *__restrict__ tau,
+    const int32_t *__restrict__ bad, const __half *__restrict__ w16, float scale, int32_t chunk, int32_t npt,
+    int64_t npairs, float *__restrict__ fac, float *__restrict__ table, float *__restrict__ tau0) {
+    __shared__ float qs[4][64];
+    __shared__ __attribute__((aligned(16))) float h1s[4][kPtGroup][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t pr = (int64_t)blockIdx.x * 4 + wave;
+    if (pr >= npairs) return;
+    const int64_t qi = pr / (nprobe - 1);
+    const int32_t r = (int32_t)(pr - qi * (nprobe - 1)) + 1;
+    const float t = __uint_as_float(tau[qi]);
+    if (tau0 && r == 1 && lane == 0) tau0[qi] = t;
+    if (!w16) return;
+    const size_t row = (size_t)pr * npt;
+    if (bad[qi]) {
+        if (table)
+            for (int32_t c = lane; c < npt; c += 64) table[row + c] = __uint_as_float(0x7fc00000u);
+        return;
+    }
+    qs[wave][lane] = lane < d ? qrot[qi * d + lane] : 0.0f;
+    wave_lds_handoff();
+    const float *cq = cd + qi * nlist;
+    const int32_t *pq = probe + qi * nprobe;
+    const float d0 = cq[pq[0]] + 1e-20f, dr = cq[pq[r]] + 1e-20f;
+    const float u = mlp_a1_run(w16, qs[wave], lane, 0, 64, h2f(w16, kOffB1 + lane));
+    const __half *r1 = w16 + kOffW1 + lane * kMlpIn + 64;
+    const __half *r2 = w16 + kOffW2 + lane * kMlpH;
+    const float b2 = h2f(w16, kOffB2 + lane), w3 = h2f(w16, kOffW3 + lane), b3 = h2f(w16, kOffB3);
+    for (int32_t cb = 0; cb < npt; cb += kPtGroup) {
+#pragma unroll
+        for (int g = 0; g < kPtGroup; ++g) {
+            float h = 0.0f;
+            if (cb + g < npt) {
+                float x[8];
+                prune_inputs(t, d0, dr, r, nprobe, (cb + g + 1) * chunk, d, x);
+                float a1 = u;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) a1 = fmaf(h2f(r1, i), x[i], a1);
+                h = fmaxf(a1, 0.0f);
+            }
+            h1s[wave][g][lane] = h;
+        }
+        wave_lds_handoff();
+        float a2[kPtGroup];
+#pragma unroll
+        for (int g = 0; g < kPtGroup; ++g) a2[g] = b2;
+#pragma unroll 2
+        for (int i = 0; i < kMlpH; i += 4) {
+            const float w0 = h2f(r2, i), w1 = h2f(r2, i + 1), w2 = h2f(r2, i + 2), w3i = h2f(r2, i + 3);
+#pragma unroll
+            for (int g = 0; g < kPtGroup; ++g) {
+                const float4 hv = *reinterpret_cast<const float4 *>(&h1s[wave][g][i]);
+                a2[g] = fmaf(w0, hv.x, a2[g]);
+                a2[g] = fmaf(w1, hv.y, a2[g]);
+                a2[g] = fmaf(w2, hv.z, a2[g]);
+                a2[g] = fmaf(w3i, hv.w, a2[g]);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kPtGroup; ++g) {
+            float part = w3 * fmaxf(a2[g], 0.0f);
+            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            const int32_t c = cb + g;
+            if (c < npt && lane == 0) {
+                const float m = fminf(scale * expf(part + b3), 1.0e30f);
+                fac[row + c] = ((float)(c + 1) * (float)chunk / (float)d) * m;
+                if (table) table[row + c] = m;
+            }
+        }
+        wave_lds_handoff();  // the group's reads are done before the next group's writes
+    }
+}
+
+// Training traces of the prune-multiplier network, after the result is
+// known: one wave per (query, result slot i).  The i-th id's partial
+// distance after each test point's c1 dimensions (rotated rows, natural
+// order) gives the target ln(max(partial D / (c1 tau_k), 1e-30)), tau_k
+// the result's k-th distance; the inputs are those of (query, rank of the
+// id's bucket, c) with the START threshold tau0.  No sample (target NaN,
+// inputs 0): no id, an id of the START bucket, tau_k not positive and
+// finite, a non-finite query.
+__global__ __launch_bounds__(256) void prune_trace_kernel(
+    const int64_t *__restrict__ ids, const float *__restrict__ dist, int32_t k, const int32_t *__restrict__ assign,
+    const float *__restrict__ xrow, const float *__restrict__ qrot, int32_t d, const float *__restrict__ cd,
+    int32_t nlist, const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ tau0,
+    const int32_t *__restrict__ bad, int32_t chunk, int32_t npt, int64_t nslots, float *__restrict__ feat_out,
+    float *__restrict__ target_out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t si = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (si >= nslots) return;
+    const int64_t qi = si / k;
+    const int64_t id = ids[si];
+    const float tk = dist[qi * k + (k - 1)];
+    bool ok = !bad[qi] && id >= 0 && tk > 0.0f && tk < INFINITY;
+    int32_t r = -1;
+    if (ok) {
+        const int32_t l = assign[id];
+        for (int32_t r0 = 0; r0 < nprobe && r < 0; r0 += 64) {
+            const unsigned long long hit = __ballot(r0 + lane < nprobe && probe[qi * nprobe + r0 + lane] == l);
+            if (hit) r = r0 + __builtin_ctzll(hit);
+        }
+        ok = r >= 1;
+    }
+    float *fo = feat_out + (size_t)si * npt * kMlpIn;
+    float *to = target_out + (size_t)si * npt;
+    if (!ok) {
+        for (int32_t c = 0; c < npt; ++c) {
+            fo[(size_t)c * kMlpIn + lane] = 0.0f;
+            if (lane < kMlpIn - 64) fo[(size_t)c * kMlpIn + 64 + lane] = 0.0f;
+            if (lane == 0) to[c] = __uint_as_float(0x7fc00000u);
+        }
+        return;
+    }
+    const float *cq = cd + qi * nlist;
+    const int32_t *pq = probe + qi * nprobe;
+    const float d0 = cq[pq[0]] + 1e-20f, dr = cq[pq[r]] + 1e-20f;
+    const float qv = lane < d ? qrot[qi * d + lane] : 0.0f;
+    const float *xv = xrow + id * d, *qp = qrot + qi * d;
+    float partial = 0.0f;
+    for (int32_t c = 0; c < npt; ++c) {
+        const int32_t c0 = c * chunk, c1 = c0 + chunk;
+        float sum = 0.0f;
+        for (int32_t j = c0 + lane; j < c1; j += 64) {
+            const float t = xv[j] - qp[j];
+            sum = fmaf(t, t, sum);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        partial += sum;
+        float x[8];
+        prune_inputs(tau0[qi], d0, dr, r, nprobe, c1, d, x);
+        float mine = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mine = lane == i ? x[i] : mine;
+        fo[(size_t)c * kMlpIn + lane] = qv;
+        if (lane < kMlpIn - 64) fo[(size_t)c * kMlpIn + 64 + lane] = mine;
+        if (lane == 0) to[c] = logf(fmaxf(partial * (float)d / ((float)c1 * tk), 1e-30f));
+    }
 }
 
 // k-best over a query's item lists: the START lists (if use0) and the lists
@@ -713,6 +883,16 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
                             pl.kk};
     }
     pl.rkeys = pl.rerank > 0 ? c.take<uint64_t>(q * pl.kk) : nullptr;
+    // learned prune multipliers and their traces
+    pl.npt = dd < ix->d ? (ix->d + dd - 1) / dd - 1 : 0;
+    pl.pw16 = (p && p->prune_mlp) ? mlp_layout(const_cast<void *>(p->prune_mlp)).w16 : nullptr;
+    pl.pscale = (p && p->prune_scale > 0.0f) ? p->prune_scale : 1.0f;
+    pl.ptable = p ? p->prune_table : nullptr;
+    pl.trace_pf = p ? p->trace_prune_features : nullptr;
+    pl.trace_pt = p ? p->trace_prune_target : nullptr;
+    pl.pfac = (pl.pw16 && nprobe > 1 && pl.npt > 0) ? c.take<float>(q * (nprobe - 1) * pl.npt) : nullptr;
+    pl.tau0 = (pl.trace_pf && pl.npt > 0) ? c.take<float>(q) : nullptr;
+    pl.rule = PruneRule{pl.eps0, pl.pfac, pl.npt};
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
     pl.counters = p ? p->counters : nullptr;
     if (plan) *plan = pl;
@@ -787,7 +967,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
 #define PDX_SCAN(P, S)                                                                                          \
     ivf_scan_kernel<P, S><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, cap,  \
                                                pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm, pl.chunk,        \
-                                               pl.eps0, cnt, nwg)
+                                               pl.rule, cnt, nwg)
             if (prune) {
                 if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16);
                 else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8);
@@ -804,12 +984,12 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         if (pl.matrix)
             return launch_ivf_mscan(prune, pl.dtype, qb / 16, data, ix->fp8_scale, d, ix->slot_id, ix->list_goff,
                                     ix->centroids, items, nb, xr, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm,
-                                    pl.chunk, pl.eps0, cnt, s);
+                                    pl.chunk, pl.rule, cnt, s);
         const unsigned grid = (unsigned)((nb + 3) / 4);
 #define PDX_BSCAN(P, S, Q)                                                                                        \
     ivf_bscan_kernel<P, S, Q><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, nb, \
                                                    pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm, pl.chunk,      \
-                                                   pl.eps0, cnt)
+                                                   pl.rule, cnt)
 #define PDX_BSCAN_Q(P, S)                      \
     switch (qb) {                              \
         case 2: PDX_BSCAN(P, S, 2); break;     \
@@ -842,6 +1022,14 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                   pl.w16, pl.zthr, pl.budget, pl.trace_f);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    // learned prune factors (and the START threshold for the traces)
+    if ((pl.pfac || pl.tau0) && pl.nprobe > 1) {
+        const int64_t npairs = nq * (pl.nprobe - 1);
+        prune_table_kernel<<<(unsigned)((npairs + 3) / 4), 256, 0, s>>>(
+            pl.qrot, d, pl.cd, ix->nlist, pl.probe, pl.nprobe, pl.tau, pl.bad, pl.pfac ? pl.pw16 : nullptr,
+            pl.pscale, pl.chunk, pl.npt, npairs, pl.pfac, pl.ptable, pl.tau0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (later) {  // items of ranks 1 .. budget - 1
         item_count_kernel<<<gb, 256, 0, s>>>(pl.probe, nq, pl.nprobe, 1, pl.nprobe, pl.budget, pl.cnt0, pl.cnt1);
         batch_prefix_kernel<<<1, 1024, pow2 * sizeof(uint64_t) + ix->nlist * sizeof(int32_t), s>>>(
@@ -872,6 +1060,13 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                     out_dist, nullptr);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (pl.trace_pf && pl.npt > 0) {
+        const int64_t nslots = nq * pl.k;
+        prune_trace_kernel<<<(unsigned)((nslots + 3) / 4), 256, 0, s>>>(
+            out_ids, out_dist, pl.k, ix->assign, ix->xrow, pl.qrot, d, pl.cd, ix->nlist, pl.probe, pl.nprobe,
+            pl.tau0, pl.bad, pl.chunk, pl.npt, nslots, pl.trace_pf, pl.trace_pt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (pl.trace_need) {
         need_kernel<<<(unsigned)nq, 64, 0, s>>>(out_ids, pl.k, ix->assign, pl.probe, pl.nprobe, pl.trace_need);
         if ((e = hipGetLastError()) != hipSuccess) return e;

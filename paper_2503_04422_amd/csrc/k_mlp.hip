@@ -22,12 +22,14 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const __half *__restri
 }
 
 // Per sample: forward, loss term, and the backpropagated signals
-//   dz = (-y (1-p) + w0 (1-y) p) / n,  dh2_j = dz w3_j [a2_j > 0],
+//   weighted cross-entropy (w = w0):  dz = (-y (1-p) + w0 (1-y) p) / n,
+//   pinball at level w:               dz = ([z > y] - w) / n,
+//   dh2_j = dz w3_j [a2_j > 0],
 //   dh1_i = sum_j W2[j][i] dh2_j [a1_i > 0]
 // stored for the reduction kernel (H1, H2, DH1, DH2 are [n][64]).
 __global__ __launch_bounds__(256) void mlp_backprop_kernel(const __half *__restrict__ w, const float *__restrict__ x,
-                                                           const float *__restrict__ y, int64_t n, float w0,
-                                                           float *__restrict__ H1, float *__restrict__ H2,
+                                                           const float *__restrict__ y, int64_t n, int32_t kind,
+                                                           float w0, float *__restrict__ H1, float *__restrict__ H2,
                                                            float *__restrict__ DH1, float *__restrict__ DH2,
                                                            float *__restrict__ DZ, float *__restrict__ LS) {
     const int lane = threadIdx.x & 63;
@@ -37,7 +39,8 @@ __global__ __launch_bounds__(256) void mlp_backprop_kernel(const __half *__restr
     const float z = mlp_forward_wave(w, x + s * kMlpIn, lane, &a1, &h1, &a2, &h2);
     const float yy = y[s];
     const float p = 1.0f / (1.0f + expf(-z));
-    const float dz = (-yy * (1.0f - p) + w0 * (1.0f - yy) * p) / (float)n;
+    const float dz = kind == PDX_LOSS_PINBALL ? ((z > yy ? 1.0f : 0.0f) - w0) / (float)n
+                                              : (-yy * (1.0f - p) + w0 * (1.0f - yy) * p) / (float)n;
     const float dh2 = a2 > 0.0f ? dz * h2f(w, kOffW3 + lane) : 0.0f;
     // dh1_i for i = lane: sum over j of W2[j][lane] dh2_j
     float dh1 = 0.0f;
@@ -49,10 +52,14 @@ __global__ __launch_bounds__(256) void mlp_backprop_kernel(const __half *__restr
     DH2[s * kMlpH + lane] = dh2;
     if (lane == 0) {
         DZ[s] = dz;
-        // softplus form of the loss term
-        const float spn = fmaxf(-z, 0.0f) + log1pf(expf(-fabsf(z)));
-        const float spp = fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z)));
-        LS[s] = (yy * spn + w0 * (1.0f - yy) * spp) / (float)n;
+        if (kind == PDX_LOSS_PINBALL) {
+            const float u = yy - z;
+            LS[s] = u * (u < 0.0f ? w0 - 1.0f : w0) / (float)n;
+        } else {  // softplus form of the loss term
+            const float spn = fmaxf(-z, 0.0f) + log1pf(expf(-fabsf(z)));
+            const float spp = fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z)));
+            LS[s] = (yy * spn + w0 * (1.0f - yy) * spp) / (float)n;
+        }
     }
 }
 
@@ -151,11 +158,11 @@ hipError_t launch_mlp_forward(const __half *w16, const float *x, int64_t n, floa
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const MlpLayout &L, const float *x, const float *y, int64_t n, float w0, float *work,
-                           float *grad, float *loss, hipStream_t s) {
+hipError_t launch_mlp_grad(const MlpLayout &L, const float *x, const float *y, int64_t n, int32_t kind, float w0,
+                           float *work, float *grad, float *loss, hipStream_t s) {
     float *H1 = work, *H2 = H1 + n * kMlpH, *DH1 = H2 + n * kMlpH, *DH2 = DH1 + n * kMlpH, *DZ = DH2 + n * kMlpH,
           *LS = DZ + n;
-    mlp_backprop_kernel<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(L.w16, x, y, n, w0, H1, H2, DH1, DH2, DZ, LS);
+    mlp_backprop_kernel<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(L.w16, x, y, n, kind, w0, H1, H2, DH1, DH2, DZ, LS);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     mlp_grad_reduce_kernel<<<(kMlpPad + 255) / 256, 256, 0, s>>>(x, n, H1, H2, DH1, DH2, DZ, LS, grad, loss);

@@ -134,6 +134,25 @@ struct SlotMap {
     }
 };
 
+// The test of a bucket of probe rank r >= 1 after c1 < D dimensions: drop
+// a vector when its partial distance exceeds tau_now * factor, with factor
+// (c1/D) (1 + eps0/sqrt(c1))^2 (ADSampling), or (c1/D) m from the learned
+// table fac [nq][nprobe-1][npt] at test point c = c0 / chunk.  After all D
+// dimensions the factor is 1 (exact).
+struct PruneRule {
+    float eps0;
+    const float *fac;  // null: ADSampling
+    int32_t npt;       // test points per bucket: ceil(D / chunk) - 1
+    __device__ __forceinline__ float ads(int32_t c1, int32_t d) const {
+        const float dc = (float)c1;
+        const float f = 1.0f + eps0 / sqrtf(dc);
+        return (dc / (float)d) * f * f;
+    }
+    __device__ __forceinline__ float learned(int64_t q, int32_t r, int32_t nprobe, int32_t c) const {
+        return fac[((size_t)q * (nprobe - 1) + (r - 1)) * npt + c];
+    }
+};
+
 struct IvfPlan {
     int64_t nq;
     int32_t k;
@@ -156,6 +175,15 @@ struct IvfPlan {
     float zthr;        // stop when the logit exceeds this
     float *trace_f;
     int32_t *trace_need;
+    const __half *pw16;   // prune-multiplier network (null: ADSampling)
+    float pscale;         // multiplier scale
+    float *pfac;          // [nq][nprobe-1][npt] learned test factors
+    float *ptable;        // optional out: the multipliers
+    float *trace_pf;      // prune traces: [nq][k][npt][72] inputs
+    float *trace_pt;      // [nq][k][npt] targets
+    float *tau0;          // [nq] k-th distance after START (prune network / traces)
+    int32_t npt;          // test points per bucket
+    PruneRule rule;
     int32_t matrix;    // bucket scan on the matrix cores (16 queries per wave)
     int32_t qb0, qb1;  // queries per wave in the START / later bucket scans
     int32_t bond;      // PDX-BOND bound instead of ADSampling
@@ -185,7 +213,7 @@ hipError_t launch_ivf_mscan(bool prune, int32_t store, int32_t tiles, const void
                             int32_t d, const int32_t *slot_id, const int32_t *goff, const float *cen,
                             const int2 *items, int64_t nbatch, const int32_t *xcd_range, const int32_t *probe,
                             int32_t nprobe, const float *qrot, uint32_t *tau, const int32_t *bad, SlotMap slots,
-                            int32_t chunk, float eps0, unsigned long long *counters, hipStream_t s);
+                            int32_t chunk, PruneRule rule, unsigned long long *counters, hipStream_t s);
 
 // Item slots for nq queries x `ranks` probe ranks when every bucket's count
 // is rounded up to a multiple of qb (at most qb - 1 padding slots per bucket).
@@ -287,8 +315,8 @@ struct MlpLayout {
 MlpLayout mlp_layout(void *base);
 hipError_t launch_mlp_init(const MlpLayout &L, const float *theta0, hipStream_t s);
 hipError_t launch_mlp_forward(const __half *w16, const float *x, int64_t n, float *z, hipStream_t s);
-hipError_t launch_mlp_grad(const MlpLayout &L, const float *x, const float *y, int64_t n, float w0, float *work,
-                           float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_grad(const MlpLayout &L, const float *x, const float *y, int64_t n, int32_t kind, float w0,
+                           float *work, float *grad, float *loss, hipStream_t s);
 hipError_t launch_mlp_adam(const MlpLayout &L, float lr, int64_t step, hipStream_t s);
 size_t mlp_work_floats(int64_t n);
 

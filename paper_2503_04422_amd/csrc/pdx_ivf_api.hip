@@ -317,6 +317,22 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
         set_error("pdx_search_ivf: the PDX-BOND bound scans f32 storage only");
         return PDX_EUNSUPPORTED;
     }
+    if (params && params->prune_mlp && params->bound != 0) {
+        set_error("pdx_search_ivf: the learned prune multiplier replaces the ADSampling test (bound 0)");
+        return PDX_EINVAL;
+    }
+    if (params && !(params->prune_scale >= 0.0f && params->prune_scale < INFINITY)) {
+        set_error("pdx_search_ivf: prune_scale must be finite and >= 0");
+        return PDX_EINVAL;
+    }
+    if (params && params->prune_table && !params->prune_mlp) {
+        set_error("pdx_search_ivf: prune_table needs prune_mlp");
+        return PDX_EINVAL;
+    }
+    if (params && (!params->trace_prune_features) != (!params->trace_prune_target)) {
+        set_error("pdx_search_ivf: trace_prune_features and trace_prune_target go together");
+        return PDX_EINVAL;
+    }
     if (params && (params->engine < 0 || params->engine > 2)) {
         set_error("pdx_search_ivf: engine must be 0, 1 or 2");
         return PDX_EINVAL;

@@ -44,11 +44,21 @@ pdx_status pdx_mlp_forward(const void *mlp, const float *x, int64_t n, float *z,
     return PDX_OK;
 }
 
-pdx_status pdx_mlp_grad(const void *mlp, const float *x, const float *y, int64_t n, float w0, void *ws,
-                        size_t ws_bytes, float *grad, float *loss, void *stream) {
+namespace {
+// w: the negatives' weight w0 >= 0 (PDX_LOSS_BCE) or the level in (0, 1)
+// (PDX_LOSS_PINBALL)
+bool loss_ok(int32_t kind, float w) {
+    if (kind == PDX_LOSS_BCE) return w >= 0.0f && w < INFINITY;
+    if (kind == PDX_LOSS_PINBALL) return w > 0.0f && w < 1.0f;
+    return false;
+}
+}  // namespace
+
+pdx_status pdx_mlp_grad(const void *mlp, const float *x, const float *y, int64_t n, int32_t loss_kind, float w,
+                        void *ws, size_t ws_bytes, float *grad, float *loss, void *stream) {
     const char *what = "pdx_mlp_grad";
-    if (n < 1 || !mlp || !x || !y || !ws || !grad || !(w0 >= 0.0f)) {
-        set_error("pdx_mlp_grad: need n >= 1, w0 >= 0 and non-null pointers");
+    if (n < 1 || !mlp || !x || !y || !ws || !grad || !loss_ok(loss_kind, w)) {
+        set_error("pdx_mlp_grad: need n >= 1, a known loss with a valid w and non-null pointers");
         return PDX_EINVAL;
     }
     if (ws_bytes < pdx_mlp_workspace(n)) {
@@ -56,15 +66,17 @@ pdx_status pdx_mlp_grad(const void *mlp, const float *x, const float *y, int64_t
         return PDX_EWORKSPACE;
     }
     MlpLayout L = mlp_layout(const_cast<void *>(mlp));
-    TRY(launch_mlp_grad(L, x, y, n, w0, static_cast<float *>(ws), grad, loss, static_cast<hipStream_t>(stream)));
+    TRY(launch_mlp_grad(L, x, y, n, loss_kind, w, static_cast<float *>(ws), grad, loss,
+                        static_cast<hipStream_t>(stream)));
     return PDX_OK;
 }
 
-pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y, int64_t n, float w0, float lr, int64_t step,
-                              void *ws, size_t ws_bytes, float *loss, void *stream) {
+pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y, int64_t n, int32_t loss_kind, float w,
+                              float lr, int64_t step, void *ws, size_t ws_bytes, float *loss, void *stream) {
     const char *what = "pdx_mlp_train_step";
-    if (n < 1 || !mlp || !x || !y || !ws || step < 1 || !(lr > 0.0f) || !(w0 >= 0.0f)) {
-        set_error("pdx_mlp_train_step: need n >= 1, step >= 1, lr > 0, w0 >= 0 and non-null pointers");
+    if (n < 1 || !mlp || !x || !y || !ws || step < 1 || !(lr > 0.0f) || !loss_ok(loss_kind, w)) {
+        set_error("pdx_mlp_train_step: need n >= 1, step >= 1, lr > 0, a known loss with a valid w and "
+                  "non-null pointers");
         return PDX_EINVAL;
     }
     if (ws_bytes < pdx_mlp_workspace(n)) {
@@ -73,7 +85,7 @@ pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y, int64_t
     }
     MlpLayout L = mlp_layout(mlp);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    TRY(launch_mlp_grad(L, x, y, n, w0, static_cast<float *>(ws), L.g, loss ? loss : L.loss, s));
+    TRY(launch_mlp_grad(L, x, y, n, loss_kind, w, static_cast<float *>(ws), L.g, loss ? loss : L.loss, s));
     TRY(launch_mlp_adam(L, lr, step, s));
     return PDX_OK;
 }

@@ -56,8 +56,9 @@ pdx_status pdx_ivf_tune(const pdx_index *index, const float *q, int64_t nq, int3
         pdx::set_error("pdx_ivf_tune: need index, params, queries, workspace, nq >= 1 and reps >= 1");
         return PDX_EINVAL;
     }
-    if (params->mlp || params->trace_features || params->trace_need) {
-        pdx::set_error("pdx_ivf_tune: tune the search without the network or traces");
+    if (params->mlp || params->trace_features || params->trace_need || params->prune_mlp || params->prune_table ||
+        params->trace_prune_features || params->trace_prune_target) {
+        pdx::set_error("pdx_ivf_tune: tune the search without the networks or traces");
         return PDX_EINVAL;
     }
     const size_t need = pdx_ivf_tune_workspace(index, nq, k, nprobe, params);

@@ -44,3 +44,15 @@ def test_host_side_argument_errors():
     assert lib.pdx_search_exact_workspace(None, 1, 10, None) == 0
     assert lib.pdx_search_ivf(None, None, 1, 10, 1, None, None, 0, None, None, None) == _lib.PDX_EINVAL
     assert lib.pdx_version().startswith(b"pdx ")
+
+
+def test_network_loss_arguments_checked_on_the_host():
+    from paper_2503_04422_amd import _lib
+    lib = _lib.lib
+    fake = ctypes.c_void_p(4096)  # never dereferenced: the arguments are rejected first
+    for kind, w in ((7, 0.5), (_lib.PDX_LOSS_PINBALL, 0.0), (_lib.PDX_LOSS_PINBALL, 1.0),
+                    (_lib.PDX_LOSS_BCE, -1.0), (_lib.PDX_LOSS_BCE, float("inf"))):
+        assert lib.pdx_mlp_grad(fake, fake, fake, 4, kind, w, fake, 1 << 30, fake, None, None) == _lib.PDX_EINVAL
+        assert lib.pdx_mlp_train_step(fake, fake, fake, 4, kind, w, 1e-3, 1, fake, 1 << 30, None,
+                                      None) == _lib.PDX_EINVAL
+    assert b"loss" in lib.pdx_last_error()

@@ -11,6 +11,19 @@ traces it is trained on.
   centroid-distance ratios);
 * a network that never fires gives the plain search's result bit for bit;
   one that always fires gives the result of probing 1 bucket.
+
+Prune multiplier:
+* the pinball gradient and loss equal the oracle's;
+* the multipliers the search computes after START equal the oracle's
+  network evaluated on the oracle's inputs (START threshold, centroid
+  distances, test points);
+* traces of an exact search: targets and inputs equal the oracle's for
+  every returned neighbour (NaN for the START bucket's);
+* a huge multiplier gives the exact-within-buckets search bit for bit and
+  a vanishing one the START bucket's result, on every scan engine;
+* designed networks' searches have the oracle's recall within 0.03;
+* pinball training on the device, with its final bias calibration, covers
+  its level of the training targets.
 """
 import numpy as np
 import pytest
@@ -96,7 +109,7 @@ def ivf(pdx):
     c, lab, _ = kmeans.lloyd(x, init, 6)
     c32 = c.astype(np.float32)
     ix = pdx.pdx_ivf_build(_dev(x), nlist, None, None, centroids=_dev(c32), assign=_dev(lab.astype(np.int32)))
-    return dict(x=x, q=q, c32=c32, lists=kmeans.lists_from_labels(lab, nlist), ix=ix)
+    return dict(x=x, q=q, c32=c32, lists=kmeans.lists_from_labels(lab, nlist), ix=ix, mix=mix, labels=lab)
 
 
 def test_budget_traces_match_oracle(pdx, ivf):
@@ -155,3 +168,170 @@ def test_abstaining_and_always_stopping_networks(pdx, ivf):
         ai, ad = (_np(t) for t in pdx.pdx_search_ivf(ivf["ix"], _dev(q), k, 24, eps0=float("inf"), engine=engine,
                                                       mlp=pdx.MlpState(_dev(always)), mlp_threshold=0.5))
         assert np.array_equal(ai, one_i) and np.array_equal(ad, one_d)
+
+
+# ---------------------------------------------------------------------------
+# learned prune multiplier
+# ---------------------------------------------------------------------------
+
+def _net(entries, b3):
+    parts = {"W1": np.zeros((64, 72)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+             "w3": np.zeros(64), "b3": np.array([b3])}
+    for (name, idx), v in entries.items():
+        parts[name][idx] = v
+    return omlp.pack(parts).astype(np.float32)
+
+
+def test_pinball_gradient_and_loss_match_oracle(pdx):
+    th = _theta(11)
+    st = pdx.MlpState(_dev(th))
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((300, omlp.F_IN)).astype(np.float32)
+    th16 = omlp.fp16_round(th)
+    z, _ = omlp.forward(th16, x)
+    y = (z + rng.uniform(0.05, 1.0, 300) * rng.choice([-1.0, 1.0], 300)).astype(np.float32)  # no kinks
+    g, loss = st.grad(_dev(x), _dev(y), 0.9, kind="pinball")
+    g, loss = _np(g), float(_np(loss)[0])
+    gw = omlp.grad(th16, x, y.astype(np.float64), 0.9, "pinball")
+    np.testing.assert_allclose(g[:omlp.P_USED], gw[:omlp.P_USED], rtol=1e-3, atol=1e-3 * np.abs(gw).max())
+    assert abs(loss - omlp.loss(th16, x, y.astype(np.float64), 0.9, "pinball")) <= 1e-4 * abs(loss)
+
+
+def _probe_context(ivf, i, k, nprobe):
+    """Oracle probe order, sorted probed centroid distances, START threshold,
+    or None when a rounding-level tie decides the probe order."""
+    x, q, c32, lists = ivf["x"], ivf["q"], ivf["c32"], ivf["lists"]
+    q64 = q[i].astype(np.float64)
+    cd = np.sort(exact.sqdist(c32, q64))
+    if np.any(np.diff(cd[: nprobe + 1]) <= 1e-6 * cd[nprobe]):
+        return None
+    order = px.ivf_probe_order(c32, q64, nprobe)
+    start = px.ivf_flat(x, lists, c32, q64, k, 1)[1]
+    tau = start[-1] if np.isfinite(start[-1]) else np.inf
+    return order, cd[:nprobe], tau
+
+
+def test_prune_table_matches_oracle(pdx, ivf):
+    import torch
+    q = ivf["q"]
+    nq, k, nprobe, dd = q.shape[0], 10, 12, 24  # D = 96: tests after 24, 48, 72 dimensions
+    npt = pdx.ivf_test_points(96)
+    assert npt == 3
+    th = _theta(13, 0.05)
+    st = pdx.MlpState(_dev(th))
+    th16 = omlp.fp16_round(th)
+    for engine in (1, 2):
+        table = torch.empty((nq, nprobe - 1, npt), dtype=torch.float32, device="cuda")
+        pdx.pdx_search_ivf(ivf["ix"], _dev(q), k, nprobe, prune_mlp=st, prune_scale=1.5, prune_table=table,
+                           engine=engine)
+        table = _np(table)
+        checked = 0
+        for i in range(nq):
+            ctx = _probe_context(ivf, i, k, nprobe)
+            if ctx is None:
+                continue
+            _, cd, tau = ctx
+            want = omlp.prune_multipliers(th16, q[i].astype(np.float64), tau, cd, nprobe, dd, 1.5)
+            np.testing.assert_allclose(table[i], want, rtol=2e-3)
+            checked += 1
+        assert checked >= nq - 3
+
+
+def test_prune_traces_match_oracle(pdx, ivf):
+    import torch
+    x, q, c32, lists, labels = ivf["x"], ivf["q"], ivf["c32"], ivf["lists"], ivf["labels"]
+    nq, k, nprobe, dd = q.shape[0], 10, 12, 24
+    npt = 3
+    pf = torch.empty((nq, k, npt, 72), dtype=torch.float32, device="cuda")
+    pt = torch.empty((nq, k, npt), dtype=torch.float32, device="cuda")
+    gi, gd = pdx.pdx_search_ivf(ivf["ix"], _dev(q), k, nprobe, eps0=float("inf"), prune_trace=(pf, pt))
+    pf, pt, gi, gd = _np(pf), _np(pt), _np(gi), _np(gd)
+    want = [px.ivf_flat(x, lists, c32, q[i].astype(np.float64), k, nprobe) for i in range(nq)]
+    check_knn(x, q, gi, gd, np.stack([w[0] for w in want]), np.stack([w[1] for w in want]))
+    checked = samples = 0
+    for i in range(nq):
+        ctx = _probe_context(ivf, i, k, nprobe)
+        if ctx is None or gi[i].tolist() != want[i][0].tolist():
+            continue  # probe order or neighbour order decided by a rounding-level tie
+        order, cd, tau = ctx
+        rank = {int(b): r for r, b in enumerate(order)}
+        q64 = q[i].astype(np.float64)
+        targets = omlp.prune_targets(x, q64, want[i][0], want[i][1][-1], dd)
+        for a, v in enumerate(want[i][0]):
+            r = rank[int(labels[v])]
+            if r == 0:  # START bucket: scanned whole, no sample
+                assert np.isnan(pt[i, a]).all() and np.all(pf[i, a] == 0)
+                continue
+            np.testing.assert_allclose(pt[i, a], targets[a], rtol=0, atol=1e-4)
+            for c, c1 in enumerate(omlp.test_points(96, dd)):
+                ref = omlp.prune_inputs(q64, tau, cd, r, nprobe, c1)
+                assert np.array_equal(pf[i, a, c, :64], q[i, :64])
+                np.testing.assert_allclose(pf[i, a, c, 64:70], ref[64:70], rtol=1e-4)
+                assert np.all(pf[i, a, c, 70:] == 0)
+            samples += 1
+        checked += 1
+    assert checked >= nq - 5 and samples >= 100
+
+
+def test_prune_extremes_on_every_engine(pdx, ivf):
+    q, k = ivf["q"], 10
+    keep_all = pdx.MlpState(_dev(_net({}, 80.0)))   # m = 1e30 (capped): nothing is dropped before D
+    drop_all = pdx.MlpState(_dev(_net({}, -80.0)))  # m = 2e-35: every positive partial is dropped
+    for engine, qpw in ((1, 1), (1, 4), (2, 0)):
+        sched = dict(engine=engine, queries_per_wave=qpw)
+        print(f"prune extremes engine {engine} qpw {qpw}", flush=True)
+        base_i, base_d = (_np(t) for t in pdx.pdx_search_ivf(ivf["ix"], _dev(q), k, 24, eps0=float("inf"), **sched))
+        gi, gd = (_np(t) for t in pdx.pdx_search_ivf(ivf["ix"], _dev(q), k, 24, prune_mlp=keep_all, **sched))
+        assert np.array_equal(gi, base_i) and np.array_equal(gd, base_d)
+        one_i, one_d = (_np(t) for t in pdx.pdx_search_ivf(ivf["ix"], _dev(q), k, 1, eps0=float("inf"), **sched))
+        gi, gd = (_np(t) for t in pdx.pdx_search_ivf(ivf["ix"], _dev(q), k, 24, prune_mlp=drop_all, **sched))
+        assert np.array_equal(gi, one_i) and np.array_equal(gd, one_d)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.0])
+def test_designed_network_recall_band(pdx, ivf, alpha):
+    """m = exp(alpha / sqrt(c1)): one hidden unit passes input 69
+    (1/sqrt(c1)); alpha 1 keeps about 95% of IVF-flat's neighbours in the
+    oracle's sequential search, alpha 0 (m = 1) about 85%.  The device
+    tightens the threshold inside a bucket while the sequential search
+    holds it per bucket, hence a band of 0.03."""
+    x, q, c32, lists = ivf["x"], ivf["q"], ivf["c32"], ivf["lists"]
+    nq, k, nprobe, dd = q.shape[0], 10, 12, 24
+    th = _net({("W1", (0, 69)): alpha, ("W2", (0, 0)): 1.0, ("w3", 0): 1.0}, 0.0)
+    st = pdx.MlpState(_dev(th))
+    th16 = omlp.fp16_round(th)
+    flat, seq = [], []
+    for i in range(nq):
+        q64 = q[i].astype(np.float64)
+        order = px.ivf_probe_order(c32, q64, nprobe)
+        cd = exact.sqdist(c32, q64)[order]
+        start = px.ivf_flat(x, lists, c32, q64, k, 1)[1]
+        tau = start[-1] if np.isfinite(start[-1]) else np.inf
+        mult = omlp.prune_multipliers(th16, q64, tau, cd, nprobe, dd)
+        seq.append(px.learned_ivf_search(x, lists, c32, q64, k, nprobe, mult, dd)[0])
+        flat.append(px.ivf_flat(x, lists, c32, q64, k, nprobe)[0])
+    flat, seq = np.stack(flat), np.stack(seq)
+    r_seq = exact.recall_at_k(flat, seq)
+    assert r_seq < 0.99  # the multipliers do prune neighbours: the band is a real check
+    for engine in (1, 2):
+        gi, gd = (_np(t) for t in pdx.pdx_search_ivf(ivf["ix"], _dev(q), k, nprobe, prune_mlp=st, engine=engine))
+        r_dev = exact.recall_at_k(flat, gi)
+        print(f"alpha {alpha} engine {engine}: recall {r_dev:.4f}, oracle sequential {r_seq:.4f}", flush=True)
+        assert abs(r_dev - r_seq) <= 0.03
+        ok = gi >= 0
+        true = ((x[gi[ok]].astype(np.float64) - q.astype(np.float64)[np.nonzero(ok)[0]]) ** 2).sum(1)
+        np.testing.assert_allclose(gd[ok], true, rtol=1e-5)
+
+
+def test_pinball_training_calibrates_the_multiplier(pdx, ivf):
+    qt = ivf["mix"].queries(800, 99)
+    feats, targets, stats = pdx.learn.prune_traces(ivf["ix"], _dev(qt), 10, 12)
+    assert stats["samples"] >= 2000 and stats["test_points"] == 3
+    st, info = pdx.learn.train_prune_network(feats, targets, steps=1500, batch=2048, lr=3e-3, level=0.9)
+    z = _np(st.forward(feats))
+    t = _np(targets)
+    frac = float(np.mean(t <= z))
+    print(f"samples {t.size}, loss {info['loss_first']:.4f} -> {info['loss_last']:.4f}, covered {frac:.3f}",
+          flush=True)
+    assert info["loss_last"] < info["loss_first"]
+    assert abs(frac - 0.9) <= 0.01  # the bias calibration (rounded to float16 in the deployed copy)

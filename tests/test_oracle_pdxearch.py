@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import exact, kmeans, pdxearch as px
+from oracle import exact, kmeans, mlp, pdxearch as px
 from oracle.layout import column_means_f32
 from tests.conftest import golden
 
@@ -135,3 +135,61 @@ def test_means_rounding_is_single():
     m = column_means_f32(x)
     assert m[0] == np.float32(7.0 / 3.0)
     assert m[1] == np.float32((np.float64(np.float32(0.1)) + np.float64(np.float32(0.2)) + np.float64(np.float32(0.3))) / 3)
+
+
+# ---------------------------------------------------------------------------
+# the learned prune multiplier's search (one multiplier per bucket and test)
+# ---------------------------------------------------------------------------
+
+def _ads_rows(eps0, d, dd, nprobe):
+    pts = np.arange(dd, d, dd, dtype=np.float64)
+    return np.tile((1.0 + eps0 / np.sqrt(pts)) ** 2, (nprobe - 1, 1))
+
+
+def test_table_search_reduces_to_ads_and_to_ivf_flat():
+    x, q, c, lists = _small_ivf(seed=4)
+    nprobe, dd = 8, 16
+    for i in range(q.shape[0]):
+        qq = q[i].astype(np.float64)
+        ai, ad = px.ads_ivf_search(x, lists, c, qq, 10, nprobe, eps0=2.1, delta_d=dd)
+        ti, td = px.learned_ivf_search(x, lists, c, qq, 10, nprobe, _ads_rows(2.1, 64, dd, nprobe), dd)
+        assert ti.tolist() == ai.tolist() and np.array_equal(td, ad)
+        fi, fd = px.ivf_flat(x, lists, c, qq, 10, nprobe)
+        ti, td = px.learned_ivf_search(x, lists, c, qq, 10, nprobe, np.full((nprobe - 1, 3), 1e30), dd)
+        assert ti.tolist() == fi.tolist()
+        # multipliers of 0 drop every vector with a positive partial: only START remains
+        si, sd = px.ivf_flat(x, lists, c, qq, 10, 1)
+        ti, td = px.learned_ivf_search(x, lists, c, qq, 10, nprobe, np.zeros((nprobe - 1, 3)), dd)
+        assert ti.tolist() == si.tolist()
+
+
+def test_multipliers_from_the_targets_keep_every_neighbour():
+    """A multiplier at or above each returned neighbour's target (the
+    largest over the neighbours in that bucket; 0 for buckets holding none)
+    keeps every neighbour, because the threshold in force never falls below
+    the final k-th distance: the search returns IVF-flat's result, while a
+    multiplier just below a target loses that neighbour."""
+    x, q, c, lists = _small_ivf(seed=5, n=4000, d=64, nlist=20)
+    nprobe, dd, k = 10, 16, 10
+    labels = np.empty(x.shape[0], np.int64)
+    for l, rows in enumerate(lists):
+        labels[rows] = l
+    lost = 0
+    for i in range(q.shape[0]):
+        qq = q[i].astype(np.float64)
+        fi, fd = px.ivf_flat(x, lists, c, qq, k, nprobe)
+        probe = px.ivf_probe_order(c, qq, nprobe)
+        rank = {int(b): r for r, b in enumerate(probe)}
+        t = mlp.prune_targets(x, qq, fi, fd[-1], dd)
+        mult = np.zeros((nprobe - 1, t.shape[1]))
+        for a, v in enumerate(fi):
+            r = rank[int(labels[v])]
+            if r >= 1:
+                mult[r - 1] = np.maximum(mult[r - 1], np.exp(t[a]) * (1 + 1e-12))
+        gi, gd = px.learned_ivf_search(x, lists, c, qq, k, nprobe, mult, dd)
+        assert gi.tolist() == fi.tolist()
+        # the same multipliers lowered a little lose a neighbour outside START
+        if mult.max() > 0:
+            gi2, _ = px.learned_ivf_search(x, lists, c, qq, k, nprobe, mult * 0.5, dd)
+            lost += gi2.tolist() != fi.tolist()
+    assert lost >= 1
