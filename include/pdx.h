@@ -255,30 +255,30 @@ typedef struct {
                                  is exact within the probed buckets (eps0,
                                  engine and queries_per_wave are ignored;
                                  f32 storage only)                          */
-    /* Learned prune multiplier (see pdx_mlp_*; NULL = ADSampling's).       */
-    const void *prune_mlp;    /* network state: after START, every (query,
-                                 rank r >= 1, test point c) gets the
-                                 multiplier m = prune_scale * exp(z) in
-                                 place of (1 + eps0/sqrt(c1))^2 (bound 0
-                                 only; eps0 is then unused)                 */
-    float prune_scale;        /* > 0; 0 = 1                                 */
-    float *prune_table;       /* optional out, [nq][nprobe-1][C]: m of rank
-                                 r (row r - 1) at test point c; needs
-                                 prune_mlp                                   */
+    /* Learned prune bound (see pdx_mlp_*; NULL = ADSampling's eps0).       */
+    const void *prune_mlp;    /* network state: after START every (query,
+                                 rank r >= 1) gets its own eps, the
+                                 multiplier at test point c being
+                                 max(1 + eps/sqrt(c1), 0)^2 (bound 0 only;
+                                 eps0 is then unused)                       */
+    float prune_scale;        /* eps = prune_scale * z; > 0; 0 = 1          */
+    float *prune_table;       /* optional out, [nq][nprobe-1][C]: the
+                                 multiplier of rank r (row r - 1) at test
+                                 point c; needs prune_mlp                    */
     /* Prune-network traces (NULL = off; the search itself is unchanged):   */
-    float *trace_prune_features; /* [nq][k][C][72]: the inputs for (query,
-                                    rank of the bucket of the i-th returned
-                                    id, c)                                   */
-    float *trace_prune_target;   /* [nq][k][C]: ln(partial * D/(c1 tau_k))
-                                    of the i-th returned id after c1
-                                    dimensions (partial in the rotated
-                                    space, dimensions in natural order);
-                                    NaN where there is no sample: no id,
-                                    an id of the START bucket, or tau_k not
-                                    positive and finite.  Labels hold for
-                                    the exact result when the search is
-                                    exact within the probed buckets
-                                    (eps0 = +INFINITY or bound 1)            */
+    float *trace_prune_features; /* [nq][k][72]: the inputs for (query,
+                                    rank of the bucket of the i-th
+                                    returned id)                             */
+    float *trace_prune_target;   /* [nq][k]: the smallest eps keeping the
+                                    i-th returned id at every test point
+                                    (partials in the rotated space,
+                                    dimensions in natural order); NaN where
+                                    there is no sample: no id, an id of the
+                                    START bucket, tau_k not positive and
+                                    finite.  Targets hold for the exact
+                                    result when the search is exact within
+                                    the probed buckets (eps0 = +INFINITY or
+                                    bound 1)                                 */
 } pdx_ivf_search_params;
 
 /* pdx_ivf_tune -- pick the fastest scan schedule for a workload.
@@ -350,19 +350,21 @@ PDX_API pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_
  * probed), then 3 zeros; z is a logit.  The query probes the smallest r
  * whose output fires.
  *
- * Prune multiplier (pdx_ivf_search_params.prune_mlp).  For each bucket of
- * probe rank r >= 1 and each test point c (after c1 = (c + 1) delta_d < D
- * dimensions; C = ceil(D / delta_d) - 1 points) the network sees: the same
- * 64 coordinates, then tau/d_r, d_r/d_0, tau/d_0, log2(r)/log2(nprobe),
- * c1/D and 1/sqrt(c1) (d_r: the bucket being scanned), then 2 zeros; the
- * multiplier is m = prune_scale * exp(z), capped at 1e30.  A vector of
- * that bucket is dropped after c1 dimensions when partial * D/c1 >
- * tau_now * m, in place of ADSampling's (1 + eps0/sqrt(c1))^2; the test
- * after all D dimensions stays exact.  Its training target for a returned
- * neighbour (outside the START bucket) is ln(partial * D / (c1 * tau_k)),
- * tau_k being the search's final k-th distance: a multiplier at or above
- * it keeps that neighbour whatever the running threshold, so the network
- * is trained for a high quantile of it (PDX_LOSS_PINBALL).
+ * Prune bound (pdx_ivf_search_params.prune_mlp).  For the bucket of probe
+ * rank r >= 1 the network sees the same 64 coordinates, then tau/d_r,
+ * d_r/d_0, tau/d_0 and log2(r)/log2(nprobe) (d_r: the bucket being
+ * scanned), then 4 zeros; eps = prune_scale * z is that (query, bucket)'s
+ * error bound.  After c1 < D dimensions (test points c1 =
+ * (c + 1) delta_d; C = ceil(D / delta_d) - 1 of them) a vector of the
+ * bucket is dropped when partial * D/c1 > tau_now * m with
+ * m = max(1 + eps/sqrt(c1), 0)^2 (capped at 1e30), ADSampling's
+ * (1 + eps0/sqrt(c1))^2 with a learned eps in place of eps0; the test after
+ * all D dimensions stays exact.  Its training target for a returned
+ * neighbour outside the START bucket is the smallest eps that keeps it at
+ * every test point, max over c of (sqrt(partial(c1) * D / (c1 * tau_k)) -
+ * 1) * sqrt(c1), tau_k being the search's final k-th distance (the running
+ * threshold never falls below it); the network is trained for a high
+ * quantile of it (PDX_LOSS_PINBALL).
  *
  * State buffer (pdx_mlp_bytes): float32 parameters W1[64][72] b1[64]
  * W2[64][64] b2[64] w3[64] b3 (8897 used, 8960 padded), Adam moments,

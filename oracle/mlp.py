@@ -4,7 +4,7 @@ oracle (test infrastructure).
 The paper prunes with fixed rules; these networks are additions beside the
 ADSampling test (Section 2.3) and the fixed-nprobe IVF search (Section
 2.1): a per-query probe budget (a stop decision per probe count) and a
-per-(query, bucket, test point) prune multiplier.
+per-(query, bucket) error bound for the ADSampling-shaped prune test.
 Architecture: x (F = 72 inputs) -> h1 = relu(W1 x + b1) (64)
 -> h2 = relu(W2 h1 + b2) (64) -> z = w3 . h2 + b3.  The search uses the
 weights rounded to float16, so the oracle evaluates the same rounded
@@ -16,13 +16,14 @@ Losses (mean over n samples):
   costs recall:
       L = (1/n) sum( -y log p - w0 (1 - y) log(1 - p) ),
       dL/dz = (1/n)(-y (1-p) + w0 (1-y) p);
-* "pinball" at level w in (0, 1), prune multiplier, y a real target, z
+* "pinball" at level w in (0, 1), prune bound, y a real target, z
   then estimates the w-quantile of y (quantile regression):
       L = (1/n) sum( u (w - [u < 0]) ),  u = y - z,
       dL/dz = (1/n)([z > y] - w).
 
-Prune multiplier: for a bucket of probe rank r >= 1 after c1 of D
-dimensions, m = scale * exp(z) (capped at 1e30) replaces
+Prune bound: the network gives each (query, bucket of probe rank r >= 1)
+an error bound eps = scale * z; after c1 of D dimensions the multiplier
+m = max(1 + eps/sqrt(c1), 0)^2 (capped at 1e30) replaces ADSampling's
 (1 + eps0/sqrt(c1))^2 in the test partial * D/c1 > tau * m.
 
 Parameter vector layout (float32 on the device, float64 here):
@@ -130,25 +131,22 @@ def numeric_grad(theta: np.ndarray, x: np.ndarray, y: np.ndarray, w0: float, idx
 
 
 # --------------------------------------------------------------------------
-# prune multiplier: inputs, multipliers, training targets
+# prune bound: inputs, multipliers, training targets
 # --------------------------------------------------------------------------
 
-def prune_inputs(qrot: np.ndarray, tau: float, cd: np.ndarray, r: int, nprobe: int, c1: int) -> np.ndarray:
-    """The 72 inputs for a bucket of probe rank r >= 1 after c1 dimensions:
-    the first 64 rotated query coordinates (zero-padded), then tau/d_r,
-    d_r/d_0, tau/d_0 (each clamped to [0, 1e4]), log2(r)/log2(nprobe), c1/D,
-    1/sqrt(c1), then 2 zeros.  tau: the k-th distance in the START bucket;
-    cd: squared centroid distances of the probed buckets, nearest first."""
+def prune_inputs(qrot: np.ndarray, tau: float, cd: np.ndarray, r: int, nprobe: int) -> np.ndarray:
+    """The 72 inputs for the bucket of probe rank r >= 1: the first 64
+    rotated query coordinates (zero-padded), then tau/d_r, d_r/d_0, tau/d_0
+    (each clamped to [0, 1e4]) and log2(r)/log2(nprobe), then 4 zeros.
+    tau: the k-th distance in the START bucket; cd: squared centroid
+    distances of the probed buckets, nearest first."""
     d = qrot.shape[0]
     x = np.zeros(F_IN, dtype=np.float64)
     m = min(d, 64)
     x[:m] = qrot[:m]
     d0, dr = max(cd[0], 1e-20), max(cd[r], 1e-20)  # a zero distance is read as 1e-20
-    ratios = np.array([tau / dr, dr / d0, tau / d0], dtype=np.float64)
-    x[64:67] = np.clip(ratios, 0.0, 1e4)
+    x[64:67] = np.clip(np.array([tau / dr, dr / d0, tau / d0], dtype=np.float64), 0.0, 1e4)
     x[67] = np.log2(r) / np.log2(nprobe)
-    x[68] = c1 / d
-    x[69] = 1.0 / np.sqrt(c1)
     return x
 
 
@@ -158,25 +156,30 @@ def test_points(d: int, delta_d: int):
     return list(range(delta_d, d, delta_d))
 
 
+def multiplier(eps: float, c1: int) -> float:
+    """max(1 + eps/sqrt(c1), 0)^2, capped at 1e30."""
+    b = max(1.0 + eps / np.sqrt(c1), 0.0)
+    return min(b * b, 1e30)
+
+
 def prune_multipliers(theta: np.ndarray, qrot: np.ndarray, tau: float, cd: np.ndarray, nprobe: int,
                       delta_d: int, scale: float = 1.0) -> np.ndarray:
     """m [nprobe - 1][C] of one query: row r - 1 for probe rank r."""
     pts = test_points(qrot.shape[0], delta_d)
-    rows = [prune_inputs(qrot, tau, cd, r, nprobe, c1) for r in range(1, nprobe) for c1 in pts]
-    if not rows:
-        return np.zeros((max(nprobe - 1, 0), len(pts)))
-    z, _ = forward(theta, np.stack(rows))
-    return np.minimum(scale * np.exp(z), 1e30).reshape(nprobe - 1, len(pts))
+    if nprobe < 2:
+        return np.zeros((0, len(pts)))
+    z, _ = forward(theta, np.stack([prune_inputs(qrot, tau, cd, r, nprobe) for r in range(1, nprobe)]))
+    return np.array([[multiplier(scale * e, c1) for c1 in pts] for e in z])
 
 
 def prune_targets(xrot: np.ndarray, qrot: np.ndarray, ids: np.ndarray, tau_k: float, delta_d: int) -> np.ndarray:
-    """[len(ids)][C] targets ln(max(partial(c1) * D / (c1 tau_k), 1e-30)),
+    """[len(ids)]: the smallest eps keeping each id at every test point,
+    max over c1 of (sqrt(partial(c1) D / (c1 tau_k)) - 1) sqrt(c1), with
     partial(c1) the squared distance over the first c1 rotated dimensions."""
     d = qrot.shape[0]
-    pts = test_points(d, delta_d)
     diff = np.asarray(xrot, dtype=np.float64)[np.asarray(ids, dtype=np.int64)] - qrot[None, :]
     pref = np.cumsum(diff * diff, axis=1)
-    out = np.empty((len(ids), len(pts)))
-    for c, c1 in enumerate(pts):
-        out[:, c] = np.log(np.maximum(pref[:, c1 - 1] * d / (c1 * tau_k), 1e-30))
+    out = np.full(len(ids), -np.inf)
+    for c1 in test_points(d, delta_d):
+        out = np.maximum(out, (np.sqrt(pref[:, c1 - 1] * d / (c1 * tau_k)) - 1.0) * np.sqrt(c1))
     return out

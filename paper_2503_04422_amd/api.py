@@ -192,7 +192,7 @@ _LOSSES = {"bce": _lib.PDX_LOSS_BCE, "pinball": _lib.PDX_LOSS_PINBALL}
 class MlpState:
     """Device state of one of the search's networks (pdx_mlp_*): the probe
     budget (weighted cross-entropy, kind "bce", w = the negatives' weight)
-    or the prune multiplier (kind "pinball", w = the quantile level)."""
+    or the prune bound (kind "pinball", w = the quantile level)."""
 
     def __init__(self, theta0: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
         if not theta0.is_cuda or theta0.dtype != torch.float32 or theta0.numel() != _lib.MLP_PARAMS:
@@ -253,10 +253,10 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
     """Approximate k nearest neighbours (IVF + ADSampling), optionally with the
     learned probe budget (mlp) or recording its training traces
     (trace = (features [nq, nprobe, 72] float32, need [nq] int32)), and
-    with the learned prune multiplier (prune_mlp, prune_scale; prune_table
-    receives the multipliers [nq, nprobe - 1, C]) or recording its traces
-    (prune_trace = (features [nq, k, C, 72], target [nq, k, C]) float32);
-    C = ivf_test_points(D, delta_d)."""
+    with the learned prune bound (prune_mlp, prune_scale; prune_table
+    receives the multipliers [nq, nprobe - 1, C], C = ivf_test_points(D,
+    delta_d)) or recording its traces (prune_trace = (features [nq, k, 72],
+    target [nq, k]) float32)."""
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     if q.shape[1] != index.d:
@@ -272,11 +272,10 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                                     or prune_table.numel() != nq * max(nprobe - 1, 0) * npt):
         raise TypeError(f"prune_table must be contiguous float32 [nq, nprobe - 1, {npt}]")
     pf, pt = (None, None) if prune_trace is None else prune_trace
-    if pf is not None and (pf.dtype != torch.float32 or not pf.is_contiguous()
-                           or pf.numel() != nq * k * npt * _lib.MLP_IN):
-        raise TypeError(f"prune trace features must be contiguous float32 [nq, k, {npt}, 72]")
-    if pt is not None and (pt.dtype != torch.float32 or not pt.is_contiguous() or pt.numel() != nq * k * npt):
-        raise TypeError(f"prune trace targets must be contiguous float32 [nq, k, {npt}]")
+    if pf is not None and (pf.dtype != torch.float32 or not pf.is_contiguous() or pf.numel() != nq * k * _lib.MLP_IN):
+        raise TypeError("prune trace features must be contiguous float32 [nq, k, 72]")
+    if pt is not None and (pt.dtype != torch.float32 or not pt.is_contiguous() or pt.numel() != nq * k):
+        raise TypeError("prune trace targets must be contiguous float32 [nq, k]")
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
                                    _DTYPES[dtype], int(rerank),
                                    ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,

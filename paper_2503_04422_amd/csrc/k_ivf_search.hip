@@ -10,7 +10,8 @@
 //  5. the other probed buckets are scanned chunk by chunk in the rotated
 //     (natural) dimension order; after d < D dimensions a vector is dropped
 //     when partial * D/d > tau * (1 + eps0/sqrt(d))^2 (ADSampling test of
-//     Section 2.3), or > tau * m with m from the learned multiplier table,
+//     Section 2.3), or with a learned error bound per (query, bucket) in
+//     place of eps0,
 //     at d = D when partial > tau; survivors enter the wave's k-best list,
 //     whose k-th distance tightens the query's threshold;
 //  6. merge of the per-item k-best lists.
@@ -490,46 +491,37 @@ __global__ __launch_bounds__(64) void need_kernel(const int64_t *__restrict__ id
     if (lane == 0) need[qi] = mine;
 }
 
-// Inputs 64 .. 71 of the prune-multiplier network for a bucket of probe
-// rank r >= 1 after c1 dimensions (inputs 0 .. 63: the rotated query's
-// first coordinates); the same in every lane.
-__device__ __forceinline__ void prune_inputs(float t, float d0, float dr, int32_t r, int32_t nprobe, int32_t c1,
-                                             int32_t d, float (&x)[8]) {
+// Inputs 64 .. 71 of the prune network for the bucket of probe rank
+// r >= 1 (inputs 0 .. 63: the rotated query's first coordinates); the same
+// in every lane.
+__device__ __forceinline__ void prune_inputs(float t, float d0, float dr, int32_t r, int32_t nprobe,
+                                             float (&x)[8]) {
     auto clampr = [](float v) { return fminf(fmaxf(v, 0.0f), 1.0e4f); };
     x[0] = clampr(t / dr);
     x[1] = clampr(dr / d0);
     x[2] = clampr(t / d0);
     x[3] = log2f((float)r) / log2f((float)nprobe);
-    x[4] = (float)c1 / (float)d;
-    x[5] = 1.0f / sqrtf((float)c1);
-    x[6] = 0.0f;
-    x[7] = 0.0f;
+    x[4] = x[5] = x[6] = x[7] = 0.0f;
 }
 
-// Learned prune factors after START: one wave per (query, rank r >= 1).
-// The first layer's query part is evaluated once; then, for groups of
-// kPtGroup test points (c1 = (c + 1) chunk < d), the hidden layer of every
-// point goes to LDS and lane j accumulates unit j of the second layer over
-// all points of the group, in the same order as the one-sample forward
-// pass (so each value equals pdx_mlp_forward on the same inputs).  fac
-// receives (c1/d) m, m = min(scale exp(z), 1e30); table (optional)
-// receives m.  Also records the START threshold in tau0.  Non-finite
+// The multiplier after c1 dimensions for the learned error bound eps:
+// max(1 + eps/sqrt(c1), 0)^2, capped at 1e30.
+__device__ __forceinline__ float prune_mult(float eps, int32_t c1) {
+    const float b = fmaxf(1.0f + eps / sqrtf((float)c1), 0.0f);
+    return fminf(b * b, 1.0e30f);
+}
+
+// Learned prune factors after START: one wave per (query, rank r >= 1)
+// evaluates the network once (eps = scale * z), then lanes fill the test
+// points c (c1 = (c + 1) chunk < d): fac receives (c1/d) m, table
+// (optional) m.  Also records the START threshold in tau0.  Non-finite
 // queries are not scanned: their rows hold NaN in `table`.
-constexpr int kPtGroup = 8;
-
-__device__ __forceinline__ void wave_lds_handoff() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __global__ __launch_bounds__(256) void prune_table_kernel(
     const float *__restrict__ qrot, int32_t d, const float *__restrict__ cd, int32_t nlist,
     const int32_t *__restrict__ probe, int32_t nprobe, const uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, const __half *__restrict__ w16, float scale, int32_t chunk, int32_t npt,
     int64_t npairs, float *__restrict__ fac, float *__restrict__ table, float *__restrict__ tau0) {
-    __shared__ float qs[4][64];
-    __shared__ __attribute__((aligned(16))) float h1s[4][kPtGroup][64];
+    __shared__ float feat[4][kMlpIn];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t pr = (int64_t)blockIdx.x * 4 + wave;
     if (pr >= npairs) return;
@@ -544,68 +536,37 @@ __global__ __launch_bounds__(256) void prune_table_kernel(
             for (int32_t c = lane; c < npt; c += 64) table[row + c] = __uint_as_float(0x7fc00000u);
         return;
     }
-    qs[wave][lane] = lane < d ? qrot[qi * d + lane] : 0.0f;
-    wave_lds_handoff();
     const float *cq = cd + qi * nlist;
     const int32_t *pq = probe + qi * nprobe;
-    const float d0 = cq[pq[0]] + 1e-20f, dr = cq[pq[r]] + 1e-20f;
-    const float u = mlp_a1_run(w16, qs[wave], lane, 0, 64, h2f(w16, kOffB1 + lane));
-    const __half *r1 = w16 + kOffW1 + lane * kMlpIn + 64;
-    const __half *r2 = w16 + kOffW2 + lane * kMlpH;
-    const float b2 = h2f(w16, kOffB2 + lane), w3 = h2f(w16, kOffW3 + lane), b3 = h2f(w16, kOffB3);
-    for (int32_t cb = 0; cb < npt; cb += kPtGroup) {
+    float x[8];
+    prune_inputs(t, cq[pq[0]] + 1e-20f, cq[pq[r]] + 1e-20f, r, nprobe, x);
+    feat[wave][lane] = lane < d ? qrot[qi * d + lane] : 0.0f;
+    float mine = 0.0f;
 #pragma unroll
-        for (int g = 0; g < kPtGroup; ++g) {
-            float h = 0.0f;
-            if (cb + g < npt) {
-                float x[8];
-                prune_inputs(t, d0, dr, r, nprobe, (cb + g + 1) * chunk, d, x);
-                float a1 = u;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) a1 = fmaf(h2f(r1, i), x[i], a1);
-                h = fmaxf(a1, 0.0f);
-            }
-            h1s[wave][g][lane] = h;
-        }
-        wave_lds_handoff();
-        float a2[kPtGroup];
-#pragma unroll
-        for (int g = 0; g < kPtGroup; ++g) a2[g] = b2;
-#pragma unroll 2
-        for (int i = 0; i < kMlpH; i += 4) {
-            const float w0 = h2f(r2, i), w1 = h2f(r2, i + 1), w2 = h2f(r2, i + 2), w3i = h2f(r2, i + 3);
-#pragma unroll
-            for (int g = 0; g < kPtGroup; ++g) {
-                const float4 hv = *reinterpret_cast<const float4 *>(&h1s[wave][g][i]);
-                a2[g] = fmaf(w0, hv.x, a2[g]);
-                a2[g] = fmaf(w1, hv.y, a2[g]);
-                a2[g] = fmaf(w2, hv.z, a2[g]);
-                a2[g] = fmaf(w3i, hv.w, a2[g]);
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < kPtGroup; ++g) {
-            float part = w3 * fmaxf(a2[g], 0.0f);
-            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-            const int32_t c = cb + g;
-            if (c < npt && lane == 0) {
-                const float m = fminf(scale * expf(part + b3), 1.0e30f);
-                fac[row + c] = ((float)(c + 1) * (float)chunk / (float)d) * m;
-                if (table) table[row + c] = m;
-            }
-        }
-        wave_lds_handoff();  // the group's reads are done before the next group's writes
+    for (int i = 0; i < 8; ++i) mine = lane == i ? x[i] : mine;
+    if (lane < kMlpIn - 64) feat[wave][64 + lane] = mine;
+    // the wave's own LDS row: a wavefront-scope hand-off between its lanes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float eps = scale * mlp_forward_wave(w16, feat[wave], lane, nullptr, nullptr, nullptr, nullptr);
+    for (int32_t c = lane; c < npt; c += 64) {
+        const int32_t c1 = (c + 1) * chunk;
+        const float m = prune_mult(eps, c1);
+        fac[row + c] = ((float)c1 / (float)d) * m;
+        if (table) table[row + c] = m;
     }
 }
 
-// Training traces of the prune-multiplier network, after the result is
-// known: one wave per (query, result slot i).  The i-th id's partial
-// distance after each test point's c1 dimensions (rotated rows, natural
-// order) gives the target ln(max(partial D / (c1 tau_k), 1e-30)), tau_k
-// the result's k-th distance; the inputs are those of (query, rank of the
-// id's bucket, c) with the START threshold tau0.  No sample (target NaN,
-// inputs 0): no id, an id of the START bucket, tau_k not positive and
-// finite, a non-finite query.
+// Training traces of the prune network, after the result is known: one
+// wave per (query, result slot i).  Target: the smallest error bound that
+// keeps the i-th id at every test point, max over c of
+// (sqrt(partial(c1) D / (c1 tau_k)) - 1) sqrt(c1), with partial(c1) its
+// squared distance over the first c1 rotated dimensions and tau_k the
+// result's k-th distance; inputs: those of (query, rank of the id's bucket)
+// with the START threshold tau0.  No sample (target NaN, inputs 0): no id,
+// an id of the START bucket, tau_k not positive and finite, a non-finite
+// query.
 __global__ __launch_bounds__(256) void prune_trace_kernel(
     const int64_t *__restrict__ ids, const float *__restrict__ dist, int32_t k, const int32_t *__restrict__ assign,
     const float *__restrict__ xrow, const float *__restrict__ qrot, int32_t d, const float *__restrict__ cd,
@@ -628,22 +589,24 @@ __global__ __launch_bounds__(256) void prune_trace_kernel(
         }
         ok = r >= 1;
     }
-    float *fo = feat_out + (size_t)si * npt * kMlpIn;
-    float *to = target_out + (size_t)si * npt;
+    float *fo = feat_out + (size_t)si * kMlpIn;
     if (!ok) {
-        for (int32_t c = 0; c < npt; ++c) {
-            fo[(size_t)c * kMlpIn + lane] = 0.0f;
-            if (lane < kMlpIn - 64) fo[(size_t)c * kMlpIn + 64 + lane] = 0.0f;
-            if (lane == 0) to[c] = __uint_as_float(0x7fc00000u);
-        }
+        fo[lane] = 0.0f;
+        if (lane < kMlpIn - 64) fo[64 + lane] = 0.0f;
+        if (lane == 0) target_out[si] = __uint_as_float(0x7fc00000u);
         return;
     }
     const float *cq = cd + qi * nlist;
     const int32_t *pq = probe + qi * nprobe;
-    const float d0 = cq[pq[0]] + 1e-20f, dr = cq[pq[r]] + 1e-20f;
-    const float qv = lane < d ? qrot[qi * d + lane] : 0.0f;
+    float x[8];
+    prune_inputs(tau0[qi], cq[pq[0]] + 1e-20f, cq[pq[r]] + 1e-20f, r, nprobe, x);
+    float mine = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) mine = lane == i ? x[i] : mine;
+    fo[lane] = lane < d ? qrot[qi * d + lane] : 0.0f;
+    if (lane < kMlpIn - 64) fo[64 + lane] = mine;
     const float *xv = xrow + id * d, *qp = qrot + qi * d;
-    float partial = 0.0f;
+    float partial = 0.0f, need = -INFINITY;
     for (int32_t c = 0; c < npt; ++c) {
         const int32_t c0 = c * chunk, c1 = c0 + chunk;
         float sum = 0.0f;
@@ -654,15 +617,10 @@ __global__ __launch_bounds__(256) void prune_trace_kernel(
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
         partial += sum;
-        float x[8];
-        prune_inputs(tau0[qi], d0, dr, r, nprobe, c1, d, x);
-        float mine = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) mine = lane == i ? x[i] : mine;
-        fo[(size_t)c * kMlpIn + lane] = qv;
-        if (lane < kMlpIn - 64) fo[(size_t)c * kMlpIn + 64 + lane] = mine;
-        if (lane == 0) to[c] = logf(fmaxf(partial * (float)d / ((float)c1 * tk), 1e-30f));
+        const float sc = sqrtf((float)c1);
+        need = fmaxf(need, (sqrtf(partial * (float)d / ((float)c1 * tk)) - 1.0f) * sc);
     }
+    if (lane == 0) target_out[si] = need;
 }
 
 // k-best over a query's item lists: the START lists (if use0) and the lists

@@ -1,5 +1,5 @@
 """Training drivers of the search's networks (pdx_mlp_*): the learned
-probe budget and the learned prune multiplier.
+probe budget and the learned prune bound.
 
 Probe budget.
 
@@ -21,17 +21,19 @@ The IVF search of Section 2.1 with the ADSampling test of Section 2.3 stays
 the fallback: a query the network never stops is searched exactly as
 without it.
 
-Prune multiplier.  In place of ADSampling's (1 + eps0/sqrt(c1))^2, a
-vector of a bucket of probe rank r >= 1 is dropped after c1 dimensions
-when partial * D/c1 > tau_now * m(query, r, c1).  A search exact within
-the probed buckets (eps0 = +inf) records, for every returned neighbour
-outside the START bucket and every test point, the network's inputs and
-the target ln(partial * D / (c1 tau_k)): a multiplier at or above it keeps
-that neighbour, since the running threshold never falls below the final
-k-th distance tau_k.  The network is fitted to a high quantile of the
-target (pinball loss), so it keeps that share of true neighbours at each
-test while pruning the rest as hard as their statistics allow; a scale
-applied at search time trades speed for recall like eps0 does.
+Prune bound.  ADSampling drops a vector of a bucket after c1 dimensions
+when partial * D/c1 > tau_now * (1 + eps0/sqrt(c1))^2 with one eps0 for
+every query and bucket.  The network gives each (query, bucket of probe
+rank r >= 1) its own eps.  A search exact within the probed buckets
+(eps0 = +inf) records, for every returned neighbour outside the START
+bucket, the network's inputs and the smallest eps that keeps that neighbour
+at every test point, max over c1 of (sqrt(partial * D / (c1 tau_k)) - 1)
+sqrt(c1): the running threshold never falls below the final k-th distance
+tau_k, so any eps at or above it keeps the neighbour.  The network is
+fitted to a high quantile of that target (pinball loss), which keeps about
+that share of the true neighbours while bounding each (query, bucket) as
+tightly as its statistics allow; a scale applied at search time trades
+speed for recall like eps0 does.
 
 Sample selection and shuffling are plain tensor operations; every
 forward, backward and update of the networks runs in the library's
@@ -79,8 +81,8 @@ def prune_traces(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, delta_d:
     npt = ivf_test_points(index.d, delta_d)
     if npt == 0:
         raise ValueError("no prune tests: delta_d covers every dimension")
-    pf = torch.empty((nq, k, npt, _lib.MLP_IN), dtype=torch.float32, device=q.device)
-    pt = torch.empty((nq, k, npt), dtype=torch.float32, device=q.device)
+    pf = torch.empty((nq, k, _lib.MLP_IN), dtype=torch.float32, device=q.device)
+    pt = torch.empty((nq, k), dtype=torch.float32, device=q.device)
     pdx_search_ivf(index, q, k, nprobe, eps0=float("inf"), delta_d=delta_d, prune_trace=(pf, pt), **schedule)
     keep = torch.isfinite(pt.reshape(-1))
     feats = pf.reshape(-1, _lib.MLP_IN)[keep].contiguous()

@@ -128,25 +128,29 @@ def test_pinball_planted_level_swap_is_caught():
 def test_prune_inputs_hand_worked():
     q = np.arange(1.0, 101.0)  # D = 100: the first 64 coordinates are 1 .. 64
     cd = np.array([2.0, 4.0, 8.0, 16.0])
-    x = mlp.prune_inputs(q, 6.0, cd, 2, 4, 25)
+    x = mlp.prune_inputs(q, 6.0, cd, 2, 4)
     np.testing.assert_array_equal(x[:64], np.arange(1.0, 65.0))
-    # tau/d_2 = 0.75, d_2/d_0 = 4, tau/d_0 = 3, log2(2)/log2(4) = 0.5, 25/100, 1/5
-    np.testing.assert_allclose(x[64:70], [0.75, 4.0, 3.0, 0.5, 0.25, 0.2], rtol=0, atol=1e-15)
-    assert np.all(x[70:] == 0)
+    # tau/d_2 = 0.75, d_2/d_0 = 4, tau/d_0 = 3, log2(2)/log2(4) = 0.5
+    np.testing.assert_allclose(x[64:68], [0.75, 4.0, 3.0, 0.5], rtol=0, atol=1e-15)
+    assert np.all(x[68:] == 0)
     # short queries are zero-padded; an infinite START threshold clamps to 1e4
-    x = mlp.prune_inputs(np.ones(10), np.inf, cd, 1, 4, 5)
+    x = mlp.prune_inputs(np.ones(10), np.inf, cd, 1, 4)
     assert np.all(x[:10] == 1) and np.all(x[10:64] == 0)
     assert x[64] == 1e4 and x[66] == 1e4 and x[65] == 2.0
 
 
 def test_prune_multipliers_follow_the_network():
-    th = _constant_net(np.log(3.0))
-    m = mlp.prune_multipliers(th, np.ones(96), 5.0, np.array([1.0, 2.0, 3.0]), 3, 32, scale=2.0)
+    th = _constant_net(2.0)  # z = 2 for every rank
+    m = mlp.prune_multipliers(th, np.ones(96), 5.0, np.array([1.0, 2.0, 3.0]), 3, 32, scale=1.5)
     assert m.shape == (2, 2)  # ranks 1, 2; test points after 32 and 64 of 96 dimensions
-    np.testing.assert_allclose(m, 6.0, rtol=1e-15)
+    # eps = 3: (1 + 3/sqrt(32))^2 and (1 + 3/sqrt(64))^2
+    np.testing.assert_allclose(m[0], [(1 + 3 / np.sqrt(32)) ** 2, (1 + 3 / 8) ** 2], rtol=1e-15)
+    np.testing.assert_array_equal(m[0], m[1])
     assert mlp.test_points(96, 32) == [32, 64] and mlp.test_points(97, 32) == [32, 64, 96]
-    big = mlp.prune_multipliers(_constant_net(500.0), np.ones(96), 5.0, np.array([1.0, 2.0]), 2, 32)
-    assert np.all(big == 1e30)
+    # a bound below -sqrt(c1) gives multiplier 0; a huge one is capped
+    assert mlp.multiplier(-10.0, 64) == 0.0 and mlp.multiplier(1e20, 64) == 1e30
+    # eps0 itself reproduces ADSampling's multiplier
+    assert mlp.multiplier(2.1, 50) == (1.0 + 2.1 / np.sqrt(50)) ** 2
 
 
 def test_prune_targets_brute_force():
@@ -155,8 +159,14 @@ def test_prune_targets_brute_force():
     q = rng.standard_normal(70)
     ids = np.array([3, 17, 29])
     t = mlp.prune_targets(xr, q, ids, 2.5, 16)
-    assert t.shape == (3, 4)  # after 16, 32, 48, 64 of 70 dimensions
+    assert t.shape == (3,)  # test points after 16, 32, 48, 64 of 70 dimensions
     for a, i in enumerate(ids):
-        for c, c1 in enumerate((16, 32, 48, 64)):
+        need = []
+        for c1 in (16, 32, 48, 64):
             part = sum((xr[i, j] - q[j]) ** 2 for j in range(c1))
-            assert abs(t[a, c] - np.log(part * 70 / (c1 * 2.5))) < 1e-12
+            need.append((np.sqrt(part * 70 / (c1 * 2.5)) - 1) * np.sqrt(c1))
+        assert abs(t[a] - max(need)) < 1e-12
+        # the target is the smallest bound that keeps the id at every test point
+        for c1 in (16, 32, 48, 64):
+            part = sum((xr[i, j] - q[j]) ** 2 for j in range(c1))
+            assert part * 70 / c1 <= 2.5 * mlp.multiplier(t[a], c1) * (1 + 1e-12)

@@ -163,14 +163,14 @@ def test_table_search_reduces_to_ads_and_to_ivf_flat():
         assert ti.tolist() == si.tolist()
 
 
-def test_multipliers_from_the_targets_keep_every_neighbour():
-    """A multiplier at or above each returned neighbour's target (the
-    largest over the neighbours in that bucket; 0 for buckets holding none)
-    keeps every neighbour, because the threshold in force never falls below
-    the final k-th distance: the search returns IVF-flat's result, while a
-    multiplier just below a target loses that neighbour."""
+def test_bounds_from_the_targets_keep_every_neighbour():
+    """Each bucket's bound at the largest target of its returned neighbours
+    (none: multiplier 0) keeps every neighbour, because the threshold in
+    force never falls below the final k-th distance: the search returns
+    IVF-flat's result, while the same multipliers halved lose one."""
     x, q, c, lists = _small_ivf(seed=5, n=4000, d=64, nlist=20)
     nprobe, dd, k = 10, 16, 10
+    pts = mlp.test_points(64, dd)
     labels = np.empty(x.shape[0], np.int64)
     for l, rows in enumerate(lists):
         labels[rows] = l
@@ -181,14 +181,15 @@ def test_multipliers_from_the_targets_keep_every_neighbour():
         probe = px.ivf_probe_order(c, qq, nprobe)
         rank = {int(b): r for r, b in enumerate(probe)}
         t = mlp.prune_targets(x, qq, fi, fd[-1], dd)
-        mult = np.zeros((nprobe - 1, t.shape[1]))
+        eps = np.full(nprobe - 1, -np.inf)
         for a, v in enumerate(fi):
             r = rank[int(labels[v])]
             if r >= 1:
-                mult[r - 1] = np.maximum(mult[r - 1], np.exp(t[a]) * (1 + 1e-12))
+                eps[r - 1] = max(eps[r - 1], t[a])
+        mult = np.array([[0.0 if e == -np.inf else mlp.multiplier(e, c1) * (1 + 1e-12) for c1 in pts]
+                         for e in eps])
         gi, gd = px.learned_ivf_search(x, lists, c, qq, k, nprobe, mult, dd)
         assert gi.tolist() == fi.tolist()
-        # the same multipliers lowered a little lose a neighbour outside START
         if mult.max() > 0:
             gi2, _ = px.learned_ivf_search(x, lists, c, qq, k, nprobe, mult * 0.5, dd)
             lost += gi2.tolist() != fi.tolist()
