@@ -18,7 +18,9 @@ skewed Gaussian mixture standing in for GIST/960), 1,000 queries, K = 10.
   sample).  extra.approx_bond_bound: the same index with PDX-BOND as the
   bound inside the probed buckets.  extra.learned_stop: plain ADSampling
   against the learned probe budget, and against the learned prune
-  multiplier, at recall@10 >= 0.95 on 10,000 evaluation queries.
+  bound, at recall@10 >= 0.95 on 10,000 evaluation queries.  extra.metrics:
+  L1 with PDX-BOND and the inner product (matrix-core linear scan) on the
+  exact search's index and queries.
 * roofline: the dominant kernel (the LDS-tile scan, 8 launches per step):
   algorithmic flops (3 per evaluated value, from the library's counters)
   over its event-timed duration, against the vector-ALU ceiling.
@@ -240,6 +242,35 @@ def bench_bond_ivf(pdx, torch, np, ix, q_dev, nprobes, k, steps, warmup, truth_i
     return {"bound": "PDX-BOND (exact within the probed buckets)", "sweep": rows}
 
 
+def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d):
+    """The kernel listing's other distances on the same index and queries:
+    L1 with PDX-BOND (vectorgroup path) and the inner product (linear scan
+    on the matrix cores; roofline: 2 flops per (query, vector, dimension)
+    over the scan's event-timed duration, against dense FP32 MFMA)."""
+    nq = q.shape[0]
+    out = {}
+    for metric, mode in (("l1", "bond"), ("ip", "linear")):
+        ws = torch.empty(max(1, pdx.pdx_search_exact_workspace(ix, nq, k, mode=mode, metric=metric)),
+                         dtype=torch.uint8, device="cuda")
+
+        def run(evs, ws=ws, metric=metric, mode=mode):
+            pdx.pdx_search_exact(ix, q, k, mode=mode, metric=metric, workspace=ws, phase_events=evs)
+
+        elapsed, ph = timed_steps(run, steps, warmup, torch, np)
+        row = {"mode": mode, "qps": round(nq * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
+               "phases_ms": {"prep_start": round(ph[0], 3), "scan": round(ph[1], 3), "merge": round(ph[2], 3)}}
+        if metric == "ip" and ph[1] > 0:
+            flops = 2.0 * nq * n * d
+            achieved = flops / (ph[1] * 1e-3) / 1e12
+            row["roofline"] = {"bound": "mfma", "kernel": "ip_scan_kernel (16 queries x 64 vectors per wave)",
+                               "achieved": round(achieved, 3), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(achieved / MFMA_F32_PEAK_TFLOPS, 4), "algorithmic_flops_per_launch": flops,
+                               "kernel_ms_per_launch": round(ph[1], 4), "launches_per_step": 1}
+        print(f"# metric {metric}: {row}", file=sys.stderr, flush=True)
+        out[metric] = row
+    return out
+
+
 def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu_seconds, target=0.95,
                   nprobe_max=32, n_train=8000, n_val=2000, seed_train=43, seed_eval=44, prune_levels=(0.95, 0.98, 0.99),
                   prune_scales=(0.8, 1.0, 1.25)):
@@ -279,10 +310,13 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
 
     cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
 
+    issued = {}
+
     def search(qd, **kw):
         cnt.zero_()
         i, _ = pdx.pdx_search_ivf(ix, qd, k, eps0=2.1, counters=cnt, **kw)
         c = cnt.cpu().numpy()
+        issued["last"] = float(c[1] + c[3]) / qd.shape[0]  # lane slots the scans issued, live or not
         return i.cpu().numpy(), float(c[0] + c[2]) / qd.shape[0]
 
     plain_np = [2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32]
@@ -292,7 +326,8 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
     for p in plain_np:
         ids, work = search(qv, nprobe=p)
         r = recall_at_k(tv, ids)
-        val["plain"].append({"nprobe": p, "recall@10": round(r, 4), "values_per_query": round(work)})
+        val["plain"].append({"nprobe": p, "recall@10": round(r, 4), "values_per_query": round(work),
+                             "issued_per_query": round(issued["last"])})
         if pick_p is None and r >= target:
             pick_p = p
     for t in thresholds:
@@ -305,7 +340,9 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
 
     def timed(**kw):
         ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, qe.shape[0], k, kw["nprobe"], mlp=kw.get("mlp"),
-                                                             prune_mlp=kw.get("prune_mlp"))),
+                                                             prune_mlp=kw.get("prune_mlp"),
+                                                             engine=kw.get("engine", 0),
+                                                             queries_per_wave=kw.get("queries_per_wave", 0))),
                          dtype=torch.uint8, device="cuda")
         out = {}
 
@@ -368,7 +405,7 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
                 ids, work = search(qv, nprobe=p, prune_mlp=net_l, prune_scale=sc)
                 r = recall_at_k(tv, ids)
                 row = {"level": level, "nprobe": p, "scale": sc, "recall@10": round(r, 4),
-                       "values_per_query": round(work)}
+                       "values_per_query": round(work), "issued_per_query": round(issued["last"])}
                 if r >= target:  # operating point: the fastest configuration reaching the target
                     row["ms"] = round(1e3 * vtime(nprobe=p, prune_mlp=net_l, prune_scale=sc), 3)
                     if best is None or row["ms"] < best[0]:
@@ -387,8 +424,14 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
                                **timed(nprobe=best[2], prune_mlp=nets[best[1]], prune_scale=best[3]))
         if "plain" in res:
             pres["speedup_qps"] = round(pres["learned"]["qps"] / res["plain"]["qps"], 3)
+            # the same two operating points on the vector-ALU scan (4 queries per
+            # wave), whose cost follows the live values rather than whole tiles
+            valu = dict(engine=1, queries_per_wave=4)
+            pv = timed(nprobe=pick_p, **valu)
+            lv = timed(nprobe=best[2], prune_mlp=nets[best[1]], prune_scale=best[3], **valu)
+            pres["vector_alu_scan"] = {"plain": pv, "learned": lv, "speedup_qps": round(lv["qps"] / pv["qps"], 3)}
     print(f"# learned prune: {pres.get('learned')}", file=sys.stderr, flush=True)
-    res["prune_multiplier"] = pres
+    res["prune_bound"] = pres
     return res
 
 
@@ -458,6 +501,7 @@ def main() -> int:
     ap.add_argument("--no-linear", action="store_true", help="skip the unpruned comparison run")
     ap.add_argument("--no-ivf", action="store_true", help="skip the IVF + ADSampling leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned early-termination leg")
+    ap.add_argument("--no-metrics", action="store_true", help="skip the L1 / inner-product leg")
     ap.add_argument("--nprobe", type=int, nargs="*", default=None, help="IVF workloads: nprobe values to run")
     ap.add_argument("--flat", action="store_true", help="exact search on the flat layout instead of buckets")
     ap.add_argument("--exact-nlist", type=int, default=1024, help="buckets of the exact search's layout")
@@ -636,6 +680,8 @@ def main() -> int:
         tl = time.perf_counter() - tl
         extra["own_linear_scan"] = {"qps": round(nq / tl, 1), "ms": round(1e3 * tl, 2),
                                     "note": "same kernels, no pruning (PDX linear scan)"}
+    if mode == "bond" and not args.no_metrics:
+        extra["metrics"] = bench_metrics(pdx, torch, np, ix, q, k, 3, 1, n, d)
     del ws
     if mode == "bond" and not args.no_ivf:
         ivf_ix = build_ivf(pdx, torch, np, x, 1024)

@@ -97,6 +97,17 @@ enum {
     PDX_MODE_BOND = 1    /* PDXearch with the PDX-BOND bound and order */
 };
 
+/* Distances of the exact search (the L2, L1 and IP kernels of Section 3's
+ * listing).  Results are ascending in the reported value in every case. */
+enum {
+    PDX_METRIC_L2 = 0, /* sum_j (q_j - v_j)^2                                  */
+    PDX_METRIC_L1 = 1, /* sum_j |q_j - v_j|; PDX-BOND prunes it like L2: its
+                          partial sums are lower bounds too                      */
+    PDX_METRIC_IP = 2  /* -sum_j q_j v_j (largest inner product first), on the
+                          matrix cores; PDX_MODE_LINEAR only: a partial inner
+                          product bounds nothing                                 */
+};
+
 typedef struct {
     int32_t mode;        /* PDX_MODE_LINEAR or PDX_MODE_BOND */
     int32_t chunk;       /* dimensions per pruning step; 0 = 32 */
@@ -111,6 +122,7 @@ typedef struct {
                             [1] lane slots START issued, [2] values evaluated
                             by the pruned scan (live lanes only), [3] lane
                             slots it issued (live and pruned lanes) */
+    int32_t metric;      /* PDX_METRIC_*; 0 = L2 */
 } pdx_search_params;
 
 /* Workspace bytes for pdx_search_exact with these arguments. */
@@ -136,13 +148,20 @@ PDX_API size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, in
  * BOND means are those of the stored rows; a rotated index rotates the
  * queries first and reports distances in rotated space.
  *
+ * Metrics (params->metric): L2 as above; L1 with the same phases (the
+ * LDS-tile kernel is L2 only, so L1 scans vectorgroups per wave); IP in
+ * linear mode as one matrix-core pass, 16 queries x 64 vectors per wave,
+ * reporting -q.v.  A rotated index preserves L2 and IP, not L1: L1 on it
+ * is measured in rotated space.
+ *
  * q         [nq][d] float32 device.
  * ws        device workspace of ws_bytes >= pdx_search_exact_workspace(...).
  * out_ids   [nq][k] int64 device;  out_dist [nq][k] float32 device.
  * A query holding a non-finite value gets ids -1 and NaN distances (the
  * check runs on the device; the call still returns PDX_OK).
  * nq = 0 is a successful no-op.  Returns PDX_EINVAL (null pointers, nq < 0,
- * k < 1, unknown mode), PDX_EUNSUPPORTED (k > PDX_MAX_K), PDX_EWORKSPACE. */
+ * k < 1, unknown mode or metric), PDX_EUNSUPPORTED (k > PDX_MAX_K, IP with
+ * PDX_MODE_BOND), PDX_EWORKSPACE. */
 PDX_API pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, int32_t k,
                             const pdx_search_params *params, void *ws, size_t ws_bytes,
                             int64_t *out_ids, float *out_dist, void *stream);

@@ -9,6 +9,11 @@ here are ordered by (delta, row id) ascending.  When k exceeds the number
 of rows the tail is padded with id -1 and distance +inf.
 
 Every float32 input is widened exactly to float64 before any arithmetic.
+
+The kernel listing of Section 3 gives two more distances over the same
+layout: L1, sum_i |v_i - q_i|, and the inner product sum_i v_i q_i, whose
+nearest neighbours are the largest values; here the inner product is
+scored as its negation so that every metric ranks ascending.
 """
 from __future__ import annotations
 
@@ -28,6 +33,20 @@ def sqdist(x: np.ndarray, q: np.ndarray) -> np.ndarray:
     return np.einsum("ij,ij->i", diff, diff)
 
 
+def l1dist(x: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """sum_i |v_i - q_i| for every row v of x, in float64."""
+    diff = np.asarray(x, dtype=np.float64) - np.asarray(q, dtype=np.float64)[None, :]
+    return np.abs(diff).sum(axis=1)
+
+
+def neg_ip(x: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """-sum_i v_i q_i for every row v of x, in float64."""
+    return -(np.asarray(x, dtype=np.float64) @ np.asarray(q, dtype=np.float64))
+
+
+METRICS = {"l2": sqdist, "l1": l1dist, "ip": neg_ip}
+
+
 def topk_by_dist_then_id(dist: np.ndarray, ids: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndarray]:
     """The k smallest (dist, id) pairs, ascending; pads with (-1, +inf)."""
     order = np.lexsort((ids, dist))[:k]
@@ -38,11 +57,13 @@ def topk_by_dist_then_id(dist: np.ndarray, ids: np.ndarray, k: int) -> Tuple[np.
     return out_i, out_d
 
 
-def knn_exact(x: np.ndarray, queries: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndarray]:
-    """Brute-force exact KNN over the horizontal (row-major) layout.
+def knn_exact(x: np.ndarray, queries: np.ndarray, k: int, metric: str = "l2") -> Tuple[np.ndarray, np.ndarray]:
+    """Brute-force exact KNN over the horizontal (row-major) layout, for the
+    metric "l2" (the default), "l1" or "ip" (scored as -q.v).
 
     Returns (ids [nq, k] int64, dist [nq, k] float64).
     """
+    score = METRICS[metric]
     x = np.asarray(x)
     queries = np.atleast_2d(np.asarray(queries))
     n = x.shape[0]
@@ -50,7 +71,41 @@ def knn_exact(x: np.ndarray, queries: np.ndarray, k: int) -> Tuple[np.ndarray, n
     out_i = np.empty((queries.shape[0], k), dtype=np.int64)
     out_d = np.empty((queries.shape[0], k), dtype=np.float64)
     for qi in range(queries.shape[0]):
-        out_i[qi], out_d[qi] = topk_by_dist_then_id(sqdist(x, queries[qi]), ids, k)
+        out_i[qi], out_d[qi] = topk_by_dist_then_id(score(x, queries[qi]), ids, k)
+    return out_i, out_d
+
+
+def knn_exact_blocked(x: np.ndarray, queries: np.ndarray, k: int, metric: str = "l2",
+                      block: int = 65536) -> Tuple[np.ndarray, np.ndarray]:
+    """:func:`knn_exact` over blocks of rows (every query against one block
+    at a time, keeping each query's k best so far), for collections too
+    large to widen to float64 at once.  Same results."""
+    x = np.asarray(x)
+    queries = np.atleast_2d(np.asarray(queries, dtype=np.float64))
+    nq = queries.shape[0]
+    best_i = np.full((nq, 0), -1, dtype=np.int64)
+    best_d = np.zeros((nq, 0), dtype=np.float64)
+    for b0 in range(0, x.shape[0], block):
+        xb = np.asarray(x[b0:b0 + block], dtype=np.float64)
+        ids = np.arange(b0, b0 + xb.shape[0], dtype=np.int64)
+        if metric == "ip":
+            sc = -(queries @ xb.T)
+        elif metric == "l1":
+            sc = np.stack([np.abs(xb - qq[None, :]).sum(1) for qq in queries])
+        else:
+            sc = np.stack([((xb - qq[None, :]) ** 2).sum(1) for qq in queries])
+        new_i = np.empty((nq, min(k, best_i.shape[1] + ids.size)), dtype=np.int64)
+        new_d = np.empty(new_i.shape, dtype=np.float64)
+        for qi in range(nq):
+            di = np.concatenate([best_d[qi], sc[qi]])
+            ii = np.concatenate([best_i[qi], ids])
+            o = np.lexsort((ii, di))[: new_i.shape[1]]
+            new_i[qi], new_d[qi] = ii[o], di[o]
+        best_i, best_d = new_i, new_d
+    out_i = np.full((nq, k), -1, dtype=np.int64)
+    out_d = np.full((nq, k), np.inf, dtype=np.float64)
+    out_i[:, : best_i.shape[1]] = best_i
+    out_d[:, : best_d.shape[1]] = best_d
     return out_i, out_d
 
 

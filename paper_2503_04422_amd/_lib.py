@@ -26,6 +26,10 @@ PDX_MAX_DIM = 4096
 PDX_MODE_LINEAR = 0
 PDX_MODE_BOND = 1
 
+PDX_METRIC_L2 = 0
+PDX_METRIC_L1 = 1
+PDX_METRIC_IP = 2
+
 PDX_DTYPE_F32 = 0
 PDX_DTYPE_BF16 = 1
 PDX_DTYPE_FP8 = 2
@@ -48,7 +52,8 @@ class pdx_build_params(ctypes.Structure):
 
 class pdx_search_params(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("chunk", c_int32), ("tile_groups", c_int32),
-                ("queries_per_block", c_int32), ("phase_events", c_void_p), ("counters", c_void_p)]
+                ("queries_per_block", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
+                ("metric", c_int32)]
 
 
 class pdx_ivf_params(ctypes.Structure):

@@ -103,9 +103,16 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
     }
 }
 
+// One term of the distance: (q - x)^2 (L2) or |q - x| (L1, the kernel
+// listing's second distance) added to acc.
+template <bool L1>
+__device__ __forceinline__ float dist_term(float acc, float t) {
+    return L1 ? acc + fabsf(t) : fmaf(t, t, acc);
+}
+
 // Chunk [c0, c1) of the visit order for one lane's vector: the first 16
 // dimensions and the rest are summed separately, then added.
-template <bool FULL32>
+template <bool FULL32, bool L1>
 __device__ __forceinline__ float chunk_sum(const float *__restrict__ gp, const int32_t *__restrict__ po,
                                            const float *__restrict__ qp, int32_t c0, int32_t c1) {
     float lo = 0.0f, hi = 0.0f;
@@ -114,32 +121,20 @@ __device__ __forceinline__ float chunk_sum(const float *__restrict__ gp, const i
 #pragma unroll
         for (int u = 0; u < 32; ++u) x[u] = gp[po[c0 + u] * kGroup];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            float t = qp[c0 + u] - x[u];
-            lo = fmaf(t, t, lo);
-        }
+        for (int u = 0; u < 16; ++u) lo = dist_term<L1>(lo, qp[c0 + u] - x[u]);
 #pragma unroll
-        for (int u = 16; u < 32; ++u) {
-            float t = qp[c0 + u] - x[u];
-            hi = fmaf(t, t, hi);
-        }
+        for (int u = 16; u < 32; ++u) hi = dist_term<L1>(hi, qp[c0 + u] - x[u]);
     } else {
         const int32_t mid = min(c0 + 16, c1);
-        for (int32_t j = c0; j < mid; ++j) {
-            float t = qp[j] - gp[po[j] * kGroup];
-            lo = fmaf(t, t, lo);
-        }
-        for (int32_t j = mid; j < c1; ++j) {
-            float t = qp[j] - gp[po[j] * kGroup];
-            hi = fmaf(t, t, hi);
-        }
+        for (int32_t j = c0; j < mid; ++j) lo = dist_term<L1>(lo, qp[j] - gp[po[j] * kGroup]);
+        for (int32_t j = mid; j < c1; ++j) hi = dist_term<L1>(hi, qp[j] - gp[po[j] * kGroup]);
     }
     return lo + hi;
 }
 
 // One wave scans groups [g0, g1) for query qi and writes its k-best list to
 // myslot.  PRUNE: drop lanes whose partial exceeds the threshold.
-template <bool PRUNE>
+template <bool PRUNE, bool L1 = false>
 __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int64_t n,
                                             const int32_t *__restrict__ slot_id, int32_t d, int32_t g0,
                                             int32_t g1, int64_t qi, const int32_t *__restrict__ perm,
@@ -173,7 +168,8 @@ __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int6
                 lane_vals += 64ull * (c1 - c0);
             }
             float s = 0.0f;
-            if (alive) s = (c1 - c0 == 32) ? chunk_sum<true>(gp, po, qp, c0, c1) : chunk_sum<false>(gp, po, qp, c0, c1);
+            if (alive)
+                s = (c1 - c0 == 32) ? chunk_sum<true, L1>(gp, po, qp, c0, c1) : chunk_sum<false, L1>(gp, po, qp, c0, c1);
             partial += s;
             if (PRUNE) alive = alive && !(partial > tau_eff);
         }
@@ -197,7 +193,7 @@ __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int6
 // query blocks of one tile run on the same XCD (ids are dealt round-robin to
 // the 8 XCDs), keeping the tile's rows in that XCD's L2.
 // ---------------------------------------------------------------------------
-template <bool PRUNE>
+template <bool PRUNE, bool L1>
 __global__ __launch_bounds__(512) void scan_kernel(
     const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t g_begin,
     int32_t g_end,
@@ -222,7 +218,7 @@ __global__ __launch_bounds__(512) void scan_kernel(
     }
     const int32_t g0 = g_begin + tile * tile_groups;
     const int32_t g1 = min(g0 + tile_groups, g_end);
-    scan_groups<PRUNE>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
+    scan_groups<PRUNE, L1>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
 }
 
 // Nearest bucket of each query (distances [nq][nlist]; ties to the lower
@@ -248,6 +244,7 @@ __global__ __launch_bounds__(64) void nearest_kernel(const float *__restrict__ c
 // START on a bucket layout (Section 4, PHASE 0 on the query's nearest
 // bucket instead of the first rows): `parts` waves per query share the
 // bucket's groups, each writing its own k-best list.
+template <bool L1>
 __global__ __launch_bounds__(256) void start_bucket_kernel(
     const float *__restrict__ pdxd, const int32_t *__restrict__ slot_id, int32_t d,
     const int32_t *__restrict__ goff, const int32_t *__restrict__ nearest, int64_t nq, int32_t parts,
@@ -267,7 +264,7 @@ __global__ __launch_bounds__(256) void start_bucket_kernel(
     const int32_t l = nearest[qi];
     const int32_t a = goff[l], len = goff[l + 1] - a;
     const int32_t g0 = a + (int32_t)((int64_t)len * part / parts), g1 = a + (int32_t)((int64_t)len * (part + 1) / parts);
-    scan_groups<false>(pdxd, 0, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
+    scan_groups<false, L1>(pdxd, 0, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
 }
 
 // Group path for the queries whose candidate buffer overflowed in the tile
@@ -679,7 +676,7 @@ size_t max_dynamic_lds() {
 }
 
 bool tile_path(const pdx_index *ix, const ExactPlan &pl) {
-    return pl.mode == PDX_MODE_BOND && pl.chunk == 32 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
+    return pl.mode == PDX_MODE_BOND && pl.metric == PDX_METRIC_L2 && pl.chunk == 32 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
            pl.tiles_main > 0 && tile_lds_bytes(ix->d) <= max_dynamic_lds();
 }
 
@@ -723,6 +720,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.tile_groups = (p && p->tile_groups > 0) ? p->tile_groups : 16;
     pl.qpb = (p && p->queries_per_block > 0) ? p->queries_per_block : 4;
     pl.ivf = ix->kind == kIvf;
+    pl.metric = p ? p->metric : PDX_METRIC_L2;
     if (pl.ivf) {
         pl.start_groups = 0;  // START is each query's nearest bucket
     } else if (pl.mode == PDX_MODE_BOND) {
@@ -741,7 +739,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.bad = c.take<int32_t>(q);
     pl.perm = c.take<int32_t>(q * ix->d);
     pl.qperm = c.take<float>(q * ix->d);
-    pl.slots = c.take<uint64_t>(q * pl.nslots * k);
+    pl.slots = pl.metric == PDX_METRIC_IP ? nullptr : c.take<uint64_t>(q * pl.nslots * k);
     if (pl.ivf) {
         pl.start_parts = 4;
         pl.qrot = ix->has_rot ? c.take<float>(q * ix->d) : nullptr;
@@ -757,6 +755,10 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
         pl.cand_cnt = c.take<int32_t>(q);
         pl.over_list = c.take<int32_t>(q);
         pl.over_count = c.take<int32_t>(64);
+    }
+    if (pl.metric == PDX_METRIC_IP) {
+        pl.ip_parts = ip_parts_for(nq, ix->ngroups);
+        pl.ip_slots = c.take<uint64_t>(q * pl.ip_parts * k);
     }
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
     pl.counters = p ? p->counters : nullptr;
@@ -781,18 +783,33 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     prep_kernel<<<dim3((unsigned)pl.nq), dim3(256), lds, s>>>(qs, d, ix->means, pl.mode, pow2, pl.perm,
                                                               pl.qperm, pl.tau, pl.bad);
     if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (pl.metric == PDX_METRIC_IP) {  // linear inner-product scan on the matrix cores
+        if ((err = mark(1)) != hipSuccess) return err;
+        if ((err = launch_ip_scan(ix, qs, pl.nq, pl.bad, pl.ip_parts, pl.ip_slots, pl.k, s)) != hipSuccess)
+            return err;
+        if ((err = mark(2)) != hipSuccess) return err;
+        if ((err = launch_ip_merge(pl.ip_slots, pl.nq, pl.ip_parts, pl.k, pl.bad, out_ids, out_dist, s)) !=
+            hipSuccess)
+            return err;
+        return mark(3);
+    }
+    const bool l1 = pl.metric == PDX_METRIC_L1;
     const int32_t nqb = (int32_t)((pl.nq + pl.qpb - 1) / pl.qpb);
     auto scan = [&](bool prune, int32_t gb, int32_t ge, int32_t ntiles, int32_t slot0, unsigned long long *cnt) {
         unsigned grid = 8u * (unsigned)((ntiles + 7) / 8) * (unsigned)nqb;
         dim3 block(64 * pl.qpb);
-        if (prune)
-            scan_kernel<true><<<grid, block, 0, s>>>(ix->pdx, ix->n, sid, d, gb, ge, pl.tile_groups, ntiles, nqb,
-                                                     pl.nq, pl.qpb, pl.perm, pl.qperm, pl.tau, pl.bad,
-                                                     pl.slots, pl.nslots, slot0, pl.k, pl.chunk, cnt);
-        else
-            scan_kernel<false><<<grid, block, 0, s>>>(ix->pdx, ix->n, sid, d, gb, ge, pl.tile_groups, ntiles, nqb,
-                                                      pl.nq, pl.qpb, pl.perm, pl.qperm, pl.tau, pl.bad,
-                                                      pl.slots, pl.nslots, slot0, pl.k, pl.chunk, cnt);
+#define PDX_GROUP_SCAN(P, M)                                                                                   \
+    scan_kernel<P, M><<<grid, block, 0, s>>>(ix->pdx, ix->n, sid, d, gb, ge, pl.tile_groups, ntiles, nqb, pl.nq, \
+                                             pl.qpb, pl.perm, pl.qperm, pl.tau, pl.bad, pl.slots, pl.nslots,     \
+                                             slot0, pl.k, pl.chunk, cnt)
+        if (prune) {
+            if (l1) PDX_GROUP_SCAN(true, true);
+            else PDX_GROUP_SCAN(true, false);
+        } else {
+            if (l1) PDX_GROUP_SCAN(false, true);
+            else PDX_GROUP_SCAN(false, false);
+        }
+#undef PDX_GROUP_SCAN
         return hipGetLastError();
     };
     const unsigned nqu = (unsigned)pl.nq;
@@ -804,9 +821,14 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
             return err;
         nearest_kernel<<<nqu, 64, 0, s>>>(pl.cd, ix->nlist, pl.nearest);
         const int64_t waves = pl.nq * pl.start_parts;
-        start_bucket_kernel<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
-            ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest, pl.nq, pl.start_parts, pl.perm, pl.qperm, pl.tau,
-            pl.bad, pl.start_slots, pl.k, pl.chunk, pl.counters);
+        if (l1)
+            start_bucket_kernel<true><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
+                ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest, pl.nq, pl.start_parts, pl.perm, pl.qperm,
+                pl.tau, pl.bad, pl.start_slots, pl.k, pl.chunk, pl.counters);
+        else
+            start_bucket_kernel<false><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
+                ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest, pl.nq, pl.start_parts, pl.perm, pl.qperm,
+                pl.tau, pl.bad, pl.start_slots, pl.k, pl.chunk, pl.counters);
         merge_kernel<<<nqu, 64, 0, s>>>(pl.start_slots, pl.start_parts, 0, pl.start_parts, pl.k, pl.bad, pl.tau,
                                         nullptr, nullptr, nullptr, nullptr, 0);
         if ((err = hipGetLastError()) != hipSuccess) return err;

@@ -83,7 +83,8 @@ __device__ __forceinline__ void mscan_unit(
     for (int mt = 0; mt < MT; ++mt) qrow[mt] = qrot + (int64_t)(row_ok[mt] ? mine[mt].x : q0) * d;
     const float *crow = cen + (int64_t)l * d;
     // query slots of this lane's D rows
-    int32_t rowq[MT][4], rowr[MT][4];
+    int32_t rowq[MT][4];
+    float rowe[MT][4];  // learned bound of the row's (query, bucket)
     bool rowuse[MT][4];
     float kthr[MT][4];  // k-th distance of the query in D row 4 kq + r of tile mt
 #pragma unroll
@@ -91,8 +92,9 @@ __device__ __forceinline__ void mscan_unit(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             rowq[mt][r] = __shfl(mine[mt].x, 4 * kq + r);
-            rowr[mt][r] = __shfl(mine[mt].y, 4 * kq + r);
+            const int32_t rr = __shfl(mine[mt].y, 4 * kq + r);
             rowuse[mt][r] = (use >> (16 * mt + 4 * kq + r)) & 1u;
+            rowe[mt][r] = (PRUNE && rule.eps && rowuse[mt][r]) ? rule.eps_at(rowq[mt][r], rr, nprobe) : 0.0f;
             kthr[mt][r] = INFINITY;
         }
 #pragma unroll
@@ -208,9 +210,13 @@ __device__ __forceinline__ void mscan_unit(
                 xx[t] += __shfl_xor(xx[t], 16);
                 xx[t] += __shfl_xor(xx[t], 32);
             }
-            float fac = 1.0f;
-            const bool learned = PRUNE && c1 < d && rule.fac;
-            if (PRUNE && c1 < d && !rule.fac) fac = rule.ads(c1, d);
+            float fac = 1.0f, cdl = 0.0f, rsl = 0.0f;
+            const bool learned = PRUNE && c1 < d && rule.eps;
+            if (PRUNE && c1 < d && !rule.eps) fac = rule.ads(c1, d);
+            if (learned) {
+                cdl = (float)c1 / (float)d;
+                rsl = prune_rs(c1);
+            }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 if (!((tl >> mt) & 1u)) continue;
@@ -219,8 +225,7 @@ __device__ __forceinline__ void mscan_unit(
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float qn = __shfl(qq[mt], 4 * kq + r);
-                    const float fr = (learned && rowuse[mt][r])
-                                         ? rule.learned(rowq[mt][r], rowr[mt][r], nprobe, c0 / chunk) : fac;
+                    const float fr = learned ? PruneRule::learned(rowe[mt][r], cdl, rsl) : fac;
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         part_[mt][r][t] += fmaxf(qn + xx[t] - 2.0f * acc[mt][t][r], 0.0f);

@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
     }
     const int32_t l = probe[qi * nprobe + r];
     const float *qp = qrot + qi * d;
+    const float eps_i = (PRUNE && rule.eps) ? rule.eps_at(qi, r, nprobe) : 0.0f;
     uint64_t e = kEmptyKey, kth = kEmptyKey;
     unsigned long long live_vals = 0, lane_vals = 0;
     for (int32_t g = goff[l]; g < goff[l + 1]; ++g) {
@@ -257,7 +258,9 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
             if (PRUNE) {
                 // the prune test after c1 of d dimensions (exact at c1 = d)
                 float thr = tau_eff;
-                if (c1 < d) thr = tau_eff * (rule.fac ? rule.learned(qi, r, nprobe, c0 / chunk) : rule.ads(c1, d));
+                if (c1 < d)
+                    thr = tau_eff * (rule.eps ? PruneRule::learned(eps_i, (float)c1 / (float)d, prune_rs(c1))
+                                              : rule.ads(c1, d));
                 alive = alive && !(partial > thr);
             }
         }
@@ -314,6 +317,10 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
         }
     }
     if (!use) return;
+    float epsq[QB];  // learned bound of each query's item
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+        epsq[q] = (PRUNE && rule.eps && ((use >> q) & 1u)) ? rule.eps_at(qid[q], rk[q], nprobe) : 0.0f;
     uint64_t e[QB], kth[QB];
     float part[QB], s[QB];
 #pragma unroll
@@ -380,15 +387,19 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
                     }
                 }
             }
-            float fac = 1.0f;
-            const bool learned = PRUNE && c1 < d && rule.fac;
-            if (PRUNE && c1 < d && !rule.fac) fac = rule.ads(c1, d);
+            float fac = 1.0f, cdl = 0.0f, rsl = 0.0f;
+            const bool learned = PRUNE && c1 < d && rule.eps;
+            if (PRUNE && c1 < d && !rule.eps) fac = rule.ads(c1, d);
+            if (learned) {
+                cdl = (float)c1 / (float)d;
+                rsl = prune_rs(c1);
+            }
 #pragma unroll
             for (int q = 0; q < QB; ++q) {
                 if ((qa >> q) & 1u) {
                     part[q] += s[q];
                     // the prune test after c1 of d dimensions (exact at c1 = d)
-                    const float fq = learned ? rule.learned(qid[q], rk[q], nprobe, c0 / chunk) : fac;
+                    const float fq = learned ? PruneRule::learned(epsq[q], cdl, rsl) : fac;
                     if (PRUNE && part[q] > teff[q] * fq) am &= ~(1u << q);
                 }
             }
@@ -504,23 +515,16 @@ __device__ __forceinline__ void prune_inputs(float t, float d0, float dr, int32_
     x[4] = x[5] = x[6] = x[7] = 0.0f;
 }
 
-// The multiplier after c1 dimensions for the learned error bound eps:
-// max(1 + eps/sqrt(c1), 0)^2, capped at 1e30.
-__device__ __forceinline__ float prune_mult(float eps, int32_t c1) {
-    const float b = fmaxf(1.0f + eps / sqrtf((float)c1), 0.0f);
-    return fminf(b * b, 1.0e30f);
-}
-
-// Learned prune factors after START: one wave per (query, rank r >= 1)
-// evaluates the network once (eps = scale * z), then lanes fill the test
-// points c (c1 = (c + 1) chunk < d): fac receives (c1/d) m, table
-// (optional) m.  Also records the START threshold in tau0.  Non-finite
+// Learned prune bounds after START: one wave per (query, rank r >= 1)
+// evaluates the network once: eps = scale * z; table (optional) receives
+// the multiplier prune_mult(eps, c1) of every test point c (c1 = (c + 1)
+// chunk < d).  Also records the START threshold in tau0.  Non-finite
 // queries are not scanned: their rows hold NaN in `table`.
 __global__ __launch_bounds__(256) void prune_table_kernel(
     const float *__restrict__ qrot, int32_t d, const float *__restrict__ cd, int32_t nlist,
     const int32_t *__restrict__ probe, int32_t nprobe, const uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, const __half *__restrict__ w16, float scale, int32_t chunk, int32_t npt,
-    int64_t npairs, float *__restrict__ fac, float *__restrict__ table, float *__restrict__ tau0) {
+    int64_t npairs, float *__restrict__ epsq, float *__restrict__ table, float *__restrict__ tau0) {
     __shared__ float feat[4][kMlpIn];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t pr = (int64_t)blockIdx.x * 4 + wave;
@@ -550,12 +554,9 @@ __global__ __launch_bounds__(256) void prune_table_kernel(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const float eps = scale * mlp_forward_wave(w16, feat[wave], lane, nullptr, nullptr, nullptr, nullptr);
-    for (int32_t c = lane; c < npt; c += 64) {
-        const int32_t c1 = (c + 1) * chunk;
-        const float m = prune_mult(eps, c1);
-        fac[row + c] = ((float)c1 / (float)d) * m;
-        if (table) table[row + c] = m;
-    }
+    if (lane == 0) epsq[pr] = eps;
+    if (table)
+        for (int32_t c = lane; c < npt; c += 64) table[row + c] = prune_mult(eps, prune_rs((c + 1) * chunk));
 }
 
 // Training traces of the prune network, after the result is known: one
@@ -848,9 +849,9 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.ptable = p ? p->prune_table : nullptr;
     pl.trace_pf = p ? p->trace_prune_features : nullptr;
     pl.trace_pt = p ? p->trace_prune_target : nullptr;
-    pl.pfac = (pl.pw16 && nprobe > 1 && pl.npt > 0) ? c.take<float>(q * (nprobe - 1) * pl.npt) : nullptr;
+    pl.peps = (pl.pw16 && nprobe > 1 && pl.npt > 0) ? c.take<float>(q * (nprobe - 1)) : nullptr;
     pl.tau0 = (pl.trace_pf && pl.npt > 0) ? c.take<float>(q) : nullptr;
-    pl.rule = PruneRule{pl.eps0, pl.pfac, pl.npt};
+    pl.rule = PruneRule{pl.eps0, pl.peps};
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
     pl.counters = p ? p->counters : nullptr;
     if (plan) *plan = pl;
@@ -980,12 +981,12 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                   pl.w16, pl.zthr, pl.budget, pl.trace_f);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // learned prune factors (and the START threshold for the traces)
-    if ((pl.pfac || pl.tau0) && pl.nprobe > 1) {
+    // learned prune bounds (and the START threshold for the traces)
+    if ((pl.peps || pl.tau0) && pl.nprobe > 1) {
         const int64_t npairs = nq * (pl.nprobe - 1);
         prune_table_kernel<<<(unsigned)((npairs + 3) / 4), 256, 0, s>>>(
-            pl.qrot, d, pl.cd, ix->nlist, pl.probe, pl.nprobe, pl.tau, pl.bad, pl.pfac ? pl.pw16 : nullptr,
-            pl.pscale, pl.chunk, pl.npt, npairs, pl.pfac, pl.ptable, pl.tau0);
+            pl.qrot, d, pl.cd, ix->nlist, pl.probe, pl.nprobe, pl.tau, pl.bad, pl.peps ? pl.pw16 : nullptr,
+            pl.pscale, pl.chunk, pl.npt, npairs, pl.peps, pl.ptable, pl.tau0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (later) {  // items of ranks 1 .. budget - 1

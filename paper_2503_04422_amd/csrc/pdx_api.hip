@@ -134,6 +134,7 @@ pdx_status pdx_build(const float *x, int64_t n, int32_t d, const pdx_build_param
 size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, int32_t k,
                                   const pdx_search_params *params) {
     if (!index || (index->kind != kFlat && index->kind != kIvf) || nq < 0 || k < 1 || k > PDX_MAX_K) return 0;
+    if (params && (params->metric < PDX_METRIC_L2 || params->metric > PDX_METRIC_IP)) return 0;
     return exact_plan(index, nq, k, params, nullptr, nullptr);
 }
 
@@ -155,6 +156,14 @@ pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, 
     if (params && params->mode != PDX_MODE_LINEAR && params->mode != PDX_MODE_BOND) {
         set_error("pdx_search_exact: unknown mode %d", params->mode);
         return PDX_EINVAL;
+    }
+    if (params && (params->metric < PDX_METRIC_L2 || params->metric > PDX_METRIC_IP)) {
+        set_error("pdx_search_exact: unknown metric %d", params->metric);
+        return PDX_EINVAL;
+    }
+    if (params && params->metric == PDX_METRIC_IP && params->mode != PDX_MODE_LINEAR) {
+        set_error("pdx_search_exact: the inner product has no pruning bound; use PDX_MODE_LINEAR");
+        return PDX_EUNSUPPORTED;
     }
     if (params && (params->chunk < 0 || params->tile_groups < 0 ||
                    !(params->queries_per_block == 0 || params->queries_per_block == 1 ||

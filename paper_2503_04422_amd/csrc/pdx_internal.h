@@ -88,6 +88,9 @@ struct ExactPlan {
     bool use_tiles;        // LDS tile path (else the group path only)
     bool ivf;              // bucket layout (IVF index): rows in bucket order, ids through slot_id
     int32_t start_parts;   // bucket layout: waves per query in START
+    int32_t metric;        // PDX_METRIC_*
+    int32_t ip_parts;      // inner product: vectorgroup ranges (a multiple of 8)
+    uint64_t *ip_slots;    // inner product: [nq][ip_parts][k] k-best lists
     // workspace parts
     uint32_t *tau;
     int32_t *bad;
@@ -134,23 +137,33 @@ struct SlotMap {
     }
 };
 
+// The multiplier after c1 dimensions for an error bound eps:
+// max(1 + eps/sqrt(c1), 0)^2, capped at 1e30 (ADSampling's shape).  rs is
+// 1/sqrt(c1) (prune_rs), computed once per test point by the scans.
+__device__ __forceinline__ float prune_rs(int32_t c1) { return 1.0f / sqrtf((float)c1); }
+__device__ __forceinline__ float prune_mult(float eps, float rs) {
+    const float b = fmaxf(fmaf(eps, rs, 1.0f), 0.0f);
+    return fminf(b * b, 1.0e30f);
+}
+
 // The test of a bucket of probe rank r >= 1 after c1 < D dimensions: drop
 // a vector when its partial distance exceeds tau_now * factor, with factor
-// (c1/D) (1 + eps0/sqrt(c1))^2 (ADSampling), or (c1/D) m from the learned
-// table fac [nq][nprobe-1][npt] at test point c = c0 / chunk.  After all D
-// dimensions the factor is 1 (exact).
+// (c1/D) (1 + eps0/sqrt(c1))^2 (ADSampling), or (c1/D) prune_mult(eps, c1)
+// with the learned bound eps [nq][nprobe-1] of the (query, bucket).  After
+// all D dimensions the factor is 1 (exact).
 struct PruneRule {
     float eps0;
-    const float *fac;  // null: ADSampling
-    int32_t npt;       // test points per bucket: ceil(D / chunk) - 1
+    const float *eps;  // null: ADSampling
     __device__ __forceinline__ float ads(int32_t c1, int32_t d) const {
         const float dc = (float)c1;
         const float f = 1.0f + eps0 / sqrtf(dc);
         return (dc / (float)d) * f * f;
     }
-    __device__ __forceinline__ float learned(int64_t q, int32_t r, int32_t nprobe, int32_t c) const {
-        return fac[((size_t)q * (nprobe - 1) + (r - 1)) * npt + c];
+    __device__ __forceinline__ float eps_at(int64_t q, int32_t r, int32_t nprobe) const {
+        return eps[(size_t)q * (nprobe - 1) + (r - 1)];
     }
+    // (c1/D) prune_mult(e, rs): cd = c1/D and rs = 1/sqrt(c1) of the test point
+    __device__ __forceinline__ static float learned(float e, float cd, float rs) { return cd * prune_mult(e, rs); }
 };
 
 struct IvfPlan {
@@ -177,7 +190,7 @@ struct IvfPlan {
     int32_t *trace_need;
     const __half *pw16;   // prune-multiplier network (null: ADSampling)
     float pscale;         // multiplier scale
-    float *pfac;          // [nq][nprobe-1][npt] learned test factors
+    float *peps;          // [nq][nprobe-1] learned error bounds
     float *ptable;        // optional out: the multipliers
     float *trace_pf;      // prune traces: [nq][k][npt][72] inputs
     float *trace_pt;      // [nq][k][npt] targets
@@ -198,6 +211,15 @@ struct IvfPlan {
     hipEvent_t *events;
     unsigned long long *counters;
 };
+
+// Exact inner-product search on the matrix cores (k_exact_ip.hip): 64
+// queries x the vectorgroups of one of `parts` ranges per workgroup, then
+// the per-range lists merged; -q.v reported.
+hipError_t launch_ip_scan(const pdx_index *ix, const float *q, int64_t nq, const int32_t *bad, int32_t parts,
+                          uint64_t *slots, int32_t k, hipStream_t s);
+hipError_t launch_ip_merge(const uint64_t *slots, int64_t nq, int32_t parts, int32_t k, const int32_t *bad,
+                           int64_t *out_ids, float *out_dist, hipStream_t s);
+int32_t ip_parts_for(int64_t nq, int32_t ngroups);
 
 // PDX-BOND inside IVF (k_exact.hip): query order and per-item bucket scans.
 hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *means, int32_t *perm, float *qperm,

@@ -88,3 +88,62 @@ def test_recall_definition():
     t = np.array([[1, 2, 3, 4]])
     assert exact.recall_at_k(t, np.array([[4, 3, 9, 8]])) == 0.5
     assert exact.recall_at_k(t, t) == 1.0
+
+
+# ---------------------------------------------------------------------------
+# L1 and inner product (the other two kernels of Section 3's listing)
+# ---------------------------------------------------------------------------
+
+def test_metrics_hand_worked():
+    # rows (0,0), (1,2), (3,-1), (-2,2); query (1,1)
+    x = np.array([[0.0, 0.0], [1.0, 2.0], [3.0, -1.0], [-2.0, 2.0]])
+    q = np.array([[1.0, 1.0]])
+    # L1: 2, 1, 4, 4 -> ids 1, 0, then the tie 2 / 3 by id
+    i, d = exact.knn_exact(x, q, 4, metric="l1")
+    assert i[0].tolist() == [1, 0, 2, 3] and d[0].tolist() == [1.0, 2.0, 4.0, 4.0]
+    # inner products 0, 3, 2, 0 -> scores -3, -2, then 0, 0 by id
+    i, d = exact.knn_exact(x, q, 4, metric="ip")
+    assert i[0].tolist() == [1, 2, 0, 3] and d[0].tolist() == [-3.0, -2.0, 0.0, 0.0]
+
+
+def test_l1_matches_scipy_cityblock():
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((300, 17)).astype(np.float32)
+    q = rng.standard_normal((5, 17)).astype(np.float32)
+    i, d = exact.knn_exact(x, q, 12, metric="l1")
+    ref = cdist(q.astype(np.float64), x.astype(np.float64), "cityblock")
+    for r in range(5):
+        o = np.lexsort((np.arange(300), ref[r]))[:12]
+        assert i[r].tolist() == o.tolist()
+        np.testing.assert_allclose(d[r], ref[r][o], rtol=1e-13)
+
+
+def test_inner_product_brute_force_and_unit_norm_equivalence():
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal((40, 6))
+    q = rng.standard_normal((3, 6))
+    i, d = exact.knn_exact(x, q, 7, metric="ip")
+    for r in range(3):
+        ip = [sum(x[v, j] * q[r, j] for j in range(6)) for v in range(40)]
+        o = sorted(range(40), key=lambda v: (-ip[v], v))[:7]
+        assert i[r].tolist() == o
+        np.testing.assert_allclose(d[r], [-ip[v] for v in o], rtol=1e-12)
+    # on unit vectors |q - v|^2 = 2 - 2 q.v: the same order as L2
+    xn = x / np.linalg.norm(x, axis=1, keepdims=True)
+    qn = q / np.linalg.norm(q, axis=1, keepdims=True)
+    i2, d2 = exact.knn_exact(xn, qn, 7)
+    ii, di = exact.knn_exact(xn, qn, 7, metric="ip")
+    assert np.array_equal(i2, ii)
+    np.testing.assert_allclose(d2, 2.0 + 2.0 * di, rtol=1e-12, atol=1e-12)
+
+
+def test_blocked_brute_force_equals_plain():
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal((1000, 9)).astype(np.float32)
+    q = rng.standard_normal((4, 9)).astype(np.float32)
+    for metric in ("l2", "l1", "ip"):
+        for k in (1, 10, 1200):
+            a = exact.knn_exact(x, q, k, metric=metric)
+            b = exact.knn_exact_blocked(x, q, k, metric=metric, block=97)
+            assert np.array_equal(a[0], b[0]) and np.allclose(a[1], b[1], rtol=1e-13, atol=0)
