@@ -34,18 +34,25 @@
 namespace pdx {
 namespace {
 
+constexpr int kTV = 32;       // vectors per LDS tile (half a vectorgroup)
+constexpr int kTW = 16;       // waves per workgroup
+constexpr int kQCap = 2048;   // survivor queue entries per tile in LDS
+constexpr int kGCap = 16384;  // further entries per workgroup in global memory
+
 // ---------------------------------------------------------------------------
 // Query preparation: visit order and permuted query values.
 // PDX-BOND (Section 5): dimensions by |q_j - mean_j| descending, ties by j.
 // Sort key (ascending): (~bits(|q_j - mean_j|) << 32) | j.
-// perm[j] is the j-th visited dimension; qperm[j] the query value there.
+// perm[j] is the j-th visited dimension; qperm[j] the query value there;
+// poff[j] (optional, tile path: d kTV < 65536) its LDS tile row offset
+// perm[j] * kTV, half the size of perm in the tile kernel's registers.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, int32_t d,
                                                    const float *__restrict__ means, int32_t mode,
                                                    int32_t pow2, int32_t *__restrict__ perm,
                                                    float *__restrict__ qperm,
                                                    uint32_t *__restrict__ tau,
-                                                   int32_t *__restrict__ bad) {
+                                                   int32_t *__restrict__ bad, uint16_t *__restrict__ poff) {
     extern __shared__ uint64_t smem[];
     uint64_t *keys = smem;                                   // [pow2]
     float *qs = reinterpret_cast<float *>(smem + pow2);     // [d]
@@ -60,10 +67,12 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
     nonfinite = __syncthreads_or(nonfinite);
     int32_t *po = perm + qi * d;
     float *qp = qperm + qi * d;
+    uint16_t *pf = poff ? poff + qi * d : nullptr;
     if (mode == PDX_MODE_LINEAR) {
         for (int j = threadIdx.x; j < d; j += blockDim.x) {
             po[j] = j;
             qp[j] = qs[j];
+            if (pf) pf[j] = static_cast<uint16_t>(j * kTV);
         }
     } else {
         for (int j = threadIdx.x; j < pow2; j += blockDim.x) {
@@ -95,6 +104,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
             int32_t src = static_cast<int32_t>(keys[j] & 0xffffffffu);
             po[j] = src;
             qp[j] = qs[src];
+            if (pf) pf[j] = static_cast<uint16_t>(src * kTV);
         }
     }
     if (threadIdx.x == 0) {
@@ -389,10 +399,6 @@ __global__ void over_list_kernel(const int32_t *__restrict__ cand_cnt, int64_t n
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kTV = 32;       // vectors per LDS tile (half a vectorgroup)
-constexpr int kTW = 16;       // waves per workgroup
-constexpr int kQCap = 4096;   // survivor queue entries per tile in LDS
-constexpr int kGCap = 16384;  // further entries per workgroup in global memory
 
 __device__ __forceinline__ void cand_append(uint64_t *__restrict__ cand, int32_t *__restrict__ cnt, int32_t cap,
                                             int64_t qi, float dist, uint32_t id) {
@@ -405,21 +411,32 @@ __device__ __forceinline__ int lane_rank(unsigned long long m) {
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0));
 }
 
-// Full chunk c of the visit order for vector v of the LDS tile: 16 + 16
-// fused multiply-adds, per-lane query (metadata loaded 16 bytes at a time).
-__device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, const int32_t *__restrict__ po,
+// Four LDS row offsets (tile path) from two words of 16-bit offsets.
+__device__ __forceinline__ void unpack_off(uint32_t w0, uint32_t w1, int (&o)[4]) {
+    o[0] = (int)(w0 & 0xffffu);
+    o[1] = (int)(w0 >> 16);
+    o[2] = (int)(w1 & 0xffffu);
+    o[3] = (int)(w1 >> 16);
+}
+
+// Full chunk of 32 visited dimensions for vector v of the LDS tile: 16 + 16
+// fused multiply-adds, per-lane query (pf: the chunk's 16-bit row offsets,
+// qp: its query values; loaded 16 bytes at a time).
+__device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, const uint16_t *__restrict__ pf,
                                             const float *__restrict__ qp, int v) {
-    const int4 *o4 = reinterpret_cast<const int4 *>(po);
+    const uint4 *o4 = reinterpret_cast<const uint4 *>(pf);
     const float4 *q4 = reinterpret_cast<const float4 *>(qp);
     float lo = 0.0f, hi = 0.0f;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        int4 o = o4[u];
+        const uint4 ow = o4[u >> 1];
+        int o[4];
+        unpack_off((u & 1) ? ow.z : ow.x, (u & 1) ? ow.w : ow.y, o);
         float4 qq = q4[u];
-        float t0 = qq.x - tile[o.x * kTV + v];
-        float t1 = qq.y - tile[o.y * kTV + v];
-        float t2 = qq.z - tile[o.z * kTV + v];
-        float t3 = qq.w - tile[o.w * kTV + v];
+        float t0 = qq.x - tile[o[0] + v];
+        float t1 = qq.y - tile[o[1] + v];
+        float t2 = qq.z - tile[o[2] + v];
+        float t3 = qq.w - tile[o[3] + v];
         float &s = u < 4 ? lo : hi;
         s = fmaf(t0, t0, s);
         s = fmaf(t1, t1, s);
@@ -430,22 +447,22 @@ __device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, cons
 }
 
 // One query's first visited chunk as this lane's half sees it: 16
-// dimensions and query values, the threshold and the non-finite flag.
+// dimensions (16-bit LDS row offsets, query values), the threshold and
+// the non-finite flag.
 struct FirstChunk {
-    int4 o[4];
+    uint4 o[2];
     float4 q[4];
     float tau;
     int bad;
-    __device__ __forceinline__ void load(const int32_t *__restrict__ perm, const float *__restrict__ qperm,
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ poff, const float *__restrict__ qperm,
                                          const uint32_t *__restrict__ tau_all, const int32_t *__restrict__ bad_all,
                                          int64_t qi, int32_t d, int half) {
-        const int4 *o4 = reinterpret_cast<const int4 *>(perm + qi * d + half * 16);
+        const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + half * 16);
         const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + half * 16);
+        o[0] = o4[0];
+        o[1] = o4[1];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            o[u] = o4[u];
-            q[u] = q4[u];
-        }
+        for (int u = 0; u < 4; ++u) q[u] = q4[u];
         tau = __uint_as_float(tau_all[qi]);
         bad = bad_all[qi];
     }
@@ -455,18 +472,29 @@ constexpr int kDense = 8;  // survivors of the first chunk from which a (query, 
 
 // DENSE (bucket layout, where a query's own cluster fills whole tiles): a
 // (query, tile) pair with at least kDense first-chunk survivors is finished
-// by its wave; other survivors go to the queue.
+// by its wave; other survivors go to the queue.  On this layout a tile's
+// rows lie within radius r of their bucket's centroid c, so every row is at
+// squared distance at least (|q - c| - r)^2 from the query (triangle
+// inequality): a query whose threshold is below that bound skips the tile.
+// The bound takes |q - c| 1e-4 low (sqrt of a float32 sum of D squares)
+// and r rounded up, so it never exceeds a row's distance.  Per tile, the
+// queries that remain are listed in LDS, kList at a time, and the waves
+// take them from the list.
+constexpr int kList = 1024;
+
 template <bool DENSE>
 __global__ __launch_bounds__(1024) void tile_kernel(
     const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t t_begin,
     int32_t t_end, int64_t nq,
-    const int32_t *__restrict__ perm, const float *__restrict__ qperm, const uint32_t *__restrict__ tau,
+    const uint16_t *__restrict__ poff, const float *__restrict__ qperm, const uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, uint64_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int32_t cap,
-    uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters) {
+    uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters, const float *__restrict__ cd,
+    int32_t nlist, const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad) {
     extern __shared__ float4 smem4[];
     float *tile = reinterpret_cast<float *>(smem4);                          // [d][32]
     uint2 *queue = reinterpret_cast<uint2 *>(tile + (size_t)d * kTV);        // [kQCap]
-    __shared__ int32_t qcount, qhead;
+    __shared__ int32_t qcount, qhead, lcount;
+    __shared__ int32_t qlist[DENSE ? kList : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int v = lane & 31;
@@ -496,19 +524,52 @@ __global__ __launch_bounds__(1024) void tile_kernel(
         // The next query's first-chunk metadata is loaded while the current
         // one is scanned (one query per wave in flight otherwise stalls on
         // memory latency).
-        FirstChunk cur, nxt;
-        if (wave < nq) cur.load(perm, qperm, tau, bad, wave, d, half);
-        for (int64_t qi = wave; qi < nq; qi += kTW) {
-            const int64_t qn = qi + kTW;
-            if (qn < nq) nxt.load(perm, qperm, tau, bad, qn, d, half);
+        int32_t tb = 0;
+        float trad = 0.0f;
+        if (DENSE) {
+            tb = group_bucket[t >> 1];
+            trad = tile_rad[t];
+        }
+        for (int64_t q0 = 0; q0 < nq; q0 += (DENSE ? kList : nq)) {
+          int32_t cnt = (int32_t)nq;
+          if (DENSE) {
+            // the queries of [q0, q0 + kList) the centroid bound keeps
+            __syncthreads();  // the previous list is no longer read
+            if (threadIdx.x == 0) lcount = 0;
+            __syncthreads();
+            const int64_t qt = q0 + threadIdx.x;
+            bool keep = false;
+            if (threadIdx.x < kList && qt < nq && !bad[qt]) {
+                const float dq = sqrtf(cd[qt * nlist + tb]) * (1.0f - 1e-4f);
+                const float gap = fmaxf(dq - trad, 0.0f);
+                const float tq = __uint_as_float(__hip_atomic_load(tau + qt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                keep = !(gap * gap > tq);
+            }
+            const unsigned long long km = __ballot(keep);
+            int lb = 0;
+            if (lane == 0 && km) lb = atomicAdd(&lcount, __popcll(km));
+            lb = __shfl(lb, 0);
+            if (keep) qlist[lb + lane_rank(km)] = (int32_t)qt;
+            __syncthreads();
+            cnt = lcount;
+          }
+          auto qid = [&](int32_t e) -> int64_t { return DENSE ? (int64_t)qlist[e] : (int64_t)e; };
+          FirstChunk cur, nxt;
+          if (wave < cnt) cur.load(poff, qperm, tau, bad, qid(wave), d, half);
+          for (int32_t e = wave; e < cnt; e += kTW) {
+            const int64_t qi = qid(e);
+            if (e + kTW < cnt) nxt.load(poff, qperm, tau, bad, qid(e + kTW), d, half);
             if (!cur.bad) {
                 float s = 0.0f;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    float t0 = cur.q[u].x - tile[cur.o[u].x * kTV + v];
-                    float t1 = cur.q[u].y - tile[cur.o[u].y * kTV + v];
-                    float t2 = cur.q[u].z - tile[cur.o[u].z * kTV + v];
-                    float t3 = cur.q[u].w - tile[cur.o[u].w * kTV + v];
+                    const uint4 ow = cur.o[u >> 1];
+                    int o[4];
+                    unpack_off((u & 1) ? ow.z : ow.x, (u & 1) ? ow.w : ow.y, o);
+                    float t0 = cur.q[u].x - tile[o[0] + v];
+                    float t1 = cur.q[u].y - tile[o[1] + v];
+                    float t2 = cur.q[u].z - tile[o[2] + v];
+                    float t3 = cur.q[u].w - tile[o[3] + v];
                     s = fmaf(t0, t0, s);
                     s = fmaf(t1, t1, s);
                     s = fmaf(t2, t2, s);
@@ -526,24 +587,26 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                     // lanes = 32 vectors x 2 half-chunks as in the first chunk
                     bool al = (m >> v) & 1ull;
                     float p = partial;
-                    const int4 *o4 = reinterpret_cast<const int4 *>(perm + qi * d + half * 16);
+                    const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + half * 16);
                     const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + half * 16);
                     for (int32_t c = 1; c < nchunks; ++c) {
                         if (!__any(al)) break;
-                        int4 oc[4];
+                        uint4 oc[2];
                         float4 qc[4];
+                        oc[0] = o4[4 * c];
+                        oc[1] = o4[4 * c + 1];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            oc[u] = o4[8 * c + u];
-                            qc[u] = q4[8 * c + u];
-                        }
+                        for (int u = 0; u < 4; ++u) qc[u] = q4[8 * c + u];
                         float s2 = 0.0f;
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            float t0 = qc[u].x - tile[oc[u].x * kTV + v];
-                            float t1 = qc[u].y - tile[oc[u].y * kTV + v];
-                            float t2 = qc[u].z - tile[oc[u].z * kTV + v];
-                            float t3 = qc[u].w - tile[oc[u].w * kTV + v];
+                            const uint4 ow = oc[u >> 1];
+                            int o[4];
+                            unpack_off((u & 1) ? ow.z : ow.x, (u & 1) ? ow.w : ow.y, o);
+                            float t0 = qc[u].x - tile[o[0] + v];
+                            float t1 = qc[u].y - tile[o[1] + v];
+                            float t2 = qc[u].z - tile[o[2] + v];
+                            float t3 = qc[u].w - tile[o[3] + v];
                             s2 = fmaf(t0, t0, s2);
                             s2 = fmaf(t1, t1, s2);
                             s2 = fmaf(t2, t2, s2);
@@ -576,12 +639,12 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                                 own = true;
                         }
                         if (__any(own)) {
-                            const int32_t *po = perm + qi * d;
+                            const uint16_t *pf = poff + qi * d;
                             const float *qp = qperm + qi * d;
                             float p = partial;
                             for (int32_t c = 1; c < nchunks && __any(own); ++c) {
                                 if (own) {
-                                    p += tile_chunk(tile, po + c * 32, qp + c * 32, v);
+                                    p += tile_chunk(tile, pf + c * 32, qp + c * 32, v);
                                     own = !(p > cur.tau);
                                 }
                             }
@@ -591,6 +654,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                 }
             }
             cur = nxt;
+          }
         }
         __syncthreads();
 
@@ -635,7 +699,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
             if (act) {
                 const int64_t qi = qv >> 5;
                 const int vv = qv & 31;
-                p += tile_chunk(tile, perm + qi * d + c * 32, qperm + qi * d + c * 32, vv);
+                p += tile_chunk(tile, poff + qi * d + c * 32, qperm + qi * d + c * 32, vv);
                 ++c;
                 if (p > tl) {
                     act = false;
@@ -672,11 +736,12 @@ size_t max_dynamic_lds() {
     if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
     if (hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) plain = 0;
     size_t m = (size_t)(optin > plain ? optin : plain);
-    return m > 64 ? m - 64 : 0;  // room for the kernel's static LDS
+    const size_t stat = 64 + kList * sizeof(int32_t);  // room for the kernel's static LDS (scalars, query list)
+    return m > stat ? m - stat : 0;
 }
 
 bool tile_path(const pdx_index *ix, const ExactPlan &pl) {
-    return pl.mode == PDX_MODE_BOND && pl.metric == PDX_METRIC_L2 && pl.chunk == 32 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
+    return pl.mode == PDX_MODE_BOND && pl.metric == PDX_METRIC_L2 && pl.chunk == 32 && ix->d * kTV < 65536 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
            pl.tiles_main > 0 && tile_lds_bytes(ix->d) <= max_dynamic_lds();
 }
 
@@ -741,13 +806,17 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.qperm = c.take<float>(q * ix->d);
     pl.slots = pl.metric == PDX_METRIC_IP ? nullptr : c.take<uint64_t>(q * pl.nslots * k);
     if (pl.ivf) {
-        pl.start_parts = 4;
+        // waves per query in START: about 8 per SIMD in all, 1 .. 16
+        int32_t sp = 1;
+        while (sp < 16 && (int64_t)sp * nq < 8 * 4 * (int64_t)device_cus()) sp <<= 1;
+        pl.start_parts = sp;
         pl.qrot = ix->has_rot ? c.take<float>(q * ix->d) : nullptr;
         pl.cd = pl.mode == PDX_MODE_BOND ? c.take<float>(q * ix->nlist) : nullptr;
         pl.nearest = pl.mode == PDX_MODE_BOND ? c.take<int32_t>(q) : nullptr;
         pl.start_slots = pl.mode == PDX_MODE_BOND ? c.take<uint64_t>(q * pl.start_parts * k) : nullptr;
     }
     if (pl.use_tiles) {
+        pl.poff = c.take<uint16_t>(q * ix->d);
         const int32_t cus = device_cus();
         pl.tile_grid = cus;  // one workgroup per compute unit (the LDS tile fills the CU)
         pl.gqueue = c.take<uint64_t>((size_t)cus * kGCap);
@@ -781,7 +850,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         qs = pl.qrot;
     }
     prep_kernel<<<dim3((unsigned)pl.nq), dim3(256), lds, s>>>(qs, d, ix->means, pl.mode, pow2, pl.perm,
-                                                              pl.qperm, pl.tau, pl.bad);
+                                                              pl.qperm, pl.tau, pl.bad, pl.use_tiles ? pl.poff : nullptr);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (pl.metric == PDX_METRIC_IP) {  // linear inner-product scan on the matrix cores
         if ((err = mark(1)) != hipSuccess) return err;
@@ -872,13 +941,13 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         if (b <= a) continue;
         const unsigned grid = (unsigned)min(b - a, cus);
         if (pl.ivf)
-            tile_kernel<true><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.perm, pl.qperm,
+            tile_kernel<true><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,
                                                            pl.tau, pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue,
-                                                           cmain);
+                                                           cmain, pl.cd, ix->nlist, ix->group_bucket, ix->tile_rad);
         else
-            tile_kernel<false><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.perm, pl.qperm,
+            tile_kernel<false><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,
                                                             pl.tau, pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue,
-                                                            cmain);
+                                                            cmain, nullptr, 0, nullptr, nullptr);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         if (r + 1 < kRounds) {
             cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, pl.k, pl.bad, pl.tau, nullptr, 0, 0,
@@ -908,7 +977,8 @@ hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *
     if (nq <= 0) return hipSuccess;
     const int32_t pow2 = next_pow2(d);
     const size_t lds = pow2 * sizeof(uint64_t) + d * sizeof(float);
-    prep_kernel<<<dim3((unsigned)nq), dim3(256), lds, s>>>(q, d, means, PDX_MODE_BOND, pow2, perm, qperm, tau, bad);
+    prep_kernel<<<dim3((unsigned)nq), dim3(256), lds, s>>>(q, d, means, PDX_MODE_BOND, pow2, perm, qperm, tau, bad,
+                                                           nullptr);
     return hipGetLastError();
 }
 

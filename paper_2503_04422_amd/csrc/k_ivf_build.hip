@@ -320,7 +320,56 @@ __global__ __launch_bounds__(256) void gather_lowp_kernel(const float *__restric
     }
 }
 
+// The bucket of every stored vectorgroup (one thread per bucket).
+__global__ void group_bucket_kernel(const int32_t *__restrict__ goff, int32_t nlist, int32_t *__restrict__ gb) {
+    const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nlist) return;
+    for (int32_t g = goff[b]; g < goff[b + 1]; ++g) gb[g] = b;
+}
+
+// Radius of every 32-vector tile (half a vectorgroup) around its bucket's
+// centroid: the largest |x - c| over the tile's rows, float64 sums, widened
+// by 1e-6 and rounded up to float32 (0 for a tile of padding only).  One
+// wave per tile; lanes 0..31 are its vectors.
+__global__ __launch_bounds__(256) void tile_radius_kernel(const float *__restrict__ pdx,
+                                                          const int32_t *__restrict__ slot_id,
+                                                          const int32_t *__restrict__ goff, int32_t nlist,
+                                                          const int32_t *__restrict__ gb,
+                                                          const float *__restrict__ cen, int32_t d, int64_t max_tiles,
+                                                          float *__restrict__ rad) {
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (t >= max_tiles) return;
+    const int32_t g = (int32_t)(t >> 1);
+    if (g >= goff[nlist]) return;
+    const int32_t b = gb[g];
+    const int v = (int)(t & 1) * 32 + (lane & 31);
+    double acc = 0.0;
+    if (lane < 32 && slot_id[(int64_t)g * kGroup + v] >= 0) {
+        const float *xp = pdx + (int64_t)g * d * kGroup + v;
+        const float *cp = cen + (int64_t)b * d;
+        for (int32_t j = 0; j < d; ++j) {
+            const double e = (double)xp[(int64_t)j * kGroup] - (double)cp[j];
+            acc = fma(e, e, acc);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc = fmax(acc, __shfl_xor(acc, off));
+    if (lane == 0) rad[t] = __double2float_ru(sqrt(acc) * (1.0 + 1e-6));
+}
+
 }  // namespace
+
+hipError_t launch_tile_radii(const float *pdx, const int32_t *slot_id, const int32_t *goff, int32_t nlist,
+                             const float *cen, int32_t d, int64_t max_groups, int32_t *gb, float *rad,
+                             hipStream_t s) {
+    group_bucket_kernel<<<(unsigned)((nlist + 255) / 256), 256, 0, s>>>(goff, nlist, gb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t tiles = 2 * max_groups;
+    tile_radius_kernel<<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(pdx, slot_id, goff, nlist, gb, cen, d, tiles, rad);
+    return hipGetLastError();
+}
 
 hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int32_t *slot_id, const int32_t *stats,
                              int64_t max_groups, uint16_t *pdx16, uint8_t *pdx8, float *scale, uint32_t *maxbits,

@@ -44,6 +44,8 @@ struct pdx_index {
     float *fp8_scale;    // [d] per-dimension scale (optional)
     float *xrow;         // [n][d] rotated rows, row-major (rerank)
     int32_t max_list;    // largest bucket, rows
+    int32_t *group_bucket;  // [ngroups] bucket of each vectorgroup
+    float *tile_rad;        // [2 ngroups] radius of each 32-vector tile around its centroid
 };
 
 namespace pdx {
@@ -96,6 +98,7 @@ struct ExactPlan {
     int32_t *bad;
     int32_t *perm;         // [nq][d] visited dimension order
     float *qperm;          // [nq][d] query values in that order
+    uint16_t *poff;        // tile path: [nq][d] LDS tile row offsets of that order
     uint64_t *slots;       // [nq][nslots][k] group-path k-best lists
     uint64_t *cand;        // [nq][cap] tile-path candidates
     int32_t *cand_cnt;     // [nq]
@@ -315,6 +318,11 @@ __device__ inline uint32_t e4m3_encode(float v) {
 // instruction reads the OCP e4m3 format from the low byte.
 __device__ inline float e4m3_decode(uint32_t c) { return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(c), 0); }
 
+// Bucket layout: the bucket of every vectorgroup, and the radius of every
+// 32-vector tile around its bucket's centroid (rounded up).
+hipError_t launch_tile_radii(const float *pdx, const int32_t *slot_id, const int32_t *goff, int32_t nlist,
+                             const float *cen, int32_t d, int64_t max_groups, int32_t *gb, float *rad,
+                             hipStream_t s);
 hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int32_t *slot_id, const int32_t *stats,
                              int64_t max_groups, uint16_t *pdx16, uint8_t *pdx8, float *scale, uint32_t *maxbits,
                              hipStream_t s);
