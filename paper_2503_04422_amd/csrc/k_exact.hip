@@ -251,6 +251,29 @@ __global__ __launch_bounds__(64) void nearest_kernel(const float *__restrict__ c
     if (lane == 0) nearest[qi] = static_cast<int32_t>(best & 0xffffffffu);
 }
 
+// Centroid bound inputs for the tile kernel: dql[l][q] = sqrt(cd[q][l])
+// lowered by 1e-4 (a lower bound of |q - c_l|: the float32 sum of D squares
+// carries at most about D 2^-24 relative error), bucket-major so that the
+// queries of one tile read one contiguous row.  32 x 32 blocks through LDS.
+__global__ __launch_bounds__(256) void centroid_lo_kernel(const float *__restrict__ cd, int64_t nq, int32_t nlist,
+                                                          float *__restrict__ dql) {
+    __shared__ float blk[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int64_t q0 = (int64_t)blockIdx.x * 32;
+    const int32_t l0 = blockIdx.y * 32;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t q = q0 + r;
+        const int32_t l = l0 + tx;
+        blk[r][tx] = (q < nq && l < nlist) ? sqrtf(cd[q * nlist + l]) * (1.0f - 1e-4f) : 0.0f;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int32_t l = l0 + r;
+        const int64_t q = q0 + tx;
+        if (q < nq && l < nlist) dql[(int64_t)l * nq + q] = blk[tx][r];
+    }
+}
+
 // START on a bucket layout (Section 4, PHASE 0 on the query's nearest
 // bucket instead of the first rows): `parts` waves per query share the
 // bucket's groups, each writing its own k-best list.
@@ -476,8 +499,8 @@ constexpr int kDense = 8;  // survivors of the first chunk from which a (query, 
 // rows lie within radius r of their bucket's centroid c, so every row is at
 // squared distance at least (|q - c| - r)^2 from the query (triangle
 // inequality): a query whose threshold is below that bound skips the tile.
-// The bound takes |q - c| 1e-4 low (sqrt of a float32 sum of D squares)
-// and r rounded up, so it never exceeds a row's distance.  Per tile, the
+// The bound takes |q - c| 1e-4 low (dql, from centroid_lo_kernel) and r
+// rounded up, so it never exceeds a row's distance.  Per tile, the
 // queries that remain are listed in LDS, kList at a time, and the waves
 // take them from the list.
 constexpr int kList = 1024;
@@ -488,8 +511,8 @@ __global__ __launch_bounds__(1024) void tile_kernel(
     int32_t t_end, int64_t nq,
     const uint16_t *__restrict__ poff, const float *__restrict__ qperm, const uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, uint64_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int32_t cap,
-    uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters, const float *__restrict__ cd,
-    int32_t nlist, const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad) {
+    uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters, const float *__restrict__ dql,
+    const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad) {
     extern __shared__ float4 smem4[];
     float *tile = reinterpret_cast<float *>(smem4);                          // [d][32]
     uint2 *queue = reinterpret_cast<uint2 *>(tile + (size_t)d * kTV);        // [kQCap]
@@ -540,8 +563,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
             const int64_t qt = q0 + threadIdx.x;
             bool keep = false;
             if (threadIdx.x < kList && qt < nq && !bad[qt]) {
-                const float dq = sqrtf(cd[qt * nlist + tb]) * (1.0f - 1e-4f);
-                const float gap = fmaxf(dq - trad, 0.0f);
+                const float gap = fmaxf(dql[(int64_t)tb * nq + qt] - trad, 0.0f);
                 const float tq = __uint_as_float(__hip_atomic_load(tau + qt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                 keep = !(gap * gap > tq);
             }
@@ -812,6 +834,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
         pl.start_parts = sp;
         pl.qrot = ix->has_rot ? c.take<float>(q * ix->d) : nullptr;
         pl.cd = pl.mode == PDX_MODE_BOND ? c.take<float>(q * ix->nlist) : nullptr;
+        pl.dql = pl.mode == PDX_MODE_BOND ? c.take<float>(q * ix->nlist) : nullptr;
         pl.nearest = pl.mode == PDX_MODE_BOND ? c.take<int32_t>(q) : nullptr;
         pl.start_slots = pl.mode == PDX_MODE_BOND ? c.take<uint64_t>(q * pl.start_parts * k) : nullptr;
     }
@@ -889,6 +912,8 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
             hipSuccess)
             return err;
         nearest_kernel<<<nqu, 64, 0, s>>>(pl.cd, ix->nlist, pl.nearest);
+        centroid_lo_kernel<<<dim3((unsigned)((pl.nq + 31) / 32), (unsigned)((ix->nlist + 31) / 32)), 256, 0, s>>>(
+            pl.cd, pl.nq, ix->nlist, pl.dql);
         const int64_t waves = pl.nq * pl.start_parts;
         if (l1)
             start_bucket_kernel<true><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
@@ -943,11 +968,11 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         if (pl.ivf)
             tile_kernel<true><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,
                                                            pl.tau, pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue,
-                                                           cmain, pl.cd, ix->nlist, ix->group_bucket, ix->tile_rad);
+                                                           cmain, pl.dql, ix->group_bucket, ix->tile_rad);
         else
             tile_kernel<false><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,
                                                             pl.tau, pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue,
-                                                            cmain, nullptr, 0, nullptr, nullptr);
+                                                            cmain, nullptr, nullptr, nullptr);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         if (r + 1 < kRounds) {
             cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, pl.k, pl.bad, pl.tau, nullptr, 0, 0,

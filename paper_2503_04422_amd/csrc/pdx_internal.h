@@ -108,6 +108,7 @@ struct ExactPlan {
     uint64_t *gqueue;      // [tile_grid][overflow cap] survivor entries
     float *qrot;           // bucket layout, rotated: [nq][d] rotated queries
     float *cd;             // bucket layout: [nq][nlist] centroid distances
+    float *dql;            // bucket layout: [nlist][nq] |q - c| lowered (centroid bound)
     int32_t *nearest;      // bucket layout: [nq] START bucket
     uint64_t *start_slots; // bucket layout: [nq][start_parts][k] START lists
     hipEvent_t *events;              // optional [4]
