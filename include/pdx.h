@@ -123,6 +123,11 @@ typedef struct {
                             by the pruned scan (live lanes only), [3] lane
                             slots it issued (live and pruned lanes) */
     int32_t metric;      /* PDX_METRIC_*; 0 = L2 */
+    int32_t start_rows;  /* bucket layout (IVF index): rows of the query's
+                            nearest bucket that START scans, in whole
+                            vectorgroups (Section 6.5 sizes the START block
+                            "at most"); 0 = 128.  The flat index takes its
+                            START block from pdx_build_params. */
 } pdx_search_params;
 
 /* Workspace bytes for pdx_search_exact with these arguments. */

@@ -53,7 +53,7 @@ class pdx_build_params(ctypes.Structure):
 class pdx_search_params(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("chunk", c_int32), ("tile_groups", c_int32),
                 ("queries_per_block", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
-                ("metric", c_int32)]
+                ("metric", c_int32), ("start_rows", c_int32)]
 
 
 class pdx_ivf_params(ctypes.Structure):

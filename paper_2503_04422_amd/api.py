@@ -84,8 +84,10 @@ _METRICS = {"l2": _lib.PDX_METRIC_L2, "l1": _lib.PDX_METRIC_L1, "ip": _lib.PDX_M
 
 
 def pdx_search_exact_workspace(index: PdxIndex, nq: int, k: int, mode: str = "bond", chunk: int = 0,
-                               tile_groups: int = 0, queries_per_block: int = 0, metric: str = "l2") -> int:
-    p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block, None, None, _METRICS[metric])
+                               tile_groups: int = 0, queries_per_block: int = 0, metric: str = "l2",
+                               start_rows: int = 0) -> int:
+    p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block, None, None, _METRICS[metric],
+                               int(start_rows))
     return int(lib.pdx_search_exact_workspace(index.handle, nq, k, ctypes.byref(p)))
 
 
@@ -94,11 +96,14 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
                      workspace: Optional[torch.Tensor] = None,
                      phase_events=None, counters: Optional[torch.Tensor] = None,
                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, metric: str = "l2",
+                     start_rows: int = 0,
                      stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Exact k nearest neighbours; returns (ids [nq, k] int64, dist [nq, k] float32).
 
     ``metric``: "l2" (squared Euclidean), "l1" (sum of absolute
     differences) or "ip" (-q.v, mode "linear" only).
+    ``start_rows``: bucket layout, rows of the nearest bucket START scans
+    (0 = 128).
     ``phase_events``: optional ctypes array of 4 hipEvent_t handles;
     ``counters``: optional int64 GPU tensor of 4 value counters."""
     q = _dev_f32(q, "q")
@@ -107,7 +112,7 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
         raise ValueError("query dimension does not match the index")
     p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block,
                                ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
-                               _ptr(counters), _METRICS[metric])
+                               _ptr(counters), _METRICS[metric], int(start_rows))
     if out is None:
         ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
         dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)

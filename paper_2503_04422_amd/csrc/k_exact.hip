@@ -275,12 +275,13 @@ __global__ __launch_bounds__(256) void centroid_lo_kernel(const float *__restric
 }
 
 // START on a bucket layout (Section 4, PHASE 0 on the query's nearest
-// bucket instead of the first rows): `parts` waves per query share the
-// bucket's groups, each writing its own k-best list.
+// bucket instead of the first rows): the first maxg vectorgroups of the
+// bucket; `parts` waves per query share them, each writing its own k-best
+// list.
 template <bool L1>
 __global__ __launch_bounds__(256) void start_bucket_kernel(
     const float *__restrict__ pdxd, const int32_t *__restrict__ slot_id, int32_t d,
-    const int32_t *__restrict__ goff, const int32_t *__restrict__ nearest, int64_t nq, int32_t parts,
+    const int32_t *__restrict__ goff, const int32_t *__restrict__ nearest, int64_t nq, int32_t parts, int32_t maxg,
     const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t k, int32_t chunk,
     unsigned long long *__restrict__ counters) {
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(256) void start_bucket_kernel(
         return;
     }
     const int32_t l = nearest[qi];
-    const int32_t a = goff[l], len = goff[l + 1] - a;
+    const int32_t a = goff[l], len = min(goff[l + 1] - a, maxg);
     const int32_t g0 = a + (int32_t)((int64_t)len * part / parts), g1 = a + (int32_t)((int64_t)len * (part + 1) / parts);
     scan_groups<false, L1>(pdxd, 0, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
 }
@@ -828,9 +829,13 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.qperm = c.take<float>(q * ix->d);
     pl.slots = pl.metric == PDX_METRIC_IP ? nullptr : c.take<uint64_t>(q * pl.nslots * k);
     if (pl.ivf) {
-        // waves per query in START: about 8 per SIMD in all, 1 .. 16
+        // START: the first start_rows rows (whole vectorgroups) of the
+        // nearest bucket; waves per query about 8 per SIMD in all, at most
+        // one per vectorgroup
+        const int32_t sr = (p && p->start_rows > 0) ? p->start_rows : 128;
+        pl.start_maxg = (int32_t)std::min<int64_t>(((int64_t)sr + kGroup - 1) / kGroup, ix->ngroups);
         int32_t sp = 1;
-        while (sp < 16 && (int64_t)sp * nq < 8 * 4 * (int64_t)device_cus()) sp <<= 1;
+        while (sp < 16 && sp < pl.start_maxg && (int64_t)sp * nq < 8 * 4 * (int64_t)device_cus()) sp <<= 1;
         pl.start_parts = sp;
         pl.qrot = ix->has_rot ? c.take<float>(q * ix->d) : nullptr;
         pl.cd = pl.mode == PDX_MODE_BOND ? c.take<float>(q * ix->nlist) : nullptr;
@@ -917,11 +922,11 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         const int64_t waves = pl.nq * pl.start_parts;
         if (l1)
             start_bucket_kernel<true><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
-                ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest, pl.nq, pl.start_parts, pl.perm, pl.qperm,
+                ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest, pl.nq, pl.start_parts, pl.start_maxg, pl.perm, pl.qperm,
                 pl.tau, pl.bad, pl.start_slots, pl.k, pl.chunk, pl.counters);
         else
             start_bucket_kernel<false><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
-                ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest, pl.nq, pl.start_parts, pl.perm, pl.qperm,
+                ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest, pl.nq, pl.start_parts, pl.start_maxg, pl.perm, pl.qperm,
                 pl.tau, pl.bad, pl.start_slots, pl.k, pl.chunk, pl.counters);
         merge_kernel<<<nqu, 64, 0, s>>>(pl.start_slots, pl.start_parts, 0, pl.start_parts, pl.k, pl.bad, pl.tau,
                                         nullptr, nullptr, nullptr, nullptr, 0);

@@ -165,6 +165,10 @@ pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, 
         set_error("pdx_search_exact: the inner product has no pruning bound; use PDX_MODE_LINEAR");
         return PDX_EUNSUPPORTED;
     }
+    if (params && params->start_rows < 0) {
+        set_error("pdx_search_exact: start_rows must be >= 0");
+        return PDX_EINVAL;
+    }
     if (params && (params->chunk < 0 || params->tile_groups < 0 ||
                    !(params->queries_per_block == 0 || params->queries_per_block == 1 ||
                      params->queries_per_block == 2 || params->queries_per_block == 4 ||

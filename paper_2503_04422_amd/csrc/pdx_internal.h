@@ -90,6 +90,7 @@ struct ExactPlan {
     bool use_tiles;        // LDS tile path (else the group path only)
     bool ivf;              // bucket layout (IVF index): rows in bucket order, ids through slot_id
     int32_t start_parts;   // bucket layout: waves per query in START
+    int32_t start_maxg;    // bucket layout: vectorgroups of the nearest bucket START scans
     int32_t metric;        // PDX_METRIC_*
     int32_t ip_parts;      // inner product: vectorgroup ranges (a multiple of 8)
     uint64_t *ip_slots;    // inner product: [nq][ip_parts][k] k-best lists

@@ -63,10 +63,11 @@ def test_bond_skewed_bucket_layout(pdx):
     ix = _bucket_index(pdx, x, 64, 1)
     wi, wd = exact.knn_exact_c(x, q, 10)
     ref = None
-    for kw in (dict(), dict(tile_groups=3, queries_per_block=1), dict(chunk=8, queries_per_block=8)):
+    for kw in (dict(), dict(tile_groups=3, queries_per_block=1), dict(chunk=8, queries_per_block=8),
+               dict(start_rows=1), dict(start_rows=1 << 20)):
         gi, gd = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10, mode="bond", **kw))
         check_knn(x, q, gi, gd, wi, wd)
-        if kw.get("chunk", 32) == 32:  # same summation order: bit-identical across schedules
+        if kw.get("chunk", 32) == 32:  # same summation order: bit-identical across schedules and START sizes
             if ref is None:
                 ref = (gi, gd)
             else:
