@@ -361,12 +361,13 @@ __global__ __launch_bounds__(64) void merge_kernel(const uint64_t *__restrict__ 
     }
 }
 
-// k-best of a query's candidate buffer (plus, for a query whose buffer
-// overflowed, the first k entries and the fallback slots).  Refresh mode:
+// k-best of a query's candidate buffer (for a query whose buffer
+// overflowed: its first `head` entries, which hold rows outside the main
+// range, and the fallback slots over the main range).  Refresh mode:
 // tighten the threshold; final mode: write the result.
 __global__ __launch_bounds__(64) void cand_merge_kernel(const uint64_t *__restrict__ cand,
                                                         const int32_t *__restrict__ cand_cnt, int32_t cap,
-                                                        int32_t k, const int32_t *__restrict__ bad,
+                                                        int32_t head, int32_t k, const int32_t *__restrict__ bad,
                                                         uint32_t *__restrict__ tau,
                                                         const uint64_t *__restrict__ slots, int32_t nslots,
                                                         int32_t slot_begin, int32_t slot_count,
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(64) void cand_merge_kernel(const uint64_t *__restri
     const int32_t cnt = cand_cnt[qi];
     const bool over = cnt > cap;
     const uint64_t *cb = cand + (size_t)qi * cap;
-    const int32_t nc = over && out_ids ? k : min(cnt, cap);
+    const int32_t nc = over && out_ids ? head : min(cnt, cap);
     uint64_t e = kEmptyKey, kth = kEmptyKey;
     for (int32_t i0 = 0; i0 < nc; i0 += kWave) {
         uint64_t key = (i0 + lane < nc) ? cb[i0 + lane] : kEmptyKey;
@@ -748,7 +749,7 @@ int32_t next_pow2(int32_t v) {
 }
 
 constexpr int32_t kCandCap = 2048;  // candidates per query in the tile path
-constexpr int32_t kRounds = 8;      // threshold refreshes in the tile path
+constexpr int32_t kRounds = 4;      // threshold refreshes in the tile path
 
 size_t tile_lds_bytes(int32_t d) { return (size_t)d * kTV * sizeof(float) + kQCap * sizeof(uint2); }
 
@@ -980,8 +981,8 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
                                                             cmain, nullptr, nullptr, nullptr);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         if (r + 1 < kRounds) {
-            cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, pl.k, pl.bad, pl.tau, nullptr, 0, 0,
-                                                 0, nullptr, nullptr);
+            cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, 0, pl.k, pl.bad, pl.tau, nullptr, 0,
+                                                 0, 0, nullptr, nullptr);
             if ((err = hipGetLastError()) != hipSuccess) return err;
         }
     }
@@ -993,8 +994,12 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
                                          pl.slots, pl.nslots, pl.tiles_start, pl.k, pl.chunk);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if ((err = mark(2)) != hipSuccess) return err;
-    cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, pl.k, pl.bad, pl.tau, pl.slots, pl.nslots,
-                                         pl.tiles_start, pl.tiles_main, out_ids, out_dist);
+    // an overflowed buffer's head: START's k best on the flat layout (rows
+    // before the main range); on the bucket layout START's rows lie inside
+    // the main range and the fallback finds them again, so nothing is kept
+    const int32_t head = pl.ivf ? 0 : pl.k;
+    cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, head, pl.k, pl.bad, pl.tau, pl.slots,
+                                         pl.nslots, pl.tiles_start, pl.tiles_main, out_ids, out_dist);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return mark(3);
 }
