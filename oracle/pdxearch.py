@@ -17,7 +17,8 @@ What is followed, in the paper's order:
 * Section 2.3 (exact bounds) and Section 5 (PDX-BOND): the bound is the
   partial distance itself; a vector is pruned when it is strictly higher
   than the threshold (the current k-th best exact distance).  Dimensions
-  are visited in decreasing order of |q_j - mean_j| (distance to means).
+  are visited in decreasing order of |q_j - mean_j| (distance to means),
+  or (dimension zones) zone by zone, zones ranked by that criterion.
 * Section 2.3 (ADSampling): on randomly rotated vectors, visited in their
   natural order, every delta_d dimensions the partial distance is tested
   against the threshold with the error bound eps0.  The paper describes
@@ -51,6 +52,24 @@ def bond_order(q: np.ndarray, mu32: np.ndarray) -> np.ndarray:
     in float32, the precision of the stored vectors and means."""
     key = np.abs(np.asarray(q, dtype=np.float32) - np.asarray(mu32, dtype=np.float32))
     return np.argsort(-key, kind="stable").astype(np.int64)
+
+
+def zone_order(q: np.ndarray, mu32: np.ndarray, zone: int = 32) -> np.ndarray:
+    """Dimension zones (Section 5, Figure "dz"): runs of `zone` consecutive
+    stored dimensions, ranked by the summed distance to means
+    sum_j |q_j - mean_j| of their dimensions, most promising first; inside a
+    zone the dimensions keep their storage order.  Readings (the paper fixes
+    neither): equal scores go by zone index ascending, and when D is not a
+    multiple of `zone` the shorter last zone is visited last, so that every
+    fetch of `zone` dimensions is one whole zone.  zone = 1 is the
+    distance-to-means order, zone = D the natural order."""
+    key = np.abs(np.asarray(q, dtype=np.float32) - np.asarray(mu32, dtype=np.float32)).astype(np.float64)
+    d = key.size
+    nz = d // zone
+    score = key[: nz * zone].reshape(nz, zone).sum(axis=1)
+    rank = np.argsort(-score, kind="stable")
+    full = (rank[:, None] * zone + np.arange(zone)[None, :]).reshape(-1)
+    return np.concatenate([full, np.arange(nz * zone, d)]).astype(np.int64)
 
 
 def ads_delta_d(d: int) -> int:
@@ -240,6 +259,23 @@ def ads_ivf_search(xrot: np.ndarray, lists: Sequence[np.ndarray], centroids: np.
     blocks = [np.asarray(lists[p], dtype=np.int64) for p in probe]
     return pdxearch(xrot, qrot, k, blocks, fixed_chunks(np.arange(d), dd),
                     make_ads_prunes(eps0), switch, stats)
+
+
+def bond_ivf_search(xrot: np.ndarray, lists: Sequence[np.ndarray], centroids: np.ndarray,
+                    qrot: np.ndarray, k: int, nprobe: int, mu32: np.ndarray, chunk: int = 32,
+                    zone: Optional[int] = None, switch: float = 0.2,
+                    stats: Optional[SearchStats] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """PDX-BOND inside IVF (Section 5 within Section 2.1's IVF): the probed
+    buckets nearest first (the first is START), dimensions in the query's
+    distance-to-means order (zone None) or in dimension zones of `zone`
+    dimensions, fetched `chunk` at a time, a vector dropped once its partial
+    distance exceeds the k-th best.  mu32: per-dimension means of the stored
+    rows.  Exact within the probed buckets."""
+    xrot = np.asarray(xrot)
+    probe = ivf_probe_order(centroids, qrot, nprobe)
+    blocks = [np.asarray(lists[p], dtype=np.int64) for p in probe]
+    order = bond_order(qrot, mu32) if zone is None else zone_order(qrot, mu32, zone)
+    return pdxearch(xrot, qrot, k, blocks, fixed_chunks(order, chunk), bond_prunes, switch, stats)
 
 
 def make_table_prunes(mult_row: np.ndarray, delta_d: int) -> Callable[[np.ndarray, float, int, int], np.ndarray]:

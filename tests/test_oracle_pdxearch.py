@@ -36,6 +36,69 @@ def test_hand_bond_orders():
         assert o.tolist() == c["order"]
 
 
+def test_hand_zone_orders():
+    """Dimension zones worked by hand: zone scores and visit order."""
+    for c in golden("hand_zones.json")["cases"]:
+        qv = np.array(c["query"], np.float32)
+        mu = np.array(c["means"], np.float32)
+        z = c["zone"]
+        nz = qv.size // z
+        assert [float(np.abs(qv[i * z:(i + 1) * z] - mu[i * z:(i + 1) * z]).sum()) for i in range(nz)] == c["scores"]
+        assert px.zone_order(qv, mu, z).tolist() == c["order"], c
+
+
+@pytest.mark.parametrize("d", [1, 5, 31, 32, 96, 100, 960])
+def test_zone_order_special_cases(d):
+    """zone = 1 is the distance-to-means order (PDX-BOND's), zone = D the
+    natural order; every order is a permutation made of whole zones in
+    storage order, full zones by non-increasing summed key, a partial zone
+    last."""
+    rng = np.random.default_rng(d)
+    qv = rng.standard_normal(d).astype(np.float32)
+    mu = rng.standard_normal(d).astype(np.float32)
+    qv[: d // 3] = mu[: d // 3]  # ties in the per-dimension key
+    assert np.array_equal(px.zone_order(qv, mu, 1), px.bond_order(qv, mu))
+    assert np.array_equal(px.zone_order(qv, mu, d), np.arange(d))
+    key = np.abs(qv - mu).astype(np.float64)
+    for z in (2, 7, 32):
+        o = px.zone_order(qv, mu, z)
+        assert np.array_equal(np.sort(o), np.arange(d))
+        nz = d // z
+        runs = o[: nz * z].reshape(nz, z)
+        assert np.all(runs % z == np.arange(z)) and np.all(np.diff(runs, axis=1) == 1)
+        sc = key[runs].sum(axis=1)
+        assert np.all(np.diff(sc) <= 0)
+        assert np.array_equal(o[nz * z:], np.arange(nz * z, d))
+
+
+@pytest.mark.parametrize("zone", [None, 1, 7, 32])
+def test_bond_ivf_search_equals_ivf_flat(zone):
+    """PDX-BOND inside IVF, per-dimension or zone order, is exact within
+    the probed buckets: integer inputs bit for bit, real inputs to 1e-12;
+    pruning happens."""
+    xi, qi = synth.integer_grid(2500, 64, 6, lo=-3, hi=3, seed=4)
+    init = np.random.default_rng(4).choice(2500, 12, replace=False)
+    c, lab, _ = kmeans.lloyd(xi, init, 3)
+    lists = kmeans.lists_from_labels(lab, 12)
+    mu = column_means_f32(xi)
+    for i in range(qi.shape[0]):
+        qq = qi[i].astype(np.float64)
+        for nprobe in (1, 4, 12):
+            fi, fd = px.ivf_flat(xi, lists, c, qq, 10, nprobe)
+            bi, bd = px.bond_ivf_search(xi, lists, c, qq, 10, nprobe, mu, zone=zone)
+            assert bi.tolist() == fi.tolist() and np.array_equal(bd, fd)
+    x, q, c, lists = _small_ivf(seed=3, d=96)
+    mu = column_means_f32(x)
+    for i in range(q.shape[0]):
+        qq = q[i].astype(np.float64)
+        fi, fd = px.ivf_flat(x, lists, c, qq, 10, 6)
+        st = px.SearchStats()
+        bi, bd = px.bond_ivf_search(x, lists, c, qq, 10, 6, mu, zone=zone, stats=st)
+        assert bi.tolist() == fi.tolist()
+        np.testing.assert_allclose(bd, fd, rtol=1e-12)
+        assert st.pruning_power > 0.1
+
+
 def test_hand_ads_thresholds():
     g = golden("hand_ads.json")
     prune = px.make_ads_prunes(g["eps0"])
