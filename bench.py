@@ -213,33 +213,38 @@ def bench_ivf(pdx, torch, np, x_dev, q_dev, nlist, nprobes, k, steps, warmup, tr
 
 def bench_bond_ivf(pdx, torch, np, ix, q_dev, nprobes, k, steps, warmup, truth_ids):
     """PDX-BOND as the bound inside IVF: every probed bucket scanned in the
-    query's BOND order with strict pruning (exact within the probed
-    buckets), on the same index and queries as the ADSampling sweep."""
+    query's BOND order, or zone by zone (dimension zones of 32 consecutive
+    dimensions), with strict pruning (exact within the probed buckets), on
+    the same index and queries as the ADSampling sweep."""
     from oracle.exact import recall_at_k
     nq = q_dev.shape[0]
-    rows = []
-    for p in nprobes:
-        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, p, bound="bond")), dtype=torch.uint8,
-                         device="cuda")
-        out = {}
+    out = {"bound": "PDX-BOND (exact within the probed buckets)"}
+    for bound, key in (("bond", "sweep"), ("zones", "zones")):
+        rows = []
+        for p in nprobes:
+            ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, p, bound=bound)), dtype=torch.uint8,
+                             device="cuda")
+            res = {}
 
-        def run(evs, p=p, ws=ws, out=out):
-            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, p, workspace=ws, phase_events=evs, bound="bond")
+            def run(evs, p=p, ws=ws, res=res, bound=bound):
+                res["r"] = pdx.pdx_search_ivf(ix, q_dev, k, p, workspace=ws, phase_events=evs, bound=bound)
 
-        elapsed, ph = timed_steps(run, steps, warmup, torch, np)
-        ids = out["r"][0].cpu().numpy()
-        rec = recall_at_k(truth_ids, ids[: truth_ids.shape[0]]) if truth_ids is not None else None
-        cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
-        pdx.pdx_search_ivf(ix, q_dev, k, p, counters=cnt, bound="bond")
-        c = [float(v) for v in cnt.cpu().tolist()]
-        rows.append({"nprobe": p, "qps": round(nq * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
-                     "recall@10": None if rec is None else round(rec, 4),
-                     "phases_ms": {"prep_start": round(ph[0], 3), "pruned_scan": round(ph[1], 3),
-                                   "merge": round(ph[2], 3)},
-                     "live_values": c[2], "computed_values": c[3]})
-        print(f"# bond-in-ivf nprobe {p}: {rows[-1]['qps']} qps recall {rows[-1]['recall@10']}", file=sys.stderr,
-              flush=True)
-    return {"bound": "PDX-BOND (exact within the probed buckets)", "sweep": rows}
+            elapsed, ph = timed_steps(run, steps, warmup, torch, np)
+            ids = res["r"][0].cpu().numpy()
+            rec = recall_at_k(truth_ids, ids[: truth_ids.shape[0]]) if truth_ids is not None else None
+            cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+            pdx.pdx_search_ivf(ix, q_dev, k, p, counters=cnt, bound=bound)
+            c = [float(v) for v in cnt.cpu().tolist()]
+            rows.append({"nprobe": p, "qps": round(nq * steps / elapsed, 1),
+                         "ms_per_step": round(1e3 * elapsed / steps, 3),
+                         "recall@10": None if rec is None else round(rec, 4),
+                         "phases_ms": {"prep_start": round(ph[0], 3), "pruned_scan": round(ph[1], 3),
+                                       "merge": round(ph[2], 3)},
+                         "live_values": c[2], "computed_values": c[3]})
+            print(f"# {bound}-in-ivf nprobe {p}: {rows[-1]['qps']} qps recall {rows[-1]['recall@10']}",
+                  file=sys.stderr, flush=True)
+        out[key] = rows
+    return out
 
 
 def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d):

@@ -278,7 +278,14 @@ typedef struct {
                                  the running k-th distance, so the result
                                  is exact within the probed buckets (eps0,
                                  engine and queries_per_wave are ignored;
-                                 f32 storage only)                          */
+                                 f32 storage only);
+                                 2: PDX-BOND with dimension zones (Section
+                                 5, Figure "dz"): zones of 32 consecutive
+                                 stored dimensions visited by
+                                 sum_j |q'_j - mean_j| descending (ties by
+                                 zone; a shorter last zone last), one zone
+                                 per 32-dimension fetch (delta_d ignored);
+                                 exact within the probed buckets as for 1 */
     /* Learned prune bound (see pdx_mlp_*; NULL = ADSampling's eps0).       */
     const void *prune_mlp;    /* network state: after START every (query,
                                  rank r >= 1) gets its own eps, the
@@ -301,8 +308,15 @@ typedef struct {
                                     START bucket, tau_k not positive and
                                     finite.  Targets hold for the exact
                                     result when the search is exact within
-                                    the probed buckets (eps0 = +INFINITY or
-                                    bound 1)                                 */
+                                    the probed buckets (eps0 = +INFINITY,
+                                    bound 1 or 2)                            */
+    int32_t zone_rows;        /* bound 2: once a vectorgroup has at most this
+                                 many surviving vectors, each survivor's
+                                 zone is read from the row-major f32 copy
+                                 (one 128-byte line) instead of 32
+                                 dimension rows of the group; 0 = 32,
+                                 < 0 = never.  Needs D % 4 == 0 (else never).
+                                 Does not change the result, bit for bit.  */
 } pdx_ivf_search_params;
 
 /* pdx_ivf_tune -- pick the fastest scan schedule for a workload.

@@ -35,7 +35,7 @@ def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 _MODES = {"linear": _lib.PDX_MODE_LINEAR, "bond": _lib.PDX_MODE_BOND}
-_BOUNDS = {"ads": 0, "bond": 1}
+_BOUNDS = {"ads": 0, "bond": 1, "zones": 2}
 _DTYPES = {"f32": _lib.PDX_DTYPE_F32, "bf16": _lib.PDX_DTYPE_BF16, "fp8": _lib.PDX_DTYPE_FP8}
 
 
@@ -258,9 +258,12 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                    queries_per_wave: int = 0, bucket_order: int = 0, engine: int = 0, bucket_split: int = 0,
                    bound: str = "ads", prune_mlp: Optional[MlpState] = None, prune_scale: float = 1.0,
                    prune_table: Optional[torch.Tensor] = None,
-                   prune_trace: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                   prune_trace: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, zone_rows: int = 0,
                    stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
-    """Approximate k nearest neighbours (IVF + ADSampling), optionally with the
+    """Approximate k nearest neighbours (IVF + ADSampling; bound "bond" or
+    "zones": PDX-BOND in per-dimension or dimension-zone order, exact within
+    the probed buckets, zone_rows the survivor count at or below which
+    zones are read from the row-major copy), optionally with the
     learned probe budget (mlp) or recording its training traces
     (trace = (features [nq, nprobe, 72] float32, need [nq] int32)), and
     with the learned prune bound (prune_mlp, prune_scale; prune_table
@@ -293,7 +296,7 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                                    _ptr(tf), _ptr(ti), int(queries_per_wave), int(bucket_order), int(engine),
                                    int(bucket_split), _BOUNDS[bound],
                                    None if prune_mlp is None else _ptr(prune_mlp.mem), float(prune_scale),
-                                   _ptr(prune_table), _ptr(pf), _ptr(pt))
+                                   _ptr(prune_table), _ptr(pf), _ptr(pt), int(zone_rows))
     ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
     need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))

@@ -38,11 +38,18 @@ constexpr int kTV = 32;       // vectors per LDS tile (half a vectorgroup)
 constexpr int kTW = 16;       // waves per workgroup
 constexpr int kQCap = 2048;   // survivor queue entries per tile in LDS
 constexpr int kGCap = 16384;  // further entries per workgroup in global memory
+constexpr int kZone = 32;     // dimensions per zone (one chunk)
+constexpr int32_t kModeZones = 2;  // prep_kernel: dimension-zone order
 
 // ---------------------------------------------------------------------------
 // Query preparation: visit order and permuted query values.
 // PDX-BOND (Section 5): dimensions by |q_j - mean_j| descending, ties by j.
 // Sort key (ascending): (~bits(|q_j - mean_j|) << 32) | j.
+// Dimension zones (Section 5, Figure "dz"; mode kModeZones): zones of kZone
+// consecutive stored dimensions by sum_j |q_j - mean_j| descending (float32,
+// j ascending), ties by zone; storage order inside a zone; when D is not a
+// multiple of kZone the shorter last zone comes last, so every chunk of
+// kZone visited dimensions is one whole zone.
 // perm[j] is the j-th visited dimension; qperm[j] the query value there;
 // poff[j] (optional, tile path: d kTV < 65536) its LDS tile row offset
 // perm[j] * kTV, half the size of perm in the tile kernel's registers.
@@ -75,18 +82,28 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
             if (pf) pf[j] = static_cast<uint16_t>(j * kTV);
         }
     } else {
-        for (int j = threadIdx.x; j < pow2; j += blockDim.x) {
+        const bool zones = mode == kModeZones;
+        const int32_t cnt = zones ? d / kZone : d;  // sort keys: zones or dimensions
+        int32_t p2 = 1;
+        while (p2 < cnt) p2 <<= 1;  // <= pow2
+        for (int j = threadIdx.x; j < p2; j += blockDim.x) {
             uint64_t key = kEmptyKey;
-            if (j < d) {
-                uint32_t kb = __float_as_uint(fabsf(qs[j] - means[j]));
-                key = (static_cast<uint64_t>(~kb) << 32) | static_cast<uint32_t>(j);
+            if (j < cnt) {
+                float sc;
+                if (zones) {
+                    sc = 0.0f;
+                    for (int u = 0; u < kZone; ++u) sc += fabsf(qs[j * kZone + u] - means[j * kZone + u]);
+                } else {
+                    sc = fabsf(qs[j] - means[j]);
+                }
+                key = (static_cast<uint64_t>(~__float_as_uint(sc)) << 32) | static_cast<uint32_t>(j);
             }
             keys[j] = key;
         }
         __syncthreads();
-        for (int k2 = 2; k2 <= pow2; k2 <<= 1) {
+        for (int k2 = 2; k2 <= p2; k2 <<= 1) {
             for (int j2 = k2 >> 1; j2 > 0; j2 >>= 1) {
-                for (int i = threadIdx.x; i < pow2; i += blockDim.x) {
+                for (int i = threadIdx.x; i < p2; i += blockDim.x) {
                     int ixj = i ^ j2;
                     if (ixj > i) {
                         uint64_t a = keys[i], b = keys[ixj];
@@ -101,7 +118,11 @@ __global__ __launch_bounds__(256) void prep_kernel(const float *__restrict__ q, 
             }
         }
         for (int j = threadIdx.x; j < d; j += blockDim.x) {
-            int32_t src = static_cast<int32_t>(keys[j] & 0xffffffffu);
+            int32_t src;
+            if (zones)
+                src = j < cnt * kZone ? static_cast<int32_t>(keys[j / kZone] & 0xffffffffu) * kZone + j % kZone : j;
+            else
+                src = static_cast<int32_t>(keys[j] & 0xffffffffu);
             po[j] = src;
             qp[j] = qs[src];
             if (pf) pf[j] = static_cast<uint16_t>(src * kTV);
@@ -142,15 +163,43 @@ __device__ __forceinline__ float chunk_sum(const float *__restrict__ gp, const i
     return lo + hi;
 }
 
+// One whole zone (kZone = 32 consecutive stored dimensions) of one row,
+// read from the row-major copy as one 128-byte line (xr 16-byte aligned),
+// summed exactly as chunk_sum<true, false> sums the same dimensions from
+// the vectorgroup rows: the first and second 16 separately, then added.
+__device__ __forceinline__ float zone_sum(const float *__restrict__ xr, const float *__restrict__ qp) {
+    float x[kZone];
+#pragma unroll
+    for (int u = 0; u < kZone / 4; ++u) {
+        const float4 v = reinterpret_cast<const float4 *>(xr)[u];
+        x[4 * u] = v.x;
+        x[4 * u + 1] = v.y;
+        x[4 * u + 2] = v.z;
+        x[4 * u + 3] = v.w;
+    }
+    float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lo = dist_term<false>(lo, qp[u] - x[u]);
+#pragma unroll
+    for (int u = 16; u < 32; ++u) hi = dist_term<false>(hi, qp[u] - x[u]);
+    return lo + hi;
+}
+
 // One wave scans groups [g0, g1) for query qi and writes its k-best list to
 // myslot.  PRUNE: drop lanes whose partial exceeds the threshold.
-template <bool PRUNE, bool L1 = false>
+// ZONES (dimension-zone order, chunk = kZone): after the first chunk, a
+// vectorgroup with at most zone_rows live lanes reads each live row's zone
+// from the row-major copy xrow ([n][d], by row id, d % 4 == 0) -- one line
+// per survivor instead of kZone dimension rows of the group.  Both reads
+// give the same bits.
+template <bool PRUNE, bool L1 = false, bool ZONES = false>
 __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int64_t n,
                                             const int32_t *__restrict__ slot_id, int32_t d, int32_t g0,
                                             int32_t g1, int64_t qi, const int32_t *__restrict__ perm,
                                             const float *__restrict__ qperm, uint32_t *__restrict__ tau,
                                             uint64_t *__restrict__ myslot, int32_t k, int32_t chunk,
-                                            unsigned long long *__restrict__ counters) {
+                                            unsigned long long *__restrict__ counters,
+                                            const float *__restrict__ xrow = nullptr, int32_t zone_rows = 0) {
     const int lane = threadIdx.x & 63;
     const int32_t *po = perm + qi * d;
     const float *qp = qperm + qi * d;
@@ -178,8 +227,11 @@ __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int6
                 lane_vals += 64ull * (c1 - c0);
             }
             float s = 0.0f;
-            if (alive)
+            if (ZONES && c0 > 0 && c1 - c0 == kZone && __popcll(__ballot(alive)) <= zone_rows) {
+                if (alive) s = zone_sum(xrow + (int64_t)rid * d + po[c0], qp + c0);
+            } else if (alive) {
                 s = (c1 - c0 == 32) ? chunk_sum<true, L1>(gp, po, qp, c0, c1) : chunk_sum<false, L1>(gp, po, qp, c0, c1);
+            }
             partial += s;
             if (PRUNE) alive = alive && !(partial > tau_eff);
         }
@@ -774,13 +826,13 @@ bool tile_path(const pdx_index *ix, const ExactPlan &pl) {
 // item's k-best list; PRUNE drops a vector once its partial distance
 // exceeds the threshold (exact within the probed buckets).  Items are
 // grouped by bucket; workgroup ids map to XCD-contiguous ranges of items.
-template <bool PRUNE>
+template <bool PRUNE, bool ZONES>
 __global__ __launch_bounds__(256) void bond_item_kernel(
     const float *__restrict__ pdxd, const int32_t *__restrict__ slot_id, int32_t d, const int32_t *__restrict__ goff,
     const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ probe, int32_t nprobe,
     const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, unsigned long long *__restrict__ counters,
-    uint32_t nwg) {
+    uint32_t nwg, const float *__restrict__ xrow, int32_t zone_rows) {
     const uint32_t per_xcd = gridDim.x >> 3;
     const uint32_t wg = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     const int lane = threadIdx.x & 63;
@@ -793,8 +845,8 @@ __global__ __launch_bounds__(256) void bond_item_kernel(
         return;
     }
     const int32_t l = probe[(int64_t)item.x * nprobe + item.y];
-    scan_groups<PRUNE>(pdxd, 0, slot_id, d, goff[l], goff[l + 1], item.x, perm, qperm, tau, myslot, slots.kk, chunk,
-                       counters);
+    scan_groups<PRUNE, false, ZONES>(pdxd, 0, slot_id, d, goff[l], goff[l + 1], item.x, perm, qperm, tau, myslot,
+                                     slots.kk, chunk, counters, xrow, zone_rows);
 }
 
 }  // namespace
@@ -1007,29 +1059,39 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
 // ---------------------------------------------------------------------------
 // PDX-BOND inside IVF (pdx_search_ivf with the BOND bound)
 // ---------------------------------------------------------------------------
-hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *means, int32_t *perm, float *qperm,
-                            uint32_t *tau, int32_t *bad, hipStream_t s) {
+hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *means, bool zones, int32_t *perm,
+                            float *qperm, uint32_t *tau, int32_t *bad, hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     const int32_t pow2 = next_pow2(d);
     const size_t lds = pow2 * sizeof(uint64_t) + d * sizeof(float);
-    prep_kernel<<<dim3((unsigned)nq), dim3(256), lds, s>>>(q, d, means, PDX_MODE_BOND, pow2, perm, qperm, tau, bad,
-                                                           nullptr);
+    prep_kernel<<<dim3((unsigned)nq), dim3(256), lds, s>>>(q, d, means, zones ? kModeZones : PDX_MODE_BOND, pow2,
+                                                           perm, qperm, tau, bad, nullptr);
     return hipGetLastError();
+}
+
+int32_t bond_zone_rows(int32_t d, int32_t requested) {
+    if (d % 4 != 0 || requested < 0) return 0;  // row-major zone reads need 16-byte aligned rows
+    return requested == 0 ? 32 : requested;
 }
 
 hipError_t launch_bond_items(bool prune, const pdx_index *ix, const int2 *items, int64_t nitems,
                              const int32_t *probe, int32_t nprobe, const int32_t *perm, const float *qperm,
                              uint32_t *tau, const int32_t *bad, SlotMap slots, int32_t chunk,
-                             unsigned long long *counters, hipStream_t s) {
+                             unsigned long long *counters, bool zones, int32_t zone_rows, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const uint32_t nwg = (uint32_t)((nitems + 3) / 4);
     const unsigned grid = 8u * ((nwg + 7u) / 8u);
-    if (prune)
-        bond_item_kernel<true><<<grid, 256, 0, s>>>(ix->pdx, ix->slot_id, ix->d, ix->list_goff, items, nitems, probe,
-                                                    nprobe, perm, qperm, tau, bad, slots, chunk, counters, nwg);
-    else
-        bond_item_kernel<false><<<grid, 256, 0, s>>>(ix->pdx, ix->slot_id, ix->d, ix->list_goff, items, nitems, probe,
-                                                     nprobe, perm, qperm, tau, bad, slots, chunk, counters, nwg);
+    const int32_t zr = zones ? zone_rows : 0;
+#define PDX_BOND_ITEMS(P, Z)                                                                                       \
+    bond_item_kernel<P, Z><<<grid, 256, 0, s>>>(ix->pdx, ix->slot_id, ix->d, ix->list_goff, items, nitems, probe, \
+                                                nprobe, perm, qperm, tau, bad, slots, chunk, counters, nwg, ix->xrow, zr)
+    if (prune) {
+        if (zones) PDX_BOND_ITEMS(true, true);
+        else PDX_BOND_ITEMS(true, false);
+    } else {
+        PDX_BOND_ITEMS(false, false);  // no pruning: every lane stays live, zones change only the order
+    }
+#undef PDX_BOND_ITEMS
     return hipGetLastError();
 }
 

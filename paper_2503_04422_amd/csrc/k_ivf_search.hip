@@ -775,7 +775,9 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         if (r == 0) r = min(4 * k, PDX_MAX_K);
         pl.rerank = r < 0 ? 0 : max(r, k);
     }
-    pl.bond = (p && p->bound == 1) ? 1 : 0;
+    pl.bond = (p && (p->bound == 1 || p->bound == 2)) ? 1 : 0;
+    pl.zones = (p && p->bound == 2) ? 1 : 0;
+    pl.zone_rows = pl.zones ? bond_zone_rows(ix->d, p->zone_rows) : 0;
     {
         int32_t eng = p ? p->engine : 0;
         if (eng == 0)  // automatic: matrix cores once buckets see enough queries to fill 16-row tiles
@@ -809,7 +811,7 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.cap0 = ivf_item_capacity(nq, 1, pl.qb0, ix->nlist);
     pl.cap1 = ivf_item_capacity(nq, nprobe - 1, pl.qb1, ix->nlist);
     int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
-    pl.chunk = dd;
+    pl.chunk = pl.zones ? 32 : dd;  // zones: every chunk is one whole zone
     size_t q = (size_t)(nq > 0 ? nq : 0);
     Carver c(ws);
     pl.qrot = c.take<float>(q * ix->d);
@@ -881,7 +883,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                                                          pl.probe, pl.bad, pl.tau);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // PDX-BOND: each query's dimension order by |q'_j - mean_j| (Section 5)
-    if (pl.bond && (e = launch_bond_prep(pl.qrot, nq, d, ix->means, pl.perm, pl.qperm, pl.tau, pl.bad, s)) != hipSuccess)
+    if (pl.bond && (e = launch_bond_prep(pl.qrot, nq, d, ix->means, pl.zones != 0, pl.perm, pl.qperm, pl.tau, pl.bad, s)) != hipSuccess)
         return e;
     // 3. work items grouped by bucket
     if ((e = launch_fill_i32(pl.cnt0, ix->nlist, 0, s)) != hipSuccess) return e;
@@ -919,7 +921,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         if (cap <= 0) return hipSuccess;
         if (pl.bond)
             return launch_bond_items(prune, ix, items, cap, pl.probe, pl.nprobe, pl.perm, pl.qperm, pl.tau, pl.bad,
-                                     sm, pl.chunk, cnt, s);
+                                     sm, pl.chunk, cnt, pl.zones != 0, pl.zone_rows, s);
         if (qb == 1) {
             const uint32_t nwg = (uint32_t)((cap + 3) / 4);
             const unsigned grid = 8u * ((nwg + 7u) / 8u);

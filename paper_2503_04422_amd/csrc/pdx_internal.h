@@ -205,6 +205,8 @@ struct IvfPlan {
     int32_t matrix;    // bucket scan on the matrix cores (16 queries per wave)
     int32_t qb0, qb1;  // queries per wave in the START / later bucket scans
     int32_t bond;      // PDX-BOND bound instead of ADSampling
+    int32_t zones;     // with bond: dimension-zone order (chunks of 32 = zones)
+    int32_t zone_rows; // with zones: row-major zone reads at or below this many survivors
     int32_t *perm;     // bond: [nq][d] visited dimension order
     float *qperm;      // bond: [nq][d] rotated query values in that order
     int32_t by_size;   // lay buckets out larger first
@@ -227,12 +229,17 @@ hipError_t launch_ip_merge(const uint64_t *slots, int64_t nq, int32_t parts, int
 int32_t ip_parts_for(int64_t nq, int32_t ngroups);
 
 // PDX-BOND inside IVF (k_exact.hip): query order and per-item bucket scans.
-hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *means, int32_t *perm, float *qperm,
-                            uint32_t *tau, int32_t *bad, hipStream_t s);
+// zones: the dimension-zone order (32 consecutive dimensions per zone)
+// instead of the per-dimension one
+hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *means, bool zones, int32_t *perm,
+                            float *qperm, uint32_t *tau, int32_t *bad, hipStream_t s);
+// survivors at or below which a vectorgroup reads zones from the row-major
+// copy (0: never); requested 0 = 32, < 0 = never
+int32_t bond_zone_rows(int32_t d, int32_t requested);
 hipError_t launch_bond_items(bool prune, const pdx_index *ix, const int2 *items, int64_t nitems,
                              const int32_t *probe, int32_t nprobe, const int32_t *perm, const float *qperm,
                              uint32_t *tau, const int32_t *bad, SlotMap slots, int32_t chunk,
-                             unsigned long long *counters, hipStream_t s);
+                             unsigned long long *counters, bool zones, int32_t zone_rows, hipStream_t s);
 
 // Bucket scan on the matrix cores (k_ivf_mscan.hip): batches of 16 * tiles
 // queries (tiles = 1 or 2) per wave.

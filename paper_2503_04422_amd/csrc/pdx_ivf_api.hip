@@ -315,11 +315,11 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
         set_error("pdx_search_ivf: bucket_split must be 0, 1, 2, 4 or 8 (got %d)", params->bucket_split);
         return PDX_EINVAL;
     }
-    if (params && (params->bound < 0 || params->bound > 1)) {
-        set_error("pdx_search_ivf: bound must be 0 (ADSampling) or 1 (PDX-BOND)");
+    if (params && (params->bound < 0 || params->bound > 2)) {
+        set_error("pdx_search_ivf: bound must be 0 (ADSampling), 1 (PDX-BOND) or 2 (PDX-BOND, dimension zones)");
         return PDX_EINVAL;
     }
-    if (params && params->bound == 1 && params->dtype != PDX_DTYPE_F32) {
+    if (params && params->bound != 0 && params->dtype != PDX_DTYPE_F32) {
         set_error("pdx_search_ivf: the PDX-BOND bound scans f32 storage only");
         return PDX_EUNSUPPORTED;
     }

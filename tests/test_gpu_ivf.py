@@ -273,12 +273,39 @@ def test_matrix_scan_split_is_invisible(pdx):
         pdx.pdx_search_ivf(ix, _dev(q), k, 4, engine=2, bucket_split=3)
 
 
+@pytest.mark.parametrize("bound", ["bond", "zones"])
+def test_bond_bound_integer_bit_exact(pdx, bound):
+    """Integer-valued rows and queries on an unrotated index: every partial
+    sum is exact, so PDX-BOND (either order) returns IVF-flat's ids and
+    distances bit for bit."""
+    n, d, nlist = 12_000, 96, 24
+    x, q = synth.integer_grid(n, d, 30, lo=-4, hi=4, seed=21)
+    q[3] = x[17]
+    c, lab, _ = kmeans.lloyd(x, np.random.default_rng(2).choice(n, nlist, replace=False), 3)
+    c32 = c.astype(np.float32)
+    lists = kmeans.lists_from_labels(lab, nlist)
+    ix = pdx.pdx_ivf_build(_dev(x), nlist, None, None, centroids=_dev(c32), assign=_dev(lab.astype(np.int32)))
+    xr = x.astype(np.float64)
+    for nprobe in (2, nlist):
+        print(f"bond integer bound={bound} nprobe={nprobe}", flush=True)
+        gi, gd = (_np(t) for t in pdx.pdx_search_ivf(ix, _dev(q), 10, nprobe, bound=bound))
+        keep = [i for i in range(q.shape[0]) if not _probe_tied(c32, q[i].astype(np.float64), nprobe)]
+        want = [px.ivf_flat(xr, lists, c32, q[i].astype(np.float64), 10, nprobe) for i in keep]
+        check_knn(xr, q[keep], gi[keep], gd[keep], np.stack([w[0] for w in want]), np.stack([w[1] for w in want]),
+                  exact=True)
+
+
+@pytest.mark.parametrize("bound", ["bond", "zones"])
 @pytest.mark.parametrize("n,d,nlist,k,rotated", [(20_000, 128, 50, 10, True), (9_000, 37, 16, 5, False),
-                                                 (6_000, 1536, 24, 10, True), (30_000, 96, 40, 64, False)])
-def test_bond_bound_exact_within_probed_buckets(pdx, n, d, nlist, k, rotated):
-    """PDX-BOND inside IVF: at every nprobe the result is the exact k-NN of
-    the probed buckets (the oracle's IVF-flat), with all buckets the exact
-    k-NN; rotated and unrotated indexes."""
+                                                 (6_000, 1536, 24, 10, True), (30_000, 96, 40, 64, False),
+                                                 (8_000, 100, 20, 10, False)])
+def test_bond_bound_exact_within_probed_buckets(pdx, n, d, nlist, k, rotated, bound):
+    """PDX-BOND inside IVF, per-dimension order or dimension zones: at every
+    nprobe the result is the exact k-NN of the probed buckets (the oracle's
+    IVF-flat), with all buckets the exact k-NN; rotated and unrotated
+    indexes, D a multiple of 32 or not (a partial last zone; D = 37: no
+    row-major zone reads).  Zones: the same bits whether survivors' zones
+    are read from the row-major copy or from the vectorgroup rows."""
     from paper_2503_04422_amd._lib import PdxError
     mix = synth.skewed_mixture(d, 16, 8.0, 4.0, n % 89)
     x = mix.data(n)
@@ -294,12 +321,17 @@ def test_bond_bound_exact_within_probed_buckets(pdx, n, d, nlist, k, rotated):
                            centroids=_dev(c.astype(np.float32)), assign=_dev(lab.astype(np.int32)))
     qr = rotation.rotate_rows(q, r32.astype(np.float64)) if rotated else q.astype(np.float64)
     for nprobe in (1, 3, nlist):
-        gi, gd = (_np(t) for t in pdx.pdx_search_ivf(ix, _dev(q), k, nprobe, bound="bond"))
+        print(f"  bound={bound} nprobe={nprobe}", flush=True)
+        gi, gd = (_np(t) for t in pdx.pdx_search_ivf(ix, _dev(q), k, nprobe, bound=bound))
         keep = [i for i in range(q.shape[0]) if not _probe_tied(c.astype(np.float32), qr[i], nprobe)]
         want = [px.ivf_flat(xr, lists, c.astype(np.float32), qr[i], k, nprobe) for i in keep]
         check_knn(xr, qr[keep], gi[keep], gd[keep], np.stack([w[0] for w in want]), np.stack([w[1] for w in want]))
         if nprobe == nlist:
             ei, ed = exact.knn_exact(xr, qr, k)
             check_knn(xr, qr, gi, gd, ei, ed)
+        if bound == "zones":
+            for zr in (-1, 1, 64):
+                zi, zd = (_np(t) for t in pdx.pdx_search_ivf(ix, _dev(q), k, nprobe, bound=bound, zone_rows=zr))
+                assert np.array_equal(zi, gi) and np.array_equal(zd, gd), zr
     with pytest.raises(PdxError):
-        pdx.pdx_search_ivf(ix, _dev(q), k, 2, bound="bond", dtype="bf16")
+        pdx.pdx_search_ivf(ix, _dev(q), k, 2, bound=bound, dtype="bf16")
