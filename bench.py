@@ -493,6 +493,95 @@ def bench_lowp(pdx, torch, np, x_np, q_np, x_dev, q_dev, k, steps, warmup, truth
             "bytes_per_vector": {"f32": 4 * d, "bf16": 2 * d, "fp8": d}, "recall_queries": s_n, "by_dtype": res}
 
 
+def kernel_sweep(ns, ds, reps_s=4e-3) -> dict:
+    """The kernel study of Section 6.4 on the GPU: one query against a whole
+    collection of N(0, 1) float32 vectors, no search; the row-major (N-ary,
+    one vector per lane) kernel against the PDX kernel with blocks of 64 for
+    L2, L1 and the inner product (Table "kernels"), and the L2 PDX kernel
+    with blocks of 16 .. 512 (Table "block").  Time per launch: the launches
+    are captured back to back in a HIP graph (so host overhead does not
+    hide small kernels), which is replayed once to warm up and once between
+    HIP events; the replayed output is checked against the eager one."""
+    import numpy as np
+    import torch
+
+    import paper_2503_04422_amd as pdx
+    import synth
+    stream = torch.cuda.current_stream()
+
+    def per_launch(fn, nbytes, out):
+        est = nbytes / 5e12 + 2e-6
+        reps = int(min(400, max(10, reps_s / est)))
+        fn()
+        torch.cuda.synchronize()
+        eager = out.clone()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(reps):
+                fn()
+        out.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        if not torch.equal(out, eager):
+            raise RuntimeError("kernel sweep: replayed output differs from the eager launch")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        graph.replay()
+        e1.record(stream)
+        e1.synchronize()
+        del graph
+        return e0.elapsed_time(e1) * 1e3 / reps  # microseconds
+
+    points = []
+    for d in ds:
+        xa, qa = synth.standard_normal(max(ns), d, 1)
+        xfull, q = torch.from_numpy(xa).cuda(), torch.from_numpy(qa).cuda()
+        del xa
+        for n in ns:
+            x = xfull[:n]
+            out = torch.empty((1, n), dtype=torch.float32, device="cuda")
+            nbytes = 4.0 * n * d
+            pt = {"n": n, "d": d, "us": {}}
+            blocks = {b: pdx.pdx_layout_blocks(x, b) for b in synth.KERNEL_STUDY_BLOCKS}
+            for metric in ("l2", "l1", "ip"):
+                pt["us"][f"nary_{metric}"] = per_launch(
+                    lambda: pdx.pdx_distances(x, q, layout="nary", metric=metric, out=out), nbytes, out)
+                pt["us"][f"pdx64_{metric}"] = per_launch(
+                    lambda: pdx.pdx_distances(blocks[64], q, n=n, layout="pdx", metric=metric, out=out), nbytes,
+                    out)
+            for b in synth.KERNEL_STUDY_BLOCKS:
+                if b != 64:
+                    pt["us"][f"pdx{b}_l2"] = per_launch(
+                        lambda: pdx.pdx_distances(blocks[b], q, n=n, layout="pdx", metric="l2", out=out), nbytes,
+                        out)
+            pt["us"] = {k2: round(v, 3) for k2, v in pt["us"].items()}
+            pt["pdx64_l2_GBps"] = round(nbytes / (pt["us"]["pdx64_l2"] * 1e-6) / 1e9, 1)
+            points.append(pt)
+            print(f"# sweep n={n} d={d}: {pt['us']}", file=sys.stderr, flush=True)
+            del blocks, out
+        del xfull
+        torch.cuda.empty_cache()
+
+    def mean_speedup(sel, num, den):
+        v = [p["us"][num] / p["us"][den] for p in points if sel(p["d"])]
+        return round(float(np.exp(np.mean(np.log(v)))), 3) if v else None
+
+    groups = {"d=8": lambda d: d == 8, "8<d<=32": lambda d: 8 < d <= 32, "d>32": lambda d: d > 32,
+              "all": lambda d: True}
+    table_kernels = {m: {g: mean_speedup(f, f"nary_{m}", f"pdx64_{m}") for g, f in groups.items()}
+                     for m in ("l2", "l1", "ip")}
+    table_block = {b: mean_speedup(lambda d: True, "nary_l2", f"pdx{b}_l2") for b in synth.KERNEL_STUDY_BLOCKS}
+    big = max(points, key=lambda p: p["n"] * p["d"])
+    return {"kernel_sweep": {
+        "what": "one query vs n N(0,1) float32 vectors, distances only; speedup = N-ary time / PDX time "
+                "(geometric mean over the grid points of each group)",
+        "n": list(ns), "d": list(ds), "speedup_pdx64_vs_nary": table_kernels, "speedup_l2_by_block": table_block,
+        "largest": {"n": big["n"], "d": big["d"], "pdx64_l2_us": big["us"]["pdx64_l2"],
+                    "nary_l2_us": big["us"]["nary_l2"], "pdx64_l2_GBps": big["pdx64_l2_GBps"],
+                    "hbm_peak_GBps": HBM_PEAK_GBS},
+        "points": points}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -520,7 +609,17 @@ def main() -> int:
                                        "instead of the autotuner")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (calibrates HBM byte counters)")
+    ap.add_argument("--kernel-sweep", action="store_true",
+                    help="only run the distance-kernel study (PDX vs row-major, block sizes) over the N, D grid")
+    ap.add_argument("--sweep-n", type=int, nargs="*", default=None, help="kernel sweep: collection sizes")
+    ap.add_argument("--sweep-d", type=int, nargs="*", default=None, help="kernel sweep: dimensionalities")
     args = ap.parse_args()
+
+    if args.kernel_sweep:
+        import synth
+        res = kernel_sweep(args.sweep_n or synth.KERNEL_STUDY_N, args.sweep_d or synth.KERNEL_STUDY_D)
+        print(json.dumps(res), flush=True)
+        return 0
 
     if args.copy_probe:
         import torch

@@ -438,6 +438,43 @@ PDX_API pdx_status pdx_mlp_train_step(void *mlp, const float *x, const float *y,
 PDX_API pdx_status pdx_mlp_export(const void *mlp, float *theta, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Distance kernels without a search (the kernel study of Section 6.4,
+ * Tables "kernels" and "block"; the kernels of Section 3's listing)
+ * ------------------------------------------------------------------ */
+
+typedef enum {
+    PDX_LAYOUT_NARY = 0, /* row-major [n][d] ("horizontal"), one vector per lane */
+    PDX_LAYOUT_PDX = 1   /* PDX blocks of `block` vectors (pdx_layout_blocks)  */
+} pdx_layout;
+
+/* Bytes of the PDX block layout of n x d float32 rows with blocks of
+ * `block` vectors: ceil(n / block) * block * d * 4; 0 for bad arguments. */
+PDX_API size_t pdx_layout_blocks_bytes(int64_t n, int32_t d, int32_t block);
+
+/* pdx_layout_blocks -- Section 3: the rows x [n][d] (device, float32,
+ * row-major) cut into blocks of `block` vectors; inside a block, dimension
+ * j of the block's v-th vector sits at offset j * block + v, i.e. out is
+ * [ceil(n / block)][d][block], the last block's missing vectors zero.
+ * block: 16, 32, 64, 128, 256 or 512.  out: device, caller-owned,
+ * pdx_layout_blocks_bytes bytes.  Asynchronous on `stream`.  PDX_EINVAL for
+ * bad sizes, a bad block or null pointers. */
+PDX_API pdx_status pdx_layout_blocks(const float *x, int64_t n, int32_t d, int32_t block, float *out, void *stream);
+
+/* pdx_distances -- the L2 (squared), L1 or inner-product (reported as
+ * -q.v) score of every vector for each query, no search: out[i][v] for
+ * query i and vector v, [nq][n] float32 (device, caller-owned).
+ * data: PDX_LAYOUT_NARY, the rows [n][d] (16-byte aligned when d % 4 == 0);
+ * PDX_LAYOUT_PDX, the output of pdx_layout_blocks with the same block.
+ * q: [nq][d] row-major, 0 <= nq <= 65535.  Both layouts sum a vector's
+ * terms in one fixed order (32-dimension chunks, sequential inside a chunk,
+ * chunk sums added in order), so they return the same bits.  Non-finite
+ * inputs give non-finite scores.  Asynchronous on `stream`.  PDX_EINVAL for
+ * bad sizes, an unknown layout or metric, a bad block, null pointers or
+ * misaligned row-major data; nq = 0 is a no-op. */
+PDX_API pdx_status pdx_distances(const float *data, int32_t layout, int32_t block, int64_t n, int32_t d,
+                                 const float *q, int64_t nq, int32_t metric, float *out, void *stream);
+
+/* ---------------------------------------------------------------------
  * Handles and diagnostics
  * ------------------------------------------------------------------ */
 

@@ -9,9 +9,11 @@ from .api import (  # noqa: F401
     PdxIndex,
     ivf_test_points,
     pdx_build,
+    pdx_distances,
     pdx_ivf_build,
     pdx_ivf_export,
     pdx_ivf_tune,
+    pdx_layout_blocks,
     pdx_search_exact,
     pdx_search_exact_workspace,
     pdx_search_ivf,

@@ -30,6 +30,9 @@ PDX_METRIC_L2 = 0
 PDX_METRIC_L1 = 1
 PDX_METRIC_IP = 2
 
+PDX_LAYOUT_NARY = 0
+PDX_LAYOUT_PDX = 1
+
 PDX_DTYPE_F32 = 0
 PDX_DTYPE_BF16 = 1
 PDX_DTYPE_FP8 = 2
@@ -114,6 +117,10 @@ SIGNATURES = {
     "pdx_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, ctypes.c_float,
                                      ctypes.c_float, c_int64, c_void_p, c_size_t, c_void_p, c_void_p]),
     "pdx_free": (None, [c_void_p]),
+    "pdx_layout_blocks_bytes": (c_size_t, [c_int64, c_int32, c_int32]),
+    "pdx_layout_blocks": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p]),
+    "pdx_distances": (c_int32, [c_void_p, c_int32, c_int32, c_int64, c_int32, c_void_p, c_int64, c_int32,
+                                c_void_p, c_void_p]),
     "pdx_last_error": (ctypes.c_char_p, []),
     "pdx_version": (ctypes.c_char_p, []),
 }

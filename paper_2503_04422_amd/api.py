@@ -333,5 +333,57 @@ def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: fl
     return sched, rows
 
 
+def pdx_layout_blocks(x: torch.Tensor, block: int = 64,
+                      stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Rows [n, d] -> PDX blocks [ceil(n / block), d, block] (Section 3),
+    the last block zero-padded."""
+    x = _dev_f32(x, "x")
+    n, d = x.shape
+    nbytes = lib.pdx_layout_blocks_bytes(n, d, int(block))
+    if nbytes == 0:
+        raise ValueError("pdx_layout_blocks: need n, d >= 1 and block in 16, 32, 64, 128, 256, 512")
+    out = torch.empty(((n + block - 1) // block, d, block), dtype=torch.float32, device=x.device)
+    check(lib.pdx_layout_blocks(_ptr(x), n, d, int(block), _ptr(out), _stream(stream)), "pdx_layout_blocks")
+    return out
+
+
+def pdx_distances(data: torch.Tensor, q: torch.Tensor, n: Optional[int] = None, layout: str = "pdx",
+                  metric: str = "l2", stream: Optional[torch.cuda.Stream] = None,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Scores of every vector for each query, no search: [nq, n] float32.
+    layout "nary": data = rows [n, d]; layout "pdx": data = the blocks of
+    pdx_layout_blocks [nblocks, d, block] (block read from the shape) and n
+    the number of real vectors (default: every slot)."""
+    q = _dev_f32(q, "q")
+    if not isinstance(data, torch.Tensor) or not data.is_cuda or data.dtype != torch.float32:
+        raise TypeError("data must be a float32 GPU tensor")
+    data = data.contiguous()
+    if layout == "nary":
+        if data.dim() != 2:
+            raise TypeError("row-major data must be [n, d]")
+        nn, d = data.shape
+        block = 0
+    elif layout == "pdx":
+        if data.dim() != 3:
+            raise TypeError("PDX data must be [nblocks, d, block]")
+        nb, d, block = data.shape
+        nn = nb * block if n is None else int(n)
+        if not (nb - 1) * block < nn <= nb * block:
+            raise ValueError("n does not match the number of blocks")
+    else:
+        raise ValueError(f"unknown layout {layout!r}")
+    if q.shape[1] != d:
+        raise ValueError("query dimension does not match the data")
+    nq = q.shape[0]
+    if out is None:
+        out = torch.empty((nq, nn), dtype=torch.float32, device=q.device)
+    elif out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != nq * nn:
+        raise TypeError("out must be contiguous float32 [nq, n]")
+    lay = _lib.PDX_LAYOUT_NARY if layout == "nary" else _lib.PDX_LAYOUT_PDX
+    check(lib.pdx_distances(_ptr(data), lay, int(block), nn, d, _ptr(q), nq, _METRICS[metric], _ptr(out),
+                            _stream(stream)), "pdx_distances")
+    return out
+
+
 def pdx_version() -> str:
     return lib.pdx_version().decode()

@@ -87,7 +87,7 @@ pdx_status pdx_ivf_tune(const pdx_index *index, const float *q, int64_t nq, int3
         return PDX_EHIP;
     }
     if (hipEventCreate(&ev[1]) != hipSuccess) {
-        hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[0]);  // best effort on the error path
         pdx::set_error("pdx_ivf_tune: hipEventCreate failed");
         return PDX_EHIP;
     }
@@ -119,8 +119,8 @@ pdx_status pdx_ivf_tune(const pdx_index *index, const float *q, int64_t nq, int3
         }
         if (table) table[ci] = pdx_ivf_schedule{c.engine, c.qpw, c.order, c.delta_d ? c.delta_d : params->delta_d, ms};
     }
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
+    if (hipEventDestroy(ev[0]) != hipSuccess) event_failed = true;
+    if (hipEventDestroy(ev[1]) != hipSuccess) event_failed = true;
     if (event_failed) pdx::set_error("pdx_ivf_tune: a HIP event call failed");
     if (st != PDX_OK) return st;
     const Candidate &c = kCandidates[best];

@@ -11,6 +11,10 @@ from .gen import (  # noqa: F401
     skewed_mixture,
     anisotropic_unit_mixture,
     integer_grid,
+    standard_normal,
+    KERNEL_STUDY_N,
+    KERNEL_STUDY_D,
+    KERNEL_STUDY_BLOCKS,
     workload,
     WORKLOADS,
 )

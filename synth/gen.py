@@ -148,6 +148,22 @@ def integer_grid(n: int, d: int, nq: int, lo: int = -8, hi: int = 8,
     return x, q
 
 
+def standard_normal(n: int, d: int, nq: int, seed: int = 11) -> Tuple[np.ndarray, np.ndarray]:
+    """The kernel study's collections (Section 6.4): n vectors and nq
+    queries of d independent N(0, 1) float32 values."""
+    rng = _rng(seed, 101, d)
+    x = rng.standard_normal((n, d), dtype=np.float32)
+    q = rng.standard_normal((nq, d), dtype=np.float32)
+    return x, q
+
+
+# the kernel study's grid (Section 6.4): collection sizes 64 .. 131,072 and
+# these dimensionalities
+KERNEL_STUDY_N = (64, 1024, 16384, 131072)
+KERNEL_STUDY_D = (8, 16, 32, 64, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 4096, 8192)
+KERNEL_STUDY_BLOCKS = (16, 32, 64, 128, 256, 512)
+
+
 # name -> (mixture factory, full n, full nq, query seed)
 WORKLOADS = {
     # exact linear scan: 10,000 x 128, 100 queries

@@ -56,3 +56,36 @@ def test_network_loss_arguments_checked_on_the_host():
         assert lib.pdx_mlp_train_step(fake, fake, fake, 4, kind, w, 1e-3, 1, fake, 1 << 30, None,
                                       None) == _lib.PDX_EINVAL
     assert b"loss" in lib.pdx_last_error()
+
+
+def test_distance_kernel_arguments_checked_on_the_host():
+    """pdx_layout_blocks / pdx_distances: sizes, block, layout, metric and
+    null pointers are rejected before any GPU call; nq = 0 is a no-op."""
+    from paper_2503_04422_amd import _lib
+    lib = _lib.lib
+    assert lib.pdx_layout_blocks_bytes(100, 8, 64) == 2 * 64 * 8 * 4
+    assert lib.pdx_layout_blocks_bytes(64, 3, 16) == 64 * 3 * 4
+    assert lib.pdx_layout_blocks_bytes(1, 1, 512) == 512 * 4
+    for n, d, b in ((0, 8, 64), (10, 0, 64), (10, 8, 48), (10, 8, 1024), (10, 8, 0)):
+        assert lib.pdx_layout_blocks_bytes(n, d, b) == 0
+    assert lib.pdx_layout_blocks(None, 10, 8, 48, None, None) == _lib.PDX_EINVAL
+    assert b"block" in lib.pdx_last_error()
+    assert lib.pdx_layout_blocks(None, 10, 8, 64, None, None) == _lib.PDX_EINVAL
+    assert b"null" in lib.pdx_last_error()
+    D = lib.pdx_distances
+    P, N = _lib.PDX_LAYOUT_PDX, _lib.PDX_LAYOUT_NARY
+    assert D(None, P, 64, 10, 8, None, 0, _lib.PDX_METRIC_L2, None, None) == _lib.PDX_OK
+    assert D(None, P, 64, 10, 8, None, 1, _lib.PDX_METRIC_L2, None, None) == _lib.PDX_EINVAL
+    assert b"null" in lib.pdx_last_error()
+    assert D(None, 7, 64, 10, 8, None, 1, _lib.PDX_METRIC_L2, None, None) == _lib.PDX_EINVAL
+    assert b"layout" in lib.pdx_last_error()
+    assert D(None, P, 100, 10, 8, None, 1, _lib.PDX_METRIC_L2, None, None) == _lib.PDX_EINVAL
+    assert b"block" in lib.pdx_last_error()
+    assert D(None, N, 0, 10, 8, None, 1, 9, None, None) == _lib.PDX_EINVAL
+    assert b"metric" in lib.pdx_last_error()
+    for n, d, nq in ((0, 8, 1), (10, 0, 1), (10, 8, -1), (10, 8, 65536)):
+        assert D(None, N, 0, n, d, None, nq, _lib.PDX_METRIC_L2, None, None) == _lib.PDX_EINVAL
+    # misaligned row-major data (checked before any launch)
+    assert D(ctypes.c_void_p(0x1004), N, 0, 10, 8, ctypes.c_void_p(0x2000), 1, _lib.PDX_METRIC_L2,
+             ctypes.c_void_p(0x3000), None) == _lib.PDX_EINVAL
+    assert b"aligned" in lib.pdx_last_error()
