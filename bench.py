@@ -572,13 +572,15 @@ def kernel_sweep(ns, ds, reps_s=4e-3) -> dict:
                      for m in ("l2", "l1", "ip")}
     table_block = {b: mean_speedup(lambda d: True, "nary_l2", f"pdx{b}_l2") for b in synth.KERNEL_STUDY_BLOCKS}
     big = max(points, key=lambda p: p["n"] * p["d"])
+    traffic, src = profiled_traffic("dist_kernels_n131072_d8192.md") if (big["n"], big["d"]) == (131072, 8192) \
+        else (None, "not profiled for this size")
     return {"kernel_sweep": {
         "what": "one query vs n N(0,1) float32 vectors, distances only; speedup = N-ary time / PDX time "
                 "(geometric mean over the grid points of each group)",
         "n": list(ns), "d": list(ds), "speedup_pdx64_vs_nary": table_kernels, "speedup_l2_by_block": table_block,
         "largest": {"n": big["n"], "d": big["d"], "pdx64_l2_us": big["us"]["pdx64_l2"],
                     "nary_l2_us": big["us"]["nary_l2"], "pdx64_l2_GBps": big["pdx64_l2_GBps"],
-                    "hbm_peak_GBps": HBM_PEAK_GBS},
+                    "hbm_peak_GBps": HBM_PEAK_GBS, "pdx64_l2_traffic_bytes": traffic, "traffic_source": src},
         "points": points}}
 
 
