@@ -3,9 +3,11 @@
 // merge.
 //
 // Every vector's distance to a query is accumulated in one fixed order:
-// chunk by chunk in the query's visit order, each chunk as (fused
-// multiply-adds over its first 16 dimensions) + (over the rest), then added
-// to the running partial.  Whichever kernel, wave or launch evaluates a
+// chunk by chunk in the query's visit order, each chunk of 32 dimensions as
+// four octets (fused multiply-adds over 8 consecutive visited dimensions
+// from zero) combined as (o0 + o1) + (o2 + o3), a chunk of any other
+// length as (its first 16 dimensions) + (the rest), then added to the
+// running partial.  Whichever kernel, wave or launch evaluates a
 // (query, vector) pair therefore produces the same float32 value, and the
 // partial after any chunk is a lower bound of the full distance (sums of
 // non-negative terms are monotone under round-to-nearest).
@@ -21,7 +23,7 @@
 //  * tile_kernel ("tile" path): a workgroup stages 32 vectors x all D
 //    dimensions in LDS once and scans them for every query of the batch, so
 //    HBM is read once per batch instead of once per query.  The first chunk
-//    is scanned densely (lanes = 32 vectors x 2 half-chunks); the few
+//    is scanned densely (lanes = 16 vector pairs x 4 octets); the few
 //    survivors go to an LDS queue and are finished by "persistent" lanes,
 //    each lane carrying one (query, vector) pair chunk by chunk and taking a
 //    new pair from the queue when its pair is pruned or complete.  Completed
@@ -141,32 +143,38 @@ __device__ __forceinline__ float dist_term(float acc, float t) {
     return L1 ? acc + fabsf(t) : fmaf(t, t, acc);
 }
 
-// Chunk [c0, c1) of the visit order for one lane's vector: the first 16
-// dimensions and the rest are summed separately, then added.
+// Four octet sums of a 32-dimension chunk combined in the fixed order.
+__device__ __forceinline__ float octets(float o0, float o1, float o2, float o3) { return (o0 + o1) + (o2 + o3); }
+
+// Chunk [c0, c1) of the visit order for one lane's vector: a full chunk of
+// 32 as four octets, any other length as (first 16) + (rest).
 template <bool FULL32, bool L1>
 __device__ __forceinline__ float chunk_sum(const float *__restrict__ gp, const int32_t *__restrict__ po,
                                            const float *__restrict__ qp, int32_t c0, int32_t c1) {
-    float lo = 0.0f, hi = 0.0f;
     if (FULL32) {
         float x[32];
 #pragma unroll
         for (int u = 0; u < 32; ++u) x[u] = gp[po[c0 + u] * kGroup];
+        float o[4];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) lo = dist_term<L1>(lo, qp[c0 + u] - x[u]);
+        for (int g = 0; g < 4; ++g) {
+            o[g] = 0.0f;
 #pragma unroll
-        for (int u = 16; u < 32; ++u) hi = dist_term<L1>(hi, qp[c0 + u] - x[u]);
-    } else {
-        const int32_t mid = min(c0 + 16, c1);
-        for (int32_t j = c0; j < mid; ++j) lo = dist_term<L1>(lo, qp[j] - gp[po[j] * kGroup]);
-        for (int32_t j = mid; j < c1; ++j) hi = dist_term<L1>(hi, qp[j] - gp[po[j] * kGroup]);
+            for (int u = 8 * g; u < 8 * g + 8; ++u) o[g] = dist_term<L1>(o[g], qp[c0 + u] - x[u]);
+        }
+        return octets(o[0], o[1], o[2], o[3]);
     }
+    float lo = 0.0f, hi = 0.0f;
+    const int32_t mid = min(c0 + 16, c1);
+    for (int32_t j = c0; j < mid; ++j) lo = dist_term<L1>(lo, qp[j] - gp[po[j] * kGroup]);
+    for (int32_t j = mid; j < c1; ++j) hi = dist_term<L1>(hi, qp[j] - gp[po[j] * kGroup]);
     return lo + hi;
 }
 
 // One whole zone (kZone = 32 consecutive stored dimensions) of one row,
 // read from the row-major copy as one 128-byte line (xr 16-byte aligned),
 // summed exactly as chunk_sum<true, false> sums the same dimensions from
-// the vectorgroup rows: the first and second 16 separately, then added.
+// the vectorgroup rows (four octets).
 __device__ __forceinline__ float zone_sum(const float *__restrict__ xr, const float *__restrict__ qp) {
     float x[kZone];
 #pragma unroll
@@ -177,12 +185,14 @@ __device__ __forceinline__ float zone_sum(const float *__restrict__ xr, const fl
         x[4 * u + 2] = v.z;
         x[4 * u + 3] = v.w;
     }
-    float lo = 0.0f, hi = 0.0f;
+    float o[4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) lo = dist_term<false>(lo, qp[u] - x[u]);
+    for (int g = 0; g < 4; ++g) {
+        o[g] = 0.0f;
 #pragma unroll
-    for (int u = 16; u < 32; ++u) hi = dist_term<false>(hi, qp[u] - x[u]);
-    return lo + hi;
+        for (int u = 8 * g; u < 8 * g + 8; ++u) o[g] = dist_term<false>(o[g], qp[u] - x[u]);
+    }
+    return octets(o[0], o[1], o[2], o[3]);
 }
 
 // One wave scans groups [g0, g1) for query qi and writes its k-best list to
@@ -496,14 +506,14 @@ __device__ __forceinline__ void unpack_off(uint32_t w0, uint32_t w1, int (&o)[4]
     o[3] = (int)(w1 >> 16);
 }
 
-// Full chunk of 32 visited dimensions for vector v of the LDS tile: 16 + 16
-// fused multiply-adds, per-lane query (pf: the chunk's 16-bit row offsets,
-// qp: its query values; loaded 16 bytes at a time).
+// Full chunk of 32 visited dimensions for vector v of the LDS tile, four
+// octets of fused multiply-adds (pf: the chunk's 16-bit row offsets, qp:
+// its query values; loaded 16 bytes at a time).
 __device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, const uint16_t *__restrict__ pf,
                                             const float *__restrict__ qp, int v) {
     const uint4 *o4 = reinterpret_cast<const uint4 *>(pf);
     const float4 *q4 = reinterpret_cast<const float4 *>(qp);
-    float lo = 0.0f, hi = 0.0f;
+    float oc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const uint4 ow = o4[u >> 1];
@@ -514,32 +524,70 @@ __device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, cons
         float t1 = qq.y - tile[o[1] + v];
         float t2 = qq.z - tile[o[2] + v];
         float t3 = qq.w - tile[o[3] + v];
-        float &s = u < 4 ? lo : hi;
+        float &s = oc[u >> 1];
         s = fmaf(t0, t0, s);
         s = fmaf(t1, t1, s);
         s = fmaf(t2, t2, s);
         s = fmaf(t3, t3, s);
     }
-    return lo + hi;
+    return octets(oc[0], oc[1], oc[2], oc[3]);
 }
 
-// One query's first visited chunk as this lane's half sees it: 16
-// dimensions (16-bit LDS row offsets, query values), the threshold and
-// the non-finite flag.
+// One octet (8 visited dimensions) of a chunk for the tile's vectors p and
+// p + 16: each dimension's LDS row address serves both (one paired read).
+__device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4 ow, float4 q0, float4 q1, int p,
+                                           float &a, float &b) {
+    int o[8];
+    unpack_off(ow.x, ow.y, *reinterpret_cast<int(*)[4]>(o));
+    unpack_off(ow.z, ow.w, *reinterpret_cast<int(*)[4]>(o + 4));
+    const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    a = 0.0f;
+    b = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float *r = tile + o[u] + p;
+        const float ta = qv[u] - r[0];
+        const float tb = qv[u] - r[16];
+        a = fmaf(ta, ta, a);
+        b = fmaf(tb, tb, b);
+    }
+}
+
+// Octet sums of the four 16-lane rows (octets 0..3 of one vector pair)
+// combined as (o0 + o1) + (o2 + o3) in every lane.  gfx950's row swaps
+// (v_permlane16_swap, v_permlane32_swap) applied to a value and itself hand
+// each lane its own row's value and the partner row's, in the VALU with no
+// LDS round trip: after the first swap the two results are o0 and o1 (rows
+// 0, 1) or o2 and o3 (rows 2, 3), after the second the two halves' sums.
+// The whole wave must be active.
+__device__ __forceinline__ float octet_total(float s) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    const float t = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const auto r2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+    return __uint_as_float(r2[0]) + __uint_as_float(r2[1]);
+}
+
+// Bit v: vector v of the tile (pairs p, p + 16 held by lanes p of every
+// octet; the lanes of octet 0 stand for them).
+__device__ __forceinline__ uint32_t pair_mask(bool a, bool b) {
+    return static_cast<uint32_t>(__ballot(a) & 0xffffull) | (static_cast<uint32_t>(__ballot(b) & 0xffffull) << 16);
+}
+
+// One query's first visited chunk as this lane's octet sees it: 8
+// dimensions (16-bit LDS row offsets, query values), the threshold and the
+// non-finite flag.
 struct FirstChunk {
-    uint4 o[2];
-    float4 q[4];
+    uint4 o;
+    float4 q[2];
     float tau;
     int bad;
     __device__ __forceinline__ void load(const uint16_t *__restrict__ poff, const float *__restrict__ qperm,
                                          const uint32_t *__restrict__ tau_all, const int32_t *__restrict__ bad_all,
-                                         int64_t qi, int32_t d, int half) {
-        const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + half * 16);
-        const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + half * 16);
-        o[0] = o4[0];
-        o[1] = o4[1];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) q[u] = q4[u];
+                                         int64_t qi, int32_t d, int oct) {
+        o = *reinterpret_cast<const uint4 *>(poff + qi * d + oct * 8);
+        const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + oct * 8);
+        q[0] = q4[0];
+        q[1] = q4[1];
         tau = __uint_as_float(tau_all[qi]);
         bad = bad_all[qi];
     }
@@ -558,6 +606,7 @@ constexpr int kDense = 8;  // survivors of the first chunk from which a (query, 
 // queries that remain are listed in LDS, kList at a time, and the waves
 // take them from the list.
 constexpr int kList = 1024;
+typedef __attribute__((address_space(3))) void lds_void_t;  // LDS destination of direct loads
 
 template <bool DENSE>
 __global__ __launch_bounds__(1024) void tile_kernel(
@@ -574,33 +623,39 @@ __global__ __launch_bounds__(1024) void tile_kernel(
     __shared__ int32_t qlist[DENSE ? kList : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int v = lane & 31;
-    const int half = lane >> 5;
+    const int pr = lane & 15;   // vector pair (pr, pr + 16) of the tile
+    const int oct = lane >> 4;  // octet of the chunk
     const int32_t nchunks = d / 32;
     uint64_t *gq = gqueue + (size_t)blockIdx.x * kGCap;  // this workgroup's overflow entries
     unsigned long long live_vals = 0, lane_vals = 0;
 
     for (int32_t t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
-        // stage 32 vectors x d dimensions: one 128-byte half row per dimension
+        // stage 32 vectors x d dimensions (one 128-byte half row per
+        // dimension) with direct global-to-LDS loads: a wave's 64 lanes
+        // bring 16 bytes each into 1 KB of contiguous LDS, 8 tile rows, with
+        // no registers holding the data, so every piece is in flight at once
         const float *src = pdxd + (int64_t)(t >> 1) * d * kGroup + (t & 1) * kTV;
-        for (int32_t i = threadIdx.x; i < d * 8; i += blockDim.x) {
-            const int32_t row = i >> 3, part = i & 7;
-            reinterpret_cast<v4f *>(tile + row * kTV)[part] =
-                __builtin_nontemporal_load(reinterpret_cast<const v4f *>(src + (int64_t)row * kGroup + part * 4));
+        const int32_t nv4 = d * 8;  // a multiple of 256: whole waves
+        for (int32_t iw = wave * 64; iw < nv4; iw += 1024) {
+            const int32_t i = iw + lane;
+            __builtin_amdgcn_global_load_lds(src + (int64_t)(i >> 3) * kGroup + (i & 7) * 4,
+                                             (lds_void_t *)(tile + (size_t)iw * 4), 16, 0, 0);
         }
         if (threadIdx.x == 0) {
             qcount = 0;
             qhead = 0;
         }
         __syncthreads();
-        const int64_t vid = (int64_t)t * kTV + v;
-        const int32_t rid = slot_id ? slot_id[vid] : (vid < n ? (int32_t)vid : -1);  // row id (-1: padding)
-        const bool valid = rid >= 0;
+        // row ids of the pair (-1: padding)
+        const int64_t vid_a = (int64_t)t * kTV + pr, vid_b = vid_a + 16;
+        const int32_t rid_a = slot_id ? slot_id[vid_a] : (vid_a < n ? (int32_t)vid_a : -1);
+        const int32_t rid_b = slot_id ? slot_id[vid_b] : (vid_b < n ? (int32_t)vid_b : -1);
+        const uint32_t valid_m = pair_mask(rid_a >= 0, rid_b >= 0);
 
-        // Phase A: first chunk of every query, lanes = 32 vectors x 2 halves.
-        // The next query's first-chunk metadata is loaded while the current
-        // one is scanned (one query per wave in flight otherwise stalls on
-        // memory latency).
+        // Phase A: first chunk of every query, lanes = 16 vector pairs x 4
+        // octets.  The next query's first-chunk metadata is loaded while the
+        // current one is scanned (one query per wave in flight otherwise
+        // stalls on memory latency).
         int32_t tb = 0;
         float trad = 0.0f;
         if (DENSE) {
@@ -631,100 +686,98 @@ __global__ __launch_bounds__(1024) void tile_kernel(
           }
           auto qid = [&](int32_t e) -> int64_t { return DENSE ? (int64_t)qlist[e] : (int64_t)e; };
           FirstChunk cur, nxt;
-          if (wave < cnt) cur.load(poff, qperm, tau, bad, qid(wave), d, half);
+          if (wave < cnt) cur.load(poff, qperm, tau, bad, qid(wave), d, oct);
           for (int32_t e = wave; e < cnt; e += kTW) {
             const int64_t qi = qid(e);
-            if (e + kTW < cnt) nxt.load(poff, qperm, tau, bad, qid(e + kTW), d, half);
+            if (e + kTW < cnt) nxt.load(poff, qperm, tau, bad, qid(e + kTW), d, oct);
             if (!cur.bad) {
-                float s = 0.0f;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint4 ow = cur.o[u >> 1];
-                    int o[4];
-                    unpack_off((u & 1) ? ow.z : ow.x, (u & 1) ? ow.w : ow.y, o);
-                    float t0 = cur.q[u].x - tile[o[0] + v];
-                    float t1 = cur.q[u].y - tile[o[1] + v];
-                    float t2 = cur.q[u].z - tile[o[2] + v];
-                    float t3 = cur.q[u].w - tile[o[3] + v];
-                    s = fmaf(t0, t0, s);
-                    s = fmaf(t1, t1, s);
-                    s = fmaf(t2, t2, s);
-                    s = fmaf(t3, t3, s);
-                }
-                const float partial = s + __shfl_xor(s, 32);  // (first 16) + (last 16)
-                const bool alive = half == 0 && valid && !(partial > cur.tau);
+                float sa, sb;
+                octet_pair(tile, cur.o, cur.q[0], cur.q[1], pr, sa, sb);
+                const float pa = octet_total(sa), pb = octet_total(sb);
+                const bool al_a = rid_a >= 0 && !(pa > cur.tau);
+                const bool al_b = rid_b >= 0 && !(pb > cur.tau);
                 if (counters) {
-                    live_vals += 32ull * __popcll(__ballot(half == 0 && valid));
+                    live_vals += 32ull * __popc(valid_m);
                     lane_vals += 64ull * 16;
                 }
-                const unsigned long long m = __ballot(alive);
-                if (DENSE && m != 0 && nchunks > 1 && __popcll(m) >= kDense) {
+                const uint32_t m = pair_mask(al_a, al_b);
+                if (DENSE && m != 0 && nchunks > 1 && __popc(m) >= kDense) {
                     // dense pair: this wave finishes the query on the tile,
-                    // lanes = 32 vectors x 2 half-chunks as in the first chunk
-                    bool al = (m >> v) & 1ull;
-                    float p = partial;
-                    const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + half * 16);
-                    const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + half * 16);
+                    // lanes = 16 vector pairs x 4 octets as in the first
+                    // chunk; the next chunk's metadata is fetched while the
+                    // current one is summed
+                    bool la = al_a, lb = al_b;
+                    float xa = pa, xb = pb;
+                    const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + oct * 8);
+                    const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + oct * 8);
+                    uint4 on = o4[4];
+                    float4 qn0 = q4[8], qn1 = q4[9];
                     for (int32_t c = 1; c < nchunks; ++c) {
-                        if (!__any(al)) break;
-                        uint4 oc[2];
-                        float4 qc[4];
-                        oc[0] = o4[4 * c];
-                        oc[1] = o4[4 * c + 1];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) qc[u] = q4[8 * c + u];
-                        float s2 = 0.0f;
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const uint4 ow = oc[u >> 1];
-                            int o[4];
-                            unpack_off((u & 1) ? ow.z : ow.x, (u & 1) ? ow.w : ow.y, o);
-                            float t0 = qc[u].x - tile[o[0] + v];
-                            float t1 = qc[u].y - tile[o[1] + v];
-                            float t2 = qc[u].z - tile[o[2] + v];
-                            float t3 = qc[u].w - tile[o[3] + v];
-                            s2 = fmaf(t0, t0, s2);
-                            s2 = fmaf(t1, t1, s2);
-                            s2 = fmaf(t2, t2, s2);
-                            s2 = fmaf(t3, t3, s2);
+                        if (!__any(la || lb)) break;
+                        const uint4 oc = on;
+                        const float4 qc0 = qn0, qc1 = qn1;
+                        if (c + 1 < nchunks) {
+                            on = o4[4 * (c + 1)];
+                            qn0 = q4[8 * (c + 1)];
+                            qn1 = q4[8 * (c + 1) + 1];
                         }
-                        p += s2 + __shfl_xor(s2, 32);  // (first 16) + (last 16), then onto the partial
-                        al = al && !(p > cur.tau);
+                        float ta, tb2;
+                        octet_pair(tile, oc, qc0, qc1, pr, ta, tb2);
+                        xa += octet_total(ta);
+                        xb += octet_total(tb2);
+                        la = la && !(xa > cur.tau);
+                        lb = lb && !(xb > cur.tau);
                         if (counters) {
-                            live_vals += 32ull * __popcll(__ballot(half == 0 && al));
+                            live_vals += 32ull * __popc(pair_mask(la, lb));
                             lane_vals += 64ull * 16;
                         }
                     }
-                    if (half == 0 && al) cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)rid);
+                    if (oct == 0 && la) cand_append(cand, cand_cnt, cap, qi, xa, (uint32_t)rid_a);
+                    if (oct == 0 && lb) cand_append(cand, cand_cnt, cap, qi, xb, (uint32_t)rid_b);
                 } else if (m != 0) {
                     if (nchunks == 1) {
-                        if (alive) cand_append(cand, cand_cnt, cap, qi, partial, (uint32_t)rid);
+                        if (oct == 0 && al_a) cand_append(cand, cand_cnt, cap, qi, pa, (uint32_t)rid_a);
+                        if (oct == 0 && al_b) cand_append(cand, cand_cnt, cap, qi, pb, (uint32_t)rid_b);
                     } else {
                         int base = 0;
-                        if (lane == 0) base = atomicAdd(&qcount, __popcll(m));
+                        if (lane == 0) base = atomicAdd(&qcount, __popc(m));
                         base = __shfl(base, 0);
-                        const int pos = base + lane_rank(m);
-                        bool own = false;  // both queues are full: finish this survivor here
-                        if (alive) {
-                            const uint32_t key = (static_cast<uint32_t>(qi) << 5) | static_cast<uint32_t>(v);
-                            if (pos < kQCap)
-                                queue[pos] = make_uint2(key, __float_as_uint(partial));
-                            else if (pos < kQCap + kGCap)
-                                gq[pos - kQCap] = (static_cast<uint64_t>(__float_as_uint(partial)) << 32) | key;
-                            else
-                                own = true;
+                        // queue slot of vector v: base + the survivors below v
+                        bool own_a = false, own_b = false;  // both queues are full: finish it here
+                        if (oct == 0) {
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const bool al = h ? al_b : al_a;
+                                if (!al) continue;
+                                const int vv = pr + 16 * h;
+                                const int pos = base + __popc(m & ((1u << vv) - 1u));
+                                const uint32_t key = (static_cast<uint32_t>(qi) << 5) | static_cast<uint32_t>(vv);
+                                const float pv = h ? pb : pa;
+                                if (pos < kQCap)
+                                    queue[pos] = make_uint2(key, __float_as_uint(pv));
+                                else if (pos < kQCap + kGCap)
+                                    gq[pos - kQCap] = (static_cast<uint64_t>(__float_as_uint(pv)) << 32) | key;
+                                else if (h)
+                                    own_b = true;
+                                else
+                                    own_a = true;
+                            }
                         }
+                        // lanes of octet 0 finish vector pr, lanes of octet 1 vector pr + 16
+                        const bool own_b_here = __shfl(own_b, pr);
+                        bool own = (oct == 0 && own_a) || (oct == 1 && own_b_here);
                         if (__any(own)) {
+                            const int vv = pr + 16 * (oct & 1);
                             const uint16_t *pf = poff + qi * d;
                             const float *qp = qperm + qi * d;
-                            float p = partial;
+                            float x = (oct & 1) ? pb : pa;
                             for (int32_t c = 1; c < nchunks && __any(own); ++c) {
                                 if (own) {
-                                    p += tile_chunk(tile, pf + c * 32, qp + c * 32, v);
-                                    own = !(p > cur.tau);
+                                    x += tile_chunk(tile, pf + c * 32, qp + c * 32, vv);
+                                    own = !(x > cur.tau);
                                 }
                             }
-                            if (own) cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)rid);
+                            if (own) cand_append(cand, cand_cnt, cap, qi, x, (uint32_t)((oct & 1) ? rid_b : rid_a));
                         }
                     }
                 }
