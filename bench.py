@@ -249,7 +249,7 @@ def bench_bond_ivf(pdx, torch, np, ix, q_dev, nprobes, k, steps, warmup, truth_i
 
 def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d):
     """The kernel listing's other distances on the same index and queries:
-    L1 with PDX-BOND (vectorgroup path) and the inner product (linear scan
+    L1 with PDX-BOND (LDS-tile path with the L1 centroid bound) and the inner product (linear scan
     on the matrix cores; roofline: 2 flops per (query, vector, dimension)
     over the scan's event-timed duration, against dense FP32 MFMA)."""
     nq = q.shape[0]

@@ -314,11 +314,12 @@ __global__ __launch_bounds__(64) void nearest_kernel(const float *__restrict__ c
 }
 
 // Centroid bound inputs for the tile kernel: dql[l][q] = sqrt(cd[q][l])
-// lowered by 1e-4 (a lower bound of |q - c_l|: the float32 sum of D squares
+// (L2; cd[q][l] itself for L1, where cd holds L1 distances) lowered by 1e-4
+// (a lower bound of |q - c_l|: the float32 sum of D non-negative terms
 // carries at most about D 2^-24 relative error), bucket-major so that the
 // queries of one tile read one contiguous row.  32 x 32 blocks through LDS.
 __global__ __launch_bounds__(256) void centroid_lo_kernel(const float *__restrict__ cd, int64_t nq, int32_t nlist,
-                                                          float *__restrict__ dql) {
+                                                          float *__restrict__ dql, int32_t l1) {
     __shared__ float blk[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     const int64_t q0 = (int64_t)blockIdx.x * 32;
@@ -326,7 +327,8 @@ __global__ __launch_bounds__(256) void centroid_lo_kernel(const float *__restric
     for (int r = ty; r < 32; r += 8) {
         const int64_t q = q0 + r;
         const int32_t l = l0 + tx;
-        blk[r][tx] = (q < nq && l < nlist) ? sqrtf(cd[q * nlist + l]) * (1.0f - 1e-4f) : 0.0f;
+        const float c = (q < nq && l < nlist) ? cd[q * nlist + l] : 0.0f;
+        blk[r][tx] = (l1 ? c : sqrtf(c)) * (1.0f - 1e-4f);
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
@@ -365,6 +367,7 @@ __global__ __launch_bounds__(256) void start_bucket_kernel(
 
 // Group path for the queries whose candidate buffer overflowed in the tile
 // path: every (listed query, group tile) pair, grid-stride.
+template <bool L1>
 __global__ __launch_bounds__(256) void fallback_kernel(
     const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t g_begin,
     int32_t g_end, int32_t tile_groups,
@@ -378,8 +381,8 @@ __global__ __launch_bounds__(256) void fallback_kernel(
         const int32_t tile = (int32_t)(it % ntiles);
         const int32_t g0 = g_begin + tile * tile_groups;
         const int32_t g1 = min(g0 + tile_groups, g_end);
-        scan_groups<true>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau,
-                          slots + ((size_t)qi * nslots + slot0 + tile) * k, k, chunk, nullptr);
+        scan_groups<true, L1>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau,
+                              slots + ((size_t)qi * nslots + slot0 + tile) * k, k, chunk, nullptr);
     }
 }
 
@@ -509,6 +512,7 @@ __device__ __forceinline__ void unpack_off(uint32_t w0, uint32_t w1, int (&o)[4]
 // Full chunk of 32 visited dimensions for vector v of the LDS tile, four
 // octets of fused multiply-adds (pf: the chunk's 16-bit row offsets, qp:
 // its query values; loaded 16 bytes at a time).
+template <bool L1>
 __device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, const uint16_t *__restrict__ pf,
                                             const float *__restrict__ qp, int v) {
     const uint4 *o4 = reinterpret_cast<const uint4 *>(pf);
@@ -525,16 +529,17 @@ __device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, cons
         float t2 = qq.z - tile[o[2] + v];
         float t3 = qq.w - tile[o[3] + v];
         float &s = oc[u >> 1];
-        s = fmaf(t0, t0, s);
-        s = fmaf(t1, t1, s);
-        s = fmaf(t2, t2, s);
-        s = fmaf(t3, t3, s);
+        s = dist_term<L1>(s, t0);
+        s = dist_term<L1>(s, t1);
+        s = dist_term<L1>(s, t2);
+        s = dist_term<L1>(s, t3);
     }
     return octets(oc[0], oc[1], oc[2], oc[3]);
 }
 
 // One octet (8 visited dimensions) of a chunk for the tile's vectors p and
 // p + 16: each dimension's LDS row address serves both (one paired read).
+template <bool L1>
 __device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4 ow, float4 q0, float4 q1, int p,
                                            float &a, float &b) {
     int o[8];
@@ -546,10 +551,8 @@ __device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const float *r = tile + o[u] + p;
-        const float ta = qv[u] - r[0];
-        const float tb = qv[u] - r[16];
-        a = fmaf(ta, ta, a);
-        b = fmaf(tb, tb, b);
+        a = dist_term<L1>(a, qv[u] - r[0]);
+        b = dist_term<L1>(b, qv[u] - r[16]);
     }
 }
 
@@ -608,7 +611,7 @@ constexpr int kDense = 8;  // survivors of the first chunk from which a (query, 
 constexpr int kList = 1024;
 typedef __attribute__((address_space(3))) void lds_void_t;  // LDS destination of direct loads
 
-template <bool DENSE>
+template <bool DENSE, bool L1>
 __global__ __launch_bounds__(1024) void tile_kernel(
     const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t t_begin,
     int32_t t_end, int64_t nq,
@@ -674,7 +677,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
             if (threadIdx.x < kList && qt < nq && !bad[qt]) {
                 const float gap = fmaxf(dql[(int64_t)tb * nq + qt] - trad, 0.0f);
                 const float tq = __uint_as_float(__hip_atomic_load(tau + qt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                keep = !(gap * gap > tq);
+                keep = L1 ? !(gap > tq) : !(gap * gap > tq);  // L1: the bound is the gap itself
             }
             const unsigned long long km = __ballot(keep);
             int lb = 0;
@@ -692,7 +695,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
             if (e + kTW < cnt) nxt.load(poff, qperm, tau, bad, qid(e + kTW), d, oct);
             if (!cur.bad) {
                 float sa, sb;
-                octet_pair(tile, cur.o, cur.q[0], cur.q[1], pr, sa, sb);
+                octet_pair<L1>(tile, cur.o, cur.q[0], cur.q[1], pr, sa, sb);
                 const float pa = octet_total(sa), pb = octet_total(sb);
                 const bool al_a = rid_a >= 0 && !(pa > cur.tau);
                 const bool al_b = rid_b >= 0 && !(pb > cur.tau);
@@ -722,7 +725,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                             qn1 = q4[8 * (c + 1) + 1];
                         }
                         float ta, tb2;
-                        octet_pair(tile, oc, qc0, qc1, pr, ta, tb2);
+                        octet_pair<L1>(tile, oc, qc0, qc1, pr, ta, tb2);
                         xa += octet_total(ta);
                         xb += octet_total(tb2);
                         la = la && !(xa > cur.tau);
@@ -773,7 +776,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                             float x = (oct & 1) ? pb : pa;
                             for (int32_t c = 1; c < nchunks && __any(own); ++c) {
                                 if (own) {
-                                    x += tile_chunk(tile, pf + c * 32, qp + c * 32, vv);
+                                    x += tile_chunk<L1>(tile, pf + c * 32, qp + c * 32, vv);
                                     own = !(x > cur.tau);
                                 }
                             }
@@ -828,7 +831,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
             if (act) {
                 const int64_t qi = qv >> 5;
                 const int vv = qv & 31;
-                p += tile_chunk(tile, poff + qi * d + c * 32, qperm + qi * d + c * 32, vv);
+                p += tile_chunk<L1>(tile, poff + qi * d + c * 32, qperm + qi * d + c * 32, vv);
                 ++c;
                 if (p > tl) {
                     act = false;
@@ -870,7 +873,7 @@ size_t max_dynamic_lds() {
 }
 
 bool tile_path(const pdx_index *ix, const ExactPlan &pl) {
-    return pl.mode == PDX_MODE_BOND && pl.metric == PDX_METRIC_L2 && pl.chunk == 32 && ix->d * kTV < 65536 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
+    return pl.mode == PDX_MODE_BOND && (pl.metric == PDX_METRIC_L2 || pl.metric == PDX_METRIC_L1) && pl.chunk == 32 && ix->d * kTV < 65536 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
            pl.tiles_main > 0 && tile_lds_bytes(ix->d) <= max_dynamic_lds();
 }
 
@@ -1019,12 +1022,13 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     if (pl.ivf && pl.mode == PDX_MODE_BOND) {
         // START on the nearest bucket: its k-th distance is the initial
         // threshold (its rows are found again by the main scan)
-        if ((err = launch_pair(1, 0, qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) !=
-            hipSuccess)
+        // centroid distances in the search's metric (L2 squared, or L1)
+        if ((err = launch_pair(l1 ? 2 : 1, 0, qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr,
+                               s)) != hipSuccess)
             return err;
         nearest_kernel<<<nqu, 64, 0, s>>>(pl.cd, ix->nlist, pl.nearest);
         centroid_lo_kernel<<<dim3((unsigned)((pl.nq + 31) / 32), (unsigned)((ix->nlist + 31) / 32)), 256, 0, s>>>(
-            pl.cd, pl.nq, ix->nlist, pl.dql);
+            pl.cd, pl.nq, ix->nlist, pl.dql, l1 ? 1 : 0);
         const int64_t waves = pl.nq * pl.start_parts;
         if (l1)
             start_bucket_kernel<true><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(
@@ -1063,27 +1067,37 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     }
     // tile path: rounds of 32-vector tiles, threshold refreshed in between
     const size_t tile_lds = tile_lds_bytes(d);
-    const void *tk = pl.ivf ? reinterpret_cast<const void *>(tile_kernel<true>)
-                            : reinterpret_cast<const void *>(tile_kernel<false>);
+    // kernel: the centroid bound and dense pairs on the bucket layout (the
+    // tile radii in the search's metric); on the flat layout every query
+    // meets every tile
+    const void *tk = pl.ivf ? (l1 ? reinterpret_cast<const void *>(tile_kernel<true, true>)
+                                  : reinterpret_cast<const void *>(tile_kernel<true, false>))
+                            : (l1 ? reinterpret_cast<const void *>(tile_kernel<false, true>)
+                                  : reinterpret_cast<const void *>(tile_kernel<false, false>));
     if (tile_lds > 64 * 1024) {
         if ((err = hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds)) != hipSuccess)
             return err;
     }
     const int32_t t0 = 2 * pl.start_groups, t1 = 2 * ix->ngroups;
     const int cus = pl.tile_grid;
+    const float *trad = pl.ivf ? (l1 ? ix->tile_rad1 : ix->tile_rad) : nullptr;
     for (int32_t r = 0; r < kRounds; ++r) {
         const int32_t a = t0 + (int32_t)((int64_t)(t1 - t0) * r / kRounds);
         const int32_t b = t0 + (int32_t)((int64_t)(t1 - t0) * (r + 1) / kRounds);
         if (b <= a) continue;
         const unsigned grid = (unsigned)min(b - a, cus);
-        if (pl.ivf)
-            tile_kernel<true><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,
-                                                           pl.tau, pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue,
-                                                           cmain, pl.dql, ix->group_bucket, ix->tile_rad);
-        else
-            tile_kernel<false><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,
-                                                            pl.tau, pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue,
-                                                            cmain, nullptr, nullptr, nullptr);
+#define PDX_TILE(DN, M)                                                                                              \
+    tile_kernel<DN, M><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm, pl.tau, \
+                                                    pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue, cmain,       \
+                                                    DN ? pl.dql : nullptr, DN ? ix->group_bucket : nullptr, trad)
+        if (pl.ivf) {
+            if (l1) PDX_TILE(true, true);
+            else PDX_TILE(true, false);
+        } else {
+            if (l1) PDX_TILE(false, true);
+            else PDX_TILE(false, false);
+        }
+#undef PDX_TILE
         if ((err = hipGetLastError()) != hipSuccess) return err;
         if (r + 1 < kRounds) {
             cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, 0, pl.k, pl.bad, pl.tau, nullptr, 0,
@@ -1094,9 +1108,16 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     // queries whose buffer overflowed: group path over the main range
     if ((err = launch_fill_i32(pl.over_count, 1, 0, s)) != hipSuccess) return err;
     over_list_kernel<<<(nqu + 255) / 256, 256, 0, s>>>(pl.cand_cnt, pl.nq, kCandCap, pl.over_list, pl.over_count);
-    fallback_kernel<<<2048, 256, 0, s>>>(ix->pdx, ix->n, sid, d, pl.start_groups, ix->ngroups, pl.tile_groups,
-                                         pl.tiles_main, pl.over_list, pl.over_count, pl.perm, pl.qperm, pl.tau,
-                                         pl.slots, pl.nslots, pl.tiles_start, pl.k, pl.chunk);
+    if (l1)
+        fallback_kernel<true><<<2048, 256, 0, s>>>(ix->pdx, ix->n, sid, d, pl.start_groups, ix->ngroups,
+                                                   pl.tile_groups, pl.tiles_main, pl.over_list, pl.over_count,
+                                                   pl.perm, pl.qperm, pl.tau, pl.slots, pl.nslots, pl.tiles_start,
+                                                   pl.k, pl.chunk);
+    else
+        fallback_kernel<false><<<2048, 256, 0, s>>>(ix->pdx, ix->n, sid, d, pl.start_groups, ix->ngroups,
+                                                    pl.tile_groups, pl.tiles_main, pl.over_list, pl.over_count,
+                                                    pl.perm, pl.qperm, pl.tau, pl.slots, pl.nslots, pl.tiles_start,
+                                                    pl.k, pl.chunk);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if ((err = mark(2)) != hipSuccess) return err;
     // an overflowed buffer's head: START's k best on the flat layout (rows

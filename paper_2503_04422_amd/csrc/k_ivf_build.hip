@@ -328,9 +328,11 @@ __global__ void group_bucket_kernel(const int32_t *__restrict__ goff, int32_t nl
 }
 
 // Radius of every 32-vector tile (half a vectorgroup) around its bucket's
-// centroid: the largest |x - c| over the tile's rows, float64 sums, widened
-// by 1e-6 and rounded up to float32 (0 for a tile of padding only).  One
-// wave per tile; lanes 0..31 are its vectors.
+// centroid: the largest |x - c| (L2, or the L1 norm when L1) over the
+// tile's rows, float64 sums, widened by 1e-6 and rounded up to float32 (0
+// for a tile of padding only).  One wave per tile; lanes 0..31 are its
+// vectors.
+template <bool L1>
 __global__ __launch_bounds__(256) void tile_radius_kernel(const float *__restrict__ pdx,
                                                           const int32_t *__restrict__ slot_id,
                                                           const int32_t *__restrict__ goff, int32_t nlist,
@@ -350,24 +352,27 @@ __global__ __launch_bounds__(256) void tile_radius_kernel(const float *__restric
         const float *cp = cen + (int64_t)b * d;
         for (int32_t j = 0; j < d; ++j) {
             const double e = (double)xp[(int64_t)j * kGroup] - (double)cp[j];
-            acc = fma(e, e, acc);
+            acc = L1 ? acc + fabs(e) : fma(e, e, acc);
         }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc = fmax(acc, __shfl_xor(acc, off));
-    if (lane == 0) rad[t] = __double2float_ru(sqrt(acc) * (1.0 + 1e-6));
+    if (lane == 0) rad[t] = __double2float_ru((L1 ? acc : sqrt(acc)) * (1.0 + 1e-6));
 }
 
 }  // namespace
 
 hipError_t launch_tile_radii(const float *pdx, const int32_t *slot_id, const int32_t *goff, int32_t nlist,
                              const float *cen, int32_t d, int64_t max_groups, int32_t *gb, float *rad,
-                             hipStream_t s) {
+                             float *rad1, hipStream_t s) {
     group_bucket_kernel<<<(unsigned)((nlist + 255) / 256), 256, 0, s>>>(goff, nlist, gb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t tiles = 2 * max_groups;
-    tile_radius_kernel<<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(pdx, slot_id, goff, nlist, gb, cen, d, tiles, rad);
+    tile_radius_kernel<false><<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(pdx, slot_id, goff, nlist, gb, cen, d,
+                                                                          tiles, rad);
+    tile_radius_kernel<true><<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(pdx, slot_id, goff, nlist, gb, cen, d,
+                                                                         tiles, rad1);
     return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // matrices A [m][k] and B [nb][k]:
 //   DOT: C[i][j] = sum_t A[i][t] * B[j][t]      (rotation: X R^T)
 //   L2 : C[i][j] = sum_t (A[i][t] - B[j][t])^2  (centroid distances)
+//   L1 : C[i][j] = sum_t |A[i][t] - B[j][t]|    (L1 centroid distances)
 // Output either stored (C, leading dimension ldc) or reduced per row of A
 // to the nearest B row: an atomic minimum over the 64-bit key
 // (distance bits << 32 | j), i.e. the smallest distance, ties to lower j
@@ -58,6 +59,8 @@ __global__ __launch_bounds__(256) void pair_kernel(const float *__restrict__ A, 
                 for (int w = 0; w < 4; ++w) {
                     if (MODE == 0) {
                         acc[u][w] = fmaf(a[u], b[w], acc[u][w]);
+                    } else if (MODE == 2) {
+                        acc[u][w] += fabsf(a[u] - b[w]);
                     } else {
                         float dd = a[u] - b[w];
                         acc[u][w] = fmaf(dd, dd, acc[u][w]);
@@ -115,6 +118,8 @@ hipError_t launch_pair(int mode, int out, const float *A, int64_t m, const float
         pair_kernel<1, 0><<<grid, 256, 0, s>>>(A, m, B, nb, k, C, ldc, best);
     else if (mode == 1 && out == 1)
         pair_kernel<1, 1><<<grid, 256, 0, s>>>(A, m, B, nb, k, C, ldc, best);
+    else if (mode == 2 && out == 0)
+        pair_kernel<2, 0><<<grid, 256, 0, s>>>(A, m, B, nb, k, C, ldc, best);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

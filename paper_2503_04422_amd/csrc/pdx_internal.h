@@ -46,6 +46,7 @@ struct pdx_index {
     int32_t max_list;    // largest bucket, rows
     int32_t *group_bucket;  // [ngroups] bucket of each vectorgroup
     float *tile_rad;        // [2 ngroups] radius of each 32-vector tile around its centroid
+    float *tile_rad1;       // [2 ngroups] the same in the L1 norm
 };
 
 namespace pdx {
@@ -331,7 +332,7 @@ __device__ inline float e4m3_decode(uint32_t c) { return __builtin_amdgcn_cvt_f3
 // 32-vector tile around its bucket's centroid (rounded up).
 hipError_t launch_tile_radii(const float *pdx, const int32_t *slot_id, const int32_t *goff, int32_t nlist,
                              const float *cen, int32_t d, int64_t max_groups, int32_t *gb, float *rad,
-                             hipStream_t s);
+                             float *rad1, hipStream_t s);
 hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int32_t *slot_id, const int32_t *stats,
                              int64_t max_groups, uint16_t *pdx16, uint8_t *pdx8, float *scale, uint32_t *maxbits,
                              hipStream_t s);

@@ -13,7 +13,7 @@ constexpr int32_t kRowsPerBlock = 1024;
 constexpr int32_t kMeanChunksIvf = 256;
 
 struct IvfLayout {
-    float *rot, *centroids, *pdx, *xrot, *fp8_scale, *means, *tile_rad;
+    float *rot, *centroids, *pdx, *xrot, *fp8_scale, *means, *tile_rad, *tile_rad1;
     uint16_t *pdx16;
     uint8_t *pdx8;
     uint32_t *maxbits;
@@ -42,6 +42,7 @@ IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, voi
     l.means = c.take<float>(d);             // per-dimension means of the stored rows (exact search order)
     l.group_bucket = c.take<int32_t>((size_t)l.max_groups);
     l.tile_rad = c.take<float>((size_t)l.max_groups * 2);
+    l.tile_rad1 = c.take<float>((size_t)l.max_groups * 2);
     if (lowp_mask & (1 << PDX_DTYPE_BF16)) l.pdx16 = c.take<uint16_t>((size_t)l.max_groups * d * kGroup);
     if (lowp_mask & (1 << PDX_DTYPE_FP8)) {
         l.pdx8 = c.take<uint8_t>((size_t)l.max_groups * d * kGroup);
@@ -201,7 +202,7 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     TRY(launch_bucketize(L.xrot, n, d, L.assign, nlist, L.blk_cnt, L.list_size, L.list_goff, L.stats, L.slot_id,
                          L.max_groups * kGroup, L.pdx, L.max_groups, s));
     TRY(launch_tile_radii(L.pdx, L.slot_id, L.list_goff, nlist, L.centroids, d, L.max_groups, L.group_bucket,
-                          L.tile_rad, s));
+                          L.tile_rad, L.tile_rad1, s));
     if (L.pdx16 || L.pdx8)
         TRY(launch_lowp_store(L.xrot, n, d, L.slot_id, L.stats, L.max_groups, L.pdx16, L.pdx8, L.fp8_scale, L.maxbits,
                               s));
@@ -236,6 +237,7 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     ix->means = L.means;
     ix->group_bucket = L.group_bucket;
     ix->tile_rad = L.tile_rad;
+    ix->tile_rad1 = L.tile_rad1;
     *out = ix;
     return PDX_OK;
 }

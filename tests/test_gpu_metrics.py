@@ -138,3 +138,26 @@ def test_inner_product_full_size_sampled(pdx):
     check_knn_metric(x, q[sample], gi[sample], gd[sample], wi, wd, "ip")
     assert (np.diff(gd, axis=1) >= 0).all()
     assert (gi >= 0).all() and (gi < x.shape[0]).all()
+
+
+@pytest.mark.parametrize("layout", ["flat", "buckets"])
+@pytest.mark.parametrize("d", [128, 960])
+def test_l1_tile_path(pdx, layout, d):
+    """L1 with PDX-BOND on shapes the LDS-tile path takes (D a multiple of
+    32): real inputs under the relative 1e-5 rule, and a tie-heavy case
+    whose candidate buffers overflow (the L1 fallback path), bit for bit."""
+    x, q, _ = synth.workload("bond_1m_d960", n=12_000, nq=20)
+    x, q = x[:, :d].copy(), q[:, :d].copy()
+    ix = pdx.pdx_build(_dev(x)) if layout == "flat" else _buckets(pdx, x, 24, d)
+    print(f"l1 tile path {layout} d={d}", flush=True)
+    gi, gd = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10, mode="bond", metric="l1"))
+    wi, wd = exact.knn_exact(x, q, 10, metric="l1")
+    check_knn_metric(x, q, gi, gd, wi, wd, "l1")
+    z = np.zeros((8_000, d), dtype=np.float32)
+    z[::5, 3] = 1.0
+    qz = np.zeros((6, d), dtype=np.float32)
+    iz = pdx.pdx_build(_dev(z)) if layout == "flat" else _buckets(pdx, z, 8, 5)
+    print(f"l1 tile path overflow {layout} d={d}", flush=True)
+    gi, gd = (_np(t) for t in pdx.pdx_search_exact(iz, _dev(qz), 10, mode="bond", metric="l1"))
+    wi, wd = exact.knn_exact(z, qz, 10, metric="l1")
+    check_knn_metric(z, qz, gi, gd, wi, wd, "l1", exact=True)
