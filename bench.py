@@ -51,6 +51,8 @@ HBM_PEAK_GBS = 8000.0
 # (3 flops) and one 4-byte LDS read (LDS: 256 CUs x 128 B/clk = the same
 # 1.97e13 values/s).  3 flops x 1.966e13 values/s:
 ALU_PEAK_TFLOPS = 3 * 256 * 64 * 2.4e9 / 2 / 1e12
+# one fused multiply-add (2 flops) per lane and clock, packed FP32 off
+FMA_PEAK_TFLOPS = 2 * 256 * 64 * 2.4e9 / 1e12
 METRIC = "QPS (K=10) exact + at recall@10>=0.95, 1Mx960 fp32; achieved HBM GB/s"
 
 
@@ -247,11 +249,15 @@ def bench_bond_ivf(pdx, torch, np, ix, q_dev, nprobes, k, steps, warmup, truth_i
     return out
 
 
-def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d):
+def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d, layout="buckets"):
     """The kernel listing's other distances on the same index and queries:
-    L1 with PDX-BOND (LDS-tile path with the L1 centroid bound) and the inner product (linear scan
-    on the matrix cores; roofline: 2 flops per (query, vector, dimension)
-    over the scan's event-timed duration, against dense FP32 MFMA)."""
+    L1 with PDX-BOND (LDS-tile path with the L1 centroid bound) and the
+    inner product.  On the bucket layout the inner product runs on the
+    LDS-tile path with the Cauchy-Schwarz tile bound (roofline: 2 flops per
+    value the kernel evaluates, from its own counters, over the scan's
+    event-timed duration, against the FP32 fused multiply-add vector peak);
+    on the flat layout it is the matrix-core scan of every row (2 flops per
+    (query, vector, dimension) against dense FP32 MFMA)."""
     nq = q.shape[0]
     out = {}
     for metric, mode in (("l1", "bond"), ("ip", "linear")):
@@ -264,7 +270,19 @@ def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d):
         elapsed, ph = timed_steps(run, steps, warmup, torch, np)
         row = {"mode": mode, "qps": round(nq * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
                "phases_ms": {"prep_start": round(ph[0], 3), "scan": round(ph[1], 3), "merge": round(ph[2], 3)}}
-        if metric == "ip" and ph[1] > 0:
+        if metric == "ip" and ph[1] > 0 and layout == "buckets":
+            cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+            pdx.pdx_search_exact(ix, q, k, mode=mode, metric=metric, workspace=ws, counters=cnt)
+            c = [float(v) for v in cnt.cpu().tolist()]
+            flops = 2.0 * c[2]
+            achieved = flops / (ph[1] * 1e-3) / 1e12
+            row["values_evaluated"] = {"scan": c[2], "of_all": round(c[2] / (nq * n * d), 5)}
+            row["roofline"] = {"bound": "alu", "kernel": "ip_tile_kernel (tile bound, LDS tiles)",
+                               "achieved": round(achieved, 3), "peak": FMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(achieved / FMA_PEAK_TFLOPS, 4), "traffic": None,
+                               "traffic_source": "not profiled", "algorithmic_flops_per_step": flops,
+                               "scan_ms": round(ph[1], 4)}
+        elif metric == "ip" and ph[1] > 0:
             flops = 2.0 * nq * n * d
             achieved = flops / (ph[1] * 1e-3) / 1e12
             traffic, src = profiled_traffic("ip_scan_bond_1m_d960.md") if (n, d, k) == (1_000_000, 960, 10) \
@@ -277,7 +295,6 @@ def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d):
         print(f"# metric {metric}: {row}", file=sys.stderr, flush=True)
         out[metric] = row
     return out
-
 
 def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu_seconds, target=0.95,
                   nprobe_max=32, n_train=8000, n_val=2000, seed_train=43, seed_eval=44, prune_levels=(0.95, 0.98, 0.99),
@@ -792,7 +809,7 @@ def main() -> int:
         extra["own_linear_scan"] = {"qps": round(nq / tl, 1), "ms": round(1e3 * tl, 2),
                                     "note": "same kernels, no pruning (PDX linear scan)"}
     if mode == "bond" and not args.no_metrics:
-        extra["metrics"] = bench_metrics(pdx, torch, np, ix, q, k, 3, 1, n, d)
+        extra["metrics"] = bench_metrics(pdx, torch, np, ix, q, k, 3, 1, n, d, layout)
     del ws
     if mode == "bond" and not args.no_ivf:
         ivf_ix = build_ivf(pdx, torch, np, x, 1024)

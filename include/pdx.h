@@ -103,9 +103,13 @@ enum {
     PDX_METRIC_L2 = 0, /* sum_j (q_j - v_j)^2                                  */
     PDX_METRIC_L1 = 1, /* sum_j |q_j - v_j|; PDX-BOND prunes it like L2: its
                           partial sums are lower bounds too                      */
-    PDX_METRIC_IP = 2  /* -sum_j q_j v_j (largest inner product first), on the
-                          matrix cores; PDX_MODE_LINEAR only: a partial inner
-                          product bounds nothing                                 */
+    PDX_METRIC_IP = 2  /* -sum_j q_j v_j (largest inner product first);
+                          PDX_MODE_LINEAR only: a partial inner product bounds
+                          nothing.  Flat index: a matrix-core scan of every
+                          row.  Bucket layout with D % 32 == 0: whole tiles
+                          are skipped by q.v <= q.c + |q| r (Cauchy-Schwarz,
+                          c the bucket centroid, r the tile radius) and the
+                          rest scanned in full                                   */
 };
 
 typedef struct {
@@ -124,10 +128,13 @@ typedef struct {
                             slots it issued (live and pruned lanes) */
     int32_t metric;      /* PDX_METRIC_*; 0 = L2 */
     int32_t start_rows;  /* bucket layout (IVF index): rows of the query's
-                            nearest bucket that START scans, in whole
-                            vectorgroups (Section 6.5 sizes the START block
-                            "at most"); 0 = 128.  The flat index takes its
-                            START block from pdx_build_params. */
+                            nearest bucket (inner product: the bucket with
+                            the largest q.c) that START scans, in whole
+                            vectorgroups (Section 6.5 bounds the START
+                            block's size); 0 = 128 (1,024 for the inner
+                            product, whose START threshold is looser).  The
+                            flat index takes its START block from
+                            pdx_build_params. */
 } pdx_search_params;
 
 /* Workspace bytes for pdx_search_exact with these arguments. */

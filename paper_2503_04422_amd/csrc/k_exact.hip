@@ -430,19 +430,21 @@ __global__ __launch_bounds__(64) void merge_kernel(const uint64_t *__restrict__ 
 // overflowed: its first `head` entries, which hold rows outside the main
 // range, and the fallback slots over the main range).  Refresh mode:
 // tighten the threshold; final mode: write the result.
-__global__ __launch_bounds__(64) void cand_merge_kernel(const uint64_t *__restrict__ cand,
-                                                        const int32_t *__restrict__ cand_cnt, int32_t cap,
+__global__ __launch_bounds__(64) void cand_merge_kernel(uint64_t *__restrict__ cand,
+                                                        int32_t *__restrict__ cand_cnt, int32_t cap,
                                                         int32_t head, int32_t k, const int32_t *__restrict__ bad,
                                                         uint32_t *__restrict__ tau,
                                                         const uint64_t *__restrict__ slots, int32_t nslots,
                                                         int32_t slot_begin, int32_t slot_count,
                                                         int64_t *__restrict__ out_ids,
-                                                        float *__restrict__ out_dist) {
+                                                        float *__restrict__ out_dist,
+                                                        const float *__restrict__ qshift, int32_t compact) {
     const int64_t qi = blockIdx.x;
     const int lane = threadIdx.x;
     const int32_t cnt = cand_cnt[qi];
     const bool over = cnt > cap;
     const uint64_t *cb = cand + (size_t)qi * cap;
+    uint64_t *cb_w = cand + (size_t)qi * cap;
     const int32_t nc = over && out_ids ? head : min(cnt, cap);
     uint64_t e = kEmptyKey, kth = kEmptyKey;
     for (int32_t i0 = 0; i0 < nc; i0 += kWave) {
@@ -462,6 +464,14 @@ __global__ __launch_bounds__(64) void cand_merge_kernel(const uint64_t *__restri
             uint32_t kb = static_cast<uint32_t>(kth >> 32);
             if (kb < tau[qi]) tau[qi] = kb;
         }
+        if (compact && !over) {
+            // keep only the k best: an entry with k better ones never
+            // reaches the result (bucket layout only, where an overflowed
+            // query keeps no buffer head)
+            const unsigned long long has = __ballot(lane < k && e != kEmptyKey);
+            if (lane < k && e != kEmptyKey) cb_w[lane] = e;
+            if (lane == 0) cand_cnt[qi] = __popcll(has);
+        }
         return;
     }
     if (lane < k) {
@@ -471,7 +481,7 @@ __global__ __launch_bounds__(64) void cand_merge_kernel(const uint64_t *__restri
             dist = __uint_as_float(0x7fc00000u);
         } else if (e != kEmptyKey) {
             id = static_cast<int64_t>(e & 0xffffffffu);
-            dist = key_dist(e);
+            dist = qshift ? key_dist(e) - qshift[qi] : key_dist(e);  // inner product: s' - B_q = -q.x
         }
         out_ids[qi * k + lane] = id;
         out_dist[qi * k + lane] = dist;
@@ -856,8 +866,10 @@ int32_t next_pow2(int32_t v) {
     return p;
 }
 
-constexpr int32_t kCandCap = 2048;  // candidates per query in the tile path
+constexpr int32_t kCandCap = 2048;     // candidates per query in the tile path
+constexpr int32_t kCandCapIp = 65536;  // the same for the inner product (looser START threshold)
 constexpr int32_t kRounds = 4;      // threshold refreshes in the tile path
+constexpr int32_t kRoundsIp = 16;   // the same for the inner product (its START threshold is looser)
 
 size_t tile_lds_bytes(int32_t d) { return (size_t)d * kTV * sizeof(float) + kQCap * sizeof(uint2); }
 
@@ -873,6 +885,9 @@ size_t max_dynamic_lds() {
 }
 
 bool tile_path(const pdx_index *ix, const ExactPlan &pl) {
+    if (pl.metric == PDX_METRIC_IP)  // inner product: the bucket layout's tile bound
+        return ix->kind == kIvf && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) && pl.tiles_main > 0 &&
+               (size_t)ix->d * kTV * sizeof(float) <= max_dynamic_lds();
     return pl.mode == PDX_MODE_BOND && (pl.metric == PDX_METRIC_L2 || pl.metric == PDX_METRIC_L1) && pl.chunk == 32 && ix->d * kTV < 65536 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
            pl.tiles_main > 0 && tile_lds_bytes(ix->d) <= max_dynamic_lds();
 }
@@ -903,6 +918,280 @@ __global__ __launch_bounds__(256) void bond_item_kernel(
     const int32_t l = probe[(int64_t)item.x * nprobe + item.y];
     scan_groups<PRUNE, false, ZONES>(pdxd, 0, slot_id, d, goff[l], goff[l + 1], item.x, perm, qperm, tau, myslot,
                                      slots.kk, chunk, counters, xrow, zone_rows);
+}
+
+// ---------------------------------------------------------------------------
+// Inner product on the bucket layout (tile path).  A partial inner product
+// bounds nothing, so a (query, tile) pair is scanned in full once kept; what
+// prunes is the tile bound: for x within radius r of its bucket's centroid
+// c, q.x <= q.c + |q| r (Cauchy-Schwarz).  Scores are ranked as
+// s' = B_q - q.x with B_q a power of two at or above |q| M (1 + 2^-10) and
+// M >= every |x| (the largest |c| + r over the tiles), so s' > 0 and the
+// non-negative key and threshold machinery of the L2 path applies; the
+// result reports s' - B_q.
+// Every q.x is summed in the one fixed order of the other metrics (natural
+// dimension order, 32-dimension chunks as four octets), so START, the tile
+// kernel and the fallback agree bit for bit.
+// ---------------------------------------------------------------------------
+
+// |row| of every row of a [m][d] matrix, one wave per row.
+__global__ __launch_bounds__(64) void row_norm_kernel(const float *__restrict__ a, int32_t d, float *__restrict__ nrm) {
+    const int64_t i = blockIdx.x;
+    float s = 0.0f;
+    for (int32_t j = threadIdx.x; j < d; j += kWave) s = fmaf(a[i * d + j], a[i * d + j], s);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) nrm[i] = sqrtf(s);
+}
+
+// M: the largest |c| + r over the stored tiles, rounded up by 2^-20 (float
+// bits of a non-negative value order like the value).
+__global__ __launch_bounds__(256) void ip_max_norm_kernel(const float *__restrict__ cn,
+                                                          const int32_t *__restrict__ group_bucket,
+                                                          const float *__restrict__ tile_rad, int32_t ngroups,
+                                                          uint32_t *__restrict__ mbits) {
+    float m = 0.0f;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * (int64_t)ngroups;
+         t += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, (cn[group_bucket[t >> 1]] + tile_rad[t]) * (1.0f + 0x1p-20f));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(mbits, __float_as_uint(m));
+}
+
+// Per query: |q| and B_q, the power of two at or above |q| M (1 + 2^-10)
+// (a power of two keeps B_q - q.x exact wherever q.x is, e.g. on integer
+// data, and then s' - B_q gives back -q.x exactly).
+__global__ __launch_bounds__(64) void ip_query_kernel(const float *__restrict__ q, int32_t d,
+                                                      const uint32_t *__restrict__ mbits, float *__restrict__ qn,
+                                                      float *__restrict__ qshift) {
+    const int64_t qi = blockIdx.x;
+    float s = 0.0f;
+    for (int32_t j = threadIdx.x; j < d; j += kWave) s = fmaf(q[qi * d + j], q[qi * d + j], s);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) {
+        const float n = sqrtf(s) * (1.0f + 0x1p-20f);
+        qn[qi] = n;
+        int e = 0;
+        (void)frexpf(n * __uint_as_float(*mbits) * (1.0f + 0x1p-10f), &e);
+        qshift[qi] = ldexpf(1.0f, e);
+    }
+}
+
+// From cd[q][l] = q.c_l: cd[q][l] becomes B_q - q.c_l (>= 0; its minimum is
+// the START bucket), and dql[l][q] = B_q - q.c_l - margin, bucket-major: a
+// lower bound of s' over the bucket's rows before the |q| r term.  margin
+// covers the float32 rounding of q.c ((D + 8) 2^-24 |q| |c|), of the fixed-
+// order q.x ((10 + D/32) 2^-24 |q| M) and of s' itself (2^-23 B_q), twice.
+__global__ __launch_bounds__(256) void ip_bound_kernel(float *__restrict__ cd, int64_t nq, int32_t nlist, int32_t d,
+                                                       const float *__restrict__ qn,
+                                                       const float *__restrict__ qshift,
+                                                       const float *__restrict__ cn,
+                                                       const uint32_t *__restrict__ mbits,
+                                                       float *__restrict__ dql) {
+    __shared__ float blk[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int64_t q0 = (int64_t)blockIdx.x * 32;
+    const int32_t l0 = blockIdx.y * 32;
+    const float m = __uint_as_float(*mbits);
+    const float rel = (float)(d + 64) * 0x1p-23f;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t q = q0 + r;
+        const int32_t l = l0 + tx;
+        float v = 0.0f;
+        if (q < nq && l < nlist) {
+            const float sp = qshift[q] - cd[q * nlist + l];
+            cd[q * nlist + l] = fmaxf(sp, 0.0f);
+            v = sp - (rel * qn[q] * (cn[l] + m) + 0x1p-22f * qshift[q]);
+        }
+        blk[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int32_t l = l0 + r;
+        const int64_t q = q0 + tx;
+        if (q < nq && l < nlist) dql[(int64_t)l * nq + q] = blk[tx][r];
+    }
+}
+
+// One wave scans vectorgroups [g0, g1) for query qi (natural order q row
+// qrow): s' = B - q.x per row, k-best list to myslot.
+__device__ __forceinline__ void ip_groups(const float *__restrict__ pdxd, const int32_t *__restrict__ slot_id,
+                                          int32_t d, int32_t g0, int32_t g1, const float *__restrict__ qrow,
+                                          float shift, uint64_t *__restrict__ myslot, int32_t k) {
+    const int lane = threadIdx.x & 63;
+    uint64_t e = kEmptyKey, kth = kEmptyKey;
+    for (int32_t g = g0; g < g1; ++g) {
+        const int32_t rid = slot_id[(int64_t)g * kGroup + lane];
+        const float *gp = pdxd + (int64_t)g * d * kGroup + lane;
+        float dot = 0.0f;
+        for (int32_t c0 = 0; c0 < d; c0 += 32) {
+            float o[4];
+#pragma unroll
+            for (int gg = 0; gg < 4; ++gg) {
+                o[gg] = 0.0f;
+#pragma unroll
+                for (int u = 8 * gg; u < 8 * gg + 8; ++u)
+                    o[gg] = fmaf(qrow[c0 + u], gp[(int64_t)(c0 + u) * kGroup], o[gg]);
+            }
+            dot += octets(o[0], o[1], o[2], o[3]);
+        }
+        topk_offer(e, kth, make_key(shift - dot, static_cast<uint32_t>(rid)), rid >= 0, k, lane);
+    }
+    if (lane < k) myslot[lane] = e;
+}
+
+// START for the inner product: the first maxg vectorgroups of the bucket
+// with the largest q.c; `parts` waves per query, each its own k-best list.
+__global__ __launch_bounds__(256) void ip_start_kernel(const float *__restrict__ pdxd,
+                                                       const int32_t *__restrict__ slot_id, int32_t d,
+                                                       const int32_t *__restrict__ goff,
+                                                       const int32_t *__restrict__ nearest, int64_t nq, int32_t parts,
+                                                       int32_t maxg, const float *__restrict__ q,
+                                                       const float *__restrict__ qshift,
+                                                       const int32_t *__restrict__ bad, uint64_t *__restrict__ slots,
+                                                       int32_t k) {
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t qi = w / parts;
+    const int32_t part = (int32_t)(w - qi * parts);
+    const int lane = threadIdx.x & 63;
+    if (qi >= nq) return;
+    uint64_t *myslot = slots + ((size_t)qi * parts + part) * k;
+    if (bad[qi]) {
+        if (lane < k) myslot[lane] = kEmptyKey;
+        return;
+    }
+    const int32_t l = nearest[qi];
+    const int32_t a = goff[l], len = min(goff[l + 1] - a, maxg);
+    const int32_t g0 = a + (int32_t)((int64_t)len * part / parts), g1 = a + (int32_t)((int64_t)len * (part + 1) / parts);
+    ip_groups(pdxd, slot_id, d, g0, g1, q + qi * d, qshift[qi], myslot, k);
+}
+
+// Overflowed queries: every (listed query, group tile) pair in full.
+__global__ __launch_bounds__(256) void ip_fallback_kernel(const float *__restrict__ pdxd,
+                                                          const int32_t *__restrict__ slot_id, int32_t d,
+                                                          int32_t g_end, int32_t tile_groups, int32_t ntiles,
+                                                          const int32_t *__restrict__ over_list,
+                                                          const int32_t *__restrict__ over_count,
+                                                          const float *__restrict__ q,
+                                                          const float *__restrict__ qshift,
+                                                          uint64_t *__restrict__ slots, int32_t nslots, int32_t k) {
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t total = (int64_t)(*over_count) * ntiles;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < total; it += (int64_t)gridDim.x * 4) {
+        const int64_t qi = over_list[it / ntiles];
+        const int32_t tile = (int32_t)(it % ntiles);
+        const int32_t g0 = tile * tile_groups;
+        const int32_t g1 = min(g0 + tile_groups, g_end);
+        ip_groups(pdxd, slot_id, d, g0, g1, q + qi * d, qshift[qi], slots + ((size_t)qi * nslots + tile) * k, k);
+    }
+}
+
+// One octet of a chunk (8 consecutive dimensions from j) for the tile's
+// vectors p and p + 16: q.x terms.
+__device__ __forceinline__ void octet_pair_ip(const float *__restrict__ tile, int32_t j, float4 q0, float4 q1, int p,
+                                              float &a, float &b) {
+    const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    a = 0.0f;
+    b = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float *r = tile + (j + u) * kTV + p;
+        a = fmaf(qv[u], r[0], a);
+        b = fmaf(qv[u], r[16], b);
+    }
+}
+
+// Tile kernel for the inner product: tiles staged as in tile_kernel; per
+// tile the queries whose bound B_q - q.c - margin - |q| r is not above
+// their threshold are listed, and each listed query's wave forms q.x for
+// the 32 vectors over all chunks (lanes = 16 vector pairs x 4 octets, the
+// next chunk's query values prefetched), appending rows with s' within the
+// threshold.
+__global__ __launch_bounds__(1024) void ip_tile_kernel(
+    const float *__restrict__ pdxd, const int32_t *__restrict__ slot_id, int32_t d, int32_t t_begin, int32_t t_end,
+    int64_t nq, const float *__restrict__ q, const float *__restrict__ qn, const float *__restrict__ qshift,
+    const uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ cand,
+    int32_t *__restrict__ cand_cnt, int32_t cap, const float *__restrict__ dql,
+    const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad,
+    unsigned long long *__restrict__ counters) {
+    extern __shared__ float4 smem4[];
+    float *tile = reinterpret_cast<float *>(smem4);  // [d][32]
+    __shared__ int32_t lcount;
+    __shared__ int32_t qlist[kList];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int pr = lane & 15, oct = lane >> 4;
+    const int32_t nchunks = d / 32;
+    unsigned long long live_vals = 0, lane_vals = 0;
+    for (int32_t t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
+        const float *src = pdxd + (int64_t)(t >> 1) * d * kGroup + (t & 1) * kTV;
+        const int32_t nv4 = d * 8;
+        for (int32_t iw = wave * 64; iw < nv4; iw += 1024) {
+            const int32_t i = iw + lane;
+            __builtin_amdgcn_global_load_lds(src + (int64_t)(i >> 3) * kGroup + (i & 7) * 4,
+                                             (lds_void_t *)(tile + (size_t)iw * 4), 16, 0, 0);
+        }
+        __syncthreads();
+        const int64_t vid_a = (int64_t)t * kTV + pr, vid_b = vid_a + 16;
+        const int32_t rid_a = slot_id[vid_a], rid_b = slot_id[vid_b];
+        const uint32_t valid_m = pair_mask(rid_a >= 0, rid_b >= 0);
+        const int32_t tb = group_bucket[t >> 1];
+        const float trad = tile_rad[t];
+        for (int64_t q0 = 0; q0 < nq; q0 += kList) {
+            __syncthreads();  // the previous list is no longer read
+            if (threadIdx.x == 0) lcount = 0;
+            __syncthreads();
+            const int64_t qt = q0 + threadIdx.x;
+            bool keep = false;
+            if (threadIdx.x < kList && qt < nq && !bad[qt] && valid_m) {
+                const float lb = dql[(int64_t)tb * nq + qt] - qn[qt] * trad;
+                const float tq =
+                    __uint_as_float(__hip_atomic_load(tau + qt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                keep = !(lb > tq);
+            }
+            const unsigned long long km = __ballot(keep);
+            int lb0 = 0;
+            if (lane == 0 && km) lb0 = atomicAdd(&lcount, __popcll(km));
+            lb0 = __shfl(lb0, 0);
+            if (keep) qlist[lb0 + lane_rank(km)] = (int32_t)qt;
+            __syncthreads();
+            const int32_t cnt = lcount;
+            for (int32_t e = wave; e < cnt; e += kTW) {
+                const int64_t qi = qlist[e];
+                const float *qr = q + qi * d + oct * 8;
+                float4 qn0 = *reinterpret_cast<const float4 *>(qr);
+                float4 qn1 = *reinterpret_cast<const float4 *>(qr + 4);
+                float xa = 0.0f, xb = 0.0f;
+                for (int32_t c = 0; c < nchunks; ++c) {
+                    const float4 qc0 = qn0, qc1 = qn1;
+                    if (c + 1 < nchunks) {
+                        qn0 = *reinterpret_cast<const float4 *>(qr + (c + 1) * 32);
+                        qn1 = *reinterpret_cast<const float4 *>(qr + (c + 1) * 32 + 4);
+                    }
+                    float sa, sb;
+                    octet_pair_ip(tile, c * 32 + oct * 8, qc0, qc1, pr, sa, sb);
+                    xa += octet_total(sa);
+                    xb += octet_total(sb);
+                }
+                if (counters) {
+                    live_vals += (unsigned long long)d * __popc(valid_m);
+                    lane_vals += 32ull * d;
+                }
+                const float tq = __uint_as_float(tau[qi]);
+                const float sh = qshift[qi];
+                const float sa = sh - xa, sb = sh - xb;
+                if (oct == 0 && rid_a >= 0 && !(sa > tq)) cand_append(cand, cand_cnt, cap, qi, sa, (uint32_t)rid_a);
+                if (oct == 0 && rid_b >= 0 && !(sb > tq)) cand_append(cand, cand_cnt, cap, qi, sb, (uint32_t)rid_b);
+            }
+        }
+        __syncthreads();
+    }
+    if (counters && lane == 0) {
+        atomicAdd(counters, live_vals);
+        atomicAdd(counters + 1, lane_vals);
+    }
 }
 
 }  // namespace
@@ -936,33 +1225,42 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.bad = c.take<int32_t>(q);
     pl.perm = c.take<int32_t>(q * ix->d);
     pl.qperm = c.take<float>(q * ix->d);
-    pl.slots = pl.metric == PDX_METRIC_IP ? nullptr : c.take<uint64_t>(q * pl.nslots * k);
+    const bool ip_tiles = pl.metric == PDX_METRIC_IP && pl.use_tiles;
+    pl.slots = (pl.metric == PDX_METRIC_IP && !ip_tiles) ? nullptr : c.take<uint64_t>(q * pl.nslots * k);
     if (pl.ivf) {
         // START: the first start_rows rows (whole vectorgroups) of the
         // nearest bucket; waves per query about 8 per SIMD in all, at most
         // one per vectorgroup
-        const int32_t sr = (p && p->start_rows > 0) ? p->start_rows : 128;
+        const int32_t sr = (p && p->start_rows > 0) ? p->start_rows : (pl.metric == PDX_METRIC_IP ? 1024 : 128);
         pl.start_maxg = (int32_t)std::min<int64_t>(((int64_t)sr + kGroup - 1) / kGroup, ix->ngroups);
         int32_t sp = 1;
         while (sp < 16 && sp < pl.start_maxg && (int64_t)sp * nq < 8 * 4 * (int64_t)device_cus()) sp <<= 1;
         pl.start_parts = sp;
         pl.qrot = ix->has_rot ? c.take<float>(q * ix->d) : nullptr;
-        pl.cd = pl.mode == PDX_MODE_BOND ? c.take<float>(q * ix->nlist) : nullptr;
-        pl.dql = pl.mode == PDX_MODE_BOND ? c.take<float>(q * ix->nlist) : nullptr;
-        pl.nearest = pl.mode == PDX_MODE_BOND ? c.take<int32_t>(q) : nullptr;
-        pl.start_slots = pl.mode == PDX_MODE_BOND ? c.take<uint64_t>(q * pl.start_parts * k) : nullptr;
+        const bool bstart = pl.mode == PDX_MODE_BOND || ip_tiles;  // START on the nearest bucket
+        pl.cd = bstart ? c.take<float>(q * ix->nlist) : nullptr;
+        pl.dql = bstart ? c.take<float>(q * ix->nlist) : nullptr;
+        pl.nearest = bstart ? c.take<int32_t>(q) : nullptr;
+        pl.start_slots = bstart ? c.take<uint64_t>(q * pl.start_parts * k) : nullptr;
+        if (ip_tiles) {
+            pl.qn = c.take<float>(q);
+            pl.qshift = c.take<float>(q);
+            pl.cn = c.take<float>(ix->nlist);
+            pl.mbits = c.take<uint32_t>(64);
+        }
     }
     if (pl.use_tiles) {
-        pl.poff = c.take<uint16_t>(q * ix->d);
+        pl.poff = ip_tiles ? nullptr : c.take<uint16_t>(q * ix->d);
         const int32_t cus = device_cus();
         pl.tile_grid = cus;  // one workgroup per compute unit (the LDS tile fills the CU)
         pl.gqueue = c.take<uint64_t>((size_t)cus * kGCap);
-        pl.cand = c.take<uint64_t>(q * kCandCap);
+        pl.cand_cap = ip_tiles ? kCandCapIp : kCandCap;
+        pl.cand = c.take<uint64_t>(q * pl.cand_cap);
         pl.cand_cnt = c.take<int32_t>(q);
         pl.over_list = c.take<int32_t>(q);
         pl.over_count = c.take<int32_t>(64);
     }
-    if (pl.metric == PDX_METRIC_IP) {
+    if (pl.metric == PDX_METRIC_IP && !ip_tiles) {
         pl.ip_parts = ip_parts_for(nq, ix->ngroups);
         pl.ip_slots = c.take<uint64_t>(q * pl.ip_parts * k);
     }
@@ -970,6 +1268,73 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.counters = p ? p->counters : nullptr;
     if (plan) *plan = pl;
     return c.bytes();
+}
+
+// Inner product on the bucket layout: bound inputs, START on the bucket with
+// the largest q.c, rounds of tiles with the threshold refreshed in between,
+// the full scan for overflowed queries, and the k best with the shift undone.
+template <typename Mark>
+hipError_t run_ip_tiles(const pdx_index *ix, const float *qs, const ExactPlan &pl, int64_t *out_ids,
+                        float *out_dist, hipStream_t s, Mark &mark) {
+    const int32_t d = ix->d;
+    const unsigned nqu = (unsigned)pl.nq;
+    hipError_t err;
+    row_norm_kernel<<<(unsigned)ix->nlist, 64, 0, s>>>(ix->centroids, d, pl.cn);
+    if ((err = launch_fill_i32(reinterpret_cast<int32_t *>(pl.mbits), 1, 0, s)) != hipSuccess) return err;
+    ip_max_norm_kernel<<<256, 256, 0, s>>>(pl.cn, ix->group_bucket, ix->tile_rad, ix->ngroups, pl.mbits);
+    ip_query_kernel<<<nqu, 64, 0, s>>>(qs, d, pl.mbits, pl.qn, pl.qshift);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = launch_pair(0, 0, qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) != hipSuccess)
+        return err;
+    ip_bound_kernel<<<dim3((unsigned)((pl.nq + 31) / 32), (unsigned)((ix->nlist + 31) / 32)), 256, 0, s>>>(
+        pl.cd, pl.nq, ix->nlist, d, pl.qn, pl.qshift, pl.cn, pl.mbits, pl.dql);
+    nearest_kernel<<<nqu, 64, 0, s>>>(pl.cd, ix->nlist, pl.nearest);
+    const int64_t waves = pl.nq * pl.start_parts;
+    ip_start_kernel<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(ix->pdx, ix->slot_id, d, ix->list_goff, pl.nearest,
+                                                                pl.nq, pl.start_parts, pl.start_maxg, qs, pl.qshift,
+                                                                pl.bad, pl.start_slots, pl.k);
+    merge_kernel<<<nqu, 64, 0, s>>>(pl.start_slots, pl.start_parts, 0, pl.start_parts, pl.k, pl.bad, pl.tau, nullptr,
+                                    nullptr, nullptr, nullptr, 0);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = launch_fill_i32(pl.cand_cnt, pl.nq, 0, s)) != hipSuccess) return err;
+    if ((err = mark(1)) != hipSuccess) return err;
+    const size_t lds = (size_t)d * kTV * sizeof(float);
+    if (lds > 64 * 1024 &&
+        (err = hipFuncSetAttribute(reinterpret_cast<const void *>(ip_tile_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+        return err;
+    unsigned long long *cmain = pl.counters ? pl.counters + 2 : nullptr;
+    // rounds of at most cap - k rows each: with the buffer compacted to its k
+    // best between rounds no buffer can overflow (the full scan stays as the
+    // guard)
+    const int32_t t1 = 2 * ix->ngroups;
+    const int64_t tiles_per_round = std::max<int64_t>(1, (pl.cand_cap - pl.k) / kTV);
+    const int32_t rounds = (int32_t)std::max<int64_t>(kRoundsIp, (t1 + tiles_per_round - 1) / tiles_per_round);
+    for (int32_t r = 0; r < rounds; ++r) {
+        const int32_t a = (int32_t)((int64_t)t1 * r / rounds), b = (int32_t)((int64_t)t1 * (r + 1) / rounds);
+        if (b <= a) continue;
+        const unsigned grid = (unsigned)min(b - a, pl.tile_grid);
+        ip_tile_kernel<<<grid, 1024, lds, s>>>(ix->pdx, ix->slot_id, d, a, b, pl.nq, qs, pl.qn, pl.qshift, pl.tau,
+                                               pl.bad, pl.cand, pl.cand_cnt, pl.cand_cap, pl.dql, ix->group_bucket,
+                                               ix->tile_rad, cmain);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (r + 1 < rounds) {
+            cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, pl.cand_cap, 0, pl.k, pl.bad, pl.tau, nullptr, 0,
+                                                 0, 0, nullptr, nullptr, nullptr, 1);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
+    }
+    if ((err = launch_fill_i32(pl.over_count, 1, 0, s)) != hipSuccess) return err;
+    over_list_kernel<<<(nqu + 255) / 256, 256, 0, s>>>(pl.cand_cnt, pl.nq, pl.cand_cap, pl.over_list, pl.over_count);
+    ip_fallback_kernel<<<2048, 256, 0, s>>>(ix->pdx, ix->slot_id, d, ix->ngroups, pl.tile_groups, pl.tiles_main,
+                                            pl.over_list, pl.over_count, qs, pl.qshift, pl.slots, pl.nslots, pl.k);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = mark(2)) != hipSuccess) return err;
+    // an overflowed query keeps nothing of its buffer: the full scan covers every row
+    cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, pl.cand_cap, 0, pl.k, pl.bad, pl.tau, pl.slots, pl.nslots,
+                                         0, pl.tiles_main, out_ids, out_dist, pl.qshift, 0);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    return mark(3);
 }
 
 hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, int64_t *out_ids,
@@ -989,6 +1354,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     prep_kernel<<<dim3((unsigned)pl.nq), dim3(256), lds, s>>>(qs, d, ix->means, pl.mode, pow2, pl.perm,
                                                               pl.qperm, pl.tau, pl.bad, pl.use_tiles ? pl.poff : nullptr);
     if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (pl.metric == PDX_METRIC_IP && pl.use_tiles) return run_ip_tiles(ix, qs, pl, out_ids, out_dist, s, mark);
     if (pl.metric == PDX_METRIC_IP) {  // linear inner-product scan on the matrix cores
         if ((err = mark(1)) != hipSuccess) return err;
         if ((err = launch_ip_scan(ix, qs, pl.nq, pl.bad, pl.ip_parts, pl.ip_slots, pl.k, s)) != hipSuccess)
@@ -1048,7 +1414,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         // its k-th distance becomes the initial threshold.
         if ((err = scan(false, 0, pl.start_groups, pl.tiles_start, 0, pl.counters)) != hipSuccess) return err;
         merge_kernel<<<nqu, 64, 0, s>>>(pl.slots, pl.nslots, 0, pl.tiles_start, pl.k, pl.bad, pl.tau, nullptr,
-                                        nullptr, pl.use_tiles ? pl.cand : nullptr, pl.cand_cnt, kCandCap);
+                                        nullptr, pl.use_tiles ? pl.cand : nullptr, pl.cand_cnt, pl.cand_cap);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     if ((err = mark(1)) != hipSuccess) return err;
@@ -1088,7 +1454,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         const unsigned grid = (unsigned)min(b - a, cus);
 #define PDX_TILE(DN, M)                                                                                              \
     tile_kernel<DN, M><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm, pl.tau, \
-                                                    pl.bad, pl.cand, pl.cand_cnt, kCandCap, pl.gqueue, cmain,       \
+                                                    pl.bad, pl.cand, pl.cand_cnt, pl.cand_cap, pl.gqueue, cmain,       \
                                                     DN ? pl.dql : nullptr, DN ? ix->group_bucket : nullptr, trad)
         if (pl.ivf) {
             if (l1) PDX_TILE(true, true);
@@ -1100,14 +1466,14 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
 #undef PDX_TILE
         if ((err = hipGetLastError()) != hipSuccess) return err;
         if (r + 1 < kRounds) {
-            cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, 0, pl.k, pl.bad, pl.tau, nullptr, 0,
-                                                 0, 0, nullptr, nullptr);
+            cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, pl.cand_cap, 0, pl.k, pl.bad, pl.tau, nullptr, 0,
+                                                 0, 0, nullptr, nullptr, nullptr, pl.ivf ? 1 : 0);
             if ((err = hipGetLastError()) != hipSuccess) return err;
         }
     }
     // queries whose buffer overflowed: group path over the main range
     if ((err = launch_fill_i32(pl.over_count, 1, 0, s)) != hipSuccess) return err;
-    over_list_kernel<<<(nqu + 255) / 256, 256, 0, s>>>(pl.cand_cnt, pl.nq, kCandCap, pl.over_list, pl.over_count);
+    over_list_kernel<<<(nqu + 255) / 256, 256, 0, s>>>(pl.cand_cnt, pl.nq, pl.cand_cap, pl.over_list, pl.over_count);
     if (l1)
         fallback_kernel<true><<<2048, 256, 0, s>>>(ix->pdx, ix->n, sid, d, pl.start_groups, ix->ngroups,
                                                    pl.tile_groups, pl.tiles_main, pl.over_list, pl.over_count,
@@ -1124,8 +1490,8 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     // before the main range); on the bucket layout START's rows lie inside
     // the main range and the fallback finds them again, so nothing is kept
     const int32_t head = pl.ivf ? 0 : pl.k;
-    cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, kCandCap, head, pl.k, pl.bad, pl.tau, pl.slots,
-                                         pl.nslots, pl.tiles_start, pl.tiles_main, out_ids, out_dist);
+    cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, pl.cand_cap, head, pl.k, pl.bad, pl.tau, pl.slots,
+                                         pl.nslots, pl.tiles_start, pl.tiles_main, out_ids, out_dist, nullptr, 0);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     return mark(3);
 }

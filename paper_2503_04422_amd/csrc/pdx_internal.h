@@ -107,10 +107,15 @@ struct ExactPlan {
     int32_t *over_list;    // [nq] queries whose candidates overflowed
     int32_t *over_count;
     int32_t tile_grid;     // tile-path workgroups per launch
+    int32_t cand_cap;      // tile path: candidate buffer entries per query
     uint64_t *gqueue;      // [tile_grid][overflow cap] survivor entries
     float *qrot;           // bucket layout, rotated: [nq][d] rotated queries
     float *cd;             // bucket layout: [nq][nlist] centroid distances
     float *dql;            // bucket layout: [nlist][nq] |q - c| lowered (centroid bound)
+    float *qn;             // inner product, tile path: [nq] |q| (rounded up)
+    float *qshift;         // inner product, tile path: [nq] B_q, the score shift
+    float *cn;             // inner product, tile path: [nlist] |c|
+    uint32_t *mbits;       // inner product, tile path: bits of M >= every |x|
     int32_t *nearest;      // bucket layout: [nq] START bucket
     uint64_t *start_slots; // bucket layout: [nq][start_parts][k] START lists
     hipEvent_t *events;              // optional [4]

@@ -161,3 +161,41 @@ def test_l1_tile_path(pdx, layout, d):
     gi, gd = (_np(t) for t in pdx.pdx_search_exact(iz, _dev(qz), 10, mode="bond", metric="l1"))
     wi, wd = exact.knn_exact(z, qz, 10, metric="l1")
     check_knn_metric(z, qz, gi, gd, wi, wd, "l1", exact=True)
+
+
+@pytest.mark.parametrize("d", [128, 960])
+def test_inner_product_tile_path(pdx, d):
+    """Inner product on the bucket layout with D a multiple of 32 (the tile
+    path with the Cauchy-Schwarz tile bound): real inputs, rotated and
+    unrotated, under the 1e-5 |q| max|v| rule; integer inputs bit for bit;
+    a tie-heavy case whose candidate buffers overflow (the full-scan
+    fallback); k above the bucket sizes."""
+    x, q, _ = synth.workload("bond_1m_d960", n=12_000, nq=20)
+    x, q = x[:, :d].copy(), q[:, :d].copy()
+    for gauss in (None, np.random.default_rng(d).standard_normal((d, d))):
+        print(f"ip tile path d={d} rotated={gauss is not None}", flush=True)
+        ix = _buckets(pdx, x, 24, d, gaussian=gauss)
+        gi, gd = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10, mode="linear", metric="ip"))
+        wi, wd = exact.knn_exact(x, q, 10, metric="ip")
+        check_knn_metric(x, q, gi, gd, wi, wd, "ip")
+    xi, qi = synth.integer_grid(5000, d, 12, lo=-4, hi=4, seed=d)
+    qi[3] = xi[17]
+    ixi = _buckets(pdx, xi, 16, 7)
+    print(f"ip tile path integer d={d}", flush=True)
+    gi, gd = (_np(t) for t in pdx.pdx_search_exact(ixi, _dev(qi), 10, mode="linear", metric="ip"))
+    wi, wd = exact.knn_exact(xi, qi, 10, metric="ip")
+    check_knn_metric(xi, qi, gi, gd, wi, wd, "ip", exact=True)
+    z = np.zeros((12_000, d), dtype=np.float32)
+    z[::2, 5] = 1.0  # 6,000 rows tie for the best score: more than a candidate buffer holds
+    qz = np.zeros((5, d), dtype=np.float32)
+    qz[:, 5] = 1.0
+    iz = _buckets(pdx, z, 6, 3)
+    print(f"ip tile path overflow d={d}", flush=True)
+    gi, gd = (_np(t) for t in pdx.pdx_search_exact(iz, _dev(qz), 10, mode="linear", metric="ip"))
+    wi, wd = exact.knn_exact(z, qz, 10, metric="ip")
+    check_knn_metric(z, qz, gi, gd, wi, wd, "ip", exact=True)
+    x2, q2 = synth.integer_grid(40, 32 if d == 128 else 64, 3, seed=9)
+    ix2 = _buckets(pdx, x2, 3, 2)
+    gi, gd = (_np(t) for t in pdx.pdx_search_exact(ix2, _dev(q2), 50, mode="linear", metric="ip"))
+    wi, wd = exact.knn_exact(x2, q2, 50, metric="ip")
+    check_knn_metric(x2, q2, gi, gd, wi, wd, "ip", exact=True)
