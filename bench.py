@@ -277,10 +277,14 @@ def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d, layout="buckets
             flops = 2.0 * c[2]
             achieved = flops / (ph[1] * 1e-3) / 1e12
             row["values_evaluated"] = {"scan": c[2], "of_all": round(c[2] / (nq * n * d), 5)}
+            # 16 launches per search at this size (rounds no larger than the candidate buffer)
+            traffic, src = profiled_traffic("ip_tile_bond_1m_d960_buckets.md") if (n, d, k, nq) == \
+                (1_000_000, 960, 10, 1000) else (None, "not profiled for this workload")
             row["roofline"] = {"bound": "alu", "kernel": "ip_tile_kernel (tile bound, LDS tiles)",
                                "achieved": round(achieved, 3), "peak": FMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                               "frac": round(achieved / FMA_PEAK_TFLOPS, 4), "traffic": None,
-                               "traffic_source": "not profiled", "algorithmic_flops_per_step": flops,
+                               "frac": round(achieved / FMA_PEAK_TFLOPS, 4),
+                               "traffic": None if traffic is None else traffic * 16,
+                               "traffic_source": src, "algorithmic_flops_per_step": flops,
                                "scan_ms": round(ph[1], 4)}
         elif metric == "ip" and ph[1] > 0:
             flops = 2.0 * nq * n * d

@@ -867,7 +867,7 @@ int32_t next_pow2(int32_t v) {
 }
 
 constexpr int32_t kCandCap = 2048;     // candidates per query in the tile path
-constexpr int32_t kCandCapIp = 65536;  // the same for the inner product (looser START threshold)
+constexpr int32_t kCandCapIp = 65536;  // the inner product's largest (looser START threshold)
 constexpr int32_t kRounds = 4;      // threshold refreshes in the tile path
 constexpr int32_t kRoundsIp = 16;   // the same for the inner product (its START threshold is looser)
 
@@ -1254,7 +1254,12 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
         const int32_t cus = device_cus();
         pl.tile_grid = cus;  // one workgroup per compute unit (the LDS tile fills the CU)
         pl.gqueue = c.take<uint64_t>((size_t)cus * kGCap);
-        pl.cand_cap = ip_tiles ? kCandCapIp : kCandCap;
+        if (ip_tiles) {  // about 1 GiB of buffers at most; fewer entries mean more rounds
+            const int64_t fit = ((int64_t)1 << 30) / (int64_t)sizeof(uint64_t) / std::max<int64_t>(nq, 1);
+            pl.cand_cap = (int32_t)std::max<int64_t>(4096, std::min<int64_t>(kCandCapIp, fit / 64 * 64));
+        } else {
+            pl.cand_cap = kCandCap;
+        }
         pl.cand = c.take<uint64_t>(q * pl.cand_cap);
         pl.cand_cnt = c.take<int32_t>(q);
         pl.over_list = c.take<int32_t>(q);
