@@ -131,10 +131,8 @@ typedef struct {
                             nearest bucket (inner product: the bucket with
                             the largest q.c) that START scans, in whole
                             vectorgroups (Section 6.5 bounds the START
-                            block's size); 0 = 128 (1,024 for the inner
-                            product, whose START threshold is looser).  The
-                            flat index takes its START block from
-                            pdx_build_params. */
+                            block's size); 0 = 128.  The flat index takes
+                            its START block from pdx_build_params. */
 } pdx_search_params;
 
 /* Workspace bytes for pdx_search_exact with these arguments. */

@@ -869,7 +869,7 @@ int32_t next_pow2(int32_t v) {
 constexpr int32_t kCandCap = 2048;     // candidates per query in the tile path
 constexpr int32_t kCandCapIp = 65536;  // the inner product's largest (looser START threshold)
 constexpr int32_t kRounds = 4;      // threshold refreshes in the tile path
-constexpr int32_t kRoundsIp = 16;   // the same for the inner product (its START threshold is looser)
+constexpr int32_t kRoundsIp = 16;   // the inner product's least (rounds are also bounded by the buffer size)
 
 size_t tile_lds_bytes(int32_t d) { return (size_t)d * kTV * sizeof(float) + kQCap * sizeof(uint2); }
 
@@ -1231,7 +1231,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
         // START: the first start_rows rows (whole vectorgroups) of the
         // nearest bucket; waves per query about 8 per SIMD in all, at most
         // one per vectorgroup
-        const int32_t sr = (p && p->start_rows > 0) ? p->start_rows : (pl.metric == PDX_METRIC_IP ? 1024 : 128);
+        const int32_t sr = (p && p->start_rows > 0) ? p->start_rows : 128;
         pl.start_maxg = (int32_t)std::min<int64_t>(((int64_t)sr + kGroup - 1) / kGroup, ix->ngroups);
         int32_t sp = 1;
         while (sp < 16 && sp < pl.start_maxg && (int64_t)sp * nq < 8 * 4 * (int64_t)device_cus()) sp <<= 1;
@@ -1275,8 +1275,8 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     return c.bytes();
 }
 
-// Inner product on the bucket layout: bound inputs, START on the bucket with
-// the largest q.c, rounds of tiles with the threshold refreshed in between,
+// Inner product on the bucket layout: bound inputs, START on the first rows
+// of the bucket with the largest q.c, rounds of tiles with the threshold refreshed in between,
 // the full scan for overflowed queries, and the k best with the shift undone.
 template <typename Mark>
 hipError_t run_ip_tiles(const pdx_index *ix, const float *qs, const ExactPlan &pl, int64_t *out_ids,
