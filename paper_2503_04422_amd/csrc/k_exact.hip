@@ -888,7 +888,10 @@ bool tile_path(const pdx_index *ix, const ExactPlan &pl) {
     if (pl.metric == PDX_METRIC_IP)  // inner product: the bucket layout's tile bound
         return ix->kind == kIvf && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) && pl.tiles_main > 0 &&
                (size_t)ix->d * kTV * sizeof(float) <= max_dynamic_lds();
-    return pl.mode == PDX_MODE_BOND && (pl.metric == PDX_METRIC_L2 || pl.metric == PDX_METRIC_L1) && pl.chunk == 32 && ix->d * kTV < 65536 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
+    // L1 only on the bucket layout, where its centroid bound applies (on the
+    // flat layout the vectorgroup path is faster for it)
+    return pl.mode == PDX_MODE_BOND && (pl.metric == PDX_METRIC_L2 || (pl.metric == PDX_METRIC_L1 && pl.ivf)) &&
+           pl.chunk == 32 && ix->d * kTV < 65536 && ix->d % 32 == 0 && pl.nq < (int64_t(1) << 27) &&
            pl.tiles_main > 0 && tile_lds_bytes(ix->d) <= max_dynamic_lds();
 }
 

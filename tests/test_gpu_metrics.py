@@ -143,9 +143,11 @@ def test_inner_product_full_size_sampled(pdx):
 @pytest.mark.parametrize("layout", ["flat", "buckets"])
 @pytest.mark.parametrize("d", [128, 960])
 def test_l1_tile_path(pdx, layout, d):
-    """L1 with PDX-BOND on shapes the LDS-tile path takes (D a multiple of
-    32): real inputs under the relative 1e-5 rule, and a tie-heavy case
-    whose candidate buffers overflow (the L1 fallback path), bit for bit."""
+    """L1 with PDX-BOND at D a multiple of 32 (the bucket layout's LDS-tile
+    path with the L1 centroid bound; the flat layout's vectorgroup path):
+    real inputs under the relative 1e-5 rule, and a tie-heavy case whose
+    candidate buffers overflow on the bucket layout (the L1 fallback path),
+    bit for bit."""
     x, q, _ = synth.workload("bond_1m_d960", n=12_000, nq=20)
     x, q = x[:, :d].copy(), q[:, :d].copy()
     ix = pdx.pdx_build(_dev(x)) if layout == "flat" else _buckets(pdx, x, 24, d)
