@@ -628,11 +628,11 @@ __global__ __launch_bounds__(1024) void tile_kernel(
     const uint16_t *__restrict__ poff, const float *__restrict__ qperm, const uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, uint64_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int32_t cap,
     uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters, const float *__restrict__ dql,
-    const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad) {
+    const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad, int32_t *__restrict__ tile_ctr) {
     extern __shared__ float4 smem4[];
     float *tile = reinterpret_cast<float *>(smem4);                          // [d][32]
     uint2 *queue = reinterpret_cast<uint2 *>(tile + (size_t)d * kTV);        // [kQCap]
-    __shared__ int32_t qcount, qhead, lcount;
+    __shared__ int32_t qcount, qhead, lcount, next_t;
     __shared__ int32_t qlist[DENSE ? kList : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -642,7 +642,13 @@ __global__ __launch_bounds__(1024) void tile_kernel(
     uint64_t *gq = gqueue + (size_t)blockIdx.x * kGCap;  // this workgroup's overflow entries
     unsigned long long live_vals = 0, lane_vals = 0;
 
-    for (int32_t t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
+    // tiles are taken from a counter shared by the launch's workgroups, so
+    // workgroups that meet cheap tiles take more (tile costs vary widely)
+    for (;;) {
+        if (threadIdx.x == 0) next_t = t_begin + atomicAdd(tile_ctr, 1);
+        __syncthreads();  // every thread read the previous value before the last barrier of the loop
+        const int32_t t = next_t;
+        if (t >= t_end) break;
         // stage 32 vectors x d dimensions (one 128-byte half row per
         // dimension) with direct global-to-LDS loads: a wave's 64 lanes
         // bring 16 bytes each into 1 KB of contiguous LDS, 8 tile rows, with
@@ -1118,17 +1124,21 @@ __global__ __launch_bounds__(1024) void ip_tile_kernel(
     const uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, uint64_t *__restrict__ cand,
     int32_t *__restrict__ cand_cnt, int32_t cap, const float *__restrict__ dql,
     const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad,
-    unsigned long long *__restrict__ counters) {
+    unsigned long long *__restrict__ counters, int32_t *__restrict__ tile_ctr) {
     extern __shared__ float4 smem4[];
     float *tile = reinterpret_cast<float *>(smem4);  // [d][32]
-    __shared__ int32_t lcount;
+    __shared__ int32_t lcount, next_t;
     __shared__ int32_t qlist[kList];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int pr = lane & 15, oct = lane >> 4;
     const int32_t nchunks = d / 32;
     unsigned long long live_vals = 0, lane_vals = 0;
-    for (int32_t t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
+    for (;;) {  // tiles from the launch's shared counter, as in tile_kernel
+        if (threadIdx.x == 0) next_t = t_begin + atomicAdd(tile_ctr, 1);
+        __syncthreads();
+        const int32_t t = next_t;
+        if (t >= t_end) break;
         const float *src = pdxd + (int64_t)(t >> 1) * d * kGroup + (t & 1) * kTV;
         const int32_t nv4 = d * 8;
         for (int32_t iw = wave * 64; iw < nv4; iw += 1024) {
@@ -1257,6 +1267,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
         const int32_t cus = device_cus();
         pl.tile_grid = cus;  // one workgroup per compute unit (the LDS tile fills the CU)
         pl.gqueue = c.take<uint64_t>((size_t)cus * kGCap);
+        pl.tile_ctr = c.take<int32_t>(64);
         if (ip_tiles) {  // about 1 GiB of buffers at most; fewer entries mean more rounds
             const int64_t fit = ((int64_t)1 << 30) / (int64_t)sizeof(uint64_t) / std::max<int64_t>(nq, 1);
             pl.cand_cap = (int32_t)std::max<int64_t>(4096, std::min<int64_t>(kCandCapIp, fit / 64 * 64));
@@ -1322,9 +1333,10 @@ hipError_t run_ip_tiles(const pdx_index *ix, const float *qs, const ExactPlan &p
         const int32_t a = (int32_t)((int64_t)t1 * r / rounds), b = (int32_t)((int64_t)t1 * (r + 1) / rounds);
         if (b <= a) continue;
         const unsigned grid = (unsigned)min(b - a, pl.tile_grid);
+        if ((err = launch_fill_i32(pl.tile_ctr, 1, 0, s)) != hipSuccess) return err;
         ip_tile_kernel<<<grid, 1024, lds, s>>>(ix->pdx, ix->slot_id, d, a, b, pl.nq, qs, pl.qn, pl.qshift, pl.tau,
                                                pl.bad, pl.cand, pl.cand_cnt, pl.cand_cap, pl.dql, ix->group_bucket,
-                                               ix->tile_rad, cmain);
+                                               ix->tile_rad, cmain, pl.tile_ctr);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         if (r + 1 < rounds) {
             cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, pl.cand_cap, 0, pl.k, pl.bad, pl.tau, nullptr, 0,
@@ -1455,6 +1467,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     const int32_t t0 = 2 * pl.start_groups, t1 = 2 * ix->ngroups;
     const int cus = pl.tile_grid;
     const float *trad = pl.ivf ? (l1 ? ix->tile_rad1 : ix->tile_rad) : nullptr;
+    if ((err = launch_fill_i32(pl.tile_ctr, kRounds, 0, s)) != hipSuccess) return err;
     for (int32_t r = 0; r < kRounds; ++r) {
         const int32_t a = t0 + (int32_t)((int64_t)(t1 - t0) * r / kRounds);
         const int32_t b = t0 + (int32_t)((int64_t)(t1 - t0) * (r + 1) / kRounds);
@@ -1463,7 +1476,8 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
 #define PDX_TILE(DN, M)                                                                                              \
     tile_kernel<DN, M><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm, pl.tau, \
                                                     pl.bad, pl.cand, pl.cand_cnt, pl.cand_cap, pl.gqueue, cmain,       \
-                                                    DN ? pl.dql : nullptr, DN ? ix->group_bucket : nullptr, trad)
+                                                    DN ? pl.dql : nullptr, DN ? ix->group_bucket : nullptr, trad,   \
+                                                    pl.tile_ctr + r)
         if (pl.ivf) {
             if (l1) PDX_TILE(true, true);
             else PDX_TILE(true, false);

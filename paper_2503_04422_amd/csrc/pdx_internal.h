@@ -109,6 +109,7 @@ struct ExactPlan {
     int32_t tile_grid;     // tile-path workgroups per launch
     int32_t cand_cap;      // tile path: candidate buffer entries per query
     uint64_t *gqueue;      // [tile_grid][overflow cap] survivor entries
+    int32_t *tile_ctr;     // tile path: [64] next-tile counters, one per launch
     float *qrot;           // bucket layout, rotated: [nq][d] rotated queries
     float *cd;             // bucket layout: [nq][nlist] centroid distances
     float *dql;            // bucket layout: [nlist][nq] |q - c| lowered (centroid bound)
