@@ -293,6 +293,32 @@ __global__ __launch_bounds__(512) void scan_kernel(
     scan_groups<PRUNE, L1>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
 }
 
+// |row|^2 of every row of a [m][d] matrix, one wave per row.
+__global__ __launch_bounds__(64) void row_sq_kernel(const float *__restrict__ a, int32_t d, float *__restrict__ sq) {
+    const int64_t i = blockIdx.x;
+    float s = 0.0f;
+    for (int32_t j = threadIdx.x; j < d; j += kWave) s = fmaf(a[i * d + j], a[i * d + j], s);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) sq[i] = s;
+}
+
+// Squared centroid distances from the matrix-core products g[q][l] = q.c_l
+// (in place): |q|^2 + |c|^2 - 2 q.c lowered by 2 (D + 64) 2^-24
+// (|q|^2 + |c|^2), twice the float32 rounding of the expanded form, and
+// clamped at 0 -- a lower bound of |q - c|^2, which is all the centroid
+// bound and the START choice need.
+__global__ __launch_bounds__(256) void l2_from_dot_kernel(float *__restrict__ g, int64_t nq, int32_t nlist, int32_t d,
+                                                          const float *__restrict__ qsq,
+                                                          const float *__restrict__ csq) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq * nlist) return;
+    const int64_t q = i / nlist;
+    const int32_t l = (int32_t)(i - q * nlist);
+    const float nn = qsq[q] + csq[l];
+    g[i] = fmaxf(nn - 2.0f * g[i] - (float)(d + 64) * 0x1p-23f * nn, 0.0f);
+}
+
 // Nearest bucket of each query (distances [nq][nlist]; ties to the lower
 // bucket id), one wave per query.
 __global__ __launch_bounds__(64) void nearest_kernel(const float *__restrict__ cd, int32_t nlist,
@@ -1255,10 +1281,12 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
         pl.dql = bstart ? c.take<float>(q * ix->nlist) : nullptr;
         pl.nearest = bstart ? c.take<int32_t>(q) : nullptr;
         pl.start_slots = bstart ? c.take<uint64_t>(q * pl.start_parts * k) : nullptr;
-        if (ip_tiles) {
+        if (bstart) {  // norms: |q| and |c| (inner product) or their squares (L2 centroid distances)
             pl.qn = c.take<float>(q);
-            pl.qshift = c.take<float>(q);
             pl.cn = c.take<float>(ix->nlist);
+        }
+        if (ip_tiles) {
+            pl.qshift = c.take<float>(q);
             pl.mbits = c.take<uint32_t>(64);
         }
     }
@@ -1408,10 +1436,22 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     if (pl.ivf && pl.mode == PDX_MODE_BOND) {
         // START on the nearest bucket: its k-th distance is the initial
         // threshold (its rows are found again by the main scan)
-        // centroid distances in the search's metric (L2 squared, or L1)
-        if ((err = launch_pair(l1 ? 2 : 1, 0, qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr,
-                               s)) != hipSuccess)
-            return err;
+        // centroid distances in the search's metric: L1 on the vector ALU;
+        // L2 as a lower bound from matrix-core products (expanded form)
+        if (l1) {
+            if ((err = launch_pair(2, 0, qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) !=
+                hipSuccess)
+                return err;
+        } else {
+            row_sq_kernel<<<nqu, 64, 0, s>>>(qs, d, pl.qn);
+            row_sq_kernel<<<(unsigned)ix->nlist, 64, 0, s>>>(ix->centroids, d, pl.cn);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+            if ((err = launch_gemm_abt(qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, s)) != hipSuccess)
+                return err;
+            const int64_t pairs = pl.nq * ix->nlist;
+            l2_from_dot_kernel<<<(unsigned)((pairs + 255) / 256), 256, 0, s>>>(pl.cd, pl.nq, ix->nlist, d, pl.qn,
+                                                                               pl.cn);
+        }
         nearest_kernel<<<nqu, 64, 0, s>>>(pl.cd, ix->nlist, pl.nearest);
         centroid_lo_kernel<<<dim3((unsigned)((pl.nq + 31) / 32), (unsigned)((ix->nlist + 31) / 32)), 256, 0, s>>>(
             pl.cd, pl.nq, ix->nlist, pl.dql, l1 ? 1 : 0);

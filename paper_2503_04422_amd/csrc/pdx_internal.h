@@ -113,9 +113,9 @@ struct ExactPlan {
     float *qrot;           // bucket layout, rotated: [nq][d] rotated queries
     float *cd;             // bucket layout: [nq][nlist] centroid distances
     float *dql;            // bucket layout: [nlist][nq] |q - c| lowered (centroid bound)
-    float *qn;             // inner product, tile path: [nq] |q| (rounded up)
+    float *qn;             // bucket layout: [nq] |q| (inner product, rounded up) or |q|^2 (L2)
     float *qshift;         // inner product, tile path: [nq] B_q, the score shift
-    float *cn;             // inner product, tile path: [nlist] |c|
+    float *cn;             // bucket layout: [nlist] |c| (inner product) or |c|^2 (L2)
     uint32_t *mbits;       // inner product, tile path: bits of M >= every |x|
     int32_t *nearest;      // bucket layout: [nq] START bucket
     uint64_t *start_slots; // bucket layout: [nq][start_parts][k] START lists
