@@ -1018,7 +1018,8 @@ __global__ __launch_bounds__(64) void ip_query_kernel(const float *__restrict__ 
 // the START bucket), and dql[l][q] = B_q - q.c_l - margin, bucket-major: a
 // lower bound of s' over the bucket's rows before the |q| r term.  margin
 // covers the float32 rounding of q.c ((D + 8) 2^-24 |q| |c|), of the fixed-
-// order q.x ((10 + D/32) 2^-24 |q| M) and of s' itself (2^-23 B_q), twice.
+// order q.x ((10 + D/32) 2^-24 |q| M) and of s' itself (2^-23 B_q), twice
+// (q.c from the matrix cores: at most about (D + 16) 2^-24 |q| |c|).
 __global__ __launch_bounds__(256) void ip_bound_kernel(float *__restrict__ cd, int64_t nq, int32_t nlist, int32_t d,
                                                        const float *__restrict__ qn,
                                                        const float *__restrict__ qshift,
@@ -1331,8 +1332,8 @@ hipError_t run_ip_tiles(const pdx_index *ix, const float *qs, const ExactPlan &p
     ip_max_norm_kernel<<<256, 256, 0, s>>>(pl.cn, ix->group_bucket, ix->tile_rad, ix->ngroups, pl.mbits);
     ip_query_kernel<<<nqu, 64, 0, s>>>(qs, d, pl.mbits, pl.qn, pl.qshift);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    if ((err = launch_pair(0, 0, qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) != hipSuccess)
-        return err;
+    // q.c on the matrix cores (its rounding is within ip_bound_kernel's margin)
+    if ((err = launch_gemm_abt(qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, s)) != hipSuccess) return err;
     ip_bound_kernel<<<dim3((unsigned)((pl.nq + 31) / 32), (unsigned)((ix->nlist + 31) / 32)), 256, 0, s>>>(
         pl.cd, pl.nq, ix->nlist, d, pl.qn, pl.qshift, pl.cn, pl.mbits, pl.dql);
     nearest_kernel<<<nqu, 64, 0, s>>>(pl.cd, ix->nlist, pl.nearest);
