@@ -5,7 +5,8 @@ pdx_search_exact on an index built by pdx_ivf_build visits every vector
 (bucket by bucket, START on the query's nearest bucket), so its answer is
 the exact k-NN of all rows: integer inputs must match the oracle bit for
 bit (unrotated index), real inputs under the tie rule; a rotated index
-answers in rotated space.
+answers in rotated space.  More than 1,024 queries (two query lists per
+tile) for L2, L1 and the inner product.
 """
 import numpy as np
 import pytest
@@ -109,6 +110,26 @@ def test_bucket_layout_ties_overflow_and_edges(pdx):
     check_knn(x2, q2[keep], gi[keep], gd[keep], wi, wd, exact=True)
     ids, _ = pdx.pdx_search_exact(ix2, torch.empty((0, 32), device="cuda"), 5)
     assert ids.shape == (0, 5)
+
+
+@pytest.mark.parametrize("metric,mode", [("l2", "bond"), ("l1", "bond"), ("ip", "linear")])
+def test_more_queries_than_one_list(pdx, metric, mode):
+    """1,100 queries on the bucket layout's tile path: more than one
+    workgroup's query list holds (1,024), so every tile lists the queries
+    that its centroid bound keeps in two passes; each query against the
+    oracle."""
+    from tests.parity import check_knn_metric
+    x, q, _ = synth.workload("bond_1m_d960", n=12_000, nq=1100)
+    x, q = x[:, :64].copy(), q[:, :64].copy()
+    print(f"bucket layout 1,100 queries {metric} {mode}", flush=True)
+    ix = _bucket_index(pdx, x, 24, 13)
+    gi, gd = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10, mode=mode, metric=metric))
+    if metric == "l2":
+        wi, wd = exact.knn_exact_c(x, q, 10)
+        check_knn(x, q, gi, gd, wi, wd)
+    else:
+        wi, wd = exact.knn_exact(x, q, 10, metric=metric)
+        check_knn_metric(x, q, gi, gd, wi, wd, metric)
 
 
 def test_full_size_bucket_layout_sampled(pdx):
