@@ -4,6 +4,7 @@ against the FP64 oracle, through the C ABI.
 Sizes span several vectorgroups and wave tiles with ragged tails (n not a
 multiple of 64, D not a multiple of the chunk), plus the edge cases of the
 method: k = 1, k = 64, k > n, duplicates, a query equal to a row, nq = 0,
+D at 1,536 and at its limit 4,096 (no LDS tile),
 non-finite queries, and schedule-independence of the result.
 """
 import numpy as np
@@ -173,3 +174,31 @@ def test_tile_path_binary_ties(pdx):
     wi, wd = exact.knn_exact_c(x, q, 16)
     _, gi, gd = _search(pdx, x, q, 16, mode="bond", start_rows=1000)
     check_knn(x, q, gi, gd, wi, wd, exact=True)
+
+
+@pytest.mark.parametrize("d", [1536, 4096])
+def test_largest_dimensions(pdx, d):
+    """D above what one LDS tile holds (1,536) and at PDX_MAX_DIM (4,096):
+    both layouts take the vectorgroup path.  Per-dimension scales from 0.1
+    to 3 (so the PDX-BOND order matters) and queries near rows (so it
+    prunes); L2 linear and PDX-BOND, L1 PDX-BOND and the inner product
+    against the oracle, flat and bucket layouts."""
+    from tests.parity import check_knn_metric
+    rng = np.random.default_rng(d)
+    scale = np.linspace(0.1, 3.0, d)
+    x = (rng.standard_normal((3000, d)) * scale).astype(np.float32)
+    q = (x[rng.choice(3000, 6, replace=False)] + 0.3 * rng.standard_normal((6, d)) * scale).astype(np.float32)
+    init = rng.choice(3000, 8, replace=False).astype(np.int64)
+    indexes = (("flat", pdx.pdx_build(_dev(x))),
+               ("buckets", pdx.pdx_ivf_build(_dev(x), 8, None, _dev(init), kmeans_iters=3)))
+    wi, wd = exact.knn_exact_c(x, q, 10)
+    for name, ix in indexes:
+        for mode in ("linear", "bond"):
+            print(f"largest d={d} {name} l2 {mode}", flush=True)
+            ids, dist = pdx.pdx_search_exact(ix, _dev(q), 10, mode=mode)
+            check_knn(x, q, ids.cpu().numpy(), dist.cpu().numpy(), wi, wd)
+        for metric, mode in (("l1", "bond"), ("ip", "linear")):
+            print(f"largest d={d} {name} {metric} {mode}", flush=True)
+            ids, dist = pdx.pdx_search_exact(ix, _dev(q), 10, mode=mode, metric=metric)
+            mi, md = exact.knn_exact(x, q, 10, metric=metric)
+            check_knn_metric(x, q, ids.cpu().numpy(), dist.cpu().numpy(), mi, md, metric)
