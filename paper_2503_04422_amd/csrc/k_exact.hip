@@ -755,17 +755,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                     float xa = pa, xb = pb;
                     const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + oct * 8);
                     const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + oct * 8);
-                    uint4 on = o4[4];
-                    float4 qn0 = q4[8], qn1 = q4[9];
-                    for (int32_t c = 1; c < nchunks; ++c) {
-                        if (!__any(la || lb)) break;
-                        const uint4 oc = on;
-                        const float4 qc0 = qn0, qc1 = qn1;
-                        if (c + 1 < nchunks) {
-                            on = o4[4 * (c + 1)];
-                            qn0 = q4[8 * (c + 1)];
-                            qn1 = q4[8 * (c + 1) + 1];
-                        }
+                    auto dense_step = [&](const uint4 oc, const float4 qc0, const float4 qc1) {
                         float ta, tb2;
                         octet_pair<L1>(tile, oc, qc0, qc1, pr, ta, tb2);
                         xa += octet_total(ta);
@@ -776,6 +766,28 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                             live_vals += 32ull * __popc(pair_mask(la, lb));
                             lane_vals += 64ull * 16;
                         }
+                    };
+                    // two metadata sets in turn (chunks c and c + 1), so a
+                    // prefetched set is used where it landed, never copied
+                    uint4 oa = o4[4];
+                    float4 qa0 = q4[8], qa1 = q4[9];
+                    uint4 ob = oa;
+                    float4 qb0 = qa0, qb1 = qa1;
+                    for (int32_t c = 1; c < nchunks; c += 2) {
+                        if (!__any(la || lb)) break;
+                        if (c + 1 < nchunks) {
+                            ob = o4[4 * (c + 1)];
+                            qb0 = q4[8 * (c + 1)];
+                            qb1 = q4[8 * (c + 1) + 1];
+                        }
+                        dense_step(oa, qa0, qa1);
+                        if (c + 1 == nchunks || !__any(la || lb)) break;
+                        if (c + 2 < nchunks) {
+                            oa = o4[4 * (c + 2)];
+                            qa0 = q4[8 * (c + 2)];
+                            qa1 = q4[8 * (c + 2) + 1];
+                        }
+                        dense_step(ob, qb0, qb1);
                     }
                     if (oct == 0 && la) cand_append(cand, cand_cnt, cap, qi, xa, (uint32_t)rid_a);
                     if (oct == 0 && lb) cand_append(cand, cand_cnt, cap, qi, xb, (uint32_t)rid_b);
