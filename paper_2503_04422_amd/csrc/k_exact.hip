@@ -1213,19 +1213,30 @@ __global__ __launch_bounds__(1024) void ip_tile_kernel(
             for (int32_t e = wave; e < cnt; e += kTW) {
                 const int64_t qi = qlist[e];
                 const float *qr = q + qi * d + oct * 8;
-                float4 qn0 = *reinterpret_cast<const float4 *>(qr);
-                float4 qn1 = *reinterpret_cast<const float4 *>(qr + 4);
                 float xa = 0.0f, xb = 0.0f;
-                for (int32_t c = 0; c < nchunks; ++c) {
-                    const float4 qc0 = qn0, qc1 = qn1;
-                    if (c + 1 < nchunks) {
-                        qn0 = *reinterpret_cast<const float4 *>(qr + (c + 1) * 32);
-                        qn1 = *reinterpret_cast<const float4 *>(qr + (c + 1) * 32 + 4);
-                    }
+                auto ip_step = [&](int32_t c, const float4 qc0, const float4 qc1) {
                     float sa, sb;
                     octet_pair_ip(tile, c * 32 + oct * 8, qc0, qc1, pr, sa, sb);
                     xa += octet_total(sa);
                     xb += octet_total(sb);
+                };
+                // two query-value sets in turn (chunks c and c + 1), so a
+                // prefetched set is used where it landed, never copied
+                float4 qa0 = *reinterpret_cast<const float4 *>(qr);
+                float4 qa1 = *reinterpret_cast<const float4 *>(qr + 4);
+                float4 qb0 = qa0, qb1 = qa1;
+                for (int32_t c = 0; c < nchunks; c += 2) {
+                    if (c + 1 < nchunks) {
+                        qb0 = *reinterpret_cast<const float4 *>(qr + (c + 1) * 32);
+                        qb1 = *reinterpret_cast<const float4 *>(qr + (c + 1) * 32 + 4);
+                    }
+                    ip_step(c, qa0, qa1);
+                    if (c + 1 == nchunks) break;
+                    if (c + 2 < nchunks) {
+                        qa0 = *reinterpret_cast<const float4 *>(qr + (c + 2) * 32);
+                        qa1 = *reinterpret_cast<const float4 *>(qr + (c + 2) * 32 + 4);
+                    }
+                    ip_step(c + 1, qb0, qb1);
                 }
                 if (counters) {
                     live_vals += (unsigned long long)d * __popc(valid_m);
