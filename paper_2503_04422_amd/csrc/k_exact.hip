@@ -606,6 +606,20 @@ __device__ __forceinline__ float octet_total(float s) {
     return __uint_as_float(r2[0]) + __uint_as_float(r2[1]);
 }
 
+// Both vectors' totals at once from the octet sums sa (vector p) and sb
+// (vector p + 16): the first row swap exchanges rows between sa and sb, so
+// a lane of row 0 or 2 then holds o0 + o1 or o2 + o3 of vector p, a lane of
+// row 1 or 3 the same of vector p + 16; the second swap adds the halves.
+// Rows 0 and 2 end with vector p's total, rows 1 and 3 with vector p + 16's,
+// each summed as (o0 + o1) + (o2 + o3), as octet_total sums them.  The
+// whole wave must be active.
+__device__ __forceinline__ float pair_total(float sa, float sb) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(sa), __float_as_uint(sb), false, false);
+    const float t = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const auto r2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+    return __uint_as_float(r2[0]) + __uint_as_float(r2[1]);
+}
+
 // Bit v: vector v of the tile (pairs p, p + 16 held by lanes p of every
 // octet; the lanes of octet 0 stand for them).
 __device__ __forceinline__ uint32_t pair_mask(bool a, bool b) {
@@ -696,6 +710,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
         const int32_t rid_a = slot_id ? slot_id[vid_a] : (vid_a < n ? (int32_t)vid_a : -1);
         const int32_t rid_b = slot_id ? slot_id[vid_b] : (vid_b < n ? (int32_t)vid_b : -1);
         const uint32_t valid_m = pair_mask(rid_a >= 0, rid_b >= 0);
+        const int32_t rid_v = (oct & 1) ? rid_b : rid_a;  // row id of this lane's vector
 
         // Phase A: first chunk of every query, lanes = 16 vector pairs x 4
         // octets.  The next query's first-chunk metadata is loaded while the
@@ -738,32 +753,30 @@ __global__ __launch_bounds__(1024) void tile_kernel(
             if (!cur.bad) {
                 float sa, sb;
                 octet_pair<L1>(tile, cur.o, cur.q[0], cur.q[1], pr, sa, sb);
-                const float pa = octet_total(sa), pb = octet_total(sb);
-                const bool al_a = rid_a >= 0 && !(pa > cur.tau);
-                const bool al_b = rid_b >= 0 && !(pb > cur.tau);
+                // this lane's vector (pr in rows 0 and 2, pr + 16 in rows 1 and 3)
+                const float p1 = pair_total(sa, sb);
+                const bool al1 = rid_v >= 0 && !(p1 > cur.tau);
                 if (counters) {
                     live_vals += 32ull * __popc(valid_m);
                     lane_vals += 64ull * 16;
                 }
-                const uint32_t m = pair_mask(al_a, al_b);
+                const uint32_t m = static_cast<uint32_t>(__ballot(al1));  // bit v: vector v (rows 0 and 1)
                 if (DENSE && m != 0 && nchunks > 1 && __popc(m) >= kDense) {
                     // dense pair: this wave finishes the query on the tile,
                     // lanes = 16 vector pairs x 4 octets as in the first
                     // chunk; the next chunk's metadata is fetched while the
                     // current one is summed
-                    bool la = al_a, lb = al_b;
-                    float xa = pa, xb = pb;
+                    bool al = al1;
+                    float x = p1;
                     const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + oct * 8);
                     const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + oct * 8);
                     auto dense_step = [&](const uint4 oc, const float4 qc0, const float4 qc1) {
                         float ta, tb2;
                         octet_pair<L1>(tile, oc, qc0, qc1, pr, ta, tb2);
-                        xa += octet_total(ta);
-                        xb += octet_total(tb2);
-                        la = la && !(xa > cur.tau);
-                        lb = lb && !(xb > cur.tau);
+                        x += pair_total(ta, tb2);
+                        al = al && !(x > cur.tau);
                         if (counters) {
-                            live_vals += 32ull * __popc(pair_mask(la, lb));
+                            live_vals += 32ull * __popc(static_cast<uint32_t>(__ballot(al)));
                             lane_vals += 64ull * 16;
                         }
                     };
@@ -774,14 +787,14 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                     uint4 ob = oa;
                     float4 qb0 = qa0, qb1 = qa1;
                     for (int32_t c = 1; c < nchunks; c += 2) {
-                        if (!__any(la || lb)) break;
+                        if (!__any(al)) break;
                         if (c + 1 < nchunks) {
                             ob = o4[4 * (c + 1)];
                             qb0 = q4[8 * (c + 1)];
                             qb1 = q4[8 * (c + 1) + 1];
                         }
                         dense_step(oa, qa0, qa1);
-                        if (c + 1 == nchunks || !__any(la || lb)) break;
+                        if (c + 1 == nchunks || !__any(al)) break;
                         if (c + 2 < nchunks) {
                             oa = o4[4 * (c + 2)];
                             qa0 = q4[8 * (c + 2)];
@@ -789,52 +802,40 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                         }
                         dense_step(ob, qb0, qb1);
                     }
-                    if (oct == 0 && la) cand_append(cand, cand_cnt, cap, qi, xa, (uint32_t)rid_a);
-                    if (oct == 0 && lb) cand_append(cand, cand_cnt, cap, qi, xb, (uint32_t)rid_b);
+                    if (oct < 2 && al) cand_append(cand, cand_cnt, cap, qi, x, (uint32_t)rid_v);
                 } else if (m != 0) {
                     if (nchunks == 1) {
-                        if (oct == 0 && al_a) cand_append(cand, cand_cnt, cap, qi, pa, (uint32_t)rid_a);
-                        if (oct == 0 && al_b) cand_append(cand, cand_cnt, cap, qi, pb, (uint32_t)rid_b);
+                        if (oct < 2 && al1) cand_append(cand, cand_cnt, cap, qi, p1, (uint32_t)rid_v);
                     } else {
                         int base = 0;
                         if (lane == 0) base = atomicAdd(&qcount, __popc(m));
                         base = __shfl(base, 0);
-                        // queue slot of vector v: base + the survivors below v
-                        bool own_a = false, own_b = false;  // both queues are full: finish it here
-                        if (oct == 0) {
-#pragma unroll
-                            for (int h = 0; h < 2; ++h) {
-                                const bool al = h ? al_b : al_a;
-                                if (!al) continue;
-                                const int vv = pr + 16 * h;
-                                const int pos = base + __popc(m & ((1u << vv) - 1u));
-                                const uint32_t key = (static_cast<uint32_t>(qi) << 5) | static_cast<uint32_t>(vv);
-                                const float pv = h ? pb : pa;
-                                if (pos < kQCap)
-                                    queue[pos] = make_uint2(key, __float_as_uint(pv));
-                                else if (pos < kQCap + kGCap)
-                                    gq[pos - kQCap] = (static_cast<uint64_t>(__float_as_uint(pv)) << 32) | key;
-                                else if (h)
-                                    own_b = true;
-                                else
-                                    own_a = true;
-                            }
+                        // queue slot of vector v: base + the survivors below
+                        // v; rows 0 and 1 enqueue their vectors
+                        bool own = false;  // both queues are full: finish it here
+                        if (oct < 2 && al1) {
+                            const int vv = pr + 16 * oct;
+                            const int pos = base + __popc(m & ((1u << vv) - 1u));
+                            const uint32_t key = (static_cast<uint32_t>(qi) << 5) | static_cast<uint32_t>(vv);
+                            if (pos < kQCap)
+                                queue[pos] = make_uint2(key, __float_as_uint(p1));
+                            else if (pos < kQCap + kGCap)
+                                gq[pos - kQCap] = (static_cast<uint64_t>(__float_as_uint(p1)) << 32) | key;
+                            else
+                                own = true;
                         }
-                        // lanes of octet 0 finish vector pr, lanes of octet 1 vector pr + 16
-                        const bool own_b_here = __shfl(own_b, pr);
-                        bool own = (oct == 0 && own_a) || (oct == 1 && own_b_here);
                         if (__any(own)) {
                             const int vv = pr + 16 * (oct & 1);
                             const uint16_t *pf = poff + qi * d;
                             const float *qp = qperm + qi * d;
-                            float x = (oct & 1) ? pb : pa;
+                            float x = p1;
                             for (int32_t c = 1; c < nchunks && __any(own); ++c) {
                                 if (own) {
                                     x += tile_chunk<L1>(tile, pf + c * 32, qp + c * 32, vv);
                                     own = !(x > cur.tau);
                                 }
                             }
-                            if (own) cand_append(cand, cand_cnt, cap, qi, x, (uint32_t)((oct & 1) ? rid_b : rid_a));
+                            if (own) cand_append(cand, cand_cnt, cap, qi, x, (uint32_t)rid_v);
                         }
                     }
                 }
