@@ -592,27 +592,15 @@ __device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4
     }
 }
 
-// Octet sums of the four 16-lane rows (octets 0..3 of one vector pair)
-// combined as (o0 + o1) + (o2 + o3) in every lane.  gfx950's row swaps
-// (v_permlane16_swap, v_permlane32_swap) applied to a value and itself hand
-// each lane its own row's value and the partner row's, in the VALU with no
-// LDS round trip: after the first swap the two results are o0 and o1 (rows
-// 0, 1) or o2 and o3 (rows 2, 3), after the second the two halves' sums.
-// The whole wave must be active.
-__device__ __forceinline__ float octet_total(float s) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s), __float_as_uint(s), false, false);
-    const float t = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    const auto r2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(t), __float_as_uint(t), false, false);
-    return __uint_as_float(r2[0]) + __uint_as_float(r2[1]);
-}
-
-// Both vectors' totals at once from the octet sums sa (vector p) and sb
-// (vector p + 16): the first row swap exchanges rows between sa and sb, so
-// a lane of row 0 or 2 then holds o0 + o1 or o2 + o3 of vector p, a lane of
-// row 1 or 3 the same of vector p + 16; the second swap adds the halves.
-// Rows 0 and 2 end with vector p's total, rows 1 and 3 with vector p + 16's,
-// each summed as (o0 + o1) + (o2 + o3), as octet_total sums them.  The
-// whole wave must be active.
+// A chunk's total for both vectors of a pair from the octet sums sa
+// (vector p) and sb (vector p + 16), one per 16-lane row (octets 0..3),
+// combined as (o0 + o1) + (o2 + o3) in the VALU with no LDS round trip.
+// gfx950's first row swap (v_permlane16_swap) trades the odd rows of sa for
+// the even rows of sb, so the two results add to o0 + o1 (row 0) and
+// o2 + o3 (row 2) of vector p and the same (rows 1, 3) of vector p + 16;
+// the second (v_permlane32_swap, a value with itself) adds the halves.
+// Rows 0 and 2 end with vector p's total, rows 1 and 3 with vector
+// p + 16's.  The whole wave must be active.
 __device__ __forceinline__ float pair_total(float sa, float sb) {
     const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(sa), __float_as_uint(sb), false, false);
     const float t = __uint_as_float(r[0]) + __uint_as_float(r[1]);
@@ -1214,12 +1202,11 @@ __global__ __launch_bounds__(1024) void ip_tile_kernel(
             for (int32_t e = wave; e < cnt; e += kTW) {
                 const int64_t qi = qlist[e];
                 const float *qr = q + qi * d + oct * 8;
-                float xa = 0.0f, xb = 0.0f;
+                float x = 0.0f;  // this lane's vector: pr in rows 0 and 2, pr + 16 in rows 1 and 3
                 auto ip_step = [&](int32_t c, const float4 qc0, const float4 qc1) {
                     float sa, sb;
                     octet_pair_ip(tile, c * 32 + oct * 8, qc0, qc1, pr, sa, sb);
-                    xa += octet_total(sa);
-                    xb += octet_total(sb);
+                    x += pair_total(sa, sb);
                 };
                 // two query-value sets in turn (chunks c and c + 1), so a
                 // prefetched set is used where it landed, never copied
@@ -1244,10 +1231,9 @@ __global__ __launch_bounds__(1024) void ip_tile_kernel(
                     lane_vals += 32ull * d;
                 }
                 const float tq = __uint_as_float(tau[qi]);
-                const float sh = qshift[qi];
-                const float sa = sh - xa, sb = sh - xb;
-                if (oct == 0 && rid_a >= 0 && !(sa > tq)) cand_append(cand, cand_cnt, cap, qi, sa, (uint32_t)rid_a);
-                if (oct == 0 && rid_b >= 0 && !(sb > tq)) cand_append(cand, cand_cnt, cap, qi, sb, (uint32_t)rid_b);
+                const float sv = qshift[qi] - x;
+                const int32_t rid_v = (oct & 1) ? rid_b : rid_a;
+                if (oct < 2 && rid_v >= 0 && !(sv > tq)) cand_append(cand, cand_cnt, cap, qi, sv, (uint32_t)rid_v);
             }
         }
         __syncthreads();
