@@ -7,13 +7,20 @@
 * decode error bounds (unit roundoff of the format: 8 significant bits for
   bfloat16, 4 for e4m3): |x - bf16(x)| <= 2^-8 |x|; e4m3 relative error
   <= 2^-4 in the normal range;
-* the rerank reference keeps the exact top-k when r covers every row.
+* fp8 scales, codes and decoded values pinned by value on a hand-worked
+  matrix (tests/golden/hand_fp8_scales.json); a planted divisor of 240
+  (another 8-bit format's largest value) is caught;
+* the rerank reference keeps the exact top-k when r covers every row, and a
+  hand-worked case (tests/golden/hand_rerank.json) pins the first stage's
+  ranking, its cut at r and its ties: a planted first stage ranked by the
+  exact distance, or cut at r + 1, is caught.
 """
 import numpy as np
 import pytest
 import torch
 
 from oracle import exact, lowp
+from tests.conftest import golden
 
 HAND_BF16 = [(1.0, 0x3F80), (-2.0, 0xC000), (1.00390625, 0x3F80),   # tie 1 + 2^-8 -> even (down)
              (1.01171875, 0x3F82), (3.140625, 0x4049), (0.0, 0x0000)]
@@ -82,3 +89,39 @@ def test_rerank_full_r_is_exact():
     wi, wd = exact.knn_exact(x, q[None], 10)
     assert ids.tolist() == wi[0].tolist()
     np.testing.assert_allclose(dist, wd[0], rtol=1e-12)
+
+
+def test_fp8_scales_hand_worked():
+    g = golden("hand_fp8_scales.json")
+    x = np.array(g["x"], np.float32)
+    s = lowp.fp8_scales(x)
+    assert s.dtype == np.float32 and s.tolist() == g["scales"]
+    codes = lowp.fp8_encode(x, s)
+    assert codes.tolist() == g["codes"]
+    assert lowp.fp8_decode(codes, s).tolist() == g["decoded"]
+    # a planted divisor of 240 instead of 448 gives other scales; the codes
+    # alone would not show it (the largest value saturates either way)
+    planted = (np.abs(x).max(axis=0) / np.float32(240.0)).astype(np.float32)
+    planted[np.abs(x).max(axis=0) == 0] = 1.0
+    assert planted.tolist() != g["scales"]
+
+
+def _rerank_exact_first(x_exact, x_approx, rows, q, k, r):
+    """A planted mistake: the first stage ranks by the exact distance."""
+    return lowp.rerank(x_exact, x_exact, rows, q, k, r)
+
+
+def test_rerank_hand_worked():
+    g = golden("hand_rerank.json")
+    xe = np.array(g["exact"], np.float32)
+    xa = np.array(g["approx"], np.float32)
+    q = np.array(g["query"], np.float32)
+    rows = np.arange(xe.shape[0])
+    for c in g["cases"]:
+        ids, dist = lowp.rerank(xe, xa, rows, q, c["k"], c["r"])
+        assert ids.tolist() == c["ids"], c
+        assert dist.tolist() == [float(v) for v in c["dist"]], c
+    # planted mistakes disagree with the hand-worked cases
+    c = g["cases"][0]
+    assert _rerank_exact_first(xe, xa, rows, q, c["k"], c["r"])[0].tolist() != c["ids"]
+    assert lowp.rerank(xe, xa, rows, q, c["k"], c["r"] + 1)[0].tolist() != c["ids"]
