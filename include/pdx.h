@@ -133,6 +133,15 @@ typedef struct {
                             vectorgroups (Section 6.5 bounds the START
                             block's size); 0 = 128.  The flat index takes
                             its START block from pdx_build_params. */
+    /* Optional instrumentation (NULL = off; does not change the result):
+     * device [ceil(D / chunk)], added to (not cleared).  Entry c counts the
+     * (query, vector) pairs of the pruned scan (PDX_MODE_BOND after START;
+     * L2 and L1) whose partial distance after the c-th chunk of the visit
+     * order is still at or below the threshold the scan compares it with,
+     * i.e. the survivors of each chunk (Section 2.3's pruning power per
+     * step).  Pairs the bucket layout's centroid bound skips are never
+     * evaluated and count nowhere.  Slows the scan (atomics per chunk). */
+    unsigned long long *chunk_survivors;
 } pdx_search_params;
 
 /* Workspace bytes for pdx_search_exact with these arguments. */
@@ -175,6 +184,48 @@ PDX_API size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, in
 PDX_API pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, int32_t k,
                             const pdx_search_params *params, void *ws, size_t ws_bytes,
                             int64_t *out_ids, float *out_dist, void *stream);
+
+/* Dimension visit orders (pdx_query_order). */
+enum {
+    PDX_ORDER_NATURAL = 0, /* stored dimension order (linear scan, ADSampling) */
+    PDX_ORDER_BOND = 1,    /* PDX-BOND, Section 5: |q_j - mean_j| descending,
+                              equal keys by j ascending (keys in float32)      */
+    PDX_ORDER_ZONES = 2    /* dimension zones, Section 5 and Figure "dz": zones
+                              of 32 consecutive stored dimensions by
+                              sum_j |q_j - mean_j| descending (float32 sums, j
+                              ascending), equal scores by zone; storage order
+                              inside a zone; a shorter last zone (D % 32 != 0)
+                              is visited last                                   */
+};
+
+/* Workspace bytes for pdx_query_order over nq queries (0 for bad arguments). */
+PDX_API size_t pdx_query_order_workspace(const pdx_index *index, int64_t nq);
+
+/* pdx_query_order -- the dimension visit order each query's search uses.
+ *
+ * Section 5 (PDX-BOND, "distance to means"; dimension zones): runs the
+ * query preparation of pdx_search_exact (PDX_ORDER_BOND: mode BOND) and of
+ * pdx_search_ivf's PDX-BOND bounds (PDX_ORDER_BOND: bound 1,
+ * PDX_ORDER_ZONES: bound 2) and returns what it produced: means are the
+ * index's (flat: the collection's; IVF: those of the stored rows), and a
+ * rotated IVF index rotates the queries first (dimensions are then the
+ * rotated ones).
+ *
+ * q            [nq][d] float32 device, read only.
+ * order        PDX_ORDER_*.
+ * out_perm     [nq][d] int32 device: the j-th visited dimension.
+ * out_qval     [nq][d] float32 device or NULL: the (rotated) query value
+ *              at that dimension.
+ * out_tile_off [nq][d] uint16 device or NULL: the LDS row offsets
+ *              (32 * dimension) the exact search's tile scan reads for that
+ *              order; needs d * 32 < 65536.
+ * ws           pdx_query_order_workspace(index, nq) bytes, 16-byte aligned.
+ * Asynchronous on `stream`.  nq = 0 is a no-op.  Returns PDX_EINVAL (null
+ * pointers, nq < 0, unknown order), PDX_EUNSUPPORTED (out_tile_off with
+ * d * 32 >= 65536), PDX_EWORKSPACE. */
+PDX_API pdx_status pdx_query_order(const pdx_index *index, const float *q, int64_t nq, int32_t order,
+                                   int32_t *out_perm, float *out_qval, uint16_t *out_tile_off, void *ws,
+                                   size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------
  * IVF index with ADSampling

@@ -14,6 +14,7 @@ from .api import (  # noqa: F401
     pdx_ivf_export,
     pdx_ivf_tune,
     pdx_layout_blocks,
+    pdx_query_order,
     pdx_search_exact,
     pdx_search_exact_workspace,
     pdx_search_ivf,

@@ -30,6 +30,10 @@ PDX_METRIC_L2 = 0
 PDX_METRIC_L1 = 1
 PDX_METRIC_IP = 2
 
+PDX_ORDER_NATURAL = 0
+PDX_ORDER_BOND = 1
+PDX_ORDER_ZONES = 2
+
 PDX_LAYOUT_NARY = 0
 PDX_LAYOUT_PDX = 1
 
@@ -56,7 +60,7 @@ class pdx_build_params(ctypes.Structure):
 class pdx_search_params(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("chunk", c_int32), ("tile_groups", c_int32),
                 ("queries_per_block", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
-                ("metric", c_int32), ("start_rows", c_int32)]
+                ("metric", c_int32), ("start_rows", c_int32), ("chunk_survivors", c_void_p)]
 
 
 class pdx_ivf_params(ctypes.Structure):
@@ -93,6 +97,9 @@ SIGNATURES = {
     "pdx_search_exact": (c_int32, [c_void_p, c_void_p, c_int64, c_int32,
                                    ctypes.POINTER(pdx_search_params), c_void_p, c_size_t,
                                    c_void_p, c_void_p, c_void_p]),
+    "pdx_query_order_workspace": (c_size_t, [c_void_p, c_int64]),
+    "pdx_query_order": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_size_t, c_void_p]),
     "pdx_ivf_build_bytes": (c_size_t, [c_int64, c_int32, c_int32, ctypes.POINTER(pdx_ivf_params)]),
     "pdx_ivf_build": (c_int32, [c_void_p, c_int64, c_int32, c_int32, ctypes.POINTER(pdx_ivf_params),
                                 c_void_p, c_size_t, c_void_p, ctypes.POINTER(c_void_p)]),

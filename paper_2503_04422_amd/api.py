@@ -4,10 +4,21 @@ Each function has the name of the C entry point it calls.  Tensors must be
 CUDA (HIP) tensors; torch provides the device memory (index buffers,
 workspaces, outputs) and the current stream.  Every step of the search runs
 in the library's HIP kernels.
+
+``stream=``: when a stream is given, the call's own allocations and copies
+(workspace, outputs, contiguous copies of the inputs) are made with that
+stream current, so torch's caching allocator ties them to the stream the
+library's kernels run on and cannot hand their memory to other work while
+those kernels still read it; the searches also record the index memory on
+the stream.  Inputs the caller made on another stream must be ordered
+before the call by the caller, as with any torch op.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
+import functools
+import inspect
 import math
 from typing import Optional, Tuple
 
@@ -20,6 +31,28 @@ from ._lib import check, lib
 def _stream(stream: Optional[torch.cuda.Stream]) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
+
+
+def _on_stream(fn):
+    """Run ``fn`` with its ``stream`` argument (if given) as torch's current
+    stream, so every tensor the call allocates or copies belongs to the
+    stream the library's kernels are queued on."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapped(*args, **kwargs):
+        stream = sig.bind_partial(*args, **kwargs).arguments.get("stream")
+        ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+        with ctx:
+            return fn(*args, **kwargs)
+
+    return wrapped
+
+
+def _hold_index(index: "PdxIndex") -> None:
+    """The index memory stays reserved until the current stream's queued
+    work (this call's kernels) is done, even if the index is dropped."""
+    index.mem.record_stream(torch.cuda.current_stream(index.mem.device))
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -63,6 +96,7 @@ class PdxIndex:
             self._h = ctypes.c_void_p(None)
 
 
+@_on_stream
 def pdx_build(x: torch.Tensor, start_rows: int = 0,
               stream: Optional[torch.cuda.Stream] = None) -> PdxIndex:
     """Flat PDX index of the rows of ``x`` ([n, d] float32 on the GPU)."""
@@ -91,12 +125,13 @@ def pdx_search_exact_workspace(index: PdxIndex, nq: int, k: int, mode: str = "bo
     return int(lib.pdx_search_exact_workspace(index.handle, nq, k, ctypes.byref(p)))
 
 
+@_on_stream
 def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond", chunk: int = 0,
                      tile_groups: int = 0, queries_per_block: int = 0,
                      workspace: Optional[torch.Tensor] = None,
                      phase_events=None, counters: Optional[torch.Tensor] = None,
                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, metric: str = "l2",
-                     start_rows: int = 0,
+                     start_rows: int = 0, chunk_survivors: Optional[torch.Tensor] = None,
                      stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Exact k nearest neighbours; returns (ids [nq, k] int64, dist [nq, k] float32).
 
@@ -105,14 +140,16 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
     ``start_rows``: bucket layout, rows of the nearest bucket START scans
     (0 = 128).
     ``phase_events``: optional ctypes array of 4 hipEvent_t handles;
-    ``counters``: optional int64 GPU tensor of 4 value counters."""
+    ``counters``: optional int64 GPU tensor of 4 value counters;
+    ``chunk_survivors``: optional int64 GPU tensor of ceil(D / chunk)
+    per-chunk survivor counts of the pruned scan (added to)."""
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     if q.shape[1] != index.d:
         raise ValueError("query dimension does not match the index")
     p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block,
                                ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
-                               _ptr(counters), _METRICS[metric], int(start_rows))
+                               _ptr(counters), _METRICS[metric], int(start_rows), _ptr(chunk_survivors))
     if out is None:
         ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
         dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
@@ -121,12 +158,38 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
     need = lib.pdx_search_exact_workspace(index.handle, nq, k, ctypes.byref(p))
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
+    _hold_index(index)
     st = lib.pdx_search_exact(index.handle, _ptr(q), nq, k, ctypes.byref(p), _ptr(workspace),
                               workspace.numel(), _ptr(ids), _ptr(dist), _stream(stream))
     check(st, "pdx_search_exact")
     return ids, dist
 
 
+_ORDERS = {"natural": _lib.PDX_ORDER_NATURAL, "bond": _lib.PDX_ORDER_BOND, "zones": _lib.PDX_ORDER_ZONES}
+
+
+@_on_stream
+def pdx_query_order(index: PdxIndex, q: torch.Tensor, order: str = "bond", tile_offsets: bool = False,
+                    stream: Optional[torch.cuda.Stream] = None):
+    """The dimension visit order the searches use for each query
+    (pdx_query_order): (perm [nq, d] int32, qval [nq, d] float32, off
+    [nq, d] int16 holding the uint16 LDS tile offsets, or None)."""
+    q = _dev_f32(q, "q")
+    nq = q.shape[0]
+    if q.shape[1] != index.d:
+        raise ValueError("query dimension does not match the index")
+    perm = torch.empty((nq, index.d), dtype=torch.int32, device=q.device)
+    qval = torch.empty((nq, index.d), dtype=torch.float32, device=q.device)
+    off = torch.empty((nq, index.d), dtype=torch.int16, device=q.device) if tile_offsets else None
+    need = lib.pdx_query_order_workspace(index.handle, nq)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
+    _hold_index(index)
+    check(lib.pdx_query_order(index.handle, _ptr(q), nq, _ORDERS[order], _ptr(perm), _ptr(qval), _ptr(off),
+                              _ptr(ws), ws.numel(), _stream(stream)), "pdx_query_order")
+    return perm, qval, off
+
+
+@_on_stream
 def pdx_ivf_build(x: torch.Tensor, nlist: int, gaussian: Optional[torch.Tensor],
                   init_rows: Optional[torch.Tensor], kmeans_iters: int = 0, lowp: Tuple[str, ...] = (),
                   rotation: Optional[torch.Tensor] = None, centroids: Optional[torch.Tensor] = None,
@@ -160,6 +223,7 @@ def pdx_ivf_build(x: torch.Tensor, nlist: int, gaussian: Optional[torch.Tensor],
     return PdxIndex(h, mem, n, d, "ivf", nlist, "+".join(("f32",) + tuple(lowp)))
 
 
+@_on_stream
 def pdx_ivf_export(index: PdxIndex, stream: Optional[torch.cuda.Stream] = None):
     """(rotation [d,d], centroids [nlist,d], assign [n] int32, list_sizes [nlist] int32)."""
     dev = index.mem.device
@@ -204,6 +268,7 @@ class MlpState:
     budget (weighted cross-entropy, kind "bce", w = the negatives' weight)
     or the prune bound (kind "pinball", w = the quantile level)."""
 
+    @_on_stream
     def __init__(self, theta0: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
         if not theta0.is_cuda or theta0.dtype != torch.float32 or theta0.numel() != _lib.MLP_PARAMS:
             raise TypeError(f"theta0 must be a float32 GPU tensor of {_lib.MLP_PARAMS} values")
@@ -217,12 +282,14 @@ class MlpState:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.mem.device)
         return self._ws
 
+    @_on_stream
     def forward(self, x: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
         x = _dev_f32(x, "x")
         z = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
         check(lib.pdx_mlp_forward(_ptr(self.mem), _ptr(x), x.shape[0], _ptr(z), _stream(stream)), "pdx_mlp_forward")
         return z
 
+    @_on_stream
     def grad(self, x: torch.Tensor, y: torch.Tensor, w: float, kind: str = "bce",
              stream: Optional[torch.cuda.Stream] = None):
         x = _dev_f32(x, "x")
@@ -234,12 +301,14 @@ class MlpState:
                                ws.numel(), _ptr(g), _ptr(loss), _stream(stream)), "pdx_mlp_grad")
         return g, loss
 
+    @_on_stream
     def theta(self, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
         """The float32 parameters [8960] (a copy)."""
         t = torch.empty(_lib.MLP_PARAMS, dtype=torch.float32, device=self.mem.device)
         check(lib.pdx_mlp_export(_ptr(self.mem), _ptr(t), _stream(stream)), "pdx_mlp_export")
         return t
 
+    @_on_stream
     def train_step(self, x: torch.Tensor, y: torch.Tensor, w: float, lr: float, step: int,
                    loss: Optional[torch.Tensor] = None, kind: str = "bce",
                    stream: Optional[torch.cuda.Stream] = None) -> None:
@@ -250,6 +319,7 @@ class MlpState:
                                      _stream(stream)), "pdx_mlp_train_step")
 
 
+@_on_stream
 def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1,
                    delta_d: int = 0, dtype: str = "f32", rerank: int = 0,
                    workspace: Optional[torch.Tensor] = None, phase_events=None,
@@ -302,12 +372,14 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
     need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
+    _hold_index(index)
     st = lib.pdx_search_ivf(index.handle, _ptr(q), nq, k, nprobe, ctypes.byref(p), _ptr(workspace),
                             workspace.numel(), _ptr(ids), _ptr(dist), _stream(stream))
     check(st, "pdx_search_ivf")
     return ids, dist
 
 
+@_on_stream
 def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1, delta_d: int = 0,
                  dtype: str = "f32", rerank: int = 0, tune_delta_d: bool = True, reps: int = 3,
                  stream: Optional[torch.cuda.Stream] = None):
@@ -323,6 +395,7 @@ def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: fl
     need = lib.pdx_ivf_tune_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
     table = (_lib.pdx_ivf_schedule * _lib.TUNE_CANDIDATES)()
+    _hold_index(index)
     st = lib.pdx_ivf_tune(index.handle, _ptr(q), nq, k, nprobe, ctypes.byref(p), int(bool(tune_delta_d)), int(reps),
                           table, _ptr(ws), ws.numel(), _stream(stream))
     check(st, "pdx_ivf_tune")
@@ -333,6 +406,7 @@ def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: fl
     return sched, rows
 
 
+@_on_stream
 def pdx_layout_blocks(x: torch.Tensor, block: int = 64,
                       stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
     """Rows [n, d] -> PDX blocks [ceil(n / block), d, block] (Section 3),
@@ -347,6 +421,7 @@ def pdx_layout_blocks(x: torch.Tensor, block: int = 64,
     return out
 
 
+@_on_stream
 def pdx_distances(data: torch.Tensor, q: torch.Tensor, n: Optional[int] = None, layout: str = "pdx",
                   metric: str = "l2", stream: Optional[torch.cuda.Stream] = None,
                   out: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -202,6 +202,8 @@ __device__ __forceinline__ float zone_sum(const float *__restrict__ xr, const fl
 // from the row-major copy xrow ([n][d], by row id, d % 4 == 0) -- one line
 // per survivor instead of kZone dimension rows of the group.  Both reads
 // give the same bits.
+// surv (optional, PRUNE only): per-chunk survivor counts, entry c0 / chunk
+// += the lanes still alive after chunk [c0, c1).
 template <bool PRUNE, bool L1 = false, bool ZONES = false>
 __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int64_t n,
                                             const int32_t *__restrict__ slot_id, int32_t d, int32_t g0,
@@ -209,7 +211,8 @@ __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int6
                                             const float *__restrict__ qperm, uint32_t *__restrict__ tau,
                                             uint64_t *__restrict__ myslot, int32_t k, int32_t chunk,
                                             unsigned long long *__restrict__ counters,
-                                            const float *__restrict__ xrow = nullptr, int32_t zone_rows = 0) {
+                                            const float *__restrict__ xrow = nullptr, int32_t zone_rows = 0,
+                                            unsigned long long *__restrict__ surv = nullptr) {
     const int lane = threadIdx.x & 63;
     const int32_t *po = perm + qi * d;
     const float *qp = qperm + qi * d;
@@ -244,6 +247,10 @@ __device__ __forceinline__ void scan_groups(const float *__restrict__ pdxd, int6
             }
             partial += s;
             if (PRUNE) alive = alive && !(partial > tau_eff);
+            if (PRUNE && surv) {
+                const int na = __popcll(__ballot(alive));
+                if (lane == 0 && na) atomicAdd(surv + c0 / chunk, (unsigned long long)na);
+            }
         }
         topk_offer(e, kth, make_key(partial, static_cast<uint32_t>(rid)), alive, k, lane);
         if (PRUNE && kth != kEmptyKey) {
@@ -272,7 +279,7 @@ __global__ __launch_bounds__(512) void scan_kernel(
     int32_t tile_groups, int32_t ntiles, int32_t nqb, int64_t nq, int32_t qpb,
     const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, uint64_t *__restrict__ slots, int32_t nslots, int32_t slot0,
-    int32_t k, int32_t chunk, unsigned long long *__restrict__ counters) {
+    int32_t k, int32_t chunk, unsigned long long *__restrict__ counters, unsigned long long *__restrict__ surv) {
     const uint32_t L = blockIdx.x;
     const int32_t xcd = L & 7;
     const uint32_t r = L >> 3;
@@ -290,7 +297,8 @@ __global__ __launch_bounds__(512) void scan_kernel(
     }
     const int32_t g0 = g_begin + tile * tile_groups;
     const int32_t g1 = min(g0 + tile_groups, g_end);
-    scan_groups<PRUNE, L1>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters);
+    scan_groups<PRUNE, L1>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau, myslot, k, chunk, counters, nullptr, 0,
+                           surv);
 }
 
 // |row|^2 of every row of a [m][d] matrix, one wave per row.
@@ -399,7 +407,8 @@ __global__ __launch_bounds__(256) void fallback_kernel(
     int32_t g_end, int32_t tile_groups,
     int32_t ntiles, const int32_t *__restrict__ over_list, const int32_t *__restrict__ over_count,
     const int32_t *__restrict__ perm, const float *__restrict__ qperm, uint32_t *__restrict__ tau,
-    uint64_t *__restrict__ slots, int32_t nslots, int32_t slot0, int32_t k, int32_t chunk) {
+    uint64_t *__restrict__ slots, int32_t nslots, int32_t slot0, int32_t k, int32_t chunk,
+    unsigned long long *__restrict__ surv) {
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t total = (int64_t)(*over_count) * ntiles;
     for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < total; it += (int64_t)gridDim.x * 4) {
@@ -408,7 +417,7 @@ __global__ __launch_bounds__(256) void fallback_kernel(
         const int32_t g0 = g_begin + tile * tile_groups;
         const int32_t g1 = min(g0 + tile_groups, g_end);
         scan_groups<true, L1>(pdxd, n, slot_id, d, g0, g1, qi, perm, qperm, tau,
-                              slots + ((size_t)qi * nslots + slot0 + tile) * k, k, chunk, nullptr);
+                              slots + ((size_t)qi * nslots + slot0 + tile) * k, k, chunk, nullptr, nullptr, 0, surv);
     }
 }
 
@@ -649,14 +658,16 @@ constexpr int kDense = 8;  // survivors of the first chunk from which a (query, 
 constexpr int kList = 1024;
 typedef __attribute__((address_space(3))) void lds_void_t;  // LDS destination of direct loads
 
-template <bool DENSE, bool L1>
+// STATS (instrumentation build only): per-chunk survivor counts in surv.
+template <bool DENSE, bool L1, bool STATS>
 __global__ __launch_bounds__(1024) void tile_kernel(
     const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t t_begin,
     int32_t t_end, int64_t nq,
     const uint16_t *__restrict__ poff, const float *__restrict__ qperm, const uint32_t *__restrict__ tau,
     const int32_t *__restrict__ bad, uint64_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int32_t cap,
     uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters, const float *__restrict__ dql,
-    const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad, int32_t *__restrict__ tile_ctr) {
+    const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad, int32_t *__restrict__ tile_ctr,
+    unsigned long long *__restrict__ surv) {
     extern __shared__ float4 smem4[];
     float *tile = reinterpret_cast<float *>(smem4);                          // [d][32]
     uint2 *queue = reinterpret_cast<uint2 *>(tile + (size_t)d * kTV);        // [kQCap]
@@ -749,6 +760,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                     lane_vals += 64ull * 16;
                 }
                 const uint32_t m = static_cast<uint32_t>(__ballot(al1));  // bit v: vector v (rows 0 and 1)
+                if (STATS && lane == 0 && m) atomicAdd(surv, (unsigned long long)__popc(m));
                 if (DENSE && m != 0 && nchunks > 1 && __popc(m) >= kDense) {
                     // dense pair: this wave finishes the query on the tile,
                     // lanes = 16 vector pairs x 4 octets as in the first
@@ -758,14 +770,18 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                     float x = p1;
                     const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + oct * 8);
                     const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + oct * 8);
-                    auto dense_step = [&](const uint4 oc, const float4 qc0, const float4 qc1) {
+                    auto dense_step = [&](int32_t c, const uint4 oc, const float4 qc0, const float4 qc1) {
                         float ta, tb2;
+                        if (counters) {  // the vectors still alive evaluate this chunk
+                            live_vals += 32ull * __popc(static_cast<uint32_t>(__ballot(al)));
+                            lane_vals += 64ull * 16;
+                        }
                         octet_pair<L1>(tile, oc, qc0, qc1, pr, ta, tb2);
                         x += pair_total(ta, tb2);
                         al = al && !(x > cur.tau);
-                        if (counters) {
-                            live_vals += 32ull * __popc(static_cast<uint32_t>(__ballot(al)));
-                            lane_vals += 64ull * 16;
+                        if (STATS) {
+                            const uint32_t ms = static_cast<uint32_t>(__ballot(al));
+                            if (lane == 0 && ms) atomicAdd(surv + c, (unsigned long long)__popc(ms));
                         }
                     };
                     // two metadata sets in turn (chunks c and c + 1), so a
@@ -781,14 +797,14 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                             qb0 = q4[8 * (c + 1)];
                             qb1 = q4[8 * (c + 1) + 1];
                         }
-                        dense_step(oa, qa0, qa1);
+                        dense_step(c, oa, qa0, qa1);
                         if (c + 1 == nchunks || !__any(al)) break;
                         if (c + 2 < nchunks) {
                             oa = o4[4 * (c + 2)];
                             qa0 = q4[8 * (c + 2)];
                             qa1 = q4[8 * (c + 2) + 1];
                         }
-                        dense_step(ob, qb0, qb1);
+                        dense_step(c + 1, ob, qb0, qb1);
                     }
                     if (oct < 2 && al) cand_append(cand, cand_cnt, cap, qi, x, (uint32_t)rid_v);
                 } else if (m != 0) {
@@ -818,9 +834,17 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                             const float *qp = qperm + qi * d;
                             float x = p1;
                             for (int32_t c = 1; c < nchunks && __any(own); ++c) {
+                                if (counters) {  // rows 0 and 1 hold the wave's vectors
+                                    live_vals += 32ull * __popc(static_cast<uint32_t>(__ballot(own)));
+                                    lane_vals += 64ull * 32;
+                                }
                                 if (own) {
                                     x += tile_chunk<L1>(tile, pf + c * 32, qp + c * 32, vv);
                                     own = !(x > cur.tau);
+                                }
+                                if (STATS) {  // rows 0 and 1 hold the wave's vectors
+                                    const uint32_t ms = static_cast<uint32_t>(__ballot(own));
+                                    if (lane == 0 && ms) atomicAdd(surv + c, (unsigned long long)__popc(ms));
                                 }
                             }
                             if (own) cand_append(cand, cand_cnt, cap, qi, x, (uint32_t)rid_v);
@@ -875,6 +899,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                 const int64_t qi = qv >> 5;
                 const int vv = qv & 31;
                 p += tile_chunk<L1>(tile, poff + qi * d + c * 32, qperm + qi * d + c * 32, vv);
+                if (STATS && !(p > tl)) atomicAdd(surv + c, 1ull);
                 ++c;
                 if (p > tl) {
                     act = false;
@@ -1324,6 +1349,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     }
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
     pl.counters = p ? p->counters : nullptr;
+    pl.surv = (p && pl.mode == PDX_MODE_BOND) ? p->chunk_survivors : nullptr;
     if (plan) *plan = pl;
     return c.bytes();
 }
@@ -1432,7 +1458,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
 #define PDX_GROUP_SCAN(P, M)                                                                                   \
     scan_kernel<P, M><<<grid, block, 0, s>>>(ix->pdx, ix->n, sid, d, gb, ge, pl.tile_groups, ntiles, nqb, pl.nq, \
                                              pl.qpb, pl.perm, pl.qperm, pl.tau, pl.bad, pl.slots, pl.nslots,     \
-                                             slot0, pl.k, pl.chunk, cnt)
+                                             slot0, pl.k, pl.chunk, cnt, P ? pl.surv : nullptr)
         if (prune) {
             if (l1) PDX_GROUP_SCAN(true, true);
             else PDX_GROUP_SCAN(true, false);
@@ -1507,10 +1533,13 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     // kernel: the centroid bound and dense pairs on the bucket layout (the
     // tile radii in the search's metric); on the flat layout every query
     // meets every tile
-    const void *tk = pl.ivf ? (l1 ? reinterpret_cast<const void *>(tile_kernel<true, true>)
-                                  : reinterpret_cast<const void *>(tile_kernel<true, false>))
-                            : (l1 ? reinterpret_cast<const void *>(tile_kernel<false, true>)
-                                  : reinterpret_cast<const void *>(tile_kernel<false, false>));
+    const bool st = pl.surv != nullptr;  // instrumentation build of the kernel
+    const void *tk;
+#define PDX_TILE_FN(DN, M) \
+    (st ? reinterpret_cast<const void *>(tile_kernel<DN, M, true>) : reinterpret_cast<const void *>(tile_kernel<DN, M, false>))
+    if (pl.ivf) tk = l1 ? PDX_TILE_FN(true, true) : PDX_TILE_FN(true, false);
+    else tk = l1 ? PDX_TILE_FN(false, true) : PDX_TILE_FN(false, false);
+#undef PDX_TILE_FN
     if (tile_lds > 64 * 1024) {
         if ((err = hipFuncSetAttribute(tk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds)) != hipSuccess)
             return err;
@@ -1524,17 +1553,25 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         const int32_t b = t0 + (int32_t)((int64_t)(t1 - t0) * (r + 1) / kRounds);
         if (b <= a) continue;
         const unsigned grid = (unsigned)min(b - a, cus);
-#define PDX_TILE(DN, M)                                                                                              \
-    tile_kernel<DN, M><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm, pl.tau, \
-                                                    pl.bad, pl.cand, pl.cand_cnt, pl.cand_cap, pl.gqueue, cmain,       \
-                                                    DN ? pl.dql : nullptr, DN ? ix->group_bucket : nullptr, trad,   \
-                                                    pl.tile_ctr + r)
-        if (pl.ivf) {
-            if (l1) PDX_TILE(true, true);
-            else PDX_TILE(true, false);
+#define PDX_TILE(DN, M, ST)                                                                                      \
+    tile_kernel<DN, M, ST><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,     \
+                                                        pl.tau, pl.bad, pl.cand, pl.cand_cnt, pl.cand_cap, pl.gqueue, \
+                                                        cmain, DN ? pl.dql : nullptr, DN ? ix->group_bucket : nullptr, \
+                                                        trad, pl.tile_ctr + r, pl.surv)
+        if (st) {
+            if (pl.ivf) {
+                if (l1) PDX_TILE(true, true, true);
+                else PDX_TILE(true, false, true);
+            } else {
+                if (l1) PDX_TILE(false, true, true);
+                else PDX_TILE(false, false, true);
+            }
+        } else if (pl.ivf) {
+            if (l1) PDX_TILE(true, true, false);
+            else PDX_TILE(true, false, false);
         } else {
-            if (l1) PDX_TILE(false, true);
-            else PDX_TILE(false, false);
+            if (l1) PDX_TILE(false, true, false);
+            else PDX_TILE(false, false, false);
         }
 #undef PDX_TILE
         if ((err = hipGetLastError()) != hipSuccess) return err;
@@ -1551,12 +1588,12 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         fallback_kernel<true><<<2048, 256, 0, s>>>(ix->pdx, ix->n, sid, d, pl.start_groups, ix->ngroups,
                                                    pl.tile_groups, pl.tiles_main, pl.over_list, pl.over_count,
                                                    pl.perm, pl.qperm, pl.tau, pl.slots, pl.nslots, pl.tiles_start,
-                                                   pl.k, pl.chunk);
+                                                   pl.k, pl.chunk, pl.surv);
     else
         fallback_kernel<false><<<2048, 256, 0, s>>>(ix->pdx, ix->n, sid, d, pl.start_groups, ix->ngroups,
                                                     pl.tile_groups, pl.tiles_main, pl.over_list, pl.over_count,
                                                     pl.perm, pl.qperm, pl.tau, pl.slots, pl.nslots, pl.tiles_start,
-                                                    pl.k, pl.chunk);
+                                                    pl.k, pl.chunk, pl.surv);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if ((err = mark(2)) != hipSuccess) return err;
     // an overflowed buffer's head: START's k best on the flat layout (rows
@@ -1579,6 +1616,27 @@ hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *
     const size_t lds = pow2 * sizeof(uint64_t) + d * sizeof(float);
     prep_kernel<<<dim3((unsigned)nq), dim3(256), lds, s>>>(q, d, means, zones ? kModeZones : PDX_MODE_BOND, pow2,
                                                            perm, qperm, tau, bad, nullptr);
+    return hipGetLastError();
+}
+
+// The visit order of pdx_query_order: the searches' own query preparation
+// (rotation of a rotated bucket layout, then prep_kernel with the index's
+// means).  order: PDX_ORDER_* (the prep_kernel modes).
+hipError_t launch_query_order(const pdx_index *ix, const float *q, int64_t nq, int32_t order, float *qrot,
+                              int32_t *perm, float *qval, uint16_t *off, uint32_t *tau, int32_t *bad,
+                              hipStream_t s) {
+    if (nq <= 0) return hipSuccess;
+    const int32_t d = ix->d;
+    const float *qs = q;
+    if (ix->kind == kIvf && ix->has_rot) {
+        const hipError_t err = launch_gemm_abt(q, nq, ix->rot, d, d, qrot, d, s);
+        if (err != hipSuccess) return err;
+        qs = qrot;
+    }
+    const int32_t pow2 = next_pow2(d);
+    const size_t lds = pow2 * sizeof(uint64_t) + d * sizeof(float);
+    const int32_t mode = order == PDX_ORDER_ZONES ? kModeZones : (order == PDX_ORDER_BOND ? PDX_MODE_BOND : PDX_MODE_LINEAR);
+    prep_kernel<<<dim3((unsigned)nq), dim3(256), lds, s>>>(qs, d, ix->means, mode, pow2, perm, qval, tau, bad, off);
     return hipGetLastError();
 }
 

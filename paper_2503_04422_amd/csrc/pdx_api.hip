@@ -200,4 +200,68 @@ pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, 
     return PDX_OK;
 }
 
+namespace {
+struct OrderWs {
+    uint32_t *tau;
+    int32_t *bad;
+    float *qrot;
+    float *qval;
+    size_t bytes;
+};
+OrderWs order_ws(const pdx_index *ix, int64_t nq, void *base) {
+    const size_t q = static_cast<size_t>(nq > 0 ? nq : 0);
+    Carver c(base);
+    OrderWs w{};
+    w.tau = c.take<uint32_t>(q);
+    w.bad = c.take<int32_t>(q);
+    w.qrot = (ix->kind == kIvf && ix->has_rot) ? c.take<float>(q * ix->d) : nullptr;
+    w.qval = c.take<float>(q * ix->d);  // used when the caller does not ask for the values
+    w.bytes = c.bytes();
+    return w;
+}
+}  // namespace
+
+size_t pdx_query_order_workspace(const pdx_index *index, int64_t nq) {
+    if (!index || (index->kind != kFlat && index->kind != kIvf) || nq < 0) return 0;
+    return order_ws(index, nq, nullptr).bytes;
+}
+
+pdx_status pdx_query_order(const pdx_index *index, const float *q, int64_t nq, int32_t order, int32_t *out_perm,
+                           float *out_qval, uint16_t *out_tile_off, void *ws, size_t ws_bytes, void *stream) {
+    if (!index || (index->kind != kFlat && index->kind != kIvf)) {
+        set_error("pdx_query_order: not an index built by pdx_build or pdx_ivf_build");
+        return PDX_EINVAL;
+    }
+    if (nq < 0 || nq > (int64_t(1) << 31) - 1) {
+        set_error("pdx_query_order: need 0 <= nq < 2^31");
+        return PDX_EINVAL;
+    }
+    if (order != PDX_ORDER_NATURAL && order != PDX_ORDER_BOND && order != PDX_ORDER_ZONES) {
+        set_error("pdx_query_order: unknown order %d", order);
+        return PDX_EINVAL;
+    }
+    if (out_tile_off && index->d * 32 >= 65536) {
+        set_error("pdx_query_order: 16-bit tile offsets need d * 32 < 65536 (d=%d)", index->d);
+        return PDX_EUNSUPPORTED;
+    }
+    if (nq == 0) return PDX_OK;
+    if (!q || !out_perm || !ws) {
+        set_error("pdx_query_order: null pointer");
+        return PDX_EINVAL;
+    }
+    if (!aligned16(q) || !aligned16(ws)) {
+        set_error("pdx_query_order: pointers must be 16-byte aligned");
+        return PDX_EINVAL;
+    }
+    OrderWs w = order_ws(index, nq, ws);
+    if (ws_bytes < w.bytes) {
+        set_error("pdx_query_order: workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
+        return PDX_EWORKSPACE;
+    }
+    hipError_t e = launch_query_order(index, q, nq, order, w.qrot, out_perm, out_qval ? out_qval : w.qval,
+                                      out_tile_off, w.tau, w.bad, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pdx_query_order");
+    return PDX_OK;
+}
+
 }  // extern "C"

@@ -121,6 +121,7 @@ struct ExactPlan {
     uint64_t *start_slots; // bucket layout: [nq][start_parts][k] START lists
     hipEvent_t *events;              // optional [4]
     unsigned long long *counters;    // optional [4]
+    unsigned long long *surv;        // optional [ceil(d / chunk)] per-chunk survivors (BOND)
 };
 
 constexpr int32_t kDefaultQueriesPerWave = 4;
@@ -240,6 +241,11 @@ int32_t ip_parts_for(int64_t nq, int32_t ngroups);
 // instead of the per-dimension one
 hipError_t launch_bond_prep(const float *q, int64_t nq, int32_t d, const float *means, bool zones, int32_t *perm,
                             float *qperm, uint32_t *tau, int32_t *bad, hipStream_t s);
+// pdx_query_order: rotation (qrot [nq][d], rotated bucket layouts only) and
+// the query preparation of the searches; off may be null
+hipError_t launch_query_order(const pdx_index *ix, const float *q, int64_t nq, int32_t order, float *qrot,
+                              int32_t *perm, float *qval, uint16_t *off, uint32_t *tau, int32_t *bad,
+                              hipStream_t s);
 // survivors at or below which a vectorgroup reads zones from the row-major
 // copy (0: never); requested 0 = 32, < 0 = never
 int32_t bond_zone_rows(int32_t d, int32_t requested);
