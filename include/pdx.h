@@ -185,6 +185,28 @@ PDX_API pdx_status pdx_search_exact(const pdx_index *index, const float *q, int6
                             const pdx_search_params *params, void *ws, size_t ws_bytes,
                             int64_t *out_ids, float *out_dist, void *stream);
 
+/* Static device scratch of pdx_search_exact_noalloc, per GPU. */
+#define PDX_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* pdx_search_exact_noalloc -- pdx_search_exact with no workspace argument,
+ * for callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * Same arguments, results and errors as pdx_search_exact, minus ws and
+ * ws_bytes: the workspace is a static device array of
+ * PDX_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU the library runs on
+ * holds until the process ends.  The call allocates nothing (no hipMalloc,
+ * no library allocator).  Returns PDX_EWORKSPACE when
+ * pdx_search_exact_workspace(...) for the same arguments exceeds the
+ * scratch (e.g. about 250 queries per call on a 1M x 960 bucket layout;
+ * search fewer queries per call).  Every call on one GPU shares that GPU's
+ * scratch and leaves its contents behind (the search initialises what it
+ * reads): calls that overlap on one GPU, on any streams or threads, race
+ * and must be serialised by the caller. */
+PDX_API pdx_status pdx_search_exact_noalloc(const pdx_index *index, const float *q, int64_t nq, int32_t k,
+                                            const pdx_search_params *params, int64_t *out_ids, float *out_dist,
+                                            void *stream);
+
 /* Dimension visit orders (pdx_query_order). */
 enum {
     PDX_ORDER_NATURAL = 0, /* stored dimension order (linear scan, ADSampling) */

@@ -22,6 +22,7 @@ PDX_EHIP = -3
 PDX_EUNSUPPORTED = -4
 PDX_MAX_K = 64
 PDX_MAX_DIM = 4096
+PDX_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 PDX_MODE_LINEAR = 0
 PDX_MODE_BOND = 1
@@ -97,6 +98,8 @@ SIGNATURES = {
     "pdx_search_exact": (c_int32, [c_void_p, c_void_p, c_int64, c_int32,
                                    ctypes.POINTER(pdx_search_params), c_void_p, c_size_t,
                                    c_void_p, c_void_p, c_void_p]),
+    "pdx_search_exact_noalloc": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(pdx_search_params),
+                                           c_void_p, c_void_p, c_void_p]),
     "pdx_query_order_workspace": (c_size_t, [c_void_p, c_int64]),
     "pdx_query_order": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_size_t, c_void_p]),
