@@ -584,6 +584,8 @@ __device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, cons
 
 // One octet (8 visited dimensions) of a chunk for the tile's vectors p and
 // p + 16: each dimension's LDS row address serves both (one paired read).
+// All 8 paired reads are issued before the first sum, so a chunk waits for
+// one LDS round trip rather than one per pair of dimensions.
 template <bool L1>
 __device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4 ow, float4 q0, float4 q1, int p,
                                            float &a, float &b) {
@@ -591,13 +593,19 @@ __device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4
     unpack_off(ow.x, ow.y, *reinterpret_cast<int(*)[4]>(o));
     unpack_off(ow.z, ow.w, *reinterpret_cast<int(*)[4]>(o + 4));
     const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    float ra[8], rb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float *r = tile + o[u] + p;
+        ra[u] = r[0];
+        rb[u] = r[16];
+    }
     a = 0.0f;
     b = 0.0f;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        const float *r = tile + o[u] + p;
-        a = dist_term<L1>(a, qv[u] - r[0]);
-        b = dist_term<L1>(b, qv[u] - r[16]);
+        a = dist_term<L1>(a, qv[u] - ra[u]);
+        b = dist_term<L1>(b, qv[u] - rb[u]);
     }
 }
 
@@ -656,11 +664,19 @@ constexpr int kDense = 8;  // survivors of the first chunk from which a (query, 
 // queries that remain are listed in LDS, kList at a time, and the waves
 // take them from the list.
 constexpr int kList = 1024;
+constexpr int kTileWaves = 16;  // waves per workgroup of the L2/L1 tile scan (kList is a multiple of their threads)
 typedef __attribute__((address_space(3))) void lds_void_t;  // LDS destination of direct loads
 
 // STATS (instrumentation build only): per-chunk survivor counts in surv.
-template <bool DENSE, bool L1, bool STATS>
-__global__ __launch_bounds__(1024) void tile_kernel(
+// NW waves per workgroup.  Per tile three barriers: after the staging loads
+// and the query list (built while the loads are in flight), before the
+// survivor queue, and at the end; the counters of a tile alternate between
+// two sets so the next tile's are cleared while this one's are in use.
+// Waves take the listed queries from an LDS counter (the next one is
+// claimed, and its first-chunk metadata loaded, while the current one is
+// scanned), so a wave that meets cheap queries takes more of them.
+template <bool DENSE, bool L1, bool STATS, int NW>
+__global__ __launch_bounds__(NW * 64) void tile_kernel(
     const float *__restrict__ pdxd, int64_t n, const int32_t *__restrict__ slot_id, int32_t d, int32_t t_begin,
     int32_t t_end, int64_t nq,
     const uint16_t *__restrict__ poff, const float *__restrict__ qperm, const uint32_t *__restrict__ tau,
@@ -668,10 +684,11 @@ __global__ __launch_bounds__(1024) void tile_kernel(
     uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters, const float *__restrict__ dql,
     const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad, int32_t *__restrict__ tile_ctr,
     unsigned long long *__restrict__ surv) {
+    constexpr int NT = NW * 64;
     extern __shared__ float4 smem4[];
     float *tile = reinterpret_cast<float *>(smem4);                          // [d][32]
     uint2 *queue = reinterpret_cast<uint2 *>(tile + (size_t)d * kTV);        // [kQCap]
-    __shared__ int32_t qcount, qhead, lcount, next_t;
+    __shared__ int32_t qcount[2], qhead[2], lcount[2], qnext[2], next_t[2];
     __shared__ int32_t qlist[DENSE ? kList : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -681,33 +698,64 @@ __global__ __launch_bounds__(1024) void tile_kernel(
     uint64_t *gq = gqueue + (size_t)blockIdx.x * kGCap;  // this workgroup's overflow entries
     unsigned long long live_vals = 0, lane_vals = 0;
 
+    // the queries of [q0, q0 + kList) the centroid bound keeps for tile
+    // (bucket tb, radius trad), appended to qlist (lcount[p] zero before)
+    auto build_list = [&](int p, int64_t q0, int32_t tb, float trad) {
+#pragma unroll
+        for (int j = 0; j < kList / NT; ++j) {
+            const int64_t qt = q0 + j * NT + threadIdx.x;
+            bool keep = false;
+            if (qt < nq && !bad[qt]) {
+                const float gap = fmaxf(dql[(int64_t)tb * nq + qt] - trad, 0.0f);
+                const float tq = __uint_as_float(__hip_atomic_load(tau + qt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                keep = L1 ? !(gap > tq) : !(gap * gap > tq);  // L1: the bound is the gap itself
+            }
+            const unsigned long long km = __ballot(keep);
+            int lb = 0;
+            if (lane == 0 && km) lb = atomicAdd(&lcount[p], __popcll(km));
+            lb = __shfl(lb, 0);
+            if (keep) qlist[lb + lane_rank(km)] = (int32_t)qt;
+        }
+    };
+
+    if (threadIdx.x == 0) {
+        next_t[0] = t_begin + atomicAdd(tile_ctr, 1);
+        qcount[0] = qhead[0] = lcount[0] = qnext[0] = 0;
+    }
+    __syncthreads();
     // tiles are taken from a counter shared by the launch's workgroups, so
     // workgroups that meet cheap tiles take more (tile costs vary widely)
-    for (;;) {
-        if (threadIdx.x == 0) next_t = t_begin + atomicAdd(tile_ctr, 1);
-        __syncthreads();  // every thread read the previous value before the last barrier of the loop
-        const int32_t t = next_t;
+    for (int p = 0;; p ^= 1) {
+        const int32_t t = next_t[p];
         if (t >= t_end) break;
+        if (threadIdx.x == 0) {  // the other set is free: every thread passed the barrier that ended its tile
+            next_t[p ^ 1] = t_begin + atomicAdd(tile_ctr, 1);
+            qcount[p ^ 1] = qhead[p ^ 1] = lcount[p ^ 1] = qnext[p ^ 1] = 0;
+        }
         // stage 32 vectors x d dimensions (one 128-byte half row per
         // dimension) with direct global-to-LDS loads: a wave's 64 lanes
         // bring 16 bytes each into 1 KB of contiguous LDS, 8 tile rows, with
         // no registers holding the data, so every piece is in flight at once
         const float *src = pdxd + (int64_t)(t >> 1) * d * kGroup + (t & 1) * kTV;
-        const int32_t nv4 = d * 8;  // a multiple of 256: whole waves
-        for (int32_t iw = wave * 64; iw < nv4; iw += 1024) {
+        const int32_t nv4 = d * 8;  // a multiple of 64: whole waves
+        for (int32_t iw = wave * 64; iw < nv4; iw += NT) {
             const int32_t i = iw + lane;
             __builtin_amdgcn_global_load_lds(src + (int64_t)(i >> 3) * kGroup + (i & 7) * 4,
                                              (lds_void_t *)(tile + (size_t)iw * 4), 16, 0, 0);
         }
-        if (threadIdx.x == 0) {
-            qcount = 0;
-            qhead = 0;
-        }
-        __syncthreads();
-        // row ids of the pair (-1: padding)
+        // while the loads are in flight: the pair's row ids (-1: padding)
+        // and the first list of queries
         const int64_t vid_a = (int64_t)t * kTV + pr, vid_b = vid_a + 16;
         const int32_t rid_a = slot_id ? slot_id[vid_a] : (vid_a < n ? (int32_t)vid_a : -1);
         const int32_t rid_b = slot_id ? slot_id[vid_b] : (vid_b < n ? (int32_t)vid_b : -1);
+        int32_t tb = 0;
+        float trad = 0.0f;
+        if (DENSE) {
+            tb = group_bucket[t >> 1];
+            trad = tile_rad[t];
+            build_list(p, 0, tb, trad);
+        }
+        __syncthreads();  // tile staged, first list complete
         const uint32_t valid_m = pair_mask(rid_a >= 0, rid_b >= 0);
         const int32_t rid_v = (oct & 1) ? rid_b : rid_a;  // row id of this lane's vector
 
@@ -715,41 +763,39 @@ __global__ __launch_bounds__(1024) void tile_kernel(
         // octets.  The next query's first-chunk metadata is loaded while the
         // current one is scanned (one query per wave in flight otherwise
         // stalls on memory latency).
-        int32_t tb = 0;
-        float trad = 0.0f;
-        if (DENSE) {
-            tb = group_bucket[t >> 1];
-            trad = tile_rad[t];
-        }
         for (int64_t q0 = 0; q0 < nq; q0 += (DENSE ? kList : nq)) {
           int32_t cnt = (int32_t)nq;
           if (DENSE) {
-            // the queries of [q0, q0 + kList) the centroid bound keeps
-            __syncthreads();  // the previous list is no longer read
-            if (threadIdx.x == 0) lcount = 0;
-            __syncthreads();
-            const int64_t qt = q0 + threadIdx.x;
-            bool keep = false;
-            if (threadIdx.x < kList && qt < nq && !bad[qt]) {
-                const float gap = fmaxf(dql[(int64_t)tb * nq + qt] - trad, 0.0f);
-                const float tq = __uint_as_float(__hip_atomic_load(tau + qt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                keep = L1 ? !(gap > tq) : !(gap * gap > tq);  // L1: the bound is the gap itself
+            if (q0 > 0) {  // a later block of kList queries: rebuild the list
+                __syncthreads();  // the previous list is no longer read
+                if (threadIdx.x == 0) lcount[p] = qnext[p] = 0;
+                __syncthreads();
+                build_list(p, q0, tb, trad);
+                __syncthreads();
             }
-            const unsigned long long km = __ballot(keep);
-            int lb = 0;
-            if (lane == 0 && km) lb = atomicAdd(&lcount, __popcll(km));
-            lb = __shfl(lb, 0);
-            if (keep) qlist[lb + lane_rank(km)] = (int32_t)qt;
-            __syncthreads();
-            cnt = lcount;
+            cnt = lcount[p];
           }
           auto qid = [&](int32_t e) -> int64_t { return DENSE ? (int64_t)qlist[e] : (int64_t)e; };
+          auto claim = [&]() -> int32_t {
+              int32_t v = 0;
+              if (lane == 0) v = atomicAdd(&qnext[p], 1);
+              return __builtin_amdgcn_readfirstlane(v);
+          };
           FirstChunk cur, nxt;
-          if (wave < cnt) cur.load(poff, qperm, tau, bad, qid(wave), d, oct);
-          for (int32_t e = wave; e < cnt; e += kTW) {
+          int32_t e = claim();
+          if (e < cnt) cur.load(poff, qperm, tau, bad, qid(e), d, oct);
+          while (e < cnt) {
             const int64_t qi = qid(e);
-            if (e + kTW < cnt) nxt.load(poff, qperm, tau, bad, qid(e + kTW), d, oct);
+            const int32_t en = claim();
+            if (en < cnt) nxt.load(poff, qperm, tau, bad, qid(en), d, oct);
             if (!cur.bad) {
+                // the second chunk's metadata, needed if the pair turns out
+                // dense (almost every listed pair on the bucket layout), is
+                // requested before the first chunk is summed
+                const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + oct * 8);
+                const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + oct * 8);
+                uint4 oa;
+                float4 qa0, qa1;
                 float sa, sb;
                 octet_pair<L1>(tile, cur.o, cur.q[0], cur.q[1], pr, sa, sb);
                 // this lane's vector (pr in rows 0 and 2, pr + 16 in rows 1 and 3)
@@ -768,8 +814,6 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                     // current one is summed
                     bool al = al1;
                     float x = p1;
-                    const uint4 *o4 = reinterpret_cast<const uint4 *>(poff + qi * d + oct * 8);
-                    const float4 *q4 = reinterpret_cast<const float4 *>(qperm + qi * d + oct * 8);
                     auto dense_step = [&](int32_t c, const uint4 oc, const float4 qc0, const float4 qc1) {
                         float ta, tb2;
                         if (counters) {  // the vectors still alive evaluate this chunk
@@ -786,10 +830,12 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                     };
                     // two metadata sets in turn (chunks c and c + 1), so a
                     // prefetched set is used where it landed, never copied
-                    uint4 oa = o4[4];
-                    float4 qa0 = q4[8], qa1 = q4[9];
-                    uint4 ob = oa;
-                    float4 qb0 = qa0, qb1 = qa1;
+                    // (the second set is first written before its first use)
+                    oa = o4[4];
+                    qa0 = q4[8];
+                    qa1 = q4[9];
+                    uint4 ob;
+                    float4 qb0, qb1;
                     for (int32_t c = 1; c < nchunks; c += 2) {
                         if (!__any(al)) break;
                         if (c + 1 < nchunks) {
@@ -812,7 +858,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                         if (oct < 2 && al1) cand_append(cand, cand_cnt, cap, qi, p1, (uint32_t)rid_v);
                     } else {
                         int base = 0;
-                        if (lane == 0) base = atomicAdd(&qcount, __popc(m));
+                        if (lane == 0) base = atomicAdd(&qcount[p], __popc(m));
                         base = __shfl(base, 0);
                         // queue slot of vector v: base + the survivors below
                         // v; rows 0 and 1 enqueue their vectors
@@ -853,21 +899,22 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                 }
             }
             cur = nxt;
+            e = en;
           }
         }
         __syncthreads();
 
         // Phase B: persistent lanes finish the queued (query, vector) pairs
-        const int32_t total = min(qcount, kQCap + kGCap);
+        const int32_t total = min(qcount[p], kQCap + kGCap);
         bool act = false;
         uint32_t qv = 0;
-        float p = 0.0f, tl = 0.0f;
+        float pq = 0.0f, tl = 0.0f;
         int32_t c = 0;
         while (true) {
             const unsigned long long idle = __ballot(!act);
             if (idle) {
                 int b = 0;
-                if (lane == 0) b = atomicAdd(&qhead, __popcll(idle));
+                if (lane == 0) b = atomicAdd(&qhead[p], __popcll(idle));
                 b = __shfl(b, 0);
                 if (!act) {
                     const int idx = b + lane_rank(idle);
@@ -875,13 +922,13 @@ __global__ __launch_bounds__(1024) void tile_kernel(
                         if (idx < kQCap) {
                             const uint2 en = queue[idx];
                             qv = en.x;
-                            p = __uint_as_float(en.y);
+                            pq = __uint_as_float(en.y);
                         } else {
                             // written by other waves of this workgroup: read past the L1
                             const uint64_t en = __hip_atomic_load(gq + (idx - kQCap), __ATOMIC_RELAXED,
                                                                   __HIP_MEMORY_SCOPE_AGENT);
                             qv = static_cast<uint32_t>(en);
-                            p = __uint_as_float(static_cast<uint32_t>(en >> 32));
+                            pq = __uint_as_float(static_cast<uint32_t>(en >> 32));
                         }
                         c = 1;
                         act = true;
@@ -898,19 +945,19 @@ __global__ __launch_bounds__(1024) void tile_kernel(
             if (act) {
                 const int64_t qi = qv >> 5;
                 const int vv = qv & 31;
-                p += tile_chunk<L1>(tile, poff + qi * d + c * 32, qperm + qi * d + c * 32, vv);
-                if (STATS && !(p > tl)) atomicAdd(surv + c, 1ull);
+                pq += tile_chunk<L1>(tile, poff + qi * d + c * 32, qperm + qi * d + c * 32, vv);
+                if (STATS && !(pq > tl)) atomicAdd(surv + c, 1ull);
                 ++c;
-                if (p > tl) {
+                if (pq > tl) {
                     act = false;
                 } else if (c == nchunks) {
                     const int64_t sv = (int64_t)t * kTV + vv;
-                    cand_append(cand, cand_cnt, cap, qi, p, (uint32_t)(slot_id ? slot_id[sv] : sv));
+                    cand_append(cand, cand_cnt, cap, qi, pq, (uint32_t)(slot_id ? slot_id[sv] : sv));
                     act = false;
                 }
             }
         }
-        __syncthreads();
+        __syncthreads();  // the tile, the queue and the list are free
     }
     if (counters && lane == 0) {
         atomicAdd(counters, live_vals);
@@ -1155,13 +1202,19 @@ __global__ __launch_bounds__(256) void ip_fallback_kernel(const float *__restric
 __device__ __forceinline__ void octet_pair_ip(const float *__restrict__ tile, int32_t j, float4 q0, float4 q1, int p,
                                               float &a, float &b) {
     const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    float ra[8], rb[8];  // all reads issued before the first product
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float *r = tile + (j + u) * kTV + p;
+        ra[u] = r[0];
+        rb[u] = r[16];
+    }
     a = 0.0f;
     b = 0.0f;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        const float *r = tile + (j + u) * kTV + p;
-        a = fmaf(qv[u], r[0], a);
-        b = fmaf(qv[u], r[16], b);
+        a = fmaf(qv[u], ra[u], a);
+        b = fmaf(qv[u], rb[u], b);
     }
 }
 
@@ -1535,8 +1588,9 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     // meets every tile
     const bool st = pl.surv != nullptr;  // instrumentation build of the kernel
     const void *tk;
-#define PDX_TILE_FN(DN, M) \
-    (st ? reinterpret_cast<const void *>(tile_kernel<DN, M, true>) : reinterpret_cast<const void *>(tile_kernel<DN, M, false>))
+#define PDX_TILE_FN(DN, M)                                                         \
+    (st ? reinterpret_cast<const void *>(tile_kernel<DN, M, true, kTileWaves>) \
+        : reinterpret_cast<const void *>(tile_kernel<DN, M, false, kTileWaves>))
     if (pl.ivf) tk = l1 ? PDX_TILE_FN(true, true) : PDX_TILE_FN(true, false);
     else tk = l1 ? PDX_TILE_FN(false, true) : PDX_TILE_FN(false, false);
 #undef PDX_TILE_FN
@@ -1554,7 +1608,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         if (b <= a) continue;
         const unsigned grid = (unsigned)min(b - a, cus);
 #define PDX_TILE(DN, M, ST)                                                                                      \
-    tile_kernel<DN, M, ST><<<grid, 1024, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,     \
+    tile_kernel<DN, M, ST, kTileWaves><<<grid, kTileWaves * 64, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,     \
                                                         pl.tau, pl.bad, pl.cand, pl.cand_cnt, pl.cand_cap, pl.gqueue, \
                                                         cmain, DN ? pl.dql : nullptr, DN ? ix->group_bucket : nullptr, \
                                                         trad, pl.tile_ctr + r, pl.surv)
