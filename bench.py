@@ -143,6 +143,8 @@ def build_ivf(pdx, torch, np, x_dev, nlist, seed=42, **kw):
     rng = np.random.default_rng(seed)
     gauss = torch.from_numpy(rng.standard_normal((d, d))).cuda()
     init = torch.from_numpy(rng.choice(n, nlist, replace=False).astype(np.int64)).cuda()
+    if kw.get("rotation_kind") == "pca":
+        gauss = None
     t0 = time.perf_counter()
     ix = pdx.pdx_ivf_build(x_dev, nlist, gauss, init, kmeans_iters=20, **kw)
     torch.cuda.synchronize()
@@ -637,6 +639,7 @@ def main() -> int:
     ap.add_argument("--no-ivf", action="store_true", help="skip the IVF + ADSampling leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned early-termination leg")
     ap.add_argument("--no-metrics", action="store_true", help="skip the L1 / inner-product leg")
+    ap.add_argument("--no-pca", action="store_true", help="skip the PCA-rotation IVF leg")
     ap.add_argument("--nprobe", type=int, nargs="*", default=None, help="IVF workloads: nprobe values to run")
     ap.add_argument("--flat", action="store_true", help="exact search on the flat layout instead of buckets")
     ap.add_argument("--exact-nlist", type=int, default=1024, help="buckets of the exact search's layout")
@@ -847,6 +850,16 @@ def main() -> int:
         ivf_ix = build_ivf(pdx, torch, np, x, 1024)
         extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, [2, 4, 8, 16, 32, 64], k, 3, 1, truth, index=ivf_ix)
         extra["approx_bond_bound"] = bench_bond_ivf(pdx, torch, np, ivf_ix[0], q, [8, 16, 32], k, 3, 1, truth)
+        if not args.no_pca:
+            # BSA's projection (Section 2.3): the rows' principal directions in
+            # place of the random rotation, same k-means seeds, same searches
+            pca_ix = build_ivf(pdx, torch, np, x, 1024, rotation_kind="pca")
+            extra["approx_pca"] = bench_ivf(pdx, torch, np, x, q, 1024, [2, 4, 8, 16, 32, 64], k, 3, 1, truth,
+                                            index=pca_ix)
+            extra["approx_pca"]["rotation"] = "pca"
+            extra["approx_pca_bond_bound"] = bench_bond_ivf(pdx, torch, np, pca_ix[0], q, [8, 16, 32], k, 3, 1,
+                                                            truth)
+            del pca_ix
         if not args.no_learned:
             extra["learned_stop"] = bench_learned(pdx, torch, np, ivf_ix[0], ix, x_np, mix, k, 3, 1,
                                                   0 if args.no_cpu_baseline else args.cpu_seconds)

@@ -267,7 +267,20 @@ typedef struct {
     const float *rotation;  /* [d][d] used as is (overrides gaussian)     */
     const float *centroids; /* [nlist][d], in rotated space: skip k-means */
     const int32_t *assign;  /* [n] bucket of each row (needs centroids)   */
+    /* Rotation kind (ignored when `rotation` is given):                    */
+    int32_t rotation_kind;  /* PDX_ROTATION_RANDOM: Q of the QR of `gaussian`
+                               (none when gaussian is NULL); PDX_ROTATION_PCA:
+                               the principal directions of the rows, largest
+                               variance first (BSA's PCA projection, Section
+                               2.3, in place of the random one): float32
+                               covariance, cyclic Jacobi sweeps, the float64
+                               Householder QR to re-orthonormalise, rows
+                               ordered by their Rayleigh quotient; gaussian
+                               is then unused                                */
+    int32_t pca_iters;      /* PCA: Jacobi sweeps; 0 = 12                    */
 } pdx_ivf_params;
+
+enum { PDX_ROTATION_RANDOM = 0, PDX_ROTATION_PCA = 1 };
 
 PDX_API size_t pdx_ivf_build_bytes(int64_t n, int32_t d, int32_t nlist, const pdx_ivf_params *params);
 

@@ -1,4 +1,5 @@
-"""Random orthogonal rotation -- oracle (test infrastructure).
+"""Random orthogonal rotation and PCA rotation -- oracle (test
+infrastructure).
 
 Section 2.3 (ADSampling) and Section 7: the collection and the queries are
 transformed by one random orthogonal matrix, which preserves Euclidean
@@ -7,6 +8,15 @@ used here is the standard Haar construction: QR-factorise a matrix of iid
 standard normal entries (drawn by the caller and passed in) and flip the
 sign of every column of Q whose diagonal entry of R is negative.  A
 vector v is rotated as R v (rows: X R^T).
+
+Section 2.3 (BSA): a PCA projection of the collection in place of the
+random one.  Its rows are the eigenvectors of the rows' covariance
+(1/n) sum (x - mean)(x - mean)^T, largest eigenvalue first; each row's sign
+is fixed so that its largest-magnitude entry (the first of equal ones) is
+positive.  Parity unpinned for the GPU's rows themselves where eigenvalues
+are (nearly) equal: any orthonormal basis of such an eigenspace is a
+correct answer, so the GPU is checked by what is unique (orthogonality,
+the variance each leading block of rows captures, the order by variance).
 """
 from __future__ import annotations
 
@@ -46,3 +56,26 @@ def householder_qr(g: np.ndarray):
         a[j:, :] -= 2.0 * np.outer(v, v @ a[j:, :])
         qacc[:, j:] -= 2.0 * np.outer(qacc[:, j:] @ v, v)
     return qacc, np.triu(a)
+
+
+def pca_rotation(x: np.ndarray):
+    """(R, eigenvalues): the rows' principal directions as the rows of R,
+    by non-increasing eigenvalue of the float64 covariance (population
+    form, 1/n), each row signed so its largest-magnitude entry is positive."""
+    x = np.asarray(x, dtype=np.float64)
+    xc = x - x.mean(axis=0)
+    cov = xc.T @ xc / x.shape[0]
+    lam, vec = np.linalg.eigh(cov)          # ascending
+    order = np.argsort(-lam, kind="stable")
+    lam, r = lam[order], vec[:, order].T    # rows = eigenvectors
+    lead = np.argmax(np.abs(r), axis=1)
+    sign = np.sign(r[np.arange(r.shape[0]), lead])
+    sign[sign == 0] = 1.0
+    return r * sign[:, None], lam
+
+
+def covariance(x: np.ndarray) -> np.ndarray:
+    """Population covariance (1/n) of the rows, float64."""
+    x = np.asarray(x, dtype=np.float64)
+    xc = x - x.mean(axis=0)
+    return xc.T @ xc / x.shape[0]

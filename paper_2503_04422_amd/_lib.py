@@ -38,6 +38,9 @@ PDX_ORDER_ZONES = 2
 PDX_LAYOUT_NARY = 0
 PDX_LAYOUT_PDX = 1
 
+PDX_ROTATION_RANDOM = 0
+PDX_ROTATION_PCA = 1
+
 PDX_DTYPE_F32 = 0
 PDX_DTYPE_BF16 = 1
 PDX_DTYPE_FP8 = 2
@@ -67,7 +70,7 @@ class pdx_search_params(ctypes.Structure):
 class pdx_ivf_params(ctypes.Structure):
     _fields_ = [("kmeans_iters", c_int32), ("lowp_mask", c_int32), ("gaussian", c_void_p),
                 ("init_rows", c_void_p), ("rotation", c_void_p), ("centroids", c_void_p),
-                ("assign", c_void_p)]
+                ("assign", c_void_p), ("rotation_kind", c_int32), ("pca_iters", c_int32)]
 
 
 class pdx_ivf_search_params(ctypes.Structure):

@@ -193,9 +193,13 @@ def pdx_query_order(index: PdxIndex, q: torch.Tensor, order: str = "bond", tile_
 def pdx_ivf_build(x: torch.Tensor, nlist: int, gaussian: Optional[torch.Tensor],
                   init_rows: Optional[torch.Tensor], kmeans_iters: int = 0, lowp: Tuple[str, ...] = (),
                   rotation: Optional[torch.Tensor] = None, centroids: Optional[torch.Tensor] = None,
-                  assign: Optional[torch.Tensor] = None,
+                  assign: Optional[torch.Tensor] = None, rotation_kind: str = "random", pca_iters: int = 0,
                   stream: Optional[torch.cuda.Stream] = None) -> PdxIndex:
-    """IVF index over randomly rotated rows; buckets stored as PDX groups."""
+    """IVF index over rotated rows; buckets stored as PDX groups.
+    rotation_kind "random": the Q of the QR of ``gaussian`` (no rotation
+    when it is None); "pca": the rows' principal directions, largest
+    variance first (``gaussian`` unused); a given ``rotation`` overrides
+    both."""
     x = _dev_f32(x, "x")
     n, d = x.shape
     keep = [t.contiguous() if t is not None else None for t in (gaussian, init_rows, rotation, centroids, assign)]
@@ -211,7 +215,11 @@ def pdx_ivf_build(x: torch.Tensor, nlist: int, gaussian: Optional[torch.Tensor],
         if name not in ("bf16", "fp8"):
             raise ValueError(f"unknown low-precision storage {name!r}")
         mask |= 1 << _DTYPES[name]
-    p = _lib.pdx_ivf_params(int(kmeans_iters), mask, _ptr(g), _ptr(ir), _ptr(rot), _ptr(cen), _ptr(asg))
+    kinds = {"random": _lib.PDX_ROTATION_RANDOM, "pca": _lib.PDX_ROTATION_PCA}
+    if rotation_kind not in kinds:
+        raise ValueError(f"unknown rotation_kind {rotation_kind!r}")
+    p = _lib.pdx_ivf_params(int(kmeans_iters), mask, _ptr(g), _ptr(ir), _ptr(rot), _ptr(cen), _ptr(asg),
+                            kinds[rotation_kind], int(pca_iters))
     nbytes = lib.pdx_ivf_build_bytes(n, d, nlist, ctypes.byref(p))
     if nbytes == 0:
         raise ValueError(f"unsupported IVF shape n={n} d={d} nlist={nlist}")

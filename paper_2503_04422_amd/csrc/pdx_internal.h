@@ -295,6 +295,17 @@ hipError_t launch_bucketize(const float *xrot, int64_t n, int32_t d, const int32
                             int32_t *blk_cnt, int32_t *size, int32_t *goff, int32_t *stats, int32_t *slot_id,
                             int64_t max_slots, float *pdx, int64_t max_groups, hipStream_t s);
 
+// PCA rotation (k_pca.hip): float32 covariance of the rows x (mu: their
+// column means), cyclic Jacobi sweeps, the float64 QR to re-orthonormalise,
+// rows by Rayleigh quotient; scratch sized by pca_part_floats (part),
+// d x d (cov, h, r2, tmp), d x d float64 (w64, acm, qd), d (v, diag, rho,
+// perm), 3 d (cs).
+size_t pca_part_floats(int64_t n, int32_t d);
+hipError_t launch_pca_rotation(const float *x, int64_t n, int32_t d, int32_t sweeps, const float *mu, float *part,
+                               float *cov, float *h, float *r2, double *w64, double *acm, double *qd, double *v,
+                               double *diag, float *tmp, float *rho, int32_t *perm, float *cs, float *rot,
+                               hipStream_t s);
+
 size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_params *p,
                   void *ws, ExactPlan *plan);
 hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &plan,

@@ -20,11 +20,14 @@ struct IvfLayout {
     int32_t *list_size, *list_goff, *stats, *assign, *slot_id, *cnt, *blk_cnt, *flag, *group_bucket;
     unsigned long long *best;
     double *sums, *acm, *qd, *v, *diag, *mean_partial;
+    float *pca_part, *pca_cov, *pca_h, *pca_r2, *pca_tmp, *pca_rho, *pca_cs;  // PCA rotation scratch (pca only)
+    double *pca_w64;
+    int32_t *pca_perm;
     int64_t max_groups;
     size_t bytes;
 };
 
-IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, void *base) {
+IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, bool pca, void *base) {
     IvfLayout l{};
     l.max_groups = (n + kGroup - 1) / kGroup + nlist;
     int64_t nblocks = (n + kRowsPerBlock - 1) / kRowsPerBlock;
@@ -60,6 +63,17 @@ IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, voi
     l.diag = c.take<double>(d);
     l.flag = c.take<int32_t>(64);
     l.mean_partial = c.take<double>((size_t)kMeanChunksIvf * d);
+    if (pca) {
+        l.pca_part = c.take<float>(pca_part_floats(n, d));
+        l.pca_cov = c.take<float>((size_t)d * d);
+        l.pca_h = c.take<float>((size_t)d * d);
+        l.pca_r2 = c.take<float>((size_t)d * d);
+        l.pca_tmp = c.take<float>((size_t)d * d);
+        l.pca_w64 = c.take<double>((size_t)d * d);
+        l.pca_rho = c.take<float>(d);
+        l.pca_perm = c.take<int32_t>(d);
+        l.pca_cs = c.take<float>((size_t)3 * d);
+    }
     l.bytes = c.bytes();
     return l;
 }
@@ -98,7 +112,11 @@ size_t pdx_ivf_build_bytes(int64_t n, int32_t d, int32_t nlist, const pdx_ivf_pa
     (void)params;
     if (!valid_shape(n, d, nlist)) return 0;
     if (params && (params->lowp_mask & ~((1 << PDX_DTYPE_BF16) | (1 << PDX_DTYPE_FP8)))) return 0;
-    return ivf_layout(n, d, nlist, params ? params->lowp_mask : 0, nullptr).bytes;
+    if (params && (params->rotation_kind < PDX_ROTATION_RANDOM || params->rotation_kind > PDX_ROTATION_PCA ||
+                   params->pca_iters < 0))
+        return 0;
+    const bool pca = params && !params->rotation && params->rotation_kind == PDX_ROTATION_PCA;
+    return ivf_layout(n, d, nlist, params ? params->lowp_mask : 0, pca, nullptr).bytes;
 }
 
 pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, const pdx_ivf_params *params,
@@ -134,7 +152,13 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
         set_error("pdx_ivf_build: pointers must be 16-byte aligned");
         return PDX_EINVAL;
     }
-    IvfLayout L = ivf_layout(n, d, nlist, params->lowp_mask, index_mem);
+    if (params->rotation_kind < PDX_ROTATION_RANDOM || params->rotation_kind > PDX_ROTATION_PCA ||
+        params->pca_iters < 0) {
+        set_error("pdx_ivf_build: unknown rotation_kind %d or negative pca_iters", params->rotation_kind);
+        return PDX_EINVAL;
+    }
+    const bool pca = !params->rotation && params->rotation_kind == PDX_ROTATION_PCA;
+    IvfLayout L = ivf_layout(n, d, nlist, params->lowp_mask, pca, index_mem);
     if (index_bytes < L.bytes) {
         set_error("pdx_ivf_build: index buffer has %zu bytes, needs %zu", index_bytes, L.bytes);
         return PDX_EWORKSPACE;
@@ -156,6 +180,13 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     int32_t has_rot = 1;
     if (params->rotation) {
         TRY(hipMemcpyAsync(L.rot, params->rotation, sizeof(float) * d * d, hipMemcpyDeviceToDevice, s));
+    } else if (pca) {
+        // the rows' column means (into the means slot, rewritten below for
+        // the rotated rows), then the principal directions
+        TRY(launch_column_means(x, n, d, L.mean_partial, kMeanChunksIvf, L.means, s));
+        TRY(launch_pca_rotation(x, n, d, params->pca_iters > 0 ? params->pca_iters : 12, L.means, L.pca_part,
+                                L.pca_cov, L.pca_h, L.pca_r2, L.pca_w64, L.acm, L.qd, L.v, L.diag, L.pca_tmp,
+                                L.pca_rho, L.pca_perm, L.pca_cs, L.rot, s));
     } else if (params->gaussian) {
         TRY(launch_qr_rotation(params->gaussian, d, L.acm, L.qd, L.v, L.diag, L.rot, s));
     } else {

@@ -45,6 +45,10 @@ def test_host_side_argument_errors():
     assert lib.pdx_search_ivf(None, None, 1, 10, 1, None, None, 0, None, None, None) == _lib.PDX_EINVAL
     assert lib.pdx_query_order(None, None, 1, 1, None, None, None, None, 0, None) == _lib.PDX_EINVAL
     assert lib.pdx_query_order_workspace(None, 1) == 0
+    bad_rot = _lib.pdx_ivf_params(0, 0, None, None, None, None, None, 7, 0)
+    assert lib.pdx_ivf_build_bytes(64, 8, 2, ctypes.byref(bad_rot)) == 0
+    pca = _lib.pdx_ivf_params(0, 0, None, None, None, None, None, _lib.PDX_ROTATION_PCA, 0)
+    assert lib.pdx_ivf_build_bytes(64, 8, 2, ctypes.byref(pca)) > lib.pdx_ivf_build_bytes(64, 8, 2, None)
     assert lib.pdx_version().startswith(b"pdx ")
 
 

@@ -73,3 +73,35 @@ def test_kmeans_invariants():
             np.testing.assert_allclose(x[m].astype(np.float64).mean(0), c[i], atol=1e-12)
     # a planted mistake (labels shifted by one bucket) is caught
     assert kmeans.check_nearest(x, c, (lab + 1) % 20) > 0
+
+
+def test_pca_rotation_hand_worked():
+    """Section 2.3 (BSA's PCA projection): hand-worked 2-D case."""
+    from tests.conftest import golden
+    g = golden("hand_pca.json")
+    r, lam = rotation.pca_rotation(np.array(g["x"]))
+    np.testing.assert_allclose(lam, g["eigenvalues"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r, g["rotation"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(rotation.rotate_rows(np.array(g["x"]), r), g["rotated"], rtol=0, atol=1e-12)
+
+
+def test_pca_rotation_against_svd_and_invariants():
+    """The principal directions equal the right singular vectors of the
+    centred rows (a library routine, up to sign) with eigenvalues s^2 / n;
+    the rotation is orthogonal; the rotated covariance is diagonal with
+    non-increasing variances; a planted ascending order is caught."""
+    rng = np.random.default_rng(9)
+    n, d = 3000, 24
+    scale = np.linspace(3.0, 0.2, d)
+    x = rng.standard_normal((n, d)) * scale[None, :] @ rotation.orthogonal_from_gaussian(rng.standard_normal((d, d)))
+    r, lam = rotation.pca_rotation(x)
+    np.testing.assert_allclose(r @ r.T, np.eye(d), atol=1e-12)
+    xc = x - x.mean(axis=0)
+    _, s, vt = np.linalg.svd(xc, full_matrices=False)
+    np.testing.assert_allclose(lam, s ** 2 / n, rtol=1e-10)
+    np.testing.assert_allclose(np.abs(np.sum(r * vt, axis=1)), 1.0, atol=1e-9)  # same directions
+    cr = rotation.covariance(rotation.rotate_rows(x, r))
+    np.testing.assert_allclose(cr, np.diag(lam), atol=1e-9 * lam[0])
+    assert np.all(np.diff(np.diag(cr)) <= 1e-9 * lam[0])
+    planted = r[::-1]
+    assert not np.all(np.diff(np.diag(rotation.covariance(rotation.rotate_rows(x, planted)))) <= 1e-9 * lam[0])
