@@ -258,6 +258,46 @@ def bench_bond_ivf(pdx, torch, np, ix, q_dev, nprobes, k, steps, warmup, truth_i
     return out
 
 
+def bench_bsa(pdx, torch, np, ix, q_dev, nprobes, ms, k, steps, warmup, truth_ids):
+    """BSA's test (Section 2.3: Cauchy-Schwarz error quantiles with the
+    multiplier m; m = 1 is exact within the probed buckets) on the vector-ALU
+    scans, schedule from the autotuner, per (nprobe, m); the fastest point
+    reaching recall@10 >= 0.95 against the FP64 oracle's truth."""
+    from oracle.exact import recall_at_k
+    nq = q_dev.shape[0]
+    rows, best = [], None
+    for p in nprobes:
+        for m in ms:
+            sched, _ = pdx.pdx_ivf_tune(ix, q_dev, k, p, bound="bsa", bsa_m=m, reps=2)
+            ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, p, bound="bsa", bsa_m=m,
+                                                                 queries_per_wave=sched["queries_per_wave"],
+                                                                 engine=sched["engine"])),
+                             dtype=torch.uint8, device="cuda")
+            out = {}
+
+            def run(evs, p=p, m=m, ws=ws, out=out, sched=sched):
+                out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, p, bound="bsa", bsa_m=m, workspace=ws,
+                                              phase_events=evs, **sched)
+
+            elapsed, ph = timed_steps(run, steps, warmup, torch, np)
+            ids = out["r"][0].cpu().numpy()
+            rec = recall_at_k(truth_ids, ids[: truth_ids.shape[0]]) if truth_ids is not None else None
+            cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+            pdx.pdx_search_ivf(ix, q_dev, k, p, bound="bsa", bsa_m=m, counters=cnt, **sched)
+            c = [float(v) for v in cnt.cpu().tolist()]
+            row = {"nprobe": p, "m": m, "qps": round(nq * steps / elapsed, 1),
+                   "ms_per_step": round(1e3 * elapsed / steps, 3),
+                   "recall@10": None if rec is None else round(rec, 4), "schedule": sched,
+                   "values_per_query": round((c[0] + c[2]) / nq)}
+            print(f"# bsa nprobe {p} m {m}: {row['qps']} qps recall {row['recall@10']}", file=sys.stderr, flush=True)
+            rows.append(row)
+            if rec is not None and rec >= 0.95 and (best is None or row["qps"] > best["qps"]):
+                best = row
+    return {"test": "BSA (Cauchy-Schwarz, multiplier m)", "sweep": rows,
+            "qps_at_recall_0.95": None if best is None else best["qps"],
+            "point_at_recall_0.95": None if best is None else {"nprobe": best["nprobe"], "m": best["m"]}}
+
+
 def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d, layout="buckets"):
     """The kernel listing's other distances on the same index and queries:
     L1 with PDX-BOND (LDS-tile path with the L1 centroid bound) and the
@@ -859,6 +899,9 @@ def main() -> int:
             extra["approx_pca"]["rotation"] = "pca"
             extra["approx_pca_bond_bound"] = bench_bond_ivf(pdx, torch, np, pca_ix[0], q, [8, 16, 32], k, 3, 1,
                                                             truth)
+            extra["approx_pca_bsa"] = bench_bsa(pdx, torch, np, pca_ix[0], q, [8, 16, 32], [1.0, 0.9, 0.8, 0.7],
+                                                k, 3, 1, truth)
+            extra["approx_random_bsa"] = bench_bsa(pdx, torch, np, ivf_ix[0], q, [16], [1.0, 0.8], k, 3, 1, truth)
             del pca_ix
         if not args.no_learned:
             extra["learned_stop"] = bench_learned(pdx, torch, np, ivf_ix[0], ix, x_np, mix, k, 3, 1,

@@ -376,7 +376,22 @@ typedef struct {
                                  sum_j |q'_j - mean_j| descending (ties by
                                  zone; a shorter last zone last), one zone
                                  per 32-dimension fetch (delta_d ignored);
-                                 exact within the probed buckets as for 1 */
+                                 exact within the probed buckets as for 1;
+                                 3: BSA's test by error quantiles from the
+                                 Cauchy-Schwarz inequality (Section 2.3,
+                                 with a PCA index its projection): after d
+                                 < D dimensions in natural order a vector
+                                 is dropped when partial + max(|q_r|^2 +
+                                 |x_r|^2 - 2 bsa_m |q_r| |x_r| - err, 0)
+                                 > tau (1 + 2^-16), r the dimensions not
+                                 yet seen (the build stores |x_r| at each
+                                 test point of the default delta_d), err =
+                                 2 (D + 4) 2^-24 (|q_r| + |x_r|)^2 covers
+                                 float32 rounding; exact at d = D.
+                                 bsa_m = 1 makes it a lower bound: exact
+                                 within the probed buckets.  Vector ALU
+                                 engine only; delta_d must be the
+                                 default                                  */
     /* Learned prune bound (see pdx_mlp_*; NULL = ADSampling's eps0).       */
     const void *prune_mlp;    /* network state: after START every (query,
                                  rank r >= 1) gets its own eps, the
@@ -408,6 +423,7 @@ typedef struct {
                                  dimension rows of the group; 0 = 32,
                                  < 0 = never.  Needs D % 4 == 0 (else never).
                                  Does not change the result, bit for bit.  */
+    float bsa_m;              /* bound 3: the multiplier m in [0, 1]; 0 = 1 */
 } pdx_ivf_search_params;
 
 /* pdx_ivf_tune -- pick the fastest scan schedule for a workload.

@@ -26,6 +26,15 @@ What is followed, in the paper's order:
   method: after d of D dimensions the estimate partial*D/d is compared
   with tau*(1 + eps0/sqrt(d))^2, and at d = D the comparison is exact.
   Parameters (Section 6.1): delta_d = 32 (D/4 when D < 128), eps0 = 2.1.
+* Section 2.3 (BSA): a PCA projection of the collection, and a test by
+  error quantiles from the Cauchy-Schwarz inequality with a multiplier m
+  instead of the hypothesis test.  The paper states it in words only; the
+  reading used here: after d dimensions the unseen part of the distance,
+  |q_r|^2 + |x_r|^2 - 2 q_r.x_r over the remaining dimensions, is estimated
+  by replacing q_r.x_r with m |q_r| |x_r| (the Cauchy-Schwarz maximum when
+  m = 1, which makes the estimate a lower bound and the search exact within
+  the probed buckets), and a vector is dropped when partial + max(that, 0)
+  exceeds the threshold; at d = D the comparison is exact.
 * Section 2.1 (IVF): distances to all centroids first, then the vectors in
   the nprobe nearest buckets; buckets are visited nearest first (ties by
   bucket id) and the first one is the START block.
@@ -111,6 +120,40 @@ def make_ads_prunes(eps0: float) -> Callable[[np.ndarray, float, int, int], np.n
         return partial * ratio > bound
 
     return prune
+
+
+def make_bsa_prunes(xb: np.ndarray, qv: np.ndarray, m: float) -> Callable[[np.ndarray, float, int, int], np.ndarray]:
+    """BSA's test (Section 2.3, reading above) for the rows xb of one block
+    and the query qv (both in the rotated space, visited in natural order):
+    drop iff partial + max(|q_r|^2 + |x_r|^2 - 2 m |q_r| |x_r|, 0) > tau
+    with r the dimensions not yet seen; exact at d = D."""
+    xb = np.asarray(xb, dtype=np.float64)
+    qv = np.asarray(qv, dtype=np.float64)
+
+    def prune(partial: np.ndarray, tau: float, dims_seen: int, d: int) -> np.ndarray:
+        if dims_seen >= d:
+            return partial > tau
+        xr = np.sqrt((xb[:, dims_seen:] ** 2).sum(axis=1))
+        qr = float(np.sqrt((qv[dims_seen:] ** 2).sum()))
+        rest = np.maximum(qr * qr + xr * xr - 2.0 * m * qr * xr, 0.0)
+        return partial + rest > tau
+
+    return prune
+
+
+def bsa_ivf_search(xrot: np.ndarray, lists: Sequence[np.ndarray], centroids: np.ndarray,
+                   qrot: np.ndarray, k: int, nprobe: int, m: float, delta_d: Optional[int] = None,
+                   switch: float = 0.2, stats: Optional[SearchStats] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """PDXearch with BSA's test inside IVF (Sections 2.3, 4): probed buckets
+    nearest first, dimensions in natural (rotated) order, tests every
+    delta_d dimensions."""
+    xrot = np.asarray(xrot)
+    d = xrot.shape[1]
+    dd = ads_delta_d(d) if delta_d is None else delta_d
+    probe = ivf_probe_order(centroids, qrot, nprobe)
+    blocks = [np.asarray(lists[p], dtype=np.int64) for p in probe]
+    prunes = [make_bsa_prunes(xrot[b], qrot, m) for b in blocks]
+    return pdxearch(xrot, qrot, k, blocks, fixed_chunks(np.arange(d), dd), prunes, switch, stats)
 
 
 def never_prunes(partial: np.ndarray, tau: float, dims_seen: int, d: int) -> np.ndarray:

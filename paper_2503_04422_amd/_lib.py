@@ -81,7 +81,7 @@ class pdx_ivf_search_params(ctypes.Structure):
                 ("engine", c_int32), ("bucket_split", c_int32), ("bound", c_int32),
                 ("prune_mlp", c_void_p), ("prune_scale", ctypes.c_float), ("prune_table", c_void_p),
                 ("trace_prune_features", c_void_p), ("trace_prune_target", c_void_p),
-                ("zone_rows", c_int32)]
+                ("zone_rows", c_int32), ("bsa_m", ctypes.c_float)]
 
 
 class pdx_ivf_schedule(ctypes.Structure):

@@ -68,7 +68,7 @@ def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 _MODES = {"linear": _lib.PDX_MODE_LINEAR, "bond": _lib.PDX_MODE_BOND}
-_BOUNDS = {"ads": 0, "bond": 1, "zones": 2}
+_BOUNDS = {"ads": 0, "bond": 1, "zones": 2, "bsa": 3}
 _DTYPES = {"f32": _lib.PDX_DTYPE_F32, "bf16": _lib.PDX_DTYPE_BF16, "fp8": _lib.PDX_DTYPE_FP8}
 
 
@@ -256,7 +256,7 @@ def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delt
                              dtype: str = "f32", rerank: int = 0, queries_per_wave: int = 0,
                              engine: int = 0, mlp: Optional["MlpState"] = None, bucket_split: int = 0,
                              bound: str = "ads", prune_mlp: Optional["MlpState"] = None,
-                             prune_trace: bool = False) -> int:
+                             prune_trace: bool = False, bsa_m: float = 0.0) -> int:
     """Workspace bytes of pdx_search_ivf with the same arguments (the
     learned stop adds stages, and so item padding; the prune multipliers
     and their traces add per-query tables)."""
@@ -264,7 +264,7 @@ def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delt
                                    None if mlp is None else _ptr(mlp.mem), 0.5, None, None,
                                    int(queries_per_wave), 0, int(engine), int(bucket_split), _BOUNDS[bound],
                                    None if prune_mlp is None else _ptr(prune_mlp.mem), 1.0, None,
-                                   1 if prune_trace else None, 1 if prune_trace else None)
+                                   1 if prune_trace else None, 1 if prune_trace else None, 0, float(bsa_m))
     return int(lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p)))
 
 
@@ -337,11 +337,13 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                    bound: str = "ads", prune_mlp: Optional[MlpState] = None, prune_scale: float = 1.0,
                    prune_table: Optional[torch.Tensor] = None,
                    prune_trace: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, zone_rows: int = 0,
+                   bsa_m: float = 0.0,
                    stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Approximate k nearest neighbours (IVF + ADSampling; bound "bond" or
     "zones": PDX-BOND in per-dimension or dimension-zone order, exact within
     the probed buckets, zone_rows the survivor count at or below which
-    zones are read from the row-major copy), optionally with the
+    zones are read from the row-major copy; bound "bsa": BSA's
+    Cauchy-Schwarz test with multiplier bsa_m, exact at 1), optionally with the
     learned probe budget (mlp) or recording its training traces
     (trace = (features [nq, nprobe, 72] float32, need [nq] int32)), and
     with the learned prune bound (prune_mlp, prune_scale; prune_table
@@ -374,7 +376,7 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                                    _ptr(tf), _ptr(ti), int(queries_per_wave), int(bucket_order), int(engine),
                                    int(bucket_split), _BOUNDS[bound],
                                    None if prune_mlp is None else _ptr(prune_mlp.mem), float(prune_scale),
-                                   _ptr(prune_table), _ptr(pf), _ptr(pt), int(zone_rows))
+                                   _ptr(prune_table), _ptr(pf), _ptr(pt), int(zone_rows), float(bsa_m))
     ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
     need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
@@ -390,6 +392,7 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
 @_on_stream
 def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: float = 2.1, delta_d: int = 0,
                  dtype: str = "f32", rerank: int = 0, tune_delta_d: bool = True, reps: int = 3,
+                 bound: str = "ads", bsa_m: float = 0.0,
                  stream: Optional[torch.cuda.Stream] = None):
     """Fastest scan schedule for this workload (pdx_ivf_tune).  Returns
     (schedule, table): schedule = keyword arguments for pdx_search_ivf
@@ -398,8 +401,8 @@ def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: fl
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
-                                   _DTYPES[dtype], int(rerank), None, None, None, 0.5, None, None, 0, 0, 0, 0, 0,
-                                   None, 1.0, None, None, None)
+                                   _DTYPES[dtype], int(rerank), None, None, None, 0.5, None, None, 0, 0, 0, 0,
+                                   _BOUNDS[bound], None, 1.0, None, None, None, 0, float(bsa_m))
     need = lib.pdx_ivf_tune_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
     table = (_lib.pdx_ivf_schedule * _lib.TUNE_CANDIDATES)()

@@ -257,11 +257,17 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
             partial += s;
             if (PRUNE) {
                 // the prune test after c1 of d dimensions (exact at c1 = d)
-                float thr = tau_eff;
-                if (c1 < d)
-                    thr = tau_eff * (rule.eps ? PruneRule::learned(eps_i, (float)c1 / (float)d, prune_rs(c1))
-                                              : rule.ads(c1, d));
-                alive = alive && !(partial > thr);
+                if (rule.xres && c1 < d) {  // BSA: the stored residual norms of the test point
+                    const int32_t tp = c0 / chunk;
+                    const float xr = rule.xres[((int64_t)g * rule.ntp + tp) * kGroup + lane];
+                    alive = alive && !rule.bsa_drop(partial, tau_eff, rule.qres[qi * rule.ntp + tp], xr);
+                } else {
+                    float thr = tau_eff;
+                    if (c1 < d)
+                        thr = tau_eff * (rule.eps ? PruneRule::learned(eps_i, (float)c1 / (float)d, prune_rs(c1))
+                                                  : rule.ads(c1, d));
+                    alive = alive && !(partial > thr);
+                }
             }
         }
         topk_offer(e, kth, make_key(partial, (uint32_t)vid), alive, k, lane);
@@ -387,20 +393,27 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
                     }
                 }
             }
-            float fac = 1.0f, cdl = 0.0f, rsl = 0.0f;
-            const bool learned = PRUNE && c1 < d && rule.eps;
-            if (PRUNE && c1 < d && !rule.eps) fac = rule.ads(c1, d);
+            float fac = 1.0f, cdl = 0.0f, rsl = 0.0f, xr = 0.0f;
+            const bool bsa = PRUNE && c1 < d && rule.xres;
+            const bool learned = PRUNE && c1 < d && rule.eps && !bsa;
+            if (PRUNE && c1 < d && !rule.eps && !bsa) fac = rule.ads(c1, d);
             if (learned) {
                 cdl = (float)c1 / (float)d;
                 rsl = prune_rs(c1);
             }
+            if (bsa) xr = rule.xres[((int64_t)g * rule.ntp + c0 / chunk) * kGroup + lane];
 #pragma unroll
             for (int q = 0; q < QB; ++q) {
                 if ((qa >> q) & 1u) {
                     part[q] += s[q];
                     // the prune test after c1 of d dimensions (exact at c1 = d)
-                    const float fq = learned ? PruneRule::learned(epsq[q], cdl, rsl) : fac;
-                    if (PRUNE && part[q] > teff[q] * fq) am &= ~(1u << q);
+                    if (bsa) {
+                        if (rule.bsa_drop(part[q], teff[q], rule.qres[(int64_t)qid[q] * rule.ntp + c0 / chunk], xr))
+                            am &= ~(1u << q);
+                    } else {
+                        const float fq = learned ? PruneRule::learned(epsq[q], cdl, rsl) : fac;
+                        if (PRUNE && part[q] > teff[q] * fq) am &= ~(1u << q);
+                    }
                 }
             }
         }
@@ -782,7 +795,9 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         int32_t eng = p ? p->engine : 0;
         if (eng == 0)  // automatic: matrix cores once buckets see enough queries to fill 16-row tiles
             eng = (!(p && p->queries_per_wave > 0) && (double)nq * nprobe >= 8.0 * ix->nlist) ? 2 : 1;
-        pl.matrix = (eng == 2 && !pl.bond) ? 1 : 0;  // the BOND scan gathers per-query dimensions: vector ALU
+        // the BOND scan gathers per-query dimensions, BSA's test reads a norm
+        // per vector and test point: both on the vector ALU
+        pl.matrix = (eng == 2 && !pl.bond && !(p && p->bound == 3)) ? 1 : 0;
     }
     // matrix-core scans report exact f32 distances of their k best
     if (pl.matrix && pl.dtype == PDX_DTYPE_F32) pl.rerank = k;
@@ -854,6 +869,14 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.peps = (pl.pw16 && nprobe > 1 && pl.npt > 0) ? c.take<float>(q * (nprobe - 1)) : nullptr;
     pl.tau0 = (pl.trace_pf && pl.npt > 0) ? c.take<float>(q) : nullptr;
     pl.rule = PruneRule{pl.eps0, pl.peps};
+    if (p && p->bound == 3 && ix->res_ntp > 0) {  // BSA's test with the stored residual norms
+        pl.qres = c.take<float>(q * ix->res_ntp);
+        pl.rule.xres = ix->xres;
+        pl.rule.qres = pl.qres;
+        pl.rule.ntp = ix->res_ntp;
+        pl.rule.m = p->bsa_m > 0.0f ? p->bsa_m : 1.0f;
+        pl.rule.err = 2.0f * (float)(ix->d + 4) * 0x1p-24f;
+    }
     pl.events = p ? reinterpret_cast<hipEvent_t *>(p->phase_events) : nullptr;
     pl.counters = p ? p->counters : nullptr;
     if (plan) *plan = pl;
@@ -877,6 +900,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     if ((e = launch_pair(1, 0, pl.qrot, nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) !=
         hipSuccess)
         return e;
+    if (pl.qres && (e = launch_query_residuals(pl.qrot, nq, d, pl.chunk, pl.qres, s)) != hipSuccess) return e;
     // 2. nearest buckets
     int32_t pow2 = next_pow2(ix->nlist);
     select_probe_kernel<<<(unsigned)nq, 256, pow2 * sizeof(uint64_t), s>>>(pl.cd, ix->nlist, pow2, q, d, pl.nprobe,

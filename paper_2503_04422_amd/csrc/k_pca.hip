@@ -231,7 +231,56 @@ __global__ void jacobi_rotate_kernel(const float *__restrict__ h0, const float *
     r1[e] = si * r0[(int64_t)i * d + j] + oi * r0[(int64_t)ip * d + j];
 }
 
+// |x| over [c1, d) for every test point of every vector of group g (one
+// wave per group, lane = vector), summed from the last dimension down
+__global__ __launch_bounds__(64) void residual_norms_kernel(const float *__restrict__ pdx, int32_t d,
+                                                            const int32_t *__restrict__ ngroups, int32_t dd,
+                                                            int32_t ntp, float *__restrict__ xres) {
+    const int64_t g = blockIdx.x;
+    if (ngroups && g >= *ngroups) return;
+    const int lane = threadIdx.x;
+    const float *col = pdx + g * d * kGroup + lane;
+    float s = 0.0f;
+    for (int32_t c = ntp - 1; c >= 0; --c) {
+        const int32_t c1 = (c + 1) * dd, hi = c == ntp - 1 ? d : (c + 2) * dd;
+        for (int32_t j = hi - 1; j >= c1; --j) {
+            const float v = col[(int64_t)j * kGroup];
+            s = fmaf(v, v, s);
+        }
+        xres[(g * ntp + c) * kGroup + lane] = sqrtf(s);
+    }
+}
+
+// the same for queries: one wave per query (a lane per test point)
+__global__ __launch_bounds__(64) void query_residual_kernel(const float *__restrict__ q, int32_t d, int32_t dd,
+                                                            int32_t ntp, float *__restrict__ qres) {
+    const int64_t qi = blockIdx.x;
+    const float *row = q + qi * d;
+    for (int32_t c = threadIdx.x; c < ntp; c += kWave) {
+        float s = 0.0f;
+        for (int32_t j = d - 1; j >= (c + 1) * dd; --j) s = fmaf(row[j], row[j], s);
+        qres[qi * ntp + c] = sqrtf(s);
+    }
+}
+
 }  // namespace
+
+int32_t res_test_points(int32_t d, int32_t dd) { return dd > 0 && dd < d ? (d + dd - 1) / dd - 1 : 0; }
+
+hipError_t launch_residual_norms(const float *pdx, int32_t d, int64_t ngroups, const int32_t *ngroups_dev,
+                                 int32_t dd, float *xres, hipStream_t s) {
+    const int32_t ntp = res_test_points(d, dd);
+    if (ntp == 0 || ngroups == 0) return hipSuccess;
+    residual_norms_kernel<<<(unsigned)ngroups, 64, 0, s>>>(pdx, d, ngroups_dev, dd, ntp, xres);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_residuals(const float *q, int64_t nq, int32_t d, int32_t dd, float *qres, hipStream_t s) {
+    const int32_t ntp = res_test_points(d, dd);
+    if (ntp == 0 || nq == 0) return hipSuccess;
+    query_residual_kernel<<<(unsigned)nq, 64, 0, s>>>(q, d, dd, ntp, qres);
+    return hipGetLastError();
+}
 
 int32_t pca_splits(int64_t n) { return n >= (int64_t)1 << 20 ? 16 : (n >= 65536 ? 8 : 1); }
 int32_t pca_tiles(int32_t d) { return (d + kCT - 1) / kCT; }

@@ -47,6 +47,9 @@ struct pdx_index {
     int32_t *group_bucket;  // [ngroups] bucket of each vectorgroup
     float *tile_rad;        // [2 ngroups] radius of each 32-vector tile around its centroid
     float *tile_rad1;       // [2 ngroups] the same in the L1 norm
+    float *xres;            // [ngroups][res_ntp][64] |x| over the dimensions after each test point (BSA)
+    int32_t res_ntp;        // test points of the residual norms (delta_d = res_dd)
+    int32_t res_dd;
 };
 
 namespace pdx {
@@ -167,6 +170,19 @@ __device__ __forceinline__ float prune_mult(float eps, float rs) {
 struct PruneRule {
     float eps0;
     const float *eps;  // null: ADSampling
+    // BSA (xres non-null): drop when partial + max(qr^2 + xr^2 - 2 m qr xr
+    // - err (qr + xr)^2, 0) exceeds tau (1 + 2^-16); qr, xr: the query's
+    // and the vector's norm over the dimensions not yet seen
+    const float *xres = nullptr;  // [groups][ntp][64]
+    const float *qres = nullptr;  // [nq][ntp]
+    int32_t ntp = 0;
+    float m = 1.0f;
+    float err = 0.0f;  // 2 (D + 4) 2^-24: rounding of the norms and of the estimate
+    __device__ __forceinline__ bool bsa_drop(float partial, float tau, float qr, float xr) const {
+        const float sum = qr + xr;
+        const float rest = fmaxf(fmaf(-2.0f * m * qr, xr, fmaf(qr, qr, xr * xr)) - err * sum * sum, 0.0f);
+        return (partial + rest) * (1.0f - 0x1p-16f) > tau;
+    }
     __device__ __forceinline__ float ads(int32_t c1, int32_t d) const {
         const float dc = (float)c1;
         const float f = 1.0f + eps0 / sqrtf(dc);
@@ -223,6 +239,7 @@ struct IvfPlan {
     SlotMap slots0;    // START lists [nq][1][s0][kk]
     SlotMap slots1;    // lists of ranks >= 1 [nq][nprobe-1][s1][kk]
     uint64_t *rkeys;   // [nq][kk] candidates to rerank
+    float *qres;       // BSA: [nq][ntp] query norms over the dimensions after each test point
     hipEvent_t *events;
     unsigned long long *counters;
 };
@@ -294,6 +311,14 @@ hipError_t launch_check_labels(const int32_t *lab, int64_t n, int32_t nlist, int
 hipError_t launch_bucketize(const float *xrot, int64_t n, int32_t d, const int32_t *lab, int32_t nlist,
                             int32_t *blk_cnt, int32_t *size, int32_t *goff, int32_t *stats, int32_t *slot_id,
                             int64_t max_slots, float *pdx, int64_t max_groups, hipStream_t s);
+
+// Residual norms for BSA's test (k_pca.hip): per stored vector and test
+// point c (after c1 = (c + 1) dd dimensions, c1 < d), |x| over [c1, d);
+// ntp = ceil(d / dd) - 1 test points.  And the same per query.
+int32_t res_test_points(int32_t d, int32_t dd);
+hipError_t launch_residual_norms(const float *pdx, int32_t d, int64_t ngroups, const int32_t *ngroups_dev,
+                                 int32_t dd, float *xres, hipStream_t s);
+hipError_t launch_query_residuals(const float *q, int64_t nq, int32_t d, int32_t dd, float *qres, hipStream_t s);
 
 // PCA rotation (k_pca.hip): float32 covariance of the rows x (mu: their
 // column means), cyclic Jacobi sweeps, the float64 QR to re-orthonormalise,

@@ -21,6 +21,8 @@ struct IvfLayout {
     unsigned long long *best;
     double *sums, *acm, *qd, *v, *diag, *mean_partial;
     float *pca_part, *pca_cov, *pca_h, *pca_r2, *pca_tmp, *pca_rho, *pca_cs;  // PCA rotation scratch (pca only)
+    float *xres;  // [max_groups][ntp][64] residual norms (BSA)
+    int32_t res_ntp, res_dd;
     double *pca_w64;
     int32_t *pca_perm;
     int64_t max_groups;
@@ -46,6 +48,9 @@ IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, boo
     l.group_bucket = c.take<int32_t>((size_t)l.max_groups);
     l.tile_rad = c.take<float>((size_t)l.max_groups * 2);
     l.tile_rad1 = c.take<float>((size_t)l.max_groups * 2);
+    l.res_dd = d >= 128 ? 32 : (d / 4 > 0 ? d / 4 : 1);  // ADSampling's default delta_d
+    l.res_ntp = res_test_points(d, l.res_dd);
+    l.xres = l.res_ntp > 0 ? c.take<float>((size_t)l.max_groups * l.res_ntp * kGroup) : nullptr;
     if (lowp_mask & (1 << PDX_DTYPE_BF16)) l.pdx16 = c.take<uint16_t>((size_t)l.max_groups * d * kGroup);
     if (lowp_mask & (1 << PDX_DTYPE_FP8)) {
         l.pdx8 = c.take<uint8_t>((size_t)l.max_groups * d * kGroup);
@@ -234,6 +239,7 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
                          L.max_groups * kGroup, L.pdx, L.max_groups, s));
     TRY(launch_tile_radii(L.pdx, L.slot_id, L.list_goff, nlist, L.centroids, d, L.max_groups, L.group_bucket,
                           L.tile_rad, L.tile_rad1, s));
+    if (L.xres) TRY(launch_residual_norms(L.pdx, d, L.max_groups, L.stats, L.res_dd, L.xres, s));
     if (L.pdx16 || L.pdx8)
         TRY(launch_lowp_store(L.xrot, n, d, L.slot_id, L.stats, L.max_groups, L.pdx16, L.pdx8, L.fp8_scale, L.maxbits,
                               s));
@@ -269,6 +275,9 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     ix->group_bucket = L.group_bucket;
     ix->tile_rad = L.tile_rad;
     ix->tile_rad1 = L.tile_rad1;
+    ix->xres = L.xres;
+    ix->res_ntp = L.res_ntp;
+    ix->res_dd = L.res_dd;
     *out = ix;
     return PDX_OK;
 }
@@ -348,13 +357,33 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
         set_error("pdx_search_ivf: bucket_split must be 0, 1, 2, 4 or 8 (got %d)", params->bucket_split);
         return PDX_EINVAL;
     }
-    if (params && (params->bound < 0 || params->bound > 2)) {
-        set_error("pdx_search_ivf: bound must be 0 (ADSampling), 1 (PDX-BOND) or 2 (PDX-BOND, dimension zones)");
+    if (params && (params->bound < 0 || params->bound > 3)) {
+        set_error("pdx_search_ivf: bound must be 0 (ADSampling), 1 (PDX-BOND), 2 (PDX-BOND, dimension zones) "
+                  "or 3 (BSA)");
         return PDX_EINVAL;
     }
-    if (params && params->bound != 0 && params->dtype != PDX_DTYPE_F32) {
+    if (params && (params->bound == 1 || params->bound == 2) && params->dtype != PDX_DTYPE_F32) {
         set_error("pdx_search_ivf: the PDX-BOND bound scans f32 storage only");
         return PDX_EUNSUPPORTED;
+    }
+    if (params && params->bound == 3) {
+        const int32_t dd_def = index->d >= 128 ? 32 : (index->d / 4 > 0 ? index->d / 4 : 1);
+        if (!(params->bsa_m >= 0.0f && params->bsa_m <= 1.0f)) {
+            set_error("pdx_search_ivf: bsa_m must lie in [0, 1]");
+            return PDX_EINVAL;
+        }
+        if (params->delta_d != 0 && params->delta_d != dd_def) {
+            set_error("pdx_search_ivf: BSA's residual norms are stored for delta_d = %d", dd_def);
+            return PDX_EUNSUPPORTED;
+        }
+        if (params->engine == 2) {
+            set_error("pdx_search_ivf: BSA's test runs on the vector-ALU scans (engine 0 or 1)");
+            return PDX_EUNSUPPORTED;
+        }
+        if (!index->xres && index->res_ntp > 0) {
+            set_error("pdx_search_ivf: this index holds no residual norms");
+            return PDX_EUNSUPPORTED;
+        }
     }
     if (params && params->prune_mlp && params->bound != 0) {
         set_error("pdx_search_ivf: the learned prune multiplier replaces the ADSampling test (bound 0)");

@@ -257,3 +257,54 @@ def test_bounds_from_the_targets_keep_every_neighbour():
             gi2, _ = px.learned_ivf_search(x, lists, c, qq, k, nprobe, mult * 0.5, dd)
             lost += gi2.tolist() != fi.tolist()
     assert lost >= 1
+
+
+def test_bsa_hand_worked():
+    """BSA's Cauchy-Schwarz test (Section 2.3; reading in oracle.pdxearch),
+    thresholds worked by hand (tests/golden/hand_bsa.json)."""
+    g = golden("hand_bsa.json")
+    q = np.array(g["query"])
+    for c in g["cases"]:
+        x = np.array([c["x"]])
+        partial = np.array([c["partial"]])
+        got = px.make_bsa_prunes(x, q, c["m"])(partial, g["tau"], g["dims_seen"], g["D"])
+        assert bool(got[0]) == c["pruned"], c
+        # at d = D the test is exact whatever m
+        full = float(((x[0] - q) ** 2).sum())
+        assert bool(px.make_bsa_prunes(x, q, c["m"])(np.array([full]), g["tau"], g["D"], g["D"])[0]) == (full > g["tau"])
+
+
+def test_bsa_with_m_one_is_exact_within_buckets():
+    """With m = 1 the estimate is a lower bound (Cauchy-Schwarz), so the
+    search equals IVF-flat while pruning; a planted sign error in the cross
+    term loses neighbours."""
+    rng = np.random.default_rng(21)
+    n, d, nlist, k = 3000, 64, 8, 10
+    x = (rng.standard_normal((n, d)) * np.linspace(2.0, 0.3, d)[None, :])
+    q = rng.standard_normal((12, d)) * np.linspace(2.0, 0.3, d)[None, :]
+    cen, assign, _ = kmeans.lloyd(x, rng.choice(n, nlist, replace=False), 5)
+    lists = [np.flatnonzero(assign == l) for l in range(nlist)]
+    st = px.SearchStats()
+    lost_planted = 0
+    for qq in q:
+        want = px.ivf_flat(x, lists, cen, qq, k, 4)
+        got = px.bsa_ivf_search(x, lists, cen, qq, k, 4, 1.0, delta_d=16, stats=st)
+        assert got[0].tolist() == want[0].tolist()
+        np.testing.assert_allclose(got[1], want[1], rtol=1e-12)
+
+        def planted(xb, qv, m):
+            xb, qv = np.asarray(xb, np.float64), np.asarray(qv, np.float64)
+
+            def prune(partial, tau, seen, dd):
+                if seen >= dd:
+                    return partial > tau
+                xr = np.sqrt((xb[:, seen:] ** 2).sum(axis=1))
+                qr = float(np.sqrt((qv[seen:] ** 2).sum()))
+                return partial + qr * qr + xr * xr + 2.0 * m * qr * xr > tau
+            return prune
+        probe = px.ivf_probe_order(cen, qq, 4)
+        blocks = [lists[p] for p in probe]
+        bad = px.pdxearch(x, qq, k, blocks, px.fixed_chunks(np.arange(d), 16), [planted(x[b], qq, 1.0) for b in blocks])
+        lost_planted += len(set(want[0].tolist()) - set(bad[0].tolist()))
+    assert st.pruning_power > 0.05   # the bound prunes
+    assert lost_planted > 0          # the pin catches a sign error
