@@ -55,6 +55,7 @@ typedef int32_t pdx_status;
 #define PDX_EUNSUPPORTED (-4)  /* valid request outside what is implemented */
 
 #define PDX_MAX_K 64
+#define PDX_MAX_RERANK 8192  /* candidates re-ranked by the IVF search (rerank) */
 #define PDX_MAX_DIM 4096
 
 /* Opaque host-side handle.  It points into the caller's index buffer,
@@ -318,9 +319,17 @@ typedef struct {
     int32_t delta_d;   /* dimensions between tests; 0 = 32, D/4 if D < 128 */
     int32_t dtype;     /* PDX_DTYPE_* copy to scan (must have been stored) */
     int32_t rerank;    /* BF16/FP8 scans: the R best by the scanned distance are
-                          re-ranked with exact f32 distances (k <= R <= PDX_MAX_K);
-                          0 = min(4k, PDX_MAX_K); -1 = no rerank (distances are
-                          then the scanned low-precision ones).  Ignored for F32. */
+                          re-ranked with exact f32 distances (k <= R <=
+                          PDX_MAX_RERANK); 0 = min(4k, PDX_MAX_K); -1 = no
+                          rerank (distances are then the scanned low-precision
+                          ones).  Ignored for F32.  R > PDX_MAX_K: the scans
+                          append every vector that passes the test and lies
+                          below tau to a per-query candidate buffer (tau: an
+                          upper bound of the R-th smallest buffered distance,
+                          from a histogram of the buffered distances; a full
+                          buffer is compacted to its R best and the scan
+                          resumed, so every probed vector is seen); vector-ALU
+                          engine only; no learned networks or traces.       */
     /* Optional instrumentation (NULL = off); neither changes the result.   */
     void **phase_events; /* 4 hipEvent_t recorded on `stream`: at the start,
                             after rotation + bucket selection + START, after
@@ -424,6 +433,13 @@ typedef struct {
                                  < 0 = never.  Needs D % 4 == 0 (else never).
                                  Does not change the result, bit for bit.  */
     float bsa_m;              /* bound 3: the multiplier m in [0, 1]; 0 = 1 */
+    int32_t rerank_capacity;  /* rerank > PDX_MAX_K: candidate-buffer slots
+                                 per query (8 bytes each, in the workspace):
+                                 0 = max(4 rerank, 16384), else at least
+                                 max(2 rerank, rerank + 256); capped at what
+                                 the nprobe largest buckets hold.  A smaller
+                                 buffer costs more compaction rounds (at most
+                                 1024, else PDX_EINVAL), never results.     */
 } pdx_ivf_search_params;
 
 /* pdx_ivf_tune -- pick the fastest scan schedule for a workload.

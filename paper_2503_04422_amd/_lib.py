@@ -21,6 +21,7 @@ PDX_EWORKSPACE = -2
 PDX_EHIP = -3
 PDX_EUNSUPPORTED = -4
 PDX_MAX_K = 64
+PDX_MAX_RERANK = 8192
 PDX_MAX_DIM = 4096
 PDX_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -81,7 +82,7 @@ class pdx_ivf_search_params(ctypes.Structure):
                 ("engine", c_int32), ("bucket_split", c_int32), ("bound", c_int32),
                 ("prune_mlp", c_void_p), ("prune_scale", ctypes.c_float), ("prune_table", c_void_p),
                 ("trace_prune_features", c_void_p), ("trace_prune_target", c_void_p),
-                ("zone_rows", c_int32), ("bsa_m", ctypes.c_float)]
+                ("zone_rows", c_int32), ("bsa_m", ctypes.c_float), ("rerank_capacity", c_int32)]
 
 
 class pdx_ivf_schedule(ctypes.Structure):

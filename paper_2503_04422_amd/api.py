@@ -256,7 +256,7 @@ def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delt
                              dtype: str = "f32", rerank: int = 0, queries_per_wave: int = 0,
                              engine: int = 0, mlp: Optional["MlpState"] = None, bucket_split: int = 0,
                              bound: str = "ads", prune_mlp: Optional["MlpState"] = None,
-                             prune_trace: bool = False, bsa_m: float = 0.0) -> int:
+                             prune_trace: bool = False, bsa_m: float = 0.0, rerank_capacity: int = 0) -> int:
     """Workspace bytes of pdx_search_ivf with the same arguments (the
     learned stop adds stages, and so item padding; the prune multipliers
     and their traces add per-query tables)."""
@@ -264,7 +264,8 @@ def pdx_search_ivf_workspace(index: PdxIndex, nq: int, k: int, nprobe: int, delt
                                    None if mlp is None else _ptr(mlp.mem), 0.5, None, None,
                                    int(queries_per_wave), 0, int(engine), int(bucket_split), _BOUNDS[bound],
                                    None if prune_mlp is None else _ptr(prune_mlp.mem), 1.0, None,
-                                   1 if prune_trace else None, 1 if prune_trace else None, 0, float(bsa_m))
+                                   1 if prune_trace else None, 1 if prune_trace else None, 0, float(bsa_m),
+                                   int(rerank_capacity))
     return int(lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p)))
 
 
@@ -337,7 +338,7 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                    bound: str = "ads", prune_mlp: Optional[MlpState] = None, prune_scale: float = 1.0,
                    prune_table: Optional[torch.Tensor] = None,
                    prune_trace: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, zone_rows: int = 0,
-                   bsa_m: float = 0.0,
+                   bsa_m: float = 0.0, rerank_capacity: int = 0,
                    stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Approximate k nearest neighbours (IVF + ADSampling; bound "bond" or
     "zones": PDX-BOND in per-dimension or dimension-zone order, exact within
@@ -349,7 +350,9 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
     with the learned prune bound (prune_mlp, prune_scale; prune_table
     receives the multipliers [nq, nprobe - 1, C], C = ivf_test_points(D,
     delta_d)) or recording its traces (prune_trace = (features [nq, k, 72],
-    target [nq, k]) float32)."""
+    target [nq, k]) float32).  dtype "bf16"/"fp8": the rerank best by the
+    scanned distance re-ranked in f32 (rerank > 64: through a per-query
+    candidate buffer of rerank_capacity keys, 0 = the library's default)."""
     q = _dev_f32(q, "q")
     nq = q.shape[0]
     if q.shape[1] != index.d:
@@ -376,7 +379,8 @@ def pdx_search_ivf(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: 
                                    _ptr(tf), _ptr(ti), int(queries_per_wave), int(bucket_order), int(engine),
                                    int(bucket_split), _BOUNDS[bound],
                                    None if prune_mlp is None else _ptr(prune_mlp.mem), float(prune_scale),
-                                   _ptr(prune_table), _ptr(pf), _ptr(pt), int(zone_rows), float(bsa_m))
+                                   _ptr(prune_table), _ptr(pf), _ptr(pt), int(zone_rows), float(bsa_m),
+                                   int(rerank_capacity))
     ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
     need = lib.pdx_search_ivf_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
@@ -402,7 +406,7 @@ def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: fl
     nq = q.shape[0]
     p = _lib.pdx_ivf_search_params(float(eps0) if math.isfinite(eps0) else float("inf"), int(delta_d),
                                    _DTYPES[dtype], int(rerank), None, None, None, 0.5, None, None, 0, 0, 0, 0,
-                                   _BOUNDS[bound], None, 1.0, None, None, None, 0, float(bsa_m))
+                                   _BOUNDS[bound], None, 1.0, None, None, None, 0, float(bsa_m), 0)
     need = lib.pdx_ivf_tune_workspace(index.handle, nq, k, nprobe, ctypes.byref(p))
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
     table = (_lib.pdx_ivf_schedule * _lib.TUNE_CANDIDATES)()

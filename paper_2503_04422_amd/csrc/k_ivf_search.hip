@@ -18,6 +18,7 @@
 #include "mlp_device.h"
 #include "pdx_internal.h"
 #include "wave_topk.h"
+#include "wide_sink.h"
 
 namespace pdx {
 namespace {
@@ -177,9 +178,6 @@ __global__ void item_scatter_kernel(const int32_t *__restrict__ probe, int64_t n
     else items1[atomicAdd(cur1 + l, 1)] = make_int2(qi, r);
 }
 
-// Scan of one bucket for one query per wave.  Work items are consecutive
-// per bucket; workgroup ids are mapped so each XCD takes a contiguous
-// range of items (and so of buckets).
 // Value of dimension j of the lane's vector in group g: f32, or a bfloat16 /
 // e4m3 code decoded to f32 (e4m3 times the dimension's scale).
 template <int STORE>
@@ -190,39 +188,33 @@ __device__ __forceinline__ float load_val(const void *__restrict__ data, const f
     return e4m3_decode(static_cast<const uint8_t *>(data)[at]) * scale[j];
 }
 
-template <bool PRUNE, int STORE>
-__global__ __launch_bounds__(256) void ivf_scan_kernel(
-    const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
-    const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nitems,
-    const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
-    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, PruneRule rule,
-    unsigned long long *__restrict__ counters, uint32_t nwg) {
-    // grid = 8 * ceil(nwg / 8): every (xcd, index) pair is launched once
-    const uint32_t per_xcd = gridDim.x >> 3;
-    const uint32_t wg = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int64_t it = (int64_t)wg * 4 + wave;
-    if (wg >= nwg || it >= nitems) return;
-    const int2 item = items[it];
-    const int64_t qi = item.x;
-    const int32_t r = item.y;
+// One (query, probe rank) item from vectorgroup g0 of its bucket (-1: the
+// first) for one wave: the running k-best list written to the item's slot,
+// or (WIDE) the survivors appended to the query's candidate buffer.
+template <bool PRUNE, int STORE, bool WIDE>
+__device__ __forceinline__ void scan_item(const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d,
+                                          const int32_t *__restrict__ slot_id, const int32_t *__restrict__ goff,
+                                          int64_t qi, int32_t r, int32_t g0, const int32_t *__restrict__ probe,
+                                          int32_t nprobe, const float *__restrict__ qrot, uint32_t *__restrict__ tau,
+                                          const int32_t *__restrict__ bad, const SlotMap &slots, int32_t chunk,
+                                          const PruneRule &rule, unsigned long long *__restrict__ counters,
+                                          const WideSink &wide, int lane) {
     const int32_t k = slots.kk;
-    uint64_t *myslot = slots.at(qi, r, 0);
     if (bad[qi]) {  // non-finite query
-        if (lane < k) myslot[lane] = kEmptyKey;
+        if (!WIDE && lane < k) slots.at(qi, r, 0)[lane] = kEmptyKey;
         return;
     }
     const int32_t l = probe[qi * nprobe + r];
     const float *qp = qrot + qi * d;
     const float eps_i = (PRUNE && rule.eps) ? rule.eps_at(qi, r, nprobe) : 0.0f;
+    const int32_t hb = WIDE ? wide.hbase[qi] : 0;
     uint64_t e = kEmptyKey, kth = kEmptyKey;
     unsigned long long live_vals = 0, lane_vals = 0;
-    for (int32_t g = goff[l]; g < goff[l + 1]; ++g) {
+    for (int32_t g = g0 >= 0 ? g0 : goff[l]; g < goff[l + 1]; ++g) {
         float tau_eff = INFINITY;
-        if (PRUNE) {
+        if (PRUNE || WIDE) {
             uint32_t tg = __hip_atomic_load(tau + qi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            float tl = kth == kEmptyKey ? INFINITY : key_dist(kth);
+            float tl = (WIDE || kth == kEmptyKey) ? INFINITY : key_dist(kth);
             tau_eff = fminf(__uint_as_float(tg), tl);
         }
         const int32_t vid = slot_id[(int64_t)g * kGroup + lane];
@@ -270,16 +262,72 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
                 }
             }
         }
-        topk_offer(e, kth, make_key(partial, (uint32_t)vid), alive, k, lane);
-        if (PRUNE && kth != kEmptyKey) {
-            float kt = key_dist(kth);
-            if (kt < tau_eff && lane == 0) atomicMin(tau + qi, __float_as_uint(kt));
+        if constexpr (WIDE) {
+            if (!wide_push(wide, qi, partial, (uint32_t)vid, alive && partial < tau_eff, hb, tau, lane)) {
+                wide_overflow(wide, qi, r, g, lane);
+                break;
+            }
+        } else {
+            topk_offer(e, kth, make_key(partial, (uint32_t)vid), alive, k, lane);
+            if (PRUNE && kth != kEmptyKey) {
+                float kt = key_dist(kth);
+                if (kt < tau_eff && lane == 0) atomicMin(tau + qi, __float_as_uint(kt));
+            }
         }
     }
-    if (lane < k) myslot[lane] = e;
+    if (!WIDE && lane < k) slots.at(qi, r, 0)[lane] = e;
     if (counters && lane == 0) {
         atomicAdd(counters, live_vals);
         atomicAdd(counters + 1, lane_vals);
+    }
+}
+
+// Scan of one bucket for one query per wave.  Work items are consecutive
+// per bucket; workgroup ids are mapped so each XCD takes a contiguous
+// range of items (and so of buckets).
+template <bool PRUNE, int STORE, bool WIDE>
+__global__ __launch_bounds__(256) void ivf_scan_kernel(
+    const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
+    const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nitems,
+    const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
+    uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, PruneRule rule,
+    unsigned long long *__restrict__ counters, uint32_t nwg, WideSink wide) {
+    // grid = 8 * ceil(nwg / 8): every (xcd, index) pair is launched once
+    const uint32_t per_xcd = gridDim.x >> 3;
+    const uint32_t wg = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t it = (int64_t)wg * 4 + wave;
+    if (wg >= nwg || it >= nitems) return;
+    const int2 item = items[it];
+    scan_item<PRUNE, STORE, WIDE>(pdxd, scale, d, slot_id, goff, item.x, item.y, -1, probe, nprobe, qrot, tau, bad,
+                                  slots, chunk, rule, counters, wide, lane);
+}
+
+// Resumes the items of the queries listed in round `list_round` whose
+// candidate buffer filled up (after their compaction): one item per wave,
+// grid-strided; START items (rank 0) unpruned.
+template <int STORE>
+__global__ __launch_bounds__(256) void ivf_wide_resume_kernel(
+    const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
+    const int32_t *__restrict__ goff, const int32_t *__restrict__ probe, int32_t nprobe,
+    const float *__restrict__ qrot, uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots,
+    int32_t chunk, PruneRule rule, unsigned long long *__restrict__ counters, WideSink wide, int32_t list_round) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nitems = (int64_t)wide.ocnt[list_round] * nprobe;
+    const int32_t *list = wide.olist + (int64_t)(list_round & 1) * wide.nq;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < nitems; it += (int64_t)gridDim.x * 4) {
+        const int64_t qi = list[it / nprobe];
+        const int32_t r = (int32_t)(it % nprobe);
+        const int32_t g0 = wide.resume[qi * nprobe + r];
+        if (g0 < 0) continue;
+        if (lane == 0) wide.resume[qi * nprobe + r] = -1;
+        if (r == 0)
+            scan_item<false, STORE, true>(pdxd, scale, d, slot_id, goff, qi, r, g0, probe, nprobe, qrot, tau, bad,
+                                          slots, chunk, rule, counters, wide, lane);
+        else
+            scan_item<true, STORE, true>(pdxd, scale, d, slot_id, goff, qi, r, g0, probe, nprobe, qrot, tau, bad,
+                                         slots, chunk, rule, counters, wide, lane);
     }
 }
 
@@ -291,14 +339,16 @@ __global__ __launch_bounds__(256) void ivf_scan_kernel(
 // with no alive lane in the group skips its arithmetic (wave-uniform
 // branch), and the group ends early once no (query, lane) pair is alive.
 // Summation per (query, vector): each chunk summed sequentially, then
-// added to the partial, as in the one-query kernel.
-template <bool PRUNE, int STORE, int QB>
+// added to the partial, as in the one-query kernel.  WIDE: survivors go to
+// the queries' candidate buffers; a query whose buffer fills leaves the
+// batch (its item resumes later).
+template <bool PRUNE, int STORE, int QB, bool WIDE>
 __global__ __launch_bounds__(256) void ivf_bscan_kernel(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
     uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots, int32_t chunk, PruneRule rule,
-    unsigned long long *__restrict__ counters) {
+    unsigned long long *__restrict__ counters, WideSink wide) {
     const int lane = threadIdx.x & 63;
     const int32_t k = slots.kk;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -317,7 +367,7 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
     for (int q = 0; q < QB; ++q) {
         if (qid[q] < 0) continue;
         if (bad[qid[q]]) {  // non-finite query
-            if (lane < k) slots.at(qid[q], rk[q], 0)[lane] = kEmptyKey;
+            if (!WIDE && lane < k) slots.at(qid[q], rk[q], 0)[lane] = kEmptyKey;
         } else {
             use |= 1u << q;
         }
@@ -337,9 +387,9 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             teff[q] = INFINITY;
-            if (PRUNE && ((use >> q) & 1)) {
+            if ((PRUNE || WIDE) && ((use >> q) & 1)) {
                 uint32_t tg = __hip_atomic_load(tau + qid[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                float tl = kth[q] == kEmptyKey ? INFINITY : key_dist(kth[q]);
+                float tl = (WIDE || kth[q] == kEmptyKey) ? INFINITY : key_dist(kth[q]);
                 teff[q] = fminf(__uint_as_float(tg), tl);
             }
             part[q] = 0.0f;
@@ -421,16 +471,25 @@ __global__ __launch_bounds__(256) void ivf_bscan_kernel(
         for (int q = 0; q < QB; ++q) {
             if (!((use >> q) & 1u)) continue;
             const bool cand = (am >> q) & 1u;
-            if (__ballot(cand)) topk_offer(e[q], kth[q], make_key(part[q], (uint32_t)vid), cand, k, lane);
-            if (PRUNE && kth[q] != kEmptyKey) {
-                const float kt = key_dist(kth[q]);
-                if (kt < teff[q] && lane == 0) atomicMin(tau + qid[q], __float_as_uint(kt));
+            if constexpr (WIDE) {
+                if (!wide_push(wide, qid[q], part[q], (uint32_t)vid, cand && part[q] < teff[q], wide.hbase[qid[q]],
+                               tau, lane)) {
+                    wide_overflow(wide, qid[q], rk[q], g, lane);
+                    use &= ~(1u << q);
+                }
+            } else {
+                if (__ballot(cand)) topk_offer(e[q], kth[q], make_key(part[q], (uint32_t)vid), cand, k, lane);
+                if (PRUNE && kth[q] != kEmptyKey) {
+                    const float kt = key_dist(kth[q]);
+                    if (kt < teff[q] && lane == 0) atomicMin(tau + qid[q], __float_as_uint(kt));
+                }
             }
         }
+        if (WIDE && !use) break;
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q)
-        if (((use >> q) & 1u) && lane < k) slots.at(qid[q], rk[q], 0)[lane] = e[q];
+        if (!WIDE && ((use >> q) & 1u) && lane < k) slots.at(qid[q], rk[q], 0)[lane] = e[q];
     if (counters && lane == 0) {
         atomicAdd(counters, live_vals);
         atomicAdd(counters + 1, lane_vals);
@@ -788,6 +847,7 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         if (r == 0) r = min(4 * k, PDX_MAX_K);
         pl.rerank = r < 0 ? 0 : max(r, k);
     }
+    pl.wide = pl.rerank > PDX_MAX_K ? 1 : 0;
     pl.bond = (p && (p->bound == 1 || p->bound == 2)) ? 1 : 0;
     pl.zones = (p && p->bound == 2) ? 1 : 0;
     pl.zone_rows = pl.zones ? bond_zone_rows(ix->d, p->zone_rows) : 0;
@@ -797,11 +857,11 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
             eng = (!(p && p->queries_per_wave > 0) && (double)nq * nprobe >= 8.0 * ix->nlist) ? 2 : 1;
         // the BOND scan gathers per-query dimensions, BSA's test reads a norm
         // per vector and test point: both on the vector ALU
-        pl.matrix = (eng == 2 && !pl.bond && !(p && p->bound == 3)) ? 1 : 0;
+        pl.matrix = (eng == 2 && !pl.bond && !(p && p->bound == 3) && !pl.wide) ? 1 : 0;
     }
     // matrix-core scans report exact f32 distances of their k best
     if (pl.matrix && pl.dtype == PDX_DTYPE_F32) pl.rerank = k;
-    pl.kk = pl.rerank > 0 ? pl.rerank : k;
+    pl.kk = (pl.rerank > 0 && !pl.wide) ? pl.rerank : k;
     pl.w16 = (p && p->mlp) ? mlp_layout(const_cast<void *>(p->mlp)).w16 : nullptr;
     pl.trace_f = p ? p->trace_features : nullptr;
     pl.trace_need = p ? p->trace_need : nullptr;
@@ -858,7 +918,25 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         pl.slots1 = SlotMap{c.take<uint64_t>(q * (nprobe > 1 ? nprobe - 1 : 1) * s1 * pl.kk), nprobe - 1, 1, s1,
                             pl.kk};
     }
-    pl.rkeys = pl.rerank > 0 ? c.take<uint64_t>(q * pl.kk) : nullptr;
+    pl.rkeys = (pl.rerank > 0 && !pl.wide) ? c.take<uint64_t>(q * pl.kk) : nullptr;
+    pl.ws = WideSink{};
+    pl.wide_rounds = 0;
+    if (pl.wide) {
+        const int32_t cap = wide_capacity(ix, nprobe, pl.rerank, p ? p->rerank_capacity : 0);
+        pl.wide_rounds = wide_rounds(ix, nprobe, pl.rerank, cap);
+        pl.ws.cap = cap;
+        pl.ws.r = pl.rerank;
+        pl.ws.nprobe = nprobe;
+        pl.ws.nq = (int64_t)q;
+        pl.ws.buf = c.take<uint64_t>(q * (size_t)cap);
+        pl.ws.cnt = c.take<int32_t>(q);
+        pl.ws.hist = c.take<uint32_t>(q * kWideBins);
+        pl.ws.hbase = c.take<int32_t>(q);
+        pl.ws.resume = c.take<int32_t>(q * nprobe);
+        pl.ws.over = c.take<int32_t>(q);
+        pl.ws.olist = c.take<int32_t>(2 * q);
+        pl.ws.ocnt = c.take<int32_t>((size_t)pl.wide_rounds + 1);
+    }
     // learned prune multipliers and their traces
     pl.npt = dd < ix->d ? (ix->d + dd - 1) / dd - 1 : 0;
     pl.pw16 = (p && p->prune_mlp) ? mlp_layout(const_cast<void *>(p->prune_mlp)).w16 : nullptr;
@@ -906,6 +984,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     select_probe_kernel<<<(unsigned)nq, 256, pow2 * sizeof(uint64_t), s>>>(pl.cd, ix->nlist, pow2, q, d, pl.nprobe,
                                                                          pl.probe, pl.bad, pl.tau);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (pl.wide && (e = launch_wide_init(pl.ws, pl.cd, ix->nlist, pl.probe, pl.wide_rounds, s)) != hipSuccess) return e;
     // PDX-BOND: each query's dimension order by |q'_j - mean_j| (Section 5)
     if (pl.bond && (e = launch_bond_prep(pl.qrot, nq, d, ix->means, pl.zones != 0, pl.perm, pl.qperm, pl.tau, pl.bad, s)) != hipSuccess)
         return e;
@@ -949,18 +1028,26 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         if (qb == 1) {
             const uint32_t nwg = (uint32_t)((cap + 3) / 4);
             const unsigned grid = 8u * ((nwg + 7u) / 8u);
-#define PDX_SCAN(P, S)                                                                                          \
-    ivf_scan_kernel<P, S><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, cap,  \
-                                               pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm, pl.chunk,        \
-                                               pl.rule, cnt, nwg)
-            if (prune) {
-                if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16);
-                else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8);
-                else PDX_SCAN(true, PDX_DTYPE_F32);
+#define PDX_SCAN(P, S, W)                                                                                       \
+    ivf_scan_kernel<P, S, W><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, cap, \
+                                                  pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm, pl.chunk,     \
+                                                  pl.rule, cnt, nwg, pl.ws)
+            if (pl.wide) {  // low precision only
+                if (prune) {
+                    if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16, true);
+                    else PDX_SCAN(true, PDX_DTYPE_FP8, true);
+                } else {
+                    if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(false, PDX_DTYPE_BF16, true);
+                    else PDX_SCAN(false, PDX_DTYPE_FP8, true);
+                }
+            } else if (prune) {
+                if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(true, PDX_DTYPE_BF16, false);
+                else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(true, PDX_DTYPE_FP8, false);
+                else PDX_SCAN(true, PDX_DTYPE_F32, false);
             } else {
-                if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(false, PDX_DTYPE_BF16);
-                else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(false, PDX_DTYPE_FP8);
-                else PDX_SCAN(false, PDX_DTYPE_F32);
+                if (pl.dtype == PDX_DTYPE_BF16) PDX_SCAN(false, PDX_DTYPE_BF16, false);
+                else if (pl.dtype == PDX_DTYPE_FP8) PDX_SCAN(false, PDX_DTYPE_FP8, false);
+                else PDX_SCAN(false, PDX_DTYPE_F32, false);
             }
 #undef PDX_SCAN
             return hipGetLastError();
@@ -971,18 +1058,27 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
                                     ix->centroids, items, nb, xr, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm,
                                     pl.chunk, pl.rule, cnt, s);
         const unsigned grid = (unsigned)((nb + 3) / 4);
-#define PDX_BSCAN(P, S, Q)                                                                                        \
-    ivf_bscan_kernel<P, S, Q><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, nb, \
-                                                   pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm, pl.chunk,      \
-                                                   pl.rule, cnt)
-#define PDX_BSCAN_Q(P, S)                      \
-    switch (qb) {                              \
-        case 2: PDX_BSCAN(P, S, 2); break;     \
-        case 4: PDX_BSCAN(P, S, 4); break;     \
-        case 8: PDX_BSCAN(P, S, 8); break;     \
-        default: PDX_BSCAN(P, S, 16); break;   \
+#define PDX_BSCAN(P, S, Q, W)                                                                                 \
+    ivf_bscan_kernel<P, S, Q, W><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, \
+                                                      nb, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm,     \
+                                                      pl.chunk, pl.rule, cnt, pl.ws)
+#define PDX_BSCAN_W(P, S, W)                     \
+    switch (qb) {                                \
+        case 2: PDX_BSCAN(P, S, 2, W); break;    \
+        case 4: PDX_BSCAN(P, S, 4, W); break;    \
+        case 8: PDX_BSCAN(P, S, 8, W); break;    \
+        default: PDX_BSCAN(P, S, 16, W); break;  \
     }
-        if (prune) {
+#define PDX_BSCAN_Q(P, S) PDX_BSCAN_W(P, S, false)
+        if (pl.wide) {  // low precision only
+            if (prune) {
+                if (pl.dtype == PDX_DTYPE_BF16) PDX_BSCAN_W(true, PDX_DTYPE_BF16, true)
+                else PDX_BSCAN_W(true, PDX_DTYPE_FP8, true)
+            } else {
+                if (pl.dtype == PDX_DTYPE_BF16) PDX_BSCAN_W(false, PDX_DTYPE_BF16, true)
+                else PDX_BSCAN_W(false, PDX_DTYPE_FP8, true)
+            }
+        } else if (prune) {
             if (pl.dtype == PDX_DTYPE_BF16) PDX_BSCAN_Q(true, PDX_DTYPE_BF16)
             else if (pl.dtype == PDX_DTYPE_FP8) PDX_BSCAN_Q(true, PDX_DTYPE_FP8)
             else PDX_BSCAN_Q(true, PDX_DTYPE_F32)
@@ -992,13 +1088,16 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
             else PDX_BSCAN_Q(false, PDX_DTYPE_F32)
         }
 #undef PDX_BSCAN_Q
+#undef PDX_BSCAN_W
 #undef PDX_BSCAN
         return hipGetLastError();
     };
     if ((e = scan(false, pl.items0, pl.cap0, pl.qb0, pl.slots0, pl.counters, pl.xcd)) != hipSuccess) return e;
-    ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots0, true, pl.slots1, 1, nullptr, pl.kk, pl.bad, pl.tau,
-                                                nullptr, nullptr, nullptr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!pl.wide) {  // tau: the k-th (or R-th) distance of START (the candidate buffer keeps its own)
+        ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots0, true, pl.slots1, 1, nullptr, pl.kk, pl.bad, pl.tau,
+                                                    nullptr, nullptr, nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if ((e = mark(1)) != hipSuccess) return e;
     // 5. learned probe budget (or the traces of its inputs), then the
     //    pruned scan of the other probed buckets
@@ -1032,7 +1131,26 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         return e;
     if ((e = mark(2)) != hipSuccess) return e;
     // 6. merge
-    if (pl.rerank > 0) {
+    if (pl.wide) {
+        // compaction and resume rounds, then the R best re-ranked exactly
+        for (int32_t rd = 0; rd < pl.wide_rounds; ++rd) {
+            if ((e = launch_wide_select(pl.ws, rd, pl.tau, s)) != hipSuccess) return e;
+            WideSink wr = pl.ws;
+            wr.round = rd + 1;
+#define PDX_RESUME(S)                                                                                             \
+    ivf_wide_resume_kernel<S><<<1024, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, pl.probe, \
+                                                   pl.nprobe, pl.qrot, pl.tau, pl.bad, pl.slots1, pl.chunk,      \
+                                                   pl.rule, pl.counters ? pl.counters + 2 : nullptr, wr, rd)
+            if (pl.dtype == PDX_DTYPE_BF16) PDX_RESUME(PDX_DTYPE_BF16);
+            else PDX_RESUME(PDX_DTYPE_FP8);
+#undef PDX_RESUME
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if ((e = launch_wide_select(pl.ws, -1, pl.tau, s)) != hipSuccess) return e;
+        if ((e = launch_wide_rerank(pl.ws, ix->xrow, pl.qrot, d, pl.chunk, pl.bad, pl.k, out_ids, out_dist, s)) !=
+            hipSuccess)
+            return e;
+    } else if (pl.rerank > 0) {
         ivf_merge_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.slots0, true, pl.slots1, pl.nprobe,
                                                     later ? pl.budget : nullptr, pl.kk, pl.bad, nullptr, nullptr,
                                                     nullptr, pl.rkeys);

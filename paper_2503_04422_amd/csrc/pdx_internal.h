@@ -129,6 +129,7 @@ struct ExactPlan {
 
 constexpr int32_t kDefaultQueriesPerWave = 4;
 constexpr int32_t kMaxSplit = 8;
+constexpr int32_t kMaxWideRounds = 1024;  // compaction + resume rounds of the candidate buffer
 
 // Compute units of the current device (256, the MI355X count, if the query fails).
 inline int32_t device_cus() {
@@ -195,6 +196,67 @@ struct PruneRule {
     __device__ __forceinline__ static float learned(float e, float cd, float rs) { return cd * prune_mult(e, rs); }
 };
 
+// Candidate buffer of the IVF search when more than PDX_MAX_K candidates
+// are re-ranked (R > 64): every (query, vectorgroup) appends the keys of its
+// surviving vectors whose scanned distance is below tau, reserving its slots
+// with one atomic add (all or nothing).  A per-query histogram of the stored
+// distances (kWideBins bins, 1/64 of an octave each, placed around the
+// farthest probed centroid's distance) lowers tau to the upper edge of the
+// bin holding the R-th smallest stored distance: at least R stored keys lie
+// below it, so no key at or above it can enter the R best.  A full buffer
+// stops the (query, bucket) item at the vectorgroup that did not fit; the
+// query is then compacted to its R best and the item resumed (bounded
+// number of rounds, sized by the planner), so every probed vector is seen.
+constexpr int32_t kWideBins = 1024;
+
+struct WideSink {
+    uint64_t *buf;    // [nq][cap] keys (distance bits << 32 | id), kEmptyKey = unused
+    int32_t *cnt;     // [nq] slots reserved (may exceed cap after an overflow)
+    uint32_t *hist;   // [nq][kWideBins] stored keys per distance bin
+    int32_t *hbase;   // [nq] bin 0 = distance bits >> 17 at or below this value
+    int32_t *resume;  // [nq][nprobe] first vectorgroup not stored (-1: done)
+    int32_t *over;    // [nq] 1 while the query has items to resume
+    int32_t *olist;   // [2][nq] queries that overflowed, by round parity
+    int32_t *ocnt;    // [rounds + 1] entries of each round's list
+    int32_t cap;      // buffer slots per query
+    int32_t r;        // candidates re-ranked
+    int32_t nprobe;
+    int32_t round;    // scans: the round their overflows are listed under
+    int64_t nq;
+};
+
+// Candidate-buffer slots per query for a re-rank of r > PDX_MAX_K: the
+// caller's request (0: max(4r, 16384)), at most what the nprobe largest
+// buckets can hold (plus one reservation), at least r.
+inline int32_t wide_capacity(const pdx_index *ix, int32_t nprobe, int32_t r, int32_t req) {
+    const int64_t pmax = ix->n < (int64_t)nprobe * ix->max_list ? ix->n : (int64_t)nprobe * ix->max_list;
+    int64_t cap = req > 0 ? req : (4ll * r > 16384 ? 4ll * r : 16384);
+    if (cap > pmax + 64) cap = pmax + 64;
+    if (cap < r) cap = r;
+    return (int32_t)cap;
+}
+
+// Compaction + resume rounds that make every probed vector seen: a query
+// that fills its buffer has stored at least cap - 63 vectors in the first
+// pass and at least cap - r - 63 more in each round that fills it again,
+// all distinct, so with pmax vectors probed at most (pmax - cap + 63) /
+// (cap - r - 63) rounds can fill it and one more completes it.  -1: the
+// capacity leaves no room (cap - r - 63 < 1).
+inline int32_t wide_rounds(const pdx_index *ix, int32_t nprobe, int32_t r, int32_t cap) {
+    const int64_t pmax = ix->n < (int64_t)nprobe * ix->max_list ? ix->n : (int64_t)nprobe * ix->max_list;
+    if (pmax <= cap) return 0;
+    const int64_t per = (int64_t)cap - r - 63;
+    if (per < 1) return -1;
+    const int64_t rounds = (pmax - cap + 63) / per + 1;
+    return rounds > (1 << 20) ? (1 << 20) : (int32_t)rounds;
+}
+
+hipError_t launch_wide_init(const WideSink &w, const float *cd, int32_t nlist, const int32_t *probe, int32_t rounds,
+                            hipStream_t s);
+hipError_t launch_wide_select(const WideSink &w, int32_t list_round, uint32_t *tau, hipStream_t s);
+hipError_t launch_wide_rerank(const WideSink &w, const float *xrow, const float *qrot, int32_t d, int32_t chunk,
+                              const int32_t *bad, int32_t k, int64_t *out_ids, float *out_dist, hipStream_t s);
+
 struct IvfPlan {
     int64_t nq;
     int32_t k;
@@ -239,6 +301,9 @@ struct IvfPlan {
     SlotMap slots0;    // START lists [nq][1][s0][kk]
     SlotMap slots1;    // lists of ranks >= 1 [nq][nprobe-1][s1][kk]
     uint64_t *rkeys;   // [nq][kk] candidates to rerank
+    int32_t wide;      // rerank > PDX_MAX_K: the candidate buffer (WideSink)
+    int32_t wide_rounds;  // compaction + resume rounds after the scans
+    WideSink ws;
     float *qres;       // BSA: [nq][ntp] query norms over the dimensions after each test point
     hipEvent_t *events;
     unsigned long long *counters;

@@ -332,9 +332,39 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
         set_error("pdx_search_ivf: dtype %d is not stored in this index", params ? params->dtype : -1);
         return PDX_EUNSUPPORTED;
     }
-    if (params && params->dtype != PDX_DTYPE_F32 && params->rerank > PDX_MAX_K) {
-        set_error("pdx_search_ivf: rerank=%d above PDX_MAX_K=%d", params->rerank, PDX_MAX_K);
+    if (params && params->dtype != PDX_DTYPE_F32 && params->rerank > PDX_MAX_RERANK) {
+        set_error("pdx_search_ivf: rerank=%d above PDX_MAX_RERANK=%d", params->rerank, PDX_MAX_RERANK);
         return PDX_EUNSUPPORTED;
+    }
+    if (params && params->rerank_capacity < 0) {
+        set_error("pdx_search_ivf: rerank_capacity must be >= 0");
+        return PDX_EINVAL;
+    }
+    if (params && params->dtype != PDX_DTYPE_F32 && params->rerank > PDX_MAX_K) {
+        // more candidates than a wave's register list: the candidate buffer
+        const int32_t r = params->rerank;
+        if (params->engine == 2) {
+            set_error("pdx_search_ivf: a re-rank of more than PDX_MAX_K=%d candidates runs on the vector-ALU "
+                      "scans (engine 0 or 1)", PDX_MAX_K);
+            return PDX_EUNSUPPORTED;
+        }
+        if (params->mlp || params->prune_mlp || params->trace_features || params->trace_need ||
+            params->trace_prune_features) {
+            set_error("pdx_search_ivf: the learned networks and their traces need rerank <= PDX_MAX_K=%d",
+                      PDX_MAX_K);
+            return PDX_EUNSUPPORTED;
+        }
+        if (params->rerank_capacity != 0 && (params->rerank_capacity < 2 * r || params->rerank_capacity < r + 256)) {
+            set_error("pdx_search_ivf: rerank_capacity must be 0 or at least max(2 rerank, rerank + 256)");
+            return PDX_EINVAL;
+        }
+        const int32_t cap = wide_capacity(index, nprobe, r, params->rerank_capacity);
+        const int32_t rounds = wide_rounds(index, nprobe, r, cap);
+        if (rounds < 0 || rounds > kMaxWideRounds) {
+            set_error("pdx_search_ivf: rerank_capacity %d would need %d compaction rounds (at most %d); raise it",
+                      cap, rounds, kMaxWideRounds);
+            return PDX_EINVAL;
+        }
     }
     if (nq == 0) return PDX_OK;
     if (!q || !ws || !out_ids || !out_dist) {

@@ -111,8 +111,9 @@ def test_lowp_ads_recall_and_errors(pdx, setup):
         for i in range(0, st["q"].shape[0], 7):
             ok = ai[i] >= 0
             np.testing.assert_allclose(ad[i][ok], exact.sqdist(st["x"][ai[i][ok]], st["q"][i]), rtol=1e-5)
+    from paper_2503_04422_amd._lib import PDX_MAX_RERANK
     with pytest.raises(PdxError):
-        pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, 4, dtype="bf16", rerank=65)
+        pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, 4, dtype="bf16", rerank=PDX_MAX_RERANK + 1)
     x2 = st["x"][:2000]
     ix2 = pdx.pdx_ivf_build(_dev(x2), 4, None, _dev(np.arange(4, dtype=np.int64) * 100), kmeans_iters=2)
     with pytest.raises(PdxError):
