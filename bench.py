@@ -522,7 +522,7 @@ def bench_learned(pdx, torch, np, ix, exact_ix, x_np, mix, k, steps, warmup, cpu
 
 
 def bench_lowp(pdx, torch, np, x_np, q_np, x_dev, q_dev, k, steps, warmup, truth_ids, nlist=2048, nprobe=32,
-               rerank=40, seed=42):
+               rerank=40, seed=42, legs=None):
     """IVF + ADSampling over f32, bfloat16 and float8 storage of the same
     index; recall@10 and the distance error against the FP64 oracle."""
     from oracle.exact import recall_at_k, sqdist
@@ -540,20 +540,25 @@ def bench_lowp(pdx, torch, np, x_np, q_np, x_dev, q_dev, k, steps, warmup, truth
     s_n = 0 if truth_ids is None else truth_ids.shape[0]
     qrot = q_np[:s_n].astype(np.float64) @ rot.T
     res = {}
-    for dtype in ("f32", "bf16", "fp8"):
-        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, nprobe, dtype=dtype, rerank=rerank)),
+    legs = legs or [("f32", rerank), ("bf16", rerank), ("fp8", rerank), ("bf16", 4096), ("fp8", 4096)]
+    for dtype, rr in legs:
+        name = dtype if rr == rerank else f"{dtype}_rerank{rr}"
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(ix, nq, k, nprobe, dtype=dtype, rerank=rr)),
                          dtype=torch.uint8, device="cuda")
         out = {}
 
-        def run(evs, dtype=dtype, ws=ws, out=out):
-            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, nprobe, eps0=2.1, dtype=dtype, rerank=rerank, workspace=ws,
+        def run(evs, dtype=dtype, ws=ws, out=out, rr=rr):
+            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, nprobe, eps0=2.1, dtype=dtype, rerank=rr, workspace=ws,
                                           phase_events=evs)
 
         elapsed, ph = timed_steps(run, steps, warmup, torch, np)
         ids = out["r"][0].cpu().numpy()
         row = {"qps": round(nq * steps / elapsed, 1), "ms_per_step": round(1e3 * elapsed / steps, 3),
+               "rerank": rr if dtype != "f32" else None, "workspace_bytes": int(ws.numel()),
                "phases_ms": {"prep_start": round(ph[0], 3), "pruned_scan": round(ph[1], 3), "merge_rerank": round(ph[2], 3)}}
-        if s_n:
+        if s_n and rr != rerank:
+            row["recall@10"] = round(recall_at_k(truth_ids, ids[:s_n]), 4)
+        elif s_n:
             row["recall@10"] = round(recall_at_k(truth_ids, ids[:s_n]), 4)
             # distance error of the scanned (not re-ranked) low-precision distances
             ai, ad = pdx.pdx_search_ivf(ix, q_dev[:s_n], k, nprobe, eps0=2.1, dtype=dtype, rerank=-1)
@@ -564,8 +569,8 @@ def bench_lowp(pdx, torch, np, x_np, q_np, x_dev, q_dev, k, steps, warmup, truth
                 true = sqdist(x_np[ai[i][ok]].astype(np.float64) @ rot.T, qrot[i])
                 err = max(err, float(np.max(np.abs(ad[i][ok] - true) / np.maximum(true, 1e-30))))
             row["max_rel_distance_error_scanned"] = err
-        print(f"# {dtype}: {row}", file=sys.stderr, flush=True)
-        res[dtype] = row
+        print(f"# {name}: {row}", file=sys.stderr, flush=True)
+        res[name] = row
         del ws
     return {"nlist": nlist, "nprobe": nprobe, "rerank": rerank, "eps0": 2.1, "build_s": round(build_s, 2),
             "bytes_per_vector": {"f32": 4 * d, "bf16": 2 * d, "fp8": d}, "recall_queries": s_n, "by_dtype": res}
@@ -680,6 +685,7 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true", help="skip the learned early-termination leg")
     ap.add_argument("--no-metrics", action="store_true", help="skip the L1 / inner-product leg")
     ap.add_argument("--no-pca", action="store_true", help="skip the PCA-rotation IVF leg")
+    ap.add_argument("--lowp-legs", default="", help="lowp_5m_d768: dtype:rerank legs to run, comma-separated")
     ap.add_argument("--nprobe", type=int, nargs="*", default=None, help="IVF workloads: nprobe values to run")
     ap.add_argument("--flat", action="store_true", help="exact search on the flat layout instead of buckets")
     ap.add_argument("--exact-nlist", type=int, default=1024, help="buckets of the exact search's layout")
@@ -745,7 +751,10 @@ def main() -> int:
         print(f"# oracle sample {done} queries in {tc:.1f}s", file=sys.stderr, flush=True)
 
     if args.workload == "lowp_5m_d768":
-        res = bench_lowp(pdx, torch, np, x_np, q_np, x, q, k, args.steps, args.warmup, truth)
+        legs = None
+        if args.lowp_legs:  # e.g. "f32:40,bf16:40,bf16:4096"
+            legs = [(a, int(b)) for a, b in (v.split(":") for v in args.lowp_legs.split(","))]
+        res = bench_lowp(pdx, torch, np, x_np, q_np, x, q, k, args.steps, args.warmup, truth, legs=legs)
         out = {"metric": METRIC, "value": res["by_dtype"]["fp8"]["qps"], "unit": "queries/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["by_dtype"]["fp8"]["ms_per_step"],
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp8-e4m3 storage, f32 accumulate",

@@ -395,4 +395,40 @@ hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int3
     return hipGetLastError();
 }
 
+// One wave per (vectorgroup, 32-dimension sub-chunk), lane = vector: the
+// sum of squares of the decoded values, dimensions in order.
+__global__ __launch_bounds__(64) void lowp_norms_kernel(const uint16_t *__restrict__ pdx16,
+                                                        const uint8_t *__restrict__ pdx8,
+                                                        const float *__restrict__ scale, int32_t d,
+                                                        const int32_t *__restrict__ stats, float *__restrict__ xn16,
+                                                        float *__restrict__ xn8) {
+    const int64_t g = blockIdx.x;
+    const int32_t sb = blockIdx.y, nsub = gridDim.y;
+    const int lane = threadIdx.x;
+    const int64_t at = (g * nsub + sb) * 64 + lane;
+    if (g >= stats[0]) return;
+    float a16 = 0.0f, a8 = 0.0f;
+    for (int32_t j = 32 * sb; j < min(32 * sb + 32, d); ++j) {
+        const int64_t e = (g * d + j) * 64 + lane;
+        if (pdx16) {
+            const float v = bf16_decode(pdx16[e]);
+            a16 = fmaf(v, v, a16);
+        }
+        if (pdx8) {
+            const float v = e4m3_decode(pdx8[e]) * scale[j];
+            a8 = fmaf(v, v, a8);
+        }
+    }
+    if (xn16) xn16[at] = a16;
+    if (xn8) xn8[at] = a8;
+}
+
+hipError_t launch_lowp_norms(const uint16_t *pdx16, const uint8_t *pdx8, const float *scale, int32_t d,
+                             const int32_t *stats, int64_t max_groups, float *xn16, float *xn8, hipStream_t s) {
+    if (max_groups <= 0 || (!xn16 && !xn8)) return hipSuccess;
+    const unsigned nsub = (unsigned)((d + 31) / 32);
+    lowp_norms_kernel<<<dim3((unsigned)max_groups, nsub), 64, 0, s>>>(pdx16, pdx8, scale, d, stats, xn16, xn8);
+    return hipGetLastError();
+}
+
 }  // namespace pdx

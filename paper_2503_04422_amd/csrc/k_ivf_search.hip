@@ -946,6 +946,19 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.trace_pt = p ? p->trace_prune_target : nullptr;
     pl.peps = (pl.pw16 && nprobe > 1 && pl.npt > 0) ? c.take<float>(q * (nprobe - 1)) : nullptr;
     pl.tau0 = (pl.trace_pf && pl.npt > 0) ? c.take<float>(q) : nullptr;
+    // matrix cores over low-precision codes: bfloat16 MFMA on the codes
+    // when every chunk is whole 32-dimension sub-chunks
+    pl.lp = LpOperands{};
+    if (pl.matrix && pl.dtype != PDX_DTYPE_F32 && pl.chunk % 32 == 0) {
+        const float *xn = pl.dtype == PDX_DTYPE_BF16 ? ix->xn_bf16 : ix->xn_fp8;
+        if (xn) {
+            pl.lp.nsub = ix->lp_nsub;
+            pl.lp.dpad = 32 * ix->lp_nsub;
+            pl.lp.qs = c.take<uint16_t>(q * 3 * (size_t)pl.lp.dpad);
+            pl.lp.qn = c.take<float>(q * (size_t)pl.lp.nsub);
+            pl.lp.xn = xn;
+        }
+    }
     pl.rule = PruneRule{pl.eps0, pl.peps};
     if (p && p->bound == 3 && ix->res_ntp > 0) {  // BSA's test with the stored residual norms
         pl.qres = c.take<float>(q * ix->res_ntp);
@@ -979,6 +992,10 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         hipSuccess)
         return e;
     if (pl.qres && (e = launch_query_residuals(pl.qrot, nq, d, pl.chunk, pl.qres, s)) != hipSuccess) return e;
+    if (pl.lp.qs &&
+        (e = launch_lp_query(pl.qrot, nq, d, pl.dtype == PDX_DTYPE_FP8 ? ix->fp8_scale : nullptr, pl.lp, s)) !=
+            hipSuccess)
+        return e;
     // 2. nearest buckets
     int32_t pow2 = next_pow2(ix->nlist);
     select_probe_kernel<<<(unsigned)nq, 256, pow2 * sizeof(uint64_t), s>>>(pl.cd, ix->nlist, pow2, q, d, pl.nprobe,
@@ -1056,7 +1073,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         if (pl.matrix)
             return launch_ivf_mscan(prune, pl.dtype, qb / 16, data, ix->fp8_scale, d, ix->slot_id, ix->list_goff,
                                     ix->centroids, items, nb, xr, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm,
-                                    pl.chunk, pl.rule, cnt, s);
+                                    pl.chunk, pl.rule, cnt, pl.lp, s);
         const unsigned grid = (unsigned)((nb + 3) / 4);
 #define PDX_BSCAN(P, S, Q, W)                                                                                 \
     ivf_bscan_kernel<P, S, Q, W><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, \

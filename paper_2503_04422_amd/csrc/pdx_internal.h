@@ -47,6 +47,9 @@ struct pdx_index {
     int32_t *group_bucket;  // [ngroups] bucket of each vectorgroup
     float *tile_rad;        // [2 ngroups] radius of each 32-vector tile around its centroid
     float *tile_rad1;       // [2 ngroups] the same in the L1 norm
+    float *xn_bf16;         // [ngroups][lp_nsub][64] |x_C|^2 of the decoded bfloat16 vectors per 32 dimensions
+    float *xn_fp8;          // the same for the decoded e4m3 vectors
+    int32_t lp_nsub;        // ceil(d / 32)
     float *xres;            // [ngroups][res_ntp][64] |x| over the dimensions after each test point (BSA)
     int32_t res_ntp;        // test points of the residual norms (delta_d = res_dd)
     int32_t res_dd;
@@ -196,6 +199,19 @@ struct PruneRule {
     __device__ __forceinline__ static float learned(float e, float cd, float rs) { return cd * prune_mult(e, rs); }
 };
 
+// Operands of the matrix-core scan over low-precision codes (bfloat16
+// MFMA on the stored codes): qs [nq][3][dpad] the bfloat16 terms of each
+// query, qn [nq][nsub] |q_C|^2 per 32-dimension sub-chunk, xn
+// [groups][nsub][64] |x_C|^2 of the decoded stored vectors.  qs null: the
+// scan decodes to f32 instead.
+struct LpOperands {
+    const uint16_t *qs;
+    const float *qn;
+    const float *xn;
+    int32_t nsub;
+    int32_t dpad;
+};
+
 // Candidate buffer of the IVF search when more than PDX_MAX_K candidates
 // are re-ranked (R > 64): every (query, vectorgroup) appends the keys of its
 // surviving vectors whose scanned distance is below tau, reserving its slots
@@ -305,6 +321,7 @@ struct IvfPlan {
     int32_t wide_rounds;  // compaction + resume rounds after the scans
     WideSink ws;
     float *qres;       // BSA: [nq][ntp] query norms over the dimensions after each test point
+    LpOperands lp;     // matrix-core scan of low-precision codes on bfloat16 MFMA
     hipEvent_t *events;
     unsigned long long *counters;
 };
@@ -342,7 +359,11 @@ hipError_t launch_ivf_mscan(bool prune, int32_t store, int32_t tiles, const void
                             int32_t d, const int32_t *slot_id, const int32_t *goff, const float *cen,
                             const int2 *items, int64_t nbatch, const int32_t *xcd_range, const int32_t *probe,
                             int32_t nprobe, const float *qrot, uint32_t *tau, const int32_t *bad, SlotMap slots,
-                            int32_t chunk, PruneRule rule, unsigned long long *counters, hipStream_t s);
+                            int32_t chunk, PruneRule rule, unsigned long long *counters, const LpOperands &lp,
+                            hipStream_t s);
+// The query operands of LpOperands (scale: the e4m3 scales, or null for bfloat16).
+hipError_t launch_lp_query(const float *qrot, int64_t nq, int32_t d, const float *scale, const LpOperands &lp,
+                           hipStream_t s);
 
 // Item slots for nq queries x `ranks` probe ranks when every bucket's count
 // is rounded up to a multiple of qb (at most qb - 1 padding slots per bucket).
@@ -449,6 +470,10 @@ hipError_t launch_tile_radii(const float *pdx, const int32_t *slot_id, const int
 hipError_t launch_lowp_store(const float *xrow, int64_t n, int32_t d, const int32_t *slot_id, const int32_t *stats,
                              int64_t max_groups, uint16_t *pdx16, uint8_t *pdx8, float *scale, uint32_t *maxbits,
                              hipStream_t s);
+// |x_C|^2 of the decoded low-precision vectors per 32-dimension sub-chunk
+// ([max_groups][ceil(d / 32)][64]; either code array may be null).
+hipError_t launch_lowp_norms(const uint16_t *pdx16, const uint8_t *pdx8, const float *scale, int32_t d,
+                             const int32_t *stats, int64_t max_groups, float *xn16, float *xn8, hipStream_t s);
 
 }  // namespace pdx
 

@@ -22,6 +22,7 @@ struct IvfLayout {
     double *sums, *acm, *qd, *v, *diag, *mean_partial;
     float *pca_part, *pca_cov, *pca_h, *pca_r2, *pca_tmp, *pca_rho, *pca_cs;  // PCA rotation scratch (pca only)
     float *xres;  // [max_groups][ntp][64] residual norms (BSA)
+    float *xn16, *xn8;  // [max_groups][ceil(d / 32)][64] sub-chunk norms of the low-precision codes
     int32_t res_ntp, res_dd;
     double *pca_w64;
     int32_t *pca_perm;
@@ -51,9 +52,14 @@ IvfLayout ivf_layout(int64_t n, int32_t d, int32_t nlist, int32_t lowp_mask, boo
     l.res_dd = d >= 128 ? 32 : (d / 4 > 0 ? d / 4 : 1);  // ADSampling's default delta_d
     l.res_ntp = res_test_points(d, l.res_dd);
     l.xres = l.res_ntp > 0 ? c.take<float>((size_t)l.max_groups * l.res_ntp * kGroup) : nullptr;
-    if (lowp_mask & (1 << PDX_DTYPE_BF16)) l.pdx16 = c.take<uint16_t>((size_t)l.max_groups * d * kGroup);
+    const size_t nsub = (size_t)(d + 31) / 32;
+    if (lowp_mask & (1 << PDX_DTYPE_BF16)) {
+        l.pdx16 = c.take<uint16_t>((size_t)l.max_groups * d * kGroup);
+        l.xn16 = c.take<float>((size_t)l.max_groups * nsub * kGroup);
+    }
     if (lowp_mask & (1 << PDX_DTYPE_FP8)) {
         l.pdx8 = c.take<uint8_t>((size_t)l.max_groups * d * kGroup);
+        l.xn8 = c.take<float>((size_t)l.max_groups * nsub * kGroup);
         l.fp8_scale = c.take<float>(d);
         l.maxbits = c.take<uint32_t>(d);
     }
@@ -240,9 +246,11 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     TRY(launch_tile_radii(L.pdx, L.slot_id, L.list_goff, nlist, L.centroids, d, L.max_groups, L.group_bucket,
                           L.tile_rad, L.tile_rad1, s));
     if (L.xres) TRY(launch_residual_norms(L.pdx, d, L.max_groups, L.stats, L.res_dd, L.xres, s));
-    if (L.pdx16 || L.pdx8)
+    if (L.pdx16 || L.pdx8) {
         TRY(launch_lowp_store(L.xrot, n, d, L.slot_id, L.stats, L.max_groups, L.pdx16, L.pdx8, L.fp8_scale, L.maxbits,
                               s));
+        TRY(launch_lowp_norms(L.pdx16, L.pdx8, L.fp8_scale, d, L.stats, L.max_groups, L.xn16, L.xn8, s));
+    }
     int32_t hstats[2] = {0, 0};
     TRY(hipMemcpyAsync(hstats, L.stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
@@ -262,6 +270,9 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
     ix->pdx_bf16 = L.pdx16;
     ix->pdx_fp8 = L.pdx8;
     ix->fp8_scale = L.fp8_scale;
+    ix->xn_bf16 = L.xn16;
+    ix->xn_fp8 = L.xn8;
+    ix->lp_nsub = (d + 31) / 32;
     ix->xrow = L.xrot;
     ix->has_rot = has_rot;
     ix->rot = L.rot;

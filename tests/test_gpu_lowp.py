@@ -9,6 +9,9 @@ sides encode identical inputs: the codes are compared through the search.
 * eps0 = inf with rerank R: the oracle keeps the R best by decoded distance
   and re-ranks them exactly; the GPU must agree wherever the R-th and next
   candidates are not tied, and its distances are the exact distances.
+* the same on the matrix cores with chunks of whole 32-dimension
+  sub-chunks, where the codes feed bfloat16 MFMA, at D = 96 and a ragged
+  D = 100;
 * eps0 = 2.1: recall against f32 IVF-flat stays within the statistical band.
 """
 import numpy as np
@@ -70,6 +73,43 @@ def test_lowp_scan_exact_over_decoded(pdx, setup, dtype, engine):
     for nprobe in (1, 5):
         gi, gd = pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, nprobe, eps0=float("inf"), dtype=dtype, rerank=-1,
                                     engine=engine)
+        gi, gd = _np(gi), _np(gd)
+        xd = st["dec"][dtype]
+        want = [exact.topk_by_dist_then_id(exact.sqdist(xd[r], st["q"][i]), r, 10)
+                for i, r in enumerate(_probed_rows(st, qv, nprobe) for qv in st["q"])]
+        check_knn(xd, st["q"], gi, gd, np.stack([w[0] for w in want]), np.stack([w[1] for w in want]))
+
+
+@pytest.fixture(scope="module")
+def ragged(pdx):
+    """D = 100: the last 32-dimension sub-chunk holds 4 dimensions."""
+    n, d, nlist = 8_000, 100, 16
+    mix = synth.anisotropic_unit_mixture(d, 16, 9)
+    x = mix.data(n)
+    q = mix.queries(40)
+    init = np.random.default_rng(10).choice(n, nlist, replace=False)
+    c, lab, _ = kmeans.lloyd(x, init, 5)
+    c32 = c.astype(np.float32)
+    lists = kmeans.lists_from_labels(lab, nlist)
+    ix = pdx.pdx_ivf_build(_dev(x), nlist, None, None, lowp=("bf16", "fp8"), centroids=_dev(c32),
+                           assign=_dev(lab.astype(np.int32)))
+    dec = {"bf16": lowp.bf16_decode(lowp.bf16_encode(x)),
+           "fp8": lowp.fp8_decode(lowp.fp8_encode(x, lowp.fp8_scales(x)), lowp.fp8_scales(x))}
+    return dict(x=x, q=q, c32=c32, lists=lists, ix=ix, dec=dec, nlist=nlist)
+
+
+@pytest.mark.parametrize("which,dtype,delta_d", [("setup", "bf16", 32), ("setup", "fp8", 64),
+                                                 ("ragged", "bf16", 64), ("ragged", "fp8", 32)])
+def test_lowp_matrix_codes_exact_over_decoded(pdx, setup, ragged, which, dtype, delta_d):
+    """Matrix cores with chunks of whole 32-dimension sub-chunks: the codes
+    go to bfloat16 MFMA (the query as three bfloat16 terms, stored
+    sub-chunk norms).  eps0 = inf, no rerank: the exact top-k over the
+    decoded vectors of the probed buckets, distances within the tie rule."""
+    st = setup if which == "setup" else ragged
+    print(f"lowp matrix-code scan parity {which} {dtype} delta_d={delta_d}", flush=True)
+    for nprobe, qpw in ((1, 16), (5, 16), (5, 32)):
+        gi, gd = pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, nprobe, eps0=float("inf"), dtype=dtype,
+                                    rerank=-1, engine=2, delta_d=delta_d, queries_per_wave=qpw)
         gi, gd = _np(gi), _np(gd)
         xd = st["dec"][dtype]
         want = [exact.topk_by_dist_then_id(exact.sqdist(xd[r], st["q"][i]), r, 10)
