@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", OUT + ".tmp", *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", OUT + ".tmp", *objs, "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

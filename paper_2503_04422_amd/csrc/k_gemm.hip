@@ -10,6 +10,10 @@
 // alike, so each lane reads its 8 consecutive k values with two 16-byte LDS
 // reads.  The next slice's global loads are issued before the current
 // slice's MFMAs.  Rows and k beyond the matrices read as zero.
+#include <rocblas/rocblas.h>
+
+#include <mutex>
+
 #include "pdx_internal.h"
 
 namespace pdx {
@@ -116,6 +120,38 @@ hipError_t launch_gemm_abt(const float *A, int64_t m, const float *B, int64_t n,
     const dim3 grid((unsigned)((m + BM - 1) / BM), (unsigned)((n + BN - 1) / BN));
     gemm_abt_kernel<<<grid, 256, 0, s>>>(A, m, B, n, k, C, ldc);
     return hipGetLastError();
+}
+
+// The same product through rocBLAS's f32 GEMM (a plain library GEMM: the
+// IVF query rotation, the query x centroid products, the build's rotation
+// of the rows).  Row-major C = A B^T is column-major C^T = B^T' A^T', i.e.
+// sgemm(T, N) on the column-major views of B [k][n] and A [k][m].  One
+// handle per device, created on first use (it allocates); calls that share
+// it are serialised around the stream binding.
+namespace {
+std::mutex g_blas_mu;
+rocblas_handle g_blas[64] = {};
+}  // namespace
+
+hipError_t launch_sgemm_abt(const float *A, int64_t m, const float *B, int64_t n, int32_t k, float *C, int64_t ldc,
+                            hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if (m > INT32_MAX || n > INT32_MAX || ldc > INT32_MAX) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_blas_mu);
+    if (!g_blas[dev] && rocblas_create_handle(&g_blas[dev]) != rocblas_status_success) {
+        g_blas[dev] = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    rocblas_handle h = g_blas[dev];
+    if (rocblas_set_stream(h, s) != rocblas_status_success) return hipErrorInvalidHandle;
+    const float one = 1.0f, zero = 0.0f;
+    const rocblas_status st = rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)n,
+                                            (rocblas_int)m, k, &one, B, k, A, k, &zero, C, (rocblas_int)ldc);
+    return st == rocblas_status_success ? hipGetLastError() : hipErrorLaunchFailure;
 }
 
 }  // namespace pdx

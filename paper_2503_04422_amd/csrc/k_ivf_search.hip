@@ -65,6 +65,127 @@ __global__ __launch_bounds__(256) void select_probe_kernel(const float *__restri
     }
 }
 
+// Squared norm of each row of a [rows][d] matrix, one wave per row.
+__global__ __launch_bounds__(64) void row_norm_kernel(const float *__restrict__ a, int32_t d,
+                                                      float *__restrict__ out) {
+    const int64_t i = blockIdx.x;
+    float s = 0.0f;
+    for (int32_t j = threadIdx.x; j < d; j += kWave) s = fmaf(a[i * d + j], a[i * d + j], s);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) out[i] = s;
+}
+
+// The nprobe nearest buckets (nprobe <= 64) from the matrix-core products
+// g[q][l] = q.c_l, one wave per query.  The expanded |q|^2 + |c|^2 - 2 q.c
+// is within E = 2 (D + 64) 2^-24 (|q|^2 + |c|^2) of the exact distance, so
+// every bucket of the exact nprobe best (ties by id) has a lower bound at
+// or below T, the nprobe-th smallest upper bound: only those candidates
+// get their exact f32 distance (each summed across the wave), and the
+// nprobe best of them by (distance, id) are the probes.  g[q][l] then holds the exact distance
+// of every candidate.  Too many candidates (near-equal centroid distances)
+// or fewer than nprobe (NaN bounds): every bucket is summed exactly; a
+// non-finite query gets buckets 0 .. nprobe-1 (it returns no result), so
+// the probe ids are always buckets of the index.
+constexpr int kProbeCand = 256;
+
+__global__ __launch_bounds__(256) void probe_from_dot_kernel(float *__restrict__ g, int64_t nq, int32_t nlist,
+                                                             const float *__restrict__ qsq,
+                                                             const float *__restrict__ csq,
+                                                             const float *__restrict__ qrot,
+                                                             const float *__restrict__ cen,
+                                                             const float *__restrict__ q, int32_t d, int32_t nprobe,
+                                                             int32_t *__restrict__ probe, int32_t *__restrict__ bad,
+                                                             uint32_t *__restrict__ tau) {
+    __shared__ int32_t cand[4][kProbeCand];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t qi = (int64_t)blockIdx.x * 4 + wave;
+    if (qi >= nq) return;
+    int nonfinite = 0;
+    for (int32_t j = lane; j < d; j += kWave) nonfinite |= !isfinite(q[qi * d + j]);
+    nonfinite = __any(nonfinite) ? 1 : 0;
+    if (nonfinite) {  // no result; any real buckets keep the later kernels in bounds
+        if (lane < nprobe) probe[qi * nprobe + lane] = lane;
+        if (lane == 0) {
+            bad[qi] = 1;
+            tau[qi] = kInfBits;
+        }
+        return;
+    }
+    float *gq = g + qi * nlist;
+    const float qn = qsq[qi], ef = (float)(d + 64) * 0x1p-23f;
+    // T: the nprobe-th smallest upper bound
+    uint64_t e = kEmptyKey, kth = kEmptyKey;
+    for (int32_t l0 = 0; l0 < nlist; l0 += kWave) {
+        const int32_t l = l0 + lane;
+        uint64_t key = kEmptyKey;
+        if (l < nlist) {
+            const float nn = qn + csq[l];
+            key = make_key(fmaxf(nn - 2.0f * gq[l] + ef * nn, 0.0f), (uint32_t)l);
+        }
+        topk_offer(e, kth, key, key != kEmptyKey, nprobe, lane);
+    }
+    const float T = kth == kEmptyKey ? INFINITY : key_dist(kth);
+    // candidates: lower bound at or below T
+    int32_t nc = 0;
+    for (int32_t l0 = 0; l0 < nlist; l0 += kWave) {
+        const int32_t l = l0 + lane;
+        bool in = false;
+        if (l < nlist) {
+            const float nn = qn + csq[l];
+            in = nn - 2.0f * gq[l] - ef * nn <= T;
+        }
+        const unsigned long long m = __ballot(in);
+        const int at = nc + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (in && at < kProbeCand) cand[wave][at] = l;
+        nc += __popcll(m);
+    }
+    // too many candidates, or too few (NaN bounds compare false): every
+    // bucket exactly, so the probes are always real buckets
+    const bool all = nc > kProbeCand || nc < nprobe;
+    const int32_t ncand = all ? nlist : nc;
+    // exact distances of the candidates, four at a time across the wave
+    // (lane j sums dimensions j, j + 64, ...; the lane sums then reduced)
+    const float *qp = qrot + qi * d;
+    e = kth = kEmptyKey;
+    for (int32_t i0 = 0; i0 < ncand; i0 += 4) {
+        int32_t lc[4];
+        float acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t i = min(i0 + u, ncand - 1);
+            lc[u] = all ? i : cand[wave][i];
+            acc[u] = 0.0f;
+        }
+        for (int32_t j = lane; j < d; j += kWave) {
+            const float qv = qp[j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float dd = qv - cen[(int64_t)lc[u] * d + j];
+                acc[u] = fmaf(dd, dd, acc[u]);
+            }
+        }
+        float mine = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off);
+            if (lane == u) mine = acc[u];
+        }
+        const bool ok = lane < 4 && i0 + lane < ncand;
+        int32_t myl = lc[0];
+#pragma unroll
+        for (int u = 1; u < 4; ++u) myl = lane == u ? lc[u] : myl;
+        if (ok) gq[myl] = mine;
+        topk_offer(e, kth, make_key(mine, (uint32_t)myl), ok, nprobe, lane);
+    }
+    if (lane < nprobe) probe[qi * nprobe + lane] = e != kEmptyKey ? (int32_t)(e & 0xffffffffu) : lane;
+    if (lane == 0) {
+        bad[qi] = 0;
+        tau[qi] = kInfBits;
+    }
+}
+
 // items per bucket: count, padded exclusive prefix, scatter (START items
 // r = 0 and the other ranks r >= 1 in two separate lists).  Only ranks in
 // [rlo, rhi) below the query's budget (if any) become items.
@@ -891,6 +1012,9 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     Carver c(ws);
     pl.qrot = c.take<float>(q * ix->d);
     pl.cd = c.take<float>(q * ix->nlist);
+    // up to 64 probes: centroid products on the matrix cores, exact sums only near the boundary
+    pl.qsq = nprobe <= kWave ? c.take<float>(q) : nullptr;
+    pl.csq = nprobe <= kWave ? c.take<float>((size_t)ix->nlist) : nullptr;
     pl.probe = c.take<int32_t>(q * nprobe);
     pl.bad = c.take<int32_t>(q);
     pl.tau = c.take<uint32_t>(q);
@@ -983,14 +1107,21 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
     if ((e = mark(0)) != hipSuccess) return e;
     // 1. rotation and centroid distances
     if (ix->has_rot) {
-        if ((e = launch_gemm_abt(q, nq, ix->rot, d, d, pl.qrot, d, s)) != hipSuccess) return e;
+        if ((e = launch_sgemm_abt(q, nq, ix->rot, d, d, pl.qrot, d, s)) != hipSuccess) return e;
     } else {
         if ((e = hipMemcpyAsync(pl.qrot, q, sizeof(float) * nq * d, hipMemcpyDeviceToDevice, s)) != hipSuccess)
             return e;
     }
-    if ((e = launch_pair(1, 0, pl.qrot, nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) !=
-        hipSuccess)
+    if (pl.csq) {  // products on the matrix cores; exact distances near the nprobe boundary (step 2)
+        if ((e = launch_sgemm_abt(pl.qrot, nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, s)) != hipSuccess)
+            return e;
+        row_norm_kernel<<<(unsigned)nq, 64, 0, s>>>(pl.qrot, d, pl.qsq);
+        row_norm_kernel<<<(unsigned)ix->nlist, 64, 0, s>>>(ix->centroids, d, pl.csq);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if ((e = launch_pair(1, 0, pl.qrot, nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, nullptr, s)) !=
+               hipSuccess) {
         return e;
+    }
     if (pl.qres && (e = launch_query_residuals(pl.qrot, nq, d, pl.chunk, pl.qres, s)) != hipSuccess) return e;
     if (pl.lp.qs &&
         (e = launch_lp_query(pl.qrot, nq, d, pl.dtype == PDX_DTYPE_FP8 ? ix->fp8_scale : nullptr, pl.lp, s)) !=
@@ -998,8 +1129,14 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         return e;
     // 2. nearest buckets
     int32_t pow2 = next_pow2(ix->nlist);
-    select_probe_kernel<<<(unsigned)nq, 256, pow2 * sizeof(uint64_t), s>>>(pl.cd, ix->nlist, pow2, q, d, pl.nprobe,
-                                                                         pl.probe, pl.bad, pl.tau);
+    if (pl.csq) {
+        probe_from_dot_kernel<<<(unsigned)((nq + 3) / 4), 256, 0, s>>>(pl.cd, nq, ix->nlist, pl.qsq, pl.csq, pl.qrot,
+                                                                       ix->centroids, q, d, pl.nprobe, pl.probe,
+                                                                       pl.bad, pl.tau);
+    } else {
+        select_probe_kernel<<<(unsigned)nq, 256, pow2 * sizeof(uint64_t), s>>>(pl.cd, ix->nlist, pow2, q, d,
+                                                                             pl.nprobe, pl.probe, pl.bad, pl.tau);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (pl.wide && (e = launch_wide_init(pl.ws, pl.cd, ix->nlist, pl.probe, pl.wide_rounds, s)) != hipSuccess) return e;
     // PDX-BOND: each query's dimension order by |q'_j - mean_j| (Section 5)

@@ -284,6 +284,7 @@ struct IvfPlan {
     float eps0;
     float *qrot;       // [nq][d]
     float *cd;         // [nq][nlist]
+    float *qsq, *csq;  // [nq] |q'|^2, [nlist] |c|^2 (centroid products on the matrix cores; null: vector ALU)
     int32_t *probe;    // [nq][nprobe]
     int32_t *bad;      // [nq]
     uint32_t *tau;     // [nq]
@@ -384,6 +385,11 @@ hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
 // C = A B^T on the matrix cores (A [m][k], B [n][k], C [m][ldc]).
 hipError_t launch_gemm_abt(const float *A, int64_t m, const float *B, int64_t n, int32_t k, float *C, int64_t ldc,
                            hipStream_t s);
+// The same through rocBLAS's f32 GEMM (allocates its handle on a device's
+// first call): the IVF search and build; the exact search keeps the kernel
+// above so that its no-allocation entry point allocates nothing.
+hipError_t launch_sgemm_abt(const float *A, int64_t m, const float *B, int64_t n, int32_t k, float *C, int64_t ldc,
+                            hipStream_t s);
 hipError_t launch_pair(int mode, int out, const float *A, int64_t m, const float *B, int64_t nb, int32_t k,
                        float *C, int64_t ldc, unsigned long long *best, hipStream_t s);
 hipError_t launch_qr_rotation(const double *gauss, int32_t d, double *acm, double *q, double *v, double *diag,

@@ -206,7 +206,7 @@ pdx_status pdx_ivf_build(const float *x, int64_t n, int32_t d, int32_t nlist, co
         TRY(hipGetLastError());
     }
     if (has_rot)
-        TRY(launch_gemm_abt(x, n, L.rot, d, d, L.xrot, d, s));
+        TRY(launch_sgemm_abt(x, n, L.rot, d, d, L.xrot, d, s));
     else
         TRY(hipMemcpyAsync(L.xrot, x, sizeof(float) * n * d, hipMemcpyDeviceToDevice, s));
     TRY(launch_column_means(L.xrot, n, d, L.mean_partial, kMeanChunksIvf, L.means, s));
