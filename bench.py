@@ -258,6 +258,36 @@ def bench_bond_ivf(pdx, torch, np, ix, q_dev, nprobes, k, steps, warmup, truth_i
     return out
 
 
+def bench_ivf_lowp(pdx, torch, np, ix, q_dev, k, nprobe, sched, steps, warmup, truth_ids, reranks=(16, 40)):
+    """The same IVF + ADSampling search over the index's bfloat16 and e4m3
+    copies (f32 rerank of the R best), at one operating point and schedule,
+    beside the f32 scan: QPS and recall@10 against the FP64 oracle."""
+    from oracle.exact import recall_at_k
+    nq = q_dev.shape[0]
+    rows = []
+    for dtype, rr in [("f32", 0)] + [(dt, r) for dt in ("bf16", "fp8") for r in reranks]:
+        kw = dict(sched, dtype=dtype, rerank=rr)
+        ws = torch.empty(max(1, pdx.pdx_search_ivf_workspace(
+            ix, nq, k, nprobe, delta_d=sched["delta_d"], queries_per_wave=sched["queries_per_wave"],
+            engine=sched["engine"], dtype=dtype, rerank=rr)), dtype=torch.uint8, device="cuda")
+        out = {}
+
+        def run(evs, ws=ws, out=out, kw=kw):
+            out["r"] = pdx.pdx_search_ivf(ix, q_dev, k, nprobe, eps0=2.1, workspace=ws, phase_events=evs, **kw)
+
+        elapsed, ph = timed_steps(run, steps, warmup, torch, np)
+        ids = out["r"][0].cpu().numpy()
+        rec = recall_at_k(truth_ids, ids[: truth_ids.shape[0]]) if truth_ids is not None else None
+        rows.append({"dtype": dtype, "rerank": rr if dtype != "f32" else None, "qps": round(nq * steps / elapsed, 1),
+                     "ms_per_step": round(1e3 * elapsed / steps, 3), "recall@10": None if rec is None else round(rec, 4),
+                     "phases_ms": {"prep_start": round(ph[0], 3), "pruned_scan": round(ph[1], 3),
+                                   "merge_rerank": round(ph[2], 3)}})
+        print(f"# ivf lowp {dtype} rerank {rr} nprobe {nprobe}: {rows[-1]['qps']} qps recall {rows[-1]['recall@10']}",
+              file=sys.stderr, flush=True)
+        del ws
+    return {"nprobe": nprobe, "schedule": sched, "rows": rows}
+
+
 def bench_bsa(pdx, torch, np, ix, q_dev, nprobes, ms, k, steps, warmup, truth_ids):
     """BSA's test (Section 2.3: Cauchy-Schwarz error quantiles with the
     multiplier m; m = 1 is exact within the probed buckets) on the vector-ALU
@@ -896,8 +926,14 @@ def main() -> int:
         extra["metrics"] = bench_metrics(pdx, torch, np, ix, q, k, 3, 1, n, d, layout)
     del ws
     if mode == "bond" and not args.no_ivf:
-        ivf_ix = build_ivf(pdx, torch, np, x, 1024)
-        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, [2, 4, 8, 16, 32, 64], k, 3, 1, truth, index=ivf_ix)
+        ivf_ix = build_ivf(pdx, torch, np, x, 1024, lowp=("bf16", "fp8"))
+        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, args.nprobe or [2, 4, 8, 16, 32, 64], k, 3, 1, truth,
+                                    index=ivf_ix, profile_md="ivf_mscan_bond_1m_d960.md", schedule=args.schedule)
+        best = next((r for r in extra["approx"]["sweep"] if r["nprobe"] == extra["approx"]["nprobe_at_recall_0.95"]),
+                    None)
+        if best is not None:  # the low-precision copies at the same point (f32 rerank)
+            extra["approx_lowp"] = bench_ivf_lowp(pdx, torch, np, ivf_ix[0], q, k, best["nprobe"], best["schedule"],
+                                                  3, 1, truth)
         extra["approx_bond_bound"] = bench_bond_ivf(pdx, torch, np, ivf_ix[0], q, [8, 16, 32], k, 3, 1, truth)
         if not args.no_pca:
             # BSA's projection (Section 2.3): the rows' principal directions in
