@@ -12,9 +12,12 @@
  *   Euclidean distance sum_i (v_i - q_i)^2 are returned.
  * - Every data pointer is a DEVICE pointer owned by the caller (e.g. a
  *   torch tensor), 16-byte aligned.  Matrices are row-major float32,
- *   contiguous.  The library never allocates device memory: the index
+ *   contiguous.  Indexes and search buffers are caller memory: the index
  *   lives in a caller buffer sized with the *_bytes query, and each search
- *   uses a caller workspace sized with the *_workspace query.
+ *   uses a caller workspace sized with the *_workspace query.  The only
+ *   device memory the library takes itself is rocBLAS's handle (its GEMM
+ *   workspace), once per device on the first IVF build or search, held
+ *   until the process ends; the exact search does not use it.
  * - `stream` is a hipStream_t passed as void*; NULL means the default
  *   stream.  Search calls only enqueue work on it (no host sync): outputs
  *   are valid once the caller synchronises the stream.  Build calls are
