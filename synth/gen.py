@@ -95,6 +95,19 @@ class Mixture:
     def data(self, n: int, start: int = 0) -> np.ndarray:
         return self.rows(n, _STREAM_DATA, 0, start)
 
+    def labels(self, n: int, start: int = 0) -> np.ndarray:
+        """Mixture component of data rows ``start .. start+n-1`` (int32)."""
+        out = np.empty(n, dtype=np.int32)
+        pos, r = 0, start
+        while pos < n:
+            b, off = divmod(r, _BLOCK)
+            take = min(_BLOCK - off, n - pos)
+            lab = _rng(self.seed, _STREAM_DATA, 0, b, 0).choice(self.weights.shape[0], size=_BLOCK, p=self.weights)
+            out[pos:pos + take] = lab[off:off + take]
+            pos += take
+            r += take
+        return out
+
     def queries(self, nq: int, query_seed: Optional[int] = None) -> np.ndarray:
         qs = self.seed if query_seed is None else query_seed
         return self.rows(nq, _STREAM_QUERY, qs, 0)

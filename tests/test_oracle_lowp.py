@@ -125,3 +125,25 @@ def test_rerank_hand_worked():
     c = g["cases"][0]
     assert _rerank_exact_first(xe, xa, rows, q, c["k"], c["r"])[0].tolist() != c["ids"]
     assert lowp.rerank(xe, xa, rows, q, c["k"], c["r"] + 1)[0].tolist() != c["ids"]
+
+
+def test_e4m3_array_encoding_equals_the_scalar_one():
+    """The whole-array encoder takes the scalar encoder's steps: equal codes
+    on every e4m3 code's value, the midpoints between neighbouring codes
+    (ties to even), values nudged either side of them, subnormals, zeros of
+    both signs, saturation, and random values over the whole range."""
+    codes = np.arange(256, dtype=np.uint8)
+    codes = codes[(codes & 0x7F) != 0x7F]  # no NaN codes
+    vals = lowp.e4m3_decode(codes).astype(np.float64)
+    pos = np.unique(vals[vals > 0])
+    mids = (pos[:-1] + pos[1:]) / 2
+    probe = np.concatenate([vals, mids, -mids, np.nextafter(mids.astype(np.float32), np.float32(0)),
+                            np.nextafter(mids.astype(np.float32), np.float32(np.inf)),
+                            [0.0, -0.0, 448.0, 449.0, 464.0, 1e6, -1e6, 2.0 ** -10, 2.0 ** -11, 3 * 2.0 ** -11]])
+    rng = np.random.default_rng(5)
+    probe = np.concatenate([probe, rng.standard_normal(20_000) * 2.0 ** rng.integers(-12, 10, 20_000)])
+    probe = probe.astype(np.float32)
+    assert np.array_equal(lowp.e4m3_encode_array(probe), lowp.e4m3_encode(probe))
+    x = rng.standard_normal((300, 24)).astype(np.float32) * 3
+    s = lowp.fp8_scales(x)
+    assert np.array_equal(lowp.fp8_encode_array(x, s), lowp.fp8_encode(x, s))

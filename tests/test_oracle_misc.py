@@ -105,3 +105,19 @@ def test_pca_rotation_against_svd_and_invariants():
     assert np.all(np.diff(np.diag(cr)) <= 1e-9 * lam[0])
     planted = r[::-1]
     assert not np.all(np.diff(np.diag(rotation.covariance(rotation.rotate_rows(x, planted)))) <= 1e-9 * lam[0])
+
+
+def test_mixture_labels_are_the_components_the_rows_came_from():
+    """synth.Mixture.labels: with far-apart means and tiny spreads every row
+    lies nearest the mean of its own component, across block boundaries."""
+    import synth
+    from synth.gen import Mixture
+    rng = np.random.default_rng(3)
+    means = (rng.standard_normal((12, 16)) * 100).astype(np.float32)
+    mix = Mixture(means, np.full((12, 16), 0.01, np.float32), np.full(12, 1 / 12), 7)
+    start, n = 60_000, 10_000  # spans a block boundary
+    x = mix.data(n, start)
+    lab = mix.labels(n, start)
+    near = np.argmin(((x[:, None, :] - means[None]) ** 2).sum(-1), axis=1)
+    assert np.array_equal(near, lab)
+    assert np.array_equal(mix.labels(n // 2, start + n // 2), lab[n // 2:])
