@@ -411,7 +411,7 @@ __device__ __forceinline__ void mscan_unit(
 // all batches of a bucket run on one XCD and share its L2.  Each wave
 // strides over its XCD's units.  Without xcd_range: unit = global wave index.
 template <bool PRUNE, int STORE, int MT, bool LP>
-__global__ __launch_bounds__(256) void ivf_mscan_kernel(
+__global__ __launch_bounds__(256, (MT == 1 && !LP) ? 3 : 1) void ivf_mscan_kernel(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ xcd_range, const int32_t *__restrict__ probe, int32_t nprobe,
