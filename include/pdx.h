@@ -146,6 +146,15 @@ typedef struct {
      * step).  Pairs the bucket layout's centroid bound skips are never
      * evaluated and count nowhere.  Slows the scan (atomics per chunk). */
     unsigned long long *chunk_survivors;
+    /* Schedule of the LDS-tile scan (PDX_MODE_BOND, L2 and L1; no effect on
+     * the result, which is exact whatever the schedule; pdx_exact_tune picks
+     * them).  rounds: launches the pruned range is split into, the k-th
+     * distances refreshed from the candidates in between (1..64; 0 = 4).
+     * dense_min, bucket layout: a (query, 32-row tile) pair with at least
+     * this many survivors after the first chunk is finished by the wave
+     * that found them, the rest queued (1..33, 33 = always queue; 0 = 8). */
+    int32_t rounds;
+    int32_t dense_min;
 } pdx_search_params;
 
 /* Workspace bytes for pdx_search_exact with these arguments. */
@@ -188,6 +197,36 @@ PDX_API size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, in
 PDX_API pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, int32_t k,
                             const pdx_search_params *params, void *ws, size_t ws_bytes,
                             int64_t *out_ids, float *out_dist, void *stream);
+
+/* pdx_exact_tune -- pick the fastest tile-scan schedule for an exact search.
+ *
+ * Times pdx_search_exact on the caller's queries (one warm-up, then the
+ * best of `reps` timed runs, HIP events on `stream`, synchronous) for each
+ * candidate: START block (start_rows 64, 128, 256; bucket layout), rounds
+ * (2, 4, 8) and dense_min (4, 8, 16; bucket layout), the 27 combinations
+ * in that nesting (start_rows outermost).  A candidate whose value cannot
+ * change this search (a flat index's start_rows and dense_min, a search
+ * that does not take the tile path) is timed only with that value at its
+ * default, and skipped otherwise.  Every schedule returns the same exact
+ * answer; only the time differs.
+ * params: in, the search to tune (mode, metric, chunk, tile_groups,
+ * queries_per_block kept); out, start_rows, rounds and dense_min of the
+ * fastest candidate.  table (may be NULL): PDX_EXACT_TUNE_CANDIDATES
+ * entries, filled in candidate order (ms < 0: skipped).  ws: at least
+ * pdx_exact_tune_workspace bytes, 16-byte aligned.  Returns PDX_EINVAL
+ * (null pointers, nq < 1, reps < 1, arguments pdx_search_exact rejects),
+ * PDX_EWORKSPACE, PDX_EHIP, or the search's own error. */
+#define PDX_EXACT_TUNE_CANDIDATES 27
+typedef struct {
+    int32_t start_rows, rounds, dense_min;
+    float ms; /* best timed run */
+} pdx_exact_schedule;
+
+PDX_API size_t pdx_exact_tune_workspace(const pdx_index *index, int64_t nq, int32_t k,
+                                        const pdx_search_params *params);
+PDX_API pdx_status pdx_exact_tune(const pdx_index *index, const float *q, int64_t nq, int32_t k,
+                                  pdx_search_params *params, int32_t reps, pdx_exact_schedule *table, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /* Static device scratch of pdx_search_exact_noalloc, per GPU. */
 #define PDX_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)

@@ -10,6 +10,7 @@ from .api import (  # noqa: F401
     ivf_test_points,
     pdx_build,
     pdx_distances,
+    pdx_exact_tune,
     pdx_ivf_build,
     pdx_ivf_export,
     pdx_ivf_tune,

@@ -65,7 +65,8 @@ class pdx_build_params(ctypes.Structure):
 class pdx_search_params(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("chunk", c_int32), ("tile_groups", c_int32),
                 ("queries_per_block", c_int32), ("phase_events", c_void_p), ("counters", c_void_p),
-                ("metric", c_int32), ("start_rows", c_int32), ("chunk_survivors", c_void_p)]
+                ("metric", c_int32), ("start_rows", c_int32), ("chunk_survivors", c_void_p),
+                ("rounds", c_int32), ("dense_min", c_int32)]
 
 
 class pdx_ivf_params(ctypes.Structure):
@@ -92,6 +93,13 @@ class pdx_ivf_schedule(ctypes.Structure):
 
 TUNE_CANDIDATES = 14
 
+
+class pdx_exact_schedule(ctypes.Structure):
+    _fields_ = [("start_rows", c_int32), ("rounds", c_int32), ("dense_min", c_int32), ("ms", ctypes.c_float)]
+
+
+EXACT_TUNE_CANDIDATES = 27
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "pdx_build_bytes": (c_size_t, [c_int64, c_int32, ctypes.POINTER(pdx_build_params)]),
@@ -116,6 +124,9 @@ SIGNATURES = {
     "pdx_search_ivf": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32,
                                  ctypes.POINTER(pdx_ivf_search_params), c_void_p, c_size_t,
                                  c_void_p, c_void_p, c_void_p]),
+    "pdx_exact_tune_workspace": (c_size_t, [c_void_p, c_int64, c_int32, ctypes.POINTER(pdx_search_params)]),
+    "pdx_exact_tune": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(pdx_search_params), c_int32,
+                                 ctypes.POINTER(pdx_exact_schedule), c_void_p, c_size_t, c_void_p]),
     "pdx_ivf_tune_workspace": (c_size_t, [c_void_p, c_int64, c_int32, c_int32,
                                           ctypes.POINTER(pdx_ivf_search_params)]),
     "pdx_ivf_tune": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32,

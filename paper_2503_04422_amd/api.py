@@ -119,9 +119,9 @@ _METRICS = {"l2": _lib.PDX_METRIC_L2, "l1": _lib.PDX_METRIC_L1, "ip": _lib.PDX_M
 
 def pdx_search_exact_workspace(index: PdxIndex, nq: int, k: int, mode: str = "bond", chunk: int = 0,
                                tile_groups: int = 0, queries_per_block: int = 0, metric: str = "l2",
-                               start_rows: int = 0) -> int:
+                               start_rows: int = 0, rounds: int = 0, dense_min: int = 0) -> int:
     p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block, None, None, _METRICS[metric],
-                               int(start_rows))
+                               int(start_rows), None, int(rounds), int(dense_min))
     return int(lib.pdx_search_exact_workspace(index.handle, nq, k, ctypes.byref(p)))
 
 
@@ -132,6 +132,7 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
                      phase_events=None, counters: Optional[torch.Tensor] = None,
                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, metric: str = "l2",
                      start_rows: int = 0, chunk_survivors: Optional[torch.Tensor] = None,
+                     rounds: int = 0, dense_min: int = 0,
                      stream: Optional[torch.cuda.Stream] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Exact k nearest neighbours; returns (ids [nq, k] int64, dist [nq, k] float32).
 
@@ -139,6 +140,8 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
     differences) or "ip" (-q.v, mode "linear" only).
     ``start_rows``: bucket layout, rows of the nearest bucket START scans
     (0 = 128).
+    ``rounds``, ``dense_min``: tile-scan schedule (0 = defaults 4 and 8;
+    pdx_exact_tune picks them); the result does not depend on them.
     ``phase_events``: optional ctypes array of 4 hipEvent_t handles;
     ``counters``: optional int64 GPU tensor of 4 value counters;
     ``chunk_survivors``: optional int64 GPU tensor of ceil(D / chunk)
@@ -149,7 +152,8 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
         raise ValueError("query dimension does not match the index")
     p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block,
                                ctypes.cast(phase_events, ctypes.c_void_p) if phase_events is not None else None,
-                               _ptr(counters), _METRICS[metric], int(start_rows), _ptr(chunk_survivors))
+                               _ptr(counters), _METRICS[metric], int(start_rows), _ptr(chunk_survivors),
+                               int(rounds), int(dense_min))
     if out is None:
         ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
         dist = torch.empty((nq, k), dtype=torch.float32, device=q.device)
@@ -418,6 +422,32 @@ def pdx_ivf_tune(index: PdxIndex, q: torch.Tensor, k: int, nprobe: int, eps0: fl
              "delta_d": p.delta_d}
     rows = [{"engine": t.engine, "queries_per_wave": t.queries_per_wave, "bucket_order": t.bucket_order,
              "delta_d": t.delta_d, "ms": round(float(t.ms), 4)} for t in table]
+    return sched, rows
+
+
+@_on_stream
+def pdx_exact_tune(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond", metric: str = "l2",
+                   chunk: int = 0, tile_groups: int = 0, queries_per_block: int = 0, reps: int = 3,
+                   stream: Optional[torch.cuda.Stream] = None):
+    """Fastest tile-scan schedule for this exact search (pdx_exact_tune).
+    Returns (schedule, table): schedule = keyword arguments for
+    pdx_search_exact (start_rows, rounds, dense_min); table = every
+    candidate with its best time in ms (-1: skipped)."""
+    q = _dev_f32(q, "q")
+    nq = q.shape[0]
+    if q.shape[1] != index.d:
+        raise ValueError("query dimension does not match the index")
+    p = _lib.pdx_search_params(_MODES[mode], chunk, tile_groups, queries_per_block, None, None, _METRICS[metric])
+    need = lib.pdx_exact_tune_workspace(index.handle, nq, k, ctypes.byref(p))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=q.device)
+    table = (_lib.pdx_exact_schedule * _lib.EXACT_TUNE_CANDIDATES)()
+    _hold_index(index)
+    st = lib.pdx_exact_tune(index.handle, _ptr(q), nq, k, ctypes.byref(p), int(reps), table, _ptr(ws), ws.numel(),
+                            _stream(stream))
+    check(st, "pdx_exact_tune")
+    sched = {"start_rows": p.start_rows, "rounds": p.rounds, "dense_min": p.dense_min}
+    rows = [{"start_rows": t.start_rows, "rounds": t.rounds, "dense_min": t.dense_min, "ms": round(float(t.ms), 4)}
+            for t in table]
     return sched, rows
 
 

@@ -582,10 +582,12 @@ __device__ __forceinline__ float tile_chunk(const float *__restrict__ tile, cons
     return octets(oc[0], oc[1], oc[2], oc[3]);
 }
 
-// One octet (8 visited dimensions) of a chunk for the tile's vectors p and
-// p + 16: each dimension's LDS row address serves both (one paired read).
-// All 8 paired reads are issued before the first sum, so a chunk waits for
-// one LDS round trip rather than one per pair of dimensions.
+// One octet (8 visited dimensions) of a chunk for the tile's adjacent
+// vectors 2p and 2p + 1: one 8-byte LDS read per dimension serves both.
+// The 16 lanes of an octet then read one whole 128-byte tile row, every
+// bank once, so the four octets of a wave (four rows) never wait on one
+// another's banks.  All 8 reads are issued before the first sum, so a
+// chunk waits for one LDS round trip rather than one per dimension.
 template <bool L1>
 __device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4 ow, float4 q0, float4 q1, int p,
                                            float &a, float &b) {
@@ -596,9 +598,9 @@ __device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4
     float ra[8], rb[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        const float *r = tile + o[u] + p;
-        ra[u] = r[0];
-        rb[u] = r[16];
+        const float2 r = *reinterpret_cast<const float2 *>(tile + o[u] + 2 * p);
+        ra[u] = r.x;
+        rb[u] = r.y;
     }
     a = 0.0f;
     b = 0.0f;
@@ -610,14 +612,14 @@ __device__ __forceinline__ void octet_pair(const float *__restrict__ tile, uint4
 }
 
 // A chunk's total for both vectors of a pair from the octet sums sa
-// (vector p) and sb (vector p + 16), one per 16-lane row (octets 0..3),
+// (the pair's first vector) and sb (its second), one per 16-lane row (octets 0..3),
 // combined as (o0 + o1) + (o2 + o3) in the VALU with no LDS round trip.
 // gfx950's first row swap (v_permlane16_swap) trades the odd rows of sa for
 // the even rows of sb, so the two results add to o0 + o1 (row 0) and
 // o2 + o3 (row 2) of vector p and the same (rows 1, 3) of vector p + 16;
 // the second (v_permlane32_swap, a value with itself) adds the halves.
-// Rows 0 and 2 end with vector p's total, rows 1 and 3 with vector
-// p + 16's.  The whole wave must be active.
+// Rows 0 and 2 end with the first vector's total, rows 1 and 3 with the
+// second's.  The whole wave must be active.
 __device__ __forceinline__ float pair_total(float sa, float sb) {
     const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(sa), __float_as_uint(sb), false, false);
     const float t = __uint_as_float(r[0]) + __uint_as_float(r[1]);
@@ -625,8 +627,8 @@ __device__ __forceinline__ float pair_total(float sa, float sb) {
     return __uint_as_float(r2[0]) + __uint_as_float(r2[1]);
 }
 
-// Bit v: vector v of the tile (pairs p, p + 16 held by lanes p of every
-// octet; the lanes of octet 0 stand for them).
+// Bit p: the first vector of lane p's pair, bit 16 + p: the second (pairs
+// held by lanes p of every octet; the lanes of octet 0 stand for them).
 __device__ __forceinline__ uint32_t pair_mask(bool a, bool b) {
     return static_cast<uint32_t>(__ballot(a) & 0xffffull) | (static_cast<uint32_t>(__ballot(b) & 0xffffull) << 16);
 }
@@ -651,10 +653,9 @@ struct FirstChunk {
     }
 };
 
-constexpr int kDense = 8;  // survivors of the first chunk from which a (query, tile) pair stays in its wave
 
 // DENSE (bucket layout, where a query's own cluster fills whole tiles): a
-// (query, tile) pair with at least kDense first-chunk survivors is finished
+// (query, tile) pair with at least dense_min first-chunk survivors is finished
 // by its wave; other survivors go to the queue.  On this layout a tile's
 // rows lie within radius r of their bucket's centroid c, so every row is at
 // squared distance at least (|q - c| - r)^2 from the query (triangle
@@ -683,7 +684,7 @@ __global__ __launch_bounds__(NW * 64) void tile_kernel(
     const int32_t *__restrict__ bad, uint64_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int32_t cap,
     uint64_t *__restrict__ gqueue, unsigned long long *__restrict__ counters, const float *__restrict__ dql,
     const int32_t *__restrict__ group_bucket, const float *__restrict__ tile_rad, int32_t *__restrict__ tile_ctr,
-    unsigned long long *__restrict__ surv) {
+    unsigned long long *__restrict__ surv, int32_t dense_min) {
     constexpr int NT = NW * 64;
     extern __shared__ float4 smem4[];
     float *tile = reinterpret_cast<float *>(smem4);                          // [d][32]
@@ -692,7 +693,7 @@ __global__ __launch_bounds__(NW * 64) void tile_kernel(
     __shared__ int32_t qlist[DENSE ? kList : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int pr = lane & 15;   // vector pair (pr, pr + 16) of the tile
+    const int pr = lane & 15;   // vector pair (2 pr, 2 pr + 1) of the tile
     const int oct = lane >> 4;  // octet of the chunk
     const int32_t nchunks = d / 32;
     uint64_t *gq = gqueue + (size_t)blockIdx.x * kGCap;  // this workgroup's overflow entries
@@ -745,7 +746,7 @@ __global__ __launch_bounds__(NW * 64) void tile_kernel(
         }
         // while the loads are in flight: the pair's row ids (-1: padding)
         // and the first list of queries
-        const int64_t vid_a = (int64_t)t * kTV + pr, vid_b = vid_a + 16;
+        const int64_t vid_a = (int64_t)t * kTV + 2 * pr, vid_b = vid_a + 1;
         const int32_t rid_a = slot_id ? slot_id[vid_a] : (vid_a < n ? (int32_t)vid_a : -1);
         const int32_t rid_b = slot_id ? slot_id[vid_b] : (vid_b < n ? (int32_t)vid_b : -1);
         int32_t tb = 0;
@@ -798,16 +799,17 @@ __global__ __launch_bounds__(NW * 64) void tile_kernel(
                 float4 qa0, qa1;
                 float sa, sb;
                 octet_pair<L1>(tile, cur.o, cur.q[0], cur.q[1], pr, sa, sb);
-                // this lane's vector (pr in rows 0 and 2, pr + 16 in rows 1 and 3)
+                // this lane's vector (2 pr in rows 0 and 2, 2 pr + 1 in rows 1 and 3)
                 const float p1 = pair_total(sa, sb);
                 const bool al1 = rid_v >= 0 && !(p1 > cur.tau);
                 if (counters) {
                     live_vals += 32ull * __popc(valid_m);
                     lane_vals += 64ull * 16;
                 }
-                const uint32_t m = static_cast<uint32_t>(__ballot(al1));  // bit v: vector v (rows 0 and 1)
+                // bit b: lane b of rows 0 and 1, vector 2 (b & 15) + (b >> 4)
+                const uint32_t m = static_cast<uint32_t>(__ballot(al1));
                 if (STATS && lane == 0 && m) atomicAdd(surv, (unsigned long long)__popc(m));
-                if (DENSE && m != 0 && nchunks > 1 && __popc(m) >= kDense) {
+                if (DENSE && m != 0 && nchunks > 1 && __popc(m) >= dense_min) {
                     // dense pair: this wave finishes the query on the tile,
                     // lanes = 16 vector pairs x 4 octets as in the first
                     // chunk; the next chunk's metadata is fetched while the
@@ -860,12 +862,13 @@ __global__ __launch_bounds__(NW * 64) void tile_kernel(
                         int base = 0;
                         if (lane == 0) base = atomicAdd(&qcount[p], __popc(m));
                         base = __shfl(base, 0);
-                        // queue slot of vector v: base + the survivors below
-                        // v; rows 0 and 1 enqueue their vectors
+                        // queue slot of lane b's vector: base + the
+                        // survivors of the lanes below b; rows 0 and 1 enqueue
+                        // their vectors
                         bool own = false;  // both queues are full: finish it here
                         if (oct < 2 && al1) {
-                            const int vv = pr + 16 * oct;
-                            const int pos = base + __popc(m & ((1u << vv) - 1u));
+                            const int vb = pr + 16 * oct, vv = 2 * pr + oct;
+                            const int pos = base + __popc(m & ((1u << vb) - 1u));
                             const uint32_t key = (static_cast<uint32_t>(qi) << 5) | static_cast<uint32_t>(vv);
                             if (pos < kQCap)
                                 queue[pos] = make_uint2(key, __float_as_uint(p1));
@@ -875,7 +878,7 @@ __global__ __launch_bounds__(NW * 64) void tile_kernel(
                                 own = true;
                         }
                         if (__any(own)) {
-                            const int vv = pr + 16 * (oct & 1);
+                            const int vv = 2 * pr + (oct & 1);
                             const uint16_t *pf = poff + qi * d;
                             const float *qp = qperm + qi * d;
                             float x = p1;
@@ -973,7 +976,6 @@ int32_t next_pow2(int32_t v) {
 
 constexpr int32_t kCandCap = 2048;     // candidates per query in the tile path
 constexpr int32_t kCandCapIp = 65536;  // the inner product's largest (looser START threshold)
-constexpr int32_t kRounds = 4;      // threshold refreshes in the tile path
 constexpr int32_t kRoundsIp = 16;   // the inner product's least (rounds are also bounded by the buffer size)
 
 size_t tile_lds_bytes(int32_t d) { return (size_t)d * kTV * sizeof(float) + kQCap * sizeof(uint2); }
@@ -1198,16 +1200,17 @@ __global__ __launch_bounds__(256) void ip_fallback_kernel(const float *__restric
 }
 
 // One octet of a chunk (8 consecutive dimensions from j) for the tile's
-// vectors p and p + 16: q.x terms.
+// adjacent vectors 2p and 2p + 1 (one 8-byte read per dimension, as in
+// octet_pair): q.x terms.
 __device__ __forceinline__ void octet_pair_ip(const float *__restrict__ tile, int32_t j, float4 q0, float4 q1, int p,
                                               float &a, float &b) {
     const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
     float ra[8], rb[8];  // all reads issued before the first product
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        const float *r = tile + (j + u) * kTV + p;
-        ra[u] = r[0];
-        rb[u] = r[16];
+        const float2 r = *reinterpret_cast<const float2 *>(tile + (j + u) * kTV + 2 * p);
+        ra[u] = r.x;
+        rb[u] = r.y;
     }
     a = 0.0f;
     b = 0.0f;
@@ -1253,7 +1256,7 @@ __global__ __launch_bounds__(1024) void ip_tile_kernel(
                                              (lds_void_t *)(tile + (size_t)iw * 4), 16, 0, 0);
         }
         __syncthreads();
-        const int64_t vid_a = (int64_t)t * kTV + pr, vid_b = vid_a + 16;
+        const int64_t vid_a = (int64_t)t * kTV + 2 * pr, vid_b = vid_a + 1;
         const int32_t rid_a = slot_id[vid_a], rid_b = slot_id[vid_b];
         const uint32_t valid_m = pair_mask(rid_a >= 0, rid_b >= 0);
         const int32_t tb = group_bucket[t >> 1];
@@ -1280,7 +1283,7 @@ __global__ __launch_bounds__(1024) void ip_tile_kernel(
             for (int32_t e = wave; e < cnt; e += kTW) {
                 const int64_t qi = qlist[e];
                 const float *qr = q + qi * d + oct * 8;
-                float x = 0.0f;  // this lane's vector: pr in rows 0 and 2, pr + 16 in rows 1 and 3
+                float x = 0.0f;  // this lane's vector: 2 pr in rows 0 and 2, 2 pr + 1 in rows 1 and 3
                 auto ip_step = [&](int32_t c, const float4 qc0, const float4 qc1) {
                     float sa, sb;
                     octet_pair_ip(tile, c * 32 + oct * 8, qc0, qc1, pr, sa, sb);
@@ -1333,6 +1336,8 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.chunk = (p && p->chunk > 0) ? p->chunk : 32;
     pl.tile_groups = (p && p->tile_groups > 0) ? p->tile_groups : 16;
     pl.qpb = (p && p->queries_per_block > 0) ? p->queries_per_block : 4;
+    pl.rounds = (p && p->rounds > 0) ? p->rounds : kDefaultRounds;
+    pl.dense_min = (p && p->dense_min > 0) ? p->dense_min : kDefaultDenseMin;
     pl.ivf = ix->kind == kIvf;
     pl.metric = p ? p->metric : PDX_METRIC_L2;
     if (pl.ivf) {
@@ -1384,7 +1389,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
         const int32_t cus = device_cus();
         pl.tile_grid = cus;  // one workgroup per compute unit (the LDS tile fills the CU)
         pl.gqueue = c.take<uint64_t>((size_t)cus * kGCap);
-        pl.tile_ctr = c.take<int32_t>(64);
+        pl.tile_ctr = c.take<int32_t>(kMaxTileRounds);
         if (ip_tiles) {  // about 1 GiB of buffers at most; fewer entries mean more rounds
             const int64_t fit = ((int64_t)1 << 30) / (int64_t)sizeof(uint64_t) / std::max<int64_t>(nq, 1);
             pl.cand_cap = (int32_t)std::max<int64_t>(4096, std::min<int64_t>(kCandCapIp, fit / 64 * 64));
@@ -1601,17 +1606,18 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
     const int32_t t0 = 2 * pl.start_groups, t1 = 2 * ix->ngroups;
     const int cus = pl.tile_grid;
     const float *trad = pl.ivf ? (l1 ? ix->tile_rad1 : ix->tile_rad) : nullptr;
-    if ((err = launch_fill_i32(pl.tile_ctr, kRounds, 0, s)) != hipSuccess) return err;
-    for (int32_t r = 0; r < kRounds; ++r) {
-        const int32_t a = t0 + (int32_t)((int64_t)(t1 - t0) * r / kRounds);
-        const int32_t b = t0 + (int32_t)((int64_t)(t1 - t0) * (r + 1) / kRounds);
+    const int32_t rounds = pl.rounds;
+    if ((err = launch_fill_i32(pl.tile_ctr, rounds, 0, s)) != hipSuccess) return err;
+    for (int32_t r = 0; r < rounds; ++r) {
+        const int32_t a = t0 + (int32_t)((int64_t)(t1 - t0) * r / rounds);
+        const int32_t b = t0 + (int32_t)((int64_t)(t1 - t0) * (r + 1) / rounds);
         if (b <= a) continue;
         const unsigned grid = (unsigned)min(b - a, cus);
 #define PDX_TILE(DN, M, ST)                                                                                      \
     tile_kernel<DN, M, ST, kTileWaves><<<grid, kTileWaves * 64, tile_lds, s>>>(ix->pdx, ix->n, sid, d, a, b, pl.nq, pl.poff, pl.qperm,     \
                                                         pl.tau, pl.bad, pl.cand, pl.cand_cnt, pl.cand_cap, pl.gqueue, \
                                                         cmain, DN ? pl.dql : nullptr, DN ? ix->group_bucket : nullptr, \
-                                                        trad, pl.tile_ctr + r, pl.surv)
+                                                        trad, pl.tile_ctr + r, pl.surv, pl.dense_min)
         if (st) {
             if (pl.ivf) {
                 if (l1) PDX_TILE(true, true, true);
@@ -1629,7 +1635,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         }
 #undef PDX_TILE
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        if (r + 1 < kRounds) {
+        if (r + 1 < rounds) {
             cand_merge_kernel<<<nqu, 64, 0, s>>>(pl.cand, pl.cand_cnt, pl.cand_cap, 0, pl.k, pl.bad, pl.tau, nullptr, 0,
                                                  0, 0, nullptr, nullptr, nullptr, pl.ivf ? 1 : 0);
             if ((err = hipGetLastError()) != hipSuccess) return err;

@@ -176,6 +176,11 @@ pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, 
         set_error("pdx_search_exact: bad chunk / tile_groups / queries_per_block");
         return PDX_EINVAL;
     }
+    if (params && (params->rounds < 0 || params->rounds > kMaxTileRounds || params->dense_min < 0 ||
+                   params->dense_min > 33)) {
+        set_error("pdx_search_exact: rounds must be in [0, %d], dense_min in [0, 33]", kMaxTileRounds);
+        return PDX_EINVAL;
+    }
     if (nq == 0) return PDX_OK;
     if (!q || !ws || !out_ids || !out_dist) {
         set_error("pdx_search_exact: null pointer");

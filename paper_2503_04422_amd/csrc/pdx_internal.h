@@ -90,6 +90,8 @@ struct ExactPlan {
     int32_t chunk;
     int32_t tile_groups;
     int32_t qpb;           // queries per workgroup (waves per block)
+    int32_t rounds;        // tile path (L2, L1): launches over the pruned range, threshold refreshed between
+    int32_t dense_min;     // bucket-layout tile path: first-chunk survivors that keep a (query, tile) pair in its wave
     int32_t start_groups;  // groups scanned by START
     int32_t tiles_start;
     int32_t tiles_main;
@@ -131,6 +133,9 @@ struct ExactPlan {
 };
 
 constexpr int32_t kDefaultQueriesPerWave = 4;
+constexpr int32_t kDefaultRounds = 4;     // exact tile path: threshold refreshes
+constexpr int32_t kDefaultDenseMin = 8;   // exact tile path, bucket layout: dense continuation from this many survivors
+constexpr int32_t kMaxTileRounds = 64;    // exact tile path: next-tile counters in the workspace
 constexpr int32_t kMaxSplit = 8;
 constexpr int32_t kMaxWideRounds = 1024;  // compaction + resume rounds of the candidate buffer
 

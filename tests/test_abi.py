@@ -42,6 +42,8 @@ def test_host_side_argument_errors():
                          ctypes.byref(h)) == _lib.PDX_EINVAL
     assert lib.pdx_search_exact(None, None, 1, 10, None, None, 0, None, None, None) == _lib.PDX_EINVAL
     assert lib.pdx_search_exact_workspace(None, 1, 10, None) == 0
+    assert lib.pdx_exact_tune_workspace(None, 1, 10, None) == 0
+    assert lib.pdx_exact_tune(None, None, 1, 10, None, 1, None, None, 0, None) == _lib.PDX_EINVAL
     assert lib.pdx_search_ivf(None, None, 1, 10, 1, None, None, 0, None, None, None) == _lib.PDX_EINVAL
     assert lib.pdx_query_order(None, None, 1, 1, None, None, None, None, 0, None) == _lib.PDX_EINVAL
     assert lib.pdx_query_order_workspace(None, 1) == 0

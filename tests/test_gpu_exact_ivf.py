@@ -65,7 +65,8 @@ def test_bond_skewed_bucket_layout(pdx):
     wi, wd = exact.knn_exact_c(x, q, 10)
     ref = None
     for kw in (dict(), dict(tile_groups=3, queries_per_block=1), dict(chunk=8, queries_per_block=8),
-               dict(start_rows=1), dict(start_rows=1 << 20)):
+               dict(start_rows=1), dict(start_rows=1 << 20), dict(rounds=1, dense_min=1),
+               dict(rounds=64, dense_min=33), dict(rounds=7, dense_min=16)):
         gi, gd = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10, mode="bond", **kw))
         check_knn(x, q, gi, gd, wi, wd)
         if kw.get("chunk", 32) == 32:  # same summation order: bit-identical across schedules and START sizes
@@ -144,3 +145,38 @@ def test_full_size_bucket_layout_sampled(pdx):
     check_knn(x, q[sample], gi[sample], gd[sample], wi, wd)
     assert (np.diff(gd, axis=1) >= 0).all()
     assert (gi >= 0).all() and (gi < x.shape[0]).all()
+
+
+def test_exact_tuner_schedules_give_one_answer(pdx):
+    """pdx_exact_tune times START block x rounds x dense threshold; every
+    schedule returns the same exact answer (bit-identical: the summation
+    order per (query, vector) is fixed), the chosen one is the fastest
+    measured, and values that cannot change a search are not timed."""
+    from paper_2503_04422_amd._lib import PdxError
+    x, q, _ = synth.workload("bond_1m_d960", n=40_000, nq=64)
+    print("exact tuner 40k x 960, 64 queries", flush=True)
+    ix = _bucket_index(pdx, x, 64, 2)
+    sched, table = pdx.pdx_exact_tune(ix, _dev(q), 10, reps=1)
+    assert len(table) == 27
+    assert [(t["start_rows"], t["rounds"], t["dense_min"]) for t in table] == [
+        (s, r, m) for s in (64, 128, 256) for r in (2, 4, 8) for m in (4, 8, 16)]
+    assert all(t["ms"] >= 0 for t in table)  # bucket layout, L2 BOND: every value matters
+    best = min(table, key=lambda t: t["ms"])
+    assert sched == {kk: best[kk] for kk in ("start_rows", "rounds", "dense_min")}
+    ri, rd = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10))
+    ti, td = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10, **sched))
+    assert np.array_equal(ri, ti) and np.array_equal(rd, td)
+    wi, wd = exact.knn_exact_c(x, q, 10)
+    check_knn(x, q, ti, td, wi, wd)
+    # flat index: START comes from the build and there is no dense path
+    fx = pdx.pdx_build(_dev(x))
+    fs, ft = pdx.pdx_exact_tune(fx, _dev(q), 10, reps=1)
+    timed = [(t["start_rows"], t["rounds"], t["dense_min"]) for t in ft if t["ms"] >= 0]
+    assert timed == [(128, 2, 8), (128, 4, 8), (128, 8, 8)]
+    assert fs["start_rows"] == 128 and fs["dense_min"] == 8
+    # linear mode takes no tile path: only the defaults run
+    ls, lt = pdx.pdx_exact_tune(fx, _dev(q), 10, mode="linear", reps=1)
+    assert [t["ms"] >= 0 for t in lt].count(True) == 1 and ls == {"start_rows": 128, "rounds": 4, "dense_min": 8}
+    for kw in (dict(rounds=65), dict(dense_min=34), dict(rounds=-1)):
+        with pytest.raises(PdxError):
+            pdx.pdx_search_exact(ix, _dev(q), 10, **kw)
