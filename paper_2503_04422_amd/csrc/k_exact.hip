@@ -736,13 +736,16 @@ __global__ __launch_bounds__(NW * 64) void tile_kernel(
         // stage 32 vectors x d dimensions (one 128-byte half row per
         // dimension) with direct global-to-LDS loads: a wave's 64 lanes
         // bring 16 bytes each into 1 KB of contiguous LDS, 8 tile rows, with
-        // no registers holding the data, so every piece is in flight at once
+        // no registers holding the data, so every piece is in flight at once.
+        // The loads are non-temporal (cache policy 2): the rows are read
+        // once per launch, and streaming them past the L2 keeps the queries'
+        // visit orders and values, read again for every tile, resident.
         const float *src = pdxd + (int64_t)(t >> 1) * d * kGroup + (t & 1) * kTV;
         const int32_t nv4 = d * 8;  // a multiple of 64: whole waves
         for (int32_t iw = wave * 64; iw < nv4; iw += NT) {
             const int32_t i = iw + lane;
             __builtin_amdgcn_global_load_lds(src + (int64_t)(i >> 3) * kGroup + (i & 7) * 4,
-                                             (lds_void_t *)(tile + (size_t)iw * 4), 16, 0, 0);
+                                             (lds_void_t *)(tile + (size_t)iw * 4), 16, 0, 2);
         }
         // while the loads are in flight: the pair's row ids (-1: padding)
         // and the first list of queries
@@ -1249,11 +1252,11 @@ __global__ __launch_bounds__(1024) void ip_tile_kernel(
         const int32_t t = next_t;
         if (t >= t_end) break;
         const float *src = pdxd + (int64_t)(t >> 1) * d * kGroup + (t & 1) * kTV;
-        const int32_t nv4 = d * 8;
+        const int32_t nv4 = d * 8;  // non-temporal, as in tile_kernel
         for (int32_t iw = wave * 64; iw < nv4; iw += 1024) {
             const int32_t i = iw + lane;
             __builtin_amdgcn_global_load_lds(src + (int64_t)(i >> 3) * kGroup + (i & 7) * 4,
-                                             (lds_void_t *)(tile + (size_t)iw * 4), 16, 0, 0);
+                                             (lds_void_t *)(tile + (size_t)iw * 4), 16, 0, 2);
         }
         __syncthreads();
         const int64_t vid_a = (int64_t)t * kTV + 2 * pr, vid_b = vid_a + 1;
