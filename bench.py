@@ -21,7 +21,8 @@ skewed Gaussian mixture standing in for GIST/960), 1,000 queries, K = 10.
   bound, at recall@10 >= 0.95 on 10,000 evaluation queries.  extra.metrics:
   L1 with PDX-BOND and the inner product (matrix-core linear scan) on the
   exact search's index and queries.
-* roofline: the dominant kernel (the LDS-tile scan, 4 launches per step):
+* roofline: the dominant kernel (the LDS-tile scan, 2 launches per step on
+  the bucket layout, 4 on the flat one):
   algorithmic flops (3 per evaluated value, from the library's counters)
   over its event-timed duration, against the published FP32 vector peak
   (157.3 TFLOP/s), with the fraction of the non-packed vector-ALU issue
@@ -857,9 +858,10 @@ def main() -> int:
     # the 2,048-entry survivor queue and the query list in 160 KB of LDS
     tile_path = mode == "bond" and d % 32 == 0 and d * 128 + 2048 * 8 + 4160 <= 160 * 1024
     if tile_path:
-        # 4 launches of tile_kernel per step (threshold refreshed in between);
-        # per-launch figures are the step totals divided by 4
-        launches = 4
+        # the library's default rounds: 2 launches of tile_kernel per step on
+        # the bucket layout, 4 on the flat one (threshold refreshed in
+        # between); per-launch figures are the step totals divided by them
+        launches = 2 if layout == "buckets" else 4
         flops = 3.0 * c[2] / launches
         launch_ms = kern_ms / launches
         achieved = flops / (launch_ms * 1e-3) / 1e12 if launch_ms > 0 else 0.0

@@ -149,10 +149,11 @@ typedef struct {
     /* Schedule of the LDS-tile scan (PDX_MODE_BOND, L2 and L1; no effect on
      * the result, which is exact whatever the schedule; pdx_exact_tune picks
      * them).  rounds: launches the pruned range is split into, the k-th
-     * distances refreshed from the candidates in between (1..64; 0 = 4).
+     * distances refreshed from the candidates in between (1..64; 0 = 2
+     * on the bucket layout, 4 on the flat one).
      * dense_min, bucket layout: a (query, 32-row tile) pair with at least
      * this many survivors after the first chunk is finished by the wave
-     * that found them, the rest queued (1..33, 33 = always queue; 0 = 8). */
+     * that found them, the rest queued (1..33, 33 = always queue; 0 = 4). */
     int32_t rounds;
     int32_t dense_min;
 } pdx_search_params;

@@ -140,7 +140,8 @@ def pdx_search_exact(index: PdxIndex, q: torch.Tensor, k: int, mode: str = "bond
     differences) or "ip" (-q.v, mode "linear" only).
     ``start_rows``: bucket layout, rows of the nearest bucket START scans
     (0 = 128).
-    ``rounds``, ``dense_min``: tile-scan schedule (0 = defaults 4 and 8;
+    ``rounds``, ``dense_min``: tile-scan schedule (0 = defaults: rounds 2 on
+    the bucket layout and 4 on the flat one, dense_min 4;
     pdx_exact_tune picks them); the result does not depend on them.
     ``phase_events``: optional ctypes array of 4 hipEvent_t handles;
     ``counters``: optional int64 GPU tensor of 4 value counters;

@@ -1339,9 +1339,9 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.chunk = (p && p->chunk > 0) ? p->chunk : 32;
     pl.tile_groups = (p && p->tile_groups > 0) ? p->tile_groups : 16;
     pl.qpb = (p && p->queries_per_block > 0) ? p->queries_per_block : 4;
-    pl.rounds = (p && p->rounds > 0) ? p->rounds : kDefaultRounds;
-    pl.dense_min = (p && p->dense_min > 0) ? p->dense_min : kDefaultDenseMin;
     pl.ivf = ix->kind == kIvf;
+    pl.rounds = (p && p->rounds > 0) ? p->rounds : (pl.ivf ? kDefaultRoundsBuckets : kDefaultRounds);
+    pl.dense_min = (p && p->dense_min > 0) ? p->dense_min : kDefaultDenseMin;
     pl.metric = p ? p->metric : PDX_METRIC_L2;
     if (pl.ivf) {
         pl.start_groups = 0;  // START is each query's nearest bucket

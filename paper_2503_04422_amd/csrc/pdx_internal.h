@@ -133,8 +133,9 @@ struct ExactPlan {
 };
 
 constexpr int32_t kDefaultQueriesPerWave = 4;
-constexpr int32_t kDefaultRounds = 4;     // exact tile path: threshold refreshes
-constexpr int32_t kDefaultDenseMin = 8;   // exact tile path, bucket layout: dense continuation from this many survivors
+constexpr int32_t kDefaultRounds = 4;     // exact tile path, flat layout: threshold refreshes
+constexpr int32_t kDefaultRoundsBuckets = 2;  // the same on the bucket layout (the centroid bound prunes early)
+constexpr int32_t kDefaultDenseMin = 4;   // exact tile path, bucket layout: dense continuation from this many survivors
 constexpr int32_t kMaxTileRounds = 64;    // exact tile path: next-tile counters in the workspace
 constexpr int32_t kMaxSplit = 8;
 constexpr int32_t kMaxWideRounds = 1024;  // compaction + resume rounds of the candidate buffer

@@ -172,11 +172,11 @@ def test_exact_tuner_schedules_give_one_answer(pdx):
     fx = pdx.pdx_build(_dev(x))
     fs, ft = pdx.pdx_exact_tune(fx, _dev(q), 10, reps=1)
     timed = [(t["start_rows"], t["rounds"], t["dense_min"]) for t in ft if t["ms"] >= 0]
-    assert timed == [(128, 2, 8), (128, 4, 8), (128, 8, 8)]
-    assert fs["start_rows"] == 128 and fs["dense_min"] == 8
+    assert timed == [(128, 2, 4), (128, 4, 4), (128, 8, 4)]
+    assert fs["start_rows"] == 128 and fs["dense_min"] == 4
     # linear mode takes no tile path: only the defaults run
     ls, lt = pdx.pdx_exact_tune(fx, _dev(q), 10, mode="linear", reps=1)
-    assert [t["ms"] >= 0 for t in lt].count(True) == 1 and ls == {"start_rows": 128, "rounds": 4, "dense_min": 8}
+    assert [t["ms"] >= 0 for t in lt].count(True) == 1 and ls == {"start_rows": 128, "rounds": 4, "dense_min": 4}
     for kw in (dict(rounds=65), dict(dense_min=34), dict(rounds=-1)):
         with pytest.raises(PdxError):
             pdx.pdx_search_exact(ix, _dev(q), 10, **kw)
