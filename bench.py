@@ -929,7 +929,8 @@ def main() -> int:
     del ws
     if mode == "bond" and not args.no_ivf:
         ivf_ix = build_ivf(pdx, torch, np, x, 1024, lowp=("bf16", "fp8"))
-        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, args.nprobe or [2, 4, 8, 16, 32, 64], k, 3, 1, truth,
+        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, args.nprobe or [2, 4, 8, 12, 14, 16, 32, 64], k, 3, 1,
+                                    truth,
                                     index=ivf_ix, profile_md="ivf_mscan_bond_1m_d960.md", schedule=args.schedule)
         best = next((r for r in extra["approx"]["sweep"] if r["nprobe"] == extra["approx"]["nprobe_at_recall_0.95"]),
                     None)
