@@ -148,57 +148,100 @@ __global__ __launch_bounds__(kSelThreads) void wide_select_kernel(WideSink w, in
 }
 
 // Exact f32 distance of each of the R candidates, written back as its key
-// in place (one lane per candidate, one query per wave).  The summation
-// order is the vector scans': each chunk of `chunk` dimensions summed in
-// order, the chunk sums added in order.
+// in place (one wave per 64 candidates of one query, a lane per candidate).
+// The summation order is the vector scans': each chunk of `chunk`
+// dimensions summed in order, the chunk sums added in order.  The rows are
+// read a slab of 32 dimensions at a time: coalesced loads (8 lanes per
+// 128-byte row segment) put the slab of the wave's 64 rows in its LDS
+// (row stride 33 floats, so the lanes' reads of one dimension fall in
+// distinct banks), and each lane then sums its own row's dimensions in
+// order.  A lane per row reading its row alone would touch 64 lines per
+// load and re-fetch each line for every 16 bytes of it.
+constexpr int kSlab = 32;
+constexpr int kSlabPitch = kSlab + 1;
 __global__ __launch_bounds__(256) void wide_rerank_kernel(WideSink w, const float *__restrict__ xrow,
                                                           const float *__restrict__ qrot, int32_t d, int32_t chunk,
                                                           const int32_t *__restrict__ bad) {
+    __shared__ float slab_all[4][kWave * kSlabPitch];
     const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
     const int32_t nblk = (w.r + 63) / 64;
-    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t wv = (int64_t)blockIdx.x * 4 + wid;
     const int64_t q = __builtin_amdgcn_readfirstlane((int32_t)(wv / nblk));
     const int32_t blk = (int32_t)(wv % nblk);
-    if (q >= w.nq || bad[q]) return;
+    if (q >= w.nq || bad[q]) return;  // whole waves
     const int32_t i = blk * 64 + lane;
-    if (i >= w.r) return;
     uint64_t *row = w.buf + q * (int64_t)w.cap;
-    const uint64_t key = row[i];
-    if (key == kEmptyKey) return;
+    const uint64_t key = i < w.r ? row[i] : kEmptyKey;
+    const bool live = key != kEmptyKey;
     const uint32_t id = (uint32_t)(key & 0xffffffffu);
-    const float *x = xrow + (int64_t)id * d;
+    float *sl = slab_all[wid];
     const float *qp = qrot + q * d;
-    float partial = 0.0f;
-    if ((d & 3) == 0 && (chunk & 3) == 0) {
-        const float4 *x4 = reinterpret_cast<const float4 *>(x);
-        for (int32_t c0 = 0; c0 < d; c0 += chunk) {
-            const int32_t c1 = min(c0 + chunk, d);
-            float s = 0.0f;
-            for (int32_t j = c0; j < c1; j += 4) {
-                const float4 v = x4[j >> 2];
-                float t = qp[j] - v.x;
-                s = fmaf(t, t, s);
-                t = qp[j + 1] - v.y;
-                s = fmaf(t, t, s);
-                t = qp[j + 2] - v.z;
-                s = fmaf(t, t, s);
-                t = qp[j + 3] - v.w;
-                s = fmaf(t, t, s);
-            }
-            partial += s;
-        }
-    } else {
-        for (int32_t c0 = 0; c0 < d; c0 += chunk) {
-            const int32_t c1 = min(c0 + chunk, d);
-            float s = 0.0f;
-            for (int32_t j = c0; j < c1; ++j) {
-                const float t = qp[j] - x[j];
-                s = fmaf(t, t, s);
-            }
-            partial += s;
-        }
+    const bool vec = (d & 3) == 0;
+    // the rows this lane loads: row (lane >> 3) + 8u (vector path) or
+    // (lane >> 5) + 2u (scalar path) of the wave's 64
+    const float *src[8];
+    bool ok[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int r = (lane >> 3) + 8 * u;
+        ok[u] = __shfl((int)live, r) != 0;
+        src[u] = xrow + (int64_t)(uint32_t)__shfl((int)id, r) * d;
     }
-    row[i] = make_key(partial, id);
+    float partial = 0.0f, s = 0.0f;
+    int32_t cb = chunk;  // next chunk boundary
+    for (int32_t j0 = 0; j0 < d; j0 += kSlab) {
+        const int32_t jn = min(kSlab, d - j0);
+        if (vec) {
+            const int c4 = 4 * (lane & 7);
+            float4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = (ok[u] && c4 < jn) ? *reinterpret_cast<const float4 *>(src[u] + j0 + c4)
+                                          : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                float *o = sl + ((lane >> 3) + 8 * u) * kSlabPitch + c4;
+                o[0] = v[u].x;
+                o[1] = v[u].y;
+                o[2] = v[u].z;
+                o[3] = v[u].w;
+            }
+        } else {
+            const int c = lane & 31;
+            for (int u = 0; u < 32; ++u) {
+                const int r = (lane >> 5) + 2 * u;
+                const bool rl = __shfl((int)live, r) != 0;
+                const float *xr = xrow + (int64_t)(uint32_t)__shfl((int)id, r) * d;
+                sl[r * kSlabPitch + c] = (rl && c < jn) ? xr[j0 + c] : 0.0f;
+            }
+        }
+        // the slab, written by the wave's lanes, is read by other lanes of
+        // the same wave: LDS instructions of a wave are performed in order,
+        // and the fences keep the compiler from moving the reads above the
+        // writes (or the next slab's writes above these reads, below)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float *mine = sl + lane * kSlabPitch;
+        for (int32_t jj = 0; jj < jn;) {
+            if (j0 + jj == cb) {  // a chunk ends: add its sum
+                partial += s;
+                s = 0.0f;
+                cb += chunk;
+            }
+            const int32_t seg = min(jn, cb - j0);  // this chunk's dimensions in the slab
+            for (; jj < seg; ++jj) {
+                const float t = qp[j0 + jj] - mine[jj];
+                s = fmaf(t, t, s);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    partial += s;
+    if (live) row[i] = make_key(partial, id);
 }
 
 // The k best of the R re-ranked keys; a non-finite query gets NaN rows, a
