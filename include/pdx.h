@@ -16,8 +16,9 @@
  *   lives in a caller buffer sized with the *_bytes query, and each search
  *   uses a caller workspace sized with the *_workspace query.  The only
  *   device memory the library takes itself is rocBLAS's handle (its GEMM
- *   workspace), once per device on the first IVF build or search, held
- *   until the process ends; the exact search does not use it.
+ *   workspace), once per device on the first IVF build or search or exact
+ *   search on the bucket layout, held until the process ends;
+ *   pdx_search_exact_noalloc does not use it.
  * - `stream` is a hipStream_t passed as void*; NULL means the default
  *   stream.  Search calls only enqueue work on it (no host sync): outputs
  *   are valid once the caller synchronises the stream.  Build calls are

@@ -1429,9 +1429,12 @@ hipError_t run_ip_tiles(const pdx_index *ix, const float *qs, const ExactPlan &p
     ip_max_norm_kernel<<<256, 256, 0, s>>>(pl.cn, ix->group_bucket, ix->tile_rad, ix->ngroups, pl.mbits);
     ip_query_kernel<<<nqu, 64, 0, s>>>(qs, d, pl.mbits, pl.qn, pl.qshift);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    // q.c as a library GEMM on the matrix cores (the rounding of a D-term
-    // dot product in any summation order is within ip_bound_kernel's margin)
-    if ((err = launch_sgemm_abt(qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, s)) != hipSuccess) return err;
+    // q.c on the matrix cores, a library GEMM unless the caller cannot
+    // allocate (the rounding of a D-term dot product in any summation order
+    // is within ip_bound_kernel's margin)
+    if ((err = (pl.library_gemm ? launch_sgemm_abt : launch_gemm_abt)(qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd,
+                                                                      ix->nlist, s)) != hipSuccess)
+        return err;
     ip_bound_kernel<<<dim3((unsigned)((pl.nq + 31) / 32), (unsigned)((ix->nlist + 31) / 32)), 256, 0, s>>>(
         pl.cd, pl.nq, ix->nlist, d, pl.qn, pl.qshift, pl.cn, pl.mbits, pl.dql);
     nearest_kernel<<<nqu, 64, 0, s>>>(pl.cd, ix->nlist, pl.nearest);
@@ -1545,9 +1548,10 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
             row_sq_kernel<<<nqu, 64, 0, s>>>(qs, d, pl.qn);
             row_sq_kernel<<<(unsigned)ix->nlist, 64, 0, s>>>(ix->centroids, d, pl.cn);
             if ((err = hipGetLastError()) != hipSuccess) return err;
-            // q.c as a library GEMM (any summation order is within the
-            // lower bound's margin)
-            if ((err = launch_sgemm_abt(qs, pl.nq, ix->centroids, ix->nlist, d, pl.cd, ix->nlist, s)) != hipSuccess)
+            // q.c as a library GEMM unless the caller cannot allocate (any
+            // summation order is within the lower bound's margin)
+            if ((err = (pl.library_gemm ? launch_sgemm_abt : launch_gemm_abt)(qs, pl.nq, ix->centroids, ix->nlist,
+                                                                              d, pl.cd, ix->nlist, s)) != hipSuccess)
                 return err;
             const int64_t pairs = pl.nq * ix->nlist;
             l2_from_dot_kernel<<<(unsigned)((pairs + 255) / 256), 256, 0, s>>>(pl.cd, pl.nq, ix->nlist, d, pl.qn,

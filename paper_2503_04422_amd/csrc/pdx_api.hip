@@ -141,6 +141,16 @@ size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, int32_t k,
 pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, int32_t k,
                             const pdx_search_params *params, void *ws, size_t ws_bytes,
                             int64_t *out_ids, float *out_dist, void *stream) {
+    return pdx::search_exact(index, q, nq, k, params, ws, ws_bytes, out_ids, out_dist, stream, true);
+}
+
+}  // extern "C"
+
+namespace pdx {
+
+pdx_status search_exact(const pdx_index *index, const float *q, int64_t nq, int32_t k,
+                        const pdx_search_params *params, void *ws, size_t ws_bytes, int64_t *out_ids,
+                        float *out_dist, void *stream, bool library_gemm) {
     if (!index || (index->kind != kFlat && index->kind != kIvf)) {
         set_error("pdx_search_exact: not an index built by pdx_build or pdx_ivf_build");
         return PDX_EINVAL;
@@ -200,10 +210,15 @@ pdx_status pdx_search_exact(const pdx_index *index, const float *q, int64_t nq, 
         set_error("pdx_search_exact: workspace has %zu bytes, needs %zu", ws_bytes, need);
         return PDX_EWORKSPACE;
     }
+    plan.library_gemm = library_gemm;
     hipError_t e = run_exact(index, q, plan, out_ids, out_dist, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "pdx_search_exact");
     return PDX_OK;
 }
+
+}  // namespace pdx
+
+extern "C" {
 
 namespace {
 struct OrderWs {

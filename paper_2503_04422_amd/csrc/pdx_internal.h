@@ -98,6 +98,7 @@ struct ExactPlan {
     int32_t nslots;
     bool use_tiles;        // LDS tile path (else the group path only)
     bool ivf;              // bucket layout (IVF index): rows in bucket order, ids through slot_id
+    bool library_gemm;     // centroid products on rocBLAS (else the library's own GEMM kernel, which allocates nothing)
     int32_t start_parts;   // bucket layout: waves per query in START
     int32_t start_maxg;    // bucket layout: vectorgroups of the nearest bucket START scans
     int32_t metric;        // PDX_METRIC_*
@@ -433,6 +434,10 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
                   void *ws, ExactPlan *plan);
 hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &plan,
                      int64_t *out_ids, float *out_dist, hipStream_t s);
+// pdx_search_exact; library_gemm false keeps rocBLAS (which may allocate) out of the search
+pdx_status search_exact(const pdx_index *index, const float *q, int64_t nq, int32_t k,
+                        const pdx_search_params *params, void *ws, size_t ws_bytes, int64_t *out_ids,
+                        float *out_dist, void *stream, bool library_gemm);
 
 }  // namespace pdx
 

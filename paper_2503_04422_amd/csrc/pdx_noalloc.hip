@@ -72,7 +72,7 @@ pdx_status pdx_search_exact_noalloc(const pdx_index *index, const float *q, int6
     if (nq == 0) return PDX_OK;
     const size_t need = pdx_search_exact_workspace(index, nq, k, params);
     if (need == 0) {  // arguments the sizing query rejects: let the search report them
-        return pdx_search_exact(index, q, nq, k, params, nullptr, 0, out_ids, out_dist, stream);
+        return search_exact(index, q, nq, k, params, nullptr, 0, out_ids, out_dist, stream, false);
     }
     if (need > kScratchBytes) {
         set_error("pdx_search_exact_noalloc: this search needs %zu bytes of workspace, above the static "
@@ -83,7 +83,8 @@ pdx_status pdx_search_exact_noalloc(const pdx_index *index, const float *q, int6
     void *ws = nullptr;
     const pdx_status st = scratch_address(&ws);
     if (st != PDX_OK) return st;
-    return pdx_search_exact(index, q, nq, k, params, ws, kScratchBytes, out_ids, out_dist, stream);
+    // the library's own GEMM kernel: rocBLAS may allocate (its handle, its workspace)
+    return search_exact(index, q, nq, k, params, ws, kScratchBytes, out_ids, out_dist, stream, false);
 }
 
 }  // extern "C"
