@@ -372,8 +372,14 @@ typedef struct {
                           upper bound of the R-th smallest buffered distance,
                           from a histogram of the buffered distances; a full
                           buffer is compacted to its R best and the scan
-                          resumed, so every probed vector is seen); vector-ALU
-                          engine only; no learned networks or traces.       */
+                          resumed, so every probed vector is seen).  On the
+                          matrix cores (16 queries per wave, no bucket_split,
+                          bfloat16 MFMA on the codes: delta_d a multiple of
+                          32; else the vector ALU) resumed vectors are
+                          scanned on the vector ALU, whose rounding differs,
+                          so there the candidate set can depend on the
+                          buffer size at the rounding level.  No learned
+                          networks or traces.                               */
     /* Optional instrumentation (NULL = off); neither changes the result.   */
     void **phase_events; /* 4 hipEvent_t recorded on `stream`: at the start,
                             after rotation + bucket selection + START, after

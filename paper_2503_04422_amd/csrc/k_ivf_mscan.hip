@@ -35,6 +35,7 @@
 // uncentred (the codes cannot be re-centred exactly), clamped at 0.
 #include "pdx_internal.h"
 #include "wave_topk.h"
+#include "wide_sink.h"
 
 namespace pdx {
 namespace {
@@ -69,15 +70,20 @@ __device__ __forceinline__ v4f load_quad(const void *__restrict__ data, const fl
 // items) share every loaded value of the bucket; part p of the slots.parts
 // waves sharing a batch scans vectorgroups p, p + parts, ... of the bucket.
 // The queries' k-best lists live in LDS (list m, lane i = its i-th entry)
-// and are read into a register only when they get offers.
-template <bool PRUNE, int STORE, int MT, bool LP>
+// and are read into a register only when they get offers.  WIDE (one tile,
+// one wave per batch): survivors below the query's threshold go to its
+// candidate buffer instead, one reservation per (query, vectorgroup); a
+// query whose reservation does not fit stops there, recorded for a resume
+// round, and the batch goes on without it.
+template <bool PRUNE, int STORE, int MT, bool LP, bool WIDE>
 __device__ __forceinline__ void mscan_unit(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t b,
     int32_t part, const int32_t *__restrict__ probe, int32_t nprobe, const float *__restrict__ qrot,
     uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, const SlotMap &slots, int32_t chunk,
     const PruneRule &rule, unsigned long long *__restrict__ counters, uint64_t (*lists)[kWave],
-    const LpOperands &lp) {
+    const LpOperands &lp, const WideSink &wide) {
+    static_assert(!WIDE || MT == 1, "candidate buffers: one tile per wave");
     constexpr int NQ = 16 * MT;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
@@ -95,7 +101,7 @@ __device__ __forceinline__ void mscan_unit(
         row_ok[mt] = mine[mt].x >= 0 && !bad[mine[mt].x];
         use |= (uint32_t)(__ballot(row_ok[mt]) & 0xffffull) << (16 * mt);
         // items of non-finite queries get an empty list
-        if (mine[mt].x >= 0 && !row_ok[mt] && kq == 0)
+        if (!WIDE && mine[mt].x >= 0 && !row_ok[mt] && kq == 0)
             for (int i = 0; i < k; ++i) slots.at(mine[mt].x, mine[mt].y, part)[i] = kEmptyKey;
     }
     if (!use) return;
@@ -118,8 +124,10 @@ __device__ __forceinline__ void mscan_unit(
             rowe[mt][r] = (PRUNE && rule.eps && rowuse[mt][r]) ? rule.eps_at(rowq[mt][r], rr, nprobe) : 0.0f;
             kthr[mt][r] = INFINITY;
         }
+    if constexpr (!WIDE) {
 #pragma unroll
-    for (int m = 0; m < NQ; ++m) lists[m][lane] = kEmptyKey;
+        for (int m = 0; m < NQ; ++m) lists[m][lane] = kEmptyKey;
+    }
     const bool vec_ok = (d & 3) == 0;
     unsigned long long live_vals = 0, lane_vals = 0;
     // LP: one sub-chunk's codes in registers (dimensions jl .. jl + 7 of
@@ -166,10 +174,11 @@ __device__ __forceinline__ void mscan_unit(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 teff[mt][r] = INFINITY;
-                if (PRUNE && rowuse[mt][r]) {
+                if ((PRUNE || WIDE) && rowuse[mt][r]) {
                     const uint32_t tg =
                         __hip_atomic_load(tau + rowq[mt][r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    teff[mt][r] = fminf(__uint_as_float(tg), kthr[mt][r]);
+                    // the candidate buffer's threshold bounds its R-th distance
+                    teff[mt][r] = WIDE ? __uint_as_float(tg) : fminf(__uint_as_float(tg), kthr[mt][r]);
                 }
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
@@ -363,8 +372,30 @@ __device__ __forceinline__ void mscan_unit(
                 }
             }
         }
-        // survivors enter their query's k-best list
-        if (__any(alive != 0u)) {
+        if constexpr (WIDE) {
+            // survivors below the threshold go to their query's buffer
+#pragma unroll
+            for (int m = 0; m < NQ; ++m) {
+                if (!((use >> m) & 1u)) continue;
+                const int r = m & 3;
+                const bool myrow = kq == (m >> 2);
+                const int32_t qm = __builtin_amdgcn_readlane(mine[0].x, m);
+                float dv[4];
+                bool cand[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    dv[t] = part_[0][r][t];
+                    cand[t] = myrow && ((alive >> (4 * r + t)) & 1u) && dv[t] < teff[0][r];
+                }
+                if (!wide_push4(wide, qm, dv, vid, cand, wide.hbase[qm], tau, lane)) {
+                    wide_overflow(wide, qm, __builtin_amdgcn_readlane(mine[0].y, m), g, lane);
+                    use &= ~(1u << m);
+                    if (myrow) rowuse[0][r] = false;
+                }
+            }
+            if (!use) break;
+        } else if (__any(alive != 0u)) {
+            // survivors enter their query's k-best list
 #pragma unroll
             for (int m = 0; m < NQ; ++m) {
                 if (!((use >> m) & 1u)) continue;
@@ -393,12 +424,15 @@ __device__ __forceinline__ void mscan_unit(
             }
         }
     }
+    if constexpr (!WIDE) {
 #pragma unroll
-    for (int m = 0; m < NQ; ++m) {
-        if (!((use >> m) & 1u)) continue;
-        const int mt = m >> 4, mm = m & 15;
-        const int32_t qm = __builtin_amdgcn_readlane(mine[mt].x, mm), rm = __builtin_amdgcn_readlane(mine[mt].y, mm);
-        if (lane < k) slots.at(qm, rm, part)[lane] = lists[m][lane];
+        for (int m = 0; m < NQ; ++m) {
+            if (!((use >> m) & 1u)) continue;
+            const int mt = m >> 4, mm = m & 15;
+            const int32_t qm = __builtin_amdgcn_readlane(mine[mt].x, mm),
+                          rm = __builtin_amdgcn_readlane(mine[mt].y, mm);
+            if (lane < k) slots.at(qm, rm, part)[lane] = lists[m][lane];
+        }
     }
     if (counters && lane == 0) {
         atomicAdd(counters, live_vals);
@@ -410,23 +444,23 @@ __device__ __forceinline__ void mscan_unit(
 // round-robin) are the batches in [xcd_range[x], xcd_range[x + 1]) / 16 MT:
 // all batches of a bucket run on one XCD and share its L2.  Each wave
 // strides over its XCD's units.  Without xcd_range: unit = global wave index.
-template <bool PRUNE, int STORE, int MT, bool LP>
+template <bool PRUNE, int STORE, int MT, bool LP, bool WIDE>
 __global__ __launch_bounds__(256, (MT == 1 && !LP) ? 3 : 1) void ivf_mscan_kernel(
     const void *__restrict__ pdxd, const float *__restrict__ scale, int32_t d, const int32_t *__restrict__ slot_id,
     const int32_t *__restrict__ goff, const float *__restrict__ cen, const int2 *__restrict__ items, int64_t nbatch,
     const int32_t *__restrict__ xcd_range, const int32_t *__restrict__ probe, int32_t nprobe,
     const float *__restrict__ qrot, uint32_t *__restrict__ tau, const int32_t *__restrict__ bad, SlotMap slots,
-    int32_t chunk, PruneRule rule, unsigned long long *__restrict__ counters, LpOperands lp) {
-    __shared__ uint64_t lists[4][16 * MT][kWave];
+    int32_t chunk, PruneRule rule, unsigned long long *__restrict__ counters, LpOperands lp, WideSink wide) {
+    __shared__ uint64_t lists[4][WIDE ? 1 : 16 * MT][kWave];
     const int wave = threadIdx.x >> 6;
     const int64_t parts = slots.parts;
     if (!xcd_range) {
         const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
         const int64_t b = wid / parts;
         if (b < nbatch)
-            mscan_unit<PRUNE, STORE, MT, LP>(pdxd, scale, d, slot_id, goff, cen, items, b,
-                                             (int32_t)(wid - b * parts), probe, nprobe, qrot, tau, bad, slots, chunk,
-                                             rule, counters, lists[wave], lp);
+            mscan_unit<PRUNE, STORE, MT, LP, WIDE>(pdxd, scale, d, slot_id, goff, cen, items, b,
+                                                   (int32_t)(wid - b * parts), probe, nprobe, qrot, tau, bad, slots,
+                                                   chunk, rule, counters, lists[wave], lp, wide);
         return;
     }
     const int32_t x = blockIdx.x & 7;
@@ -434,9 +468,9 @@ __global__ __launch_bounds__(256, (MT == 1 && !LP) ? 3 : 1) void ivf_mscan_kerne
     const int64_t stride = (int64_t)(gridDim.x >> 3) * 4;
     for (int64_t w = (int64_t)(blockIdx.x >> 3) * 4 + wave; w < nb * parts; w += stride) {
         const int64_t b = w / parts;
-        mscan_unit<PRUNE, STORE, MT, LP>(pdxd, scale, d, slot_id, goff, cen, items, b0 + b,
-                                         (int32_t)(w - b * parts), probe, nprobe, qrot, tau, bad, slots, chunk, rule,
-                                         counters, lists[wave], lp);
+        mscan_unit<PRUNE, STORE, MT, LP, WIDE>(pdxd, scale, d, slot_id, goff, cen, items, b0 + b,
+                                               (int32_t)(w - b * parts), probe, nprobe, qrot, tau, bad, slots, chunk,
+                                               rule, counters, lists[wave], lp, wide);
     }
 }
 
@@ -482,17 +516,34 @@ hipError_t launch_ivf_mscan(bool prune, int32_t store, int32_t tiles, const void
                             const int2 *items, int64_t nbatch, const int32_t *xcd_range, const int32_t *probe,
                             int32_t nprobe, const float *qrot, uint32_t *tau, const int32_t *bad, SlotMap slots,
                             int32_t chunk, PruneRule rule, unsigned long long *counters, const LpOperands &lp,
-                            hipStream_t s) {
+                            const WideSink *wide, hipStream_t s) {
     if (nbatch <= 0) return hipSuccess;
     // one wave per unit, or (XCD ranges) 8 equal sets of workgroups, an
     // eighth of the units each plus slack for uneven ranges
     const int64_t units = nbatch * slots.parts;
     const unsigned grid = xcd_range ? 8u * (unsigned)((units / 8 + 3) / 4 + 64) : (unsigned)((units + 3) / 4);
     const bool use_lp = lp.qs != nullptr && store != PDX_DTYPE_F32;
+    if (wide) {  // candidate buffers: one tile per wave, one wave per batch, bfloat16 MFMA on the codes
+        if (tiles != 1 || !use_lp || slots.parts != 1) return hipErrorInvalidValue;
+#define PDX_MSCAN_W(P, S)                                                                                         \
+    ivf_mscan_kernel<P, S, 1, true, true><<<grid, 256, 0, s>>>(data, scale, d, slot_id, goff, cen, items, nbatch, \
+                                                               xcd_range, probe, nprobe, qrot, tau, bad, slots,    \
+                                                               chunk, rule, counters, lp, *wide)
+        if (prune) {
+            if (store == PDX_DTYPE_BF16) PDX_MSCAN_W(true, PDX_DTYPE_BF16);
+            else PDX_MSCAN_W(true, PDX_DTYPE_FP8);
+        } else {
+            if (store == PDX_DTYPE_BF16) PDX_MSCAN_W(false, PDX_DTYPE_BF16);
+            else PDX_MSCAN_W(false, PDX_DTYPE_FP8);
+        }
+#undef PDX_MSCAN_W
+        return hipGetLastError();
+    }
+    const WideSink none{};
 #define PDX_MSCAN(P, S, M, L)                                                                                       \
-    ivf_mscan_kernel<P, S, M, L><<<grid, 256, 0, s>>>(data, scale, d, slot_id, goff, cen, items, nbatch,          \
-                                                      xcd_range, probe, nprobe, qrot, tau, bad, slots, chunk, rule, \
-                                                      counters, lp)
+    ivf_mscan_kernel<P, S, M, L, false><<<grid, 256, 0, s>>>(data, scale, d, slot_id, goff, cen, items, nbatch,   \
+                                                             xcd_range, probe, nprobe, qrot, tau, bad, slots,      \
+                                                             chunk, rule, counters, lp, none)
 #define PDX_MSCAN_T(P, S, L)                \
     if (tiles == 2) PDX_MSCAN(P, S, 2, L);  \
     else PDX_MSCAN(P, S, 1, L);

@@ -972,13 +972,20 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.bond = (p && (p->bound == 1 || p->bound == 2)) ? 1 : 0;
     pl.zones = (p && p->bound == 2) ? 1 : 0;
     pl.zone_rows = pl.zones ? bond_zone_rows(ix->d, p->zone_rows) : 0;
+    // ADSampling's test interval (delta_d)
+    const int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
     {
         int32_t eng = p ? p->engine : 0;
         if (eng == 0)  // automatic: matrix cores once buckets see enough queries to fill 16-row tiles
             eng = (!(p && p->queries_per_wave > 0) && (double)nq * nprobe >= 8.0 * ix->nlist) ? 2 : 1;
         // the BOND scan gathers per-query dimensions, BSA's test reads a norm
-        // per vector and test point: both on the vector ALU
-        pl.matrix = (eng == 2 && !pl.bond && !(p && p->bound == 3) && !pl.wide) ? 1 : 0;
+        // per vector and test point: both on the vector ALU.  Candidate
+        // buffers on the matrix cores: one tile per wave over the codes'
+        // bfloat16 MFMA (their norms stored, whole 32-dimension sub-chunks),
+        // else the vector ALU.
+        const bool wide_ok = !pl.wide || (!(p && p->queries_per_wave == 32) && dd % 32 == 0 &&
+                                          (pl.dtype == PDX_DTYPE_BF16 ? ix->xn_bf16 : ix->xn_fp8) != nullptr);
+        pl.matrix = (eng == 2 && !pl.bond && !(p && p->bound == 3) && wide_ok) ? 1 : 0;
     }
     // matrix-core scans report exact f32 distances of their k best
     if (pl.matrix && pl.dtype == PDX_DTYPE_F32) pl.rerank = k;
@@ -1006,7 +1013,6 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
     pl.by_size = !(p && p->bucket_order == 1);
     pl.cap0 = ivf_item_capacity(nq, 1, pl.qb0, ix->nlist);
     pl.cap1 = ivf_item_capacity(nq, nprobe - 1, pl.qb1, ix->nlist);
-    int32_t dd = (p && p->delta_d > 0) ? p->delta_d : (ix->d >= 128 ? 32 : (ix->d / 4 > 0 ? ix->d / 4 : 1));
     pl.chunk = pl.zones ? 32 : dd;  // zones: every chunk is one whole zone
     size_t q = (size_t)(nq > 0 ? nq : 0);
     Carver c(ws);
@@ -1030,7 +1036,7 @@ size_t ivf_plan(const pdx_index *ix, int64_t nq, int32_t k, int32_t nprobe, cons
         // waves per item: enough waves to fill the chip (about 8 per SIMD)
         // when a phase has few batches; matrix-core scans only
         auto parts_for = [&](int64_t items, int32_t qb_phase) -> int32_t {
-            if (!pl.matrix || items <= 0) return 1;
+            if (!pl.matrix || items <= 0 || pl.wide) return 1;  // candidate buffers: a resume point per item
             if (p && p->bucket_split > 0) return p->bucket_split;
             const int64_t batches = (items + 15) / 16 / (qb_phase / 16), want = 8 * 4 * (int64_t)device_cus();
             int32_t s_ = 1;
@@ -1210,7 +1216,7 @@ hipError_t run_ivf(const pdx_index *ix, const float *q, const IvfPlan &pl, int64
         if (pl.matrix)
             return launch_ivf_mscan(prune, pl.dtype, qb / 16, data, ix->fp8_scale, d, ix->slot_id, ix->list_goff,
                                     ix->centroids, items, nb, xr, pl.probe, pl.nprobe, pl.qrot, pl.tau, pl.bad, sm,
-                                    pl.chunk, pl.rule, cnt, pl.lp, s);
+                                    pl.chunk, pl.rule, cnt, pl.lp, pl.wide ? &pl.ws : nullptr, s);
         const unsigned grid = (unsigned)((nb + 3) / 4);
 #define PDX_BSCAN(P, S, Q, W)                                                                                 \
     ivf_bscan_kernel<P, S, Q, W><<<grid, 256, 0, s>>>(data, ix->fp8_scale, d, ix->slot_id, ix->list_goff, items, \

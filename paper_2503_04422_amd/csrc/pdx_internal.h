@@ -362,13 +362,15 @@ hipError_t launch_bond_items(bool prune, const pdx_index *ix, const int2 *items,
                              unsigned long long *counters, bool zones, int32_t zone_rows, hipStream_t s);
 
 // Bucket scan on the matrix cores (k_ivf_mscan.hip): batches of 16 * tiles
-// queries (tiles = 1 or 2) per wave.
+// queries (tiles = 1 or 2) per wave.  wide (non-null): survivors go to the
+// candidate buffers (tiles 1, one wave per batch, low-precision codes with
+// their LpOperands).
 hipError_t launch_ivf_mscan(bool prune, int32_t store, int32_t tiles, const void *data, const float *scale,
                             int32_t d, const int32_t *slot_id, const int32_t *goff, const float *cen,
                             const int2 *items, int64_t nbatch, const int32_t *xcd_range, const int32_t *probe,
                             int32_t nprobe, const float *qrot, uint32_t *tau, const int32_t *bad, SlotMap slots,
                             int32_t chunk, PruneRule rule, unsigned long long *counters, const LpOperands &lp,
-                            hipStream_t s);
+                            const WideSink *wide, hipStream_t s);
 // The query operands of LpOperands (scale: the e4m3 scales, or null for bfloat16).
 hipError_t launch_lp_query(const float *qrot, int64_t nq, int32_t d, const float *scale, const LpOperands &lp,
                            hipStream_t s);

@@ -354,11 +354,6 @@ pdx_status pdx_search_ivf(const pdx_index *index, const float *q, int64_t nq, in
     if (params && params->dtype != PDX_DTYPE_F32 && params->rerank > PDX_MAX_K) {
         // more candidates than a wave's register list: the candidate buffer
         const int32_t r = params->rerank;
-        if (params->engine == 2) {
-            set_error("pdx_search_ivf: a re-rank of more than PDX_MAX_K=%d candidates runs on the vector-ALU "
-                      "scans (engine 0 or 1)", PDX_MAX_K);
-            return PDX_EUNSUPPORTED;
-        }
         if (params->mlp || params->prune_mlp || params->trace_features || params->trace_need ||
             params->trace_prune_features) {
             set_error("pdx_search_ivf: the learned networks and their traces need rerank <= PDX_MAX_K=%d",

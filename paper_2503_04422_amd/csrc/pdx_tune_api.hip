@@ -29,8 +29,6 @@ pdx_ivf_search_params with(const pdx_ivf_search_params &base, const Candidate &c
 bool usable(const pdx_index *index, const pdx_ivf_search_params &base, int32_t tune_delta_d, const Candidate &c) {
     // BSA's test: vector-ALU scans and the delta_d its residual norms were stored for
     if (base.bound == 3 && (c.engine == 2 || c.delta_d)) return false;
-    // a re-rank of more than PDX_MAX_K candidates: vector-ALU scans
-    if (base.dtype != PDX_DTYPE_F32 && base.rerank > PDX_MAX_K && c.engine == 2) return false;
     if (!c.delta_d) return true;
     return tune_delta_d && std::isfinite(base.eps0) && c.delta_d < index->d;
 }

@@ -49,6 +49,16 @@ __device__ __forceinline__ void wide_refresh(const WideSink &w, int64_t q, uint3
     if (lane == 0) atomicMin(tau + q, edge);
 }
 
+// A refresh after a reservation [base, base + n): when the buffer first
+// holds r keys, then each time its count crosses a multiple of
+// kWideRefreshStep (a refresh reads the whole histogram; between refreshes
+// the threshold only stays looser, never wrong).
+constexpr int kWideRefreshStep = 256;
+__device__ __forceinline__ bool wide_due(int base, int n, int r) {
+    const int end = base + n;
+    return end >= r && (base < r || end / kWideRefreshStep != base / kWideRefreshStep);
+}
+
 // Append the keys (dist, id) of the lanes where `cand` holds for query q.
 // Returns false, storing nothing, when the reservation does not fit (the
 // slots of a reservation that straddles the end are marked empty); the
@@ -69,11 +79,48 @@ __device__ __forceinline__ bool wide_push(const WideSink &w, int64_t q, float di
             row[pos] = make_key(dist, id);
             atomicAdd(w.hist + q * kWideBins + wide_bin(dist, hb), 1u);
         }
-        if (base + n >= w.r) wide_refresh(w, q, tau, lane);
+        if (wide_due(base, n, w.r)) wide_refresh(w, q, tau, lane);
         return true;
     }
     if (cand && pos < w.cap) row[pos] = kEmptyKey;
     return false;
+}
+
+// wide_push for up to 4 candidates per lane (vectors vid[t] at distances
+// dist[t] where cand[t]): one reservation for all of them, all or nothing.
+__device__ __forceinline__ bool wide_push4(const WideSink &w, int64_t q, const float (&dist)[4],
+                                           const int32_t (&vid)[4], const bool (&cand)[4], int32_t hb, uint32_t *tau,
+                                           int lane) {
+    unsigned long long m[4];
+    int pre[4];
+    int n = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        m[t] = __ballot(cand[t]);
+        pre[t] = n;
+        n += __popcll(m[t]);
+    }
+    if (!n) return true;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(w.cnt + q, n);
+    base = __shfl(base, 0);
+    uint64_t *row = w.buf + q * (int64_t)w.cap;
+    const bool fits = base <= w.cap - n;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (!cand[t]) continue;
+        const int pos = base + pre[t] +
+                        (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m[t] >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m[t], 0u));
+        if (fits) {
+            row[pos] = make_key(dist[t], (uint32_t)vid[t]);
+            atomicAdd(w.hist + q * kWideBins + wide_bin(dist[t], hb), 1u);
+        } else if (pos < w.cap) {
+            row[pos] = kEmptyKey;
+        }
+    }
+    if (fits && wide_due(base, n, w.r)) wide_refresh(w, q, tau, lane);
+    return fits;
 }
 
 // Item (q, rank) stopped at vectorgroup g: resume there; list q once per

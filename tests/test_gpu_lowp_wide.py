@@ -78,14 +78,14 @@ def _probed_rows(st, qv, nprobe):
     return np.concatenate([st["lists"][p] for p in probe])
 
 
-def _check_rerank(st, dtype, r, nprobe, gi, gd, min_exact):
+def _check_rerank(st, dtype, r, nprobe, gi, gd, min_exact, band=1e-5):
     """Oracle parity where the R-th and next decoded distances are apart;
-    where they are tied at the rounding level (relative 1e-5) the candidate
-    set lies between the rows surely in (decoded distance below a band of
-    twice that width around the R-th) and those possibly in (at or below
-    the band's top), so: every returned id is possibly in, distances are
-    exact, and the k-th distance lies between the k-th of the exact top-k
-    of the two sets."""
+    where they are tied at the scan's rounding level (relative `band`) the
+    candidate set lies between the rows surely in (decoded distance below a
+    band of twice that width around the R-th) and those possibly in (at or
+    below the band's top), so: every returned id is possibly in, distances
+    are exact, and the k-th distance lies between the k-th of the exact
+    top-k of the two sets."""
     xd = st["dec"][dtype]
     exact_checked = 0
     for i in range(st["q"].shape[0]):
@@ -93,8 +93,8 @@ def _check_rerank(st, dtype, r, nprobe, gi, gd, min_exact):
         rows = _probed_rows(st, qv, nprobe)
         ad = exact.sqdist(xd[rows], qv)
         approx = np.sort(ad)
-        if approx.size > r and abs(approx[r] - approx[r - 1]) <= 1e-5 * approx[r]:
-            lo, hi = approx[r - 1] * (1 - 2e-5), approx[r - 1] * (1 + 2e-5)
+        if approx.size > r and abs(approx[r] - approx[r - 1]) <= band * approx[r]:
+            lo, hi = approx[r - 1] * (1 - 2 * band), approx[r - 1] * (1 + 2 * band)
             sure, maybe = rows[ad < lo], rows[ad <= hi]
             assert np.all(np.isin(gi[i], maybe)), i
             np.testing.assert_allclose(gd[i], exact.sqdist(st["x"][gi[i]], qv), rtol=1e-5)
@@ -175,11 +175,51 @@ def test_wide_rerank_argument_errors(pdx, small):
     from paper_2503_04422_amd import _lib
     st = small
     q = _dev(st["q"][:4])
-    cases = [({"rerank": 200, "engine": 2}, _lib.PDX_EUNSUPPORTED),
-             ({"rerank": _lib.PDX_MAX_RERANK + 1}, _lib.PDX_EUNSUPPORTED),
+    cases = [({"rerank": _lib.PDX_MAX_RERANK + 1}, _lib.PDX_EUNSUPPORTED),
              ({"rerank": 200, "rerank_capacity": 300}, _lib.PDX_EINVAL),
              ({"rerank": 200, "rerank_capacity": -1}, _lib.PDX_EINVAL)]
     for kw, status in cases:
         with pytest.raises(_lib.PdxError) as ei:
             pdx.pdx_search_ivf(st["ix"], q, 10, 4, dtype="bf16", **kw)
         assert ei.value.status == status, kw
+
+
+# Matrix cores (engine 2): the scanned distances come from bfloat16 MFMA on
+# the codes (|q|^2 + |x|^2 - 2 q.x per 32-dimension sub-chunk), whose
+# rounding is wider than the vector ALU's direct sums, so the tie band at
+# the R-th candidate is 1e-4.  Vectors a full buffer stopped are resumed on
+# the vector ALU.  The ADSampling test every 32 dimensions (whole
+# sub-chunks of the codes) keeps these small workloads on the matrix cores.
+@pytest.mark.parametrize("dtype,r", [("fp8", 1000), ("bf16", 300)])
+def test_matrix_engine_wide_rerank_matches_oracle(pdx, small, dtype, r):
+    st = small
+    print(f"matrix-core wide rerank parity {dtype} R={r}", flush=True)
+    gi, gd = pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, 5, eps0=float("inf"), dtype=dtype, rerank=r,
+                                engine=2, delta_d=32)
+    _check_rerank(st, dtype, r, 5, _np(gi), _np(gd), st["q"].shape[0] // 2, band=1e-4)
+    # a buffer of 2R: compaction and resume rounds (resumed on the vector ALU)
+    gi, gd = pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, 5, eps0=float("inf"), dtype=dtype, rerank=r,
+                                engine=2, delta_d=32, rerank_capacity=max(2 * r, r + 256))
+    _check_rerank(st, dtype, r, 5, _np(gi), _np(gd), st["q"].shape[0] // 2, band=1e-4)
+
+
+def test_matrix_engine_rerank_4096(pdx, big):
+    st = big
+    print("matrix-core wide rerank parity bf16 R=4096", flush=True)
+    gi, gd = pdx.pdx_search_ivf(st["ix"], _dev(st["q"]), 10, 4, eps0=float("inf"), dtype="bf16", rerank=4096,
+                                engine=2, delta_d=32)
+    _check_rerank(st, "bf16", 4096, 4, _np(gi), _np(gd), st["q"].shape[0] // 2, band=1e-4)
+    q = st["q"].copy()
+    q[3, 5] = np.nan
+    flat = np.stack([px.ivf_flat(st["x"], st["lists"], st["c32"], v, 10, 6)[0] for v in st["q"]])
+    gi, gd = pdx.pdx_search_ivf(st["ix"], _dev(q), 10, 6, eps0=2.1, dtype="bf16", rerank=4096, engine=2,
+                                delta_d=32)
+    gi, gd = _np(gi), _np(gd)
+    assert np.all(gi[3] == -1) and np.all(np.isnan(gd[3]))
+    keep = [i for i in range(q.shape[0]) if i != 3]
+    rec = exact.recall_at_k(flat[keep], gi[keep])
+    print(f"matrix-core bf16 rerank 4096 ads recall vs f32 ivf-flat {rec:.4f}", flush=True)
+    assert rec >= 0.97
+    for i in keep[::5]:
+        ok = gi[i] >= 0
+        np.testing.assert_allclose(gd[i][ok], exact.sqdist(st["x"][gi[i][ok]], st["q"][i]), rtol=1e-5)
