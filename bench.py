@@ -701,8 +701,8 @@ def kernel_sweep(ns, ds, reps_s=4e-3) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="bond_1m_d960",
                     choices=["bond_1m_d960", "ivf_1m_d1536", "lowp_5m_d768", "linear_10k_d128"])
     ap.add_argument("--k", type=int, default=10)
@@ -935,14 +935,14 @@ def main() -> int:
     del ws
     if mode == "bond" and not args.no_ivf:
         ivf_ix = build_ivf(pdx, torch, np, x, 1024, lowp=("bf16", "fp8"))
-        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, args.nprobe or [2, 4, 8, 12, 14, 16, 32, 64], k, 3, 1,
-                                    truth,
+        extra["approx"] = bench_ivf(pdx, torch, np, x, q, 1024, args.nprobe or [2, 4, 8, 12, 14, 16, 32, 64], k, 10,
+                                    3, truth,
                                     index=ivf_ix, profile_md="ivf_mscan_bond_1m_d960.md", schedule=args.schedule)
         best = next((r for r in extra["approx"]["sweep"] if r["nprobe"] == extra["approx"]["nprobe_at_recall_0.95"]),
                     None)
         if best is not None:  # the low-precision copies at the same point (f32 rerank)
             extra["approx_lowp"] = bench_ivf_lowp(pdx, torch, np, ivf_ix[0], q, k, best["nprobe"], best["schedule"],
-                                                  3, 1, truth)
+                                                  10, 3, truth)
         extra["approx_bond_bound"] = bench_bond_ivf(pdx, torch, np, ivf_ix[0], q, [8, 16, 32], k, 3, 1, truth)
         if not args.no_pca:
             # BSA's projection (Section 2.3): the rows' principal directions in
