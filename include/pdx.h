@@ -166,7 +166,13 @@ PDX_API size_t pdx_search_exact_workspace(const pdx_index *index, int64_t nq, in
 /* pdx_search_exact -- exact K-nearest neighbours of nq queries.
  *
  * PDX_MODE_LINEAR: the kernel listing of Section 3 (L2) over every
- * vectorgroup.  PDX_MODE_BOND: PDXearch (Section 4) with PDX-BOND
+ * vectorgroup.  For L2 with D % 4 == 0 (and no counters asked for) every
+ * vector's distance is evaluated on the matrix cores in the expanded form
+ * |q|^2 + |x|^2 - 2 q.x, within a margin that covers its rounding: a pass
+ * over every 8th vectorgroup bounds each query's k-th distance from above,
+ * a pass over all of them lists the vectors whose lower bound reaches it,
+ * and those are summed exactly in the vectorgroup path's order, so the
+ * answer is the same.  PDX_MODE_BOND: PDXearch (Section 4) with PDX-BOND
  * (Section 5): dimensions visited by |q_j - mean_j| descending (ties by j),
  * START scans the first start_rows rows without pruning, every later
  * vector is dropped as soon as its partial distance after a chunk is

@@ -99,6 +99,7 @@ struct ExactPlan {
     bool use_tiles;        // LDS tile path (else the group path only)
     bool ivf;              // bucket layout (IVF index): rows in bucket order, ids through slot_id
     bool library_gemm;     // centroid products on rocBLAS (else the library's own GEMM kernel, which allocates nothing)
+    bool lin_mx;           // L2 linear mode on the matrix cores (bound pass, listing pass, exact re-sum)
     int32_t start_parts;   // bucket layout: waves per query in START
     int32_t start_maxg;    // bucket layout: vectorgroups of the nearest bucket START scans
     int32_t metric;        // PDX_METRIC_*
