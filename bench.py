@@ -929,7 +929,9 @@ def main() -> int:
         torch.cuda.synchronize()
         tl = time.perf_counter() - tl
         extra["own_linear_scan"] = {"qps": round(nq / tl, 1), "ms": round(1e3 * tl, 2),
-                                    "note": "same kernels, no pruning (PDX linear scan)"}
+                                    "note": "PDX linear scan: every vector evaluated on the matrix cores (expanded "
+                                            "form within a rounding margin), the k nearest confirmed by the exact "
+                                            "chunked sum"}
     if mode == "bond" and not args.no_metrics:
         extra["metrics"] = bench_metrics(pdx, torch, np, ix, q, k, 3, 1, n, d, layout)
     del ws
