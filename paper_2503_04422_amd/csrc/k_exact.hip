@@ -1328,181 +1328,9 @@ __global__ __launch_bounds__(1024) void ip_tile_kernel(
     }
 }
 
-// ---------------------------------------------------------------------------
-// L2 linear mode on the matrix cores (the kernel listing's L2 scan, every
-// vector evaluated; exact).  Per 16 queries x 64 vectors a wave forms q.x
-// with v_mfma_f32_16x16x4f32 as the inner-product scan does, and |x|^2 from
-// the same loaded values, so each pair gets d' = |q|^2 + |x|^2 - 2 q.x.
-// e = 4 (D + 64) 2^-24 (|q|^2 + |x|^2) bounds both d' - |q - x|^2 and the
-// fixed-order float32 sum's distance from |q - x|^2, so d' - e is below and
-// d' + e above the distance every other path reports.  Pass 1 (every
-// stride-th vectorgroup) keeps each query's k smallest d' + e: their k-th
-// bounds the query's k-th distance from above (a subset's k-th is no
-// smaller).  Pass 2 (every vectorgroup) lists the vectors with d' - e at or
-// below that bound: a superset of the k nearest.  The listed vectors are
-// summed exactly (scan_groups' order) and merged; a query whose list
-// overflows takes the vectorgroup path over every row.
-// grid, lane layout and XCD mapping as in ip_scan_kernel (64 queries per
-// workgroup, ranges of vectorgroups dealt to the XCDs).
-typedef float lin_v4f __attribute__((ext_vector_type(4)));
-constexpr int kLinQueries = 64;
-template <bool PASS2>
-__global__ __launch_bounds__(256) void lin_scan_kernel(
-    const float *__restrict__ pdxd, const int32_t *__restrict__ slot_id, int64_t n, int32_t d, int32_t ngroups,
-    const float *__restrict__ q, int64_t nq, const float *__restrict__ qn, const int32_t *__restrict__ bad,
-    int32_t parts, int32_t nqb, int32_t stride, float margin, uint64_t *__restrict__ slots, int32_t k,
-    const uint32_t *__restrict__ tau, uint64_t *__restrict__ cand, int32_t *__restrict__ cand_cnt, int32_t cap) {
-    __shared__ uint64_t lists[4][PASS2 ? 1 : 16][kWave];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int col = lane & 15, kq = lane >> 4;
-    const int32_t per_xcd = parts / 8;
-    const int32_t x = blockIdx.x & 7, idx = blockIdx.x >> 3;
-    const int32_t p = x * per_xcd + idx / nqb;
-    const int64_t q0 = (int64_t)(idx % nqb) * kLinQueries + wave * 16;
-    if (q0 >= nq) return;
-    const int64_t qc = q0 + col;
-    const bool qok = qc < nq && !bad[qc];
-    const float *qrow = q + (qok ? qc : q0) * d;
-    bool rowok[4];
-    float qnr[4], taur[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t qr = q0 + 4 * kq + r;
-        rowok[r] = qr < nq && !bad[qr];
-        qnr[r] = rowok[r] ? qn[qr] : 0.0f;
-        taur[r] = (PASS2 && rowok[r]) ? __uint_as_float(tau[qr]) : 0.0f;
-    }
-    uint64_t kth[16];
-    if constexpr (!PASS2) {
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            lists[wave][m][lane] = kEmptyKey;
-            kth[m] = kEmptyKey;
-        }
-    }
-    const bool vec_ok = (d & 3) == 0;
-    const int32_t g0 = (int32_t)((int64_t)ngroups * p / parts), g1 = (int32_t)((int64_t)ngroups * (p + 1) / parts);
-    for (int32_t g = g0; g < g1; ++g) {
-        if (!PASS2 && g % stride != 0) continue;
-        int32_t sv[4];
-        bool vok[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            sv[t] = g * kGroup + 4 * col + t;
-            vok[t] = slot_id ? slot_id[sv[t]] >= 0 : sv[t] < n;
-        }
-        lin_v4f acc[4];
-        float xx[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = lin_v4f{0.0f, 0.0f, 0.0f, 0.0f};
-        const int64_t gbase = (int64_t)g * d;
-        for (int32_t j0 = 0; j0 < d; j0 += 32) {
-            const int32_t jl = j0 + 8 * kq;
-            float a[8];
-            lin_v4f bx[8];
-            if (j0 + 32 <= d && vec_ok) {
-#pragma unroll
-                for (int s8 = 0; s8 < 8; ++s8)
-                    bx[s8] = *reinterpret_cast<const lin_v4f *>(pdxd + (gbase + jl + s8) * kGroup + 4 * col);
-                const lin_v4f q_lo = *reinterpret_cast<const lin_v4f *>(qrow + jl);
-                const lin_v4f q_hi = *reinterpret_cast<const lin_v4f *>(qrow + jl + 4);
-#pragma unroll
-                for (int s8 = 0; s8 < 4; ++s8) {
-                    a[s8] = qok ? q_lo[s8] : 0.0f;
-                    a[s8 + 4] = qok ? q_hi[s8] : 0.0f;
-                }
-            } else {
-#pragma unroll
-                for (int s8 = 0; s8 < 8; ++s8) {
-                    const int32_t j = jl + s8;
-                    const bool ok = j < d;
-                    a[s8] = (ok && qok) ? qrow[j] : 0.0f;
-                    bx[s8] = ok ? *reinterpret_cast<const lin_v4f *>(pdxd + (gbase + j) * kGroup + 4 * col)
-                                : lin_v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                }
-            }
-#pragma unroll
-            for (int s8 = 0; s8 < 8; ++s8)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s8], bx[s8][t], acc[t], 0, 0, 0);
-                    xx[t] = fmaf(bx[s8][t], bx[s8][t], xx[t]);
-                }
-        }
-        // |x|^2 over all dimensions: the lanes of one column hold 8 of each 32
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            xx[t] += __shfl_xor(xx[t], 16);
-            xx[t] += __shfl_xor(xx[t], 32);
-        }
-        if constexpr (PASS2) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float nn = qnr[r] + xx[t];
-                    const float lo = nn - 2.0f * acc[t][r] - margin * nn;
-                    if (rowok[r] && vok[t] && !(lo > taur[r])) {
-                        const int64_t qr = q0 + 4 * kq + r;
-                        const int32_t pos = atomicAdd(cand_cnt + qr, 1);
-                        if (pos < cap) cand[qr * cap + pos] = (uint64_t)(uint32_t)sv[t];
-                    }
-                }
-        } else {
-            // offers: query slot m = 4 kq' + r is held by the 16 lanes with kq == kq'
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                const int r = m & 3;
-                const bool myrow = kq == (m >> 2) && rowok[r];
-                uint64_t key[4];
-                bool want[4];
-                bool any = false;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float nn = qnr[r] + xx[t];
-                    const float hi = fmaxf(nn - 2.0f * acc[t][r], 0.0f) + margin * nn;
-                    key[t] = make_key(hi, (uint32_t)sv[t]);
-                    want[t] = myrow && vok[t] && key[t] < kth[m];
-                    any |= want[t];
-                }
-                if (!__any(any)) continue;
-                uint64_t em = lists[wave][m][lane];
-                uint64_t km = kth[m];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) topk_offer(em, km, key[t], want[t], k, lane);
-                lists[wave][m][lane] = em;
-                kth[m] = km;
-            }
-        }
-    }
-    if constexpr (!PASS2) {
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int64_t qm = q0 + m;
-            if (qm < nq && lane < k) slots[((size_t)qm * parts + p) * k + lane] = lists[wave][m][lane];
-        }
-    }
-}
-
-// Each query's bound: the k-th smallest of its pass-1 keys (+inf when it
-// has fewer than k).
-__global__ __launch_bounds__(64) void lin_tau_kernel(const uint64_t *__restrict__ slots, int32_t parts, int32_t k,
-                                                     uint32_t *__restrict__ tau) {
-    const int64_t qi = blockIdx.x;
-    const int lane = threadIdx.x;
-    uint64_t e = kEmptyKey, kth = kEmptyKey;
-    const uint64_t *src = slots + (size_t)qi * parts * k;
-    const int64_t total = (int64_t)parts * k;
-    for (int64_t i = lane; i - lane < total; i += 64) {
-        const uint64_t key = i < total ? src[i] : kEmptyKey;
-        topk_offer(e, kth, key, key != kEmptyKey, k, lane);
-    }
-    if (lane == 0) tau[qi] = kth == kEmptyKey ? kInfBits : static_cast<uint32_t>(kth >> 32);
-}
-
 // The listed vectors' exact distances (scan_groups' chunk order, natural
 // dimension order), written back as keys (distance bits, row id).
-__global__ __launch_bounds__(64) void lin_rescore_kernel(const float *__restrict__ pdxd,
+__global__ __launch_bounds__(256) void lin_rescore_kernel(const float *__restrict__ pdxd,
                                                          const int32_t *__restrict__ slot_id, int32_t d,
                                                          const int32_t *__restrict__ perm,
                                                          const float *__restrict__ qperm,
@@ -1514,7 +1342,7 @@ __global__ __launch_bounds__(64) void lin_rescore_kernel(const float *__restrict
     const int32_t cnt = min(cand_cnt[qi], cap);
     const int32_t *po = perm + qi * d;
     const float *qp = qperm + qi * d;
-    for (int32_t i = threadIdx.x; i < cnt; i += 64) {
+    for (int32_t i = threadIdx.x; i < cnt; i += 256) {
         const uint32_t sv = static_cast<uint32_t>(cand[qi * cap + i]);
         const float *gp = pdxd + (int64_t)(sv / kGroup) * d * kGroup + (sv % kGroup);
         float partial = 0.0f;
@@ -1613,7 +1441,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
     pl.lin_mx = pl.mode == PDX_MODE_LINEAR && pl.metric == PDX_METRIC_L2 && ix->d % 4 == 0 &&
                 !(p && (p->counters || p->chunk_survivors));
     if (pl.lin_mx) {
-        pl.ip_parts = ip_parts_for(nq, ix->ngroups);
+        pl.ip_parts = lin_bound_parts(nq, ix->ngroups);
         pl.ip_slots = c.take<uint64_t>(q * pl.ip_parts * k);
         pl.qn = c.take<float>(q);
         pl.cand_cap = kCandCap;
@@ -1733,20 +1561,15 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         const unsigned nqu = (unsigned)pl.nq;
         if ((err = mark(1)) != hipSuccess) return err;
         row_sq_kernel<<<nqu, 64, 0, s>>>(qs, d, pl.qn);
-        const int32_t lnqb = (int32_t)((pl.nq + kLinQueries - 1) / kLinQueries);
-        const unsigned grid = 8u * (unsigned)(pl.ip_parts / 8) * (unsigned)lnqb;
-        const float margin = 4.0f * (float)(d + 64) * 0x1p-24f;
         // the bound from every 8th vectorgroup, then the listing pass
-        lin_scan_kernel<false><<<grid, 256, 0, s>>>(ix->pdx, sid, ix->n, d, ix->ngroups, qs, pl.nq, pl.qn, pl.bad,
-                                                   pl.ip_parts, lnqb, 8, margin, pl.ip_slots, pl.k, nullptr, nullptr,
-                                                   nullptr, 0);
-        lin_tau_kernel<<<nqu, 64, 0, s>>>(pl.ip_slots, pl.ip_parts, pl.k, pl.tau);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if ((err = launch_lin_bound(ix, sid, qs, pl.nq, pl.qn, pl.bad, pl.ip_parts, 8, pl.ip_slots, pl.k, pl.tau, s)) !=
+            hipSuccess)
+            return err;
         if ((err = launch_fill_i32(pl.cand_cnt, pl.nq, 0, s)) != hipSuccess) return err;
-        lin_scan_kernel<true><<<grid, 256, 0, s>>>(ix->pdx, sid, ix->n, d, ix->ngroups, qs, pl.nq, pl.qn, pl.bad,
-                                                  pl.ip_parts, lnqb, 1, margin, nullptr, pl.k, pl.tau, pl.cand,
-                                                  pl.cand_cnt, pl.cand_cap);
-        lin_rescore_kernel<<<nqu, 64, 0, s>>>(ix->pdx, sid, d, pl.perm, pl.qperm, pl.bad, pl.cand, pl.cand_cnt,
+        if ((err = launch_lin_list(ix, sid, qs, pl.nq, pl.qn, pl.bad, pl.tau, pl.cand, pl.cand_cnt, pl.cand_cap, s)) !=
+            hipSuccess)
+            return err;
+        lin_rescore_kernel<<<nqu, 256, 0, s>>>(ix->pdx, sid, d, pl.perm, pl.qperm, pl.bad, pl.cand, pl.cand_cnt,
                                              pl.cand_cap, pl.chunk);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         // a query whose list overflowed: the vectorgroup path over every row,

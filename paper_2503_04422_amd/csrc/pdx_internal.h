@@ -344,6 +344,21 @@ hipError_t launch_ip_merge(const uint64_t *slots, int64_t nq, int32_t parts, int
                            int64_t *out_ids, float *out_dist, hipStream_t s);
 int32_t ip_parts_for(int64_t nq, int32_t ngroups);
 
+// L2 linear mode on the matrix cores (k_lin.hip).  Bound pass over every
+// stride-th vectorgroup: each query's k smallest upper bounds into
+// slots[q][parts][k], their k-th into tau (float bits, +inf below k).
+// Listing pass over every vectorgroup: the row slots whose lower bound is
+// at or below tau, appended to cand[q][0..cap) with cand_cnt counting on
+// past cap (cand_cnt zeroed by the caller).  sid: slot -> row id on the
+// bucket layout, null on the flat one; qn: each query's squared norm.
+int32_t lin_bound_parts(int64_t nq, int32_t ngroups);
+hipError_t launch_lin_bound(const pdx_index *ix, const int32_t *sid, const float *q, int64_t nq, const float *qn,
+                            const int32_t *bad, int32_t parts, int32_t stride, uint64_t *slots, int32_t k,
+                            uint32_t *tau, hipStream_t s);
+hipError_t launch_lin_list(const pdx_index *ix, const int32_t *sid, const float *q, int64_t nq, const float *qn,
+                           const int32_t *bad, const uint32_t *tau, uint64_t *cand, int32_t *cand_cnt, int32_t cap,
+                           hipStream_t s);
+
 // PDX-BOND inside IVF (k_exact.hip): query order and per-item bucket scans.
 // zones: the dimension-zone order (32 consecutive dimensions per zone)
 // instead of the per-dimension one

@@ -66,6 +66,33 @@ def test_linear_small_config(pdx):
     check_knn(x, q, gi, gd, wi, wd)
 
 
+@pytest.mark.parametrize("layout", ["flat", "buckets"])
+@pytest.mark.parametrize("n,d,nq", [(20_001, 100, 300), (9_000, 128, 70), (6_000, 96, 33)])
+def test_linear_matrix_tiles_and_tails(pdx, layout, n, d, nq):
+    """The matrix-core L2 linear mode: 4 query tiles per wave (nq > 64: 300
+    leaves a last wave with two full tiles, a partial one and an empty one;
+    70 one wave of 64 and one of 6), one tile per wave (nq <= 64), D not a
+    multiple of 32 (a short last sub-chunk), a ragged last vectorgroup, a
+    non-finite query, and the bucket layout's padded buckets."""
+    import torch
+    mix = synth.skewed_mixture(d, 16, 8.0, 4.0, n % 97)
+    x, q = mix.data(n), mix.queries(nq)
+    q[nq // 2, 3] = np.inf
+    print(f"linear matrix {layout} n={n} d={d} nq={nq}", flush=True)
+    if layout == "flat":
+        ix = pdx.pdx_build(_dev(x))
+    else:
+        init = torch.arange(0, n, n // 64, device="cuda")[:64]
+        ix = pdx.pdx_ivf_build(_dev(x), 64, None, init, kmeans_iters=3)
+    ids, dist = pdx.pdx_search_exact(ix, _dev(q), 10, mode="linear")
+    torch.cuda.synchronize()
+    gi, gd = ids.cpu().numpy(), dist.cpu().numpy()
+    assert (gi[nq // 2] == -1).all() and np.isnan(gd[nq // 2]).all()
+    keep = [i for i in range(nq) if i != nq // 2]
+    wi, wd = exact.knn_exact_c(x, q[keep], 10)
+    check_knn(x, q[keep], gi[keep], gd[keep], wi, wd)
+
+
 @pytest.mark.parametrize("mode", ["linear", "bond"])
 @pytest.mark.parametrize("n,d,k", [(3001, 100, 10), (4096, 37, 1), (1000, 64, 64), (130, 5, 20)])
 def test_integer_inputs_bit_exact(pdx, mode, n, d, k):
