@@ -371,7 +371,8 @@ def bench_metrics(pdx, torch, np, ix, q, k, steps, warmup, n, d, layout="buckets
             achieved = flops / (ph[1] * 1e-3) / 1e12
             traffic, src = profiled_traffic("ip_scan_bond_1m_d960.md") if (n, d, k) == (1_000_000, 960, 10) \
                 else (None, "not profiled for this workload")
-            row["roofline"] = {"bound": "mfma", "kernel": "ip_scan_kernel (16 queries x 64 vectors per wave)",
+            row["roofline"] = {"bound": "mfma", "kernel": "ip_scan_mx_kernel (32 queries x 64 vectors per wave)" if d % 4 == 0
+                               else "ip_scan_kernel (16 queries x 64 vectors per wave)",
                                "achieved": round(achieved, 3), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": round(achieved / MFMA_F32_PEAK_TFLOPS, 4), "traffic": traffic,
                                "traffic_source": src, "algorithmic_flops_per_launch": flops,

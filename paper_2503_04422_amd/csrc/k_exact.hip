@@ -1433,7 +1433,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
         pl.over_count = c.take<int32_t>(64);
     }
     if (pl.metric == PDX_METRIC_IP && !ip_tiles) {
-        pl.ip_parts = ip_parts_for(nq, ix->ngroups);
+        pl.ip_parts = ip_parts_for(nq, ix->ngroups, ix->d);
         pl.ip_slots = c.take<uint64_t>(q * pl.ip_parts * k);
     }
     // L2 linear mode on the matrix cores (the vectorgroup path when the

@@ -20,6 +20,7 @@
 //
 // Scores are signed, so k-best keys use an order-preserving image of the
 // float bits (non-negative: sign bit set; negative: all bits complemented).
+#include "mfma_tiles.h"
 #include "pdx_internal.h"
 #include "wave_topk.h"
 
@@ -38,6 +39,7 @@ __device__ __forceinline__ float ord_float(uint32_t o) {
 }
 
 constexpr int kIpQueries = 64;  // queries per workgroup (4 waves x 16)
+constexpr int kIpTiles = 2;     // D % 4 == 0: 16-query tiles per wave
 
 // grid = 8 * (parts / 8) * nqb; XCD x = blockIdx.x % 8 takes ranges
 // [x parts/8, (x+1) parts/8), every query block of each.
@@ -145,6 +147,120 @@ __global__ __launch_bounds__(256) void ip_scan_kernel(const float *__restrict__ 
     }
 }
 
+// The same scan for D % 4 == 0 with NT tiles of 16 queries per wave: each
+// row value a lane loads feeds 4 NT MFMAs, a workgroup holds 4 such waves
+// (64 NT queries) over one range of vectorgroups, so the range's rows are
+// fetched once per 64 NT queries, and the loads run half a sub-chunk ahead
+// of the MFMAs (across vectorgroups too).  A query slot that is out of
+// range or non-finite reads another row of q; its products are never
+// offered.  The per-query lists take 16 NT x kp keys of LDS per wave (kp:
+// k rounded up to 16; dynamic LDS of 4 x 16 NT x kp keys).
+template <int NT>
+__global__ __launch_bounds__(256, 3) void ip_scan_mx_kernel(const float *__restrict__ pdxd,
+                                                            const int32_t *__restrict__ slot_id, int64_t n, int32_t d,
+                                                            int32_t ngroups, const float *__restrict__ q, int64_t nq,
+                                                            const int32_t *__restrict__ bad, int32_t parts,
+                                                            int32_t nqb, uint64_t *__restrict__ slots, int32_t k) {
+    extern __shared__ uint64_t ip_lists[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int32_t per_xcd = parts / 8;
+    const int32_t x = blockIdx.x & 7, idx = blockIdx.x >> 3;
+    const int32_t p = x * per_xcd + idx / nqb;
+    const int64_t q0 = (int64_t)(idx % nqb) * (64 * NT) + wave * (16 * NT);
+    if (q0 >= nq) return;
+    const int kp = (k + 15) & ~15;
+    uint64_t *lw = ip_lists + (size_t)wave * 16 * NT * kp;  // query slot m: lw[m kp .. m kp + kp)
+    const float *qrow[NT];
+    bool rowok[NT][4];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int64_t qc = q0 + 16 * u + col;
+        qrow[u] = q + (qc < nq ? qc : q0) * d;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t qr = q0 + 16 * u + 4 * kq + r;
+            rowok[u][r] = qr < nq && !bad[qr];
+        }
+    }
+    uint64_t kth[16 * NT];  // wave-uniform k-th key of each query's list
+#pragma unroll
+    for (int m = 0; m < 16 * NT; ++m) {
+        if (lane < kp) lw[m * kp + lane] = kEmptyKey;
+        kth[m] = kEmptyKey;
+    }
+    const int32_t g0 = (int32_t)((int64_t)ngroups * p / parts), g1 = (int32_t)((int64_t)ngroups * (p + 1) / parts);
+    const int32_t nfull = d / 32;  // whole sub-chunks; then a partial one when 32 does not divide D
+    if (g0 < g1) {
+        v4f b0[4], b1[4], a0[NT], a1[NT];
+        float xx[4];  // unused (no norms)
+        if (nfull > 0) load_half<NT>(pdxd, (int64_t)g0 * d, 0, 0, kq, col, qrow, b0, a0);
+        for (int32_t g = g0; g < g1; ++g) {
+            int32_t vid[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t sv = (int64_t)g * kGroup + 4 * col + t;
+                vid[t] = slot_id ? slot_id[sv] : (sv < n ? (int32_t)sv : -1);
+            }
+            v4f acc[NT][4];
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[u][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            const int64_t gbase = (int64_t)g * d;
+            for (int32_t c = 0; c < nfull; ++c) {
+                const int32_t j0 = 32 * c;
+                load_half<NT>(pdxd, gbase, j0, 1, kq, col, qrow, b1, a1);
+                mfma_half<NT, false>(b0, a0, acc, xx);
+                // the next whole sub-chunk: of this vectorgroup, else the
+                // next one's first (after the last, this one's first again)
+                const bool more = c + 1 < nfull;
+                const int64_t gnext = more ? gbase : (g + 1 < g1 ? gbase + d : (int64_t)g0 * d);
+                load_half<NT>(pdxd, gnext, more ? j0 + 32 : 0, 0, kq, col, qrow, b0, a0);
+                mfma_half<NT, false>(b1, a1, acc, xx);
+            }
+            if (32 * nfull < d) {
+                v4f bt[4], at[NT];
+                load_half_tail<NT>(pdxd, gbase, d, 32 * nfull, 0, kq, col, qrow, bt, at);
+                mfma_half<NT, false>(bt, at, acc, xx);
+                load_half_tail<NT>(pdxd, gbase, d, 32 * nfull, 1, kq, col, qrow, bt, at);
+                mfma_half<NT, false>(bt, at, acc, xx);
+            }
+            // offers: query slot 16 u + 4 kq' + r is held by the 16 lanes with kq == kq'
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    const int r = m & 3;
+                    const bool myrow = kq == (m >> 2) && rowok[u][r];
+                    uint64_t key[4];
+                    bool want[4];
+                    bool any = false;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float sc = -acc[u][t][r] + 0.0f;  // -q.v, zero as +0
+                        key[t] = (static_cast<uint64_t>(ord_bits(sc)) << 32) | static_cast<uint32_t>(vid[t]);
+                        want[t] = myrow && vid[t] >= 0 && key[t] < kth[16 * u + m];
+                        any |= want[t];
+                    }
+                    if (!__any(any)) continue;
+                    // lanes k .. 63 hold kEmptyKey and are never changed by an offer
+                    uint64_t em = lane < kp ? lw[(16 * u + m) * kp + lane] : kEmptyKey;
+                    uint64_t km = kth[16 * u + m];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) topk_offer(em, km, key[t], want[t], k, lane);
+                    if (lane < kp) lw[(16 * u + m) * kp + lane] = em;
+                    kth[16 * u + m] = km;
+                }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 16 * NT; ++m) {
+        const int64_t qm = q0 + m;
+        if (qm < nq && lane < k) slots[((size_t)qm * parts + p) * k + lane] = lw[m * kp + lane];
+    }
+}
+
 // k best of a query's `parts` lists: ids and -q.v; non-finite queries get
 // ids -1 and NaN, missing entries id -1 and +inf.
 __global__ __launch_bounds__(64) void ip_merge_kernel(const uint64_t *__restrict__ slots, int32_t parts, int32_t k,
@@ -178,8 +294,9 @@ __global__ __launch_bounds__(64) void ip_merge_kernel(const uint64_t *__restrict
 // Ranges of vectorgroups: enough workgroups to fill the chip (about 8 waves
 // per SIMD) for the query blocks at hand, a multiple of 8, at most one range
 // per vectorgroup.
-int32_t ip_parts_for(int64_t nq, int32_t ngroups) {
-    const int64_t nqb = (nq + kIpQueries - 1) / kIpQueries;
+int32_t ip_parts_for(int64_t nq, int32_t ngroups, int32_t d) {
+    const int64_t per = d % 4 == 0 ? 64 * kIpTiles : kIpQueries;
+    const int64_t nqb = (nq + per - 1) / per;
     const int64_t want_wg = 8 * (int64_t)device_cus();  // 4 waves each: 8 waves per SIMD
     int64_t parts = (want_wg + nqb - 1) / (nqb > 0 ? nqb : 1);
     parts = (parts + 7) / 8 * 8;
@@ -191,10 +308,18 @@ int32_t ip_parts_for(int64_t nq, int32_t ngroups) {
 hipError_t launch_ip_scan(const pdx_index *ix, const float *q, int64_t nq, const int32_t *bad, int32_t parts,
                           uint64_t *slots, int32_t k, hipStream_t s) {
     if (nq <= 0) return hipSuccess;
-    const int32_t nqb = (int32_t)((nq + kIpQueries - 1) / kIpQueries);
+    const bool mx = ix->d % 4 == 0;
+    const int64_t per = mx ? 64 * kIpTiles : kIpQueries;
+    const int32_t nqb = (int32_t)((nq + per - 1) / per);
     const unsigned grid = 8u * (unsigned)(parts / 8) * (unsigned)nqb;
     const int32_t *sid = ix->kind == kIvf ? ix->slot_id : nullptr;
-    ip_scan_kernel<<<grid, 256, 0, s>>>(ix->pdx, sid, ix->n, ix->d, ix->ngroups, q, nq, bad, parts, nqb, slots, k);
+    if (mx) {
+        const size_t lds = (size_t)4 * 16 * kIpTiles * ((k + 15) & ~15) * sizeof(uint64_t);  // at most 64 KiB
+        ip_scan_mx_kernel<kIpTiles><<<grid, 256, lds, s>>>(ix->pdx, sid, ix->n, ix->d, ix->ngroups, q, nq, bad,
+                                                           parts, nqb, slots, k);
+    }
+    else
+        ip_scan_kernel<<<grid, 256, 0, s>>>(ix->pdx, sid, ix->n, ix->d, ix->ngroups, q, nq, bad, parts, nqb, slots, k);
     return hipGetLastError();
 }
 

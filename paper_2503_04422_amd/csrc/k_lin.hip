@@ -24,10 +24,9 @@
 // Workgroup i runs on XCD i mod 8; the query blocks of one range of
 // vectorgroups are consecutive there, so the range's rows are fetched into
 // that XCD's L2 once for all of them.
+#include "mfma_tiles.h"
 #include "pdx_internal.h"
 #include "wave_topk.h"
-
-#include <algorithm>
 
 namespace pdx {
 namespace {
@@ -72,53 +71,6 @@ __device__ __forceinline__ void load_subchunk(const float *__restrict__ pdxd, in
                 else ahi[u][s - 4] = v;
             }
         }
-    }
-}
-
-// Half h of a whole sub-chunk for the listing pass: K-steps 4h .. 4h + 3
-// (the lane's dimensions jl .. jl + 3, jl = j0 + 8 kq + 4h), its four
-// vectors and NT query tiles' values.  Nothing reads the loaded values until
-// that half's MFMAs, so the loads stay in flight across the other half's.
-template <int NT>
-__device__ __forceinline__ void load_half(const float *__restrict__ pdxd, int64_t gbase, int32_t j0, int h, int kq,
-                                          int col, const float *const (&qrow)[NT], v4f (&b)[4], v4f (&a)[NT]) {
-    const int32_t jl = j0 + 8 * kq + 4 * h;
-#pragma unroll
-    for (int u = 0; u < NT; ++u) a[u] = *reinterpret_cast<const v4f *>(qrow[u] + jl);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) b[s] = *reinterpret_cast<const v4f *>(pdxd + (gbase + jl + s) * kGroup + 4 * col);
-}
-
-// The same for the last, partial sub-chunk (zero past D).
-template <int NT>
-__device__ __forceinline__ void load_half_tail(const float *__restrict__ pdxd, int64_t gbase, int32_t d, int32_t j0,
-                                               int h, int kq, int col, const float *const (&qrow)[NT], v4f (&b)[4],
-                                               v4f (&a)[NT]) {
-    const int32_t jl = j0 + 8 * kq + 4 * h;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int32_t j = jl + s;
-        const bool ok = j < d;
-        b[s] = ok ? *reinterpret_cast<const v4f *>(pdxd + (gbase + j) * kGroup + 4 * col)
-                  : v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int u = 0; u < NT; ++u) a[u][s] = ok ? qrow[u][j] : 0.0f;
-    }
-}
-
-// K-steps of one half: acc[u][t] += A(tile u) B(vectors 4 col + t), and the
-// vectors' squared norms.
-template <int NT>
-__device__ __forceinline__ void mfma_half(const v4f (&b)[4], const v4f (&a)[NT], v4f (&acc)[NT][4], float (&xx)[4]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int u = 0; u < NT; ++u)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s], b[s][t], acc[u][t], 0, 0, 0);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) xx[t] = fmaf(b[s][t], b[s][t], xx[t]);
     }
 }
 
@@ -288,20 +240,20 @@ __global__ __launch_bounds__(256, 2) void lin_list_kernel(
         for (int32_t c = 0; c < nfull; ++c) {
             const int32_t j0 = 32 * c;
             load_half<NT>(pdxd, gbase, j0, 1, kq, col, qrow, b1, a1);
-            mfma_half<NT>(b0, a0, acc, xx);
+            mfma_half<NT, true>(b0, a0, acc, xx);
             // the next whole sub-chunk: of this vectorgroup, else the next
             // one's first (after the last vectorgroup, this one's first again)
             const bool more = c + 1 < nfull;
             const int64_t gnext = more ? gbase : (g + 1 < g1 ? gbase + d : (int64_t)g0 * d);
             load_half<NT>(pdxd, gnext, more ? j0 + 32 : 0, 0, kq, col, qrow, b0, a0);
-            mfma_half<NT>(b1, a1, acc, xx);
+            mfma_half<NT, true>(b1, a1, acc, xx);
         }
         if (32 * nfull < d) {
             v4f bt[4], at[NT];
             load_half_tail<NT>(pdxd, gbase, d, 32 * nfull, 0, kq, col, qrow, bt, at);
-            mfma_half<NT>(bt, at, acc, xx);
+            mfma_half<NT, true>(bt, at, acc, xx);
             load_half_tail<NT>(pdxd, gbase, d, 32 * nfull, 1, kq, col, qrow, bt, at);
-            mfma_half<NT>(bt, at, acc, xx);
+            mfma_half<NT, true>(bt, at, acc, xx);
         }
         // |x|^2 over all dimensions: the lanes of one column hold 8 of each 32
 #pragma unroll

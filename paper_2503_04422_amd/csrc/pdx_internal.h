@@ -342,7 +342,7 @@ hipError_t launch_ip_scan(const pdx_index *ix, const float *q, int64_t nq, const
                           uint64_t *slots, int32_t k, hipStream_t s);
 hipError_t launch_ip_merge(const uint64_t *slots, int64_t nq, int32_t parts, int32_t k, const int32_t *bad,
                            int64_t *out_ids, float *out_dist, hipStream_t s);
-int32_t ip_parts_for(int64_t nq, int32_t ngroups);
+int32_t ip_parts_for(int64_t nq, int32_t ngroups, int32_t d);
 
 // L2 linear mode on the matrix cores (k_lin.hip).  Bound pass over every
 // stride-th vectorgroup: each query's k smallest upper bounds into
