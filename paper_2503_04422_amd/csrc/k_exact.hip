@@ -1442,7 +1442,7 @@ size_t exact_plan(const pdx_index *ix, int64_t nq, int32_t k, const pdx_search_p
                 !(p && (p->counters || p->chunk_survivors));
     if (pl.lin_mx) {
         pl.ip_parts = lin_bound_parts(nq, ix->ngroups);
-        pl.ip_slots = c.take<uint64_t>(q * pl.ip_parts * k);
+        pl.lin_mins = c.take<float>(q * pl.ip_parts * 16);
         pl.qn = c.take<float>(q);
         pl.cand_cap = kCandCap;
         pl.cand = c.take<uint64_t>(q * pl.cand_cap);
@@ -1562,7 +1562,7 @@ hipError_t run_exact(const pdx_index *ix, const float *q, const ExactPlan &pl, i
         if ((err = mark(1)) != hipSuccess) return err;
         row_sq_kernel<<<nqu, 64, 0, s>>>(qs, d, pl.qn);
         // the bound from every 8th vectorgroup, then the listing pass
-        if ((err = launch_lin_bound(ix, sid, qs, pl.nq, pl.qn, pl.bad, pl.ip_parts, 8, pl.ip_slots, pl.k, pl.tau, s)) !=
+        if ((err = launch_lin_bound(ix, sid, qs, pl.nq, pl.qn, pl.bad, pl.ip_parts, 8, pl.lin_mins, pl.k, pl.tau, s)) !=
             hipSuccess)
             return err;
         if ((err = launch_fill_i32(pl.cand_cnt, pl.nq, 0, s)) != hipSuccess) return err;

@@ -100,6 +100,7 @@ struct ExactPlan {
     bool ivf;              // bucket layout (IVF index): rows in bucket order, ids through slot_id
     bool library_gemm;     // centroid products on rocBLAS (else the library's own GEMM kernel, which allocates nothing)
     bool lin_mx;           // L2 linear mode on the matrix cores (bound pass, listing pass, exact re-sum)
+    float *lin_mins;       // its bound pass: [nq][ip_parts][16] lane minima
     int32_t start_parts;   // bucket layout: waves per query in START
     int32_t start_maxg;    // bucket layout: vectorgroups of the nearest bucket START scans
     int32_t metric;        // PDX_METRIC_*
@@ -345,15 +346,16 @@ hipError_t launch_ip_merge(const uint64_t *slots, int64_t nq, int32_t parts, int
 int32_t ip_parts_for(int64_t nq, int32_t ngroups, int32_t d);
 
 // L2 linear mode on the matrix cores (k_lin.hip).  Bound pass over every
-// stride-th vectorgroup: each query's k smallest upper bounds into
-// slots[q][parts][k], their k-th into tau (float bits, +inf below k).
+// stride-th vectorgroup: per query, each lane's smallest upper bound into
+// mins[q][parts][16], their k-th smallest into tau (float bits, +inf when
+// fewer than k are finite).
 // Listing pass over every vectorgroup: the row slots whose lower bound is
 // at or below tau, appended to cand[q][0..cap) with cand_cnt counting on
 // past cap (cand_cnt zeroed by the caller).  sid: slot -> row id on the
 // bucket layout, null on the flat one; qn: each query's squared norm.
 int32_t lin_bound_parts(int64_t nq, int32_t ngroups);
 hipError_t launch_lin_bound(const pdx_index *ix, const int32_t *sid, const float *q, int64_t nq, const float *qn,
-                            const int32_t *bad, int32_t parts, int32_t stride, uint64_t *slots, int32_t k,
+                            const int32_t *bad, int32_t parts, int32_t stride, float *mins, int32_t k,
                             uint32_t *tau, hipStream_t s);
 hipError_t launch_lin_list(const pdx_index *ix, const int32_t *sid, const float *q, int64_t nq, const float *qn,
                            const int32_t *bad, const uint32_t *tau, uint64_t *cand, int32_t *cand_cnt, int32_t cap,
