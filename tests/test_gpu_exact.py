@@ -182,16 +182,18 @@ def test_full_size_bond_sampled(pdx):
     assert (gi >= 0).all() and (gi < x.shape[0]).all()
 
 
-def test_tile_path_ties_overflow_and_fallback(pdx):
+@pytest.mark.parametrize("mode", ["bond", "linear"])
+def test_tile_path_ties_overflow_and_fallback(pdx, mode):
     """All rows tie with the queries: every vector survives, the LDS survivor
-    queue and the per-query candidate buffer overflow, and the group-path
-    fallback must still return the k lowest ids (distance 0)."""
+    queue and the per-query candidate buffer overflow (in linear mode the
+    matrix-core listing pass's list), and the group-path fallback must still
+    return the k lowest ids (distance 0)."""
     x = np.zeros((20_000, 64), dtype=np.float32)
     x[::7, 3] = 1.0
     q = np.zeros((70, 64), dtype=np.float32)
-    print("tile path overflow", flush=True)
+    print(f"tile path overflow {mode}", flush=True)
     wi, wd = exact.knn_exact_c(x, q, 10)
-    _, gi, gd = _search(pdx, x, q, 10, mode="bond", start_rows=256)
+    _, gi, gd = _search(pdx, x, q, 10, mode=mode, start_rows=256)
     check_knn(x, q, gi, gd, wi, wd, exact=True)
 
 

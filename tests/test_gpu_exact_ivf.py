@@ -97,9 +97,10 @@ def test_bucket_layout_ties_overflow_and_edges(pdx):
     q = np.zeros((70, 64), dtype=np.float32)
     print("bucket layout overflow", flush=True)
     ix = _bucket_index(pdx, x, 16, 3, iters=2)
-    gi, gd = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10, mode="bond"))
     wi, wd = exact.knn_exact_c(x, q, 10)
-    check_knn(x, q, gi, gd, wi, wd, exact=True)
+    for mode in ("bond", "linear"):  # linear: the listing pass overflows into the fallback
+        gi, gd = (_np(t) for t in pdx.pdx_search_exact(ix, _dev(q), 10, mode=mode))
+        check_knn(x, q, gi, gd, wi, wd, exact=True)
     # k above n, a non-finite query, no queries
     x2, q2 = synth.integer_grid(40, 32, 4, seed=8)
     ix2 = _bucket_index(pdx, x2, 3, 4)
